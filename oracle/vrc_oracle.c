@@ -1,0 +1,381 @@
+/*
+ * Plain CPU oracle for the volumetric-ray-casting (VRC) fluence estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the tests, the
+ * smoke check and the CPU-baseline timing of the benchmark may load it; the
+ * library itself never calls it, and the two share no code.
+ *
+ * It follows the method's definition step by step, in double precision:
+ *
+ *  1. Total cross section of every material at the ray energy (Sec. 3: the
+ *     cross sections of all materials are found first, by table lookup and
+ *     linear interpolation between table points).  Here: binary search for
+ *     the bracketing interval, lin-lin interpolation, end values held
+ *     outside the table.
+ *  2. Trace the ray through the mesh (Sec. 3; trav.inc): the voxels crossed,
+ *     in order, with the length in each.
+ *  3. Score every crossed voxel i by the VRC estimator (Eq. 4, i.e. the
+ *     expected-value estimator of Eq. 1 with the entering weight of Eq. 2):
+ *        W_i = w * exp(-tau_in)                       (Eq. 2)
+ *        F_i = W_i * (1 - exp(-Sigma_i * l_i)) / Sigma_i   (Eq. 1 / Eq. 3)
+ *     with 1 - exp(-x) evaluated as -expm1(-x), F_i = W_i * l_i when
+ *     Sigma_i = 0 (the limit), and tau_in advanced by Sigma_i * l_i after
+ *     the voxel.  The ray weight w already carries the 1/N of Eq. 4.
+ *  4. Accumulate F_i into the tally of the ray's energy bin with a
+ *     compensated (Neumaier) sum, and keep, per voxel, the sum of squares and
+ *     the number of rays that scored (for the relative standard error that
+ *     decides which voxels a tolerance applies to; Sec. 5 compares only cells
+ *     below 5% uncertainty).
+ *
+ * Pins (tests/test_oracle_pins.py): the lookup against numpy.interp; the
+ * traversal against exact rational arithmetic and hand cases; the scores
+ * against the homogeneous telescoping sum, the void limit, the collision
+ * form, an axis-aligned closed form and fine-step path integration; the
+ * tally against exactly rounded sums; the estimator's mean against cubature
+ * of a point source and against the track-length estimator of an analog
+ * walk.  No function here is left unpinned.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+#define REAL double
+#define TRAV_NAME(x) x##_f64
+#include "trav.inc"
+#undef REAL
+#undef TRAV_NAME
+
+#define REAL float
+#define TRAV_NAME(x) x##_f32
+#include "trav.inc"
+#undef REAL
+#undef TRAV_NAME
+
+/* ------------------------------------------------------------------------ */
+/* step 1: Sigma_t(E) by table lookup (Sec. 3)                               */
+/* ------------------------------------------------------------------------ */
+
+/* first index k in [0, K] with e[k] > E */
+static int64_t upper_bound(const double *e, int64_t K, double E)
+{
+    int64_t lo = 0, hi = K;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (e[mid] > E) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+double oracle_sigma(const double *e, const double *s, int64_t K, double E)
+{
+    int64_t ub = upper_bound(e, K, E);
+    if (ub == 0) return s[0];
+    if (ub == K) return s[K - 1];
+    int64_t k = ub - 1;
+    double slope = (s[k + 1] - s[k]) / (e[k + 1] - e[k]);
+    return s[k] + slope * (E - e[k]);
+}
+
+/* 1 if E lies outside the table (the end value was used) */
+static int outside_table(const double *e, int64_t K, double E)
+{
+    return E < e[0] || E > e[K - 1];
+}
+
+/* Sigma of every material at each of n energies: out[i*n_mat + m] */
+void oracle_sigma_all(int n_mat, const int64_t *offs, const double *energy, const double *sigma,
+                      int64_t n, const double *E, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int m = 0; m < n_mat; ++m)
+            out[i * n_mat + m] = oracle_sigma(energy + offs[m], sigma + offs[m],
+                                              offs[m + 1] - offs[m], E[i]);
+}
+
+/* energy bin: edges[b] <= E < edges[b+1]; E == edges[n_bins] goes to the last bin;
+ * -1 outside.  edges == NULL means one bin that takes every energy. */
+int oracle_ebin(int n_bins, const double *edges, double E)
+{
+    if (edges == NULL) return 0;
+    if (!(E >= edges[0] && E <= edges[n_bins])) return -1;
+    if (E == edges[n_bins]) return n_bins - 1;
+    for (int b = 0; b < n_bins; ++b)
+        if (edges[b] <= E && E < edges[b + 1]) return b;
+    return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* step 2: tracing (public wrappers around trav.inc)                         */
+/* ------------------------------------------------------------------------ */
+
+int64_t oracle_trace_f64(const double *lo, const double *h, const int32_t *n,
+                         const double *o, const double *u, int64_t cap,
+                         int64_t *vox, double *len, double *span)
+{
+    event_f64 *ws = (event_f64 *)malloc(sizeof(event_f64) * (size_t)(n[0] + n[1] + n[2] + 3));
+    if (!ws) return -1;
+    int64_t r = trace_ws_f64(lo, h, n, o, u, cap, vox, len, span, ws);
+    free(ws);
+    return r;
+}
+
+int64_t oracle_trace_f32(const float *lo, const float *h, const int32_t *n,
+                         const float *o, const float *u, int64_t cap,
+                         int64_t *vox, float *len, float *span)
+{
+    event_f32 *ws = (event_f32 *)malloc(sizeof(event_f32) * (size_t)(n[0] + n[1] + n[2] + 3));
+    if (!ws) return -1;
+    int64_t r = trace_ws_f32(lo, h, n, o, u, cap, vox, len, span, ws);
+    free(ws);
+    return r;
+}
+
+/* many FP32 rays at once, CSR output (offs has n_rays+1 entries); returns the
+ * total segment count, or -1 (inconsistency) / -2 (cap too small) */
+int64_t oracle_trace_many_f32(const float *lo, const float *h, const int32_t *n, int64_t n_rays,
+                              const float *ox, const float *oy, const float *oz,
+                              const float *ux, const float *uy, const float *uz,
+                              int64_t cap, int64_t *offs, int64_t *vox, float *len)
+{
+    event_f32 *ws = (event_f32 *)malloc(sizeof(event_f32) * (size_t)(n[0] + n[1] + n[2] + 3));
+    if (!ws) return -1;
+    int64_t total = 0;
+    offs[0] = 0;
+    for (int64_t r = 0; r < n_rays; ++r) {
+        float o[3] = {ox[r], oy[r], oz[r]};
+        float u[3] = {ux[r], uy[r], uz[r]};
+        int64_t room = cap - total;
+        if (room < 0) room = 0;
+        int64_t k = trace_ws_f32(lo, h, n, o, u, room, vox + total, len + total, NULL, ws);
+        if (k < 0) { free(ws); return -1; }
+        if (k > room) { free(ws); return -2; }
+        total += k;
+        offs[r + 1] = total;
+    }
+    free(ws);
+    return total;
+}
+
+int64_t oracle_trace_many_f64(const double *lo, const double *h, const int32_t *n, int64_t n_rays,
+                              const double *ox, const double *oy, const double *oz,
+                              const double *ux, const double *uy, const double *uz,
+                              int64_t cap, int64_t *offs, int64_t *vox, double *len)
+{
+    event_f64 *ws = (event_f64 *)malloc(sizeof(event_f64) * (size_t)(n[0] + n[1] + n[2] + 3));
+    if (!ws) return -1;
+    int64_t total = 0;
+    offs[0] = 0;
+    for (int64_t r = 0; r < n_rays; ++r) {
+        double o[3] = {ox[r], oy[r], oz[r]};
+        double u[3] = {ux[r], uy[r], uz[r]};
+        int64_t room = cap - total;
+        if (room < 0) room = 0;
+        int64_t k = trace_ws_f64(lo, h, n, o, u, room, vox + total, len + total, NULL, ws);
+        if (k < 0) { free(ws); return -1; }
+        if (k > room) { free(ws); return -2; }
+        total += k;
+        offs[r + 1] = total;
+    }
+    free(ws);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* steps 3-4: scoring and tallying                                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const double *lo, *h;
+    const int32_t *n;
+    const uint8_t *mat;
+    int n_mat;
+    const int64_t *offs;
+    const double *energy, *sigma;
+    int n_bins;
+    const double *edges;
+} problem;
+
+/* VRC score of one voxel (Eqs. 1-4): weight entering times (1-exp(-x))/Sigma */
+static double vrc_score(double w, double tau_in, double sig, double l)
+{
+    double w_in = w * exp(-tau_in);            /* Eq. 2 */
+    if (sig > 0) {
+        double x = sig * l;
+        return w_in * (-expm1(-x)) / sig;      /* Eq. 1 with W -> W_i (Eq. 3) */
+    }
+    return w_in * l;                           /* limit Sigma -> 0 */
+}
+
+/*
+ * Per-ray record: voxels, lengths and scores of one FP64 ray.  Returns the
+ * segment count (only the first cap are written), -1 on an internal error.
+ * *bin_out receives the energy bin (-1: not scored).
+ */
+int64_t oracle_ray_scores(const double *lo, const double *h, const int32_t *n, const uint8_t *mat,
+                          int n_mat, const int64_t *offs, const double *energy, const double *sigma,
+                          int n_bins, const double *edges,
+                          const double *o, const double *u, double E, double w,
+                          int64_t cap, int64_t *vox, double *len, double *score, int *bin_out)
+{
+    double sig[256];
+    if (n_mat > 256) return -1;
+    for (int m = 0; m < n_mat; ++m)
+        sig[m] = oracle_sigma(energy + offs[m], sigma + offs[m], offs[m + 1] - offs[m], E);
+    *bin_out = oracle_ebin(n_bins, edges, E);
+    int64_t k = oracle_trace_f64(lo, h, n, o, u, cap, vox, len, NULL);
+    if (k < 0) return k;
+    int64_t m_seg = k < cap ? k : cap;
+    double tau = 0.0;
+    for (int64_t s = 0; s < m_seg; ++s) {
+        double sg = sig[mat[vox[s]]];
+        score[s] = (*bin_out >= 0) ? vrc_score(w, tau, sg, len[s]) : 0.0;
+        tau += sg * len[s];
+    }
+    return k;
+}
+
+typedef struct {
+    const problem *p;
+    int64_t r0, r1;
+    const double *ox, *oy, *oz, *ux, *uy, *uz, *e, *w;
+    double *sum, *comp, *sq;
+    int64_t *cnt;
+    int64_t n_seg, n_scored, n_out_of_range, n_clamped, n_err;
+} job;
+
+static void neumaier_add(double *sum, double *comp, double x)
+{
+    double t = *sum + x;
+    if (fabs(*sum) >= fabs(x)) *comp += (*sum - t) + x;
+    else *comp += (x - t) + *sum;
+    *sum = t;
+}
+
+static void *run_job(void *arg)
+{
+    job *j = (job *)arg;
+    const problem *p = j->p;
+    const int64_t nvox = (int64_t)p->n[0] * p->n[1] * p->n[2];
+    int64_t cap = (int64_t)p->n[0] + p->n[1] + p->n[2] + 3;
+    int64_t *vox = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    double *len = (double *)malloc(sizeof(double) * (size_t)cap);
+    event_f64 *ws = (event_f64 *)malloc(sizeof(event_f64) * (size_t)cap);
+    double sig[256];
+    if (!vox || !len || !ws || p->n_mat > 256) { j->n_err = 1; free(vox); free(len); free(ws); return NULL; }
+    for (int64_t r = j->r0; r < j->r1; ++r) {
+        double E = j->e[r];
+        int b = oracle_ebin(p->n_bins, p->edges, E);
+        double o[3] = {j->ox[r], j->oy[r], j->oz[r]};
+        double u[3] = {j->ux[r], j->uy[r], j->uz[r]};
+        int64_t k = trace_ws_f64(p->lo, p->h, p->n, o, u, cap, vox, len, NULL, ws);
+        if (k < 0 || k > cap) { j->n_err++; continue; }
+        j->n_seg += k;
+        if (b < 0) { j->n_out_of_range++; continue; }
+        j->n_scored++;
+        for (int m = 0; m < p->n_mat; ++m) {
+            const double *ee = p->energy + p->offs[m];
+            int64_t K = p->offs[m + 1] - p->offs[m];
+            sig[m] = oracle_sigma(ee, p->sigma + p->offs[m], K, E);
+            if (outside_table(ee, K, E)) { j->n_clamped++; }
+        }
+        double tau = 0.0;
+        for (int64_t s = 0; s < k; ++s) {
+            double sg = sig[p->mat[vox[s]]];
+            double f = vrc_score(j->w[r], tau, sg, len[s]);
+            tau += sg * len[s];
+            int64_t t = (int64_t)b * nvox + vox[s];
+            neumaier_add(&j->sum[t], &j->comp[t], f);
+            if (j->sq) j->sq[t] += f * f;
+            if (j->cnt && f != 0.0) j->cnt[t] += 1;
+        }
+    }
+    free(vox); free(len); free(ws);
+    return NULL;
+}
+
+static double now_s(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/*
+ * Whole-tally run.  tally[b*nvox + v] receives the compensated sum; tally_sq
+ * and tally_cnt (optional) the sum of squares and the number of non-zero
+ * contributions.  Outputs are overwritten.  stats: [0] segments traced,
+ * [1] rays scored, [2] rays outside the energy bins, [3] material lookups
+ * outside a table, [4] internal errors.  *seconds: wall time of the
+ * tracing-and-scoring part (set-up and the final reduction excluded, as the
+ * paper times the transport part only, Sec. 4).  Rays are split into
+ * n_threads static chunks with private tallies.
+ */
+int oracle_cast(const double *lo, const double *h, const int32_t *n, const uint8_t *mat,
+                int n_mat, const int64_t *offs, const double *energy, const double *sigma,
+                int n_bins, const double *edges, int64_t n_rays,
+                const double *ox, const double *oy, const double *oz,
+                const double *ux, const double *uy, const double *uz,
+                const double *e, const double *w, int n_threads,
+                double *tally, double *tally_sq, int64_t *tally_cnt,
+                int64_t *stats, double *seconds)
+{
+    problem p = {lo, h, n, mat, n_mat, offs, energy, sigma, n_bins, edges};
+    const int64_t nvox = (int64_t)n[0] * n[1] * n[2];
+    const int64_t nt = (int64_t)n_bins * nvox;
+    if (n_threads < 1) n_threads = 1;
+    job *jobs = (job *)calloc((size_t)n_threads, sizeof(job));
+    pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!jobs || !th) return -3;
+    int rc = 0;
+    for (int t = 0; t < n_threads; ++t) {
+        job *j = &jobs[t];
+        j->p = &p;
+        j->r0 = n_rays * t / n_threads;
+        j->r1 = n_rays * (t + 1) / n_threads;
+        j->ox = ox; j->oy = oy; j->oz = oz; j->ux = ux; j->uy = uy; j->uz = uz; j->e = e; j->w = w;
+        j->sum = (double *)calloc((size_t)nt, sizeof(double));
+        j->comp = (double *)calloc((size_t)nt, sizeof(double));
+        j->sq = tally_sq ? (double *)calloc((size_t)nt, sizeof(double)) : NULL;
+        j->cnt = tally_cnt ? (int64_t *)calloc((size_t)nt, sizeof(int64_t)) : NULL;
+        if (!j->sum || !j->comp || (tally_sq && !j->sq) || (tally_cnt && !j->cnt)) rc = -3;
+    }
+    if (rc == 0) {
+        double t0 = now_s();
+        for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, run_job, &jobs[t]);
+        for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+        if (seconds) *seconds = now_s() - t0;
+        for (int64_t i = 0; i < nt; ++i) {
+            double s = 0.0, c = 0.0, q = 0.0;
+            int64_t k = 0;
+            for (int t = 0; t < n_threads; ++t) {
+                neumaier_add(&s, &c, jobs[t].sum[i]);
+                neumaier_add(&s, &c, jobs[t].comp[i]);
+                if (tally_sq) q += jobs[t].sq[i];
+                if (tally_cnt) k += jobs[t].cnt[i];
+            }
+            tally[i] = s + c;
+            if (tally_sq) tally_sq[i] = q;
+            if (tally_cnt) tally_cnt[i] = k;
+        }
+        if (stats) {
+            memset(stats, 0, 5 * sizeof(int64_t));
+            for (int t = 0; t < n_threads; ++t) {
+                stats[0] += jobs[t].n_seg;
+                stats[1] += jobs[t].n_scored;
+                stats[2] += jobs[t].n_out_of_range;
+                stats[3] += jobs[t].n_clamped;
+                stats[4] += jobs[t].n_err;
+            }
+            if (stats[4]) rc = -1;
+        }
+    }
+    for (int t = 0; t < n_threads; ++t) {
+        free(jobs[t].sum); free(jobs[t].comp); free(jobs[t].sq); free(jobs[t].cnt);
+    }
+    free(jobs); free(th);
+    return rc;
+}
