@@ -1,0 +1,207 @@
+"""Throughput benchmark of the VRC hot path on one MI355X.
+
+One step = one call of vrc_cast_rays over the whole ray batch of the
+multi-material workload (100^3 mesh of 0.5 cm voxels, 3 materials in
+10-voxel z slabs, 20k-point Sigma_t(E) tables, 1e6 rays with uniform
+origins, isotropic directions, log-uniform energies, lognormal weights),
+i.e. every step of the path: ray load, cross-section lookup, clip, voxel
+walk, attenuation, score and tally atomics.  Inputs are resident in HBM
+before the timed region.
+
+Prints one JSON line: segments/s (the metric), roofline of the cast kernel
+against HBM bandwidth, p50/p99 per-batch latency, and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes: ray SoA once per ray; per segment one material byte and an
+# 8-byte read-modify-write of the tally element (FP64, or the FP32 sum+compensation pair)
+RAY_BYTES = {"f32": 32, "f64": 64}
+SEG_BYTES = 1 + 2 * 8
+KERNEL_SOURCES = ["paper_1706_07476_amd/csrc/vrc_kernels.hip", "paper_1706_07476_amd/csrc/vrc_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cast_multimat_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision: str, launch: dict):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it is for this kernel."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or t.get("precision") != precision or t.get("launch") != launch:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rays", type=int, default=1_000_000)
+    ap.add_argument("--precision", default="p32_t64", choices=["p64", "p32_t64", "p32_kahan"])
+    ap.add_argument("--block", type=int, default=None)
+    ap.add_argument("--blocks-per-cu", type=int, default=None)
+    ap.add_argument("--hash-in-lds", type=int, default=None)
+    ap.add_argument("--aggregate", type=int, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the CPU oracle leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--other-forms", type=int, default=1, help="also time the other precision forms")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_casts(vrc, ctx, tid, arrays, steps, warmup, stream, torch):
+    b = vrc.make_batch(arrays)
+    for _ in range(warmup):
+        vrc.vrc_cast_rays(ctx.handle, tid, b, stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        vrc.vrc_cast_rays(ctx.handle, tid, b, stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])  # ms, per launch
+    total_ms = ev[0].elapsed_time(ev[steps])
+    return per, total_ms, wall
+
+
+def cpu_baseline(wl, target_s):
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n_cal = 2000
+    cal = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, n_cal)), n_threads=threads, with_stats=False)
+    rate = cal.segments / max(cal.seconds, 1e-6)
+    n = int(min(wl.rays.n, max(n_cal, target_s * rate / max(cal.segments / n_cal, 1))))
+    res = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, n)), n_threads=threads, with_stats=False)
+    return {"value": res.segments / res.seconds, "unit": "segments/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of the {wl.rays.n} rays of the same workload, FP64 oracle, "
+                      f"{res.segments} segments in {res.seconds:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the path shards by replicating the tally per GPU, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1706_07476_amd as vrc
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log("bench: generating the multimat workload")
+    wl = W.config2_multimaterial(n_rays=args.rays)
+    dt = "f64" if args.precision == "p64" else "f32"
+    npdt = np.float64 if dt == "f64" else np.float32
+    dev = torch.device("cuda:0")
+    arrays = [torch.from_numpy(np.ascontiguousarray(a, dtype=npdt)).to(dev) for a in wl.rays.arrays()]
+    ctx = vrc.Context(0)
+    ctx.set_mesh(0, wl.mesh)
+    ctx.set_xs(wl.xs)
+    shape = {k: v for k, v in (("block", args.block), ("blocks_per_cu", args.blocks_per_cu),
+                               ("hash_in_lds", args.hash_in_lds), ("aggregate", args.aggregate)) if v is not None}
+    if shape:
+        ctx.set_launch(**shape)
+    launch = ctx.get_launch()
+    stream = torch.cuda.current_stream()
+    counts = torch.empty(wl.rays.n, dtype=torch.int64, device=dev)
+    S = ctx.count_segments(0, args.precision, arrays, counts, stream)
+    R = wl.rays.n
+    tid = ctx.create_tally(0, args.precision)
+    log(f"bench: {R} rays, {S} segments per step; timing {args.steps} steps after {args.warmup} warm-up")
+    per, total_ms, wall = time_casts(vrc, ctx, tid, arrays, args.steps, args.warmup, stream, torch)
+    ms_step = total_ms / args.steps
+    value = S * args.steps / (total_ms / 1e3)
+    alg_bytes = RAY_BYTES[dt] * R + SEG_BYTES * S
+    kern_s = float(np.mean(per)) / 1e3
+    achieved = alg_bytes / kern_s / 1e9
+    traffic = measured_traffic(args.precision, launch)
+    others = {}
+    if args.other_forms:
+        for p in ("p64", "p32_t64", "p32_kahan"):
+            if p == args.precision:
+                continue
+            d2 = "f64" if p == "p64" else "f32"
+            arr2 = arrays if d2 == dt else [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64 if d2 == "f64" else np.float32)).to(dev)
+                                            for a in wl.rays.arrays()]
+            S2 = ctx.count_segments(0, p, arr2, counts, stream)
+            t2 = ctx.create_tally(0, p)
+            per2, tot2, _ = time_casts(vrc, ctx, t2, arr2, max(5, args.steps // 5), 2, stream, torch)
+            others[p] = {"segments_per_s": S2 * len(per2) / (tot2 / 1e3), "ms_per_step": tot2 / len(per2),
+                         "hbm_frac": (RAY_BYTES[d2] * R + SEG_BYTES * S2) / (float(np.mean(per2)) / 1e3) / 1e9 / HBM_PEAK_GBS}
+            log(f"bench: form {p}: {others[p]['segments_per_s']:.3e} segments/s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on a sample")
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+    out = {
+        "metric": "ray-voxel segments/sec on 1 MI355X + % HBM roofline; p99 batch latency",
+        "value": value,
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if dt == "f32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "multimat: 100^3 mesh of 0.5 cm voxels, 3 materials in 10-voxel z slabs, "
+                        "20k-point log-energy Sigma_t tables, 1e6 rays (uniform origins, isotropic, "
+                        "log-uniform E, lognormal w)",
+            "rays_per_step": R,
+            "segments_per_step": S,
+            "precision": args.precision,
+            "tally_dtype": "f64" if args.precision != "p32_kahan" else "f32+f32 compensated",
+            "launch": launch,
+        },
+        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
+                       "what": "per-batch kernel time of 1e6-ray batches (HIP events on the launch stream)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel_ms": kern_s * 1e3},
+        "cpu_baseline": cpu,
+        "other_forms": others,
+        "wall_s_timed": wall,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * vrc.h - C ABI of the volumetric-ray-casting (VRC) fluence tally library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the VRC estimator of Sweezy (arXiv:1706.07476),
+ * Eq. 4: every ray (collision point r, unit direction u, energy E, weight w)
+ * is cast through a Cartesian voxel mesh, and each voxel i it crosses
+ * receives
+ *
+ *     F_i = w * exp(-tau_in,i) * (1 - exp(-Sigma_i(E) l_i)) / Sigma_i(E)
+ *
+ * where l_i is the ray's length in voxel i, Sigma_i(E) the total macroscopic
+ * cross section of the voxel's material at the ray energy (Sec. 3: table
+ * lookup with linear interpolation), and tau_in,i the optical depth from the
+ * ray origin to the entry of voxel i (Eq. 2).  For Sigma_i = 0 the limit
+ * w exp(-tau_in,i) l_i is scored.  The 1/N of Eq. 4 (N rays per collision)
+ * is the caller's: pass w already divided by N.
+ *
+ * Conventions that hold for every call:
+ *   - Every function returns a vrc_status; VRC_OK is 0, errors are negative.
+ *     The text of the last error of the calling thread is vrc_last_error().
+ *   - A device fault seen by the library is sticky: every later call on the
+ *     same context returns VRC_ERR_DEVICE.
+ *   - Meshes are uniform per axis: lo[3] (cm), h[3] (cm), n[3] voxels; voxel
+ *     (i,j,k) covers [lo+i h, lo+(i+1) h) on each axis (half-open), and has
+ *     linear index i + n0 (j + n1 k) ("x fastest").  Outside the mesh is
+ *     vacuum: rays start scoring where they enter and stop where they leave
+ *     (Sec. 5.1: no reflecting boundary).
+ *   - Tallies are raw sums in weight * cm, laid out [bin][k][j][i]; divide by
+ *     the voxel volume and the source count to get a fluence.
+ *   - Host pointers passed in are read before the call returns (the caller
+ *     may reuse them at once, as the paper's CPU clears its ray buffer right
+ *     after the transfer, Sec. 3).  Device pointers are borrowed until the
+ *     work queued on the given stream has finished.
+ *   - Streams are HIP streams passed as void*; NULL is the null stream.
+ *   - Configuration calls (vrc_set_mesh, vrc_set_xs_tables, tally creation
+ *     and destruction) must not run concurrently with casting on the same
+ *     context.  Casting calls are serialised internally per context.
+ */
+#ifndef VRC_H
+#define VRC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vrc_ctx vrc_ctx;
+
+typedef enum {
+    VRC_OK = 0,
+    VRC_ERR_INVALID = -1,   /* bad argument: id, size, enum, table order, dtype */
+    VRC_ERR_STATE = -2,     /* call out of order (no mesh, no tables, ...)     */
+    VRC_ERR_NOMEM = -3,     /* device or pinned host allocation failed         */
+    VRC_ERR_DEVICE = -4,    /* a HIP call failed; sticky for the context       */
+    VRC_ERR_BUSY = -5,      /* admission refused (serving form)                */
+    VRC_ERR_TIMEOUT = -6,   /* a wait ran out of time                          */
+    VRC_ERR_CAPACITY = -7   /* output buffer too small (trace hook)            */
+} vrc_status;
+
+/* Arithmetic of a tally (Sec. 3 of the paper computes Eq. 4 in double
+ * precision from single-precision distances; the forms here are):          */
+typedef enum {
+    VRC_P64 = 0,        /* FP64 traversal, optical depth, exponentials, FP64 tally  */
+    VRC_P32_T64 = 1,    /* FP32 traversal/optical depth/exponentials, FP64 tally    */
+    VRC_P32_KAHAN = 2   /* FP32 throughout, tally kept as an FP32 sum plus an FP32
+                           compensation term (read back as their FP64 sum)          */
+} vrc_precision;
+
+/* A batch of rays as a structure of arrays, n entries each.
+ * ox,oy,oz: origin (cm); ux,uy,uz: unit direction; e: energy (MeV);
+ * w: weight (already divided by the number of rays per collision).
+ * fp64 = 1: the eight arrays are double; 0: float.  The FP64 tally form
+ * computes in double whatever the input type; the FP32 forms round double
+ * inputs to float on load.
+ * on_device = 1: device pointers (borrowed until the stream work ends);
+ * 0: host pointers (copied before the call returns).                       */
+typedef struct {
+    int64_t n;
+    const void *ox, *oy, *oz, *ux, *uy, *uz, *e, *w;
+    int32_t fp64;
+    int32_t on_device;
+} vrc_ray_batch;
+
+/* Launch shape of the casting kernel (chosen by the autotuner or by hand).
+ * block: threads per block (64..1024, multiple of 64); blocks_per_cu: resident
+ * blocks per compute unit of the grid-stride launch (0: one block per 'block'
+ * rays, no grid stride); hash_in_lds: stage the energy hash index in LDS
+ * (1) or read it from global memory (0); aggregate: combine the scores of
+ * lanes of a wavefront that hit the same voxel before the atomic (1) or not
+ * (0).  None of these change results beyond the order of summation.         */
+typedef struct {
+    int32_t block;
+    int32_t blocks_per_cu;
+    int32_t hash_in_lds;
+    int32_t aggregate;
+} vrc_launch;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  *out receives the handle.
+ * Errors: VRC_ERR_INVALID (no such device), VRC_ERR_DEVICE.               */
+vrc_status vrc_create(int device, vrc_ctx **out);
+
+/* Free every device and host resource of the context (waits for its work). */
+vrc_status vrc_destroy(vrc_ctx *ctx);
+
+/* Text of the last error returned to the calling thread ("" if none).      */
+const char *vrc_last_error(void);
+
+/* Library version string. */
+const char *vrc_version(void);
+
+/* ---- problem set-up (Sec. 3: Cartesian mesh, continuous-energy total
+ *      cross sections) ------------------------------------------------- */
+
+/* Define (or replace) mesh `mesh_id` (0..7).  lo, h (h > 0) in cm; n > 0;
+ * mat: host array of n0*n1*n2 material ids (x fastest), copied.  Replacing
+ * a mesh that tallies refer to is VRC_ERR_STATE.                           */
+vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const double h[3],
+                        const int32_t n[3], const uint8_t *mat);
+
+/* Total macroscopic cross sections Sigma_t(E) of n_mat materials (1..64).
+ * Material m's table is energy_MeV[offs[m] .. offs[m+1]) (strictly
+ * increasing, > 0) with values sigma_per_cm[...] (>= 0, finite); offs has
+ * n_mat+1 entries starting at 0.  Between table points Sigma is linear in E;
+ * outside a table the end value holds (Sec. 3: linear interpolation between
+ * table values).  Host arrays, copied.  Internally the tables are merged
+ * onto the union energy grid (exactly the same piecewise-linear functions)
+ * with a hashed log-energy index.                                          */
+vrc_status vrc_set_xs_tables(vrc_ctx *ctx, int n_mat, const int64_t *offs,
+                             const double *energy_MeV, const double *sigma_per_cm);
+
+/* ---- tallies (Sec. 3: the tally stays on the GPU until the end) ------- */
+
+/* Create a zeroed tally on mesh `mesh_id` with n_ebins energy bins
+ * (1..64; bin b takes edges[b] <= E < edges[b+1], the top edge belongs to
+ * the last bin, other energies are not scored; edges may be NULL when
+ * n_ebins == 1, then every energy is scored) in the given precision form.
+ * *tally_id receives the id.                                               */
+vrc_status vrc_create_tally(vrc_ctx *ctx, int mesh_id, int n_ebins, const double *edges,
+                            vrc_precision precision, int *tally_id);
+
+vrc_status vrc_destroy_tally(vrc_ctx *ctx, int tally_id);
+
+/* Number of doubles vrc_read_tally writes (n_ebins * n0 * n1 * n2).       */
+vrc_status vrc_tally_size(vrc_ctx *ctx, int tally_id, int64_t *n_values);
+
+/* Cast a ray batch into a tally (Eq. 4 per crossed voxel; Sec. 3: one call
+ * per full ray buffer).  Asynchronous on `hip_stream`: returns once the work
+ * is queued (host batches have been copied to pinned memory by then).
+ * Errors: VRC_ERR_INVALID (batch, id), VRC_ERR_STATE (no tables, material id
+ * >= n_mat in the mesh), VRC_ERR_DEVICE.                                   */
+vrc_status vrc_cast_rays(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch, void *hip_stream);
+
+/* Copy the tally to host memory `out` (vrc_tally_size doubles).  Waits for
+ * all casting queued on the context's streams.                              */
+vrc_status vrc_read_tally(vrc_ctx *ctx, int tally_id, double *out);
+
+/* Overwrite the tally with host values `in` (checkpoint restore).          */
+vrc_status vrc_load_tally(vrc_ctx *ctx, int tally_id, const double *in);
+
+/* Zero the tally. */
+vrc_status vrc_reset_tally(vrc_ctx *ctx, int tally_id);
+
+/* ---- launch shape ----------------------------------------------------- */
+
+vrc_status vrc_set_launch(vrc_ctx *ctx, const vrc_launch *launch);
+vrc_status vrc_get_launch(vrc_ctx *ctx, vrc_launch *launch);
+
+/* ---- inspection hooks (not on the timed path) ------------------------- */
+
+/* Number of positive-length voxel segments of every ray of a batch on mesh
+ * `mesh_id`, in the traversal precision of `precision` (FP64 for VRC_P64,
+ * FP32 otherwise).  counts: device array of batch->n int64 (written on
+ * `hip_stream`); *total (host, may be NULL) receives their sum after the
+ * stream has been synchronised.                                            */
+vrc_status vrc_count_segments(vrc_ctx *ctx, int mesh_id, vrc_precision precision,
+                              const vrc_ray_batch *batch, int64_t *counts, int64_t *total,
+                              void *hip_stream);
+
+/* Per-ray voxel sequences, lengths and scores, exactly as the casting kernel
+ * of `tally_id` computes them (same traversal and arithmetic), written as
+ * CSR into host arrays: offs[batch->n + 1], voxel[cap], len[cap],
+ * score[cap]; the tally itself is not changed.  Scores of rays whose energy
+ * is outside the tally's bins are 0.  Returns VRC_ERR_CAPACITY (with
+ * offs[batch->n] holding the needed size) if cap is too small.  Synchronous. */
+vrc_status vrc_trace_rays(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch,
+                          int64_t *offs, int64_t *voxel, double *len, double *score, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VRC_H */

@@ -1,0 +1,373 @@
+"""Python binding of libvrc.so, the MI355X (gfx950) library of the VRC estimator.
+
+The volumetric-ray-casting (VRC) estimator (Sweezy, arXiv:1706.07476, Eq. 4)
+scores, for every ray and every voxel it crosses, the expected track length
+``w exp(-tau_in) (1 - exp(-Sigma l)) / Sigma``.  All of that runs in the HIP
+kernels of ``libvrc.so``; this module only marshals arguments for the C ABI
+declared in ``include/vrc.h`` (same function names, ctypes).  Device buffers
+and streams may be PyTorch tensors and ``torch.cuda.Stream`` objects, or raw
+integers.
+
+There is no CPU fallback: if ``libvrc.so`` has not been built, importing works
+but every call raises ``VrcError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvrc.so")
+
+VRC_OK = 0
+VRC_ERR_INVALID = -1
+VRC_ERR_STATE = -2
+VRC_ERR_NOMEM = -3
+VRC_ERR_DEVICE = -4
+VRC_ERR_BUSY = -5
+VRC_ERR_TIMEOUT = -6
+VRC_ERR_CAPACITY = -7
+
+VRC_P64 = 0
+VRC_P32_T64 = 1
+VRC_P32_KAHAN = 2
+PRECISIONS = {"p64": VRC_P64, "p32_t64": VRC_P32_T64, "p32_kahan": VRC_P32_KAHAN}
+
+_STATUS_NAMES = {
+    VRC_ERR_INVALID: "VRC_ERR_INVALID", VRC_ERR_STATE: "VRC_ERR_STATE", VRC_ERR_NOMEM: "VRC_ERR_NOMEM",
+    VRC_ERR_DEVICE: "VRC_ERR_DEVICE", VRC_ERR_BUSY: "VRC_ERR_BUSY", VRC_ERR_TIMEOUT: "VRC_ERR_TIMEOUT",
+    VRC_ERR_CAPACITY: "VRC_ERR_CAPACITY",
+}
+
+
+class VrcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class vrc_ray_batch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(f, ctypes.c_void_p) for f in ("ox", "oy", "oz", "ux", "uy", "uz", "e", "w")] + [
+        ("fp64", ctypes.c_int32), ("on_device", ctypes.c_int32)]
+
+
+class vrc_launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("hash_in_lds", ctypes.c_int32),
+                ("aggregate", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+_PD = ctypes.POINTER(ctypes.c_double)
+
+# name -> argtypes (restype is vrc_status = int unless given)
+_SIGNATURES = {
+    "vrc_create": [_I, ctypes.POINTER(_P)],
+    "vrc_destroy": [_P],
+    "vrc_set_mesh": [_P, _I, _PD, _PD, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8)],
+    "vrc_set_xs_tables": [_P, _I, _PI64, _PD, _PD],
+    "vrc_create_tally": [_P, _I, _I, _PD, _I, ctypes.POINTER(_I)],
+    "vrc_destroy_tally": [_P, _I],
+    "vrc_tally_size": [_P, _I, _PI64],
+    "vrc_cast_rays": [_P, _I, ctypes.POINTER(vrc_ray_batch), _P],
+    "vrc_read_tally": [_P, _I, _PD],
+    "vrc_load_tally": [_P, _I, _PD],
+    "vrc_reset_tally": [_P, _I],
+    "vrc_set_launch": [_P, ctypes.POINTER(vrc_launch)],
+    "vrc_get_launch": [_P, ctypes.POINTER(vrc_launch)],
+    "vrc_count_segments": [_P, _I, _I, ctypes.POINTER(vrc_ray_batch), _P, _PI64, _P],
+    "vrc_trace_rays": [_P, _I, ctypes.POINTER(vrc_ray_batch), _PI64, _PI64, _PD, _PD, _I64],
+}
+_STRING_FUNCS = {"vrc_last_error": [], "vrc_version": []}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libvrc.so (once).  Raises VrcError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise VrcError(VRC_ERR_STATE, f"{path} is missing: build it with paper_1706_07476_amd/build.py "
+                                      "(or __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    for name, args in _SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    for name, args in _STRING_FUNCS.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names of the C entry points this binding expects libvrc.so to export."""
+    return sorted(list(_SIGNATURES) + list(_STRING_FUNCS))
+
+
+def _check(st: int):
+    if st != VRC_OK:
+        raise VrcError(st, load_library().vrc_last_error().decode())
+
+
+def _ptr(x) -> int:
+    """Device or host address of a torch tensor, numpy array or integer."""
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return int(x.ctypes.data)
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(s) -> int:
+    if s is None:
+        return 0
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def make_batch(arrays: Sequence, on_device: Optional[bool] = None) -> vrc_ray_batch:
+    """vrc_ray_batch over 8 equal-length arrays (ox, oy, oz, ux, uy, uz, e, w).
+
+    torch tensors (CUDA/HIP or CPU) or numpy arrays; all float32 or all
+    float64, contiguous.  The arrays must stay alive while the call using the
+    batch may still read them.
+    """
+    if len(arrays) != 8:
+        raise ValueError("a ray batch has 8 arrays")
+    n = None
+    fp64 = None
+    dev = None
+    for a in arrays:
+        if hasattr(a, "data_ptr") and not isinstance(a, np.ndarray):
+            import torch
+            if not a.is_contiguous():
+                raise ValueError("ray arrays must be contiguous")
+            if a.dtype not in (torch.float32, torch.float64):
+                raise ValueError("ray arrays must be float32 or float64")
+            is64 = a.dtype == torch.float64
+            d = a.is_cuda
+            k = a.numel()
+        else:
+            if not a.flags["C_CONTIGUOUS"] or a.dtype not in (np.float32, np.float64):
+                raise ValueError("ray arrays must be contiguous float32/float64")
+            is64 = a.dtype == np.float64
+            d = False
+            k = a.size
+        n = k if n is None else n
+        fp64 = is64 if fp64 is None else fp64
+        dev = d if dev is None else dev
+        if k != n or is64 != fp64 or d != dev:
+            raise ValueError("ray arrays must agree in length, dtype and device")
+    b = vrc_ray_batch()
+    b.n = int(n)
+    for f, a in zip(("ox", "oy", "oz", "ux", "uy", "uz", "e", "w"), arrays):
+        setattr(b, f, _ptr(a))
+    b.fp64 = 1 if fp64 else 0
+    b.on_device = int(dev if on_device is None else on_device)
+    return b
+
+
+# ----------------------------------------------------------------------------
+# thin wrappers with the C names
+# ----------------------------------------------------------------------------
+
+def vrc_create(device: int = 0) -> int:
+    L = load_library()
+    h = ctypes.c_void_p()
+    _check(L.vrc_create(device, ctypes.byref(h)))
+    return h.value
+
+
+def vrc_destroy(ctx: int) -> None:
+    _check(load_library().vrc_destroy(ctx))
+
+
+def vrc_version() -> str:
+    return load_library().vrc_version().decode()
+
+
+def vrc_set_mesh(ctx: int, mesh_id: int, lo, h, n, mat) -> None:
+    lo = np.ascontiguousarray(lo, np.float64)
+    h = np.ascontiguousarray(h, np.float64)
+    n = np.ascontiguousarray(n, np.int32)
+    mat = np.ascontiguousarray(mat, np.uint8)
+    if lo.size != 3 or h.size != 3 or n.size != 3 or mat.size != int(np.prod(n.astype(np.int64))):
+        raise ValueError("mesh arrays have the wrong size")
+    _check(load_library().vrc_set_mesh(ctx, mesh_id, lo.ctypes.data_as(_PD), h.ctypes.data_as(_PD),
+                                       n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       mat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+
+
+def vrc_set_xs_tables(ctx: int, offs, energy, sigma) -> None:
+    offs = np.ascontiguousarray(offs, np.int64)
+    energy = np.ascontiguousarray(energy, np.float64)
+    sigma = np.ascontiguousarray(sigma, np.float64)
+    if energy.size != sigma.size or offs.size < 2 or offs[-1] != energy.size:
+        raise ValueError("table arrays disagree")
+    _check(load_library().vrc_set_xs_tables(ctx, offs.size - 1, offs.ctypes.data_as(_PI64),
+                                            energy.ctypes.data_as(_PD), sigma.ctypes.data_as(_PD)))
+
+
+def vrc_create_tally(ctx: int, mesh_id: int, precision="p64", edges=None) -> int:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    tid = ctypes.c_int(-1)
+    if edges is None:
+        _check(load_library().vrc_create_tally(ctx, mesh_id, 1, ctypes.cast(None, _PD), prec, ctypes.byref(tid)))
+    else:
+        ed = np.ascontiguousarray(edges, np.float64)
+        _check(load_library().vrc_create_tally(ctx, mesh_id, ed.size - 1, ed.ctypes.data_as(_PD), prec,
+                                               ctypes.byref(tid)))
+    return tid.value
+
+
+def vrc_destroy_tally(ctx: int, tally_id: int) -> None:
+    _check(load_library().vrc_destroy_tally(ctx, tally_id))
+
+
+def vrc_tally_size(ctx: int, tally_id: int) -> int:
+    n = ctypes.c_int64(0)
+    _check(load_library().vrc_tally_size(ctx, tally_id, ctypes.byref(n)))
+    return n.value
+
+
+def vrc_cast_rays(ctx: int, tally_id: int, batch: vrc_ray_batch, stream=None) -> None:
+    _check(load_library().vrc_cast_rays(ctx, tally_id, ctypes.byref(batch), _stream(stream)))
+
+
+def vrc_read_tally(ctx: int, tally_id: int) -> np.ndarray:
+    out = np.empty(vrc_tally_size(ctx, tally_id), np.float64)
+    _check(load_library().vrc_read_tally(ctx, tally_id, out.ctypes.data_as(_PD)))
+    return out
+
+
+def vrc_load_tally(ctx: int, tally_id: int, values) -> None:
+    v = np.ascontiguousarray(values, np.float64).reshape(-1)
+    if v.size != vrc_tally_size(ctx, tally_id):
+        raise ValueError("wrong tally size")
+    _check(load_library().vrc_load_tally(ctx, tally_id, v.ctypes.data_as(_PD)))
+
+
+def vrc_reset_tally(ctx: int, tally_id: int) -> None:
+    _check(load_library().vrc_reset_tally(ctx, tally_id))
+
+
+def vrc_set_launch(ctx: int, block=256, blocks_per_cu=8, hash_in_lds=1, aggregate=0) -> None:
+    _check(load_library().vrc_set_launch(ctx, ctypes.byref(vrc_launch(block, blocks_per_cu, hash_in_lds, aggregate))))
+
+
+def vrc_get_launch(ctx: int) -> dict:
+    l = vrc_launch()
+    _check(load_library().vrc_get_launch(ctx, ctypes.byref(l)))
+    return {"block": l.block, "blocks_per_cu": l.blocks_per_cu, "hash_in_lds": l.hash_in_lds,
+            "aggregate": l.aggregate}
+
+
+def vrc_count_segments(ctx: int, mesh_id: int, precision, batch: vrc_ray_batch, counts, stream=None,
+                       want_total: bool = True) -> Optional[int]:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    tot = ctypes.c_int64(0)
+    _check(load_library().vrc_count_segments(ctx, mesh_id, prec, ctypes.byref(batch), _ptr(counts),
+                                             ctypes.byref(tot) if want_total else ctypes.cast(None, _PI64),
+                                             _stream(stream)))
+    return tot.value if want_total else None
+
+
+def vrc_trace_rays(ctx: int, tally_id: int, batch: vrc_ray_batch, cap: Optional[int] = None):
+    """CSR (offs, voxel, len, score) of every ray, as the casting kernel computes them."""
+    L = load_library()
+    offs = np.zeros(batch.n + 1, np.int64)
+    if cap is None:
+        st = L.vrc_trace_rays(ctx, tally_id, ctypes.byref(batch), offs.ctypes.data_as(_PI64),
+                              ctypes.cast(None, _PI64), ctypes.cast(None, _PD), ctypes.cast(None, _PD), 0)
+        if st not in (VRC_OK, VRC_ERR_CAPACITY):
+            _check(st)
+        cap = int(offs[-1])
+    vox = np.empty(max(cap, 1), np.int64)
+    ln = np.empty(max(cap, 1), np.float64)
+    sc = np.empty(max(cap, 1), np.float64)
+    _check(L.vrc_trace_rays(ctx, tally_id, ctypes.byref(batch), offs.ctypes.data_as(_PI64),
+                            vox.ctypes.data_as(_PI64), ln.ctypes.data_as(_PD), sc.ctypes.data_as(_PD), cap))
+    k = int(offs[-1])
+    return offs, vox[:k], ln[:k], sc[:k]
+
+
+# ----------------------------------------------------------------------------
+# convenience object
+# ----------------------------------------------------------------------------
+
+class Context:
+    """One libvrc context on one device, with the C calls as methods."""
+
+    def __init__(self, device: int = 0):
+        self.handle = vrc_create(device)
+
+    def close(self):
+        if self.handle:
+            vrc_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mesh(self, mesh_id: int, mesh) -> None:
+        vrc_set_mesh(self.handle, mesh_id, mesh.lo, mesh.h, mesh.n, mesh.mat)
+
+    def set_xs(self, xs) -> None:
+        vrc_set_xs_tables(self.handle, xs.offs, xs.energy, xs.sigma)
+
+    def create_tally(self, mesh_id: int, precision="p64", edges=None) -> int:
+        return vrc_create_tally(self.handle, mesh_id, precision, edges)
+
+    def destroy_tally(self, tally_id: int) -> None:
+        vrc_destroy_tally(self.handle, tally_id)
+
+    def cast(self, tally_id: int, arrays, stream=None) -> None:
+        b = make_batch(arrays)
+        vrc_cast_rays(self.handle, tally_id, b, stream)
+
+    def read(self, tally_id: int) -> np.ndarray:
+        return vrc_read_tally(self.handle, tally_id)
+
+    def load(self, tally_id: int, values) -> None:
+        vrc_load_tally(self.handle, tally_id, values)
+
+    def reset(self, tally_id: int) -> None:
+        vrc_reset_tally(self.handle, tally_id)
+
+    def set_launch(self, **kw) -> None:
+        cur = vrc_get_launch(self.handle)
+        cur.update(kw)
+        vrc_set_launch(self.handle, **cur)
+
+    def get_launch(self) -> dict:
+        return vrc_get_launch(self.handle)
+
+    def trace(self, tally_id: int, arrays):
+        return vrc_trace_rays(self.handle, tally_id, make_batch(arrays))
+
+    def count_segments(self, mesh_id: int, precision, arrays, counts, stream=None) -> int:
+        return vrc_count_segments(self.handle, mesh_id, precision, make_batch(arrays), counts, stream)

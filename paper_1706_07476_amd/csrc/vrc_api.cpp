@@ -1,0 +1,600 @@
+// C-ABI entry points: context, mesh and cross-section upload, tallies,
+// casting, read-back and the inspection hooks.  Everything declared in
+// include/vrc.h that is not a kernel lives here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vrc_internal.h"
+
+namespace vrc {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+vrc_status set_error(vrc_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+}  // namespace vrc
+
+using namespace vrc;
+
+namespace {
+
+// Device failure: remember it for the context and report it.
+vrc_status device_error(vrc_ctx *ctx, hipError_t e, const char *what)
+{
+    if (ctx) ctx->sticky.store(1);
+    return set_error(VRC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define VRC_HIP(ctx, call)                                        \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return device_error(ctx, e_, #call); \
+    } while (0)
+
+vrc_status check_ctx(vrc_ctx *ctx)
+{
+    if (!ctx) return set_error(VRC_ERR_INVALID, "null context");
+    if (ctx->sticky.load()) return set_error(VRC_ERR_DEVICE, "an earlier device error is sticky for this context");
+    return VRC_OK;
+}
+
+TallyHost *get_tally(vrc_ctx *ctx, int id)
+{
+    if (id < 0 || id >= static_cast<int>(ctx->tallies.size())) return nullptr;
+    return ctx->tallies[id].get();
+}
+
+template <typename T>
+void free_dev(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+vrc_status upload(vrc_ctx *ctx, void **dst, const void *src, size_t bytes)
+{
+    *dst = nullptr;
+    if (bytes == 0) return VRC_OK;
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        return set_error(VRC_ERR_NOMEM, "hipMalloc failed");
+    }
+    VRC_HIP(ctx, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return VRC_OK;
+}
+
+void free_xs(XsHost &x)
+{
+    free_dev(x.d_E64);
+    free_dev(x.d_S64);
+    free_dev(x.d_E32);
+    free_dev(x.d_S32);
+    free_dev(x.d_hash32);
+    free_dev(x.d_hash64);
+}
+
+vrc_status validate_batch(const vrc_ray_batch *b)
+{
+    if (!b) return set_error(VRC_ERR_INVALID, "null batch");
+    if (b->n < 0) return set_error(VRC_ERR_INVALID, "negative ray count");
+    if (b->n > (int64_t(1) << 40)) return set_error(VRC_ERR_INVALID, "ray count too large");
+    if (b->n == 0) return VRC_OK;
+    if (!b->ox || !b->oy || !b->oz || !b->ux || !b->uy || !b->uz || !b->e || !b->w)
+        return set_error(VRC_ERR_INVALID, "null ray array");
+    if (b->fp64 != 0 && b->fp64 != 1) return set_error(VRC_ERR_INVALID, "fp64 must be 0 or 1");
+    if (b->on_device != 0 && b->on_device != 1) return set_error(VRC_ERR_INVALID, "on_device must be 0 or 1");
+    return VRC_OK;
+}
+
+// Rays of a batch as device pointers.  Host batches go through a pinned
+// slot and an asynchronous copy on stream s; the slot's event (recorded
+// after the kernel by mark_stage_used) keeps it from being overwritten
+// while still in use.
+vrc_status stage_rays(vrc_ctx *ctx, const vrc_ray_batch *b, hipStream_t s, RaysP &out, int &slot_used)
+{
+    slot_used = -1;
+    out.n = b->n;
+    if (b->on_device || b->n == 0) {
+        out.ox = b->ox; out.oy = b->oy; out.oz = b->oz;
+        out.ux = b->ux; out.uy = b->uy; out.uz = b->uz;
+        out.e = b->e; out.w = b->w;
+        return VRC_OK;
+    }
+    const size_t el = b->fp64 ? 8 : 4;
+    const size_t arr = el * static_cast<size_t>(b->n);
+    const size_t need = 8 * arr;
+    const int si = ctx->stage_next;
+    ctx->stage_next ^= 1;
+    StageSlot &st = ctx->stage[si];
+    if (st.used) VRC_HIP(ctx, hipEventSynchronize(st.done));
+    if (st.cap < need) {
+        if (st.h_buf) (void)hipHostFree(st.h_buf);
+        free_dev(st.d_buf);
+        st.h_buf = nullptr;
+        st.cap = 0;
+        if (hipHostMalloc(&st.h_buf, need, hipHostMallocDefault) != hipSuccess) {
+            st.h_buf = nullptr;
+            return set_error(VRC_ERR_NOMEM, "pinned staging allocation failed");
+        }
+        if (hipMalloc(&st.d_buf, need) != hipSuccess) {
+            st.d_buf = nullptr;
+            return set_error(VRC_ERR_NOMEM, "device staging allocation failed");
+        }
+        st.cap = need;
+    }
+    const void *src[8] = {b->ox, b->oy, b->oz, b->ux, b->uy, b->uz, b->e, b->w};
+    for (int i = 0; i < 8; ++i) std::memcpy(static_cast<char *>(st.h_buf) + i * arr, src[i], arr);
+    VRC_HIP(ctx, hipMemcpyAsync(st.d_buf, st.h_buf, need, hipMemcpyHostToDevice, s));
+    const char *d = static_cast<const char *>(st.d_buf);
+    out.ox = d; out.oy = d + arr; out.oz = d + 2 * arr;
+    out.ux = d + 3 * arr; out.uy = d + 4 * arr; out.uz = d + 5 * arr;
+    out.e = d + 6 * arr; out.w = d + 7 * arr;
+    slot_used = si;
+    return VRC_OK;
+}
+
+vrc_status mark_stage_used(vrc_ctx *ctx, int slot, hipStream_t s)
+{
+    if (slot < 0) return VRC_OK;
+    StageSlot &st = ctx->stage[slot];
+    VRC_HIP(ctx, hipEventRecord(st.done, s));
+    st.used = true;
+    return VRC_OK;
+}
+
+vrc_status check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
+{
+    if (!ctx->xs.set) return set_error(VRC_ERR_STATE, "no cross-section tables set");
+    const MeshHost &m = ctx->meshes[t->mesh_id];
+    if (!m.set) return set_error(VRC_ERR_STATE, "tally mesh is not set");
+    if (m.max_mat >= ctx->xs.n_mat) return set_error(VRC_ERR_STATE, "mesh has a material id >= n_mat");
+    if (t->prec != VRC_P64 && !ctx->xs.f32_ok)
+        return set_error(VRC_ERR_INVALID, "energy grid is not strictly increasing once rounded to FP32");
+    return VRC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vrc_last_error(void) { return g_last_error.c_str(); }
+
+const char *vrc_version(void) { return "vrc-mi355x 0.1 (gfx950)"; }
+
+vrc_status vrc_create(int device, vrc_ctx **out)
+{
+    if (!out) return set_error(VRC_ERR_INVALID, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return set_error(VRC_ERR_DEVICE, std::string("hipGetDeviceCount: ") + hipGetErrorString(e));
+    if (device < 0 || device >= n) return set_error(VRC_ERR_INVALID, "no such device");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return set_error(VRC_ERR_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return set_error(VRC_ERR_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+    auto *ctx = new vrc_ctx();
+    ctx->device = device;
+    ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    for (auto &st : ctx->stage) {
+        e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            delete ctx;
+            return set_error(VRC_ERR_DEVICE, "hipEventCreate failed");
+        }
+    }
+    *out = ctx;
+    return VRC_OK;
+}
+
+vrc_status vrc_destroy(vrc_ctx *ctx)
+{
+    if (!ctx) return VRC_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &t : ctx->tallies) {
+        if (t) {
+            free_dev(t->d_data);
+            free_dev(t->d_edges);
+        }
+    }
+    for (auto &m : ctx->meshes) free_dev(m.d_mat);
+    free_xs(ctx->xs);
+    for (auto &st : ctx->stage) {
+        if (st.h_buf) (void)hipHostFree(st.h_buf);
+        free_dev(st.d_buf);
+        if (st.done) (void)hipEventDestroy(st.done);
+    }
+    delete ctx;
+    return VRC_OK;
+}
+
+vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const double h[3], const int32_t n[3],
+                        const uint8_t *mat)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (mesh_id < 0 || mesh_id >= kMaxMeshes) return set_error(VRC_ERR_INVALID, "mesh_id must be in 0..7");
+    if (!lo || !h || !n || !mat) return set_error(VRC_ERR_INVALID, "null mesh argument");
+    int64_t nvox = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(std::isfinite(lo[a]) && std::isfinite(h[a]) && h[a] > 0))
+            return set_error(VRC_ERR_INVALID, "lo must be finite and h finite and > 0");
+        if (n[a] <= 0 || n[a] > (1 << 20)) return set_error(VRC_ERR_INVALID, "n must be in 1..2^20 per axis");
+        nvox *= n[a];
+    }
+    if (nvox >= (int64_t(1) << 31)) return set_error(VRC_ERR_INVALID, "mesh too large (at most 2^31-1 voxels)");
+    MeshHost &m = ctx->meshes[mesh_id];
+    if (m.users > 0) return set_error(VRC_ERR_STATE, "mesh is used by a tally");
+    (void)hipSetDevice(ctx->device);
+    int max_mat = 0;
+    for (int64_t i = 0; i < nvox; ++i) max_mat = std::max(max_mat, static_cast<int>(mat[i]));
+    free_dev(m.d_mat);
+    m.set = false;
+    void *d = nullptr;
+    if (vrc_status s = upload(ctx, &d, mat, static_cast<size_t>(nvox))) return s;
+    m.d_mat = static_cast<uint8_t *>(d);
+    for (int a = 0; a < 3; ++a) {
+        m.lo[a] = lo[a];
+        m.h[a] = h[a];
+        m.n[a] = n[a];
+    }
+    m.nvox = nvox;
+    m.max_mat = max_mat;
+    m.set = true;
+    return VRC_OK;
+}
+
+vrc_status vrc_set_xs_tables(vrc_ctx *ctx, int n_mat, const int64_t *offs, const double *energy_MeV,
+                             const double *sigma_per_cm)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    XsHost x;
+    if (vrc_status s = build_xs(n_mat, offs, energy_MeV, sigma_per_cm, x)) return s;
+    (void)hipSetDevice(ctx->device);
+    VRC_HIP(ctx, hipDeviceSynchronize());
+    free_xs(ctx->xs);
+    ctx->xs = XsHost();
+    // FP64 copies
+    std::vector<double> S64(static_cast<size_t>(x.K + 1) * x.s_stride64, 0.0);
+    std::vector<float> S32(static_cast<size_t>(x.K + 1) * x.s_stride32, 0.f);
+    std::vector<float> E32(x.K);
+    for (int k = 0; k < x.K; ++k) {
+        E32[k] = static_cast<float>(x.E[k]);
+        for (int m = 0; m < x.n_mat; ++m) {
+            const double v = x.S[static_cast<size_t>(k) * x.n_mat + m];
+            S64[static_cast<size_t>(k) * x.s_stride64 + m] = v;
+            S32[static_cast<size_t>(k) * x.s_stride32 + m] = static_cast<float>(v);
+        }
+    }
+    void *p = nullptr;
+    if (vrc_status s = upload(ctx, &p, x.E.data(), sizeof(double) * x.K)) return s;
+    x.d_E64 = static_cast<double *>(p);
+    if (vrc_status s = upload(ctx, &p, S64.data(), sizeof(double) * S64.size())) { free_xs(x); return s; }
+    x.d_S64 = static_cast<double *>(p);
+    if (vrc_status s = upload(ctx, &p, E32.data(), sizeof(float) * E32.size())) { free_xs(x); return s; }
+    x.d_E32 = static_cast<float *>(p);
+    if (vrc_status s = upload(ctx, &p, S32.data(), sizeof(float) * S32.size())) { free_xs(x); return s; }
+    x.d_S32 = static_cast<float *>(p);
+    if (vrc_status s = upload(ctx, &p, x.hash32.data(), sizeof(int32_t) * x.M)) { free_xs(x); return s; }
+    x.d_hash32 = static_cast<int32_t *>(p);
+    if (vrc_status s = upload(ctx, &p, x.hash64.data(), sizeof(int32_t) * x.M)) { free_xs(x); return s; }
+    x.d_hash64 = static_cast<int32_t *>(p);
+    ctx->xs = std::move(x);
+    return VRC_OK;
+}
+
+vrc_status vrc_create_tally(vrc_ctx *ctx, int mesh_id, int n_ebins, const double *edges, vrc_precision precision,
+                            int *tally_id)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!tally_id) return set_error(VRC_ERR_INVALID, "null tally_id");
+    if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
+        return set_error(VRC_ERR_INVALID, "mesh_id does not name a set mesh");
+    if (n_ebins < 1 || n_ebins > kMaxEbins) return set_error(VRC_ERR_INVALID, "n_ebins must be in 1..64");
+    if (precision != VRC_P64 && precision != VRC_P32_T64 && precision != VRC_P32_KAHAN)
+        return set_error(VRC_ERR_INVALID, "unknown precision");
+    if (n_ebins > 1 && !edges) return set_error(VRC_ERR_INVALID, "edges are required for more than one bin");
+    if (edges) {
+        for (int b = 0; b <= n_ebins; ++b) {
+            if (!std::isfinite(edges[b])) return set_error(VRC_ERR_INVALID, "edges must be finite");
+            if (b > 0 && !(edges[b] > edges[b - 1])) return set_error(VRC_ERR_INVALID, "edges must increase");
+        }
+    }
+    (void)hipSetDevice(ctx->device);
+    auto t = std::make_unique<TallyHost>();
+    t->mesh_id = mesh_id;
+    t->n_bins = n_ebins;
+    t->prec = precision;
+    t->nvox = ctx->meshes[mesh_id].nvox;
+    const size_t el = precision == VRC_P32_KAHAN ? 2 * sizeof(float) : sizeof(double);
+    t->bytes = el * static_cast<size_t>(t->nvox) * n_ebins;
+    if (hipMalloc(&t->d_data, t->bytes) != hipSuccess) {
+        t->d_data = nullptr;
+        return set_error(VRC_ERR_NOMEM, "tally allocation failed");
+    }
+    if (edges) {
+        void *p = nullptr;
+        if (vrc_status s = upload(ctx, &p, edges, sizeof(double) * (n_ebins + 1))) {
+            free_dev(t->d_data);
+            return s;
+        }
+        t->d_edges = static_cast<double *>(p);
+    }
+    hipError_t e = launch_fill_zero(t->d_data, t->bytes, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_dev(t->d_data);
+        free_dev(t->d_edges);
+        return device_error(ctx, e, "zeroing a new tally");
+    }
+    ctx->meshes[mesh_id].users++;
+    // reuse a free slot
+    for (size_t i = 0; i < ctx->tallies.size(); ++i) {
+        if (!ctx->tallies[i]) {
+            ctx->tallies[i] = std::move(t);
+            *tally_id = static_cast<int>(i);
+            return VRC_OK;
+        }
+    }
+    ctx->tallies.push_back(std::move(t));
+    *tally_id = static_cast<int>(ctx->tallies.size() - 1);
+    return VRC_OK;
+}
+
+vrc_status vrc_destroy_tally(vrc_ctx *ctx, int tally_id)
+{
+    if (!ctx) return set_error(VRC_ERR_INVALID, "null context");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    TallyHost *t = get_tally(ctx, tally_id);
+    if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_dev(t->d_data);
+    free_dev(t->d_edges);
+    ctx->meshes[t->mesh_id].users--;
+    ctx->tallies[tally_id].reset();
+    return VRC_OK;
+}
+
+vrc_status vrc_tally_size(vrc_ctx *ctx, int tally_id, int64_t *n_values)
+{
+    if (!ctx || !n_values) return set_error(VRC_ERR_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    TallyHost *t = get_tally(ctx, tally_id);
+    if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
+    *n_values = t->nvox * t->n_bins;
+    return VRC_OK;
+}
+
+vrc_status vrc_cast_rays(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch, void *hip_stream)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    if (vrc_status s = validate_batch(batch)) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    TallyHost *t = get_tally(ctx, tally_id);
+    if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
+    if (vrc_status s = check_cast_ready(ctx, t)) return s;
+    if (batch->n == 0) return VRC_OK;
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    RaysP rays;
+    int slot = -1;
+    if (vrc_status st = stage_rays(ctx, batch, s, rays, slot)) return st;
+    hipError_t e = launch_cast(*ctx, *t, ctx->meshes[t->mesh_id], rays, batch->fp64 != 0, s);
+    if (e != hipSuccess) return device_error(ctx, e, "cast kernel launch");
+    return mark_stage_used(ctx, slot, s);
+}
+
+vrc_status vrc_read_tally(vrc_ctx *ctx, int tally_id, double *out)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    if (!out) return set_error(VRC_ERR_INVALID, "null output");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    TallyHost *t = get_tally(ctx, tally_id);
+    if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
+    (void)hipSetDevice(ctx->device);
+    VRC_HIP(ctx, hipDeviceSynchronize());
+    const size_t n = static_cast<size_t>(t->nvox) * t->n_bins;
+    if (t->prec == VRC_P32_KAHAN) {
+        double *tmp = nullptr;
+        if (hipMalloc(&tmp, n * sizeof(double)) != hipSuccess) return set_error(VRC_ERR_NOMEM, "read buffer");
+        hipError_t e = launch_tally_to_f64(*t, tmp, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(out, tmp, n * sizeof(double), hipMemcpyDeviceToHost);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return device_error(ctx, e, "reading a compensated tally");
+    } else {
+        VRC_HIP(ctx, hipMemcpy(out, t->d_data, n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return VRC_OK;
+}
+
+vrc_status vrc_load_tally(vrc_ctx *ctx, int tally_id, const double *in)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    if (!in) return set_error(VRC_ERR_INVALID, "null input");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    TallyHost *t = get_tally(ctx, tally_id);
+    if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
+    (void)hipSetDevice(ctx->device);
+    VRC_HIP(ctx, hipDeviceSynchronize());
+    const size_t n = static_cast<size_t>(t->nvox) * t->n_bins;
+    if (t->prec == VRC_P32_KAHAN) {
+        double *tmp = nullptr;
+        if (hipMalloc(&tmp, n * sizeof(double)) != hipSuccess) return set_error(VRC_ERR_NOMEM, "load buffer");
+        hipError_t e = hipMemcpy(tmp, in, n * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_tally_from_f64(*t, tmp, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return device_error(ctx, e, "loading a compensated tally");
+    } else {
+        VRC_HIP(ctx, hipMemcpy(t->d_data, in, n * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return VRC_OK;
+}
+
+vrc_status vrc_reset_tally(vrc_ctx *ctx, int tally_id)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    TallyHost *t = get_tally(ctx, tally_id);
+    if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
+    (void)hipSetDevice(ctx->device);
+    VRC_HIP(ctx, hipDeviceSynchronize());
+    VRC_HIP(ctx, launch_fill_zero(t->d_data, t->bytes, nullptr));
+    VRC_HIP(ctx, hipDeviceSynchronize());
+    return VRC_OK;
+}
+
+vrc_status vrc_set_launch(vrc_ctx *ctx, const vrc_launch *l)
+{
+    if (!ctx || !l) return set_error(VRC_ERR_INVALID, "null argument");
+    if (l->block < 64 || l->block > 1024 || l->block % 64 != 0)
+        return set_error(VRC_ERR_INVALID, "block must be a multiple of 64 in 64..1024");
+    if (l->blocks_per_cu < 0 || l->blocks_per_cu > 64) return set_error(VRC_ERR_INVALID, "blocks_per_cu in 0..64");
+    if ((l->hash_in_lds != 0 && l->hash_in_lds != 1) || (l->aggregate != 0 && l->aggregate != 1))
+        return set_error(VRC_ERR_INVALID, "hash_in_lds and aggregate are 0 or 1");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->launch.block = l->block;
+    ctx->launch.blocks_per_cu = l->blocks_per_cu;
+    ctx->launch.hash_in_lds = l->hash_in_lds;
+    ctx->launch.aggregate = l->aggregate;
+    return VRC_OK;
+}
+
+vrc_status vrc_get_launch(vrc_ctx *ctx, vrc_launch *l)
+{
+    if (!ctx || !l) return set_error(VRC_ERR_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    l->block = ctx->launch.block;
+    l->blocks_per_cu = ctx->launch.blocks_per_cu;
+    l->hash_in_lds = ctx->launch.hash_in_lds;
+    l->aggregate = ctx->launch.aggregate;
+    return VRC_OK;
+}
+
+vrc_status vrc_count_segments(vrc_ctx *ctx, int mesh_id, vrc_precision precision, const vrc_ray_batch *batch,
+                              int64_t *counts, int64_t *total, void *hip_stream)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    if (vrc_status s = validate_batch(batch)) return s;
+    if (!counts && batch->n > 0) return set_error(VRC_ERR_INVALID, "null counts");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
+        return set_error(VRC_ERR_INVALID, "mesh_id does not name a set mesh");
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    RaysP rays;
+    int slot = -1;
+    if (vrc_status st = stage_rays(ctx, batch, s, rays, slot)) return st;
+    hipError_t e = launch_count(*ctx, ctx->meshes[mesh_id], precision, rays, batch->fp64 != 0, counts, s);
+    if (e != hipSuccess) return device_error(ctx, e, "count kernel launch");
+    if (vrc_status st = mark_stage_used(ctx, slot, s)) return st;
+    if (total) {
+        *total = 0;
+        if (batch->n > 0) {
+            VRC_HIP(ctx, hipStreamSynchronize(s));
+            std::vector<int64_t> h(static_cast<size_t>(batch->n));
+            VRC_HIP(ctx, hipMemcpy(h.data(), counts, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost));
+            int64_t sum = 0;
+            for (int64_t c : h) sum += c;
+            *total = sum;
+        }
+    }
+    return VRC_OK;
+}
+
+vrc_status vrc_trace_rays(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch, int64_t *offs, int64_t *voxel,
+                          double *len, double *score, int64_t cap)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    if (vrc_status s = validate_batch(batch)) return s;
+    if (!offs) return set_error(VRC_ERR_INVALID, "null offs");
+    if (cap < 0) return set_error(VRC_ERR_INVALID, "negative cap");
+    const int64_t n = batch->n;
+    int mesh_id;
+    vrc_precision prec;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        TallyHost *t = get_tally(ctx, tally_id);
+        if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
+        if (vrc_status s = check_cast_ready(ctx, t)) return s;
+        mesh_id = t->mesh_id;
+        prec = t->prec;
+    }
+    offs[0] = 0;
+    if (n == 0) return VRC_OK;
+    (void)hipSetDevice(ctx->device);
+    // segment counts -> offsets (host scan) -> trace
+    int64_t *d_counts = nullptr;
+    if (hipMalloc(&d_counts, sizeof(int64_t) * (n + 1)) != hipSuccess) return set_error(VRC_ERR_NOMEM, "counts");
+    int64_t total = 0;
+    vrc_status st = vrc_count_segments(ctx, mesh_id, prec, batch, d_counts, &total, nullptr);
+    if (st != VRC_OK) {
+        (void)hipFree(d_counts);
+        return st;
+    }
+    std::vector<int64_t> cnt(static_cast<size_t>(n));
+    hipError_t e = hipMemcpy(cnt.data(), d_counts, sizeof(int64_t) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        (void)hipFree(d_counts);
+        return device_error(ctx, e, "reading segment counts");
+    }
+    for (int64_t i = 0; i < n; ++i) offs[i + 1] = offs[i] + cnt[static_cast<size_t>(i)];
+    if (offs[n] > cap) {
+        (void)hipFree(d_counts);
+        return set_error(VRC_ERR_CAPACITY, "trace output capacity too small; offs[n] holds the size needed");
+    }
+    if (!voxel || !len || !score) {
+        (void)hipFree(d_counts);
+        return set_error(VRC_ERR_INVALID, "null trace output");
+    }
+    const int64_t S = offs[n] > 0 ? offs[n] : 1;
+    int64_t *d_vox = nullptr;
+    double *d_len = nullptr, *d_score = nullptr;
+    e = hipMemcpy(d_counts, offs, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess && hipMalloc(&d_vox, sizeof(int64_t) * S) != hipSuccess) e = hipErrorOutOfMemory;
+    if (e == hipSuccess && hipMalloc(&d_len, sizeof(double) * S) != hipSuccess) e = hipErrorOutOfMemory;
+    if (e == hipSuccess && hipMalloc(&d_score, sizeof(double) * S) != hipSuccess) e = hipErrorOutOfMemory;
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        TallyHost *t = get_tally(ctx, tally_id);
+        RaysP rays;
+        int slot = -1;
+        st = stage_rays(ctx, batch, nullptr, rays, slot);
+        if (st == VRC_OK) {
+            e = launch_trace(*ctx, *t, ctx->meshes[mesh_id], rays, batch->fp64 != 0,
+                             TraceP{d_counts, d_vox, d_len, d_score}, nullptr);
+            if (e == hipSuccess) st = mark_stage_used(ctx, slot, nullptr);
+        }
+    }
+    if (e == hipSuccess && st == VRC_OK) e = hipDeviceSynchronize();
+    if (e == hipSuccess && st == VRC_OK) e = hipMemcpy(voxel, d_vox, sizeof(int64_t) * offs[n], hipMemcpyDeviceToHost);
+    if (e == hipSuccess && st == VRC_OK) e = hipMemcpy(len, d_len, sizeof(double) * offs[n], hipMemcpyDeviceToHost);
+    if (e == hipSuccess && st == VRC_OK) e = hipMemcpy(score, d_score, sizeof(double) * offs[n], hipMemcpyDeviceToHost);
+    (void)hipFree(d_counts);
+    free_dev(d_vox);
+    free_dev(d_len);
+    free_dev(d_score);
+    if (st != VRC_OK) return st;
+    if (e == hipErrorOutOfMemory) return set_error(VRC_ERR_NOMEM, "trace buffers");
+    if (e != hipSuccess) return device_error(ctx, e, "trace");
+    return VRC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// Internal declarations shared by the runtime (vrc_api.cpp), the cross-section
+// index builder (vrc_xs.cpp) and the kernels (vrc_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/vrc.h"
+
+namespace vrc {
+
+constexpr int kMaxMeshes = 8;
+constexpr int kMaxMaterials = 64;
+constexpr int kMaxEbins = 64;
+
+// ---------------------------------------------------------------------------
+// Parameters handed to the kernels by value.
+// ---------------------------------------------------------------------------
+
+// Uniform Cartesian mesh in the traversal precision R.
+template <typename R>
+struct MeshP {
+    R lo[3];
+    R h[3];
+    int32_t n[3];
+    const uint8_t *mat;  // n0*n1*n2 material ids, x fastest
+};
+
+// Cross sections on the union energy grid.  E[K] strictly increasing;
+// S[k * s_stride + m] = Sigma_m(E[k]).  hash[b] is the index of a grid
+// interval near the lower edge of log2-energy bin b (only a starting point
+// for the bounded search); bins are b = floor((log2 E - l2e0) * inv_dl2).
+template <typename R>
+struct XsP {
+    const R *E;
+    const R *S;
+    const int32_t *hash;
+    int32_t K;
+    int32_t n_mat;
+    int32_t s_stride;
+    int32_t M;
+    float l2e0;
+    float inv_dl2;
+};
+
+// Ray batch, structure of arrays of type RT.
+struct RaysP {
+    const void *ox, *oy, *oz, *ux, *uy, *uz, *e, *w;
+    int64_t n;
+};
+
+// Tally of one precision form.  data: double[n_bins*nvox] (FP64 tallies) or
+// float2-interleaved {sum, comp}[n_bins*nvox] (compensated FP32 tally).
+struct TallyP {
+    void *data;
+    const double *edges;  // n_bins+1 device doubles, or nullptr (one bin, all energies)
+    int64_t nvox;
+    int32_t n_bins;
+};
+
+// CSR output of the inspection hook.
+struct TraceP {
+    const int64_t *offs;  // per-ray start offsets (n+1)
+    int64_t *voxel;
+    double *len;
+    double *score;
+};
+
+struct LaunchShape {
+    int block = 256;
+    int blocks_per_cu = 8;
+    int hash_in_lds = 1;
+    int aggregate = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Host-side objects.
+// ---------------------------------------------------------------------------
+
+struct MeshHost {
+    bool set = false;
+    double lo[3] = {0, 0, 0};
+    double h[3] = {1, 1, 1};
+    int32_t n[3] = {0, 0, 0};
+    int64_t nvox = 0;
+    int max_mat = 0;
+    uint8_t *d_mat = nullptr;
+    int users = 0;  // tallies that refer to it
+};
+
+// Union-grid cross sections built on the host (vrc_xs.cpp) and their
+// device copies in both precisions.
+struct XsHost {
+    bool set = false;
+    int n_mat = 0;
+    int K = 0;
+    int M = 0;
+    int s_stride32 = 0;
+    int s_stride64 = 0;
+    float l2e0 = 0.f;
+    float inv_dl2 = 0.f;
+    bool f32_ok = false;  // FP32-rounded union grid is strictly increasing
+    std::vector<double> E;        // K
+    std::vector<double> S;        // K * n_mat
+    std::vector<int32_t> hash32;  // M (for the FP32 grid)
+    std::vector<int32_t> hash64;  // M (for the FP64 grid)
+    double *d_E64 = nullptr;
+    double *d_S64 = nullptr;
+    float *d_E32 = nullptr;
+    float *d_S32 = nullptr;
+    int32_t *d_hash32 = nullptr;
+    int32_t *d_hash64 = nullptr;
+};
+
+struct TallyHost {
+    int mesh_id = -1;
+    int n_bins = 1;
+    vrc_precision prec = VRC_P64;
+    int64_t nvox = 0;
+    void *d_data = nullptr;
+    double *d_edges = nullptr;
+    size_t bytes = 0;
+};
+
+// Pinned staging slot for host ray batches.
+struct StageSlot {
+    void *h_buf = nullptr;
+    void *d_buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;  // recorded after the kernel that reads d_buf
+    bool used = false;
+};
+
+}  // namespace vrc
+
+struct vrc_ctx {
+    int device = 0;
+    int n_cu = 0;
+    std::mutex mu;
+    vrc::MeshHost meshes[vrc::kMaxMeshes];
+    vrc::XsHost xs;
+    std::vector<std::unique_ptr<vrc::TallyHost>> tallies;
+    vrc::LaunchShape launch;
+    vrc::StageSlot stage[2];
+    int stage_next = 0;
+    std::atomic<int> sticky{0};
+};
+
+namespace vrc {
+
+// Errors ------------------------------------------------------------------
+vrc_status set_error(vrc_status st, const std::string &msg);
+
+// Cross-section index (vrc_xs.cpp) -------------------------------------------
+// Builds the union grid, per-material values on it and the log2-energy hash.
+vrc_status build_xs(int n_mat, const int64_t *offs, const double *energy, const double *sigma,
+                    XsHost &out);
+
+// Kernel launchers (vrc_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m,
+                       const RaysP &rays, bool rays_fp64, hipStream_t s);
+hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec,
+                        const RaysP &rays, bool rays_fp64, int64_t *counts, hipStream_t s);
+hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m,
+                        const RaysP &rays, bool rays_fp64, const TraceP &tr, hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_tally_to_f64(const TallyHost &t, double *out, hipStream_t s);
+hipError_t launch_tally_from_f64(const TallyHost &t, const double *in, hipStream_t s);
+
+}  // namespace vrc

@@ -1,0 +1,441 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Voxel sequences and lengths are compared bit for bit (both sides follow the
+same traversal arithmetic), per-voxel tallies within the stated tolerances:
+1e-12 relative for the FP64 form on every voxel with phi > 1e-30 max(phi),
+1e-5 relative for the FP32 forms on voxels whose oracle relative standard
+error is below 5% (the paper's own gate for single vs double precision).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from vrc_testutil import dev_arrays, f32_view, host_arrays, oracle_threads, rel_report, unscored_ok
+
+pytestmark = pytest.mark.gpu
+
+TOL_P64 = 1e-12
+TOL_P32 = 1e-5
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vrc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1706_07476_amd as vrc_mod
+    vrc_mod.load_library()
+    return vrc_mod
+
+
+@pytest.fixture()
+def ctx(vrc):
+    c = vrc.Context(0)
+    yield c
+    c.close()
+
+
+def setup(ctx, wl, mesh_id=0):
+    ctx.set_mesh(mesh_id, wl.mesh)
+    ctx.set_xs(wl.xs)
+
+
+def oracle_csr(mesh, rays, prec):
+    return oracle.trace_many(mesh, rays, precision=prec)
+
+
+# ---------------------------------------------------------------------------
+# traversal: bit-exact voxel sequences and lengths
+# ---------------------------------------------------------------------------
+
+def test_trace_bit_exact_fp64_tiny(ctx):
+    wl = W.config1_tiny(n_rays=10_000)
+    say("case: trace FP64, tiny 10^3, 1e4 rays")
+    setup(ctx, wl)
+    tid = ctx.create_tally(0, "p64")
+    offs, vox, ln, sc = ctx.trace(tid, dev_arrays(wl.rays, "f64"))
+    o_offs, o_vox, o_len = oracle_csr(wl.mesh, wl.rays, "f64")
+    np.testing.assert_array_equal(offs, o_offs)
+    np.testing.assert_array_equal(vox, o_vox)
+    np.testing.assert_array_equal(ln, o_len)
+    for r in range(0, 10_000, 97):
+        o = [wl.rays.ox[r], wl.rays.oy[r], wl.rays.oz[r]]
+        u = [wl.rays.ux[r], wl.rays.uy[r], wl.rays.uz[r]]
+        _, _, s_ref, _ = oracle.ray_scores(wl.mesh, wl.xs, o, u, wl.rays.e[r], wl.rays.w[r])
+        np.testing.assert_allclose(sc[offs[r]:offs[r + 1]], s_ref, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("prec", ["p64", "p32_t64", "p32_kahan"])
+def test_trace_bit_exact_multimaterial(ctx, prec):
+    wl = W.config2_multimaterial(n_rays=4000)
+    say(f"case: trace {prec}, multimat 100^3, 4000 rays")
+    setup(ctx, wl)
+    tid = ctx.create_tally(0, prec)
+    if prec == "p64":
+        offs, vox, ln, sc = ctx.trace(tid, dev_arrays(wl.rays, "f64"))
+        o_offs, o_vox, o_len = oracle_csr(wl.mesh, wl.rays, "f64")
+    else:
+        offs, vox, ln, sc = ctx.trace(tid, dev_arrays(wl.rays, "f32"))
+        m32 = W.Mesh(wl.mesh.lo.astype(np.float32), wl.mesh.h.astype(np.float32), wl.mesh.n, wl.mesh.mat)
+        o_offs, o_vox, o_len = oracle_csr(m32, W.rays_to_f32(wl.rays), "f32")
+    np.testing.assert_array_equal(offs, o_offs)
+    np.testing.assert_array_equal(vox, o_vox)
+    np.testing.assert_array_equal(ln, np.asarray(o_len, dtype=np.float64))
+    assert offs[-1] > 50 * 4000
+
+
+def _edge_rays():
+    """Hand-made rays: axis-aligned, on planes, outside, missing, in faces, corners."""
+    s2 = math.sqrt(0.5)
+    c3 = 1 / math.sqrt(3.0)
+    rows = [
+        ((0.25, 1.5, 2.5), (1, 0, 0)), ((0.5, 3.0, 0.5), (0, -1, 0)), ((0.5, 3.0, 0.5), (0, 1, 0)),
+        ((4.0, 1.5, 1.5), (1, 0, 0)), ((0.5, 4.0, 0.5), (1, 0, 0)), ((0.5, 0.0, 0.5), (1, 0, 0)),
+        ((-2.0, 1.5, 0.0), (1, 0, 0)), ((0.5, 0.5, 1.5), (s2, s2, 0)), ((-1, -1, -1), (c3, c3, c3)),
+        ((-1.0, 5.0, 0.5), (1, 0, 0)), ((2.0, 2.0, 2.0), (0, 0, -1)), ((2.0, 2.0, 2.0), (-c3, c3, -c3)),
+        ((4.0, 4.0, 4.0), (-c3, -c3, -c3)), ((0.0, 0.0, 0.0), (c3, c3, c3)), ((3.999999, 0.5, 0.5), (1, 0, 0)),
+    ]
+    o = np.array([r[0] for r in rows], np.float64)
+    u = np.array([r[1] for r in rows], np.float64)
+    n = len(rows)
+    return W.Rays(o[:, 0].copy(), o[:, 1].copy(), o[:, 2].copy(), u[:, 0].copy(), u[:, 1].copy(), u[:, 2].copy(),
+                  np.full(n, 1.0), np.full(n, 1.0))
+
+
+@pytest.mark.parametrize("prec", ["p64", "p32_t64"])
+def test_trace_edge_cases(ctx, prec):
+    say(f"case: trace edge rays {prec}")
+    mesh = W.Mesh(np.zeros(3), np.ones(3), np.full(3, 4, np.int32), np.zeros(64, np.uint8))
+    xs = W.gen.make_xs([W.constant_sigma_table(0.7)])
+    rays = _edge_rays()
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    tid = ctx.create_tally(0, prec)
+    dt = "f64" if prec == "p64" else "f32"
+    offs, vox, ln, _ = ctx.trace(tid, dev_arrays(rays, dt))
+    if prec == "p64":
+        o_offs, o_vox, o_len = oracle_csr(mesh, rays, "f64")
+    else:
+        m32 = W.Mesh(mesh.lo.astype(np.float32), mesh.h.astype(np.float32), mesh.n, mesh.mat)
+        o_offs, o_vox, o_len = oracle_csr(m32, W.rays_to_f32(rays), "f32")
+    np.testing.assert_array_equal(offs, o_offs)
+    np.testing.assert_array_equal(vox, o_vox)
+    np.testing.assert_array_equal(ln, np.asarray(o_len, np.float64))
+
+
+def test_segment_counts_cylinder_mesh(ctx, vrc):
+    """The 256^3 cylinder mesh (0.2 cm voxels): per-ray FP32 segment counts equal the oracle's."""
+    import torch
+    wl = W.config3_precision(n_rays=20_000)
+    say("case: count segments FP32, cylinder 256^3, 2e4 rays")
+    ctx.set_mesh(0, wl.mesh)
+    counts = torch.empty(wl.rays.n, dtype=torch.int64, device="cuda:0")
+    total = ctx.count_segments(0, "p32_t64", dev_arrays(wl.rays, "f32"), counts)
+    m32 = W.Mesh(wl.mesh.lo.astype(np.float32), wl.mesh.h.astype(np.float32), wl.mesh.n, wl.mesh.mat)
+    o_offs, _, _ = oracle_csr(m32, W.rays_to_f32(wl.rays), "f32")
+    np.testing.assert_array_equal(counts.cpu().numpy(), np.diff(o_offs))
+    assert total == o_offs[-1]
+    counts64 = torch.empty(wl.rays.n, dtype=torch.int64, device="cuda:0")
+    ctx.count_segments(0, "p64", dev_arrays(wl.rays, "f64"), counts64)
+    o_offs64, _, _ = oracle_csr(wl.mesh, wl.rays, "f64")
+    np.testing.assert_array_equal(counts64.cpu().numpy(), np.diff(o_offs64))
+
+
+# ---------------------------------------------------------------------------
+# tallies
+# ---------------------------------------------------------------------------
+
+def test_tally_tiny_fp64(ctx):
+    wl = W.config1_tiny()
+    say("case: tally FP64, tiny 10^3, 1e4 rays")
+    setup(ctx, wl)
+    tid = ctx.create_tally(0, "p64")
+    ctx.cast(tid, dev_arrays(wl.rays, "f64"))
+    got = ctx.read(tid)
+    res = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=oracle_threads())
+    g, a, _ = rel_report(got, res, gate="all")
+    say(f"  max rel {g:.3e}")
+    assert g <= TOL_P64
+
+
+def test_tally_multimaterial_fp64(ctx):
+    n_rays = 200_000
+    wl = W.config2_multimaterial(n_rays=n_rays)
+    say(f"case: tally p64, multimat 100^3, {n_rays} rays")
+    setup(ctx, wl)
+    tid = ctx.create_tally(0, "p64")
+    ctx.cast(tid, dev_arrays(wl.rays, "f64"))
+    res = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=oracle_threads())
+    g, a, n = rel_report(ctx.read(tid), res, gate="all")
+    say(f"  FP64: max rel over {n} voxels {g:.3e}")
+    assert g <= TOL_P64
+
+
+def eps_phi_max(got, res):
+    """Largest |phi_gpu - phi_oracle| / sigma over voxels with sigma > 0 (Eq. 8)."""
+    R = float(res.n_rays)
+    mean = res.tally.reshape(-1) / R
+    var = np.maximum(res.sq.reshape(-1) / R - mean * mean, 0.0) * R / max(R - 1.0, 1.0)
+    sigma = np.sqrt(var * R)  # standard deviation of the tally sum
+    ok = sigma > 0
+    return float(np.max(np.abs(np.asarray(got).reshape(-1)[ok] - res.tally.reshape(-1)[ok]) / sigma[ok]))
+
+
+@pytest.mark.parametrize("prec", ["p32_t64", "p32_kahan"])
+def test_tally_multimaterial_fp32_well_sampled(ctx, prec):
+    """FP32 forms on a well-sampled mesh (16^3 of the multimat tables, 1.6e6 rays).
+
+    Most voxels then have an oracle relative standard error below 5%, so the
+    1e-5 bound applies to nearly the whole mesh, as in the paper's gate.
+    """
+    n_rays = 1_600_000
+    wl = W.config2_multimaterial(n_rays=n_rays, n=16, h=0.5)
+    wl.mesh = W.slab_mesh(202, 16, 0.5, slab=4)
+    say(f"case: tally {prec}, multimat tables on 16^3 (4-voxel slabs), {n_rays} rays")
+    setup(ctx, wl)
+    tid = ctx.create_tally(0, prec)
+    ctx.cast(tid, dev_arrays(wl.rays, "f32"))
+    m, x, r = f32_view(wl.mesh, wl.xs, wl.rays)
+    res = oracle.cast(m, x, r, n_threads=oracle_threads())
+    got = ctx.read(tid)
+    g, a, n = rel_report(got, res, gate="stderr")
+    eps = eps_phi_max(got, res)
+    say(f"  {prec}: max rel over {n} gated voxels {g:.3e}; all voxels {a:.3e}; max eps_phi {eps:.3e}")
+    assert n > 0.5 * wl.mesh.n_voxels
+    assert g <= TOL_P32
+    assert eps <= 1e-2
+    assert unscored_ok(got, res)
+
+
+@pytest.mark.parametrize("prec", ["p32_t64", "p32_kahan"])
+def test_tally_multimaterial_fp32_100cubed(ctx, prec):
+    """FP32 forms on the 100^3 multimat mesh: statistically insignificant differences everywhere (Eq. 8)."""
+    n_rays = 200_000
+    wl = W.config2_multimaterial(n_rays=n_rays)
+    say(f"case: tally {prec}, multimat 100^3, {n_rays} rays")
+    setup(ctx, wl)
+    tid = ctx.create_tally(0, prec)
+    ctx.cast(tid, dev_arrays(wl.rays, "f32"))
+    m, x, r = f32_view(wl.mesh, wl.xs, wl.rays)
+    res = oracle.cast(m, x, r, n_threads=oracle_threads())
+    got = ctx.read(tid)
+    g, a, n = rel_report(got, res, gate="stderr")
+    eps = eps_phi_max(got, res)
+    say(f"  {prec}: gated voxels {n}, max rel there {g:.3e}; all voxels {a:.3e}; max eps_phi {eps:.3e}")
+    assert g <= TOL_P32
+    assert eps <= 1e-2
+    assert unscored_ok(got, res)
+
+
+def test_tally_cylinder_with_void(ctx):
+    """256^3 mesh with a void outside the cylinder (Sigma = 0 limit), reduced ray count."""
+    wl = W.config3_precision(n_rays=30_000)
+    say("case: tally p64 + p32_t64, cylinder 256^3 with void, 3e4 rays")
+    setup(ctx, wl)
+    t64 = ctx.create_tally(0, "p64")
+    t32 = ctx.create_tally(0, "p32_t64")
+    ctx.cast(t64, dev_arrays(wl.rays, "f64"))
+    ctx.cast(t32, dev_arrays(wl.rays, "f32"))
+    res = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=oracle_threads())
+    g, _, n = rel_report(ctx.read(t64), res, gate="all")
+    say(f"  FP64 max rel {g:.3e} over {n}")
+    assert g <= TOL_P64
+    m, x, r = f32_view(wl.mesh, wl.xs, wl.rays)
+    res32 = oracle.cast(m, x, r, n_threads=oracle_threads())
+    g32, a32, n32 = rel_report(ctx.read(t32), res32, gate="stderr")
+    say(f"  FP32 max rel {g32:.3e} over {n32} gated ({a32:.3e} all)")
+    assert g32 <= TOL_P32
+
+
+def test_energy_bins_and_out_of_range(ctx):
+    """10 log energy bins; rays below, inside, on the top edge and above the bins."""
+    wl = W.config2_multimaterial(n_rays=20_000, n=40, h=0.5)
+    edges = W.log_bin_edges(10, 1e-9, 1.0)
+    rays = wl.rays
+    rays.e[:5] = edges[-1]
+    rays.e[5:10] = edges[0]
+    say("case: 10-bin tally p64 + p32_t64, 40^3, 2e4 rays")
+    setup(ctx, wl)
+    t64 = ctx.create_tally(0, "p64", edges)
+    t32 = ctx.create_tally(0, "p32_kahan", edges)
+    ctx.cast(t64, dev_arrays(rays, "f64"))
+    ctx.cast(t32, dev_arrays(rays, "f32"))
+    res = oracle.cast(wl.mesh, wl.xs, rays, edges=edges, n_threads=oracle_threads())
+    assert res.rays_out_of_range > 1000
+    got = ctx.read(t64).reshape(10, -1)
+    g, _, _ = rel_report(got, res, gate="all")
+    assert g <= TOL_P64
+    m, x, r = f32_view(wl.mesh, wl.xs, rays)
+    res32 = oracle.cast(m, x, r, edges=edges, n_threads=oracle_threads())
+    g32, _, n32 = rel_report(ctx.read(t32), res32, gate="stderr")
+    say(f"  FP32 kahan gated {g32:.3e} over {n32}")
+    assert g32 <= TOL_P32
+
+
+@pytest.mark.parametrize("n_rays", [0, 1, 63, 65, 1023, 100_003])
+def test_ragged_batches_host_and_device(ctx, n_rays):
+    wl = W.config2_multimaterial(n_rays=max(n_rays, 1), n=24, h=0.5)
+    rays = wl.rays.take(slice(0, n_rays))
+    say(f"case: ragged batch {n_rays} rays, host + device, p64")
+    setup(ctx, wl)
+    t_dev = ctx.create_tally(0, "p64")
+    t_host = ctx.create_tally(0, "p64")
+    ctx.cast(t_dev, dev_arrays(rays, "f64"))
+    ctx.cast(t_host, host_arrays(rays, "f64"))
+    a, b = ctx.read(t_dev), ctx.read(t_host)
+    if n_rays == 0:
+        assert not a.any() and not b.any()
+        return
+    res = oracle.cast(wl.mesh, wl.xs, rays, n_threads=oracle_threads())
+    for got in (a, b):
+        g, _, _ = rel_report(got, res, gate="all")
+        assert g <= TOL_P64
+
+
+def test_fp64_rays_into_fp32_form_round_on_load(ctx):
+    wl = W.config2_multimaterial(n_rays=30_000, n=32, h=0.5)
+    say("case: FP64 rays into FP32 form")
+    setup(ctx, wl)
+    ta = ctx.create_tally(0, "p32_t64")
+    tb = ctx.create_tally(0, "p32_t64")
+    ctx.cast(ta, dev_arrays(wl.rays, "f64"))
+    ctx.cast(tb, dev_arrays(wl.rays, "f32"))
+    a, b = ctx.read(ta), ctx.read(tb)
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-300)
+
+
+def test_launch_shapes_give_the_same_tally(ctx):
+    wl = W.config2_multimaterial(n_rays=50_000, n=48, h=0.5)
+    say("case: launch shapes p64")
+    setup(ctx, wl)
+    arrays = dev_arrays(wl.rays, "f64")
+    res = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=oracle_threads())
+    for shape in [dict(block=64, blocks_per_cu=0, hash_in_lds=0, aggregate=0),
+                  dict(block=256, blocks_per_cu=8, hash_in_lds=1, aggregate=0),
+                  dict(block=1024, blocks_per_cu=1, hash_in_lds=1, aggregate=1),
+                  dict(block=128, blocks_per_cu=2, hash_in_lds=0, aggregate=1)]:
+        ctx.set_launch(**shape)
+        tid = ctx.create_tally(0, "p64")
+        ctx.cast(tid, arrays)
+        g, _, _ = rel_report(ctx.read(tid), res, gate="all")
+        say(f"  {shape}: {g:.3e}")
+        assert g <= TOL_P64
+        ctx.destroy_tally(tid)
+
+
+def test_aggregation_with_coherent_rays(ctx):
+    """Many rays from one collision point (N rays per collision, Eq. 4): aggregation on and off agree."""
+    rng = np.random.default_rng(3)
+    n = 64 * 200
+    pts = np.repeat(rng.uniform(2, 10, (n // 64, 3)), 64, axis=0)
+    u = np.stack(W.isotropic_directions(rng, n), axis=1)
+    rays = W.Rays(pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2].copy(), u[:, 0].copy(), u[:, 1].copy(),
+                  u[:, 2].copy(), np.full(n, 1.0), np.full(n, 1.0 / 64))
+    mesh = W.slab_mesh(5, 24, 0.5)
+    xs = W.gen.make_xs([W.constant_sigma_table(s) for s in (0.2, 1.0, 3.0)])
+    say("case: aggregation coherent rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    res = oracle.cast(mesh, xs, rays, n_threads=oracle_threads())
+    out = []
+    for agg in (0, 1):
+        ctx.set_launch(aggregate=agg)
+        for prec, dt in (("p64", "f64"), ("p32_kahan", "f32")):
+            tid = ctx.create_tally(0, prec)
+            ctx.cast(tid, dev_arrays(rays, dt))
+            out.append((agg, prec, ctx.read(tid)))
+            ctx.destroy_tally(tid)
+    for agg, prec, got in out:
+        if prec == "p64":
+            g, _, _ = rel_report(got, res, gate="all")
+            assert g <= TOL_P64, (agg, g)
+    m, x, r = f32_view(mesh, xs, rays)
+    res32 = oracle.cast(m, x, r, n_threads=oracle_threads())
+    for agg, prec, got in out:
+        if prec == "p32_kahan":
+            g, _, n32 = rel_report(got, res32, gate="stderr")
+            assert g <= TOL_P32, (agg, g)
+
+
+def test_single_voxel_and_long_thin_meshes(ctx):
+    say("case: 1x1x1 mesh and 1x1x2^20 mesh")
+    xs = W.gen.make_xs([W.constant_sigma_table(0.3), W.constant_sigma_table(0.0)])
+    one = W.Mesh(np.array([-1.0, 2.0, 0.5]), np.array([2.0, 0.5, 1.0]), np.ones(3, np.int32), np.zeros(1, np.uint8))
+    rays = W.rays_in_box(9, W.Mesh(one.lo - 1, one.h * 3, np.ones(3, np.int32), one.mat), 5000)
+    ctx.set_mesh(0, one)
+    ctx.set_xs(xs)
+    tid = ctx.create_tally(0, "p64")
+    ctx.cast(tid, dev_arrays(rays, "f64"))
+    res = oracle.cast(one, xs, rays)
+    g, _, _ = rel_report(ctx.read(tid), res, gate="all")
+    assert g <= TOL_P64
+    nz = 1 << 20
+    thin = W.Mesh(np.zeros(3), np.array([1.0, 1.0, 1e-3]), np.array([1, 1, nz], np.int32),
+                  (np.arange(nz) % 7 == 0).astype(np.uint8))
+    k = 16
+    rng = np.random.default_rng(1)
+    mu = np.where(np.arange(k) < k // 2, 1.0, rng.uniform(0.99999, 1.0, k))
+    s = np.sqrt(1 - mu * mu)
+    rays = W.Rays(rng.uniform(0, 1, k), rng.uniform(0, 1, k), rng.uniform(0, 1, k), s, np.zeros(k), mu,
+                  np.ones(k), np.ones(k))
+    ctx.set_mesh(1, thin)
+    t2 = ctx.create_tally(1, "p64")
+    ctx.cast(t2, dev_arrays(rays, "f64"))
+    res2 = oracle.cast(thin, xs, rays)
+    assert res2.segments > (k // 2) * 1_000_000
+    g2, _, _ = rel_report(ctx.read(t2), res2, gate="all")
+    assert g2 <= TOL_P64
+
+
+def test_reset_load_read_roundtrip(ctx):
+    wl = W.config2_multimaterial(n_rays=10_000, n=20, h=0.5)
+    say("case: reset/load/read")
+    setup(ctx, wl)
+    for prec, dt in (("p64", "f64"), ("p32_kahan", "f32"), ("p32_t64", "f32")):
+        tid = ctx.create_tally(0, prec)
+        arrays = dev_arrays(wl.rays, dt)
+        ctx.cast(tid, arrays)
+        first = ctx.read(tid)
+        ctx.reset(tid)
+        assert not ctx.read(tid).any()
+        ctx.load(tid, first)
+        np.testing.assert_allclose(ctx.read(tid), first, rtol=1e-15 if prec != "p32_kahan" else 1e-14)
+        ctx.cast(tid, arrays)
+        np.testing.assert_allclose(ctx.read(tid), 2 * first, rtol=1e-12 if prec == "p64" else 1e-6)
+
+
+def test_errors_are_reported(ctx, vrc):
+    say("case: error paths")
+    wl = W.config1_tiny(n_rays=10)
+    with pytest.raises(vrc.VrcError) as e:
+        ctx.create_tally(0, "p64")
+    assert e.value.status == vrc.VRC_ERR_INVALID
+    ctx.set_mesh(0, W.Mesh(np.zeros(3), np.ones(3), np.full(3, 2, np.int32), np.array([0, 1] * 4, np.uint8)))
+    tid = ctx.create_tally(0, "p64")
+    with pytest.raises(vrc.VrcError) as e:
+        ctx.cast(tid, dev_arrays(wl.rays, "f64"))
+    assert e.value.status == vrc.VRC_ERR_STATE  # no tables yet
+    ctx.set_xs(wl.xs)  # one material, but the mesh uses id 1
+    with pytest.raises(vrc.VrcError) as e:
+        ctx.cast(tid, dev_arrays(wl.rays, "f64"))
+    assert e.value.status == vrc.VRC_ERR_STATE
+    with pytest.raises(vrc.VrcError) as e:
+        vrc.vrc_set_xs_tables(ctx.handle, [0, 3], [1.0, 0.5, 2.0], [1.0, 1.0, 1.0])
+    assert e.value.status == vrc.VRC_ERR_INVALID
+    with pytest.raises(vrc.VrcError) as e:
+        ctx.cast(99, dev_arrays(wl.rays, "f64"))
+    assert e.value.status == vrc.VRC_ERR_INVALID
+    with pytest.raises(vrc.VrcError) as e:
+        ctx.set_mesh(0, wl.mesh)  # in use by a tally
+    assert e.value.status == vrc.VRC_ERR_STATE
+    with pytest.raises(vrc.VrcError):
+        vrc.vrc_set_launch(ctx.handle, block=100)

@@ -1,0 +1,66 @@
+"""Shared helpers of the GPU tests (no method arithmetic here)."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+
+import workloads as W
+
+
+def oracle_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def f32_view(mesh: W.Mesh, xs: W.XSTables, rays: W.Rays):
+    """Inputs as the FP32 forms see them (every value rounded to FP32), promoted back to FP64.
+
+    The FP32 forms compute on FP32 copies of the mesh spacing, the tables and
+    the rays; the oracle is run on exactly those values so that a comparison
+    measures the FP32 arithmetic, not the rounding of the inputs.
+    """
+    m = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
+               mesh.n, mesh.mat)
+    x = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
+                   xs.sigma.astype(np.float32).astype(np.float64))
+    r = W.rays_to_f32(rays).as_f64()
+    return m, x, r
+
+
+def dev_arrays(rays: W.Rays, dtype: str = "f64"):
+    import torch
+    dt = np.float64 if dtype == "f64" else np.float32
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to("cuda:0") for a in rays.arrays()]
+
+
+def host_arrays(rays: W.Rays, dtype: str = "f64"):
+    dt = np.float64 if dtype == "f64" else np.float32
+    return [np.ascontiguousarray(a, dtype=dt) for a in rays.arrays()]
+
+
+def rel_report(got: np.ndarray, res, gate: str = "stderr", se_max: float = 0.05):
+    """(max rel diff over gated voxels, max over all voxels with phi > 0, number gated).
+
+    gate "stderr": voxels whose oracle relative standard error is below se_max
+    (the paper compares cells with <5% uncertainty); gate "all": every voxel
+    with phi > 1e-30 * max phi.
+    """
+    ref = res.tally.reshape(-1)
+    got = np.asarray(got).reshape(-1)
+    pos = ref > 1e-30 * ref.max()
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(pos, np.abs(got - ref) / np.where(pos, ref, 1.0), 0.0)
+    if gate == "stderr":
+        mask = pos & (res.rel_std_err().reshape(-1) < se_max)
+    else:
+        mask = pos
+    g = float(rel[mask].max()) if mask.any() else 0.0
+    return g, float(rel[pos].max()) if pos.any() else 0.0, int(mask.sum())
+
+
+def unscored_ok(got: np.ndarray, res) -> bool:
+    """Voxels the oracle leaves (numerically) empty are empty or negligible on the GPU too."""
+    ref = res.tally.reshape(-1)
+    got = np.asarray(got).reshape(-1)
+    tiny = ~(ref > 1e-30 * ref.max())
+    return bool(np.all(np.abs(got[tiny]) <= 1e-25 * ref.max()))
