@@ -31,7 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # 8-byte read-modify-write of the tally element (FP64, or the FP32 sum+compensation pair)
 RAY_BYTES = {"f32": 32, "f64": 64}
 SEG_BYTES = 1 + 2 * 8
-KERNEL_SOURCES = ["paper_1706_07476_amd/csrc/vrc_kernels.hip", "paper_1706_07476_amd/csrc/vrc_internal.h"]
+KERNEL_SOURCES = ["paper_1706_07476_amd/csrc/vrc_kernels.hip", "paper_1706_07476_amd/csrc/vrc_internal.h",
+                  "paper_1706_07476_amd/csrc/vrc_math.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cast_multimat_traffic.json")
 
 

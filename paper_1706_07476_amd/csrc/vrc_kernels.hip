@@ -23,14 +23,16 @@
 //                    pieces of length <= 0 are not scored.
 //
 // Score (Eqs. 1-4): with W_in the weight entering a voxel (Eq. 2),
-//   x = Sigma l,  e = expm1(-x),  F = W_in (-e) / Sigma  (W_in l if Sigma = 0),
-//   W_out = W_in + W_in e  (= W_in exp(-x)).
+//   x = Sigma l,  F = W_in (1 - e^{-x}) / Sigma  (W_in l if Sigma = 0),
+//   W_out = W_in e^{-x},
+// with 1 - e^{-x} and e^{-x} from one evaluation (vrc_math.h).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
 
 #include "vrc_internal.h"
+#include "vrc_math.h"
 
 namespace vrc {
 
@@ -41,12 +43,10 @@ struct Num;
 template <>
 struct Num<float> {
     static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
-    static __device__ __forceinline__ float expm1(float x) { return expm1f(x); }
 };
 template <>
 struct Num<double> {
     static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
-    static __device__ __forceinline__ double expm1(double x) { return ::expm1(x); }
 };
 
 template <typename R>
@@ -273,9 +273,10 @@ struct Scorer {
         const R s = sig[m * stride][0];
         const R is = sig[m * stride][1];
         const R x = s * l;
-        const R e = Num<R>::expm1(-x);
-        const R f = s > R(0) ? (w_in * (-e)) * is : w_in * l;
-        w_in = w_in + w_in * e;
+        R g, em;
+        attenuation(x, g, em);
+        const R f = s > R(0) ? (w_in * em) * is : w_in * l;
+        w_in = w_in * g;
         put(vox, l, f);
     }
 };
@@ -540,17 +541,34 @@ int grid_for(const vrc_ctx &ctx, int64_t n, int block)
     return static_cast<int>(need);
 }
 
+constexpr size_t kLdsLimit = 65536;  // dynamic LDS per block this library asks for
+
+// Block size and hash placement that fit the LDS budget: the per-lane cross
+// section columns (2 values per material) always live in LDS; the hash index
+// is staged too if it still fits, else read from global memory.
 template <typename R>
-size_t lds_bytes(const XsHost &x, int block, bool hash_in_lds)
+bool pick_shape(const XsHost &x, int want_block, bool want_hash, int &block, bool &hash, size_t &lds)
 {
-    return sizeof(R) * 2 * static_cast<size_t>(x.n_mat) * block + (hash_in_lds ? sizeof(int32_t) * x.M : 0);
+    const size_t per_lane = sizeof(R) * 2 * static_cast<size_t>(x.n_mat);
+    const size_t hb = sizeof(int32_t) * static_cast<size_t>(x.M);
+    block = want_block;
+    hash = want_hash;
+    while (block > 64 && per_lane * block + (hash ? hb : 0) > kLdsLimit) block -= 64;
+    if (per_lane * block + (hash ? hb : 0) > kLdsLimit) hash = false;
+    lds = per_lane * block + (hash ? hb : 0);
+    return lds <= kLdsLimit;
 }
 
 template <typename R, typename RT>
-hipError_t cast_f64_launch(const vrc_ctx &ctx, CastArgs<R> A, int block, hipStream_t s)
+hipError_t cast_f64_launch(const vrc_ctx &ctx, CastArgs<R> A, hipStream_t s)
 {
+    int block;
+    bool hash;
+    size_t lds;
+    if (!pick_shape<R>(ctx.xs, ctx.launch.block, ctx.launch.hash_in_lds != 0, block, hash, lds))
+        return hipErrorInvalidConfiguration;
+    A.hash_in_lds = hash ? 1 : 0;
     const int grid = grid_for(ctx, A.rays.n, block);
-    const size_t lds = lds_bytes<R>(ctx.xs, block, A.hash_in_lds);
     if (ctx.launch.aggregate)
         hipLaunchKernelGGL((cast_f64_kernel<R, RT, true>), dim3(grid), dim3(block), lds, s, A);
     else
@@ -577,22 +595,24 @@ hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m
                        bool rays_fp64, hipStream_t s)
 {
     if (rays.n <= 0) return hipSuccess;
-    const int block = ctx.launch.block;
     switch (t.prec) {
     case VRC_P64: {
         CastArgs<double> A = make_args<double>(ctx, t, m, rays);
-        return rays_fp64 ? cast_f64_launch<double, double>(ctx, A, block, s)
-                         : cast_f64_launch<double, float>(ctx, A, block, s);
+        return rays_fp64 ? cast_f64_launch<double, double>(ctx, A, s) : cast_f64_launch<double, float>(ctx, A, s);
     }
     case VRC_P32_T64: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
-        return rays_fp64 ? cast_f64_launch<float, double>(ctx, A, block, s)
-                         : cast_f64_launch<float, float>(ctx, A, block, s);
+        return rays_fp64 ? cast_f64_launch<float, double>(ctx, A, s) : cast_f64_launch<float, float>(ctx, A, s);
     }
     case VRC_P32_KAHAN: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
+        int block;
+        bool hash;
+        size_t lds;
+        if (!pick_shape<float>(ctx.xs, ctx.launch.block, ctx.launch.hash_in_lds != 0, block, hash, lds))
+            return hipErrorInvalidConfiguration;
+        A.hash_in_lds = hash ? 1 : 0;
         const int grid = grid_for(ctx, rays.n, block);
-        const size_t lds = lds_bytes<float>(ctx.xs, block, A.hash_in_lds);
         if (rays_fp64)
             hipLaunchKernelGGL((cast_kahan_kernel<double>), dim3(grid), dim3(block), lds, s, A);
         else
@@ -607,18 +627,23 @@ hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &
                         bool rays_fp64, const TraceP &tr, hipStream_t s)
 {
     if (rays.n <= 0) return hipSuccess;
-    const int block = 256;
-    const int grid = static_cast<int>((rays.n + block - 1) / block);
+    int block;
+    bool hash;
+    size_t lds;
     if (t.prec == VRC_P64) {
         CastArgs<double> A = make_args<double>(ctx, t, m, rays);
         A.trace = tr;
-        const size_t lds = lds_bytes<double>(ctx.xs, block, A.hash_in_lds);
+        if (!pick_shape<double>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
+        A.hash_in_lds = hash ? 1 : 0;
+        const int grid = static_cast<int>((rays.n + block - 1) / block);
         if (rays_fp64) hipLaunchKernelGGL((trace_kernel<double, double>), dim3(grid), dim3(block), lds, s, A);
         else hipLaunchKernelGGL((trace_kernel<double, float>), dim3(grid), dim3(block), lds, s, A);
     } else {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
         A.trace = tr;
-        const size_t lds = lds_bytes<float>(ctx.xs, block, A.hash_in_lds);
+        if (!pick_shape<float>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
+        A.hash_in_lds = hash ? 1 : 0;
+        const int grid = static_cast<int>((rays.n + block - 1) / block);
         if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double>), dim3(grid), dim3(block), lds, s, A);
         else hipLaunchKernelGGL((trace_kernel<float, float>), dim3(grid), dim3(block), lds, s, A);
     }

@@ -1,0 +1,95 @@
+// Attenuation factors of one voxel segment, for the GPU kernels (and a
+// host build used only to test them).
+//
+// For the optical thickness x = Sigma * l >= 0 of a segment the score of
+// Eq. 1 needs em = 1 - exp(-x) (accurate also for tiny x) and the weight
+// leaving the voxel needs g = exp(-x) (accurate also for large x).  Forming
+// one from the other loses everything where it matters (1 + expm1(-x) for
+// x >> 1, 1 - exp(-x) for x << 1), and two library calls cost two
+// exponentials.  Both come here from a single evaluation:
+//
+//   1. Cody and Waite's argument reduction: -x = k ln2 + r, |r| <= ln2/2,
+//      with ln2 split into a head whose product with k is exact and a tail;
+//   2. q = expm1(r) from its Taylor series in Horner form (degree 13 for
+//      double, 7 for float: the truncation is below a quarter ulp for
+//      |r| <= 0.347);
+//   3. g = 2^k (1 + q) and em = (1 - 2^k) - 2^k q, each one fused
+//      multiply-add (both results are then within a few ulp).
+//
+// The split constants are ln2 rounded to 53 (24) bits with the low 21 (12)
+// bits cleared, and the rest of ln2 rounded to the working precision.
+#pragma once
+
+#ifndef VRC_HD
+#if defined(__HIPCC__)
+#define VRC_HD __host__ __device__
+#else
+#define VRC_HD
+#endif
+#endif
+
+#include <cmath>
+
+namespace vrc {
+
+template <typename R>
+struct AttenConst;
+
+template <>
+struct AttenConst<double> {
+    static constexpr double inv_ln2 = 1.4426950408889634;
+    static constexpr double ln2_hi = 0.6931471804855391;
+    static constexpr double ln2_lo = 7.440617110012397e-11;
+    static constexpr double x_max = 708.0;  // exp(-x) below the normal range beyond this
+    static constexpr int degree = 13;
+};
+
+template <>
+struct AttenConst<float> {
+    static constexpr float inv_ln2 = 1.44269502f;
+    static constexpr float ln2_hi = 0.693115234375f;
+    static constexpr float ln2_lo = 3.194618329871446e-05f;
+    static constexpr float x_max = 87.0f;
+    static constexpr int degree = 7;
+};
+
+// 1/j!, exact factorial in double (j <= 18), rounded once.
+VRC_HD constexpr double inv_factorial(int j)
+{
+    double f = 1.0;
+    for (int i = 2; i <= j; ++i) f *= static_cast<double>(i);
+    return 1.0 / f;
+}
+
+VRC_HD inline double vrc_fma(double a, double b, double c) { return ::fma(a, b, c); }
+VRC_HD inline float vrc_fma(float a, float b, float c) { return ::fmaf(a, b, c); }
+VRC_HD inline double vrc_ldexp(double a, int k) { return ::ldexp(a, k); }
+VRC_HD inline float vrc_ldexp(float a, int k) { return ::ldexpf(a, k); }
+VRC_HD inline double vrc_rint(double a) { return ::rint(a); }
+VRC_HD inline float vrc_rint(float a) { return ::rintf(a); }
+
+// g = exp(-x), em = 1 - exp(-x) for x >= 0 (x > x_max or NaN: g = 0, em = 1).
+template <typename R>
+VRC_HD inline void attenuation(R x, R &g, R &em)
+{
+    using C = AttenConst<R>;
+    if (!(x <= C::x_max)) {
+        g = R(0);
+        em = R(1);
+        return;
+    }
+    const R y = -x;
+    const R kf = vrc_rint(y * C::inv_ln2);
+    R r = vrc_fma(-kf, C::ln2_hi, y);
+    r = vrc_fma(-kf, C::ln2_lo, r);
+    // Horner: q = r (1/1! + r (1/2! + r (1/3! + ... + r / degree!)))
+    R p = static_cast<R>(inv_factorial(C::degree));
+#pragma unroll
+    for (int j = C::degree - 1; j >= 1; --j) p = vrc_fma(p, r, static_cast<R>(inv_factorial(j)));
+    const R q = p * r;
+    const R s = vrc_ldexp(R(1), static_cast<int>(kf));
+    g = vrc_fma(s, q, s);
+    em = vrc_fma(-s, q, R(1) - s);
+}
+
+}  // namespace vrc

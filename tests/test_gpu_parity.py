@@ -439,3 +439,50 @@ def test_errors_are_reported(ctx, vrc):
     assert e.value.status == vrc.VRC_ERR_STATE
     with pytest.raises(vrc.VrcError):
         vrc.vrc_set_launch(ctx.handle, block=100)
+
+
+@pytest.mark.parametrize("prec", ["p32_t64", "p64"])
+def test_full_size_bench_workload(ctx, prec):
+    """The bench workload at full size (100^3, 1e6 rays) in the bench's default launch shape.
+
+    Whole-tally comparison with the oracle, the exact segment total, and a
+    bit-exact trace of a random sample of the rays.
+    """
+    import torch
+    wl = W.config2_multimaterial()
+    say(f"case: full-size multimat 100^3, 1e6 rays, {prec}, launch {ctx.get_launch()}")
+    setup(ctx, wl)
+    dt = "f64" if prec == "p64" else "f32"
+    arrays = dev_arrays(wl.rays, dt)
+    tid = ctx.create_tally(0, prec)
+    ctx.cast(tid, arrays)
+    got = ctx.read(tid)
+    counts = torch.empty(wl.rays.n, dtype=torch.int64, device="cuda:0")
+    total = ctx.count_segments(0, prec, arrays, counts)
+    if prec == "p64":
+        res = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=oracle_threads())
+        g, a, n = rel_report(got, res, gate="all")
+        say(f"  FP64 max rel over {n} voxels {g:.3e}")
+        assert g <= TOL_P64
+    else:
+        m, x, r = f32_view(wl.mesh, wl.xs, wl.rays)
+        res = oracle.cast(m, x, r, n_threads=oracle_threads())
+        g, a, n = rel_report(got, res, gate="stderr")
+        eps = eps_phi_max(got, res)
+        say(f"  FP32: gated {n} voxels max rel {g:.3e}; all voxels {a:.3e}; max eps_phi {eps:.3e}")
+        assert g <= TOL_P32
+        assert eps <= 1e-2
+    assert total == res.segments
+    rng = np.random.default_rng(0)
+    pick = np.sort(rng.choice(wl.rays.n, 3000, replace=False))
+    sample = wl.rays.take(pick)
+    offs, vox, ln, _ = ctx.trace(tid, dev_arrays(sample, dt))
+    if prec == "p64":
+        o_offs, o_vox, o_len = oracle_csr(wl.mesh, sample, "f64")
+    else:
+        m32 = W.Mesh(wl.mesh.lo.astype(np.float32), wl.mesh.h.astype(np.float32), wl.mesh.n, wl.mesh.mat)
+        o_offs, o_vox, o_len = oracle_csr(m32, W.rays_to_f32(sample), "f32")
+    np.testing.assert_array_equal(offs, o_offs)
+    np.testing.assert_array_equal(vox, o_vox)
+    np.testing.assert_array_equal(ln, np.asarray(o_len, np.float64))
+    np.testing.assert_array_equal(counts.cpu().numpy()[pick], np.diff(o_offs))
