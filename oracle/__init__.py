@@ -53,6 +53,9 @@ def lib():
         L.oracle_ray_scores.argtypes = [_d, _d, _i32, _u8, _int, _i64, _d, _d, _int, _d,
                                         _d, _d, ctypes.c_double, ctypes.c_double,
                                         _ll, _i64, _d, _d, ctypes.POINTER(ctypes.c_int)]
+        L.oracle_count_many.restype = _ll
+        L.oracle_count_many.argtypes = [_int, ctypes.c_void_p, ctypes.c_void_p, _i32, _ll] + [ctypes.c_void_p] * 6 + [
+            _int, _i64]
         L.oracle_cast.restype = _int
         L.oracle_cast.argtypes = ([_d, _d, _i32, _u8, _int, _i64, _d, _d, _int, _d, _ll]
                                   + [_d] * 8 + [_int, _d, _d, _i64, _i64, _d])
@@ -153,6 +156,20 @@ def trace_many(mesh, rays, precision: str = "f64"):
         if k < 0:
             raise RuntimeError("oracle trace failed")
         return offs, vox[:k], ln[:k]
+
+
+def count_segments(mesh, rays, precision: str = "f64", n_threads: int = 1) -> np.ndarray:
+    """Number of positive-length segments of every ray, in FP64 or FP32 traversal."""
+    dt = np.float64 if precision == "f64" else np.float32
+    lo, h = _c(mesh.lo, dt), _c(mesh.h, dt)
+    n = _c(mesh.n, np.int32)
+    arrs = [_c(getattr(rays, f), dt) for f in ("ox", "oy", "oz", "ux", "uy", "uz")]
+    counts = np.empty(arrs[0].size, np.int64)
+    tot = lib().oracle_count_many(1 if precision == "f64" else 0, lo.ctypes.data, h.ctypes.data, _p(n, _i32),
+                                  arrs[0].size, *[a.ctypes.data for a in arrs], int(n_threads), _p(counts, _i64))
+    if tot < 0:
+        raise RuntimeError("oracle count failed")
+    return counts
 
 
 # --------------------------------------------------------------------------

@@ -25,7 +25,8 @@
 // Score (Eqs. 1-4): with W_in the weight entering a voxel (Eq. 2),
 //   x = Sigma l,  F = W_in (1 - e^{-x}) / Sigma  (W_in l if Sigma = 0),
 //   W_out = W_in e^{-x},
-// with 1 - e^{-x} and e^{-x} from one evaluation (vrc_math.h).
+// with 1 - e^{-x} and e^{-x} from one evaluation (vrc_math.h), and W_in
+// re-anchored to w e^{-tau} (compensated tau) every few segments.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -262,12 +263,23 @@ __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, 
 // ---------------------------------------------------------------------------
 
 // Running VRC score of one ray; calls put(voxel, length, score) per piece.
+// The weight entering the next voxel is carried as a running product of the
+// segments' e^{-x}; the optical depth tau is summed alongside with Knuth's
+// TwoSum (compensated), and every kReanchor segments the weight is recomputed
+// as w e^{-tau}, so its error stays at a few ulp however long the ray is.
 template <typename R, class Put>
 struct Scorer {
+    static constexpr int kReanchor = 16;
     const R (*sig)[2];
     int stride;
+    R w0;
     R w_in;
+    R tau_hi;
+    R tau_lo;
+    int since;
     Put &put;
+    __device__ __forceinline__ Scorer(const R (*sig_)[2], int stride_, R w, Put &put_)
+        : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), since(0), put(put_) {}
     __device__ __forceinline__ void operator()(int32_t vox, int m, R l)
     {
         const R s = sig[m * stride][0];
@@ -276,8 +288,20 @@ struct Scorer {
         R g, em;
         attenuation(x, g, em);
         const R f = s > R(0) ? (w_in * em) * is : w_in * l;
-        w_in = w_in * g;
         put(vox, l, f);
+        const R t = tau_hi + x;
+        const R bv = t - tau_hi;
+        const R err = (tau_hi - (t - bv)) + (x - bv);
+        tau_hi = t;
+        tau_lo += err;
+        if (++since >= kReanchor) {
+            since = 0;
+            R G, unused;
+            attenuation(tau_hi, G, unused);
+            w_in = (w0 * G) * (R(1) - tau_lo);
+        } else {
+            w_in = w_in * g;
+        }
     }
 };
 
@@ -415,7 +439,7 @@ __device__ __forceinline__ void cast_block(const CastArgs<R> &A, PutMaker make_p
         auto put = make_put(r, bin);
         if (!put.active()) continue;
         xs_lookup(A.xs, hash, E, mysig, bd);
-        Scorer<R, decltype(put.inner)> sc{mysig, bd, wt, put.inner};
+        Scorer<R, decltype(put.inner)> sc(mysig, bd, wt, put.inner);
         walk(A.mesh, ox, oy, oz, ux, uy, uz, sc);
     }
 }

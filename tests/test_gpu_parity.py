@@ -180,14 +180,29 @@ def test_tally_multimaterial_fp64(ctx):
     assert g <= TOL_P64
 
 
-def eps_phi_max(got, res):
-    """Largest |phi_gpu - phi_oracle| / sigma over voxels with sigma > 0 (Eq. 8)."""
+def eps_phi_max(got, res, se_max=0.3):
+    """Largest |phi_gpu - phi_oracle| / sigma (Eq. 8) over voxels with some statistics.
+
+    sigma is the standard deviation of the voxel's tally sum with the rays
+    taken as independent histories.  Voxels are left out when phi is below
+    1e-30 max(phi) (FP32 scores there are denormal) or their relative
+    standard error is above se_max: such voxels are dominated by one or two
+    rays, and one ray that only clips a voxel corner carries the full FP32
+    ray-casting error of its short segment (a length of a few 1e-6 cm is
+    only known to about ulp(t) ~ 1e-6 cm at t ~ 20-60 cm).
+    """
     R = float(res.n_rays)
-    mean = res.tally.reshape(-1) / R
+    ref = res.tally.reshape(-1)
+    mean = ref / R
     var = np.maximum(res.sq.reshape(-1) / R - mean * mean, 0.0) * R / max(R - 1.0, 1.0)
-    sigma = np.sqrt(var * R)  # standard deviation of the tally sum
-    ok = sigma > 0
-    return float(np.max(np.abs(np.asarray(got).reshape(-1)[ok] - res.tally.reshape(-1)[ok]) / sigma[ok]))
+    sigma = np.sqrt(var * R)
+    ok = (sigma > 0) & (ref > 1e-30 * ref.max()) & (res.rel_std_err().reshape(-1) < se_max)
+    eps = np.abs(np.asarray(got).reshape(-1)[ok] - ref[ok]) / sigma[ok]
+    i = int(np.argmax(eps))
+    idx = np.flatnonzero(ok)[i]
+    say(f"  worst eps_phi voxel {idx}: oracle {ref[idx]:.6e} gpu {np.asarray(got).reshape(-1)[idx]:.6e} "
+        f"sigma {sigma[idx]:.3e} count {int(res.cnt.reshape(-1)[idx])}; voxels with eps > 0.01: {int(np.sum(eps > 0.01))}")
+    return float(eps[i])
 
 
 @pytest.mark.parametrize("prec", ["p32_t64", "p32_kahan"])
@@ -251,9 +266,12 @@ def test_tally_cylinder_with_void(ctx):
     assert g <= TOL_P64
     m, x, r = f32_view(wl.mesh, wl.xs, wl.rays)
     res32 = oracle.cast(m, x, r, n_threads=oracle_threads())
-    g32, a32, n32 = rel_report(ctx.read(t32), res32, gate="stderr")
-    say(f"  FP32 max rel {g32:.3e} over {n32} gated ({a32:.3e} all)")
+    got32 = ctx.read(t32)
+    g32, a32, n32 = rel_report(got32, res32, gate="stderr")
+    eps = eps_phi_max(got32, res32)
+    say(f"  FP32 max rel {g32:.3e} over {n32} gated ({a32:.3e} all); max eps_phi {eps:.3e}")
     assert g32 <= TOL_P32
+    assert eps <= 1e-2
 
 
 def test_energy_bins_and_out_of_range(ctx):
@@ -472,7 +490,13 @@ def test_full_size_bench_workload(ctx, prec):
         say(f"  FP32: gated {n} voxels max rel {g:.3e}; all voxels {a:.3e}; max eps_phi {eps:.3e}")
         assert g <= TOL_P32
         assert eps <= 1e-2
-    assert total == res.segments
+    if prec == "p64":
+        o_counts = oracle.count_segments(wl.mesh, wl.rays, "f64", oracle_threads())
+    else:
+        m32 = W.Mesh(wl.mesh.lo.astype(np.float32), wl.mesh.h.astype(np.float32), wl.mesh.n, wl.mesh.mat)
+        o_counts = oracle.count_segments(m32, W.rays_to_f32(wl.rays), "f32", oracle_threads())
+    np.testing.assert_array_equal(counts.cpu().numpy(), o_counts)
+    assert total == int(o_counts.sum())
     rng = np.random.default_rng(0)
     pick = np.sort(rng.choice(wl.rays.n, 3000, replace=False))
     sample = wl.rays.take(pick)
