@@ -70,7 +70,22 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the CPU oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--other-forms", type=int, default=1, help="also time the other precision forms")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB --steps times (to scale HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int, steps: int) -> None:
+    """A plain copy kernel of known size: reads and writes mib MiB per launch."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "steps": steps, "bytes_read_per_launch": n * 4,
+                      "bytes_written_per_launch": n * 4}), flush=True)
 
 
 def log(msg):
@@ -96,16 +111,20 @@ def time_casts(vrc, ctx, tid, arrays, steps, warmup, stream, torch):
 
 
 def cpu_baseline(wl, target_s):
+    """The FP64 oracle on the same workload: whole passes on all host threads for about target_s seconds."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
-    n_cal = 2000
-    cal = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, n_cal)), n_threads=threads, with_stats=False)
-    rate = cal.segments / max(cal.seconds, 1e-6)
-    n = int(min(wl.rays.n, max(n_cal, target_s * rate / max(cal.segments / n_cal, 1))))
-    res = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, n)), n_threads=threads, with_stats=False)
-    return {"value": res.segments / res.seconds, "unit": "segments/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of the {wl.rays.n} rays of the same workload, FP64 oracle, "
-                      f"{res.segments} segments in {res.seconds:.2f} s"}
+    segs, secs, passes = 0, 0.0, 0
+    while secs < target_s and passes < 64:
+        res = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=threads, with_stats=False)
+        segs += res.segments
+        secs += res.seconds
+        passes += 1
+    one = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, 20_000)), n_threads=1, with_stats=False)
+    return {"value": segs / secs, "unit": "segments/s", "cores": threads, "kind": "oracle",
+            "sample": f"{passes} full passes over the {wl.rays.n} rays of the same workload on {threads} threads "
+                      f"(FP64 oracle, {segs} segments in {secs:.2f} s of tracing and scoring)",
+            "single_thread_segments_per_s": one.segments / one.seconds}
 
 
 def main():
@@ -114,6 +133,9 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the path shards by replicating the tally per GPU, see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, args.steps)
+        return
     import torch
     import paper_1706_07476_amd as vrc
     import workloads as W
