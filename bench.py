@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 RAY_BYTES = {"f32": 32, "f64": 64}
 SEG_BYTES = 1 + 2 * 8
 KERNEL_SOURCES = ["paper_1706_07476_amd/csrc/vrc_kernels.hip", "paper_1706_07476_amd/csrc/vrc_internal.h",
-                  "paper_1706_07476_amd/csrc/vrc_math.h"]
+                  "paper_1706_07476_amd/csrc/vrc_math.h", "paper_1706_07476_amd/csrc/vrc_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cast_multimat_traffic.json")
 
 
@@ -70,9 +70,44 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the CPU oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--other-forms", type=int, default=1, help="also time the other precision forms")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="also time the batched form (2000 uneven batches on 4 meshes) against one launch per batch")
+    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB --steps times (to scale HBM byte counters)")
     return ap.parse_args()
+
+
+def _counter_mean(csv_path: str, kernel_prefix: str, counter: str) -> float:
+    import csv
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
+            if r["Kernel_Name"].startswith(kernel_prefix) and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {kernel_prefix} in {csv_path}")
+    return sum(vals) / len(vals)
+
+
+def write_traffic(paths, precision="p32_t64", copy_mib=1024) -> None:
+    """Scale FETCH_SIZE/WRITE_SIZE (KiB per dispatch) of the cast kernel by a plain copy of known size."""
+    cf, cw, pf, pw = paths
+    cast = "void vrc::(anonymous namespace)::cast_f64_kernel<float, float, false>"
+    fetch = _counter_mean(cf, cast, "FETCH_SIZE")
+    write = _counter_mean(cw, cast, "WRITE_SIZE")
+    copy_f = _counter_mean(pf, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
+    copy_w = _counter_mean(pw, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
+    nbytes = copy_mib * (1 << 20)
+    ff, fw = nbytes / (copy_f * 1024), nbytes / (copy_w * 1024)
+    t = {"kernel": cast, "workload": "multimat 100^3, 1e6 rays (bench.py default)", "precision": precision,
+         "launch": {"block": 256, "blocks_per_cu": 8, "hash_in_lds": 1, "aggregate": 0},
+         "kernel_hash": kernel_hash(), "fetch_size_kib_per_launch": fetch, "write_size_kib_per_launch": write,
+         "copy_calibration": {"bytes_read_and_written": nbytes, "fetch_size_kib": copy_f, "write_size_kib": copy_w,
+                              "fetch_scale": ff, "write_scale": fw},
+         "bytes_per_launch": fetch * 1024 * ff + write * 1024 * fw}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(t, f, indent=1)
+    print(json.dumps(t))
 
 
 def copy_calibration(mib: int, steps: int) -> None:
@@ -127,12 +162,80 @@ def cpu_baseline(wl, target_s):
             "single_thread_segments_per_s": one.segments / one.seconds}
 
 
+def bench_batched(steps: int) -> dict:
+    """Batched form: 2000 lognormal-sized batches (median 2e4 rays, 1e3..1e6) on 64^3..200^3 meshes.
+
+    One step = every batch once, cast into the tally of its mesh (p32_t64).
+    Timed both as ONE vrc_cast_batches call (persistent kernel, hipGraph,
+    autotuned shape) and as one vrc_cast_rays launch per batch.
+    """
+    import torch
+    import paper_1706_07476_amd as vrc
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    log("bench: generating the batched workload on the GPU")
+    wl, batches = W.config4_batches_device(dev)
+    ctx = vrc.Context(0)
+    ctx.set_xs(wl.xs)
+    tallies = []
+    for i, m in enumerate(wl.extra["meshes"]):
+        ctx.set_mesh(i, m)
+        tallies.append(ctx.create_tally(i, "p32_t64"))
+    mesh_of = wl.extra["mesh_of"]
+    items = [(tallies[mesh_of[b]], batches[b]) for b in range(len(batches))]
+    counts = torch.empty(max(a[0].numel() for a in batches), dtype=torch.int64, device=dev)
+    S = 0
+    for b, a in enumerate(batches):
+        S += ctx.count_segments(int(mesh_of[b]), "p32_t64", a, counts[:a[0].numel()])
+    R = int(sum(a[0].numel() for a in batches))
+    stream = torch.cuda.current_stream()
+    shape, tune_ms = ctx.autotune_batched(items[:200], repeats=2)
+    log(f"bench: batched shape {shape} ({tune_ms:.3f} ms on the first 200 batches)")
+    arr = vrc.make_batches(items)
+    for _ in range(2):
+        vrc.vrc_cast_batches(ctx.handle, arr, len(items), stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        vrc.vrc_cast_batches(ctx.handle, arr, len(items), stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per_b = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    plain_batches = [vrc.make_batch(a) for a in batches]
+    for b, pb in enumerate(plain_batches):
+        vrc.vrc_cast_rays(ctx.handle, tallies[mesh_of[b]], pb, stream)
+    torch.cuda.synchronize()
+    p_steps = max(1, steps // 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(p_steps):
+        for b, pb in enumerate(plain_batches):
+            vrc.vrc_cast_rays(ctx.handle, tallies[mesh_of[b]], pb, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / p_steps
+    batched_ms = float(np.mean(per_b))
+    ctx.close()
+    return {"workload": "2000 batches, lognormal sizes (median 2e4, 1e3..1e6 rays), meshes 64^3/128^3/160^3/200^3 "
+                        "of 0.5 cm, multimat tables, half the origins within a voxel of a face",
+            "rays_per_step": R, "segments_per_step": S, "precision": "p32_t64", "launch": shape,
+            "batched_segments_per_s": S / (batched_ms / 1e3), "batched_ms_per_step": batched_ms,
+            "plain_segments_per_s": S / (plain_ms / 1e3), "plain_ms_per_step": plain_ms,
+            "speedup_vs_plain": plain_ms / batched_ms,
+            "hbm_frac": (32 * R + SEG_BYTES * S) / (batched_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the path shards by replicating the tally per GPU, see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.write_traffic:
+        write_traffic(args.write_traffic)
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, args.steps)
         return
@@ -184,6 +287,11 @@ def main():
             others[p] = {"segments_per_s": S2 * len(per2) / (tot2 / 1e3), "ms_per_step": tot2 / len(per2),
                          "hbm_frac": (RAY_BYTES[d2] * R + SEG_BYTES * S2) / (float(np.mean(per2)) / 1e3) / 1e9 / HBM_PEAK_GBS}
             log(f"bench: form {p}: {others[p]['segments_per_s']:.3e} segments/s")
+    batched = None
+    if args.batched:
+        batched = bench_batched(args.batched_steps)
+        log(f"bench: batched {batched['batched_segments_per_s']:.3e} vs plain {batched['plain_segments_per_s']:.3e} "
+            "segments/s")
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
@@ -220,6 +328,7 @@ def main():
                      "kernel_ms": kern_s * 1e3},
         "cpu_baseline": cpu,
         "other_forms": others,
+        "batched_form": batched,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)

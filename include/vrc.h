@@ -169,6 +169,65 @@ vrc_status vrc_reset_tally(vrc_ctx *ctx, int tally_id);
 vrc_status vrc_set_launch(vrc_ctx *ctx, const vrc_launch *launch);
 vrc_status vrc_get_launch(vrc_ctx *ctx, vrc_launch *launch);
 
+/* ---- batched form: many uneven batches in one persistent kernel ------- */
+
+/* One ray batch of a batched call: device arrays (borrowed until the stream
+ * work ends), cast into tally `tally_id` (which fixes the mesh and the energy
+ * bins).  fp64 as in vrc_ray_batch.                                        */
+typedef struct {
+    int32_t tally_id;
+    int32_t fp64;
+    int64_t n;
+    const void *ox, *oy, *oz, *ux, *uy, *uz, *e, *w;
+} vrc_batch;
+
+/* Launch shape of the persistent batched kernel.  block, blocks_per_cu,
+ * hash_in_lds, aggregate as in vrc_launch (blocks_per_cu >= 1 here: the grid
+ * is n_CU * blocks_per_cu resident blocks); chunk: rays per work item (64 ..
+ * 1<<20); use_graph: replay a captured hipGraph (descriptor copy + kernel)
+ * instead of launching directly.                                            */
+typedef struct {
+    int32_t block;
+    int32_t blocks_per_cu;
+    int32_t chunk;
+    int32_t hash_in_lds;
+    int32_t aggregate;
+    int32_t use_graph;
+} vrc_batched_launch;
+
+/* Cast n_batches device-resident ray batches, each into its own tally, with
+ * ONE persistent kernel (no launch per batch; the paper issues one call per
+ * full ray buffer, Sec. 3, which is one vrc_cast_rays each).  Batches may be
+ * of any size (empty ones are skipped) and on different meshes; all tallies
+ * must have the same precision form and all batches the same fp64 flag.
+ * The host array `batches` is copied before the call returns; the work is
+ * asynchronous on hip_stream.  Results equal those of one vrc_cast_rays per
+ * batch up to the order of the tally additions.
+ * Errors: VRC_ERR_INVALID (ids, mixed forms, host pointers are not
+ * detected), VRC_ERR_STATE (no tables, material id >= n_mat), VRC_ERR_NOMEM,
+ * VRC_ERR_DEVICE.                                                          */
+vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batches, void *hip_stream);
+
+vrc_status vrc_set_batched_launch(vrc_ctx *ctx, const vrc_batched_launch *launch);
+vrc_status vrc_get_batched_launch(vrc_ctx *ctx, vrc_batched_launch *launch);
+
+/* ---- autotuner ---------------------------------------------------------- */
+
+/* Time candidate launch shapes of the persistent kernel on the given batches
+ * (cast into scratch tallies of the same shapes; the real tallies are not
+ * touched), keep the fastest as the context's batched shape, and return it
+ * with its time per call (ms).  repeats: timed calls per candidate (>= 1).
+ * The choice is cached per (precision, ray type, materials, meshes) in the
+ * context, and in the file named by the environment variable
+ * VRC_TUNE_CACHE if it is set.  Synchronous.                               */
+vrc_status vrc_autotune_batched(vrc_ctx *ctx, int n_batches, const vrc_batch *batches, int repeats,
+                                vrc_batched_launch *best, double *best_ms);
+
+/* The same for the plain kernel on one batch (vrc_cast_rays); sets the
+ * context's vrc_launch.                                                    */
+vrc_status vrc_autotune_cast(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch, int repeats,
+                             vrc_launch *best, double *best_ms);
+
 /* ---- inspection hooks (not on the timed path) ------------------------- */
 
 /* Number of positive-length voxel segments of every ray of a batch on mesh

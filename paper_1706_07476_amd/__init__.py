@@ -59,6 +59,16 @@ class vrc_launch(ctypes.Structure):
                 ("aggregate", ctypes.c_int32)]
 
 
+class vrc_batch(ctypes.Structure):
+    _fields_ = [("tally_id", ctypes.c_int32), ("fp64", ctypes.c_int32), ("n", ctypes.c_int64)] + [
+        (f, ctypes.c_void_p) for f in ("ox", "oy", "oz", "ux", "uy", "uz", "e", "w")]
+
+
+class vrc_batched_launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("hash_in_lds", ctypes.c_int32), ("aggregate", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _I64 = ctypes.c_int64
@@ -82,6 +92,11 @@ _SIGNATURES = {
     "vrc_get_launch": [_P, ctypes.POINTER(vrc_launch)],
     "vrc_count_segments": [_P, _I, _I, ctypes.POINTER(vrc_ray_batch), _P, _PI64, _P],
     "vrc_trace_rays": [_P, _I, ctypes.POINTER(vrc_ray_batch), _PI64, _PI64, _PD, _PD, _I64],
+    "vrc_cast_batches": [_P, _I, ctypes.POINTER(vrc_batch), _P],
+    "vrc_set_batched_launch": [_P, ctypes.POINTER(vrc_batched_launch)],
+    "vrc_get_batched_launch": [_P, ctypes.POINTER(vrc_batched_launch)],
+    "vrc_autotune_batched": [_P, _I, ctypes.POINTER(vrc_batch), _I, ctypes.POINTER(vrc_batched_launch), _PD],
+    "vrc_autotune_cast": [_P, _I, ctypes.POINTER(vrc_ray_batch), _I, ctypes.POINTER(vrc_launch), _PD],
 }
 _STRING_FUNCS = {"vrc_last_error": [], "vrc_version": []}
 
@@ -306,6 +321,57 @@ def vrc_trace_rays(ctx: int, tally_id: int, batch: vrc_ray_batch, cap: Optional[
     return offs, vox[:k], ln[:k], sc[:k]
 
 
+def make_batches(items):
+    """ctypes array of vrc_batch from (tally_id, [8 device arrays]) pairs."""
+    arr = (vrc_batch * max(1, len(items)))()
+    for i, (tid, arrays) in enumerate(items):
+        rb = make_batch(arrays)
+        if not rb.on_device and rb.n > 0:
+            raise ValueError("batched casts take device arrays")
+        b = arr[i]
+        b.tally_id = int(tid)
+        b.fp64 = rb.fp64
+        b.n = rb.n
+        for f in ("ox", "oy", "oz", "ux", "uy", "uz", "e", "w"):
+            setattr(b, f, getattr(rb, f))
+    return arr
+
+
+def vrc_cast_batches(ctx: int, batches, n: int, stream=None) -> None:
+    _check(load_library().vrc_cast_batches(ctx, n, batches, _stream(stream)))
+
+
+_BL_FIELDS = ("block", "blocks_per_cu", "chunk", "hash_in_lds", "aggregate", "use_graph")
+
+
+def vrc_set_batched_launch(ctx: int, block=256, blocks_per_cu=8, chunk=1024, hash_in_lds=1, aggregate=0,
+                           use_graph=1) -> None:
+    l = vrc_batched_launch(block, blocks_per_cu, chunk, hash_in_lds, aggregate, use_graph)
+    _check(load_library().vrc_set_batched_launch(ctx, ctypes.byref(l)))
+
+
+def vrc_get_batched_launch(ctx: int) -> dict:
+    l = vrc_batched_launch()
+    _check(load_library().vrc_get_batched_launch(ctx, ctypes.byref(l)))
+    return {f: getattr(l, f) for f in _BL_FIELDS}
+
+
+def vrc_autotune_batched(ctx: int, batches, n: int, repeats: int = 2):
+    l = vrc_batched_launch()
+    ms = ctypes.c_double(0.0)
+    _check(load_library().vrc_autotune_batched(ctx, n, batches, repeats, ctypes.byref(l), ctypes.byref(ms)))
+    return {f: getattr(l, f) for f in _BL_FIELDS}, ms.value
+
+
+def vrc_autotune_cast(ctx: int, tally_id: int, batch: vrc_ray_batch, repeats: int = 2):
+    l = vrc_launch()
+    ms = ctypes.c_double(0.0)
+    _check(load_library().vrc_autotune_cast(ctx, tally_id, ctypes.byref(batch), repeats, ctypes.byref(l),
+                                            ctypes.byref(ms)))
+    return {"block": l.block, "blocks_per_cu": l.blocks_per_cu, "hash_in_lds": l.hash_in_lds,
+            "aggregate": l.aggregate}, ms.value
+
+
 # ----------------------------------------------------------------------------
 # convenience object
 # ----------------------------------------------------------------------------
@@ -371,3 +437,23 @@ class Context:
 
     def count_segments(self, mesh_id: int, precision, arrays, counts, stream=None) -> int:
         return vrc_count_segments(self.handle, mesh_id, precision, make_batch(arrays), counts, stream)
+
+    def cast_batches(self, items, stream=None) -> None:
+        """items: list of (tally_id, [8 device arrays]); one persistent-kernel launch."""
+        arr = make_batches(items)
+        vrc_cast_batches(self.handle, arr, len(items), stream)
+
+    def set_batched_launch(self, **kw) -> None:
+        cur = vrc_get_batched_launch(self.handle)
+        cur.update(kw)
+        vrc_set_batched_launch(self.handle, **cur)
+
+    def get_batched_launch(self) -> dict:
+        return vrc_get_batched_launch(self.handle)
+
+    def autotune_batched(self, items, repeats: int = 2):
+        arr = make_batches(items)
+        return vrc_autotune_batched(self.handle, arr, len(items), repeats)
+
+    def autotune_cast(self, tally_id: int, arrays, repeats: int = 2):
+        return vrc_autotune_cast(self.handle, tally_id, make_batch(arrays), repeats)

@@ -189,12 +189,29 @@ vrc_status vrc_create(int device, vrc_ctx **out)
     auto *ctx = new vrc_ctx();
     ctx->device = device;
     ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    ctx->arch = prop.gcnArchName;
     for (auto &st : ctx->stage) {
         e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
         if (e != hipSuccess) {
-            delete ctx;
+            vrc_destroy(ctx);
             return set_error(VRC_ERR_DEVICE, "hipEventCreate failed");
         }
+    }
+    for (auto &bs : ctx->bslot) {
+        e = hipEventCreateWithFlags(&bs.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            vrc_destroy(ctx);
+            return set_error(VRC_ERR_DEVICE, "hipEventCreate failed");
+        }
+    }
+    e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_mesh32, sizeof(MeshP<float>) * kMaxMeshes);
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_mesh64, sizeof(MeshP<double>) * kMaxMeshes);
+    if (e == hipSuccess) e = hipMemset(ctx->d_mesh32, 0, sizeof(MeshP<float>) * kMaxMeshes);
+    if (e == hipSuccess) e = hipMemset(ctx->d_mesh64, 0, sizeof(MeshP<double>) * kMaxMeshes);
+    if (e != hipSuccess) {
+        vrc_destroy(ctx);
+        return set_error(VRC_ERR_DEVICE, std::string("context set-up: ") + hipGetErrorString(e));
     }
     *out = ctx;
     return VRC_OK;
@@ -218,6 +235,16 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         free_dev(st.d_buf);
         if (st.done) (void)hipEventDestroy(st.done);
     }
+    for (auto &bs : ctx->bslot) {
+        if (bs.exec) (void)hipGraphExecDestroy(bs.exec);
+        if (bs.graph) (void)hipGraphDestroy(bs.graph);
+        if (bs.h_buf) (void)hipHostFree(bs.h_buf);
+        free_dev(bs.d_buf);
+        if (bs.done) (void)hipEventDestroy(bs.done);
+    }
+    free_dev(ctx->d_mesh32);
+    free_dev(ctx->d_mesh64);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
     return VRC_OK;
 }
@@ -255,6 +282,20 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
     m.nvox = nvox;
     m.max_mat = max_mat;
     m.set = true;
+    MeshP<float> m32;
+    MeshP<double> m64;
+    for (int a = 0; a < 3; ++a) {
+        m32.lo[a] = static_cast<float>(lo[a]);
+        m32.h[a] = static_cast<float>(h[a]);
+        m32.n[a] = n[a];
+        m64.lo[a] = lo[a];
+        m64.h[a] = h[a];
+        m64.n[a] = n[a];
+    }
+    m32.mat = m.d_mat;
+    m64.mat = m.d_mat;
+    VRC_HIP(ctx, hipMemcpy(ctx->d_mesh32 + mesh_id, &m32, sizeof(m32), hipMemcpyHostToDevice));
+    VRC_HIP(ctx, hipMemcpy(ctx->d_mesh64 + mesh_id, &m64, sizeof(m64), hipMemcpyHostToDevice));
     return VRC_OK;
 }
 
@@ -329,6 +370,7 @@ vrc_status vrc_create_tally(vrc_ctx *ctx, int mesh_id, int n_ebins, const double
         return set_error(VRC_ERR_NOMEM, "tally allocation failed");
     }
     if (edges) {
+        t->edges.assign(edges, edges + n_ebins + 1);
         void *p = nullptr;
         if (vrc_status s = upload(ctx, &p, edges, sizeof(double) * (n_ebins + 1))) {
             free_dev(t->d_data);
@@ -594,6 +636,148 @@ vrc_status vrc_trace_rays(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch
     if (st != VRC_OK) return st;
     if (e == hipErrorOutOfMemory) return set_error(VRC_ERR_NOMEM, "trace buffers");
     if (e != hipSuccess) return device_error(ctx, e, "trace");
+    return VRC_OK;
+}
+
+
+vrc_status vrc_set_batched_launch(vrc_ctx *ctx, const vrc_batched_launch *l)
+{
+    if (!ctx || !l) return set_error(VRC_ERR_INVALID, "null argument");
+    if (l->block < 64 || l->block > 1024 || l->block % 64 != 0)
+        return set_error(VRC_ERR_INVALID, "block must be a multiple of 64 in 64..1024");
+    if (l->blocks_per_cu < 1 || l->blocks_per_cu > 64) return set_error(VRC_ERR_INVALID, "blocks_per_cu in 1..64");
+    if (l->chunk < 64 || l->chunk > (1 << 20)) return set_error(VRC_ERR_INVALID, "chunk in 64..2^20");
+    if ((l->hash_in_lds != 0 && l->hash_in_lds != 1) || (l->aggregate != 0 && l->aggregate != 1) ||
+        (l->use_graph != 0 && l->use_graph != 1))
+        return set_error(VRC_ERR_INVALID, "hash_in_lds, aggregate and use_graph are 0 or 1");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->batched.block = l->block;
+    ctx->batched.blocks_per_cu = l->blocks_per_cu;
+    ctx->batched.chunk = l->chunk;
+    ctx->batched.hash_in_lds = l->hash_in_lds;
+    ctx->batched.aggregate = l->aggregate;
+    ctx->batched.use_graph = l->use_graph;
+    return VRC_OK;
+}
+
+vrc_status vrc_get_batched_launch(vrc_ctx *ctx, vrc_batched_launch *l)
+{
+    if (!ctx || !l) return set_error(VRC_ERR_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    l->block = ctx->batched.block;
+    l->blocks_per_cu = ctx->batched.blocks_per_cu;
+    l->chunk = ctx->batched.chunk;
+    l->hash_in_lds = ctx->batched.hash_in_lds;
+    l->aggregate = ctx->batched.aggregate;
+    l->use_graph = ctx->batched.use_graph;
+    return VRC_OK;
+}
+
+vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batches, void *hip_stream)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    if (n_batches < 0) return set_error(VRC_ERR_INVALID, "negative batch count");
+    if (n_batches > 0 && !batches) return set_error(VRC_ERR_INVALID, "null batches");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const BatchedShape shape = ctx->batched;
+    int prec = -1, fp64 = -1;
+    std::vector<BatchDescDev> desc;
+    desc.reserve(static_cast<size_t>(n_batches));
+    int64_t items = 0;
+    for (int i = 0; i < n_batches; ++i) {
+        const vrc_batch &b = batches[i];
+        TallyHost *t = get_tally(ctx, b.tally_id);
+        if (!t) return set_error(VRC_ERR_INVALID, "batch names no tally");
+        if (b.n < 0 || b.n > (int64_t(1) << 40)) return set_error(VRC_ERR_INVALID, "bad ray count in a batch");
+        if (b.fp64 != 0 && b.fp64 != 1) return set_error(VRC_ERR_INVALID, "fp64 must be 0 or 1");
+        if (prec < 0) prec = t->prec;
+        if (fp64 < 0) fp64 = b.fp64;
+        if (prec != static_cast<int>(t->prec)) return set_error(VRC_ERR_INVALID, "tallies of one call must share a precision form");
+        if (fp64 != b.fp64) return set_error(VRC_ERR_INVALID, "batches of one call must share the ray type");
+        if (vrc_status st = check_cast_ready(ctx, t)) return st;
+        if (b.n == 0) continue;
+        if (!b.ox || !b.oy || !b.oz || !b.ux || !b.uy || !b.uz || !b.e || !b.w)
+            return set_error(VRC_ERR_INVALID, "null ray array in a batch");
+        BatchDescDev d;
+        const void *src[8] = {b.ox, b.oy, b.oz, b.ux, b.uy, b.uz, b.e, b.w};
+        for (int k = 0; k < 8; ++k) d.ray[k] = src[k];
+        d.n = b.n;
+        d.item_begin = items;
+        d.tally = t->d_data;
+        d.edges = t->d_edges;
+        d.nvox = t->nvox;
+        d.n_bins = t->n_bins;
+        d.mesh = t->mesh_id;
+        items += (b.n + shape.chunk - 1) / shape.chunk;
+        desc.push_back(d);
+    }
+    if (desc.empty()) return VRC_OK;
+    if (desc.size() > (size_t(1) << 30)) return set_error(VRC_ERR_INVALID, "too many batches");
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    BatchedHeader hdr{items, static_cast<int32_t>(desc.size()), shape.chunk};
+    const size_t bytes = sizeof(BatchedHeader) + sizeof(BatchDescDev) * desc.size();
+    BatchedSlot &bs = ctx->bslot[ctx->bslot_next];
+    ctx->bslot_next ^= 1;
+    if (bs.used) VRC_HIP(ctx, hipEventSynchronize(bs.done));
+    if (bs.cap < bytes) {
+        if (bs.exec) (void)hipGraphExecDestroy(bs.exec);
+        if (bs.graph) (void)hipGraphDestroy(bs.graph);
+        bs.exec = nullptr;
+        bs.graph = nullptr;
+        if (bs.h_buf) (void)hipHostFree(bs.h_buf);
+        free_dev(bs.d_buf);
+        bs.h_buf = nullptr;
+        bs.cap = 0;
+        size_t cap = 65536;
+        while (cap < bytes) cap *= 2;
+        if (hipHostMalloc(reinterpret_cast<void **>(&bs.h_buf), cap, hipHostMallocDefault) != hipSuccess) {
+            bs.h_buf = nullptr;
+            return set_error(VRC_ERR_NOMEM, "pinned descriptor buffer");
+        }
+        if (hipMalloc(reinterpret_cast<void **>(&bs.d_buf), cap) != hipSuccess) {
+            bs.d_buf = nullptr;
+            return set_error(VRC_ERR_NOMEM, "device descriptor buffer");
+        }
+        bs.cap = cap;
+    }
+    std::memcpy(bs.h_buf, &hdr, sizeof(hdr));
+    std::memcpy(bs.h_buf + sizeof(hdr), desc.data(), sizeof(BatchDescDev) * desc.size());
+    const vrc_precision pr = static_cast<vrc_precision>(prec);
+    if (shape.use_graph) {
+        const bool stale = !bs.exec || !(bs.graph_shape == shape) || bs.graph_prec != prec || bs.graph_fp64 != fp64 ||
+                           bs.graph_bytes != bs.cap;
+        if (stale) {
+            if (bs.exec) (void)hipGraphExecDestroy(bs.exec);
+            if (bs.graph) (void)hipGraphDestroy(bs.graph);
+            bs.exec = nullptr;
+            bs.graph = nullptr;
+            // the graph: copy the whole descriptor buffer, then the persistent kernel
+            VRC_HIP(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed));
+            hipError_t e = hipMemcpyAsync(bs.d_buf, bs.h_buf, bs.cap, hipMemcpyHostToDevice, ctx->capture_stream);
+            if (e == hipSuccess) e = launch_batched(*ctx, shape, pr, fp64 != 0, bs.d_buf, ctx->capture_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &g);
+            if (e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return device_error(ctx, e, "capturing the batched graph");
+            }
+            if (e2 != hipSuccess) return device_error(ctx, e2, "hipStreamEndCapture");
+            bs.graph = g;
+            VRC_HIP(ctx, hipGraphInstantiate(&bs.exec, bs.graph, nullptr, nullptr, 0));
+            bs.graph_shape = shape;
+            bs.graph_prec = prec;
+            bs.graph_fp64 = fp64;
+            bs.graph_bytes = bs.cap;
+        }
+        VRC_HIP(ctx, hipGraphLaunch(bs.exec, s));
+    } else {
+        VRC_HIP(ctx, hipMemcpyAsync(bs.d_buf, bs.h_buf, bytes, hipMemcpyHostToDevice, s));
+        hipError_t e = launch_batched(*ctx, shape, pr, fp64 != 0, bs.d_buf, s);
+        if (e != hipSuccess) return device_error(ctx, e, "batched kernel launch");
+    }
+    VRC_HIP(ctx, hipEventRecord(bs.done, s));
+    bs.used = true;
     return VRC_OK;
 }
 

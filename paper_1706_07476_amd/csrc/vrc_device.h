@@ -1,0 +1,433 @@
+// Device-side pieces of the VRC cast shared by the plain kernels
+// (vrc_kernels.hip) and the persistent batched kernel (vrc_batched.hip):
+// traversal, cross-section lookup, score and tally sinks.
+//
+// One lane casts one ray (Sec. 3 of the paper: each GPU thread first finds
+// the cross sections, then casts the ray, then scores the VRC estimator).
+// Unlike the paper's three phases with a per-thread list of path lengths,
+// the three steps are fused into a single pass: the cross sections of every
+// material are computed once per ray and kept in LDS, the ray is walked voxel
+// by voxel (3-D DDA), and each segment is scored and tallied as soon as it is
+// known, so no per-ray segment list ever touches memory.
+//
+// Traversal arithmetic (identical in the FP32 and FP64 instantiations, and
+// the reason this file is built with -ffp-contract=off):
+//   plane            X_a(k) = lo_a + (R)k * h_a          (product, then sum)
+//   crossing time    T_a(k) = (X_a(k) - o_a) * inv_a,  inv_a = 1 / u_a
+//   parallel axis    inv_a = +-inf
+//   clip             t_enter = max(0, max_a min(T_a(0), T_a(n_a))),
+//                    t_exit  = min_a max(T_a(0), T_a(n_a))
+//   start voxel      u_a > 0: largest k with T_a(k) <= t_enter;
+//                    u_a < 0: smallest k with T_a(k+1) <= t_enter;
+//                    parallel: largest k with X_a(k) <= o_a
+//   step             the axis with the smallest next crossing, ties to the
+//                    lowest axis; crossings recomputed from the integer index;
+//                    pieces of length <= 0 are not scored.
+//
+// Score (Eqs. 1-4): with W_in the weight entering a voxel (Eq. 2),
+//   x = Sigma l,  F = W_in (1 - e^{-x}) / Sigma  (W_in l if Sigma = 0),
+//   W_out = W_in e^{-x},
+// with 1 - e^{-x} and e^{-x} from one evaluation (vrc_math.h), and W_in
+// re-anchored to w e^{-tau} (compensated tau) every few segments.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "vrc_internal.h"
+#include "vrc_math.h"
+
+namespace vrc {
+namespace dev {
+
+template <typename R>
+struct Num;
+template <>
+struct Num<float> {
+    static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
+};
+template <>
+struct Num<double> {
+    static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+};
+
+template <typename R>
+__device__ __forceinline__ R plane(R lo, R h, int k)
+{
+    R kk = static_cast<R>(k);
+    R p = kk * h;
+    return lo + p;
+}
+
+// Guess of a voxel index from a coordinate, clamped into [0, n-1] (NaN -> 0).
+template <typename R>
+__device__ __forceinline__ int guess_index(R p, R lo, R h, int n)
+{
+    R g = (p - lo) / h;
+    if (!(g >= R(0))) return 0;
+    if (g >= static_cast<R>(n)) return n - 1;
+    int k = static_cast<int>(g);
+    return k > n - 1 ? n - 1 : k;
+}
+
+// Start voxel on one axis (the rule in the file header) and its first
+// crossing time.  The guess from the entry point is corrected by a search
+// that only ever moves a step or two.
+template <typename R>
+__device__ __forceinline__ void start_axis(R lo, R h, int n, R o, R u, R inv, bool par, R t_enter,
+                                           int &idx, R &tn, int &step)
+{
+    int k;
+    if (par) {
+        k = guess_index(o, lo, h, n);
+        while (k > 0 && plane(lo, h, k) > o) --k;
+        while (k < n - 1 && plane(lo, h, k + 1) <= o) ++k;
+        tn = Num<R>::inf();
+        step = 0;
+    } else {
+        const R p = o + t_enter * u;
+        k = guess_index(p, lo, h, n);
+        if (u > R(0)) {
+            while (k > 0 && (plane(lo, h, k) - o) * inv > t_enter) --k;
+            while (k < n - 1 && (plane(lo, h, k + 1) - o) * inv <= t_enter) ++k;
+            tn = (plane(lo, h, k + 1) - o) * inv;
+            step = 1;
+        } else {
+            while (k > 0 && (plane(lo, h, k) - o) * inv <= t_enter) --k;
+            while (k < n - 1 && (plane(lo, h, k + 1) - o) * inv > t_enter) ++k;
+            tn = (plane(lo, h, k) - o) * inv;
+            step = -1;
+        }
+    }
+    idx = k;
+}
+
+// Slab clip on one axis: narrows [t_enter, t_exit]; false if the ray runs
+// parallel to the axis outside the mesh.
+template <typename R>
+__device__ __forceinline__ bool clip_axis(R lo, R h, int n, R o, R inv, bool par, R &t_enter, R &t_exit)
+{
+    const R x0 = plane(lo, h, 0);
+    const R x1 = plane(lo, h, n);
+    if (par) return x0 <= o && o < x1;
+    const R ta = (x0 - o) * inv;
+    const R tb = (x1 - o) * inv;
+    const R tmin = ta < tb ? ta : tb;
+    const R tmax = ta < tb ? tb : ta;
+    if (tmin > t_enter) t_enter = tmin;
+    if (tmax < t_exit) t_exit = tmax;
+    return true;
+}
+
+// Cast one ray through the mesh: seg(vox, mat, len) is called for every
+// positive-length piece, in order.  All traversal state lives in local
+// scalars (one set per axis), never in an array indexed by the axis, so it
+// stays in registers.  The material of the next voxel is loaded before the
+// current piece is handed on, so its latency overlaps the score and the
+// atomic.  Returns false if the ray misses the mesh.
+template <typename R, class Seg>
+__device__ __forceinline__ bool walk(const MeshP<R> &M, R ox, R oy, R oz, R ux, R uy, R uz, Seg &seg)
+{
+    const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
+    const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
+    const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
+    const R ix = R(1) / ux, iy = R(1) / uy, iz = R(1) / uz;
+    const bool px = __builtin_isinf(ix), py = __builtin_isinf(iy), pz = __builtin_isinf(iz);
+    R t_enter = R(0);
+    R t_exit = Num<R>::inf();
+    if (!clip_axis(lox, hx, nx, ox, ix, px, t_enter, t_exit)) return false;
+    if (!clip_axis(loy, hy, ny, oy, iy, py, t_enter, t_exit)) return false;
+    if (!clip_axis(loz, hz, nz, oz, iz, pz, t_enter, t_exit)) return false;
+    if (!(t_enter < t_exit)) return false;
+    if (!(t_exit < Num<R>::inf())) return false;  // zero direction: not a ray
+    int kx, ky, kz, sx, sy, sz;
+    R tx, ty, tz;
+    start_axis(lox, hx, nx, ox, ux, ix, px, t_enter, kx, tx, sx);
+    start_axis(loy, hy, ny, oy, uy, iy, py, t_enter, ky, ty, sy);
+    start_axis(loz, hz, nz, oz, uz, iz, pz, t_enter, kz, tz, sz);
+    const int32_t dy = nx;
+    const int32_t dz = nx * ny;
+    int32_t vox = kx + nx * (ky + ny * kz);
+    R cur = t_enter;
+    int budget = nx + ny + nz + 3;  // planes crossed at most
+    int m = M.mat[vox];
+    while (true) {
+        const bool ax = (tx <= ty) && (tx <= tz);
+        const bool ay = !ax && (ty <= tz);
+        const bool az = !ax && !ay;
+        const R ta = ax ? tx : (ay ? ty : tz);
+        const bool last = !(ta < t_exit);
+        const R l = (last ? t_exit : ta) - cur;
+        const int32_t vcur = vox;
+        const int mcur = m;
+        bool inside = true;
+        if (!last) {
+            // advance along the chosen axis and fetch the next voxel's material early
+            const int s = ax ? sx : (ay ? sy : sz);
+            const int ni = (ax ? kx : (ay ? ky : kz)) + s;
+            const int na = ax ? nx : (ay ? ny : nz);
+            inside = static_cast<unsigned>(ni) < static_cast<unsigned>(na);
+            if (inside) {
+                const int32_t dv = ax ? 1 : (ay ? dy : dz);
+                vox = vcur + (s > 0 ? dv : -dv);
+                m = M.mat[vox];
+                const R lo = ax ? lox : (ay ? loy : loz);
+                const R h = ax ? hx : (ay ? hy : hz);
+                const R oa = ax ? ox : (ay ? oy : oz);
+                const R inv = ax ? ix : (ay ? iy : iz);
+                const R tnew = (plane(lo, h, ni + (s > 0 ? 1 : 0)) - oa) * inv;
+                kx = ax ? ni : kx;
+                ky = ay ? ni : ky;
+                kz = az ? ni : kz;
+                tx = ax ? tnew : tx;
+                ty = ay ? tnew : ty;
+                tz = az ? tnew : tz;
+            }
+            cur = ta;
+        }
+        if (l > R(0)) seg(vcur, mcur, l);
+        if (last || !inside || --budget <= 0) break;
+    }
+    return true;
+}
+
+template <typename R, typename RT>
+__device__ __forceinline__ R ld(const void *p, int64_t i)
+{
+    return static_cast<R>(static_cast<const RT *>(p)[i]);
+}
+
+// Energy bin of a ray: edges[b] <= E < edges[b+1], the top edge in the last
+// bin, -1 outside; no edges: bin 0.
+__device__ __forceinline__ int energy_bin(const TallyP &T, double E)
+{
+    if (T.edges == nullptr) return 0;
+    const int nb = T.n_bins;
+    if (!(E >= T.edges[0] && E <= T.edges[nb])) return -1;
+    if (E == T.edges[nb]) return nb - 1;
+    int lo = 0, hi = nb;  // edges[lo] <= E < edges[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (T.edges[mid] <= E) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Sigma_m(E) of every material (Sec. 3: hashed energy lookup, linear
+// interpolation), written with 1/Sigma to the lane's LDS column:
+// sig[m * stride + lane] = {Sigma, 1/Sigma (0 for Sigma = 0)}.
+template <typename R>
+__device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, R E,
+                                          R (*sig)[2], int stride)
+{
+    const int K = X.K;
+    int k;
+    bool interp = false;
+    if (K == 1 || !(E >= X.E[0])) {
+        k = 0;
+    } else if (E >= X.E[K - 1]) {
+        k = K - 1;
+    } else {
+        float lg = __log2f(static_cast<float>(E));
+        float fb = (lg - X.l2e0) * X.inv_dl2;
+        int b = 0;
+        if (fb >= 0.f) b = fb < static_cast<float>(X.M) ? static_cast<int>(fb) : X.M - 1;
+        k = hash[b];
+        while (k > 0 && X.E[k] > E) --k;
+        while (k < K - 2 && X.E[k + 1] <= E) ++k;
+        interp = true;
+    }
+    const R *s0 = X.S + static_cast<int64_t>(k) * X.s_stride;
+    if (interp) {
+        const R e0 = X.E[k];
+        const R e1 = X.E[k + 1];
+        const R de = e1 - e0;
+        const R dx = E - e0;
+        const R *s1 = s0 + X.s_stride;
+        for (int m = 0; m < X.n_mat; ++m) {
+            R slope = (s1[m] - s0[m]) / de;
+            R v = s0[m] + slope * dx;
+            sig[m * stride][0] = v;
+            sig[m * stride][1] = v > R(0) ? R(1) / v : R(0);
+        }
+    } else {
+        for (int m = 0; m < X.n_mat; ++m) {
+            R v = s0[m];
+            sig[m * stride][0] = v;
+            sig[m * stride][1] = v > R(0) ? R(1) / v : R(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Segment consumers
+// ---------------------------------------------------------------------------
+
+// Running VRC score of one ray; calls put(voxel, length, score) per piece.
+// The weight entering the next voxel is carried as a running product of the
+// segments' e^{-x}; the optical depth tau is summed alongside with Knuth's
+// TwoSum (compensated), and every kReanchor segments the weight is recomputed
+// as w e^{-tau}, so its error stays at a few ulp however long the ray is.
+template <typename R, class Put>
+struct Scorer {
+    static constexpr int kReanchor = 16;
+    const R (*sig)[2];
+    int stride;
+    R w0;
+    R w_in;
+    R tau_hi;
+    R tau_lo;
+    int since;
+    Put &put;
+    __device__ __forceinline__ Scorer(const R (*sig_)[2], int stride_, R w, Put &put_)
+        : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), since(0), put(put_) {}
+    __device__ __forceinline__ void operator()(int32_t vox, int m, R l)
+    {
+        const R s = sig[m * stride][0];
+        const R is = sig[m * stride][1];
+        const R x = s * l;
+        R g, em;
+        attenuation(x, g, em);
+        const R f = s > R(0) ? (w_in * em) * is : w_in * l;
+        put(vox, l, f);
+        const R t = tau_hi + x;
+        const R bv = t - tau_hi;
+        const R err = (tau_hi - (t - bv)) + (x - bv);
+        tau_hi = t;
+        tau_lo += err;
+        if (++since >= kReanchor) {
+            since = 0;
+            R G, unused;
+            attenuation(tau_hi, G, unused);
+            w_in = (w0 * G) * (R(1) - tau_lo);
+        } else {
+            w_in = w_in * g;
+        }
+    }
+};
+
+// FP64 atomics into tally[base + vox]; optional wave aggregation of lanes
+// that hit the same tally element in the same step.
+template <bool AGG>
+struct PutF64 {
+    double *tally;
+    int64_t base;
+    double *wave_lds;  // 64 doubles per wave (AGG only)
+    __device__ __forceinline__ void operator()(int32_t vox, double, double f)
+    {
+        const int64_t key = base + vox;
+        if constexpr (AGG) {
+            const uint64_t act = __ballot(1);
+            const int leader = __ffsll(static_cast<unsigned long long>(act)) - 1;
+            const int64_t lkey = __shfl(key, leader);
+            const bool match = key == lkey;
+            const uint64_t mm = __ballot(match);
+            if (__popcll(mm) > 1) {
+                const int lane = __lane_id();
+                if (match) wave_lds[lane] = f;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane == leader) {
+                    double sum = 0.0;
+                    uint64_t bits = mm;
+                    while (bits) {
+                        const int j = __ffsll(static_cast<unsigned long long>(bits)) - 1;
+                        sum += wave_lds[j];
+                        bits &= bits - 1;
+                    }
+                    if (sum != 0.0) unsafeAtomicAdd(tally + key, sum);
+                } else if (!match && f != 0.0) {
+                    unsafeAtomicAdd(tally + key, f);
+                }
+                __builtin_amdgcn_wave_barrier();
+                return;
+            }
+        }
+        if (f != 0.0) unsafeAtomicAdd(tally + key, f);
+    }
+};
+
+// Compensated FP32 tally: pair {sum, comp} per element.  The atomic add
+// returns the old sum, so the rounding error of the add performed in memory
+// is recovered exactly (Knuth's TwoSum) and added to the compensation term.
+struct PutKahan {
+    float *pairs;
+    int64_t base;
+    __device__ __forceinline__ void operator()(int32_t vox, float, float f)
+    {
+        if (f == 0.f) return;
+        float *p = pairs + 2 * (base + vox);
+        const float old = unsafeAtomicAdd(p, f);
+        const float s = old + f;
+        const float bv = s - old;
+        const float av = s - bv;
+        const float err = (old - av) + (f - bv);
+        if (err != 0.f) unsafeAtomicAdd(p + 1, err);
+    }
+};
+
+template <typename R>
+struct PutTrace {
+    int64_t pos;
+    int64_t *voxel;
+    double *len;
+    double *score;
+    bool scored;
+    __device__ __forceinline__ void operator()(int32_t vox, R l, R f)
+    {
+        voxel[pos] = vox;
+        len[pos] = static_cast<double>(l);
+        score[pos] = scored ? static_cast<double>(f) : 0.0;
+        ++pos;
+    }
+};
+
+struct CountSeg {
+    int64_t n = 0;
+    template <typename R>
+    __device__ __forceinline__ void operator()(int32_t, int, R) { ++n; }
+};
+
+
+// Stage the hash index of the energy grid into LDS (if asked) and hand out
+// the block's LDS columns for per-lane cross sections.  Dynamic LDS layout:
+// [sigma columns: n_mat * blockDim pairs of R][hash: M int32 if staged].
+template <typename R>
+__device__ __forceinline__ void stage_lds(const XsP<R> &X, int hash_in_lds, const int32_t *&hash, R (*&sig)[2])
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int bd = blockDim.x;
+    sig = reinterpret_cast<R(*)[2]>(lds);
+    unsigned char *after = lds + sizeof(R) * 2 * static_cast<size_t>(X.n_mat) * bd;
+    if (hash_in_lds) {
+        int32_t *h = reinterpret_cast<int32_t *>(after);
+        for (int j = threadIdx.x; j < X.M; j += bd) h[j] = X.hash[j];
+        __syncthreads();
+        hash = h;
+    } else {
+        hash = X.hash;
+    }
+}
+
+// Cross sections of the ray's energy, then the walk with the running score.
+template <typename R, class Put>
+__device__ __forceinline__ void cast_one(const MeshP<R> &M, const XsP<R> &X, const int32_t *hash, R (*mysig)[2],
+                                         int bd, R ox, R oy, R oz, R ux, R uy, R uz, R E, R w, Put &put)
+{
+    xs_lookup(X, hash, E, mysig, bd);
+    Scorer<R, Put> sc(mysig, bd, w, put);
+    walk(M, ox, oy, oz, ux, uy, uz, sc);
+}
+
+template <typename P>
+struct Active {
+    P inner;
+    bool on;
+    __device__ __forceinline__ bool active() const { return on; }
+};
+
+}  // namespace dev
+}  // namespace vrc

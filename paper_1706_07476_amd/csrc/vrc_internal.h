@@ -79,6 +79,39 @@ struct LaunchShape {
     int aggregate = 0;
 };
 
+// One ray batch of a batched call, as the persistent kernel reads it.
+struct BatchDescDev {
+    const void *ray[8];   // ox, oy, oz, ux, uy, uz, e, w (device, RT each)
+    int64_t n;            // rays
+    int64_t item_begin;   // index of the batch's first work item
+    void *tally;          // tally data (FP64, or FP32 {sum, comp} pairs)
+    const double *edges;  // energy-bin edges or nullptr
+    int64_t nvox;
+    int32_t n_bins;
+    int32_t mesh;         // index into the device mesh table
+};
+
+// Header of a batched call: work items are chunks of `chunk` rays of one batch.
+struct BatchedHeader {
+    int64_t total_items;
+    int32_t n_batches;
+    int32_t chunk;
+};
+
+struct BatchedShape {
+    int block = 256;
+    int blocks_per_cu = 8;
+    int chunk = 1024;
+    int hash_in_lds = 1;
+    int aggregate = 0;
+    int use_graph = 1;
+    bool operator==(const BatchedShape &o) const
+    {
+        return block == o.block && blocks_per_cu == o.blocks_per_cu && chunk == o.chunk &&
+               hash_in_lds == o.hash_in_lds && aggregate == o.aggregate && use_graph == o.use_graph;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Host-side objects.
 // ---------------------------------------------------------------------------
@@ -125,7 +158,24 @@ struct TallyHost {
     int64_t nvox = 0;
     void *d_data = nullptr;
     double *d_edges = nullptr;
+    std::vector<double> edges;  // host copy (empty: one bin, all energies)
     size_t bytes = 0;
+};
+
+// Descriptor buffers of one batched call in flight (two of them alternate),
+// and the hipGraph that copies them to the device and runs the kernel.
+struct BatchedSlot {
+    unsigned char *h_buf = nullptr;  // pinned: header, then descriptors
+    unsigned char *d_buf = nullptr;  // device copy
+    size_t cap = 0;                  // bytes
+    hipEvent_t done = nullptr;       // recorded after the kernel that read d_buf
+    bool used = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BatchedShape graph_shape;        // shape and form the graph was captured with
+    int graph_prec = -1;
+    int graph_fp64 = -1;
+    size_t graph_bytes = 0;
 };
 
 // Pinned staging slot for host ray batches.
@@ -149,6 +199,14 @@ struct vrc_ctx {
     vrc::LaunchShape launch;
     vrc::StageSlot stage[2];
     int stage_next = 0;
+    // device copies of the meshes for the persistent kernel (kMaxMeshes each)
+    vrc::MeshP<float> *d_mesh32 = nullptr;
+    vrc::MeshP<double> *d_mesh64 = nullptr;
+    vrc::BatchedShape batched;
+    vrc::BatchedSlot bslot[2];
+    int bslot_next = 0;
+    hipStream_t capture_stream = nullptr;
+    std::string arch;
     std::atomic<int> sticky{0};
 };
 
@@ -170,6 +228,10 @@ hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision pre
 hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m,
                         const RaysP &rays, bool rays_fp64, const TraceP &tr, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// Persistent kernel over the descriptors at d_buf (header first).  rays_fp64
+// and prec are common to every batch of the call.
+hipError_t launch_batched(const vrc_ctx &ctx, const BatchedShape &shape, vrc_precision prec, bool rays_fp64,
+                          const unsigned char *d_buf, hipStream_t s);
 hipError_t launch_tally_to_f64(const TallyHost &t, double *out, hipStream_t s);
 hipError_t launch_tally_from_f64(const TallyHost &t, const double *in, hipStream_t s);
 

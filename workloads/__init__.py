@@ -28,6 +28,7 @@ from .gen import (  # noqa: F401
     config2_multimaterial,
     config3_precision,
     config4_batches,
+    config4_batches_device,
     config5_serving_geometry,
     rays_to_f32,
 )

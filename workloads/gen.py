@@ -383,3 +383,49 @@ def config5_serving_geometry(n: int = 200, h: float = 1.0, radius: float = 50.0,
     xs = make_xs([constant_sigma_table(0.1), constant_sigma_table(1.0)])
     return Workload("serving-200^3-sphere", mesh, xs, None, ebin_edges=log_bin_edges(n_bins),
                     extra={"p_abs": 0.3, "sigma": (0.1, 1.0), "radius": radius})
+
+
+# ----------------------------------------------------------------------------
+# device-side generation of the large batched workload (benchmark only)
+# ----------------------------------------------------------------------------
+
+def config4_batches_device(device, n_batches: int = 2000, seed: int = 404, dtype=None, **kw):
+    """The batched workload with its rays drawn on the GPU (torch generator seeded per batch).
+
+    Batch sizes, mesh assignment, meshes and tables come from
+    ``config4_batches(materialise=False)``; each batch's rays follow the same
+    recipe as ``rays_near_faces`` (half within one voxel of a random face,
+    half uniform in the box; isotropic directions; log-uniform energies;
+    lognormal(0, 0.5) weights).  Returns (workload, list of 8-tensor lists).
+    """
+    import torch
+
+    dtype = torch.float32 if dtype is None else dtype
+    wl = config4_batches(n_batches=n_batches, seed=seed, materialise=False, **kw)
+    out = []
+    for b in range(n_batches):
+        mesh = wl.extra["meshes"][wl.extra["mesh_of"][b]]
+        n = int(wl.extra["sizes"][b])
+        g = torch.Generator(device=device)
+        g.manual_seed(seed * 1000 + b)
+        lo = torch.tensor(mesh.lo, dtype=torch.float64, device=device)
+        span = torch.tensor(mesh.n * mesh.h, dtype=torch.float64, device=device)
+        hvox = torch.tensor(mesh.h, dtype=torch.float64, device=device)
+        o = lo + torch.rand((n, 3), generator=g, device=device, dtype=torch.float64) * span
+        near = torch.rand(n, generator=g, device=device, dtype=torch.float64) < 0.5
+        face = torch.randint(0, 6, (n,), generator=g, device=device)
+        d = torch.rand(n, generator=g, device=device, dtype=torch.float64)
+        for a in range(3):
+            lo_side = near & (face == 2 * a)
+            hi_side = near & (face == 2 * a + 1)
+            o[:, a] = torch.where(lo_side, lo[a] + d * hvox[a], o[:, a])
+            o[:, a] = torch.where(hi_side, lo[a] + span[a] - d * hvox[a], o[:, a])
+        mu = torch.rand(n, generator=g, device=device, dtype=torch.float64) * 2 - 1
+        phi = torch.rand(n, generator=g, device=device, dtype=torch.float64) * (2 * math.pi)
+        s = torch.sqrt(torch.clamp(1 - mu * mu, min=0))
+        e = torch.exp(math.log(E_MIN_MEV) + torch.rand(n, generator=g, device=device, dtype=torch.float64)
+                      * (math.log(E_MAX_MEV) - math.log(E_MIN_MEV)))
+        w = torch.exp(0.5 * torch.randn(n, generator=g, device=device, dtype=torch.float64))
+        cols = [o[:, 0], o[:, 1], o[:, 2], s * torch.cos(phi), s * torch.sin(phi), mu, e, w]
+        out.append([c.to(dtype).contiguous() for c in cols])
+    return wl, out
