@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched form (2000 uneven batches on 4 meshes) against one launch per batch")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--serving", type=int, default=1,
+                    help="also run the serving form fed by 8 walker threads (p50/p99 latency per offered load)")
+    ap.add_argument("--serving-seconds", type=float, default=2.0)
     ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -227,6 +230,70 @@ def bench_batched(steps: int) -> dict:
             "hbm_frac": (32 * R + SEG_BYTES * S) / (batched_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
+def bench_serving(seconds: float) -> dict:
+    """Serving form: 8 walker threads, one-group analog walk in the 200^3 sphere mesh, 10-bin FP64 tally.
+
+    For each offered load (Poisson, rays/s over all walkers) the walkers run
+    for `seconds`; reported: achieved offered rate, served segments/s (counted
+    on the device after each launch's completion event), p50/p99 latency from
+    submission to observed completion, requests per launch.  Then unpaced
+    walkers (8 rays per collision) push a fixed number of rays through the
+    serving loop and, for comparison, through one plain vrc_cast_rays per
+    walker buffer.
+    """
+    import paper_1706_07476_amd as vrc
+    import workloads as W
+
+    wl = W.config5_serving_geometry()
+    ctx = vrc.Context(0)
+    ctx.set_mesh(0, wl.mesh)
+    ctx.set_xs(wl.xs)
+    tally = ctx.create_tally(0, "p32_t64", wl.ebin_edges)
+    centre = wl.mesh.lo + 0.5 * wl.mesh.n * wl.mesh.h + 0.01
+    walk = dict(sigma=list(wl.extra["sigma"]), source=centre, n_threads=8, flush_rays=16384, flush_us=1000,
+                p_abs=wl.extra["p_abs"])
+    loads = []
+    for i, rate in enumerate((1e6, 2e6, 5e6, 1e7, 2e7)):
+        for n_per in ((1, 8) if rate == 1e7 else (1,)):
+            ctx.serve_start(count_segments=1)
+            rep = ctx.walkers_run(tally, rate_rays_per_s=rate, duration_s=seconds, rays_per_collision=n_per,
+                                  seed=100 + i, **walk)
+            st = ctx.serve_stats()
+            ctx.serve_stop()
+            loads.append({"offered_rays_per_s": rate, "rays_per_collision": n_per,
+                          "achieved_rays_per_s": rep["offered_rays_per_s"],
+                          "segments_per_s": st["segments_done"] / rep["wall_s"],
+                          "latency_p50_ms": st["latency_p50_us"] / 1e3, "latency_p99_ms": st["latency_p99_us"] / 1e3,
+                          "requests": st["requests_done"], "launches": st["launches"],
+                          "requests_per_launch": st["mean_requests_per_launch"],
+                          "admission_waits": rep["busy_retries"]})
+            log(f"bench: serving {rate:.0e} rays/s (N={n_per}): p50 {loads[-1]['latency_p50_ms']:.3f} ms, "
+                f"p99 {loads[-1]['latency_p99_ms']:.3f} ms, {loads[-1]['segments_per_s']:.3e} segments/s")
+    # saturation: unpaced walkers, same rays through the loop and through one plain cast per buffer
+    sat = {}
+    for mode in ("serving", "plain_per_buffer"):
+        if mode == "serving":
+            ctx.serve_start(count_segments=1)
+        rep = ctx.walkers_run(tally, rate_rays_per_s=0.0, duration_s=60.0, max_rays=40_000_000, rays_per_collision=8,
+                              seed=7, direct=0 if mode == "serving" else 1, **walk)
+        if mode == "serving":
+            st = ctx.serve_stats()
+            ctx.serve_stop()
+            sat[mode] = {"rays": rep["rays_submitted"], "wall_s": rep["wall_s"],
+                         "rays_per_s": rep["rays_submitted"] / rep["wall_s"],
+                         "segments_per_s": st["segments_done"] / rep["wall_s"],
+                         "latency_p50_ms": st["latency_p50_us"] / 1e3, "latency_p99_ms": st["latency_p99_us"] / 1e3,
+                         "requests_per_launch": st["mean_requests_per_launch"]}
+        else:
+            sat[mode] = {"rays": rep["rays_submitted"], "wall_s": rep["wall_s"],
+                         "rays_per_s": rep["rays_submitted"] / rep["wall_s"]}
+        log(f"bench: saturation {mode}: {sat[mode]['rays_per_s']:.3e} rays/s")
+    ctx.close()
+    return {"workload": "200^3 mesh of 1 cm, sphere r=50 cm Sigma=1.0 in Sigma=0.1, 10 log energy bins (FP64 tally, "
+                        "640 MB), 8 walker threads, one-group analog walk (p_abs 0.3), flush at 16384 rays or 1 ms",
+            "precision": "p32_t64", "loads": loads, "saturation": sat}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -292,6 +359,9 @@ def main():
         batched = bench_batched(args.batched_steps)
         log(f"bench: batched {batched['batched_segments_per_s']:.3e} vs plain {batched['plain_segments_per_s']:.3e} "
             "segments/s")
+    serving = None
+    if args.serving:
+        serving = bench_serving(args.serving_seconds)
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
@@ -329,6 +399,7 @@ def main():
         "cpu_baseline": cpu,
         "other_forms": others,
         "batched_form": batched,
+        "serving_form": serving,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)

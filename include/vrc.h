@@ -228,6 +228,129 @@ vrc_status vrc_autotune_batched(vrc_ctx *ctx, int n_batches, const vrc_batch *ba
 vrc_status vrc_autotune_cast(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch, int repeats,
                              vrc_launch *best, double *best_ms);
 
+/* ---- serving form: continuous batching of streamed ray batches ---------- */
+
+/* Settings of the serving loop (0 fields take the default in brackets).
+ * ring_bytes: device memory for admitted rays, the admission budget [256 MiB];
+ * staging_bytes: each of the two pinned host staging buffers [64 MiB];
+ * max_requests_per_launch [1024]; n_streams: compute streams launches
+ * rotate over, so consecutive launches overlap on the device [2];
+ * max_inflight: launches in flight at once [4]; linger_us: how long the
+ * dispatcher waits for more requests before sealing a launch [0];
+ * count_segments: also count each launch's segments on the device, after its
+ * completion event (for throughput reports; off the latency path) [0].     */
+typedef struct {
+    int64_t ring_bytes;
+    int64_t staging_bytes;
+    int32_t max_requests_per_launch;
+    int32_t n_streams;
+    int32_t max_inflight;
+    int32_t linger_us;
+    int32_t count_segments;
+    int32_t reserved;
+} vrc_serve_config;
+
+typedef struct {
+    int64_t requests_done;
+    int64_t rays_done;
+    int64_t segments_done;     /* 0 unless count_segments */
+    int64_t launches;
+    int64_t refused;           /* submissions that returned VRC_ERR_BUSY */
+    double latency_p50_us;     /* submit -> completion, over completed requests */
+    double latency_p99_us;
+    double latency_max_us;
+    double mean_requests_per_launch;
+    double busy_s;             /* from the first submission to the last completion */
+} vrc_serve_stats;
+
+/* Start the request loop of a context (Sec. 3: the CPU keeps walking while
+ * the GPU casts the buffers it shipped; here many CPU threads ship buffers
+ * and the loop batches whatever has arrived into each launch).  The loop
+ * owns a device ray ring, two pinned staging buffers and its threads until
+ * vrc_serve_stop.  Tallies used by requests must be FP64-tally forms
+ * (VRC_P64 or VRC_P32_T64, matching the ray type: FP32 rays for VRC_P32_T64,
+ * FP64 rays for VRC_P64) or the compensated form (FP32 rays).              */
+vrc_status vrc_serve_start(vrc_ctx *ctx, const vrc_serve_config *config);
+
+/* Submit a host ray batch for tally_id.  Admission is by memory: the rays
+ * must fit in the device ring and the filling staging buffer; if they do
+ * not, the call waits up to timeout_us (0: not at all, <0: forever) and then
+ * returns VRC_ERR_BUSY.  On success the rays have been copied (the caller may
+ * reuse its buffer) and *ticket identifies the request.  Thread-safe.      */
+vrc_status vrc_serve_submit(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch, int64_t timeout_us,
+                            uint64_t *ticket);
+
+/* Wait until request `ticket` has been cast (its tally updated);
+ * *latency_us (may be NULL) receives submit -> completion.  VRC_ERR_TIMEOUT
+ * after timeout_us (<0: forever).  Thread-safe.                             */
+vrc_status vrc_serve_wait(vrc_ctx *ctx, uint64_t ticket, int64_t timeout_us, double *latency_us);
+
+/* Wait until everything submitted so far has completed. */
+vrc_status vrc_serve_drain(vrc_ctx *ctx, int64_t timeout_us);
+
+vrc_status vrc_serve_stats_get(vrc_ctx *ctx, vrc_serve_stats *out);
+
+/* Drain, stop the threads and free the loop's buffers. */
+vrc_status vrc_serve_stop(vrc_ctx *ctx);
+
+/* ---- CPU walkers: the random walk that feeds the serving loop ----------- */
+
+/* One-group analog random walk in the mesh of a tally (Sec. 2: rays start at
+ * source and collision points): particles start at `source` with isotropic
+ * directions, fly exponentially distributed optical distances through the
+ * voxels (sigma[m] per material, one group), and at each collision are
+ * absorbed with probability p_abs or scatter isotropically; they leave at
+ * the mesh boundary.  At the source event and at every scatter each walker
+ * emits rays_per_collision rays (isotropic directions, weight
+ * 1/rays_per_collision, energy log-uniform in [e_min, e_max] MeV) and hands
+ * its buffer to vrc_serve_submit when it holds flush_rays rays or flush_us
+ * have passed (or to vrc_cast_rays if direct = 1; the serving loop need not
+ * run then).  Each of n_threads walkers emits at rate_rays_per_s /
+ * n_threads on average with exponential gaps (a Poisson process), sleeping
+ * when ahead of it.  The run ends after duration_s or after max_rays rays
+ * (if > 0); then vrc_walkers_run drains the loop.                          */
+typedef struct {
+    int32_t tally_id;
+    int32_t n_threads;
+    double rate_rays_per_s;
+    double duration_s;
+    int64_t max_rays;
+    int32_t rays_per_collision;
+    int32_t flush_rays;
+    int32_t flush_us;
+    int32_t n_sigma;
+    double sigma[64];          /* one-group total cross section per material (1/cm) */
+    double p_abs;
+    double source[3];
+    double e_min, e_max;
+    uint64_t seed;
+    int32_t fp64_rays;         /* 1: submit double rays, 0: float rays */
+    int32_t record;            /* 1: also keep every emitted ray for vrc_walkers_take */
+    int32_t direct;            /* 1: skip the serving loop: each buffer is one vrc_cast_rays
+                                  call (one launch per buffer, as the paper ships each full
+                                  buffer); for comparisons */
+    int32_t reserved;
+} vrc_walker_config;
+
+typedef struct {
+    int64_t histories;
+    int64_t collisions;
+    int64_t rays_emitted;
+    int64_t rays_submitted;
+    int64_t submits;
+    int64_t busy_retries;      /* submissions refused by admission, then retried */
+    double wall_s;
+    double offered_rays_per_s; /* rays_submitted / wall_s */
+} vrc_walker_report;
+
+vrc_status vrc_walkers_run(vrc_ctx *ctx, const vrc_walker_config *config, vrc_walker_report *report);
+
+/* Rays recorded by the last vrc_walkers_run with record = 1, in submission
+ * order per walker then by walker (double, SoA into the 8 host arrays of
+ * capacity cap); *n receives the count (VRC_ERR_CAPACITY if cap is short). */
+vrc_status vrc_walkers_take(vrc_ctx *ctx, double *ox, double *oy, double *oz, double *ux, double *uy, double *uz,
+                            double *e, double *w, int64_t cap, int64_t *n);
+
 /* ---- inspection hooks (not on the timed path) ------------------------- */
 
 /* Number of positive-length voxel segments of every ray of a batch on mesh

@@ -69,6 +69,40 @@ class vrc_batched_launch(ctypes.Structure):
                 ("hash_in_lds", ctypes.c_int32), ("aggregate", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
+class vrc_serve_config(ctypes.Structure):
+    _fields_ = [("ring_bytes", ctypes.c_int64), ("staging_bytes", ctypes.c_int64),
+                ("max_requests_per_launch", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("linger_us", ctypes.c_int32), ("count_segments", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class vrc_serve_stats(ctypes.Structure):
+    _fields_ = [("requests_done", ctypes.c_int64), ("rays_done", ctypes.c_int64), ("segments_done", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("refused", ctypes.c_int64), ("latency_p50_us", ctypes.c_double),
+                ("latency_p99_us", ctypes.c_double), ("latency_max_us", ctypes.c_double),
+                ("mean_requests_per_launch", ctypes.c_double), ("busy_s", ctypes.c_double)]
+
+
+class vrc_walker_config(ctypes.Structure):
+    _fields_ = [("tally_id", ctypes.c_int32), ("n_threads", ctypes.c_int32), ("rate_rays_per_s", ctypes.c_double),
+                ("duration_s", ctypes.c_double), ("max_rays", ctypes.c_int64), ("rays_per_collision", ctypes.c_int32),
+                ("flush_rays", ctypes.c_int32), ("flush_us", ctypes.c_int32), ("n_sigma", ctypes.c_int32),
+                ("sigma", ctypes.c_double * 64), ("p_abs", ctypes.c_double), ("source", ctypes.c_double * 3),
+                ("e_min", ctypes.c_double), ("e_max", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("fp64_rays", ctypes.c_int32), ("record", ctypes.c_int32), ("direct", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class vrc_walker_report(ctypes.Structure):
+    _fields_ = [("histories", ctypes.c_int64), ("collisions", ctypes.c_int64), ("rays_emitted", ctypes.c_int64),
+                ("rays_submitted", ctypes.c_int64), ("submits", ctypes.c_int64), ("busy_retries", ctypes.c_int64),
+                ("wall_s", ctypes.c_double), ("offered_rays_per_s", ctypes.c_double)]
+
+
+def _struct_dict(st) -> dict:
+    return {f: getattr(st, f) for f, _ in st._fields_ if f not in ("reserved",)}
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _I64 = ctypes.c_int64
@@ -97,6 +131,14 @@ _SIGNATURES = {
     "vrc_get_batched_launch": [_P, ctypes.POINTER(vrc_batched_launch)],
     "vrc_autotune_batched": [_P, _I, ctypes.POINTER(vrc_batch), _I, ctypes.POINTER(vrc_batched_launch), _PD],
     "vrc_autotune_cast": [_P, _I, ctypes.POINTER(vrc_ray_batch), _I, ctypes.POINTER(vrc_launch), _PD],
+    "vrc_serve_start": [_P, ctypes.POINTER(vrc_serve_config)],
+    "vrc_serve_submit": [_P, _I, ctypes.POINTER(vrc_ray_batch), _I64, ctypes.POINTER(ctypes.c_uint64)],
+    "vrc_serve_wait": [_P, ctypes.c_uint64, _I64, _PD],
+    "vrc_serve_drain": [_P, _I64],
+    "vrc_serve_stats_get": [_P, ctypes.POINTER(vrc_serve_stats)],
+    "vrc_serve_stop": [_P],
+    "vrc_walkers_run": [_P, ctypes.POINTER(vrc_walker_config), ctypes.POINTER(vrc_walker_report)],
+    "vrc_walkers_take": [_P] + [_PD] * 8 + [_I64, _PI64],
 }
 _STRING_FUNCS = {"vrc_last_error": [], "vrc_version": []}
 
@@ -372,6 +414,79 @@ def vrc_autotune_cast(ctx: int, tally_id: int, batch: vrc_ray_batch, repeats: in
             "aggregate": l.aggregate}, ms.value
 
 
+def vrc_serve_start(ctx: int, ring_bytes=0, staging_bytes=0, max_requests_per_launch=0, n_streams=0,
+                    max_inflight=0, linger_us=0, count_segments=0) -> None:
+    c = vrc_serve_config(ring_bytes, staging_bytes, max_requests_per_launch, n_streams, max_inflight, linger_us,
+                         count_segments, 0)
+    _check(load_library().vrc_serve_start(ctx, ctypes.byref(c)))
+
+
+def vrc_serve_submit(ctx: int, tally_id: int, batch: vrc_ray_batch, timeout_us: int = -1) -> int:
+    t = ctypes.c_uint64(0)
+    _check(load_library().vrc_serve_submit(ctx, tally_id, ctypes.byref(batch), int(timeout_us), ctypes.byref(t)))
+    return t.value
+
+
+def vrc_serve_wait(ctx: int, ticket: int, timeout_us: int = -1) -> float:
+    lat = ctypes.c_double(0.0)
+    _check(load_library().vrc_serve_wait(ctx, ticket, int(timeout_us), ctypes.byref(lat)))
+    return lat.value
+
+
+def vrc_serve_drain(ctx: int, timeout_us: int = -1) -> None:
+    _check(load_library().vrc_serve_drain(ctx, int(timeout_us)))
+
+
+def vrc_serve_stats_get(ctx: int) -> dict:
+    st = vrc_serve_stats()
+    _check(load_library().vrc_serve_stats_get(ctx, ctypes.byref(st)))
+    return _struct_dict(st)
+
+
+def vrc_serve_stop(ctx: int) -> None:
+    _check(load_library().vrc_serve_stop(ctx))
+
+
+def vrc_walkers_run(ctx: int, tally_id: int, sigma, source, n_threads=8, rate_rays_per_s=0.0, duration_s=1.0,
+                    max_rays=0, rays_per_collision=1, flush_rays=16384, flush_us=1000, p_abs=0.3,
+                    e_min=1e-11, e_max=20.0, seed=1, fp64_rays=0, record=0, direct=0) -> dict:
+    c = vrc_walker_config()
+    c.tally_id = tally_id
+    c.n_threads = n_threads
+    c.rate_rays_per_s = rate_rays_per_s
+    c.duration_s = duration_s
+    c.max_rays = max_rays
+    c.rays_per_collision = rays_per_collision
+    c.flush_rays = flush_rays
+    c.flush_us = flush_us
+    c.n_sigma = len(sigma)
+    for i, v in enumerate(sigma):
+        c.sigma[i] = float(v)
+    c.p_abs = p_abs
+    for i in range(3):
+        c.source[i] = float(source[i])
+    c.e_min, c.e_max = e_min, e_max
+    c.seed = seed
+    c.fp64_rays = fp64_rays
+    c.record = record
+    c.direct = direct
+    r = vrc_walker_report()
+    _check(load_library().vrc_walkers_run(ctx, ctypes.byref(c), ctypes.byref(r)))
+    return _struct_dict(r)
+
+
+def vrc_walkers_take(ctx: int):
+    """The rays recorded by the last walker run: 8 float64 arrays (ox, oy, oz, ux, uy, uz, e, w)."""
+    L = load_library()
+    n = ctypes.c_int64(0)
+    st = L.vrc_walkers_take(ctx, *([ctypes.cast(None, _PD)] * 8), 0, ctypes.byref(n))
+    if st not in (VRC_OK, VRC_ERR_CAPACITY):
+        _check(st)
+    arrs = [np.empty(n.value, np.float64) for _ in range(8)]
+    _check(L.vrc_walkers_take(ctx, *[a.ctypes.data_as(_PD) for a in arrs], n.value, ctypes.byref(n)))
+    return arrs
+
+
 # ----------------------------------------------------------------------------
 # convenience object
 # ----------------------------------------------------------------------------
@@ -457,3 +572,27 @@ class Context:
 
     def autotune_cast(self, tally_id: int, arrays, repeats: int = 2):
         return vrc_autotune_cast(self.handle, tally_id, make_batch(arrays), repeats)
+
+    def serve_start(self, **kw) -> None:
+        vrc_serve_start(self.handle, **kw)
+
+    def serve_submit(self, tally_id: int, arrays, timeout_us: int = -1) -> int:
+        return vrc_serve_submit(self.handle, tally_id, make_batch(arrays), timeout_us)
+
+    def serve_wait(self, ticket: int, timeout_us: int = -1) -> float:
+        return vrc_serve_wait(self.handle, ticket, timeout_us)
+
+    def serve_drain(self, timeout_us: int = -1) -> None:
+        vrc_serve_drain(self.handle, timeout_us)
+
+    def serve_stats(self) -> dict:
+        return vrc_serve_stats_get(self.handle)
+
+    def serve_stop(self) -> None:
+        vrc_serve_stop(self.handle)
+
+    def walkers_run(self, tally_id: int, sigma, source, **kw) -> dict:
+        return vrc_walkers_run(self.handle, tally_id, sigma, source, **kw)
+
+    def walkers_take(self):
+        return vrc_walkers_take(self.handle)

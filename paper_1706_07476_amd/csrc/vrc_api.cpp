@@ -27,14 +27,14 @@ vrc_status set_error(vrc_status st, const std::string &msg)
 
 using namespace vrc;
 
-namespace {
-
 // Device failure: remember it for the context and report it.
-vrc_status device_error(vrc_ctx *ctx, hipError_t e, const char *what)
+vrc_status vrc::device_error(vrc_ctx *ctx, hipError_t e, const char *what)
 {
     if (ctx) ctx->sticky.store(1);
     return set_error(VRC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+namespace {
 
 #define VRC_HIP(ctx, call)                                        \
     do {                                                          \
@@ -154,7 +154,9 @@ vrc_status mark_stage_used(vrc_ctx *ctx, int slot, hipStream_t s)
     return VRC_OK;
 }
 
-vrc_status check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
+}  // namespace
+
+vrc_status vrc::check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
 {
     if (!ctx->xs.set) return set_error(VRC_ERR_STATE, "no cross-section tables set");
     const MeshHost &m = ctx->meshes[t->mesh_id];
@@ -164,8 +166,6 @@ vrc_status check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
         return set_error(VRC_ERR_INVALID, "energy grid is not strictly increasing once rounded to FP32");
     return VRC_OK;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -220,6 +220,7 @@ vrc_status vrc_create(int device, vrc_ctx **out)
 vrc_status vrc_destroy(vrc_ctx *ctx)
 {
     if (!ctx) return VRC_OK;
+    if (ctx->serve) (void)vrc_serve_stop(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (auto &t : ctx->tallies) {
@@ -281,6 +282,7 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
     }
     m.nvox = nvox;
     m.max_mat = max_mat;
+    m.h_mat.assign(mat, mat + nvox);
     m.set = true;
     MeshP<float> m32;
     MeshP<double> m64;
@@ -673,6 +675,83 @@ vrc_status vrc_get_batched_launch(vrc_ctx *ctx, vrc_batched_launch *l)
     return VRC_OK;
 }
 
+// Copy a descriptor table through slot bs and run the persistent kernel on
+// stream s (replaying the slot's captured graph when shape.use_graph).
+// The slot's event marks when its buffers may be written again.
+}  // extern "C"
+
+vrc_status vrc::run_batched(vrc_ctx *ctx, BatchedSlot &bs, const BatchedShape &shape, vrc_precision pr, bool fp64,
+                            const std::vector<BatchDescDev> &desc, int64_t items, hipStream_t s)
+{
+    BatchedHeader hdr{items, static_cast<int32_t>(desc.size()), shape.chunk};
+    const size_t bytes = sizeof(BatchedHeader) + sizeof(BatchDescDev) * desc.size();
+    if (bs.used) VRC_HIP(ctx, hipEventSynchronize(bs.done));
+    if (bs.cap < bytes) {
+        if (bs.exec) (void)hipGraphExecDestroy(bs.exec);
+        if (bs.graph) (void)hipGraphDestroy(bs.graph);
+        bs.exec = nullptr;
+        bs.graph = nullptr;
+        if (bs.h_buf) (void)hipHostFree(bs.h_buf);
+        if (bs.d_buf) (void)hipFree(bs.d_buf);
+        bs.h_buf = nullptr;
+        bs.d_buf = nullptr;
+        bs.cap = 0;
+        size_t cap = 65536;
+        while (cap < bytes) cap *= 2;
+        if (hipHostMalloc(reinterpret_cast<void **>(&bs.h_buf), cap, hipHostMallocDefault) != hipSuccess) {
+            bs.h_buf = nullptr;
+            return set_error(VRC_ERR_NOMEM, "pinned descriptor buffer");
+        }
+        if (hipMalloc(reinterpret_cast<void **>(&bs.d_buf), cap) != hipSuccess) {
+            bs.d_buf = nullptr;
+            return set_error(VRC_ERR_NOMEM, "device descriptor buffer");
+        }
+        bs.cap = cap;
+    }
+    std::memcpy(bs.h_buf, &hdr, sizeof(hdr));
+    std::memcpy(bs.h_buf + sizeof(hdr), desc.data(), sizeof(BatchDescDev) * desc.size());
+    const int prec = static_cast<int>(pr);
+    const int f64 = fp64 ? 1 : 0;
+    if (shape.use_graph) {
+        const bool stale = !bs.exec || !(bs.graph_shape == shape) || bs.graph_prec != prec || bs.graph_fp64 != f64 ||
+                           bs.graph_bytes != bs.cap;
+        if (stale) {
+            if (bs.exec) (void)hipGraphExecDestroy(bs.exec);
+            if (bs.graph) (void)hipGraphDestroy(bs.graph);
+            bs.exec = nullptr;
+            bs.graph = nullptr;
+            // the graph: copy the whole descriptor buffer, then the persistent kernel
+            std::lock_guard<std::mutex> cl(ctx->capture_mu);
+            VRC_HIP(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed));
+            hipError_t e = hipMemcpyAsync(bs.d_buf, bs.h_buf, bs.cap, hipMemcpyHostToDevice, ctx->capture_stream);
+            if (e == hipSuccess) e = launch_batched(*ctx, shape, pr, fp64, bs.d_buf, ctx->capture_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &g);
+            if (e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return device_error(ctx, e, "capturing the batched graph");
+            }
+            if (e2 != hipSuccess) return device_error(ctx, e2, "hipStreamEndCapture");
+            bs.graph = g;
+            VRC_HIP(ctx, hipGraphInstantiate(&bs.exec, bs.graph, nullptr, nullptr, 0));
+            bs.graph_shape = shape;
+            bs.graph_prec = prec;
+            bs.graph_fp64 = f64;
+            bs.graph_bytes = bs.cap;
+        }
+        VRC_HIP(ctx, hipGraphLaunch(bs.exec, s));
+    } else {
+        VRC_HIP(ctx, hipMemcpyAsync(bs.d_buf, bs.h_buf, bytes, hipMemcpyHostToDevice, s));
+        hipError_t e = launch_batched(*ctx, shape, pr, fp64, bs.d_buf, s);
+        if (e != hipSuccess) return device_error(ctx, e, "batched kernel launch");
+    }
+    VRC_HIP(ctx, hipEventRecord(bs.done, s));
+    bs.used = true;
+    return VRC_OK;
+}
+
+extern "C" {
+
 vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batches, void *hip_stream)
 {
     if (vrc_status s = check_ctx(ctx)) return s;
@@ -714,71 +793,10 @@ vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batche
     if (desc.empty()) return VRC_OK;
     if (desc.size() > (size_t(1) << 30)) return set_error(VRC_ERR_INVALID, "too many batches");
     (void)hipSetDevice(ctx->device);
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    BatchedHeader hdr{items, static_cast<int32_t>(desc.size()), shape.chunk};
-    const size_t bytes = sizeof(BatchedHeader) + sizeof(BatchDescDev) * desc.size();
     BatchedSlot &bs = ctx->bslot[ctx->bslot_next];
     ctx->bslot_next ^= 1;
-    if (bs.used) VRC_HIP(ctx, hipEventSynchronize(bs.done));
-    if (bs.cap < bytes) {
-        if (bs.exec) (void)hipGraphExecDestroy(bs.exec);
-        if (bs.graph) (void)hipGraphDestroy(bs.graph);
-        bs.exec = nullptr;
-        bs.graph = nullptr;
-        if (bs.h_buf) (void)hipHostFree(bs.h_buf);
-        free_dev(bs.d_buf);
-        bs.h_buf = nullptr;
-        bs.cap = 0;
-        size_t cap = 65536;
-        while (cap < bytes) cap *= 2;
-        if (hipHostMalloc(reinterpret_cast<void **>(&bs.h_buf), cap, hipHostMallocDefault) != hipSuccess) {
-            bs.h_buf = nullptr;
-            return set_error(VRC_ERR_NOMEM, "pinned descriptor buffer");
-        }
-        if (hipMalloc(reinterpret_cast<void **>(&bs.d_buf), cap) != hipSuccess) {
-            bs.d_buf = nullptr;
-            return set_error(VRC_ERR_NOMEM, "device descriptor buffer");
-        }
-        bs.cap = cap;
-    }
-    std::memcpy(bs.h_buf, &hdr, sizeof(hdr));
-    std::memcpy(bs.h_buf + sizeof(hdr), desc.data(), sizeof(BatchDescDev) * desc.size());
-    const vrc_precision pr = static_cast<vrc_precision>(prec);
-    if (shape.use_graph) {
-        const bool stale = !bs.exec || !(bs.graph_shape == shape) || bs.graph_prec != prec || bs.graph_fp64 != fp64 ||
-                           bs.graph_bytes != bs.cap;
-        if (stale) {
-            if (bs.exec) (void)hipGraphExecDestroy(bs.exec);
-            if (bs.graph) (void)hipGraphDestroy(bs.graph);
-            bs.exec = nullptr;
-            bs.graph = nullptr;
-            // the graph: copy the whole descriptor buffer, then the persistent kernel
-            VRC_HIP(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed));
-            hipError_t e = hipMemcpyAsync(bs.d_buf, bs.h_buf, bs.cap, hipMemcpyHostToDevice, ctx->capture_stream);
-            if (e == hipSuccess) e = launch_batched(*ctx, shape, pr, fp64 != 0, bs.d_buf, ctx->capture_stream);
-            hipGraph_t g = nullptr;
-            hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &g);
-            if (e != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                return device_error(ctx, e, "capturing the batched graph");
-            }
-            if (e2 != hipSuccess) return device_error(ctx, e2, "hipStreamEndCapture");
-            bs.graph = g;
-            VRC_HIP(ctx, hipGraphInstantiate(&bs.exec, bs.graph, nullptr, nullptr, 0));
-            bs.graph_shape = shape;
-            bs.graph_prec = prec;
-            bs.graph_fp64 = fp64;
-            bs.graph_bytes = bs.cap;
-        }
-        VRC_HIP(ctx, hipGraphLaunch(bs.exec, s));
-    } else {
-        VRC_HIP(ctx, hipMemcpyAsync(bs.d_buf, bs.h_buf, bytes, hipMemcpyHostToDevice, s));
-        hipError_t e = launch_batched(*ctx, shape, pr, fp64 != 0, bs.d_buf, s);
-        if (e != hipSuccess) return device_error(ctx, e, "batched kernel launch");
-    }
-    VRC_HIP(ctx, hipEventRecord(bs.done, s));
-    bs.used = true;
-    return VRC_OK;
+    return run_batched(ctx, bs, shape, static_cast<vrc_precision>(prec), fp64 != 0, desc, items,
+                       static_cast<hipStream_t>(hip_stream));
 }
 
 }  // extern "C"

@@ -118,6 +118,7 @@ struct BatchedShape {
 
 struct MeshHost {
     bool set = false;
+    std::vector<uint8_t> h_mat;  // host copy (used by the CPU walkers)
     double lo[3] = {0, 0, 0};
     double h[3] = {1, 1, 1};
     int32_t n[3] = {0, 0, 0};
@@ -178,6 +179,8 @@ struct BatchedSlot {
     size_t graph_bytes = 0;
 };
 
+struct ServeState;
+
 // Pinned staging slot for host ray batches.
 struct StageSlot {
     void *h_buf = nullptr;
@@ -206,7 +209,10 @@ struct vrc_ctx {
     vrc::BatchedSlot bslot[2];
     int bslot_next = 0;
     hipStream_t capture_stream = nullptr;
+    std::mutex capture_mu;
     std::string arch;
+    vrc::ServeState *serve = nullptr;  // serving loop (vrc_serve.cpp), null when stopped
+    std::vector<double> walk_rec[8];  // rays recorded by the last walker run
     std::atomic<int> sticky{0};
 };
 
@@ -214,6 +220,12 @@ namespace vrc {
 
 // Errors ------------------------------------------------------------------
 vrc_status set_error(vrc_status st, const std::string &msg);
+vrc_status device_error(vrc_ctx *ctx, hipError_t e, const char *what);
+// Tables, mesh and material ids ready for casting into tally t.
+vrc_status check_cast_ready(vrc_ctx *ctx, const TallyHost *t);
+// Upload a descriptor table through slot bs and run the persistent kernel.
+vrc_status run_batched(vrc_ctx *ctx, BatchedSlot &bs, const BatchedShape &shape, vrc_precision prec, bool fp64,
+                       const std::vector<BatchDescDev> &desc, int64_t items, hipStream_t s);
 
 // Cross-section index (vrc_xs.cpp) -------------------------------------------
 // Builds the union grid, per-material values on it and the log2-energy hash.
@@ -228,6 +240,9 @@ hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision pre
 hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m,
                         const RaysP &rays, bool rays_fp64, const TraceP &tr, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// Adds the batch's total segment count to *total (device).
+hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
+                              bool rays_fp64, unsigned long long *total, hipStream_t s);
 // Persistent kernel over the descriptors at d_buf (header first).  rays_fp64
 // and prec are common to every batch of the call.
 hipError_t launch_batched(const vrc_ctx &ctx, const BatchedShape &shape, vrc_precision prec, bool rays_fp64,

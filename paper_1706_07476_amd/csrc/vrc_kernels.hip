@@ -94,6 +94,31 @@ __global__ void __launch_bounds__(256) count_kernel(MeshP<R> M, RaysP rays, int6
     }
 }
 
+// Total segments of a batch: per-lane counts, summed over the block in LDS,
+// one 64-bit atomic per block.
+template <typename R, typename RT>
+__global__ void __launch_bounds__(256) count_total_kernel(MeshP<R> M, RaysP rays, unsigned long long *total)
+{
+    __shared__ unsigned long long part[256];
+    const int64_t n = rays.n;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    unsigned long long mine = 0;
+    for (int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const R ox = ld<R, RT>(rays.ox, r), oy = ld<R, RT>(rays.oy, r), oz = ld<R, RT>(rays.oz, r);
+        const R ux = ld<R, RT>(rays.ux, r), uy = ld<R, RT>(rays.uy, r), uz = ld<R, RT>(rays.uz, r);
+        CountSeg c;
+        walk(M, ox, oy, oz, ux, uy, uz, c);
+        mine += static_cast<unsigned long long>(c.n);
+    }
+    part[threadIdx.x] = mine;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && part[0] != 0) atomicAdd(total, part[0]);
+}
+
 __global__ void fill_zero_kernel(uint32_t *p, size_t n_words)
 {
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
@@ -288,6 +313,24 @@ hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision pre
         MeshP<float> M = mesh_args<float>(m);
         if (rays_fp64) hipLaunchKernelGGL((count_kernel<float, double>), dim3(grid), dim3(block), 0, s, M, rays, counts);
         else hipLaunchKernelGGL((count_kernel<float, float>), dim3(grid), dim3(block), 0, s, M, rays, counts);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
+                              bool rays_fp64, unsigned long long *total, hipStream_t s)
+{
+    if (rays.n <= 0) return hipSuccess;
+    const int block = 256;
+    const int grid = grid_for(ctx, rays.n, block);
+    if (prec == VRC_P64) {
+        MeshP<double> M = mesh_args<double>(m);
+        if (rays_fp64) hipLaunchKernelGGL((count_total_kernel<double, double>), dim3(grid), dim3(block), 0, s, M, rays, total);
+        else hipLaunchKernelGGL((count_total_kernel<double, float>), dim3(grid), dim3(block), 0, s, M, rays, total);
+    } else {
+        MeshP<float> M = mesh_args<float>(m);
+        if (rays_fp64) hipLaunchKernelGGL((count_total_kernel<float, double>), dim3(grid), dim3(block), 0, s, M, rays, total);
+        else hipLaunchKernelGGL((count_total_kernel<float, float>), dim3(grid), dim3(block), 0, s, M, rays, total);
     }
     return hipGetLastError();
 }
