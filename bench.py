@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rays", type=int, default=1_000_000)
-    ap.add_argument("--precision", default="p32_t64", choices=["p64", "p32_t64", "p32_kahan"])
+    ap.add_argument("--precision", default="p32_t64", choices=["p64", "p32_t64", "p32_kahan", "p32_d64"])
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--hash-in-lds", type=int, default=None)
@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--serving-seconds", type=float, default=2.0)
     ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="only report each precision form's error against the FP64 oracle on the tiny, multimat "
+                         "and cylinder workloads (the oracle leg takes about a minute)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB --steps times (to scale HBM byte counters)")
     return ap.parse_args()
@@ -294,6 +297,87 @@ def bench_serving(seconds: float) -> dict:
             "precision": "p32_t64", "loads": loads, "saturation": sat}
 
 
+def precision_report() -> None:
+    """Per workload and form: relative error per voxel against the FP64 oracle (Eqs. 7-8).
+
+    FP32 forms are compared with the oracle run on the same FP32-rounded
+    inputs (their arithmetic error) and, separately, with the oracle on the
+    FP64 inputs (what a user of FP32 inputs sees).  Gate: voxels whose oracle
+    relative standard error is < 5% (the paper's gate); also the maximum over
+    every voxel with phi > 1e-30 max(phi), and Eq. 8's max |dphi|/sigma.
+    """
+    import torch
+    import oracle
+    import paper_1706_07476_amd as vrc
+    import workloads as W
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+
+    def f32_view(mesh, xs, rays):
+        m = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
+                   mesh.n, mesh.mat)
+        x = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
+                       xs.sigma.astype(np.float32).astype(np.float64))
+        return m, x, W.rays_to_f32(rays).as_f64()
+
+    def stats(got, res):
+        ref = res.tally.reshape(-1)
+        got = np.asarray(got).reshape(-1)
+        pos = ref > 1e-30 * ref.max()
+        rel = np.abs(got[pos] - ref[pos]) / ref[pos]
+        se = res.rel_std_err().reshape(-1)[pos]
+        gate = se < 0.05
+        R = float(res.n_rays)
+        mean = ref[pos] / R
+        var = np.maximum(res.sq.reshape(-1)[pos] / R - mean * mean, 0.0) * R / max(R - 1.0, 1.0)
+        sig = np.sqrt(var * R)
+        okv = (sig > 0) & (se < 0.3)
+        eps = np.abs(got[pos] - ref[pos])[okv] / sig[okv]
+        q = lambda a, f: float(np.quantile(a, f)) if a.size else None
+        return {"gated_voxels": int(gate.sum()), "max_rel_gated": q(rel[gate], 1.0),
+                "p99_rel_gated": q(rel[gate], 0.99), "median_rel_gated": q(rel[gate], 0.5),
+                "voxels": int(pos.sum()), "max_rel_all": q(rel, 1.0), "p99_rel_all": q(rel, 0.99),
+                "median_rel_all": q(rel, 0.5), "max_eps_phi": q(eps, 1.0)}
+
+    dev = torch.device("cuda:0")
+    cases = [("tiny", W.config1_tiny()), ("multimat", W.config2_multimaterial()),
+             ("cylinder", W.config3_precision())]
+    for name, wl in cases:
+        log(f"precision: {name}: oracle on FP64 inputs")
+        ref64 = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=threads)
+        log(f"precision: {name}: oracle on FP32-rounded inputs")
+        m32, x32, r32 = f32_view(wl.mesh, wl.xs, wl.rays)
+        ref32 = oracle.cast(m32, x32, r32, n_threads=threads)
+        ctx = vrc.Context(0)
+        ctx.set_mesh(0, wl.mesh)
+        ctx.set_xs(wl.xs)
+        for form in ("p64", "p32_t64", "p32_kahan", "p32_d64"):
+            dt = np.float64 if form == "p64" else np.float32
+            arrays = [torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev) for a in wl.rays.arrays()]
+            tid = ctx.create_tally(0, form)
+            ctx.cast(tid, arrays)
+            got = ctx.read(tid)
+            ctx.destroy_tally(tid)
+            del arrays
+            line = {"workload": name, "rays": wl.rays.n, "form": form}
+            if form == "p64":
+                line["vs_oracle"] = stats(got, ref64)
+            else:
+                line["vs_oracle_same_fp32_inputs"] = stats(got, ref32)
+                line["vs_oracle_fp64_inputs"] = stats(got, ref64)
+            print(json.dumps(line), flush=True)
+        # FP32 vs FP64 voxel sequences of the same (FP32) rays, on a sample
+        k = min(wl.rays.n, 20_000)
+        sample = W.rays_to_f32(wl.rays.take(slice(0, k)))
+        m32f = W.Mesh(wl.mesh.lo.astype(np.float32), wl.mesh.h.astype(np.float32), wl.mesh.n, wl.mesh.mat)
+        o32, v32, _ = oracle.trace_many(m32f, sample, "f32")
+        o64, v64, _ = oracle.trace_many(m32, sample.as_f64(), "f64")
+        differ = sum(1 for r in range(k) if not np.array_equal(v32[o32[r]:o32[r + 1]], v64[o64[r]:o64[r + 1]]))
+        print(json.dumps({"workload": name, "sequence_check_rays": k, "rays_whose_fp32_walk_differs_from_fp64": differ}),
+              flush=True)
+        ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -302,6 +386,9 @@ def main():
         sys.exit(2)
     if args.write_traffic:
         write_traffic(args.write_traffic)
+        return
+    if args.precision_report:
+        precision_report()
         return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, args.steps)
@@ -342,7 +429,7 @@ def main():
     traffic = measured_traffic(args.precision, launch)
     others = {}
     if args.other_forms:
-        for p in ("p64", "p32_t64", "p32_kahan"):
+        for p in ("p64", "p32_t64", "p32_kahan", "p32_d64"):
             if p == args.precision:
                 continue
             d2 = "f64" if p == "p64" else "f32"
@@ -387,6 +474,10 @@ def main():
             "segments_per_step": S,
             "precision": args.precision,
             "tally_dtype": "f64" if args.precision != "p32_kahan" else "f32+f32 compensated",
+            "forms": {"p64": "FP64 walk, optical depth, exponentials, tally",
+                      "p32_t64": "FP32 walk, optical depth, exponentials; FP64 tally",
+                      "p32_kahan": "FP32 throughout; compensated FP32 tally",
+                      "p32_d64": "FP32 cross sections and walk; FP64 optical depth, exponentials, tally"},
             "launch": launch,
         },
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),

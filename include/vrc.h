@@ -64,8 +64,11 @@ typedef enum {
 typedef enum {
     VRC_P64 = 0,        /* FP64 traversal, optical depth, exponentials, FP64 tally  */
     VRC_P32_T64 = 1,    /* FP32 traversal/optical depth/exponentials, FP64 tally    */
-    VRC_P32_KAHAN = 2   /* FP32 throughout, tally kept as an FP32 sum plus an FP32
+    VRC_P32_KAHAN = 2,  /* FP32 throughout, tally kept as an FP32 sum plus an FP32
                            compensation term (read back as their FP64 sum)          */
+    VRC_P32_D64 = 3     /* the paper's scheme (Sec. 3): FP32 cross sections and
+                           ray-cast distances, FP64 optical depth, exponentials,
+                           score and tally                                          */
 } vrc_precision;
 
 /* A batch of rays as a structure of arrays, n entries each.

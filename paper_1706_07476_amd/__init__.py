@@ -34,7 +34,8 @@ VRC_ERR_CAPACITY = -7
 VRC_P64 = 0
 VRC_P32_T64 = 1
 VRC_P32_KAHAN = 2
-PRECISIONS = {"p64": VRC_P64, "p32_t64": VRC_P32_T64, "p32_kahan": VRC_P32_KAHAN}
+VRC_P32_D64 = 3
+PRECISIONS = {"p64": VRC_P64, "p32_t64": VRC_P32_T64, "p32_kahan": VRC_P32_KAHAN, "p32_d64": VRC_P32_D64}
 
 _STATUS_NAMES = {
     VRC_ERR_INVALID: "VRC_ERR_INVALID", VRC_ERR_STATE: "VRC_ERR_STATE", VRC_ERR_NOMEM: "VRC_ERR_NOMEM",

@@ -350,7 +350,7 @@ vrc_status vrc_create_tally(vrc_ctx *ctx, int mesh_id, int n_ebins, const double
     if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
         return set_error(VRC_ERR_INVALID, "mesh_id does not name a set mesh");
     if (n_ebins < 1 || n_ebins > kMaxEbins) return set_error(VRC_ERR_INVALID, "n_ebins must be in 1..64");
-    if (precision != VRC_P64 && precision != VRC_P32_T64 && precision != VRC_P32_KAHAN)
+    if (precision != VRC_P64 && precision != VRC_P32_T64 && precision != VRC_P32_KAHAN && precision != VRC_P32_D64)
         return set_error(VRC_ERR_INVALID, "unknown precision");
     if (n_ebins > 1 && !edges) return set_error(VRC_ERR_INVALID, "edges are required for more than one bin");
     if (edges) {

@@ -41,17 +41,17 @@ __device__ __forceinline__ int find_batch(const BatchDescDev *d, int nb, int64_t
     return lo;
 }
 
-template <typename R, typename RT, bool KAHAN, bool AGG>
+template <typename R, typename RT, bool KAHAN, bool AGG, typename S>
 __global__ void __launch_bounds__(1024) batched_kernel(BatchedArgs<R> A)
 {
     __shared__ double agg_lds[AGG ? 1024 : 1];
     __shared__ int s_batch;
     double *wave_lds = agg_lds + (AGG ? (threadIdx.x & ~63u) : 0);
     const int32_t *hash;
-    R(*sig)[2];
+    S(*sig)[2];
     stage_lds(A.xs, A.hash_in_lds, hash, sig);
     const int bd = blockDim.x;
-    R(*mysig)[2] = sig + threadIdx.x;
+    S(*mysig)[2] = sig + threadIdx.x;
     const int64_t total = A.hdr->total_items;
     const int nb = A.hdr->n_batches;
     const int64_t chunk = A.hdr->chunk;
@@ -98,7 +98,7 @@ XsP<double> xs_of<double>(const XsHost &x)
 
 constexpr size_t kLdsLimitB = 65536;
 
-template <typename R, typename RT>
+template <typename R, typename RT, typename S = R>
 hipError_t launch_typed(const vrc_ctx &ctx, const BatchedShape &shape, bool kahan, const unsigned char *d_buf,
                         hipStream_t s)
 {
@@ -108,7 +108,7 @@ hipError_t launch_typed(const vrc_ctx &ctx, const BatchedShape &shape, bool kaha
     A.xs = xs_of<R>(ctx.xs);
     A.hdr = reinterpret_cast<const BatchedHeader *>(d_buf);
     A.desc = reinterpret_cast<const BatchDescDev *>(d_buf + sizeof(BatchedHeader));
-    const size_t per_lane = sizeof(R) * 2 * static_cast<size_t>(ctx.xs.n_mat);
+    const size_t per_lane = sizeof(S) * 2 * static_cast<size_t>(ctx.xs.n_mat);
     const size_t hb = sizeof(int32_t) * static_cast<size_t>(ctx.xs.M);
     int block = shape.block;
     bool hash = shape.hash_in_lds != 0;
@@ -119,11 +119,11 @@ hipError_t launch_typed(const vrc_ctx &ctx, const BatchedShape &shape, bool kaha
     A.hash_in_lds = hash ? 1 : 0;
     const int grid = ctx.n_cu * (shape.blocks_per_cu > 0 ? shape.blocks_per_cu : 1);
     if (kahan) {
-        hipLaunchKernelGGL((batched_kernel<R, RT, true, false>), dim3(grid), dim3(block), lds, s, A);
+        hipLaunchKernelGGL((batched_kernel<R, RT, true, false, R>), dim3(grid), dim3(block), lds, s, A);
     } else if (shape.aggregate) {
-        hipLaunchKernelGGL((batched_kernel<R, RT, false, true>), dim3(grid), dim3(block), lds, s, A);
+        hipLaunchKernelGGL((batched_kernel<R, RT, false, true, S>), dim3(grid), dim3(block), lds, s, A);
     } else {
-        hipLaunchKernelGGL((batched_kernel<R, RT, false, false>), dim3(grid), dim3(block), lds, s, A);
+        hipLaunchKernelGGL((batched_kernel<R, RT, false, false, S>), dim3(grid), dim3(block), lds, s, A);
     }
     return hipGetLastError();
 }
@@ -134,6 +134,9 @@ hipError_t launch_batched(const vrc_ctx &ctx, const BatchedShape &shape, vrc_pre
                           const unsigned char *d_buf, hipStream_t s)
 {
     const bool kahan = prec == VRC_P32_KAHAN;
+    if (prec == VRC_P32_D64)
+        return rays_fp64 ? launch_typed<float, double, double>(ctx, shape, false, d_buf, s)
+                         : launch_typed<float, float, double>(ctx, shape, false, d_buf, s);
     if (prec == VRC_P64)
         return rays_fp64 ? launch_typed<double, double>(ctx, shape, false, d_buf, s)
                          : launch_typed<double, float>(ctx, shape, false, d_buf, s);

@@ -216,11 +216,12 @@ __device__ __forceinline__ int energy_bin(const TallyP &T, double E)
 }
 
 // Sigma_m(E) of every material (Sec. 3: hashed energy lookup, linear
-// interpolation), written with 1/Sigma to the lane's LDS column:
+// interpolation) in the table precision R, written with 1/Sigma in the
+// scoring precision S to the lane's LDS column:
 // sig[m * stride + lane] = {Sigma, 1/Sigma (0 for Sigma = 0)}.
-template <typename R>
+template <typename R, typename S>
 __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, R E,
-                                          R (*sig)[2], int stride)
+                                          S (*sig)[2], int stride)
 {
     const int K = X.K;
     int k;
@@ -248,15 +249,15 @@ __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, 
         const R *s1 = s0 + X.s_stride;
         for (int m = 0; m < X.n_mat; ++m) {
             R slope = (s1[m] - s0[m]) / de;
-            R v = s0[m] + slope * dx;
+            const S v = static_cast<S>(s0[m] + slope * dx);
             sig[m * stride][0] = v;
-            sig[m * stride][1] = v > R(0) ? R(1) / v : R(0);
+            sig[m * stride][1] = v > S(0) ? S(1) / v : S(0);
         }
     } else {
         for (int m = 0; m < X.n_mat; ++m) {
-            R v = s0[m];
+            const S v = static_cast<S>(s0[m]);
             sig[m * stride][0] = v;
-            sig[m * stride][1] = v > R(0) ? R(1) / v : R(0);
+            sig[m * stride][1] = v > S(0) ? S(1) / v : S(0);
         }
     }
 }
@@ -283,8 +284,10 @@ struct Scorer {
     Put &put;
     __device__ __forceinline__ Scorer(const R (*sig_)[2], int stride_, R w, Put &put_)
         : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), since(0), put(put_) {}
-    __device__ __forceinline__ void operator()(int32_t vox, int m, R l)
+    template <typename L>
+    __device__ __forceinline__ void operator()(int32_t vox, int m, L len)
     {
+        const R l = static_cast<R>(len);
         const R s = sig[m * stride][0];
         const R is = sig[m * stride][1];
         const R x = s * l;
@@ -369,14 +372,14 @@ struct PutKahan {
     }
 };
 
-template <typename R>
 struct PutTrace {
     int64_t pos;
     int64_t *voxel;
     double *len;
     double *score;
     bool scored;
-    __device__ __forceinline__ void operator()(int32_t vox, R l, R f)
+    template <typename L, typename F>
+    __device__ __forceinline__ void operator()(int32_t vox, L l, F f)
     {
         voxel[pos] = vox;
         len[pos] = static_cast<double>(l);
@@ -394,14 +397,14 @@ struct CountSeg {
 
 // Stage the hash index of the energy grid into LDS (if asked) and hand out
 // the block's LDS columns for per-lane cross sections.  Dynamic LDS layout:
-// [sigma columns: n_mat * blockDim pairs of R][hash: M int32 if staged].
-template <typename R>
-__device__ __forceinline__ void stage_lds(const XsP<R> &X, int hash_in_lds, const int32_t *&hash, R (*&sig)[2])
+// [sigma columns: n_mat * blockDim pairs of S][hash: M int32 if staged].
+template <typename R, typename S>
+__device__ __forceinline__ void stage_lds(const XsP<R> &X, int hash_in_lds, const int32_t *&hash, S (*&sig)[2])
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int bd = blockDim.x;
-    sig = reinterpret_cast<R(*)[2]>(lds);
-    unsigned char *after = lds + sizeof(R) * 2 * static_cast<size_t>(X.n_mat) * bd;
+    sig = reinterpret_cast<S(*)[2]>(lds);
+    unsigned char *after = lds + sizeof(S) * 2 * static_cast<size_t>(X.n_mat) * bd;
     if (hash_in_lds) {
         int32_t *h = reinterpret_cast<int32_t *>(after);
         for (int j = threadIdx.x; j < X.M; j += bd) h[j] = X.hash[j];
@@ -412,13 +415,14 @@ __device__ __forceinline__ void stage_lds(const XsP<R> &X, int hash_in_lds, cons
     }
 }
 
-// Cross sections of the ray's energy, then the walk with the running score.
-template <typename R, class Put>
-__device__ __forceinline__ void cast_one(const MeshP<R> &M, const XsP<R> &X, const int32_t *hash, R (*mysig)[2],
+// Cross sections of the ray's energy, then the walk (in R) with the running
+// score (in S: R itself, or double over an FP32 walk).
+template <typename R, typename S, class Put>
+__device__ __forceinline__ void cast_one(const MeshP<R> &M, const XsP<R> &X, const int32_t *hash, S (*mysig)[2],
                                          int bd, R ox, R oy, R oz, R ux, R uy, R uz, R E, R w, Put &put)
 {
     xs_lookup(X, hash, E, mysig, bd);
-    Scorer<R, Put> sc(mysig, bd, w, put);
+    Scorer<S, Put> sc(mysig, bd, static_cast<S>(w), put);
     walk(M, ox, oy, oz, ux, uy, uz, sc);
 }
 

@@ -29,14 +29,14 @@ struct CastArgs {
     int hash_in_lds;
 };
 
-template <typename R, typename RT, class PutMaker>
+template <typename R, typename RT, typename S, class PutMaker>
 __device__ __forceinline__ void cast_block(const CastArgs<R> &A, PutMaker make_put)
 {
     const int32_t *hash;
-    R(*sig)[2];
+    S(*sig)[2];
     stage_lds(A.xs, A.hash_in_lds, hash, sig);
     const int bd = blockDim.x;
-    R(*mysig)[2] = sig + threadIdx.x;
+    S(*mysig)[2] = sig + threadIdx.x;
     const int64_t n = A.rays.n;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * bd;
     for (int64_t r = static_cast<int64_t>(blockIdx.x) * bd + threadIdx.x; r < n; r += stride) {
@@ -51,12 +51,13 @@ __device__ __forceinline__ void cast_block(const CastArgs<R> &A, PutMaker make_p
     }
 }
 
-template <typename R, typename RT, bool AGG>
+// S: scoring precision (R, or double over an FP32 walk: the paper's scheme).
+template <typename R, typename RT, bool AGG, typename S>
 __global__ void __launch_bounds__(1024) cast_f64_kernel(CastArgs<R> A)
 {
     __shared__ double agg_lds[AGG ? 1024 : 1];
     double *wave_lds = agg_lds + (AGG ? (threadIdx.x & ~63u) : 0);
-    cast_block<R, RT>(A, [&](int64_t, int bin) {
+    cast_block<R, RT, S>(A, [&](int64_t, int bin) {
         return Active<PutF64<AGG>>{PutF64<AGG>{static_cast<double *>(A.tally.data), bin * A.tally.nvox, wave_lds},
                                    bin >= 0};
     });
@@ -65,18 +66,18 @@ __global__ void __launch_bounds__(1024) cast_f64_kernel(CastArgs<R> A)
 template <typename RT>
 __global__ void __launch_bounds__(1024) cast_kahan_kernel(CastArgs<float> A)
 {
-    cast_block<float, RT>(A, [&](int64_t, int bin) {
+    cast_block<float, RT, float>(A, [&](int64_t, int bin) {
         return Active<PutKahan>{PutKahan{static_cast<float *>(A.tally.data), bin * A.tally.nvox}, bin >= 0};
     });
 }
 
 // Inspection: the same walk and score, written out as CSR.
-template <typename R, typename RT>
+template <typename R, typename RT, typename S>
 __global__ void __launch_bounds__(256) trace_kernel(CastArgs<R> A)
 {
-    cast_block<R, RT>(A, [&](int64_t r, int bin) {
-        return Active<PutTrace<R>>{PutTrace<R>{A.trace.offs[r], A.trace.voxel, A.trace.len, A.trace.score, bin >= 0},
-                                   true};
+    cast_block<R, RT, S>(A, [&](int64_t r, int bin) {
+        return Active<PutTrace>{PutTrace{A.trace.offs[r], A.trace.voxel, A.trace.len, A.trace.score, bin >= 0},
+                                true};
     });
 }
 
@@ -195,10 +196,10 @@ constexpr size_t kLdsLimit = 65536;  // dynamic LDS per block this library asks 
 // Block size and hash placement that fit the LDS budget: the per-lane cross
 // section columns (2 values per material) always live in LDS; the hash index
 // is staged too if it still fits, else read from global memory.
-template <typename R>
+template <typename S>
 bool pick_shape(const XsHost &x, int want_block, bool want_hash, int &block, bool &hash, size_t &lds)
 {
-    const size_t per_lane = sizeof(R) * 2 * static_cast<size_t>(x.n_mat);
+    const size_t per_lane = sizeof(S) * 2 * static_cast<size_t>(x.n_mat);
     const size_t hb = sizeof(int32_t) * static_cast<size_t>(x.M);
     block = want_block;
     hash = want_hash;
@@ -208,20 +209,20 @@ bool pick_shape(const XsHost &x, int want_block, bool want_hash, int &block, boo
     return lds <= kLdsLimit;
 }
 
-template <typename R, typename RT>
+template <typename R, typename RT, typename S = R>
 hipError_t cast_f64_launch(const vrc_ctx &ctx, CastArgs<R> A, hipStream_t s)
 {
     int block;
     bool hash;
     size_t lds;
-    if (!pick_shape<R>(ctx.xs, ctx.launch.block, ctx.launch.hash_in_lds != 0, block, hash, lds))
+    if (!pick_shape<S>(ctx.xs, ctx.launch.block, ctx.launch.hash_in_lds != 0, block, hash, lds))
         return hipErrorInvalidConfiguration;
     A.hash_in_lds = hash ? 1 : 0;
     const int grid = grid_for(ctx, A.rays.n, block);
     if (ctx.launch.aggregate)
-        hipLaunchKernelGGL((cast_f64_kernel<R, RT, true>), dim3(grid), dim3(block), lds, s, A);
+        hipLaunchKernelGGL((cast_f64_kernel<R, RT, true, S>), dim3(grid), dim3(block), lds, s, A);
     else
-        hipLaunchKernelGGL((cast_f64_kernel<R, RT, false>), dim3(grid), dim3(block), lds, s, A);
+        hipLaunchKernelGGL((cast_f64_kernel<R, RT, false, S>), dim3(grid), dim3(block), lds, s, A);
     return hipGetLastError();
 }
 
@@ -252,6 +253,11 @@ hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m
     case VRC_P32_T64: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
         return rays_fp64 ? cast_f64_launch<float, double>(ctx, A, s) : cast_f64_launch<float, float>(ctx, A, s);
+    }
+    case VRC_P32_D64: {
+        CastArgs<float> A = make_args<float>(ctx, t, m, rays);
+        return rays_fp64 ? cast_f64_launch<float, double, double>(ctx, A, s)
+                         : cast_f64_launch<float, float, double>(ctx, A, s);
     }
     case VRC_P32_KAHAN: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
@@ -285,16 +291,24 @@ hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &
         if (!pick_shape<double>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = static_cast<int>((rays.n + block - 1) / block);
-        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<double, double>), dim3(grid), dim3(block), lds, s, A);
-        else hipLaunchKernelGGL((trace_kernel<double, float>), dim3(grid), dim3(block), lds, s, A);
+        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<double, double, double>), dim3(grid), dim3(block), lds, s, A);
+        else hipLaunchKernelGGL((trace_kernel<double, float, double>), dim3(grid), dim3(block), lds, s, A);
+    } else if (t.prec == VRC_P32_D64) {
+        CastArgs<float> A = make_args<float>(ctx, t, m, rays);
+        A.trace = tr;
+        if (!pick_shape<double>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
+        A.hash_in_lds = hash ? 1 : 0;
+        const int grid = static_cast<int>((rays.n + block - 1) / block);
+        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, double>), dim3(grid), dim3(block), lds, s, A);
+        else hipLaunchKernelGGL((trace_kernel<float, float, double>), dim3(grid), dim3(block), lds, s, A);
     } else {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
         A.trace = tr;
         if (!pick_shape<float>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = static_cast<int>((rays.n + block - 1) / block);
-        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double>), dim3(grid), dim3(block), lds, s, A);
-        else hipLaunchKernelGGL((trace_kernel<float, float>), dim3(grid), dim3(block), lds, s, A);
+        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, float>), dim3(grid), dim3(block), lds, s, A);
+        else hipLaunchKernelGGL((trace_kernel<float, float, float>), dim3(grid), dim3(block), lds, s, A);
     }
     return hipGetLastError();
 }

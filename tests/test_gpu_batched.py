@@ -57,7 +57,7 @@ def setup_tallies(ctx, wl, prec):
     return meshes, tallies
 
 
-@pytest.mark.parametrize("prec", ["p64", "p32_t64", "p32_kahan"])
+@pytest.mark.parametrize("prec", ["p64", "p32_t64", "p32_kahan", "p32_d64"])
 def test_batched_equals_plain_casts(ctx, prec):
     wl = small_batched_workload()
     say(f"case: batched vs plain, {prec}, {len(wl.extra['batches'])} batches on 4 meshes")

@@ -74,7 +74,7 @@ def test_trace_bit_exact_fp64_tiny(ctx):
         np.testing.assert_allclose(sc[offs[r]:offs[r + 1]], s_ref, rtol=1e-13, atol=0)
 
 
-@pytest.mark.parametrize("prec", ["p64", "p32_t64", "p32_kahan"])
+@pytest.mark.parametrize("prec", ["p64", "p32_t64", "p32_kahan", "p32_d64"])
 def test_trace_bit_exact_multimaterial(ctx, prec):
     wl = W.config2_multimaterial(n_rays=4000)
     say(f"case: trace {prec}, multimat 100^3, 4000 rays")
@@ -206,7 +206,7 @@ def eps_phi_max(got, res, se_max=0.3):
     return float(eps[i])
 
 
-@pytest.mark.parametrize("prec", ["p32_t64", "p32_kahan"])
+@pytest.mark.parametrize("prec", ["p32_t64", "p32_kahan", "p32_d64"])
 def test_tally_multimaterial_fp32_well_sampled(ctx, prec):
     """FP32 forms on a well-sampled mesh (16^3 of the multimat tables, 1.6e6 rays).
 
@@ -401,7 +401,7 @@ def test_reset_load_read_roundtrip(ctx):
     wl = W.config2_multimaterial(n_rays=10_000, n=20, h=0.5)
     say("case: reset/load/read")
     setup(ctx, wl)
-    for prec, dt in (("p64", "f64"), ("p32_kahan", "f32"), ("p32_t64", "f32")):
+    for prec, dt in (("p64", "f64"), ("p32_kahan", "f32"), ("p32_t64", "f32"), ("p32_d64", "f32")):
         tid = ctx.create_tally(0, prec)
         arrays = dev_arrays(wl.rays, dt)
         ctx.cast(tid, arrays)
@@ -442,7 +442,7 @@ def test_errors_are_reported(ctx, vrc):
         vrc.vrc_set_launch(ctx.handle, block=100)
 
 
-@pytest.mark.parametrize("prec", ["p32_t64", "p64"])
+@pytest.mark.parametrize("prec", ["p32_t64", "p64", "p32_d64"])
 def test_full_size_bench_workload(ctx, prec):
     """The bench workload at full size (100^3, 1e6 rays) in the bench's default launch shape.
 
