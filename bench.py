@@ -5,12 +5,14 @@ multi-material workload (100^3 mesh of 0.5 cm voxels, 3 materials in
 10-voxel z slabs, 20k-point Sigma_t(E) tables, 1e6 rays with uniform
 origins, isotropic directions, log-uniform energies, lognormal weights),
 i.e. every step of the path: ray load, cross-section lookup, clip, voxel
-walk, attenuation, score and tally atomics.  Inputs are resident in HBM
+walk, attenuation, score and tally accumulation (the library's default
+tile-split accumulation: entries, scans, partition and tiles kernels; or
+one atomic per segment with --accumulate 0).  Inputs are resident in HBM
 before the timed region.
 
-Prints one JSON line: segments/s (the metric), roofline of the cast kernel
-against HBM bandwidth, p50/p99 per-batch latency, and the CPU oracle timed on
-a bounded sample of the same workload.
+Prints one JSON line: segments/s (the metric), the roofline of the cast
+(all of its kernels, per step) against HBM bandwidth, p50/p99 per-batch
+latency, and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -31,8 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # 8-byte read-modify-write of the tally element (FP64, or the FP32 sum+compensation pair)
 RAY_BYTES = {"f32": 32, "f64": 64}
 SEG_BYTES = 1 + 2 * 8
-KERNEL_SOURCES = ["paper_1706_07476_amd/csrc/vrc_kernels.hip", "paper_1706_07476_amd/csrc/vrc_internal.h",
-                  "paper_1706_07476_amd/csrc/vrc_math.h", "paper_1706_07476_amd/csrc/vrc_device.h"]
+KERNEL_SOURCES = ["paper_1706_07476_amd/csrc/vrc_kernels.hip", "paper_1706_07476_amd/csrc/vrc_sorted.hip",
+                  "paper_1706_07476_amd/csrc/vrc_internal.h", "paper_1706_07476_amd/csrc/vrc_math.h",
+                  "paper_1706_07476_amd/csrc/vrc_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cast_multimat_traffic.json")
 
 
@@ -67,6 +70,10 @@ def parse():
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--hash-in-lds", type=int, default=None)
     ap.add_argument("--aggregate", type=int, default=None)
+    ap.add_argument("--accumulate", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="0: per-segment atomics; 1: tile-split from 131072 rays (default); "
+                         "2, 3: tile-split always (atomic / plain flush)")
+    ap.add_argument("--accumulate-modes", type=int, default=1, help="also time the other accumulation modes")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the CPU oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--other-forms", type=int, default=1, help="also time the other precision forms")
@@ -86,28 +93,36 @@ def parse():
     return ap.parse_args()
 
 
-def _counter_mean(csv_path: str, kernel_prefix: str, counter: str) -> float:
+def _counter_mean(csv_path: str, kernel: str, counter: str) -> float:
+    """Mean of a counter over the dispatches of the kernels whose name contains ``kernel``."""
     import csv
     vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
-            if r["Kernel_Name"].startswith(kernel_prefix) and r["Counter_Name"] == counter]
+            if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter]
     if not vals:
-        raise SystemExit(f"no {counter} rows for {kernel_prefix} in {csv_path}")
+        raise SystemExit(f"no {counter} rows for {kernel} in {csv_path}")
     return sum(vals) / len(vals)
 
 
+# the kernels of one cast, each dispatched once per step of the bench workload
+PIPELINE = {0: ["cast_f64_kernel<float, float, false>"],
+            1: ["entries_kernel<float, float, float>", "scan_rows_kernel", "scan_keys_kernel",
+                "partition_kernel<vrc::(anonymous namespace)::Entry<float, float> >", "tile_kernel<float, float, true>"]}
+
+
 def write_traffic(paths, precision="p32_t64", copy_mib=1024) -> None:
-    """Scale FETCH_SIZE/WRITE_SIZE (KiB per dispatch) of the cast kernel by a plain copy of known size."""
+    """Scale FETCH_SIZE/WRITE_SIZE (KiB per dispatch) of the cast's kernels by a plain copy of known size."""
     cf, cw, pf, pw = paths
-    cast = "void vrc::(anonymous namespace)::cast_f64_kernel<float, float, false>"
-    fetch = _counter_mean(cf, cast, "FETCH_SIZE")
-    write = _counter_mean(cw, cast, "WRITE_SIZE")
+    acc = 1
+    launch = {"block": 256, "blocks_per_cu": 8, "hash_in_lds": 1, "aggregate": 0, "accumulate": acc}
+    fetch = sum(_counter_mean(cf, k, "FETCH_SIZE") for k in PIPELINE[acc])
+    write = sum(_counter_mean(cw, k, "WRITE_SIZE") for k in PIPELINE[acc])
     copy_f = _counter_mean(pf, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
     copy_w = _counter_mean(pw, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
     nbytes = copy_mib * (1 << 20)
     ff, fw = nbytes / (copy_f * 1024), nbytes / (copy_w * 1024)
-    t = {"kernel": cast, "workload": "multimat 100^3, 1e6 rays (bench.py default)", "precision": precision,
-         "launch": {"block": 256, "blocks_per_cu": 8, "hash_in_lds": 1, "aggregate": 0},
-         "kernel_hash": kernel_hash(), "fetch_size_kib_per_launch": fetch, "write_size_kib_per_launch": write,
+    t = {"kernels": PIPELINE[acc], "workload": "multimat 100^3, 1e6 rays (bench.py default)", "precision": precision,
+         "launch": launch, "kernel_hash": kernel_hash(), "fetch_size_kib_per_launch": fetch,
+         "write_size_kib_per_launch": write,
          "copy_calibration": {"bytes_read_and_written": nbytes, "fetch_size_kib": copy_f, "write_size_kib": copy_w,
                               "fetch_scale": ff, "write_scale": fw},
          "bytes_per_launch": fetch * 1024 * ff + write * 1024 * fw}
@@ -410,7 +425,8 @@ def main():
     ctx.set_mesh(0, wl.mesh)
     ctx.set_xs(wl.xs)
     shape = {k: v for k, v in (("block", args.block), ("blocks_per_cu", args.blocks_per_cu),
-                               ("hash_in_lds", args.hash_in_lds), ("aggregate", args.aggregate)) if v is not None}
+                               ("hash_in_lds", args.hash_in_lds), ("aggregate", args.aggregate),
+                               ("accumulate", args.accumulate)) if v is not None}
     if shape:
         ctx.set_launch(**shape)
     launch = ctx.get_launch()
@@ -427,6 +443,17 @@ def main():
     kern_s = float(np.mean(per)) / 1e3
     achieved = alg_bytes / kern_s / 1e9
     traffic = measured_traffic(args.precision, launch)
+    modes = {}
+    if args.accumulate_modes:
+        for acc in (0, 1, 3):
+            if acc == launch["accumulate"]:
+                continue
+            ctx.set_launch(accumulate=acc)
+            t3 = ctx.create_tally(0, args.precision)
+            per3, tot3, _ = time_casts(vrc, ctx, t3, arrays, max(5, args.steps // 5), 2, stream, torch)
+            modes[acc] = {"segments_per_s": S * len(per3) / (tot3 / 1e3), "ms_per_step": tot3 / len(per3)}
+            log(f"bench: accumulate={acc}: {modes[acc]['segments_per_s']:.3e} segments/s")
+        ctx.set_launch(**launch)
     others = {}
     if args.other_forms:
         for p in ("p64", "p32_t64", "p32_kahan", "p32_d64"):
@@ -486,8 +513,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel_ms": kern_s * 1e3},
+                     "kernel_ms": kern_s * 1e3,
+                     "kernels": PIPELINE[1 if launch["accumulate"] else 0]},
         "cpu_baseline": cpu,
+        "other_accumulation_modes": modes,
         "other_forms": others,
         "batched_form": batched,
         "serving_form": serving,

@@ -92,12 +92,30 @@ typedef struct {
  * rays, no grid stride); hash_in_lds: stage the energy hash index in LDS
  * (1) or read it from global memory (0); aggregate: combine the scores of
  * lanes of a wavefront that hit the same voxel before the atomic (1) or not
- * (0).  None of these change results beyond the order of summation.         */
+ * (0); accumulate (default 1): 0 = one global atomic per scored segment;
+ * 2 = tile-split accumulation: rays are split where they enter a tile of
+ * 16^3 voxels, the pieces are grouped by (tile, energy bin), scored into the
+ * tile in LDS and added to the tally with one atomic per voxel and launch;
+ * 1 = 2 for batches of at least 131072 rays, 0 for smaller ones (whose
+ * cast is dominated by the fixed cost of the tile-split launches);
+ * 3 = as 2 with a plain read-add-write of each voxel instead of the atomic,
+ * which requires that no other work writing the same tally (a cast on
+ * another stream, a batched or serving launch, load/reset) overlaps the
+ * cast: order such work with streams or events.  The tile-split modes apply
+ * to the FP64-tally forms when the tally has at most 4096 (tile, energy bin)
+ * pairs and the cross-section columns fit in LDS; otherwise the atomic path
+ * runs.  They use scratch device memory grown on demand (about n_rays *
+ * (tiles along x + y + z) * 48..96 bytes, at most about 4 GB per sub-launch),
+ * so the first cast of a larger batch allocates and is not capturable in a
+ * graph; tile-split casts of one context are serialised with each other.
+ * block and blocks_per_cu apply to the atomic path.  The scores are
+ * bit-identical in all modes: only the order of the tally additions differs. */
 typedef struct {
     int32_t block;
     int32_t blocks_per_cu;
     int32_t hash_in_lds;
     int32_t aggregate;
+    int32_t accumulate;
 } vrc_launch;
 
 /* ---- context --------------------------------------------------------- */

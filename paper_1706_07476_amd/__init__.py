@@ -57,7 +57,7 @@ class vrc_ray_batch(ctypes.Structure):
 
 class vrc_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("hash_in_lds", ctypes.c_int32),
-                ("aggregate", ctypes.c_int32)]
+                ("aggregate", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
 
 
 class vrc_batch(ctypes.Structure):
@@ -324,15 +324,16 @@ def vrc_reset_tally(ctx: int, tally_id: int) -> None:
     _check(load_library().vrc_reset_tally(ctx, tally_id))
 
 
-def vrc_set_launch(ctx: int, block=256, blocks_per_cu=8, hash_in_lds=1, aggregate=0) -> None:
-    _check(load_library().vrc_set_launch(ctx, ctypes.byref(vrc_launch(block, blocks_per_cu, hash_in_lds, aggregate))))
+def vrc_set_launch(ctx: int, block=256, blocks_per_cu=8, hash_in_lds=1, aggregate=0, accumulate=1) -> None:
+    l = vrc_launch(block, blocks_per_cu, hash_in_lds, aggregate, accumulate)
+    _check(load_library().vrc_set_launch(ctx, ctypes.byref(l)))
 
 
 def vrc_get_launch(ctx: int) -> dict:
     l = vrc_launch()
     _check(load_library().vrc_get_launch(ctx, ctypes.byref(l)))
     return {"block": l.block, "blocks_per_cu": l.blocks_per_cu, "hash_in_lds": l.hash_in_lds,
-            "aggregate": l.aggregate}
+            "aggregate": l.aggregate, "accumulate": l.accumulate}
 
 
 def vrc_count_segments(ctx: int, mesh_id: int, precision, batch: vrc_ray_batch, counts, stream=None,
@@ -412,7 +413,7 @@ def vrc_autotune_cast(ctx: int, tally_id: int, batch: vrc_ray_batch, repeats: in
     _check(load_library().vrc_autotune_cast(ctx, tally_id, ctypes.byref(batch), repeats, ctypes.byref(l),
                                             ctypes.byref(ms)))
     return {"block": l.block, "blocks_per_cu": l.blocks_per_cu, "hash_in_lds": l.hash_in_lds,
-            "aggregate": l.aggregate}, ms.value
+            "aggregate": l.aggregate, "accumulate": l.accumulate}, ms.value
 
 
 def vrc_serve_start(ctx: int, ring_bytes=0, staging_bytes=0, max_requests_per_launch=0, n_streams=0,

@@ -204,7 +204,8 @@ vrc_status vrc_create(int device, vrc_ctx **out)
             return set_error(VRC_ERR_DEVICE, "hipEventCreate failed");
         }
     }
-    e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    e = hipEventCreateWithFlags(&ctx->sort_scratch.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&ctx->d_mesh32, sizeof(MeshP<float>) * kMaxMeshes);
     if (e == hipSuccess) e = hipMalloc(&ctx->d_mesh64, sizeof(MeshP<double>) * kMaxMeshes);
     if (e == hipSuccess) e = hipMemset(ctx->d_mesh32, 0, sizeof(MeshP<float>) * kMaxMeshes);
@@ -245,6 +246,17 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
     }
     free_dev(ctx->d_mesh32);
     free_dev(ctx->d_mesh64);
+    {
+        SortScratch &sc = ctx->sort_scratch;
+        free_dev(sc.records);
+        free_dev(sc.sorted);
+        free_dev(sc.hist);
+        free_dev(sc.row_off);
+        free_dev(sc.counts);
+        free_dev(sc.key_tot);
+        free_dev(sc.key_base);
+        if (sc.done) (void)hipEventDestroy(sc.done);
+    }
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
     return VRC_OK;
@@ -440,7 +452,12 @@ vrc_status vrc_cast_rays(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch,
     RaysP rays;
     int slot = -1;
     if (vrc_status st = stage_rays(ctx, batch, s, rays, slot)) return st;
-    hipError_t e = launch_cast(*ctx, *t, ctx->meshes[t->mesh_id], rays, batch->fp64 != 0, s);
+    const MeshHost &mesh = ctx->meshes[t->mesh_id];
+    const int acc = ctx->launch.accumulate;
+    const bool split = acc != 0 && (acc != 1 || batch->n >= kSplitMinRays) && sorted_eligible(*ctx, *t, mesh);
+    hipError_t e = split ? launch_cast_sorted(*ctx, *t, mesh, rays, batch->fp64 != 0, acc != 3, s)
+                       : launch_cast(*ctx, *t, mesh, rays, batch->fp64 != 0, s);
+    if (e == hipErrorOutOfMemory) return set_error(VRC_ERR_NOMEM, "scratch of the sorted accumulation");
     if (e != hipSuccess) return device_error(ctx, e, "cast kernel launch");
     return mark_stage_used(ctx, slot, s);
 }
@@ -511,13 +528,15 @@ vrc_status vrc_set_launch(vrc_ctx *ctx, const vrc_launch *l)
     if (l->block < 64 || l->block > 1024 || l->block % 64 != 0)
         return set_error(VRC_ERR_INVALID, "block must be a multiple of 64 in 64..1024");
     if (l->blocks_per_cu < 0 || l->blocks_per_cu > 64) return set_error(VRC_ERR_INVALID, "blocks_per_cu in 0..64");
-    if ((l->hash_in_lds != 0 && l->hash_in_lds != 1) || (l->aggregate != 0 && l->aggregate != 1))
-        return set_error(VRC_ERR_INVALID, "hash_in_lds and aggregate are 0 or 1");
+    if ((l->hash_in_lds != 0 && l->hash_in_lds != 1) || (l->aggregate != 0 && l->aggregate != 1) ||
+        l->accumulate < 0 || l->accumulate > 3)
+        return set_error(VRC_ERR_INVALID, "hash_in_lds and aggregate are 0 or 1, accumulate 0..3");
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->launch.block = l->block;
     ctx->launch.blocks_per_cu = l->blocks_per_cu;
     ctx->launch.hash_in_lds = l->hash_in_lds;
     ctx->launch.aggregate = l->aggregate;
+    ctx->launch.accumulate = l->accumulate;
     return VRC_OK;
 }
 
@@ -529,6 +548,7 @@ vrc_status vrc_get_launch(vrc_ctx *ctx, vrc_launch *l)
     l->blocks_per_cu = ctx->launch.blocks_per_cu;
     l->hash_in_lds = ctx->launch.hash_in_lds;
     l->aggregate = ctx->launch.aggregate;
+    l->accumulate = ctx->launch.accumulate;
     return VRC_OK;
 }
 

@@ -28,7 +28,8 @@
 //   x = Sigma l,  F = W_in (1 - e^{-x}) / Sigma  (W_in l if Sigma = 0),
 //   W_out = W_in e^{-x},
 // with 1 - e^{-x} and e^{-x} from one evaluation (vrc_math.h), and W_in
-// re-anchored to w e^{-tau} (compensated tau) every few segments.
+// re-anchored to w e^{-tau} (compensated tau) every 16 segments and at every
+// entry into a new tile of 16^3 voxels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -121,63 +122,164 @@ __device__ __forceinline__ bool clip_axis(R lo, R h, int n, R o, R inv, bool par
     return true;
 }
 
-// Cast one ray through the mesh: seg(vox, mat, len) is called for every
-// positive-length piece, in order.  All traversal state lives in local
-// scalars (one set per axis), never in an array indexed by the axis, so it
-// stays in registers.  The material of the next voxel is loaded before the
-// current piece is handed on, so its latency overlaps the score and the
-// atomic.  Returns false if the ray misses the mesh.
-template <typename R, class Seg>
-__device__ __forceinline__ bool walk(const MeshP<R> &M, R ox, R oy, R oz, R ux, R uy, R uz, Seg &seg)
+// Tiles of 16^3 voxels: the score re-anchors the entering weight at every
+// tile entry (below), and the sorted accumulation splits rays there.
+constexpr int kTileBits = 4;
+constexpr int kTileEdge = 1 << kTileBits;
+
+// Tile coordinates packed for change detection: consecutive pieces of a ray
+// differ by at most one tile per axis, so the packed values of two tiles a
+// ray passes in turn always differ, whatever the mesh size (the fields may
+// wrap; only inequality is used).
+__device__ __forceinline__ uint32_t tile_tag(int ti, int tj, int tk)
 {
-    const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
-    const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
-    const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
-    const R ix = R(1) / ux, iy = R(1) / uy, iz = R(1) / uz;
-    const bool px = __builtin_isinf(ix), py = __builtin_isinf(iy), pz = __builtin_isinf(iz);
-    R t_enter = R(0);
-    R t_exit = Num<R>::inf();
-    if (!clip_axis(lox, hx, nx, ox, ix, px, t_enter, t_exit)) return false;
-    if (!clip_axis(loy, hy, ny, oy, iy, py, t_enter, t_exit)) return false;
-    if (!clip_axis(loz, hz, nz, oz, iz, pz, t_enter, t_exit)) return false;
-    if (!(t_enter < t_exit)) return false;
-    if (!(t_exit < Num<R>::inf())) return false;  // zero direction: not a ray
-    int kx, ky, kz, sx, sy, sz;
-    R tx, ty, tz;
-    start_axis(lox, hx, nx, ox, ux, ix, px, t_enter, kx, tx, sx);
-    start_axis(loy, hy, ny, oy, uy, iy, py, t_enter, ky, ty, sy);
-    start_axis(loz, hz, nz, oz, uz, iz, pz, t_enter, kz, tz, sz);
-    const int32_t dy = nx;
-    const int32_t dz = nx * ny;
-    int32_t vox = kx + nx * (ky + ny * kz);
-    R cur = t_enter;
-    int budget = nx + ny + nz + 3;  // planes crossed at most
-    int m = M.mat[vox];
-    while (true) {
+    return static_cast<uint32_t>(ti) + (static_cast<uint32_t>(tj) << 11) + (static_cast<uint32_t>(tk) << 22);
+}
+
+// The walk of one ray as explicit state, one piece per step(), so that a
+// lane can switch to its next ray (or ray piece) the moment the current one
+// ends instead of waiting for the longest ray of its wavefront.  All state is
+// in named scalars (one set per axis), never in an array indexed by the axis,
+// so it stays in registers.  The walk may be limited to an index range per
+// axis ([lo, lo + ex)): the whole mesh, or one tile.
+template <typename R>
+struct Walker {
+    R ox, oy, oz, ix, iy, iz;
+    int sx, sy, sz;  // step per axis: +1, -1, 0 (parallel)
+    int kx, ky, kz;  // current voxel
+    R tx, ty, tz;    // next crossing per axis
+    R cur, t_exit;   // entry parameter of the current voxel; mesh exit
+    int32_t vox;
+    int m;           // material of the current voxel
+    int budget;      // planes that may still be crossed
+    int lo_x, lo_y, lo_z, ex_x, ex_y, ex_z;
+
+    // Whole-mesh walk with the clip and start-voxel rules of the file
+    // header; false if the ray misses the mesh.
+    __device__ __forceinline__ bool start(const MeshP<R> &M, R ox_, R oy_, R oz_, R ux, R uy, R uz)
+    {
+        const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
+        const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
+        const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
+        ox = ox_;
+        oy = oy_;
+        oz = oz_;
+        ix = R(1) / ux;
+        iy = R(1) / uy;
+        iz = R(1) / uz;
+        const bool px = __builtin_isinf(ix), py = __builtin_isinf(iy), pz = __builtin_isinf(iz);
+        R t_enter = R(0);
+        t_exit = Num<R>::inf();
+        if (!clip_axis(lox, hx, nx, ox, ix, px, t_enter, t_exit)) return false;
+        if (!clip_axis(loy, hy, ny, oy, iy, py, t_enter, t_exit)) return false;
+        if (!clip_axis(loz, hz, nz, oz, iz, pz, t_enter, t_exit)) return false;
+        if (!(t_enter < t_exit)) return false;
+        if (!(t_exit < Num<R>::inf())) return false;  // zero direction: not a ray
+        start_axis(lox, hx, nx, ox, ux, ix, px, t_enter, kx, tx, sx);
+        start_axis(loy, hy, ny, oy, uy, iy, py, t_enter, ky, ty, sy);
+        start_axis(loz, hz, nz, oz, uz, iz, pz, t_enter, kz, tz, sz);
+        cur = t_enter;
+        budget = nx + ny + nz + 3;
+        lo_x = lo_y = lo_z = 0;
+        ex_x = nx;
+        ex_y = ny;
+        ex_z = nz;
+        vox = kx + nx * (ky + ny * kz);
+        m = M.mat[vox];
+        return true;
+    }
+
+    // Resume at voxel (kx, ky, kz), entered at ray parameter cur, limited to
+    // that voxel's tile.  The per-axis crossings are recomputed from the plane
+    // indices exactly as step() computes them, so the pieces are
+    // bit-identical to those of the uninterrupted walk.
+    __device__ __forceinline__ void resume_tile(const MeshP<R> &M, R ox_, R oy_, R oz_, R ux, R uy, R uz, int kx_,
+                                                int ky_, int kz_, R cur_)
+    {
+        const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
+        const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
+        const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
+        ox = ox_;
+        oy = oy_;
+        oz = oz_;
+        ix = R(1) / ux;
+        iy = R(1) / uy;
+        iz = R(1) / uz;
+        const bool px = __builtin_isinf(ix), py = __builtin_isinf(iy), pz = __builtin_isinf(iz);
+        R t_enter = R(0);
+        t_exit = Num<R>::inf();
+        clip_axis(lox, hx, nx, ox, ix, px, t_enter, t_exit);
+        clip_axis(loy, hy, ny, oy, iy, py, t_enter, t_exit);
+        clip_axis(loz, hz, nz, oz, iz, pz, t_enter, t_exit);
+        sx = px ? 0 : (ux > R(0) ? 1 : -1);
+        sy = py ? 0 : (uy > R(0) ? 1 : -1);
+        sz = pz ? 0 : (uz > R(0) ? 1 : -1);
+        kx = kx_;
+        ky = ky_;
+        kz = kz_;
+        tx = px ? Num<R>::inf() : (plane(lox, hx, kx + (sx > 0 ? 1 : 0)) - ox) * ix;
+        ty = py ? Num<R>::inf() : (plane(loy, hy, ky + (sy > 0 ? 1 : 0)) - oy) * iy;
+        tz = pz ? Num<R>::inf() : (plane(loz, hz, kz + (sz > 0 ? 1 : 0)) - oz) * iz;
+        cur = cur_;
+        budget = 3 * kTileEdge + 3;
+        lo_x = kx & ~(kTileEdge - 1);
+        lo_y = ky & ~(kTileEdge - 1);
+        lo_z = kz & ~(kTileEdge - 1);
+        ex_x = nx - lo_x < kTileEdge ? nx - lo_x : kTileEdge;
+        ex_y = ny - lo_y < kTileEdge ? ny - lo_y : kTileEdge;
+        ex_z = nz - lo_z < kTileEdge ? nz - lo_z : kTileEdge;
+        vox = kx + nx * (ky + ny * kz);
+        m = M.mat[vox];
+    }
+
+    // One piece: seg(vox, mat, len, i, j, k, t0) for a positive length
+    // ((i, j, k): the voxel's indices; t0: the ray parameter where the piece
+    // starts).  The material of the next voxel is loaded before the piece is
+    // handed on, so its latency overlaps the score.  False once the walk has
+    // ended (mesh exit, limit, or budget).
+    template <class Seg>
+    __device__ __forceinline__ bool step(const MeshP<R> &M, Seg &seg)
+    {
+        // work on local copies (no selects between members, which would force the state out of registers)
+        int kx = this->kx, ky = this->ky, kz = this->kz;
+        R tx = this->tx, ty = this->ty, tz = this->tz;
+        R cur = this->cur;
+        int32_t vox = this->vox;
+        int m = this->m;
+        const R ox = this->ox, oy = this->oy, oz = this->oz, ix = this->ix, iy = this->iy, iz = this->iz;
+        const int sx = this->sx, sy = this->sy, sz = this->sz;
+        const int lo_x = this->lo_x, lo_y = this->lo_y, lo_z = this->lo_z;
+        const int ex_x = this->ex_x, ex_y = this->ex_y, ex_z = this->ex_z;
+        const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
+        const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
+        const int nx = M.n[0], ny = M.n[1];
         const bool ax = (tx <= ty) && (tx <= tz);
         const bool ay = !ax && (ty <= tz);
         const bool az = !ax && !ay;
         const R ta = ax ? tx : (ay ? ty : tz);
         const bool last = !(ta < t_exit);
         const R l = (last ? t_exit : ta) - cur;
+        const R t0 = cur;
         const int32_t vcur = vox;
         const int mcur = m;
+        const int cx = kx, cy = ky, cz = kz;
         bool inside = true;
         if (!last) {
             // advance along the chosen axis and fetch the next voxel's material early
             const int s = ax ? sx : (ay ? sy : sz);
             const int ni = (ax ? kx : (ay ? ky : kz)) + s;
-            const int na = ax ? nx : (ay ? ny : nz);
-            inside = static_cast<unsigned>(ni) < static_cast<unsigned>(na);
+            const int lo = ax ? lo_x : (ay ? lo_y : lo_z);
+            const int ex = ax ? ex_x : (ay ? ex_y : ex_z);
+            inside = static_cast<unsigned>(ni - lo) < static_cast<unsigned>(ex);
             if (inside) {
-                const int32_t dv = ax ? 1 : (ay ? dy : dz);
+                const int32_t dv = ax ? 1 : (ay ? nx : nx * ny);
                 vox = vcur + (s > 0 ? dv : -dv);
                 m = M.mat[vox];
-                const R lo = ax ? lox : (ay ? loy : loz);
+                const R plo = ax ? lox : (ay ? loy : loz);
                 const R h = ax ? hx : (ay ? hy : hz);
                 const R oa = ax ? ox : (ay ? oy : oz);
                 const R inv = ax ? ix : (ay ? iy : iz);
-                const R tnew = (plane(lo, h, ni + (s > 0 ? 1 : 0)) - oa) * inv;
+                const R tnew = (plane(plo, h, ni + (s > 0 ? 1 : 0)) - oa) * inv;
                 kx = ax ? ni : kx;
                 ky = ay ? ni : ky;
                 kz = az ? ni : kz;
@@ -187,8 +289,27 @@ __device__ __forceinline__ bool walk(const MeshP<R> &M, R ox, R oy, R oz, R ux, 
             }
             cur = ta;
         }
-        if (l > R(0)) seg(vcur, mcur, l);
-        if (last || !inside || --budget <= 0) break;
+        this->kx = kx;
+        this->ky = ky;
+        this->kz = kz;
+        this->tx = tx;
+        this->ty = ty;
+        this->tz = tz;
+        this->cur = cur;
+        this->vox = vox;
+        this->m = m;
+        if (l > R(0)) seg(vcur, mcur, l, cx, cy, cz, t0);
+        return !(last || !inside || --budget <= 0);
+    }
+};
+
+// Cast one ray through the whole mesh; false if it misses.
+template <typename R, class Seg>
+__device__ __forceinline__ bool walk(const MeshP<R> &M, R ox, R oy, R oz, R ux, R uy, R uz, Seg &seg)
+{
+    Walker<R> w;
+    if (!w.start(M, ox, oy, oz, ux, uy, uz)) return false;
+    while (w.step(M, seg)) {
     }
     return true;
 }
@@ -266,11 +387,14 @@ __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, 
 // Segment consumers
 // ---------------------------------------------------------------------------
 
-// Running VRC score of one ray; calls put(voxel, length, score) per piece.
-// The weight entering the next voxel is carried as a running product of the
-// segments' e^{-x}; the optical depth tau is summed alongside with Knuth's
-// TwoSum (compensated), and every kReanchor segments the weight is recomputed
-// as w e^{-tau}, so its error stays at a few ulp however long the ray is.
+// Running VRC score of one ray; calls put(voxel, length, score, i, j, k)
+// per piece.  The weight entering the next voxel is carried as a running
+// product of the segments' e^{-x}; the optical depth tau is summed alongside
+// with Knuth's TwoSum (compensated), and the weight is recomputed as
+// w e^{-tau} every kReanchor segments and at every tile entry, so its error
+// stays at a few ulp however long the ray is.  Because the state at a tile
+// entry is just (tau_hi, tau_lo), a cast split at tile entries (the sorted
+// accumulation) scores bit-identically to an uninterrupted one.
 template <typename R, class Put>
 struct Scorer {
     static constexpr int kReanchor = 16;
@@ -280,13 +404,38 @@ struct Scorer {
     R w_in;
     R tau_hi;
     R tau_lo;
-    int since;
+    int since;      // pieces since the last re-anchor; -1 before the first piece
+    uint32_t tile;  // tile_tag of the current tile
     Put &put;
     __device__ __forceinline__ Scorer(const R (*sig_)[2], int stride_, R w, Put &put_)
-        : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), since(0), put(put_) {}
-    template <typename L>
-    __device__ __forceinline__ void operator()(int32_t vox, int m, L len)
+        : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), since(-1), tile(0), put(put_) {}
+    // Resume at the entry of the tile tagged tg with the optical depth
+    // accumulated before it; first: the tile holds the ray's first piece.
+    __device__ __forceinline__ void resume(R w, R th, R tl, uint32_t tg, bool first)
     {
+        w0 = w;
+        w_in = w;
+        tau_hi = th;
+        tau_lo = tl;
+        since = 0;
+        tile = tg;
+        if (!first) reanchor();
+    }
+    __device__ __forceinline__ void reanchor()
+    {
+        R G, unused;
+        attenuation(tau_hi, G, unused);
+        w_in = (w0 * G) * (R(1) - tau_lo);
+    }
+    template <typename L>
+    __device__ __forceinline__ void operator()(int32_t vox, int m, L len, int ci, int cj, int ck, L)
+    {
+        const uint32_t tg = tile_tag(ci >> kTileBits, cj >> kTileBits, ck >> kTileBits);
+        if (tg != tile || since < 0) {
+            if (since >= 0) reanchor();
+            since = 0;
+            tile = tg;
+        }
         const R l = static_cast<R>(len);
         const R s = sig[m * stride][0];
         const R is = sig[m * stride][1];
@@ -294,7 +443,7 @@ struct Scorer {
         R g, em;
         attenuation(x, g, em);
         const R f = s > R(0) ? (w_in * em) * is : w_in * l;
-        put(vox, l, f);
+        put(vox, l, f, ci, cj, ck);
         const R t = tau_hi + x;
         const R bv = t - tau_hi;
         const R err = (tau_hi - (t - bv)) + (x - bv);
@@ -302,9 +451,7 @@ struct Scorer {
         tau_lo += err;
         if (++since >= kReanchor) {
             since = 0;
-            R G, unused;
-            attenuation(tau_hi, G, unused);
-            w_in = (w0 * G) * (R(1) - tau_lo);
+            reanchor();
         } else {
             w_in = w_in * g;
         }
@@ -318,7 +465,7 @@ struct PutF64 {
     double *tally;
     int64_t base;
     double *wave_lds;  // 64 doubles per wave (AGG only)
-    __device__ __forceinline__ void operator()(int32_t vox, double, double f)
+    __device__ __forceinline__ void operator()(int32_t vox, double, double f, int, int, int)
     {
         const int64_t key = base + vox;
         if constexpr (AGG) {
@@ -359,7 +506,7 @@ struct PutF64 {
 struct PutKahan {
     float *pairs;
     int64_t base;
-    __device__ __forceinline__ void operator()(int32_t vox, float, float f)
+    __device__ __forceinline__ void operator()(int32_t vox, float, float f, int, int, int)
     {
         if (f == 0.f) return;
         float *p = pairs + 2 * (base + vox);
@@ -379,7 +526,7 @@ struct PutTrace {
     double *score;
     bool scored;
     template <typename L, typename F>
-    __device__ __forceinline__ void operator()(int32_t vox, L l, F f)
+    __device__ __forceinline__ void operator()(int32_t vox, L l, F f, int, int, int)
     {
         voxel[pos] = vox;
         len[pos] = static_cast<double>(l);
@@ -391,7 +538,7 @@ struct PutTrace {
 struct CountSeg {
     int64_t n = 0;
     template <typename R>
-    __device__ __forceinline__ void operator()(int32_t, int, R) { ++n; }
+    __device__ __forceinline__ void operator()(int32_t, int, R, int, int, int, R) { ++n; }
 };
 
 

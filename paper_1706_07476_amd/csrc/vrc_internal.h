@@ -77,6 +77,22 @@ struct LaunchShape {
     int blocks_per_cu = 8;
     int hash_in_lds = 1;
     int aggregate = 0;
+    // 0: atomics; 1: tile-split from kSplitMinRays rays; 2, 3: tile-split (atomic / plain flush)
+    int accumulate = 1;
+};
+// Smallest batch cast with the tile-split accumulation under accumulate = 1:
+// below it the fixed cost of its five launches outweighs the atomics saved.
+constexpr int64_t kSplitMinRays = int64_t(1) << 17;
+
+// Scratch of the tile-sorted accumulation (vrc_sorted.hip), grown on demand.
+struct SortScratch {
+    void *records = nullptr, *sorted = nullptr, *hist = nullptr, *row_off = nullptr;
+    void *counts = nullptr, *key_tot = nullptr, *key_base = nullptr;
+    size_t records_cap = 0, sorted_cap = 0, hist_cap = 0, row_off_cap = 0;
+    size_t counts_cap = 0, key_tot_cap = 0, key_base_cap = 0;
+    hipEvent_t done = nullptr;   // after the last kernel that used the scratch
+    hipStream_t stream = nullptr;
+    bool busy = false;
 };
 
 // One ray batch of a batched call, as the persistent kernel reads it.
@@ -200,6 +216,7 @@ struct vrc_ctx {
     vrc::XsHost xs;
     std::vector<std::unique_ptr<vrc::TallyHost>> tallies;
     vrc::LaunchShape launch;
+    vrc::SortScratch sort_scratch;
     vrc::StageSlot stage[2];
     int stage_next = 0;
     // device copies of the meshes for the persistent kernel (kMaxMeshes each)
@@ -240,6 +257,10 @@ hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision pre
 hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m,
                         const RaysP &rays, bool rays_fp64, const TraceP &tr, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// Tile-sorted accumulation (vrc_sorted.hip): usable for this tally and mesh?
+bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m);
+hipError_t launch_cast_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
+                              bool rays_fp64, bool atomic_flush, hipStream_t s);
 // Adds the batch's total segment count to *total (device).
 hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
                               bool rays_fp64, unsigned long long *total, hipStream_t s);

@@ -1,0 +1,752 @@
+// Tile-split accumulation of the plain cast: the same walk and score as the
+// atomic kernel, with the tally updated through LDS instead of one global
+// atomic per segment.
+//
+// Global floating-point atomics on this GPU are executed beyond the L2 at a
+// fixed device-wide rate (~2.4e10 per second, whatever the array size or
+// access pattern), which caps the per-segment-atomic kernel.  Here the mesh
+// is cut into tiles of 16^3 voxels and every ray is split where it enters a
+// tile; a key is (energy bin, tile).
+//
+//   1. entries: every block takes a contiguous run of rays, orders them by
+//      estimated length, and every lane walks its ray accumulating only the
+//      optical depth (no exponentials, no tally); at each tile entry it
+//      appends a record {ray, entry voxel, entry parameter, optical depth so
+//      far} to its block's region (wavefront-compacted, coalesced stores),
+//      counting records per key in LDS.  A ray crosses at most
+//      n_tx + n_ty + n_tz - 2 tiles, which sizes the regions exactly.
+//   2. scan_rows / scan_keys: exclusive scans give every (block, key) pair
+//      its place in key-major order.
+//   3. partition: every block scatters its records to their key's run.
+//   4. tiles: one block per key orders the key's records by estimated
+//      length, resumes each ray at its tile entry, scores the pieces inside
+//      the tile into an FP64 tile in LDS, and
+//      adds the tile to the tally (one atomic per non-zero voxel, or a plain
+//      read-add-write: no two blocks share a tally element).
+//
+// The score re-anchors its entering weight at every tile entry (vrc_device.h),
+// so resuming from (optical depth, entry voxel, entry parameter) reproduces
+// the uninterrupted cast's scores bit for bit: only the order of the tally
+// additions differs from the atomic kernel.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "vrc_device.h"
+
+namespace vrc {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kTileVoxels = kTileEdge * kTileEdge * kTileEdge;  // 4096
+constexpr int kLocalBits = 3 * kTileBits;                        // 12
+constexpr int kMaxKeys = 4096;
+constexpr uint32_t kFirst = 1u << 31;  // the record is the ray's first tile
+
+// One tile entry of one ray.  code: kFirst | key << 12 | voxel within tile.
+template <typename R, typename S>
+struct __align__(16) Entry {
+    R ox, oy, oz, ux, uy, uz, e, w;
+    R t0;              // ray parameter where the first piece in the tile starts
+    S tau_hi, tau_lo;  // compensated optical depth before the tile
+    uint32_t code;
+};
+
+struct SortGeom {
+    int32_t ntx, nty, n_tiles, n_keys;
+};
+
+__device__ __forceinline__ uint32_t local_index(int ci, int cj, int ck)
+{
+    return static_cast<uint32_t>((ci & (kTileEdge - 1)) | ((cj & (kTileEdge - 1)) << kTileBits) |
+                                 ((ck & (kTileEdge - 1)) << (2 * kTileBits)));
+}
+
+// ---------------------------------------------------------------------------
+// Scheduling by length.  The walks are bound by instruction issue, and a
+// wavefront runs as long as its longest ray: lanes that finish early idle.
+// Both passes therefore order their work items (rays, tile pieces) by an
+// estimate of the number of pieces, longest first, before walking them, so
+// that the lanes of one wavefront walk about equally long.  This changes only
+// which lane walks which item, never a result.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ int axis_index(R p, R lo, R inv_h, int n)
+{
+    const R g = (p - lo) * inv_h;
+    if (!(g >= R(0))) return 0;
+    return g < static_cast<R>(n) ? static_cast<int>(g) : n - 1;
+}
+
+__device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
+
+// Pieces of a whole-mesh walk, estimated from the voxels of the clipped
+// entry and exit points (0 if the ray misses the mesh).
+template <typename R>
+__device__ __forceinline__ int ray_pieces_estimate(const MeshP<R> &M, R ox, R oy, R oz, R ux, R uy, R uz)
+{
+    const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
+    const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
+    const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
+    const R ix = R(1) / ux, iy = R(1) / uy, iz = R(1) / uz;
+    const bool px = __builtin_isinf(ix), py = __builtin_isinf(iy), pz = __builtin_isinf(iz);
+    R t0 = R(0), t1 = Num<R>::inf();
+    if (!clip_axis(lox, hx, nx, ox, ix, px, t0, t1) || !clip_axis(loy, hy, ny, oy, iy, py, t0, t1) ||
+        !clip_axis(loz, hz, nz, oz, iz, pz, t0, t1) || !(t0 < t1) || !(t1 < Num<R>::inf()))
+        return 0;
+    const R gx = R(1) / hx, gy = R(1) / hy, gz = R(1) / hz;
+    return iabs(axis_index(ox + t1 * ux, lox, gx, nx) - axis_index(ox + t0 * ux, lox, gx, nx)) +
+           iabs(axis_index(oy + t1 * uy, loy, gy, ny) - axis_index(oy + t0 * uy, loy, gy, ny)) +
+           iabs(axis_index(oz + t1 * uz, loz, gz, nz) - axis_index(oz + t0 * uz, loz, gz, nz)) + 1;
+}
+
+// Exit parameter of one axis' slab [lo + a h, lo + b h) for a ray leaving
+// through the face it moves towards (infinity if it runs parallel).
+template <typename R>
+__device__ __forceinline__ R slab_exit(R lo, R h, int a, int b, R o, R u)
+{
+    if (u == R(0)) return Num<R>::inf();
+    return (plane(lo, h, u > R(0) ? b : a) - o) / u;
+}
+
+// Pieces of a walk resumed at voxel (ci, cj, ck) up to the exit of its tile.
+template <typename R>
+__device__ __forceinline__ int tile_pieces_estimate(const MeshP<R> &M, R ox, R oy, R oz, R ux, R uy, R uz, int ci,
+                                                    int cj, int ck)
+{
+    const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
+    const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
+    const int ax = ci & ~(kTileEdge - 1), ay = cj & ~(kTileEdge - 1), az = ck & ~(kTileEdge - 1);
+    const int bx = ax + kTileEdge < M.n[0] ? ax + kTileEdge : M.n[0];
+    const int by = ay + kTileEdge < M.n[1] ? ay + kTileEdge : M.n[1];
+    const int bz = az + kTileEdge < M.n[2] ? az + kTileEdge : M.n[2];
+    R t = slab_exit(lox, hx, ax, bx, ox, ux);
+    const R ty = slab_exit(loy, hy, ay, by, oy, uy);
+    const R tz = slab_exit(loz, hz, az, bz, oz, uz);
+    t = ty < t ? ty : t;
+    t = tz < t ? tz : t;
+    if (!(t < Num<R>::inf())) return 1;
+    const int ex = axis_index(ox + t * ux, lox, R(1) / hx, M.n[0]);
+    const int ey = axis_index(oy + t * uy, loy, R(1) / hy, M.n[1]);
+    const int ez = axis_index(oz + t * uz, loz, R(1) / hz, M.n[2]);
+    const int cx = ex < ax ? ax : (ex >= bx ? bx - 1 : ex);
+    const int cy = ey < ay ? ay : (ey >= by ? by - 1 : ey);
+    const int cz = ez < az ? az : (ez >= bz ? bz - 1 : ez);
+    return iabs(cx - ci) + iabs(cy - cj) + iabs(cz - ck) + 1;
+}
+
+// Exclusive scan of s_cnt[0..nb) in place (nb <= 256), by the first wavefront.
+__device__ __forceinline__ void scan_counts(uint32_t *s_cnt, int nb)
+{
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    const int per = (nb + 63) / 64;
+    const int k0 = lane * per;
+    uint32_t loc = 0;
+    for (int q = 0; q < per; ++q)
+        if (k0 + q < nb) loc += s_cnt[k0 + q];
+    uint32_t inc = loc;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d);
+        if (lane >= d) inc += y;
+    }
+    uint32_t run = inc - loc;
+    for (int q = 0; q < per; ++q) {
+        if (k0 + q < nb) {
+            const uint32_t c = s_cnt[k0 + q];
+            s_cnt[k0 + q] = run;
+            run += c;
+        }
+    }
+}
+
+// Counting sort of m <= PER * blockDim.x items, item j * blockDim.x + tid
+// held by thread tid with bucket[j] in [0, nb): s_perm lists the items by
+// bucket, largest first.  Ends with a barrier.
+template <int PER>
+__device__ __forceinline__ void sort_desc(const int (&bucket)[PER], int m, int nb, uint32_t *s_cnt, uint16_t *s_perm)
+{
+    const int bd = blockDim.x, t = threadIdx.x;
+    for (int k = t; k < nb; k += bd) s_cnt[k] = 0u;
+    __syncthreads();
+    uint32_t rank[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        rank[j] = 0u;
+        if (j * bd + t < m) rank[j] = atomicAdd(&s_cnt[nb - 1 - bucket[j]], 1u);
+    }
+    __syncthreads();
+    scan_counts(s_cnt, nb);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int idx = j * bd + t;
+        if (idx < m) s_perm[s_cnt[nb - 1 - bucket[j]] + rank[j]] = static_cast<uint16_t>(idx);
+    }
+    __syncthreads();
+}
+
+constexpr int kBucketsE = 256;  // entries: estimated pieces (scaled to fit)
+constexpr int kBucketsT = 64;   // tiles: pieces inside one tile, at most 3 * 16 - 2
+constexpr int kMaxBlock = 1024;
+
+template <typename R>
+struct EntryArgs {
+    MeshP<R> mesh;
+    XsP<R> xs;
+    RaysP rays;
+    TallyP tally;
+    int hash_in_lds;
+    SortGeom g;
+    void *records;     // G regions of cap records
+    int64_t cap;       // records per block region
+    uint32_t *counts;  // G
+    uint32_t *hist;    // G * n_keys
+    int64_t rays_per_block;
+    int bucket_shift;  // estimated pieces >> bucket_shift < kBucketsE
+};
+
+// Walk sink of the entries pass: the optical depth as the score sums it
+// (same products, same TwoSum), and a record at every tile entry.
+template <typename R, typename S>
+struct EmitEntries {
+    const S (*sig)[2];
+    int stride;
+    S tau_hi, tau_lo;
+    uint32_t tile;  // tile_tag of the current tile
+    bool started;   // a piece has been seen
+    R ox, oy, oz, ux, uy, uz, e, w;
+    int key0;  // bin * n_tiles
+    SortGeom g;
+    Entry<R, S> *region;
+    int64_t cap;
+    uint32_t *cursor;  // LDS
+    uint32_t *hist;    // LDS
+    __device__ __forceinline__ void emit(bool first, int ci, int cj, int ck, R t0)
+    {
+        const uint64_t mask = __ballot(1);
+        const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+        const uint32_t cnt = static_cast<uint32_t>(__popcll(mask));
+        const uint32_t prefix = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+        uint32_t start = 0;
+        if (static_cast<int>(__lane_id()) == leader) start = atomicAdd(cursor, cnt);
+        start = __builtin_amdgcn_readfirstlane(start);  // the leader is the first active lane
+        const int64_t pos = static_cast<int64_t>(start) + prefix;
+        const int tl = (ci >> kTileBits) + g.ntx * ((cj >> kTileBits) + g.nty * (ck >> kTileBits));
+        const uint32_t key = static_cast<uint32_t>(key0 + tl);
+        // regions are sized for the most tiles a ray can cross; the guard only keeps stores in bounds
+        if (pos < cap) {
+            Entry<R, S> r;
+            r.ox = ox;
+            r.oy = oy;
+            r.oz = oz;
+            r.ux = ux;
+            r.uy = uy;
+            r.uz = uz;
+            r.e = e;
+            r.w = w;
+            r.t0 = t0;
+            r.tau_hi = tau_hi;
+            r.tau_lo = tau_lo;
+            r.code = (first ? kFirst : 0u) | (key << kLocalBits) | local_index(ci, cj, ck);
+            region[pos] = r;
+            atomicAdd(hist + key, 1u);
+        }
+    }
+    __device__ __forceinline__ void reset(R ox_, R oy_, R oz_, R ux_, R uy_, R uz_, R e_, R w_, int key0_)
+    {
+        tau_hi = S(0);
+        tau_lo = S(0);
+        started = false;
+        ox = ox_;
+        oy = oy_;
+        oz = oz_;
+        ux = ux_;
+        uy = uy_;
+        uz = uz_;
+        e = e_;
+        w = w_;
+        key0 = key0_;
+    }
+    __device__ __forceinline__ void operator()(int32_t, int m, R len, int ci, int cj, int ck, R t0)
+    {
+        const uint32_t tg = tile_tag(ci >> kTileBits, cj >> kTileBits, ck >> kTileBits);
+        if (tg != tile || !started) {
+            const bool first = !started;
+            started = true;
+            tile = tg;
+            emit(first, ci, cj, ck, t0);
+        }
+        const S l = static_cast<S>(len);
+        const S x = sig[m * stride][0] * l;
+        const S t = tau_hi + x;
+        const S bv = t - tau_hi;
+        const S err = (tau_hi - (t - bv)) + (x - bv);
+        tau_hi = t;
+        tau_lo += err;
+    }
+};
+
+// (FP32 walks: register budget for six wavefronts per SIMD, all that LDS allows)
+template <typename R, typename RT, typename S>
+__global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
+    entries_kernel(EntryArgs<R> A)
+{
+    __shared__ uint32_t s_hist[kMaxKeys];
+    __shared__ uint32_t s_cursor;
+    __shared__ uint32_t s_cnt[kBucketsE];
+    __shared__ uint16_t s_perm[256];
+    constexpr int PER = 1;  // the rays of one block-sized chunk are ordered together
+    for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_hist[k] = 0u;
+    if (threadIdx.x == 0) s_cursor = 0u;
+    __syncthreads();
+    const int32_t *hash;
+    S(*sig)[2];
+    stage_lds(A.xs, A.hash_in_lds, hash, sig);
+    const int bd = blockDim.x;
+    S(*mysig)[2] = sig + threadIdx.x;
+    Entry<R, S> *region = static_cast<Entry<R, S> *>(A.records) + static_cast<int64_t>(blockIdx.x) * A.cap;
+    const int64_t n = A.rays.n;
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * A.rays_per_block;
+    const int64_t last = first + A.rays_per_block < n ? first + A.rays_per_block : n;
+    EmitEntries<R, S> em{mysig, bd, S(0), S(0), 0u, false, R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0),
+                         0, A.g, region, A.cap, &s_cursor, s_hist};
+    Walker<R> wk;
+    for (int64_t c0 = first; c0 < last; c0 += bd) {
+        const int m = static_cast<int>(last - c0 < bd ? last - c0 : bd);
+        int bucket[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            bucket[j] = 0;
+            const int idx = j * bd + static_cast<int>(threadIdx.x);
+            if (idx < m) {
+                const int64_t r = c0 + idx;
+                const int est = ray_pieces_estimate(A.mesh, ld<R, RT>(A.rays.ox, r), ld<R, RT>(A.rays.oy, r),
+                                                    ld<R, RT>(A.rays.oz, r), ld<R, RT>(A.rays.ux, r),
+                                                    ld<R, RT>(A.rays.uy, r), ld<R, RT>(A.rays.uz, r));
+                const int bk = est >> A.bucket_shift;
+                bucket[j] = bk < kBucketsE ? bk : kBucketsE - 1;
+            }
+        }
+        sort_desc(bucket, m, kBucketsE, s_cnt, s_perm);
+        for (int j = threadIdx.x; j < m; j += bd) {
+            const int64_t r = c0 + s_perm[j];
+            const R ox = ld<R, RT>(A.rays.ox, r), oy = ld<R, RT>(A.rays.oy, r), oz = ld<R, RT>(A.rays.oz, r);
+            const R ux = ld<R, RT>(A.rays.ux, r), uy = ld<R, RT>(A.rays.uy, r), uz = ld<R, RT>(A.rays.uz, r);
+            const R E = ld<R, RT>(A.rays.e, r);
+            const R wt = ld<R, RT>(A.rays.w, r);
+            const int bin = energy_bin(A.tally, static_cast<double>(E));
+            if (bin < 0) continue;
+            xs_lookup(A.xs, hash, E, mysig, bd);
+            em.reset(ox, oy, oz, ux, uy, uz, E, wt, bin * A.g.n_tiles);
+            if (!wk.start(A.mesh, ox, oy, oz, ux, uy, uz)) continue;
+            while (wk.step(A.mesh, em)) {
+            }
+        }
+        __syncthreads();  // s_perm is rewritten by the next chunk
+    }
+    const uint32_t used = s_cursor < A.cap ? s_cursor : static_cast<uint32_t>(A.cap);
+    if (threadIdx.x == 0) A.counts[blockIdx.x] = used;
+    uint32_t *row = A.hist + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
+    for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) row[k] = s_hist[k];
+}
+
+// Block of 1024 threads, 64 keys: lane = key, each of the 16 wavefronts a
+// slice of the blocks.  row_off[b * n_keys + key] = sum over b' < b of
+// hist[b' * n_keys + key]; key_tot[key] = the column sum.  Every access is a
+// coalesced row piece, with several loads in flight per lane.
+constexpr int kScanWaves = 16;
+__global__ void __launch_bounds__(1024) scan_rows_kernel(const uint32_t *hist, int G, int n_keys, uint32_t *row_off,
+                                                         uint32_t *key_tot)
+{
+    __shared__ uint32_t part[kScanWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int key = blockIdx.x * 64 + lane;
+    const bool on = key < n_keys;
+    const int per = (G + kScanWaves - 1) / kScanWaves;
+    const int b0 = wv * per;
+    const int b1 = b0 + per < G ? b0 + per : G;
+    uint32_t sum = 0;
+    if (on) {
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) sum += hist[static_cast<int64_t>(b) * n_keys + key];
+    }
+    part[wv][lane] = sum;
+    __syncthreads();
+    uint32_t off = 0, total = 0;
+    for (int q = 0; q < kScanWaves; ++q) {
+        if (q < wv) off += part[q][lane];
+        total += part[q][lane];
+    }
+    if (!on) return;
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) {
+        const int64_t i = static_cast<int64_t>(b) * n_keys + key;
+        const uint32_t h = hist[i];
+        row_off[i] = off;
+        off += h;
+    }
+    if (wv == 0) key_tot[key] = total;
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim.x <= 1024).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp, uint32_t &total)
+{
+    const int t = threadIdx.x;
+    tmp[t] = v;
+    __syncthreads();
+    for (int off = 1; off < static_cast<int>(blockDim.x); off <<= 1) {
+        const uint32_t add = t >= off ? tmp[t - off] : 0u;
+        __syncthreads();
+        tmp[t] += add;
+        __syncthreads();
+    }
+    total = tmp[blockDim.x - 1];
+    const uint32_t incl = tmp[t];
+    __syncthreads();
+    return incl - v;
+}
+
+// key_base[k] = sum over k' < k of key_tot[k'], for k = 0..n_keys (one block).
+__global__ void __launch_bounds__(256) scan_keys_kernel(const uint32_t *key_tot, int n_keys, uint32_t *key_base)
+{
+    __shared__ uint32_t tmp[256];
+    const int per = (n_keys + blockDim.x - 1) / blockDim.x;
+    const int k0 = threadIdx.x * per;
+    uint32_t local = 0;
+    for (int j = 0; j < per; ++j)
+        if (k0 + j < n_keys) local += key_tot[k0 + j];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(local, tmp, total);
+    for (int j = 0; j < per; ++j) {
+        if (k0 + j < n_keys) {
+            key_base[k0 + j] = run;
+            run += key_tot[k0 + j];
+        }
+    }
+    if (threadIdx.x == 0) key_base[n_keys] = total;
+}
+
+// Every block scatters its region's records to their places in key-major
+// order (the order within one key's run is immaterial).
+template <typename E>
+__global__ void __launch_bounds__(256) partition_kernel(const E *records, int64_t cap, const uint32_t *counts,
+                                                        const uint32_t *row_off, const uint32_t *key_base,
+                                                        int n_keys, E *sorted)
+{
+    __shared__ uint32_t s_base[kMaxKeys];
+    __shared__ uint32_t s_cnt[kMaxKeys];
+    const int b = blockIdx.x;
+    const uint32_t *row = row_off + static_cast<int64_t>(b) * n_keys;
+    for (int k = threadIdx.x; k < n_keys; k += blockDim.x) {
+        s_base[k] = key_base[k] + row[k];
+        s_cnt[k] = 0u;
+    }
+    __syncthreads();
+    const E *region = records + static_cast<int64_t>(b) * cap;
+    const uint32_t n = counts[b];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const E r = region[i];
+        const uint32_t key = (r.code >> kLocalBits) & static_cast<uint32_t>(kMaxKeys - 1);
+        const uint32_t slot = atomicAdd(&s_cnt[key], 1u);
+        sorted[static_cast<int64_t>(s_base[key]) + slot] = r;
+    }
+}
+
+template <typename R>
+struct TileArgs {
+    MeshP<R> mesh;
+    XsP<R> xs;
+    int hash_in_lds;
+    SortGeom g;
+    const void *sorted;
+    const uint32_t *key_base;
+    int64_t nvox;
+    double *tally;
+};
+
+struct PutLds {
+    double *acc;
+    template <typename S>
+    __device__ __forceinline__ void operator()(int32_t, S, S f, int ci, int cj, int ck)
+    {
+        if (f != S(0)) atomicAdd(acc + local_index(ci, cj, ck), static_cast<double>(f));
+    }
+};
+
+// One block per key: the key's rays resumed at their tile entries and
+// scored into the tile in LDS, then the tile into the tally.
+// (FP32 scores: register budget for eight wavefronts per SIMD, two blocks of 1024)
+template <typename R, typename S, bool ATOMIC>
+__global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(TileArgs<R> A)
+{
+    __shared__ double acc[kTileVoxels];
+    __shared__ uint32_t s_cnt[kBucketsT];
+    __shared__ uint16_t s_perm[kMaxBlock];
+    const int key = blockIdx.x;
+    const uint32_t lo = A.key_base[key], hi = A.key_base[key + 1];
+    if (lo == hi) return;
+    for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) acc[i] = 0.0;
+    const int32_t *hash;
+    S(*sig)[2];
+    stage_lds(A.xs, A.hash_in_lds, hash, sig);
+    __syncthreads();
+    const int bd = blockDim.x;
+    S(*mysig)[2] = sig + threadIdx.x;
+    const int bin = key / A.g.n_tiles;
+    const int tile = key - bin * A.g.n_tiles;
+    const int tx = tile % A.g.ntx;
+    const int ty = (tile / A.g.ntx) % A.g.nty;
+    const int tz = tile / (A.g.ntx * A.g.nty);
+    const Entry<R, S> *rec = static_cast<const Entry<R, S> *>(A.sorted);
+    PutLds put{acc};
+    Scorer<S, PutLds> sc(mysig, bd, S(0), put);
+    Walker<R> wk;
+    const uint32_t tg = tile_tag(tx, ty, tz);
+    constexpr int PER = 1;  // the records of one block-sized chunk are ordered together
+    for (uint32_t c0 = lo; c0 < hi; c0 += bd) {
+        const int m = static_cast<int>(hi - c0 < static_cast<uint32_t>(bd) ? hi - c0 : static_cast<uint32_t>(bd));
+        int bucket[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            bucket[j] = 0;
+            const int idx = j * bd + static_cast<int>(threadIdx.x);
+            if (idx < m) {
+                const Entry<R, S> &r = rec[c0 + idx];
+                const uint32_t loc = r.code & static_cast<uint32_t>(kTileVoxels - 1);
+                const int est = tile_pieces_estimate(A.mesh, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz,
+                                                     tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1)),
+                                                     ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1)),
+                                                     tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits)));
+                bucket[j] = est < kBucketsT ? est : kBucketsT - 1;
+            }
+        }
+        sort_desc(bucket, m, kBucketsT, s_cnt, s_perm);
+        for (int j = threadIdx.x; j < m; j += bd) {
+            const Entry<R, S> r = rec[c0 + s_perm[j]];
+            xs_lookup(A.xs, hash, r.e, mysig, bd);
+            const uint32_t loc = r.code & static_cast<uint32_t>(kTileVoxels - 1);
+            const int ci = tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1));
+            const int cj = ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1));
+            const int ck = tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits));
+            sc.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, tg, (r.code & kFirst) != 0u);
+            wk.resume_tile(A.mesh, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz, ci, cj, ck, r.t0);
+            while (wk.step(A.mesh, sc)) {
+            }
+        }
+        __syncthreads();  // s_perm is rewritten by the next chunk
+    }
+    const int nx = A.mesh.n[0], ny = A.mesh.n[1], nz = A.mesh.n[2];
+    double *out = A.tally + static_cast<int64_t>(bin) * A.nvox;
+    for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) {
+        const double v = acc[i];
+        if (v == 0.0) continue;
+        const int x = tx * kTileEdge + (i & (kTileEdge - 1));
+        const int y = ty * kTileEdge + ((i >> kTileBits) & (kTileEdge - 1));
+        const int z = tz * kTileEdge + (i >> (2 * kTileBits));
+        if (x >= nx || y >= ny || z >= nz) continue;
+        double *p = out + x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z);
+        if constexpr (ATOMIC)
+            unsafeAtomicAdd(p, v);
+        else
+            *p += v;
+    }
+}
+
+template <typename R>
+XsP<R> xs_of(const XsHost &x);
+template <>
+XsP<float> xs_of<float>(const XsHost &x)
+{
+    return XsP<float>{x.d_E32, x.d_S32, x.d_hash32, x.K, x.n_mat, x.s_stride32, x.M, x.l2e0, x.inv_dl2};
+}
+template <>
+XsP<double> xs_of<double>(const XsHost &x)
+{
+    return XsP<double>{x.d_E64, x.d_S64, x.d_hash64, x.K, x.n_mat, x.s_stride64, x.M, x.l2e0, x.inv_dl2};
+}
+
+hipError_t grow(void *&p, size_t &cap, size_t need)
+{
+    if (cap >= need) return hipSuccess;
+    if (p) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+        (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    cap = need;
+    return hipSuccess;
+}
+
+constexpr int kBlock = 256;  // entries and partition
+constexpr size_t kLdsMax = 65536;
+constexpr size_t kEntriesStatic = 4 * (kMaxKeys + 16) + 4 * kBucketsE + 2 * 256;          // hist, cursor, sort
+constexpr size_t kTileStatic = sizeof(double) * kTileVoxels + 4 * kBucketsT + 2 * kMaxBlock;  // acc, sort
+constexpr size_t kScratchBudget = size_t(2) << 30;            // record bytes per sub-launch
+
+SortGeom geometry(const TallyHost &t, const MeshHost &m)
+{
+    SortGeom g;
+    g.ntx = (m.n[0] + kTileEdge - 1) / kTileEdge;
+    g.nty = (m.n[1] + kTileEdge - 1) / kTileEdge;
+    const int ntz = (m.n[2] + kTileEdge - 1) / kTileEdge;
+    const int64_t tiles = static_cast<int64_t>(g.ntx) * g.nty * ntz;
+    const int64_t keys = tiles * t.n_bins;
+    g.n_tiles = tiles <= kMaxKeys ? static_cast<int32_t>(tiles) : 0;
+    g.n_keys = keys <= kMaxKeys ? static_cast<int32_t>(keys) : 0;
+    return g;
+}
+
+size_t sigma_lds(const vrc_ctx &ctx, size_t s_bytes, int block)
+{
+    return s_bytes * 2 * static_cast<size_t>(ctx.xs.n_mat) * block;
+}
+
+// Block of the tiles pass: the largest whose cross-section columns fit in
+// LDS beside the tile (more wavefronts per tile keep the CU busier while
+// one tile's records are walked); 0 if none fits.
+int tile_block(const vrc_ctx &ctx, size_t s_bytes)
+{
+    for (int b : {1024, 512, 256})
+        if (kTileStatic + sigma_lds(ctx, s_bytes, b) <= kLdsMax) return b;
+    return 0;
+}
+
+template <typename R, typename RT, typename S>
+hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays, const SortGeom &g,
+                      bool atomic_flush, hipStream_t s)
+{
+    SortScratch &sc = ctx.sort_scratch;
+    const int G = ctx.n_cu * 8;
+    const int ntz = g.n_tiles / (g.ntx * g.nty);
+    const int64_t per_ray = static_cast<int64_t>(g.ntx) + g.nty + ntz;  // > tiles a ray can cross
+    const size_t rec = sizeof(Entry<R, S>);
+    const int64_t max_rays_block = static_cast<int64_t>(kScratchBudget / (rec * per_ray * G));
+    const int64_t group_rays = (max_rays_block < 1 ? 1 : max_rays_block) * G;
+    int shift = 0;
+    while (((static_cast<int64_t>(m.n[0]) + m.n[1] + m.n[2]) >> shift) >= kBucketsE) ++shift;
+    // LDS is kept for occupancy: the energy-grid hash stays in global memory
+    // (it is read once per ray or record and stays in L2).
+    const size_t lds1 = sigma_lds(ctx, sizeof(S), kBlock);
+    const int tb = tile_block(ctx, sizeof(S));
+    const size_t lds2 = sigma_lds(ctx, sizeof(S), tb);
+    if (sc.busy && sc.stream != s) {
+        hipError_t e = hipStreamWaitEvent(s, sc.done, 0);
+        if (e != hipSuccess) return e;
+    }
+    for (int64_t r0 = 0; r0 < rays.n; r0 += group_rays) {
+        const int64_t nr = rays.n - r0 < group_rays ? rays.n - r0 : group_rays;
+        const int64_t rays_block = (nr + G - 1) / G;
+        const int64_t cap = rays_block * per_ray;
+        const size_t rec_bytes = rec * static_cast<size_t>(cap) * G;
+        hipError_t e = grow(sc.records, sc.records_cap, rec_bytes);
+        if (e == hipSuccess) e = grow(sc.sorted, sc.sorted_cap, rec_bytes);
+        if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * static_cast<size_t>(G) * g.n_keys);
+        if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * static_cast<size_t>(G) * g.n_keys);
+        if (e == hipSuccess) e = grow(sc.counts, sc.counts_cap, sizeof(uint32_t) * G);
+        if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (g.n_keys + 1));
+        if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (g.n_keys + 1));
+        if (e != hipSuccess) return e;
+        MeshP<R> mesh;
+        for (int a = 0; a < 3; ++a) {
+            mesh.lo[a] = static_cast<R>(m.lo[a]);
+            mesh.h[a] = static_cast<R>(m.h[a]);
+            mesh.n[a] = m.n[a];
+        }
+        mesh.mat = m.d_mat;
+        EntryArgs<R> A;
+        A.mesh = mesh;
+        A.xs = xs_of<R>(ctx.xs);
+        const size_t el = sizeof(RT);
+        const void *base[8] = {rays.ox, rays.oy, rays.oz, rays.ux, rays.uy, rays.uz, rays.e, rays.w};
+        const void **dst[8] = {&A.rays.ox, &A.rays.oy, &A.rays.oz, &A.rays.ux, &A.rays.uy, &A.rays.uz, &A.rays.e,
+                               &A.rays.w};
+        for (int k = 0; k < 8; ++k) *dst[k] = static_cast<const char *>(base[k]) + el * static_cast<size_t>(r0);
+        A.rays.n = nr;
+        A.tally = TallyP{t.d_data, t.d_edges, t.nvox, t.n_bins};
+        A.hash_in_lds = 0;
+        A.g = g;
+        A.records = sc.records;
+        A.cap = cap;
+        A.counts = static_cast<uint32_t *>(sc.counts);
+        A.hist = static_cast<uint32_t *>(sc.hist);
+        A.rays_per_block = rays_block;
+        A.bucket_shift = shift;
+        hipLaunchKernelGGL((entries_kernel<R, RT, S>), dim3(G), dim3(kBlock), lds1, s, A);
+        hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
+                           static_cast<const uint32_t *>(sc.hist), G, g.n_keys, static_cast<uint32_t *>(sc.row_off),
+                           static_cast<uint32_t *>(sc.key_tot));
+        hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(sc.key_tot),
+                           g.n_keys, static_cast<uint32_t *>(sc.key_base));
+        hipLaunchKernelGGL((partition_kernel<Entry<R, S>>), dim3(G), dim3(256), 0, s,
+                           static_cast<const Entry<R, S> *>(sc.records), cap, static_cast<const uint32_t *>(sc.counts),
+                           static_cast<const uint32_t *>(sc.row_off), static_cast<const uint32_t *>(sc.key_base),
+                           g.n_keys, static_cast<Entry<R, S> *>(sc.sorted));
+        TileArgs<R> T;
+        T.mesh = mesh;
+        T.xs = A.xs;
+        T.hash_in_lds = 0;
+        T.g = g;
+        T.sorted = sc.sorted;
+        T.key_base = static_cast<const uint32_t *>(sc.key_base);
+        T.nvox = t.nvox;
+        T.tally = static_cast<double *>(t.d_data);
+        if (atomic_flush)
+            hipLaunchKernelGGL((tile_kernel<R, S, true>), dim3(g.n_keys), dim3(tb), lds2, s, T);
+        else
+            hipLaunchKernelGGL((tile_kernel<R, S, false>), dim3(g.n_keys), dim3(tb), lds2, s, T);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(sc.done, s);
+    if (e != hipSuccess) return e;
+    sc.busy = true;
+    sc.stream = s;
+    return hipSuccess;
+}
+
+}  // namespace
+
+bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m)
+{
+    if (t.prec == VRC_P32_KAHAN || ctx.sort_scratch.done == nullptr) return false;
+    const SortGeom g = geometry(t, m);
+    if (g.n_keys == 0) return false;
+    const size_t sb = t.prec == VRC_P32_T64 ? sizeof(float) : sizeof(double);
+    return kEntriesStatic + sigma_lds(ctx, sb, kBlock) <= kLdsMax && tile_block(ctx, sb) > 0;
+}
+
+hipError_t launch_cast_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays, bool rays_fp64,
+                              bool atomic_flush, hipStream_t s)
+{
+    if (rays.n <= 0) return hipSuccess;
+    const SortGeom g = geometry(t, m);
+    if (g.n_keys == 0) return hipErrorInvalidValue;
+    switch (t.prec) {
+    case VRC_P64:
+        return rays_fp64 ? run_sorted<double, double, double>(ctx, t, m, rays, g, atomic_flush, s)
+                         : run_sorted<double, float, double>(ctx, t, m, rays, g, atomic_flush, s);
+    case VRC_P32_T64:
+        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, rays, g, atomic_flush, s)
+                         : run_sorted<float, float, float>(ctx, t, m, rays, g, atomic_flush, s);
+    case VRC_P32_D64:
+        return rays_fp64 ? run_sorted<float, double, double>(ctx, t, m, rays, g, atomic_flush, s)
+                         : run_sorted<float, float, double>(ctx, t, m, rays, g, atomic_flush, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace vrc

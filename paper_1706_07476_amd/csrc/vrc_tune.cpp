@@ -231,13 +231,13 @@ vrc_status vrc_autotune_cast(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *ba
         std::lock_guard<std::mutex> lk(g_cache_mu);
         load_cache_file();
         auto it = g_cache.find(key);
-        if (it != g_cache.end() && it->second.size() == 5) {
+        if (it != g_cache.end() && it->second.size() == 6) {
             const auto &v = it->second;
             vrc_launch l{static_cast<int32_t>(v[0]), static_cast<int32_t>(v[1]), static_cast<int32_t>(v[2]),
-                         static_cast<int32_t>(v[3])};
+                         static_cast<int32_t>(v[3]), static_cast<int32_t>(v[4])};
             if (vrc_status st = vrc_set_launch(ctx, &l)) return st;
             *best = l;
-            if (best_ms) *best_ms = v[4];
+            if (best_ms) *best_ms = v[5];
             return VRC_OK;
         }
     }
@@ -249,29 +249,29 @@ vrc_status vrc_autotune_cast(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *ba
     vrc_status result = tm.ok ? VRC_OK : set_error(VRC_ERR_DEVICE, "timer set-up");
     double best_t = 1e300;
     vrc_launch best_l = saved;
-    const int blocks[] = {128, 256, 512};
-    const int bpcs[] = {0, 4, 8};
-    for (int block : blocks) {
-        for (int bpc : bpcs) {
-            for (int agg = 0; agg <= 1 && result == VRC_OK; ++agg) {
-                vrc_launch l{block, bpc, 1, agg};
-                if ((result = vrc_set_launch(ctx, &l)) != VRC_OK) break;
-                if ((result = vrc_cast_rays(ctx, sid, batch, tm.s)) != VRC_OK) break;
-                if (hipEventRecord(tm.a, tm.s) != hipSuccess) { result = VRC_ERR_DEVICE; break; }
-                for (int r = 0; r < repeats && result == VRC_OK; ++r) result = vrc_cast_rays(ctx, sid, batch, tm.s);
-                if (result != VRC_OK) break;
-                float ms = 0.f;
-                if (hipEventRecord(tm.b, tm.s) != hipSuccess || hipEventSynchronize(tm.b) != hipSuccess ||
-                    hipEventElapsedTime(&ms, tm.a, tm.b) != hipSuccess) {
-                    result = set_error(VRC_ERR_DEVICE, "timing a candidate");
-                    break;
-                }
-                const double t = ms / repeats;
-                if (t < best_t) {
-                    best_t = t;
-                    best_l = l;
-                }
-            }
+    // atomic-path shapes, then the tile-sorted accumulation (its own fixed shape)
+    std::vector<vrc_launch> cands;
+    for (int block : {128, 256, 512})
+        for (int bpc : {0, 4, 8})
+            for (int agg = 0; agg <= 1; ++agg) cands.push_back(vrc_launch{block, bpc, 1, agg, 0});
+    cands.push_back(vrc_launch{256, 8, 1, 0, 1});
+    for (const vrc_launch &l : cands) {
+        if (result != VRC_OK) break;
+        if ((result = vrc_set_launch(ctx, &l)) != VRC_OK) break;
+        if ((result = vrc_cast_rays(ctx, sid, batch, tm.s)) != VRC_OK) break;
+        if (hipEventRecord(tm.a, tm.s) != hipSuccess) { result = VRC_ERR_DEVICE; break; }
+        for (int r = 0; r < repeats && result == VRC_OK; ++r) result = vrc_cast_rays(ctx, sid, batch, tm.s);
+        if (result != VRC_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(tm.b, tm.s) != hipSuccess || hipEventSynchronize(tm.b) != hipSuccess ||
+            hipEventElapsedTime(&ms, tm.a, tm.b) != hipSuccess) {
+            result = set_error(VRC_ERR_DEVICE, "timing a candidate");
+            break;
+        }
+        const double t = ms / repeats;
+        if (t < best_t) {
+            best_t = t;
+            best_l = l;
         }
     }
     (void)hipStreamSynchronize(tm.s);
@@ -285,7 +285,7 @@ vrc_status vrc_autotune_cast(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *ba
     if (best_ms) *best_ms = best_t;
     std::lock_guard<std::mutex> lk(g_cache_mu);
     store(key, {double(best_l.block), double(best_l.blocks_per_cu), double(best_l.hash_in_lds),
-                double(best_l.aggregate), best_t});
+                double(best_l.aggregate), double(best_l.accumulate), best_t});
     return VRC_OK;
 }
 

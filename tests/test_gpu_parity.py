@@ -167,11 +167,13 @@ def test_tally_tiny_fp64(ctx):
     assert g <= TOL_P64
 
 
-def test_tally_multimaterial_fp64(ctx):
+@pytest.mark.parametrize("accumulate", [0, 1])
+def test_tally_multimaterial_fp64(ctx, accumulate):
     n_rays = 200_000
     wl = W.config2_multimaterial(n_rays=n_rays)
-    say(f"case: tally p64, multimat 100^3, {n_rays} rays")
+    say(f"case: tally p64, multimat 100^3, {n_rays} rays, accumulate {accumulate}")
     setup(ctx, wl)
+    ctx.set_launch(accumulate=accumulate)
     tid = ctx.create_tally(0, "p64")
     ctx.cast(tid, dev_arrays(wl.rays, "f64"))
     res = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=oracle_threads())
@@ -206,8 +208,9 @@ def eps_phi_max(got, res, se_max=0.3):
     return float(eps[i])
 
 
-@pytest.mark.parametrize("prec", ["p32_t64", "p32_kahan", "p32_d64"])
-def test_tally_multimaterial_fp32_well_sampled(ctx, prec):
+@pytest.mark.parametrize("prec,accumulate", [("p32_t64", 0), ("p32_t64", 1), ("p32_kahan", 0), ("p32_d64", 0),
+                                              ("p32_d64", 1)])
+def test_tally_multimaterial_fp32_well_sampled(ctx, prec, accumulate):
     """FP32 forms on a well-sampled mesh (16^3 of the multimat tables, 1.6e6 rays).
 
     Most voxels then have an oracle relative standard error below 5%, so the
@@ -216,8 +219,9 @@ def test_tally_multimaterial_fp32_well_sampled(ctx, prec):
     n_rays = 1_600_000
     wl = W.config2_multimaterial(n_rays=n_rays, n=16, h=0.5)
     wl.mesh = W.slab_mesh(202, 16, 0.5, slab=4)
-    say(f"case: tally {prec}, multimat tables on 16^3 (4-voxel slabs), {n_rays} rays")
+    say(f"case: tally {prec}, multimat tables on 16^3 (4-voxel slabs), {n_rays} rays, accumulate {accumulate}")
     setup(ctx, wl)
+    ctx.set_launch(accumulate=accumulate)
     tid = ctx.create_tally(0, prec)
     ctx.cast(tid, dev_arrays(wl.rays, "f32"))
     m, x, r = f32_view(wl.mesh, wl.xs, wl.rays)
@@ -442,8 +446,8 @@ def test_errors_are_reported(ctx, vrc):
         vrc.vrc_set_launch(ctx.handle, block=100)
 
 
-@pytest.mark.parametrize("prec", ["p32_t64", "p64", "p32_d64"])
-def test_full_size_bench_workload(ctx, prec):
+@pytest.mark.parametrize("prec,accumulate", [("p32_t64", 1), ("p32_t64", 0), ("p64", 1), ("p32_d64", 1)])
+def test_full_size_bench_workload(ctx, prec, accumulate):
     """The bench workload at full size (100^3, 1e6 rays) in the bench's default launch shape.
 
     Whole-tally comparison with the oracle, the exact segment total, and a
@@ -451,8 +455,9 @@ def test_full_size_bench_workload(ctx, prec):
     """
     import torch
     wl = W.config2_multimaterial()
-    say(f"case: full-size multimat 100^3, 1e6 rays, {prec}, launch {ctx.get_launch()}")
     setup(ctx, wl)
+    ctx.set_launch(accumulate=accumulate)
+    say(f"case: full-size multimat 100^3, 1e6 rays, {prec}, launch {ctx.get_launch()}")
     dt = "f64" if prec == "p64" else "f32"
     arrays = dev_arrays(wl.rays, dt)
     tid = ctx.create_tally(0, prec)

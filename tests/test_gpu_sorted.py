@@ -1,0 +1,247 @@
+"""The tile-split accumulation of the plain cast (launch accumulate = 2 or 3: forced).
+
+Rays are split at 16^3-tile entries and scored tile by tile in LDS; the
+scores are bit-identical to the per-segment atomic path and only the order
+of the tally additions differs, so the sorted tallies meet the same bounds
+against the oracle (FP64 1e-12 on every scored voxel; FP32 forms 1e-5 on
+voxels with oracle relative standard error below 5%) and agree with the
+atomic path to 1e-12.  Cases: several energy bins on a ragged
+(non-multiple-of-16) mesh, long rays crossing many tiles, the largest
+eligible key count with several sub-launches, a tally beyond the key limit
+(atomic path), ragged batch sizes, and sorted casts on two streams.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from vrc_testutil import dev_arrays, f32_view, oracle_threads, rel_report
+
+pytestmark = pytest.mark.gpu
+
+TOL_P64 = 1e-12
+TOL_P32 = 1e-5
+TOL_ORDER = 1e-12  # sorted vs atomic: same addends, another order
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vrc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1706_07476_amd as vrc_mod
+    vrc_mod.load_library()
+    return vrc_mod
+
+
+@pytest.fixture()
+def ctx(vrc):
+    c = vrc.Context(0)
+    yield c
+    c.close()
+
+
+def ragged_mesh(seed=505, n=(37, 29, 21), h=(0.5, 0.6, 0.7)):
+    """Box of 37 x 29 x 21 voxels (3 x 2 x 2 tiles of 16^3, all ragged), random materials from 3."""
+    rng = np.random.default_rng(seed)
+    nn = np.asarray(n, np.int32)
+    mat = rng.integers(0, 3, int(np.prod(nn))).astype(np.uint8)
+    return W.Mesh(np.array([-3.0, 1.0, 0.5]), np.asarray(h, np.float64), nn, mat)
+
+
+def cast_both(ctx, mesh_id, prec, arrays, edges=None, accumulate=2):
+    """(sorted tally, atomic tally) of the same rays."""
+    ts = ctx.create_tally(mesh_id, prec, edges)
+    ta = ctx.create_tally(mesh_id, prec, edges)
+    ctx.set_launch(accumulate=accumulate)
+    ctx.cast(ts, arrays)
+    ctx.set_launch(accumulate=0)
+    ctx.cast(ta, arrays)
+    return ctx.read(ts), ctx.read(ta)
+
+
+def order_rel(a, b):
+    scale = np.abs(b).max()
+    pos = np.abs(b) > 1e-30 * scale
+    assert np.all(a[~pos] == 0.0) or np.abs(a[~pos]).max() <= 1e-25 * scale
+    return float((np.abs(a[pos] - b[pos]) / np.abs(b[pos])).max()) if pos.any() else 0.0
+
+
+@pytest.mark.parametrize("accumulate", [2, 3])
+def test_sorted_fp64_multibin_ragged_mesh(ctx, accumulate):
+    mesh = ragged_mesh()
+    wl = W.config2_multimaterial(n_rays=0)
+    rays = W.rays_in_box(506, mesh, 150_000)
+    edges = W.log_bin_edges(10, 1e-9, 1.0)
+    say(f"case: sorted accumulate={accumulate} p64, 37x29x21, 10 bins, 1.5e5 rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    got, atom = cast_both(ctx, 0, "p64", dev_arrays(rays, "f64"), edges, accumulate)
+    res = oracle.cast(mesh, wl.xs, rays, edges=edges, n_threads=oracle_threads())
+    g, _, n = rel_report(got.reshape(10, -1), res, gate="all")
+    o = order_rel(got, atom)
+    say(f"  sorted vs oracle max rel {g:.3e} over {n}; sorted vs atomic {o:.3e}")
+    assert n > 0.5 * mesh.n_voxels
+    assert g <= TOL_P64
+    assert o <= TOL_ORDER
+
+
+@pytest.mark.parametrize("prec", ["p32_t64", "p32_d64"])
+def test_sorted_fp32_forms(ctx, prec):
+    mesh = W.slab_mesh(202, 16, 0.5, slab=4)
+    wl = W.config2_multimaterial(n_rays=0)
+    rays = W.rays_in_box(507, mesh, 1_600_000)
+    say(f"case: sorted {prec}, 16^3, 1.6e6 rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    got, atom = cast_both(ctx, 0, prec, dev_arrays(rays, "f32"))
+    m, x, r = f32_view(mesh, wl.xs, rays)
+    res = oracle.cast(m, x, r, n_threads=oracle_threads())
+    g, a, n = rel_report(got, res, gate="stderr")
+    o = order_rel(got, atom)
+    say(f"  sorted vs oracle gated max rel {g:.3e} over {n} ({a:.3e} all); sorted vs atomic {o:.3e}")
+    assert n > 0.5 * mesh.n_voxels
+    assert g <= TOL_P32
+    assert o <= TOL_ORDER
+
+
+def diagonal_rays(seed, mesh, n):
+    """Rays from near the low corner along directions close to the main diagonal (about n_x+n_y+n_z voxels each)."""
+    rng = np.random.default_rng(seed)
+    o = mesh.lo[None, :] + rng.uniform(0.0, 2.0, (n, 3)) * mesh.h[None, :]
+    u = np.array([1.0, 1.0, 1.0]) + rng.uniform(-0.05, 0.05, (n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    e = W.log_uniform_energies(rng, n)
+    w = rng.lognormal(0.0, 0.5, n)
+    return W.Rays(o[:, 0].copy(), o[:, 1].copy(), o[:, 2].copy(), u[:, 0].copy(), u[:, 1].copy(), u[:, 2].copy(),
+                  e, w)
+
+
+def test_sorted_long_rays_many_tiles(ctx):
+    """Every ray crosses ~190 voxels and ~10 tiles (the most a ray can cross in 4^3 tiles)."""
+    mesh = W.slab_mesh(508, 64, 0.5)
+    wl = W.config2_multimaterial(n_rays=0)
+    rays = diagonal_rays(509, mesh, 300_000)
+    say("case: sorted p64, 64^3, 3e5 diagonal rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    got, atom = cast_both(ctx, 0, "p64", dev_arrays(rays, "f64"))
+    res = oracle.cast(mesh, wl.xs, rays, n_threads=oracle_threads())
+    segs = oracle.count_segments(mesh, rays, "f64", oracle_threads())
+    g, _, n = rel_report(got, res, gate="all")
+    o = order_rel(got, atom)
+    say(f"  mean segments/ray {segs.mean():.1f}; sorted vs oracle {g:.3e} over {n}; vs atomic {o:.3e}")
+    assert segs.mean() > 150
+    assert g <= TOL_P64
+    assert o <= TOL_ORDER
+
+
+@pytest.mark.parametrize("prec", ["p64", "p32_t64"])
+def test_sorted_max_keys_several_sub_launches(ctx, prec):
+    """256^3 with one bin: exactly 4096 keys; 6e5 rays exceed one sub-launch's 2048 x 256 rays."""
+    wl = W.config3_precision(n_rays=0)
+    mesh = wl.mesh
+    rays = W.rays_in_box(510, mesh, 600_000)
+    say(f"case: sorted {prec}, cylinder 256^3 (4096 keys), 6e5 rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    dt = "f64" if prec == "p64" else "f32"
+    got, atom = cast_both(ctx, 0, prec, dev_arrays(rays, dt))
+    o = order_rel(got, atom)
+    say(f"  sorted vs atomic {o:.3e}")
+    assert o <= TOL_ORDER
+    if prec == "p64":
+        res = oracle.cast(mesh, wl.xs, rays, n_threads=oracle_threads())
+        g, _, n = rel_report(got, res, gate="all")
+        say(f"  sorted vs oracle {g:.3e} over {n}")
+        assert g <= TOL_P64
+
+
+def test_beyond_key_limit_uses_atomics(ctx):
+    """128^3 with 9 bins = 4608 keys: the sorted setting falls back to the atomic path."""
+    mesh = W.slab_mesh(511, 128, 0.5)
+    wl = W.config2_multimaterial(n_rays=0)
+    rays = W.rays_in_box(512, mesh, 50_000)
+    edges = W.log_bin_edges(9, 1e-9, 1.0)
+    say("case: sorted setting beyond the key limit, 128^3 x 9 bins")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    got, atom = cast_both(ctx, 0, "p64", dev_arrays(rays, "f64"), edges)
+    res = oracle.cast(mesh, wl.xs, rays, edges=edges, n_threads=oracle_threads())
+    g, _, _ = rel_report(got.reshape(9, -1), res, gate="all")
+    assert g <= TOL_P64
+    assert order_rel(got, atom) <= TOL_ORDER
+
+
+@pytest.mark.parametrize("n_rays", [0, 1, 65, 1023, 70_001])
+def test_sorted_ragged_batches(ctx, n_rays):
+    mesh = ragged_mesh(seed=513)
+    wl = W.config2_multimaterial(n_rays=0)
+    rays = W.rays_in_box(514, mesh, max(n_rays, 1)).take(slice(0, n_rays))
+    say(f"case: sorted p64 ragged batch {n_rays}")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    tid = ctx.create_tally(0, "p64")
+    ctx.set_launch(accumulate=2)
+    ctx.cast(tid, dev_arrays(rays, "f64"))
+    got = ctx.read(tid)
+    if n_rays == 0:
+        assert not got.any()
+        return
+    res = oracle.cast(mesh, wl.xs, rays, n_threads=oracle_threads())
+    g, _, _ = rel_report(got, res, gate="all")
+    assert g <= TOL_P64
+
+
+def test_sorted_casts_on_two_streams(ctx):
+    """Sorted casts issued on two streams share one scratch; they are ordered and both tallies are right."""
+    import torch
+    mesh = ragged_mesh(seed=515)
+    wl = W.config2_multimaterial(n_rays=0)
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    say("case: sorted casts on two streams")
+    parts = [W.rays_in_box(600 + i, mesh, 40_000 + 1000 * i) for i in range(6)]
+    arrs = [dev_arrays(p, "f64") for p in parts]
+    ta = ctx.create_tally(0, "p64")
+    tb = ctx.create_tally(0, "p64")
+    ctx.set_launch(accumulate=2)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for i, a in enumerate(arrs):
+        ctx.cast(ta if i % 2 == 0 else tb, a, stream=(s1 if i % 2 == 0 else s2).cuda_stream)
+    torch.cuda.synchronize()
+    ca = ctx.create_tally(0, "p64")
+    cb = ctx.create_tally(0, "p64")
+    ctx.set_launch(accumulate=0)
+    for i, a in enumerate(arrs):
+        ctx.cast(ca if i % 2 == 0 else cb, a)
+    assert order_rel(ctx.read(ta), ctx.read(ca)) <= TOL_ORDER
+    assert order_rel(ctx.read(tb), ctx.read(cb)) <= TOL_ORDER
+
+
+def test_autotune_cast_considers_sorted(ctx, monkeypatch, tmp_path):
+    monkeypatch.setenv("VRC_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    wl = W.config2_multimaterial(n_rays=200_000)
+    say("case: cast autotuner over atomic shapes and the sorted mode")
+    ctx.set_mesh(0, wl.mesh)
+    ctx.set_xs(wl.xs)
+    arrays = dev_arrays(wl.rays, "f32")
+    tid = ctx.create_tally(0, "p32_t64")
+    best, ms = ctx.autotune_cast(tid, arrays, repeats=1)
+    say(f"  best {best} {ms:.3f} ms")
+    assert best["accumulate"] in (0, 1) and ms > 0
+    assert ctx.get_launch() == best
+    chk = ctx.create_tally(0, "p32_t64")
+    ctx.cast(chk, arrays)
+    ref = ctx.create_tally(0, "p32_t64")
+    ctx.set_launch(accumulate=0)
+    ctx.cast(ref, arrays)
+    assert order_rel(ctx.read(chk), ctx.read(ref)) <= TOL_ORDER
