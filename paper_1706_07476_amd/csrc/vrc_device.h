@@ -136,6 +136,22 @@ __device__ __forceinline__ uint32_t tile_tag(int ti, int tj, int tk)
     return static_cast<uint32_t>(ti) + (static_cast<uint32_t>(tj) << 11) + (static_cast<uint32_t>(tk) << 22);
 }
 
+// Where a walk reads voxel materials: the mesh array in global memory, or a
+// copy of one tile's materials in LDS (indexed by the voxel's position in
+// its tile).
+struct MeshMaterials {
+    const uint8_t *mat;
+    __device__ __forceinline__ int operator()(int32_t vox, int, int, int) const { return mat[vox]; }
+};
+struct TileMaterials {
+    const uint8_t *mat;  // LDS, kTileEdge^3, x fastest
+    int lo_x, lo_y, lo_z;
+    __device__ __forceinline__ int operator()(int32_t, int i, int j, int k) const
+    {
+        return mat[(i - lo_x) + kTileEdge * ((j - lo_y) + kTileEdge * (k - lo_z))];
+    }
+};
+
 // The walk of one ray as explicit state, one piece per step(), so that a
 // lane can switch to its next ray (or ray piece) the moment the current one
 // ends instead of waiting for the longest ray of its wavefront.  All state is
@@ -193,8 +209,9 @@ struct Walker {
     // that voxel's tile.  The per-axis crossings are recomputed from the plane
     // indices exactly as step() computes them, so the pieces are
     // bit-identical to those of the uninterrupted walk.
-    __device__ __forceinline__ void resume_tile(const MeshP<R> &M, R ox_, R oy_, R oz_, R ux, R uy, R uz, int kx_,
-                                                int ky_, int kz_, R cur_)
+    template <class Mat>
+    __device__ __forceinline__ void resume_tile(const MeshP<R> &M, const Mat &mats, R ox_, R oy_, R oz_, R ux, R uy,
+                                                R uz, int kx_, int ky_, int kz_, R cur_)
     {
         const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
         const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
@@ -229,7 +246,7 @@ struct Walker {
         ex_y = ny - lo_y < kTileEdge ? ny - lo_y : kTileEdge;
         ex_z = nz - lo_z < kTileEdge ? nz - lo_z : kTileEdge;
         vox = kx + nx * (ky + ny * kz);
-        m = M.mat[vox];
+        m = mats(vox, kx, ky, kz);
     }
 
     // One piece: seg(vox, mat, len, i, j, k, t0) for a positive length
@@ -237,8 +254,8 @@ struct Walker {
     // starts).  The material of the next voxel is loaded before the piece is
     // handed on, so its latency overlaps the score.  False once the walk has
     // ended (mesh exit, limit, or budget).
-    template <class Seg>
-    __device__ __forceinline__ bool step(const MeshP<R> &M, Seg &seg)
+    template <class Seg, class Mat = MeshMaterials>
+    __device__ __forceinline__ bool step(const MeshP<R> &M, Seg &seg, const Mat &mats)
     {
         // work on local copies (no selects between members, which would force the state out of registers)
         int kx = this->kx, ky = this->ky, kz = this->kz;
@@ -274,7 +291,7 @@ struct Walker {
             if (inside) {
                 const int32_t dv = ax ? 1 : (ay ? nx : nx * ny);
                 vox = vcur + (s > 0 ? dv : -dv);
-                m = M.mat[vox];
+                m = mats(vox, ax ? ni : kx, ay ? ni : ky, az ? ni : kz);
                 const R plo = ax ? lox : (ay ? loy : loz);
                 const R h = ax ? hx : (ay ? hy : hz);
                 const R oa = ax ? ox : (ay ? oy : oz);
@@ -309,7 +326,8 @@ __device__ __forceinline__ bool walk(const MeshP<R> &M, R ox, R oy, R oz, R ux, 
 {
     Walker<R> w;
     if (!w.start(M, ox, oy, oz, ux, uy, uz)) return false;
-    while (w.step(M, seg)) {
+    const MeshMaterials mats{M.mat};
+    while (w.step(M, seg, mats)) {
     }
     return true;
 }

@@ -8,9 +8,10 @@
 // is cut into tiles of 16^3 voxels and every ray is split where it enters a
 // tile; a key is (energy bin, tile).
 //
-//   1. entries: every block takes a contiguous run of rays, orders them by
-//      estimated length, and every lane walks its ray accumulating only the
-//      optical depth (no exponentials, no tally); at each tile entry it
+//   0. order: the rays are ordered by estimated length (counting sort).
+//   1. entries: every block takes a run of the ordered rays and every lane
+//      walks its ray accumulating only the optical depth (no exponentials,
+//      no tally); at each tile entry it
 //      appends a record {ray, entry voxel, entry parameter, optical depth so
 //      far} to its block's region (wavefront-compacted, coalesced stores),
 //      counting records per key in LDS.  A ray crosses at most
@@ -193,6 +194,46 @@ constexpr int kBucketsE = 256;  // entries: estimated pieces (scaled to fit)
 constexpr int kBucketsT = 64;   // tiles: pieces inside one tile, at most 3 * 16 - 2
 constexpr int kMaxBlock = 1024;
 
+// Ordering of the rays by estimated length, longest first (a counting sort
+// over the whole batch, through the same block-row scans as the records):
+// order_hist counts each block's rays per length bucket, order_scatter
+// writes the ray indices to their places.
+template <typename R, typename RT>
+__global__ void __launch_bounds__(256) order_hist_kernel(MeshP<R> M, RaysP rays, int64_t rays_per_block, int shift,
+                                                         uint8_t *bucket, uint32_t *hist)
+{
+    __shared__ uint32_t s_hist[kBucketsE];
+    for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) s_hist[k] = 0u;
+    __syncthreads();
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
+    const int64_t last = first + rays_per_block < rays.n ? first + rays_per_block : rays.n;
+    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) {
+        const int est = ray_pieces_estimate(M, ld<R, RT>(rays.ox, r), ld<R, RT>(rays.oy, r), ld<R, RT>(rays.oz, r),
+                                            ld<R, RT>(rays.ux, r), ld<R, RT>(rays.uy, r), ld<R, RT>(rays.uz, r));
+        const int bk = est >> shift;
+        const int slot = kBucketsE - 1 - (bk < kBucketsE ? bk : kBucketsE - 1);  // longest first
+        bucket[r] = static_cast<uint8_t>(slot);
+        atomicAdd(&s_hist[slot], 1u);
+    }
+    __syncthreads();
+    uint32_t *row = hist + static_cast<int64_t>(blockIdx.x) * kBucketsE;
+    for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) row[k] = s_hist[k];
+}
+
+__global__ void __launch_bounds__(256) order_scatter_kernel(const uint8_t *bucket, int64_t n, int64_t rays_per_block,
+                                                            const uint32_t *row_off, const uint32_t *key_base,
+                                                            uint32_t *order)
+{
+    __shared__ uint32_t s_base[kBucketsE];
+    const uint32_t *row = row_off + static_cast<int64_t>(blockIdx.x) * kBucketsE;
+    for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) s_base[k] = key_base[k] + row[k];
+    __syncthreads();
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
+    const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
+    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x)
+        order[atomicAdd(&s_base[bucket[r]], 1u)] = static_cast<uint32_t>(r);
+}
+
 template <typename R>
 struct EntryArgs {
     MeshP<R> mesh;
@@ -206,7 +247,7 @@ struct EntryArgs {
     uint32_t *counts;  // G
     uint32_t *hist;    // G * n_keys
     int64_t rays_per_block;
-    int bucket_shift;  // estimated pieces >> bucket_shift < kBucketsE
+    const uint32_t *order;  // rays by estimated length, longest first
 };
 
 // Walk sink of the entries pass: the optical depth as the score sums it
@@ -298,9 +339,6 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
 {
     __shared__ uint32_t s_hist[kMaxKeys];
     __shared__ uint32_t s_cursor;
-    __shared__ uint32_t s_cnt[kBucketsE];
-    __shared__ uint16_t s_perm[256];
-    constexpr int PER = 1;  // the rays of one block-sized chunk are ordered together
     for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_hist[k] = 0u;
     if (threadIdx.x == 0) s_cursor = 0u;
     __syncthreads();
@@ -316,39 +354,22 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     EmitEntries<R, S> em{mysig, bd, S(0), S(0), 0u, false, R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0),
                          0, A.g, region, A.cap, &s_cursor, s_hist};
     Walker<R> wk;
-    for (int64_t c0 = first; c0 < last; c0 += bd) {
-        const int m = static_cast<int>(last - c0 < bd ? last - c0 : bd);
-        int bucket[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            bucket[j] = 0;
-            const int idx = j * bd + static_cast<int>(threadIdx.x);
-            if (idx < m) {
-                const int64_t r = c0 + idx;
-                const int est = ray_pieces_estimate(A.mesh, ld<R, RT>(A.rays.ox, r), ld<R, RT>(A.rays.oy, r),
-                                                    ld<R, RT>(A.rays.oz, r), ld<R, RT>(A.rays.ux, r),
-                                                    ld<R, RT>(A.rays.uy, r), ld<R, RT>(A.rays.uz, r));
-                const int bk = est >> A.bucket_shift;
-                bucket[j] = bk < kBucketsE ? bk : kBucketsE - 1;
-            }
+    const MeshMaterials mats{A.mesh.mat};
+    for (int64_t j = first + threadIdx.x; j < last; j += bd) {
+        const int64_t r = A.order[j];
+        const R ox = ld<R, RT>(A.rays.ox, r), oy = ld<R, RT>(A.rays.oy, r), oz = ld<R, RT>(A.rays.oz, r);
+        const R ux = ld<R, RT>(A.rays.ux, r), uy = ld<R, RT>(A.rays.uy, r), uz = ld<R, RT>(A.rays.uz, r);
+        const R E = ld<R, RT>(A.rays.e, r);
+        const R wt = ld<R, RT>(A.rays.w, r);
+        const int bin = energy_bin(A.tally, static_cast<double>(E));
+        if (bin < 0) continue;
+        xs_lookup(A.xs, hash, E, mysig, bd);
+        em.reset(ox, oy, oz, ux, uy, uz, E, wt, bin * A.g.n_tiles);
+        if (!wk.start(A.mesh, ox, oy, oz, ux, uy, uz)) continue;
+        while (wk.step(A.mesh, em, mats)) {
         }
-        sort_desc(bucket, m, kBucketsE, s_cnt, s_perm);
-        for (int j = threadIdx.x; j < m; j += bd) {
-            const int64_t r = c0 + s_perm[j];
-            const R ox = ld<R, RT>(A.rays.ox, r), oy = ld<R, RT>(A.rays.oy, r), oz = ld<R, RT>(A.rays.oz, r);
-            const R ux = ld<R, RT>(A.rays.ux, r), uy = ld<R, RT>(A.rays.uy, r), uz = ld<R, RT>(A.rays.uz, r);
-            const R E = ld<R, RT>(A.rays.e, r);
-            const R wt = ld<R, RT>(A.rays.w, r);
-            const int bin = energy_bin(A.tally, static_cast<double>(E));
-            if (bin < 0) continue;
-            xs_lookup(A.xs, hash, E, mysig, bd);
-            em.reset(ox, oy, oz, ux, uy, uz, E, wt, bin * A.g.n_tiles);
-            if (!wk.start(A.mesh, ox, oy, oz, ux, uy, uz)) continue;
-            while (wk.step(A.mesh, em)) {
-            }
-        }
-        __syncthreads();  // s_perm is rewritten by the next chunk
     }
+    __syncthreads();
     const uint32_t used = s_cursor < A.cap ? s_cursor : static_cast<uint32_t>(A.cap);
     if (threadIdx.x == 0) A.counts[blockIdx.x] = used;
     uint32_t *row = A.hist + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
@@ -433,28 +454,46 @@ __global__ void __launch_bounds__(256) scan_keys_kernel(const uint32_t *key_tot,
 }
 
 // Every block scatters its region's records to their places in key-major
-// order (the order within one key's run is immaterial).
+// order (the order within one key's run is immaterial).  Each record goes
+// to a place of its own, so a record per lane written with 16-byte stores
+// would leave the memory system many partial-sector writes; instead the
+// block stages 256 records in LDS and writes them back word by word, so
+// consecutive lanes write consecutive words of one record.
 template <typename E>
 __global__ void __launch_bounds__(256) partition_kernel(const E *records, int64_t cap, const uint32_t *counts,
                                                         const uint32_t *row_off, const uint32_t *key_base,
                                                         int n_keys, E *sorted)
 {
+    constexpr int W = static_cast<int>(sizeof(E) / 4);  // words per record
     __shared__ uint32_t s_base[kMaxKeys];
     __shared__ uint32_t s_cnt[kMaxKeys];
+    __shared__ uint32_t s_stage[256 * W];
+    __shared__ uint32_t s_dst[256];
     const int b = blockIdx.x;
+    const int t = threadIdx.x;
     const uint32_t *row = row_off + static_cast<int64_t>(b) * n_keys;
-    for (int k = threadIdx.x; k < n_keys; k += blockDim.x) {
+    for (int k = t; k < n_keys; k += blockDim.x) {
         s_base[k] = key_base[k] + row[k];
         s_cnt[k] = 0u;
     }
     __syncthreads();
     const E *region = records + static_cast<int64_t>(b) * cap;
+    uint32_t *out = reinterpret_cast<uint32_t *>(sorted);
     const uint32_t n = counts[b];
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const E r = region[i];
-        const uint32_t key = (r.code >> kLocalBits) & static_cast<uint32_t>(kMaxKeys - 1);
-        const uint32_t slot = atomicAdd(&s_cnt[key], 1u);
-        sorted[static_cast<int64_t>(s_base[key]) + slot] = r;
+    for (uint32_t c0 = 0; c0 < n; c0 += 256) {
+        const int m = n - c0 < 256u ? static_cast<int>(n - c0) : 256;
+        if (t < m) {
+            const E r = region[c0 + t];
+            const uint32_t key = (r.code >> kLocalBits) & static_cast<uint32_t>(kMaxKeys - 1);
+            s_dst[t] = s_base[key] + atomicAdd(&s_cnt[key], 1u);
+            *reinterpret_cast<E *>(s_stage + t * W) = r;
+        }
+        __syncthreads();
+        for (int w = t; w < m * W; w += 256) {
+            const int q = w / W;
+            out[static_cast<int64_t>(s_dst[q]) * W + (w - q * W)] = s_stage[w];
+        }
+        __syncthreads();
     }
 }
 
@@ -486,23 +525,35 @@ template <typename R, typename S, bool ATOMIC>
 __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(TileArgs<R> A)
 {
     __shared__ double acc[kTileVoxels];
+    __shared__ uint8_t s_mat[kTileVoxels];
     __shared__ uint32_t s_cnt[kBucketsT];
     __shared__ uint16_t s_perm[kMaxBlock];
     const int key = blockIdx.x;
     const uint32_t lo = A.key_base[key], hi = A.key_base[key + 1];
     if (lo == hi) return;
-    for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) acc[i] = 0.0;
+    const int bin = key / A.g.n_tiles;
+    const int tile = key - bin * A.g.n_tiles;
+    const int tx = tile % A.g.ntx;
+    const int ty = (tile / A.g.ntx) % A.g.nty;
+    const int tz = tile / (A.g.ntx * A.g.nty);
+    const int nx = A.mesh.n[0], ny = A.mesh.n[1], nz = A.mesh.n[2];
+    // the tile's materials (voxels beyond the mesh are never read)
+    for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) {
+        acc[i] = 0.0;
+        const int x = tx * kTileEdge + (i & (kTileEdge - 1));
+        const int y = ty * kTileEdge + ((i >> kTileBits) & (kTileEdge - 1));
+        const int z = tz * kTileEdge + (i >> (2 * kTileBits));
+        s_mat[i] = (x < nx && y < ny && z < nz)
+                       ? A.mesh.mat[x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z)]
+                       : static_cast<uint8_t>(0);
+    }
     const int32_t *hash;
     S(*sig)[2];
     stage_lds(A.xs, A.hash_in_lds, hash, sig);
     __syncthreads();
     const int bd = blockDim.x;
     S(*mysig)[2] = sig + threadIdx.x;
-    const int bin = key / A.g.n_tiles;
-    const int tile = key - bin * A.g.n_tiles;
-    const int tx = tile % A.g.ntx;
-    const int ty = (tile / A.g.ntx) % A.g.nty;
-    const int tz = tile / (A.g.ntx * A.g.nty);
+    const TileMaterials mats{s_mat, tx * kTileEdge, ty * kTileEdge, tz * kTileEdge};
     const Entry<R, S> *rec = static_cast<const Entry<R, S> *>(A.sorted);
     PutLds put{acc};
     Scorer<S, PutLds> sc(mysig, bd, S(0), put);
@@ -535,13 +586,12 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
             const int cj = ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1));
             const int ck = tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits));
             sc.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, tg, (r.code & kFirst) != 0u);
-            wk.resume_tile(A.mesh, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz, ci, cj, ck, r.t0);
-            while (wk.step(A.mesh, sc)) {
+            wk.resume_tile(A.mesh, mats, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz, ci, cj, ck, r.t0);
+            while (wk.step(A.mesh, sc, mats)) {
             }
         }
         __syncthreads();  // s_perm is rewritten by the next chunk
     }
-    const int nx = A.mesh.n[0], ny = A.mesh.n[1], nz = A.mesh.n[2];
     double *out = A.tally + static_cast<int64_t>(bin) * A.nvox;
     for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) {
         const double v = acc[i];
@@ -592,8 +642,8 @@ hipError_t grow(void *&p, size_t &cap, size_t need)
 
 constexpr int kBlock = 256;  // entries and partition
 constexpr size_t kLdsMax = 65536;
-constexpr size_t kEntriesStatic = 4 * (kMaxKeys + 16) + 4 * kBucketsE + 2 * 256;          // hist, cursor, sort
-constexpr size_t kTileStatic = sizeof(double) * kTileVoxels + 4 * kBucketsT + 2 * kMaxBlock;  // acc, sort
+constexpr size_t kEntriesStatic = 4 * (kMaxKeys + 16);                                      // hist, cursor
+constexpr size_t kTileStatic = (sizeof(double) + 1) * kTileVoxels + 4 * kBucketsT + 2 * kMaxBlock;  // acc, mat, sort
 constexpr size_t kScratchBudget = size_t(2) << 30;            // record bytes per sub-launch
 
 SortGeom geometry(const TallyHost &t, const MeshHost &m)
@@ -637,6 +687,7 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
     const int64_t group_rays = (max_rays_block < 1 ? 1 : max_rays_block) * G;
     int shift = 0;
     while (((static_cast<int64_t>(m.n[0]) + m.n[1] + m.n[2]) >> shift) >= kBucketsE) ++shift;
+    const int hist_keys = g.n_keys > kBucketsE ? g.n_keys : kBucketsE;  // hist rows serve both sorts
     // LDS is kept for occupancy: the energy-grid hash stays in global memory
     // (it is read once per ray or record and stays in L2).
     const size_t lds1 = sigma_lds(ctx, sizeof(S), kBlock);
@@ -653,11 +704,13 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         const size_t rec_bytes = rec * static_cast<size_t>(cap) * G;
         hipError_t e = grow(sc.records, sc.records_cap, rec_bytes);
         if (e == hipSuccess) e = grow(sc.sorted, sc.sorted_cap, rec_bytes);
-        if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * static_cast<size_t>(G) * g.n_keys);
-        if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * static_cast<size_t>(G) * g.n_keys);
+        if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * static_cast<size_t>(G) * hist_keys);
+        if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * static_cast<size_t>(G) * hist_keys);
         if (e == hipSuccess) e = grow(sc.counts, sc.counts_cap, sizeof(uint32_t) * G);
-        if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (g.n_keys + 1));
-        if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (g.n_keys + 1));
+        if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (hist_keys + 1));
+        if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (hist_keys + 1));
+        if (e == hipSuccess) e = grow(sc.order, sc.order_cap, sizeof(uint32_t) * static_cast<size_t>(nr));
+        if (e == hipSuccess) e = grow(sc.bucket, sc.bucket_cap, static_cast<size_t>(nr));
         if (e != hipSuccess) return e;
         MeshP<R> mesh;
         for (int a = 0; a < 3; ++a) {
@@ -683,7 +736,19 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         A.counts = static_cast<uint32_t *>(sc.counts);
         A.hist = static_cast<uint32_t *>(sc.hist);
         A.rays_per_block = rays_block;
-        A.bucket_shift = shift;
+        A.order = static_cast<const uint32_t *>(sc.order);
+        uint32_t *hist = static_cast<uint32_t *>(sc.hist);
+        uint32_t *row_off = static_cast<uint32_t *>(sc.row_off);
+        uint32_t *key_tot = static_cast<uint32_t *>(sc.key_tot);
+        uint32_t *key_base = static_cast<uint32_t *>(sc.key_base);
+        hipLaunchKernelGGL((order_hist_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, mesh, A.rays, rays_block, shift,
+                           static_cast<uint8_t *>(sc.bucket), hist);
+        hipLaunchKernelGGL(scan_rows_kernel, dim3(kBucketsE / 64), dim3(64 * kScanWaves), 0, s, hist, G, kBucketsE,
+                           row_off, key_tot);
+        hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, key_tot, kBucketsE, key_base);
+        hipLaunchKernelGGL(order_scatter_kernel, dim3(G), dim3(kBlock), 0, s,
+                           static_cast<const uint8_t *>(sc.bucket), nr, rays_block, row_off, key_base,
+                           static_cast<uint32_t *>(sc.order));
         hipLaunchKernelGGL((entries_kernel<R, RT, S>), dim3(G), dim3(kBlock), lds1, s, A);
         hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
                            static_cast<const uint32_t *>(sc.hist), G, g.n_keys, static_cast<uint32_t *>(sc.row_off),
