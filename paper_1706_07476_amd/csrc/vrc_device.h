@@ -28,8 +28,8 @@
 //   x = Sigma l,  F = W_in (1 - e^{-x}) / Sigma  (W_in l if Sigma = 0),
 //   W_out = W_in e^{-x},
 // with 1 - e^{-x} and e^{-x} from one evaluation (vrc_math.h), and W_in
-// re-anchored to w e^{-tau} (compensated tau) every 16 segments and at every
-// entry into a new tile of 16^3 voxels.
+// re-anchored to w e^{-tau} (compensated tau) at every entry into a new tile
+// of 16^3 voxels (so at most 3 * 16 - 2 products apart).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -156,19 +156,22 @@ struct TileMaterials {
 // lane can switch to its next ray (or ray piece) the moment the current one
 // ends instead of waiting for the longest ray of its wavefront.  All state is
 // in named scalars (one set per axis), never in an array indexed by the axis,
-// so it stays in registers.  The walk may be limited to an index range per
-// axis ([lo, lo + ex)): the whole mesh, or one tile.
+// so it stays in registers.  The walk may be limited per axis to an index
+// range (the whole mesh, or one tile); it ends when the index it steps to on
+// an axis equals that axis' stop index (one past the range in the direction
+// of travel).
 template <typename R>
 struct Walker {
     R ox, oy, oz, ix, iy, iz;
-    int sx, sy, sz;  // step per axis: +1, -1, 0 (parallel)
-    int kx, ky, kz;  // current voxel
-    R tx, ty, tz;    // next crossing per axis
-    R cur, t_exit;   // entry parameter of the current voxel; mesh exit
+    int sx, sy, sz;        // step per axis: +1, -1, 0 (parallel)
+    int dvx, dvy, dvz;     // change of the linear voxel index per step on each axis
+    int stop_x, stop_y, stop_z;
+    int kx, ky, kz;        // current voxel
+    R tx, ty, tz;          // next crossing per axis
+    R cur, t_exit;         // entry parameter of the current voxel; mesh exit
     int32_t vox;
-    int m;           // material of the current voxel
-    int budget;      // planes that may still be crossed
-    int lo_x, lo_y, lo_z, ex_x, ex_y, ex_z;
+    int m;                 // material of the current voxel
+    int budget;            // planes that may still be crossed
 
     // Whole-mesh walk with the clip and start-voxel rules of the file
     // header; false if the ray misses the mesh.
@@ -196,10 +199,12 @@ struct Walker {
         start_axis(loz, hz, nz, oz, uz, iz, pz, t_enter, kz, tz, sz);
         cur = t_enter;
         budget = nx + ny + nz + 3;
-        lo_x = lo_y = lo_z = 0;
-        ex_x = nx;
-        ex_y = ny;
-        ex_z = nz;
+        stop_x = sx > 0 ? nx : -1;
+        stop_y = sy > 0 ? ny : -1;
+        stop_z = sz > 0 ? nz : -1;
+        dvx = sx;
+        dvy = sy * nx;
+        dvz = sz * nx * ny;
         vox = kx + nx * (ky + ny * kz);
         m = M.mat[vox];
         return true;
@@ -239,12 +244,13 @@ struct Walker {
         tz = pz ? Num<R>::inf() : (plane(loz, hz, kz + (sz > 0 ? 1 : 0)) - oz) * iz;
         cur = cur_;
         budget = 3 * kTileEdge + 3;
-        lo_x = kx & ~(kTileEdge - 1);
-        lo_y = ky & ~(kTileEdge - 1);
-        lo_z = kz & ~(kTileEdge - 1);
-        ex_x = nx - lo_x < kTileEdge ? nx - lo_x : kTileEdge;
-        ex_y = ny - lo_y < kTileEdge ? ny - lo_y : kTileEdge;
-        ex_z = nz - lo_z < kTileEdge ? nz - lo_z : kTileEdge;
+        const int ax0 = kx & ~(kTileEdge - 1), ay0 = ky & ~(kTileEdge - 1), az0 = kz & ~(kTileEdge - 1);
+        stop_x = sx > 0 ? (ax0 + kTileEdge < nx ? ax0 + kTileEdge : nx) : ax0 - 1;
+        stop_y = sy > 0 ? (ay0 + kTileEdge < ny ? ay0 + kTileEdge : ny) : ay0 - 1;
+        stop_z = sz > 0 ? (az0 + kTileEdge < nz ? az0 + kTileEdge : nz) : az0 - 1;
+        dvx = sx;
+        dvy = sy * nx;
+        dvz = sz * nx * ny;
         vox = kx + nx * (ky + ny * kz);
         m = mats(vox, kx, ky, kz);
     }
@@ -265,11 +271,10 @@ struct Walker {
         int m = this->m;
         const R ox = this->ox, oy = this->oy, oz = this->oz, ix = this->ix, iy = this->iy, iz = this->iz;
         const int sx = this->sx, sy = this->sy, sz = this->sz;
-        const int lo_x = this->lo_x, lo_y = this->lo_y, lo_z = this->lo_z;
-        const int ex_x = this->ex_x, ex_y = this->ex_y, ex_z = this->ex_z;
+        const int dvx = this->dvx, dvy = this->dvy, dvz = this->dvz;
+        const int stop_x = this->stop_x, stop_y = this->stop_y, stop_z = this->stop_z;
         const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
         const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
-        const int nx = M.n[0], ny = M.n[1];
         const bool ax = (tx <= ty) && (tx <= tz);
         const bool ay = !ax && (ty <= tz);
         const bool az = !ax && !ay;
@@ -285,12 +290,9 @@ struct Walker {
             // advance along the chosen axis and fetch the next voxel's material early
             const int s = ax ? sx : (ay ? sy : sz);
             const int ni = (ax ? kx : (ay ? ky : kz)) + s;
-            const int lo = ax ? lo_x : (ay ? lo_y : lo_z);
-            const int ex = ax ? ex_x : (ay ? ex_y : ex_z);
-            inside = static_cast<unsigned>(ni - lo) < static_cast<unsigned>(ex);
+            inside = ni != (ax ? stop_x : (ay ? stop_y : stop_z));
             if (inside) {
-                const int32_t dv = ax ? 1 : (ay ? nx : nx * ny);
-                vox = vcur + (s > 0 ? dv : -dv);
+                vox = vcur + (ax ? dvx : (ay ? dvy : dvz));
                 m = mats(vox, ax ? ni : kx, ay ? ni : ky, az ? ni : kz);
                 const R plo = ax ? lox : (ay ? loy : loz);
                 const R h = ax ? hx : (ay ? hy : hz);
@@ -408,25 +410,25 @@ __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, 
 // Running VRC score of one ray; calls put(voxel, length, score, i, j, k)
 // per piece.  The weight entering the next voxel is carried as a running
 // product of the segments' e^{-x}; the optical depth tau is summed alongside
-// with Knuth's TwoSum (compensated), and the weight is recomputed as
-// w e^{-tau} every kReanchor segments and at every tile entry, so its error
-// stays at a few ulp however long the ray is.  Because the state at a tile
-// entry is just (tau_hi, tau_lo), a cast split at tile entries (the sorted
-// accumulation) scores bit-identically to an uninterrupted one.
+// with Knuth's TwoSum (compensated), and at every tile entry the weight is
+// recomputed as w e^{-tau}, so its error stays at a few ulp however long the
+// ray is (a tile holds at most 3 * 16 - 2 pieces of one ray).  Because the
+// state at a tile entry is just (tau_hi, tau_lo), a cast split at tile
+// entries (the tile-split accumulation) scores bit-identically to an
+// uninterrupted one.
 template <typename R, class Put>
 struct Scorer {
-    static constexpr int kReanchor = 16;
     const R (*sig)[2];
     int stride;
     R w0;
     R w_in;
     R tau_hi;
     R tau_lo;
-    int since;      // pieces since the last re-anchor; -1 before the first piece
+    bool started;   // a piece has been scored
     uint32_t tile;  // tile_tag of the current tile
     Put &put;
     __device__ __forceinline__ Scorer(const R (*sig_)[2], int stride_, R w, Put &put_)
-        : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), since(-1), tile(0), put(put_) {}
+        : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), started(false), tile(0), put(put_) {}
     // Resume at the entry of the tile tagged tg with the optical depth
     // accumulated before it; first: the tile holds the ray's first piece.
     __device__ __forceinline__ void resume(R w, R th, R tl, uint32_t tg, bool first)
@@ -435,7 +437,7 @@ struct Scorer {
         w_in = w;
         tau_hi = th;
         tau_lo = tl;
-        since = 0;
+        started = true;
         tile = tg;
         if (!first) reanchor();
     }
@@ -449,9 +451,9 @@ struct Scorer {
     __device__ __forceinline__ void operator()(int32_t vox, int m, L len, int ci, int cj, int ck, L)
     {
         const uint32_t tg = tile_tag(ci >> kTileBits, cj >> kTileBits, ck >> kTileBits);
-        if (tg != tile || since < 0) {
-            if (since >= 0) reanchor();
-            since = 0;
+        if (tg != tile || !started) {
+            if (started) reanchor();
+            started = true;
             tile = tg;
         }
         const R l = static_cast<R>(len);
@@ -467,12 +469,7 @@ struct Scorer {
         const R err = (tau_hi - (t - bv)) + (x - bv);
         tau_hi = t;
         tau_lo += err;
-        if (++since >= kReanchor) {
-            since = 0;
-            reanchor();
-        } else {
-            w_in = w_in * g;
-        }
+        w_in = w_in * g;
     }
 };
 

@@ -69,16 +69,14 @@ VRC_HD inline double vrc_rint(double a) { return ::rint(a); }
 VRC_HD inline float vrc_rint(float a) { return ::rintf(a); }
 
 // g = exp(-x), em = 1 - exp(-x) for x >= 0 (x > x_max or NaN: g = 0, em = 1).
+// Branch-free: out-of-range arguments are evaluated at 0 and their results
+// replaced, so the lanes of a wavefront never split here.
 template <typename R>
 VRC_HD inline void attenuation(R x, R &g, R &em)
 {
     using C = AttenConst<R>;
-    if (!(x <= C::x_max)) {
-        g = R(0);
-        em = R(1);
-        return;
-    }
-    const R y = -x;
+    const bool big = !(x <= C::x_max);
+    const R y = big ? R(0) : -x;
     const R kf = vrc_rint(y * C::inv_ln2);
     R r = vrc_fma(-kf, C::ln2_hi, y);
     r = vrc_fma(-kf, C::ln2_lo, r);
@@ -88,8 +86,10 @@ VRC_HD inline void attenuation(R x, R &g, R &em)
     for (int j = C::degree - 1; j >= 1; --j) p = vrc_fma(p, r, static_cast<R>(inv_factorial(j)));
     const R q = p * r;
     const R s = vrc_ldexp(R(1), static_cast<int>(kf));
-    g = vrc_fma(s, q, s);
-    em = vrc_fma(-s, q, R(1) - s);
+    const R gv = vrc_fma(s, q, s);
+    const R ev = vrc_fma(-s, q, R(1) - s);
+    g = big ? R(0) : gv;
+    em = big ? R(1) : ev;
 }
 
 }  // namespace vrc
