@@ -93,36 +93,44 @@ def parse():
     return ap.parse_args()
 
 
-def _counter_mean(csv_path: str, kernel: str, counter: str) -> float:
-    """Mean of a counter over the dispatches of the kernels whose name contains ``kernel``."""
+def _counter_rows(csv_path: str, kernel: str, counter: str) -> list:
+    """Counter values of every dispatch of the kernels whose name contains ``kernel``."""
     import csv
     vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
             if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter]
     if not vals:
         raise SystemExit(f"no {counter} rows for {kernel} in {csv_path}")
-    return sum(vals) / len(vals)
+    return vals
 
 
-# the kernels of one cast, each dispatched once per step of the bench workload
-PIPELINE = {0: ["cast_f64_kernel<float, float, false>"],
-            1: ["entries_kernel<float, float, float>", "scan_rows_kernel", "scan_keys_kernel",
+# the kernels of one cast of the bench workload; the first one runs exactly once per cast
+PIPELINE = {0: ["cast_f64_kernel<float, float, false"],
+            1: ["entries_kernel<float, float, float>", "order_hist_kernel<float, float>",
+                "order_scatter_kernel<float, float>", "scan_rows_kernel", "scan_keys_kernel",
                 "partition_kernel<vrc::(anonymous namespace)::Entry<float, float> >", "tile_kernel<float, float, true>"]}
 
 
 def write_traffic(paths, precision="p32_t64", copy_mib=1024) -> None:
-    """Scale FETCH_SIZE/WRITE_SIZE (KiB per dispatch) of the cast's kernels by a plain copy of known size."""
+    """Scale FETCH_SIZE/WRITE_SIZE (KiB per dispatch) of the cast's kernels by a plain copy of known size.
+
+    Per cast: the sum over every dispatch of the cast's kernels divided by the
+    number of casts (dispatches of the first kernel of the list).
+    """
     cf, cw, pf, pw = paths
     acc = 1
     launch = {"block": 256, "blocks_per_cu": 8, "hash_in_lds": 1, "aggregate": 0, "accumulate": acc}
-    fetch = sum(_counter_mean(cf, k, "FETCH_SIZE") for k in PIPELINE[acc])
-    write = sum(_counter_mean(cw, k, "WRITE_SIZE") for k in PIPELINE[acc])
-    copy_f = _counter_mean(pf, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
-    copy_w = _counter_mean(pw, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
+    casts = len(_counter_rows(cf, PIPELINE[acc][0], "FETCH_SIZE"))
+    fetch = sum(sum(_counter_rows(cf, k, "FETCH_SIZE")) for k in PIPELINE[acc]) / casts
+    write = sum(sum(_counter_rows(cw, k, "WRITE_SIZE")) for k in PIPELINE[acc]) / casts
+    copy_f = sum(_counter_rows(pf, "__amd_rocclr_copyBuffer", "FETCH_SIZE"))
+    copy_f /= len(_counter_rows(pf, "__amd_rocclr_copyBuffer", "FETCH_SIZE"))
+    copy_w = sum(_counter_rows(pw, "__amd_rocclr_copyBuffer", "WRITE_SIZE"))
+    copy_w /= len(_counter_rows(pw, "__amd_rocclr_copyBuffer", "WRITE_SIZE"))
     nbytes = copy_mib * (1 << 20)
     ff, fw = nbytes / (copy_f * 1024), nbytes / (copy_w * 1024)
     t = {"kernels": PIPELINE[acc], "workload": "multimat 100^3, 1e6 rays (bench.py default)", "precision": precision,
-         "launch": launch, "kernel_hash": kernel_hash(), "fetch_size_kib_per_launch": fetch,
-         "write_size_kib_per_launch": write,
+         "launch": launch, "kernel_hash": kernel_hash(), "casts_profiled": casts,
+         "fetch_size_kib_per_launch": fetch, "write_size_kib_per_launch": write,
          "copy_calibration": {"bytes_read_and_written": nbytes, "fetch_size_kib": copy_f, "write_size_kib": copy_w,
                               "fetch_scale": ff, "write_scale": fw},
          "bytes_per_launch": fetch * 1024 * ff + write * 1024 * fw}
@@ -355,8 +363,10 @@ def precision_report() -> None:
                 "median_rel_all": q(rel, 0.5), "max_eps_phi": q(eps, 1.0)}
 
     dev = torch.device("cuda:0")
+    well = W.config2_multimaterial(n_rays=1_600_000, n=16, h=0.5)
+    well.mesh = W.slab_mesh(202, 16, 0.5, slab=4)  # every voxel well sampled: the 5% gate is populated
     cases = [("tiny", W.config1_tiny()), ("multimat", W.config2_multimaterial()),
-             ("cylinder", W.config3_precision())]
+             ("multimat-16^3-well-sampled", well), ("cylinder", W.config3_precision())]
     for name, wl in cases:
         log(f"precision: {name}: oracle on FP64 inputs")
         ref64 = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=threads)

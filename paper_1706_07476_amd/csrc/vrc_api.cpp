@@ -255,7 +255,7 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         free_dev(sc.counts);
         free_dev(sc.key_tot);
         free_dev(sc.key_base);
-        free_dev(sc.order);
+        free_dev(sc.ordered);
         free_dev(sc.bucket);
         if (sc.done) (void)hipEventDestroy(sc.done);
     }

@@ -87,9 +87,9 @@ constexpr int64_t kSplitMinRays = int64_t(1) << 17;
 // Scratch of the tile-sorted accumulation (vrc_sorted.hip), grown on demand.
 struct SortScratch {
     void *records = nullptr, *sorted = nullptr, *hist = nullptr, *row_off = nullptr;
-    void *counts = nullptr, *key_tot = nullptr, *key_base = nullptr, *order = nullptr, *bucket = nullptr;
+    void *counts = nullptr, *key_tot = nullptr, *key_base = nullptr, *ordered = nullptr, *bucket = nullptr;
     size_t records_cap = 0, sorted_cap = 0, hist_cap = 0, row_off_cap = 0;
-    size_t counts_cap = 0, key_tot_cap = 0, key_base_cap = 0, order_cap = 0, bucket_cap = 0;
+    size_t counts_cap = 0, key_tot_cap = 0, key_base_cap = 0, ordered_cap = 0, bucket_cap = 0;
     hipEvent_t done = nullptr;   // after the last kernel that used the scratch
     hipStream_t stream = nullptr;
     bool busy = false;

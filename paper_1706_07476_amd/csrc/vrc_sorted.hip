@@ -8,7 +8,8 @@
 // is cut into tiles of 16^3 voxels and every ray is split where it enters a
 // tile; a key is (energy bin, tile).
 //
-//   0. order: the rays are ordered by estimated length (counting sort).
+//   0. order: the rays are copied in order of estimated length (counting
+//      sort), as one record per ray.
 //   1. entries: every block takes a run of the ordered rays and every lane
 //      walks its ray accumulating only the optical depth (no exponentials,
 //      no tally); at each tile entry it
@@ -197,7 +198,7 @@ constexpr int kMaxBlock = 1024;
 // Ordering of the rays by estimated length, longest first (a counting sort
 // over the whole batch, through the same block-row scans as the records):
 // order_hist counts each block's rays per length bucket, order_scatter
-// writes the ray indices to their places.
+// writes each ray, as one record, to its place.
 template <typename R, typename RT>
 __global__ void __launch_bounds__(256) order_hist_kernel(MeshP<R> M, RaysP rays, int64_t rays_per_block, int shift,
                                                          uint8_t *bucket, uint32_t *hist)
@@ -220,18 +221,37 @@ __global__ void __launch_bounds__(256) order_hist_kernel(MeshP<R> M, RaysP rays,
     for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) row[k] = s_hist[k];
 }
 
-__global__ void __launch_bounds__(256) order_scatter_kernel(const uint8_t *bucket, int64_t n, int64_t rays_per_block,
+// One ray in the working precision, as the ordering writes it: the walk
+// then reads its rays as consecutive records instead of gathering eight
+// scattered values per ray.
+template <typename R>
+struct __align__(16) RayRec {
+    R ox, oy, oz, ux, uy, uz, e, w;
+};
+
+template <typename R, typename RT>
+__global__ void __launch_bounds__(256) order_scatter_kernel(RaysP rays, const uint8_t *bucket, int64_t rays_per_block,
                                                             const uint32_t *row_off, const uint32_t *key_base,
-                                                            uint32_t *order)
+                                                            RayRec<R> *ordered)
 {
     __shared__ uint32_t s_base[kBucketsE];
     const uint32_t *row = row_off + static_cast<int64_t>(blockIdx.x) * kBucketsE;
     for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) s_base[k] = key_base[k] + row[k];
     __syncthreads();
     const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
-    const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
-    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x)
-        order[atomicAdd(&s_base[bucket[r]], 1u)] = static_cast<uint32_t>(r);
+    const int64_t last = first + rays_per_block < rays.n ? first + rays_per_block : rays.n;
+    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) {
+        RayRec<R> rr;
+        rr.ox = ld<R, RT>(rays.ox, r);
+        rr.oy = ld<R, RT>(rays.oy, r);
+        rr.oz = ld<R, RT>(rays.oz, r);
+        rr.ux = ld<R, RT>(rays.ux, r);
+        rr.uy = ld<R, RT>(rays.uy, r);
+        rr.uz = ld<R, RT>(rays.uz, r);
+        rr.e = ld<R, RT>(rays.e, r);
+        rr.w = ld<R, RT>(rays.w, r);
+        ordered[atomicAdd(&s_base[bucket[r]], 1u)] = rr;
+    }
 }
 
 template <typename R>
@@ -247,7 +267,7 @@ struct EntryArgs {
     uint32_t *counts;  // G
     uint32_t *hist;    // G * n_keys
     int64_t rays_per_block;
-    const uint32_t *order;  // rays by estimated length, longest first
+    const void *ordered;  // RayRec<R>: the rays by estimated length, longest first
 };
 
 // Walk sink of the entries pass: the optical depth as the score sums it
@@ -355,12 +375,10 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
                          0, A.g, region, A.cap, &s_cursor, s_hist};
     Walker<R> wk;
     const MeshMaterials mats{A.mesh.mat};
+    const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
     for (int64_t j = first + threadIdx.x; j < last; j += bd) {
-        const int64_t r = A.order[j];
-        const R ox = ld<R, RT>(A.rays.ox, r), oy = ld<R, RT>(A.rays.oy, r), oz = ld<R, RT>(A.rays.oz, r);
-        const R ux = ld<R, RT>(A.rays.ux, r), uy = ld<R, RT>(A.rays.uy, r), uz = ld<R, RT>(A.rays.uz, r);
-        const R E = ld<R, RT>(A.rays.e, r);
-        const R wt = ld<R, RT>(A.rays.w, r);
+        const RayRec<R> rr = ordered[j];
+        const R ox = rr.ox, oy = rr.oy, oz = rr.oz, ux = rr.ux, uy = rr.uy, uz = rr.uz, E = rr.e, wt = rr.w;
         const int bin = energy_bin(A.tally, static_cast<double>(E));
         if (bin < 0) continue;
         xs_lookup(A.xs, hash, E, mysig, bd);
@@ -709,7 +727,7 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         if (e == hipSuccess) e = grow(sc.counts, sc.counts_cap, sizeof(uint32_t) * G);
         if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (hist_keys + 1));
         if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (hist_keys + 1));
-        if (e == hipSuccess) e = grow(sc.order, sc.order_cap, sizeof(uint32_t) * static_cast<size_t>(nr));
+        if (e == hipSuccess) e = grow(sc.ordered, sc.ordered_cap, sizeof(RayRec<R>) * static_cast<size_t>(nr));
         if (e == hipSuccess) e = grow(sc.bucket, sc.bucket_cap, static_cast<size_t>(nr));
         if (e != hipSuccess) return e;
         MeshP<R> mesh;
@@ -736,7 +754,7 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         A.counts = static_cast<uint32_t *>(sc.counts);
         A.hist = static_cast<uint32_t *>(sc.hist);
         A.rays_per_block = rays_block;
-        A.order = static_cast<const uint32_t *>(sc.order);
+        A.ordered = sc.ordered;
         uint32_t *hist = static_cast<uint32_t *>(sc.hist);
         uint32_t *row_off = static_cast<uint32_t *>(sc.row_off);
         uint32_t *key_tot = static_cast<uint32_t *>(sc.key_tot);
@@ -746,9 +764,9 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         hipLaunchKernelGGL(scan_rows_kernel, dim3(kBucketsE / 64), dim3(64 * kScanWaves), 0, s, hist, G, kBucketsE,
                            row_off, key_tot);
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, key_tot, kBucketsE, key_base);
-        hipLaunchKernelGGL(order_scatter_kernel, dim3(G), dim3(kBlock), 0, s,
-                           static_cast<const uint8_t *>(sc.bucket), nr, rays_block, row_off, key_base,
-                           static_cast<uint32_t *>(sc.order));
+        hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, A.rays,
+                           static_cast<const uint8_t *>(sc.bucket), rays_block, row_off, key_base,
+                           static_cast<RayRec<R> *>(sc.ordered));
         hipLaunchKernelGGL((entries_kernel<R, RT, S>), dim3(G), dim3(kBlock), lds1, s, A);
         hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
                            static_cast<const uint32_t *>(sc.hist), G, g.n_keys, static_cast<uint32_t *>(sc.row_off),
