@@ -245,3 +245,88 @@ def test_autotune_cast_considers_sorted(ctx, monkeypatch, tmp_path):
     ctx.set_launch(accumulate=0)
     ctx.cast(ref, arrays)
     assert order_rel(ctx.read(chk), ctx.read(ref)) <= TOL_ORDER
+
+
+def tile_edge_rays():
+    """Rays along tile faces, edges and corners of a 32^3 unit mesh (tiles of 16^3), and entering from outside."""
+    c3 = 1 / np.sqrt(3.0)
+    s2 = np.sqrt(0.5)
+    rows = [
+        ((16.0, 16.0, 0.5), (0, 0, 1)), ((0.5, 16.0, 16.0), (1, 0, 0)), ((16.0, 0.5, 16.0), (0, 1, 0)),
+        ((0.0, 0.0, 0.0), (c3, c3, c3)), ((32.0, 32.0, 32.0), (-c3, -c3, -c3)), ((-1.0, 16.0, 16.0), (1, 0, 0)),
+        ((31.999, 0.5, 0.5), (-1, 0, 0)), ((16.0, 16.0, 16.0), (-c3, c3, -c3)), ((8.0, 16.0, 0.0), (s2, 0, s2)),
+        ((0.5, 0.5, 16.0), (s2, s2, 0)), ((16.0, 31.5, 15.999999), (0, -1, 0)), ((40.0, 16.0, 16.0), (-1, 0, 0)),
+    ]
+    o = np.array([r[0] for r in rows], np.float64)
+    u = np.array([r[1] for r in rows], np.float64)
+    n = len(rows)
+    rng = np.random.default_rng(3)
+    return W.Rays(o[:, 0].copy(), o[:, 1].copy(), o[:, 2].copy(), u[:, 0].copy(), u[:, 1].copy(), u[:, 2].copy(),
+                  W.log_uniform_energies(rng, n), np.full(n, 1.0))
+
+
+@pytest.mark.parametrize("prec", ["p64", "p32_t64"])
+def test_sorted_tile_boundary_rays(ctx, prec):
+    """Rays lying in tile faces, through tile edges and corners, starting on tile planes: same scores as the atomic path."""
+    mesh = W.slab_mesh(516, 32, 1.0, slab=5)
+    wl = W.config2_multimaterial(n_rays=0)
+    rays = tile_edge_rays()
+    say(f"case: sorted {prec}, tile-boundary rays, 32^3")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    dt = "f64" if prec == "p64" else "f32"
+    got, atom = cast_both(ctx, 0, prec, dev_arrays(rays, dt))
+    assert order_rel(got, atom) <= TOL_ORDER
+    if prec == "p64":
+        res = oracle.cast(mesh, wl.xs, rays)
+        g, _, n = rel_report(got, res, gate="all")
+        say(f"  sorted vs oracle {g:.3e} over {n} voxels")
+        assert n > 100 and g <= TOL_P64
+
+
+def test_sorted_long_thin_mesh(ctx):
+    """1 x 1 x 65536 mesh (4096 tiles, the key limit): rays along it cross every tile, one record per tile."""
+    xs = W.gen.make_xs([W.constant_sigma_table(0.3), W.constant_sigma_table(0.0)])
+    nz = 1 << 16
+    thin = W.Mesh(np.zeros(3), np.array([1.0, 1.0, 1e-3]), np.array([1, 1, nz], np.int32),
+                  (np.arange(nz) % 7 == 0).astype(np.uint8))
+    k = 16
+    rng = np.random.default_rng(2)
+    mu = np.where(np.arange(k) < k // 2, 1.0, rng.uniform(0.99999, 1.0, k))
+    s = np.sqrt(1 - mu * mu)
+    rays = W.Rays(rng.uniform(0, 1, k), rng.uniform(0, 1, k), rng.uniform(0, 1e-3, k), s, np.zeros(k), mu,
+                  np.ones(k), np.ones(k))
+    say("case: sorted p64, 1x1x65536 mesh, 16 long rays")
+    ctx.set_mesh(0, thin)
+    ctx.set_xs(xs)
+    got, atom = cast_both(ctx, 0, "p64", dev_arrays(rays, "f64"))
+    res = oracle.cast(thin, xs, rays)
+    assert res.segments > (k // 2) * 60_000
+    g, _, _ = rel_report(got, res, gate="all")
+    say(f"  sorted vs oracle {g:.3e}; vs atomic {order_rel(got, atom):.3e}")
+    assert g <= TOL_P64
+    assert order_rel(got, atom) <= TOL_ORDER
+
+
+def test_fp64_rays_into_fp32_forms_and_small_batch_switch(ctx):
+    """FP64 ray arrays into the FP32 forms (rounded on load) take the tile-split path like FP32 arrays;
+    accumulate 1 casts a batch below 131072 rays with atomics, with the same result."""
+    mesh = ragged_mesh(seed=517)
+    wl = W.config2_multimaterial(n_rays=0)
+    rays = W.rays_in_box(518, mesh, 150_000)
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    say("case: sorted, FP64 rays into p32_t64 / p32_d64; small-batch switch")
+    for prec in ("p32_t64", "p32_d64"):
+        a64, atom = cast_both(ctx, 0, prec, dev_arrays(rays, "f64"))
+        a32, _ = cast_both(ctx, 0, prec, dev_arrays(rays, "f32"))
+        assert order_rel(a64, atom) <= TOL_ORDER
+        assert order_rel(a64, a32) <= TOL_ORDER
+    small = rays.take(slice(0, 5000))
+    t1 = ctx.create_tally(0, "p64")
+    t2 = ctx.create_tally(0, "p64")
+    ctx.set_launch(accumulate=1)
+    ctx.cast(t1, dev_arrays(small, "f64"))
+    ctx.set_launch(accumulate=2)
+    ctx.cast(t2, dev_arrays(small, "f64"))
+    assert order_rel(ctx.read(t1), ctx.read(t2)) <= TOL_ORDER
