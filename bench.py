@@ -195,8 +195,10 @@ def bench_batched(steps: int) -> dict:
     """Batched form: 2000 lognormal-sized batches (median 2e4 rays, 1e3..1e6) on 64^3..200^3 meshes.
 
     One step = every batch once, cast into the tally of its mesh (p32_t64).
-    Timed both as ONE vrc_cast_batches call (persistent kernel, hipGraph,
-    autotuned shape) and as one vrc_cast_rays launch per batch.
+    Timed both as ONE vrc_cast_batches call (autotuned: the persistent kernel
+    in a hipGraph, or the tile-split accumulation per tally) and as one
+    vrc_cast_rays launch per batch; the other batched accumulation is timed
+    too, for comparison.
     """
     import torch
     import paper_1706_07476_amd as vrc
@@ -222,16 +224,25 @@ def bench_batched(steps: int) -> dict:
     shape, tune_ms = ctx.autotune_batched(items[:200], repeats=2)
     log(f"bench: batched shape {shape} ({tune_ms:.3f} ms on the first 200 batches)")
     arr = vrc.make_batches(items)
-    for _ in range(2):
-        vrc.vrc_cast_batches(ctx.handle, arr, len(items), stream)
-    torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-    ev[0].record(stream)
-    for k in range(steps):
-        vrc.vrc_cast_batches(ctx.handle, arr, len(items), stream)
-        ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    per_b = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+
+    def time_calls(n_steps):
+        for _ in range(2):
+            vrc.vrc_cast_batches(ctx.handle, arr, len(items), stream)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_steps + 1)]
+        ev[0].record(stream)
+        for k in range(n_steps):
+            vrc.vrc_cast_batches(ctx.handle, arr, len(items), stream)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(n_steps)])
+
+    per_b = time_calls(steps)
+    # the other accumulation of the batched form, for comparison
+    other = dict(shape, split=1 - shape["split"])
+    ctx.set_batched_launch(**other)
+    other_ms = float(np.mean(time_calls(max(1, steps // 2))))
+    ctx.set_batched_launch(**shape)
     plain_batches = [vrc.make_batch(a) for a in batches]
     for b, pb in enumerate(plain_batches):
         vrc.vrc_cast_rays(ctx.handle, tallies[mesh_of[b]], pb, stream)
@@ -253,6 +264,7 @@ def bench_batched(steps: int) -> dict:
             "batched_segments_per_s": S / (batched_ms / 1e3), "batched_ms_per_step": batched_ms,
             "plain_segments_per_s": S / (plain_ms / 1e3), "plain_ms_per_step": plain_ms,
             "speedup_vs_plain": plain_ms / batched_ms,
+            "other_split_setting": {"launch": other, "segments_per_s": S / (other_ms / 1e3), "ms_per_step": other_ms},
             "hbm_frac": (32 * R + SEG_BYTES * S) / (batched_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 

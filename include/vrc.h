@@ -202,11 +202,18 @@ typedef struct {
     const void *ox, *oy, *oz, *ux, *uy, *uz, *e, *w;
 } vrc_batch;
 
-/* Launch shape of the persistent batched kernel.  block, blocks_per_cu,
- * hash_in_lds, aggregate as in vrc_launch (blocks_per_cu >= 1 here: the grid
- * is n_CU * blocks_per_cu resident blocks); chunk: rays per work item (64 ..
+/* Launch shape of the batched cast.  block, blocks_per_cu, hash_in_lds,
+ * aggregate as in vrc_launch (blocks_per_cu >= 1 here: the grid is
+ * n_CU * blocks_per_cu resident blocks); chunk: rays per work item (64 ..
  * 1<<20); use_graph: replay a captured hipGraph (descriptor copy + kernel)
- * instead of launching directly.                                            */
+ * instead of launching directly; these six shape the persistent kernel.
+ * split: 0 = the persistent kernel (one atomic per segment); 1 = the
+ * tile-split accumulation of vrc_launch (rays ordered by length, split at
+ * tile entries, scored per tile in LDS), run once per tally over all of that
+ * tally's batches, when every tally of the call allows it (FP64-tally forms,
+ * at most 4096 (tile, bin) pairs), else the persistent kernel.  With split,
+ * a call waits on the host for the previous tile-split work of the context
+ * before it rewrites its batch table.                                      */
 typedef struct {
     int32_t block;
     int32_t blocks_per_cu;
@@ -214,6 +221,7 @@ typedef struct {
     int32_t hash_in_lds;
     int32_t aggregate;
     int32_t use_graph;
+    int32_t split;
 } vrc_batched_launch;
 
 /* Cast n_batches device-resident ray batches, each into its own tally, with

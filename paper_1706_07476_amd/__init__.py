@@ -67,7 +67,8 @@ class vrc_batch(ctypes.Structure):
 
 class vrc_batched_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("hash_in_lds", ctypes.c_int32), ("aggregate", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("hash_in_lds", ctypes.c_int32), ("aggregate", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("split", ctypes.c_int32)]
 
 
 class vrc_serve_config(ctypes.Structure):
@@ -385,12 +386,12 @@ def vrc_cast_batches(ctx: int, batches, n: int, stream=None) -> None:
     _check(load_library().vrc_cast_batches(ctx, n, batches, _stream(stream)))
 
 
-_BL_FIELDS = ("block", "blocks_per_cu", "chunk", "hash_in_lds", "aggregate", "use_graph")
+_BL_FIELDS = ("block", "blocks_per_cu", "chunk", "hash_in_lds", "aggregate", "use_graph", "split")
 
 
 def vrc_set_batched_launch(ctx: int, block=256, blocks_per_cu=8, chunk=1024, hash_in_lds=1, aggregate=0,
-                           use_graph=1) -> None:
-    l = vrc_batched_launch(block, blocks_per_cu, chunk, hash_in_lds, aggregate, use_graph)
+                           use_graph=1, split=0) -> None:
+    l = vrc_batched_launch(block, blocks_per_cu, chunk, hash_in_lds, aggregate, use_graph, split)
     _check(load_library().vrc_set_batched_launch(ctx, ctypes.byref(l)))
 
 

@@ -256,6 +256,8 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         free_dev(sc.key_tot);
         free_dev(sc.key_base);
         free_dev(sc.ordered);
+        free_dev(sc.d_refs);
+        if (sc.h_refs) (void)hipHostFree(sc.h_refs);
         free_dev(sc.bucket);
         if (sc.done) (void)hipEventDestroy(sc.done);
     }
@@ -672,8 +674,8 @@ vrc_status vrc_set_batched_launch(vrc_ctx *ctx, const vrc_batched_launch *l)
     if (l->blocks_per_cu < 1 || l->blocks_per_cu > 64) return set_error(VRC_ERR_INVALID, "blocks_per_cu in 1..64");
     if (l->chunk < 64 || l->chunk > (1 << 20)) return set_error(VRC_ERR_INVALID, "chunk in 64..2^20");
     if ((l->hash_in_lds != 0 && l->hash_in_lds != 1) || (l->aggregate != 0 && l->aggregate != 1) ||
-        (l->use_graph != 0 && l->use_graph != 1))
-        return set_error(VRC_ERR_INVALID, "hash_in_lds, aggregate and use_graph are 0 or 1");
+        (l->use_graph != 0 && l->use_graph != 1) || (l->split != 0 && l->split != 1))
+        return set_error(VRC_ERR_INVALID, "hash_in_lds, aggregate, use_graph and split are 0 or 1");
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->batched.block = l->block;
     ctx->batched.blocks_per_cu = l->blocks_per_cu;
@@ -681,6 +683,7 @@ vrc_status vrc_set_batched_launch(vrc_ctx *ctx, const vrc_batched_launch *l)
     ctx->batched.hash_in_lds = l->hash_in_lds;
     ctx->batched.aggregate = l->aggregate;
     ctx->batched.use_graph = l->use_graph;
+    ctx->batched.split = l->split;
     return VRC_OK;
 }
 
@@ -694,6 +697,7 @@ vrc_status vrc_get_batched_launch(vrc_ctx *ctx, vrc_batched_launch *l)
     l->hash_in_lds = ctx->batched.hash_in_lds;
     l->aggregate = ctx->batched.aggregate;
     l->use_graph = ctx->batched.use_graph;
+    l->split = ctx->batched.split;
     return VRC_OK;
 }
 
@@ -701,6 +705,64 @@ vrc_status vrc_get_batched_launch(vrc_ctx *ctx, vrc_batched_launch *l)
 // stream s (replaying the slot's captured graph when shape.use_graph).
 // The slot's event marks when its buffers may be written again.
 }  // extern "C"
+
+// The batched cast with the tile-split accumulation: the batches of each
+// tally go through one tile-split pipeline, reading their rays through a
+// device table of the tally's batches.
+vrc_status vrc::run_split_batches(vrc_ctx *ctx, const std::vector<int> &ids,
+                                  const std::map<int, std::vector<int>> &groups, const vrc_batch *batches, bool fp64,
+                                  hipStream_t s)
+{
+    SortScratch &sc = ctx->sort_scratch;
+    size_t n_refs = 0;
+    for (int id : ids) n_refs += groups.at(id).size();
+    const size_t bytes = sizeof(BatchRef) * n_refs;
+    // the previous call's table may still be in use: wait for it before rewriting
+    if (sc.busy) VRC_HIP(ctx, hipEventSynchronize(sc.done));
+    if (sc.refs_cap < bytes) {
+        VRC_HIP(ctx, hipDeviceSynchronize());
+        if (sc.h_refs) (void)hipHostFree(sc.h_refs);
+        if (sc.d_refs) (void)hipFree(sc.d_refs);
+        sc.h_refs = sc.d_refs = nullptr;
+        sc.refs_cap = 0;
+        if (hipHostMalloc(&sc.h_refs, bytes, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&sc.d_refs, bytes) != hipSuccess) {
+            if (sc.h_refs) (void)hipHostFree(sc.h_refs);
+            if (sc.d_refs) (void)hipFree(sc.d_refs);
+            sc.h_refs = sc.d_refs = nullptr;
+            return set_error(VRC_ERR_NOMEM, "batch table of the tile-split batched cast");
+        }
+        sc.refs_cap = bytes;
+    }
+    BatchRef *h = static_cast<BatchRef *>(sc.h_refs);
+    std::vector<std::pair<size_t, int64_t>> spans;  // (first ref, rays) per tally
+    size_t k = 0;
+    for (int id : ids) {
+        const size_t first = k;
+        int64_t begin = 0;
+        for (int i : groups.at(id)) {
+            const vrc_batch &b = batches[i];
+            const void *src[8] = {b.ox, b.oy, b.oz, b.ux, b.uy, b.uz, b.e, b.w};
+            for (int q = 0; q < 8; ++q) h[k].ray[q] = src[q];
+            h[k].begin = begin;
+            begin += b.n;
+            ++k;
+        }
+        spans.emplace_back(first, begin);
+    }
+    if (sc.busy && sc.stream != s) VRC_HIP(ctx, hipStreamWaitEvent(s, sc.done, 0));
+    VRC_HIP(ctx, hipMemcpyAsync(sc.d_refs, sc.h_refs, bytes, hipMemcpyHostToDevice, s));
+    const BatchRef *d = static_cast<const BatchRef *>(sc.d_refs);
+    for (size_t g = 0; g < ids.size(); ++g) {
+        TallyHost *t = get_tally(ctx, ids[g]);
+        const size_t nr = groups.at(ids[g]).size();
+        hipError_t e = launch_cast_sorted_batches(*ctx, *t, ctx->meshes[t->mesh_id], d + spans[g].first,
+                                                  static_cast<int>(nr), spans[g].second, fp64, true, s);
+        if (e == hipErrorOutOfMemory) return set_error(VRC_ERR_NOMEM, "scratch of the sorted accumulation");
+        if (e != hipSuccess) return device_error(ctx, e, "tile-split batched cast");
+    }
+    return VRC_OK;
+}
 
 vrc_status vrc::run_batched(vrc_ctx *ctx, BatchedSlot &bs, const BatchedShape &shape, vrc_precision pr, bool fp64,
                             const std::vector<BatchDescDev> &desc, int64_t items, hipStream_t s)
@@ -815,6 +877,26 @@ vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batche
     if (desc.empty()) return VRC_OK;
     if (desc.size() > (size_t(1) << 30)) return set_error(VRC_ERR_INVALID, "too many batches");
     (void)hipSetDevice(ctx->device);
+    if (shape.split) {
+        // tile-split accumulation, one pipeline per tally, if every tally allows it
+        std::vector<int> ids;  // tallies in order of first use
+        std::map<int, std::vector<int>> groups;
+        bool ok = true;
+        for (int i = 0; i < n_batches && ok; ++i) {
+            const vrc_batch &b = batches[i];
+            if (b.n == 0) continue;
+            auto it = groups.find(b.tally_id);
+            if (it == groups.end()) {
+                TallyHost *t = get_tally(ctx, b.tally_id);
+                ok = sorted_eligible(*ctx, *t, ctx->meshes[t->mesh_id]);
+                ids.push_back(b.tally_id);
+                it = groups.emplace(b.tally_id, std::vector<int>()).first;
+            }
+            it->second.push_back(i);
+        }
+        if (ok)
+            return run_split_batches(ctx, ids, groups, batches, fp64 != 0, static_cast<hipStream_t>(hip_stream));
+    }
     BatchedSlot &bs = ctx->bslot[ctx->bslot_next];
     ctx->bslot_next ^= 1;
     return run_batched(ctx, bs, shape, static_cast<vrc_precision>(prec), fp64 != 0, desc, items,

@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/vrc.h"
@@ -93,6 +94,9 @@ struct SortScratch {
     hipEvent_t done = nullptr;   // after the last kernel that used the scratch
     hipStream_t stream = nullptr;
     bool busy = false;
+    // batch tables of tile-split batched casts: pinned host copy, device copy
+    void *h_refs = nullptr, *d_refs = nullptr;
+    size_t refs_cap = 0;  // bytes of each
 };
 
 // One ray batch of a batched call, as the persistent kernel reads it.
@@ -121,10 +125,12 @@ struct BatchedShape {
     int hash_in_lds = 1;
     int aggregate = 0;
     int use_graph = 1;
+    int split = 0;  // 1: tile-split accumulation per tally instead of the persistent kernel
     bool operator==(const BatchedShape &o) const
     {
         return block == o.block && blocks_per_cu == o.blocks_per_cu && chunk == o.chunk &&
-               hash_in_lds == o.hash_in_lds && aggregate == o.aggregate && use_graph == o.use_graph;
+               hash_in_lds == o.hash_in_lds && aggregate == o.aggregate && use_graph == o.use_graph &&
+               split == o.split;
     }
 };
 
@@ -243,6 +249,8 @@ vrc_status check_cast_ready(vrc_ctx *ctx, const TallyHost *t);
 // Upload a descriptor table through slot bs and run the persistent kernel.
 vrc_status run_batched(vrc_ctx *ctx, BatchedSlot &bs, const BatchedShape &shape, vrc_precision prec, bool fp64,
                        const std::vector<BatchDescDev> &desc, int64_t items, hipStream_t s);
+vrc_status run_split_batches(vrc_ctx *ctx, const std::vector<int> &ids, const std::map<int, std::vector<int>> &groups,
+                             const vrc_batch *batches, bool fp64, hipStream_t s);
 
 // Cross-section index (vrc_xs.cpp) -------------------------------------------
 // Builds the union grid, per-material values on it and the log2-energy hash.
@@ -257,10 +265,21 @@ hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision pre
 hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m,
                         const RaysP &rays, bool rays_fp64, const TraceP &tr, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// One batch of a tile-split batched cast: its rays are numbered after those
+// of the batches before it (begin = number of its first ray).
+struct BatchRef {
+    const void *ray[8];
+    int64_t begin;
+};
+
 // Tile-sorted accumulation (vrc_sorted.hip): usable for this tally and mesh?
 bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m);
 hipError_t launch_cast_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
                               bool rays_fp64, bool atomic_flush, hipStream_t s);
+// The same over several device batches (d_refs: device table of n_refs
+// batches holding n_rays rays in all), all cast into tally t.
+hipError_t launch_cast_sorted_batches(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const BatchRef *d_refs,
+                                      int n_refs, int64_t n_rays, bool rays_fp64, bool atomic_flush, hipStream_t s);
 // Adds the batch's total segment count to *total (device).
 hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
                               bool rays_fp64, unsigned long long *total, hipStream_t s);

@@ -195,22 +195,68 @@ constexpr int kBucketsE = 256;  // entries: estimated pieces (scaled to fit)
 constexpr int kBucketsT = 64;   // tiles: pieces inside one tile, at most 3 * 16 - 2
 constexpr int kMaxBlock = 1024;
 
+// Where the ordering pass reads its rays: one batch (pointers already at the
+// sub-launch's first ray), or several batches numbered one after the other
+// (the tile-split form of the batched cast).
+struct RaySrc {
+    RaysP rays;
+    const BatchRef *refs;  // nullptr: one batch
+    int n_refs;
+    int64_t first;  // several batches: number of the sub-launch's first ray
+};
+
+template <typename R, typename RT>
+__device__ __forceinline__ void load_ray(const RaySrc &S, int64_t r, R &ox, R &oy, R &oz, R &ux, R &uy, R &uz, R &e,
+                                         R &w)
+{
+    const void *p0 = S.rays.ox, *p1 = S.rays.oy, *p2 = S.rays.oz, *p3 = S.rays.ux;
+    const void *p4 = S.rays.uy, *p5 = S.rays.uz, *p6 = S.rays.e, *p7 = S.rays.w;
+    int64_t i = r;
+    if (S.refs != nullptr) {
+        const int64_t g = S.first + r;
+        int lo = 0, hi = S.n_refs;  // last batch whose first ray is <= g
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (S.refs[mid].begin <= g) lo = mid; else hi = mid;
+        }
+        const BatchRef &B = S.refs[lo];
+        p0 = B.ray[0];
+        p1 = B.ray[1];
+        p2 = B.ray[2];
+        p3 = B.ray[3];
+        p4 = B.ray[4];
+        p5 = B.ray[5];
+        p6 = B.ray[6];
+        p7 = B.ray[7];
+        i = g - B.begin;
+    }
+    ox = ld<R, RT>(p0, i);
+    oy = ld<R, RT>(p1, i);
+    oz = ld<R, RT>(p2, i);
+    ux = ld<R, RT>(p3, i);
+    uy = ld<R, RT>(p4, i);
+    uz = ld<R, RT>(p5, i);
+    e = ld<R, RT>(p6, i);
+    w = ld<R, RT>(p7, i);
+}
+
 // Ordering of the rays by estimated length, longest first (a counting sort
 // over the whole batch, through the same block-row scans as the records):
 // order_hist counts each block's rays per length bucket, order_scatter
 // writes each ray, as one record, to its place.
 template <typename R, typename RT>
-__global__ void __launch_bounds__(256) order_hist_kernel(MeshP<R> M, RaysP rays, int64_t rays_per_block, int shift,
-                                                         uint8_t *bucket, uint32_t *hist)
+__global__ void __launch_bounds__(256) order_hist_kernel(MeshP<R> M, RaySrc src, int64_t n, int64_t rays_per_block,
+                                                         int shift, uint8_t *bucket, uint32_t *hist)
 {
     __shared__ uint32_t s_hist[kBucketsE];
     for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) s_hist[k] = 0u;
     __syncthreads();
     const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
-    const int64_t last = first + rays_per_block < rays.n ? first + rays_per_block : rays.n;
+    const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
     for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) {
-        const int est = ray_pieces_estimate(M, ld<R, RT>(rays.ox, r), ld<R, RT>(rays.oy, r), ld<R, RT>(rays.oz, r),
-                                            ld<R, RT>(rays.ux, r), ld<R, RT>(rays.uy, r), ld<R, RT>(rays.uz, r));
+        R ox, oy, oz, ux, uy, uz, e, w;
+        load_ray<R, RT>(src, r, ox, oy, oz, ux, uy, uz, e, w);
+        const int est = ray_pieces_estimate(M, ox, oy, oz, ux, uy, uz);
         const int bk = est >> shift;
         const int slot = kBucketsE - 1 - (bk < kBucketsE ? bk : kBucketsE - 1);  // longest first
         bucket[r] = static_cast<uint8_t>(slot);
@@ -230,26 +276,19 @@ struct __align__(16) RayRec {
 };
 
 template <typename R, typename RT>
-__global__ void __launch_bounds__(256) order_scatter_kernel(RaysP rays, const uint8_t *bucket, int64_t rays_per_block,
-                                                            const uint32_t *row_off, const uint32_t *key_base,
-                                                            RayRec<R> *ordered)
+__global__ void __launch_bounds__(256) order_scatter_kernel(RaySrc src, int64_t n, const uint8_t *bucket,
+                                                            int64_t rays_per_block, const uint32_t *row_off,
+                                                            const uint32_t *key_base, RayRec<R> *ordered)
 {
     __shared__ uint32_t s_base[kBucketsE];
     const uint32_t *row = row_off + static_cast<int64_t>(blockIdx.x) * kBucketsE;
     for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) s_base[k] = key_base[k] + row[k];
     __syncthreads();
     const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
-    const int64_t last = first + rays_per_block < rays.n ? first + rays_per_block : rays.n;
+    const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
     for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) {
         RayRec<R> rr;
-        rr.ox = ld<R, RT>(rays.ox, r);
-        rr.oy = ld<R, RT>(rays.oy, r);
-        rr.oz = ld<R, RT>(rays.oz, r);
-        rr.ux = ld<R, RT>(rays.ux, r);
-        rr.uy = ld<R, RT>(rays.uy, r);
-        rr.uz = ld<R, RT>(rays.uz, r);
-        rr.e = ld<R, RT>(rays.e, r);
-        rr.w = ld<R, RT>(rays.w, r);
+        load_ray<R, RT>(src, r, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz, rr.e, rr.w);
         ordered[atomicAdd(&s_base[bucket[r]], 1u)] = rr;
     }
 }
@@ -693,8 +732,8 @@ int tile_block(const vrc_ctx &ctx, size_t s_bytes)
 }
 
 template <typename R, typename RT, typename S>
-hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays, const SortGeom &g,
-                      bool atomic_flush, hipStream_t s)
+hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
+                      const SortGeom &g, bool atomic_flush, hipStream_t s)
 {
     SortScratch &sc = ctx.sort_scratch;
     const int G = ctx.n_cu * 8;
@@ -715,8 +754,8 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         hipError_t e = hipStreamWaitEvent(s, sc.done, 0);
         if (e != hipSuccess) return e;
     }
-    for (int64_t r0 = 0; r0 < rays.n; r0 += group_rays) {
-        const int64_t nr = rays.n - r0 < group_rays ? rays.n - r0 : group_rays;
+    for (int64_t r0 = 0; r0 < n_rays; r0 += group_rays) {
+        const int64_t nr = n_rays - r0 < group_rays ? n_rays - r0 : group_rays;
         const int64_t rays_block = (nr + G - 1) / G;
         const int64_t cap = rays_block * per_ray;
         const size_t rec_bytes = rec * static_cast<size_t>(cap) * G;
@@ -740,12 +779,19 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         EntryArgs<R> A;
         A.mesh = mesh;
         A.xs = xs_of<R>(ctx.xs);
-        const size_t el = sizeof(RT);
-        const void *base[8] = {rays.ox, rays.oy, rays.oz, rays.ux, rays.uy, rays.uz, rays.e, rays.w};
-        const void **dst[8] = {&A.rays.ox, &A.rays.oy, &A.rays.oz, &A.rays.ux, &A.rays.uy, &A.rays.uz, &A.rays.e,
-                               &A.rays.w};
-        for (int k = 0; k < 8; ++k) *dst[k] = static_cast<const char *>(base[k]) + el * static_cast<size_t>(r0);
-        A.rays.n = nr;
+        RaySrc sub = src;  // the sub-launch's rays
+        if (src.refs == nullptr) {
+            const size_t el = sizeof(RT);
+            const RaysP &rays = src.rays;
+            const void *base[8] = {rays.ox, rays.oy, rays.oz, rays.ux, rays.uy, rays.uz, rays.e, rays.w};
+            const void **dst[8] = {&sub.rays.ox, &sub.rays.oy, &sub.rays.oz, &sub.rays.ux, &sub.rays.uy,
+                                   &sub.rays.uz, &sub.rays.e, &sub.rays.w};
+            for (int k = 0; k < 8; ++k) *dst[k] = static_cast<const char *>(base[k]) + el * static_cast<size_t>(r0);
+        } else {
+            sub.first = src.first + r0;
+        }
+        sub.rays.n = nr;
+        A.rays = sub.rays;
         A.tally = TallyP{t.d_data, t.d_edges, t.nvox, t.n_bins};
         A.hash_in_lds = 0;
         A.g = g;
@@ -759,12 +805,12 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         uint32_t *row_off = static_cast<uint32_t *>(sc.row_off);
         uint32_t *key_tot = static_cast<uint32_t *>(sc.key_tot);
         uint32_t *key_base = static_cast<uint32_t *>(sc.key_base);
-        hipLaunchKernelGGL((order_hist_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, mesh, A.rays, rays_block, shift,
+        hipLaunchKernelGGL((order_hist_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, mesh, sub, nr, rays_block, shift,
                            static_cast<uint8_t *>(sc.bucket), hist);
         hipLaunchKernelGGL(scan_rows_kernel, dim3(kBucketsE / 64), dim3(64 * kScanWaves), 0, s, hist, G, kBucketsE,
                            row_off, key_tot);
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, key_tot, kBucketsE, key_base);
-        hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, A.rays,
+        hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, sub, nr,
                            static_cast<const uint8_t *>(sc.bucket), rays_block, row_off, key_base,
                            static_cast<RayRec<R> *>(sc.ordered));
         hipLaunchKernelGGL((entries_kernel<R, RT, S>), dim3(G), dim3(kBlock), lds1, s, A);
@@ -811,25 +857,46 @@ bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m)
     return kEntriesStatic + sigma_lds(ctx, sb, kBlock) <= kLdsMax && tile_block(ctx, sb) > 0;
 }
 
-hipError_t launch_cast_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays, bool rays_fp64,
-                              bool atomic_flush, hipStream_t s)
+namespace {
+
+hipError_t dispatch_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n,
+                           bool rays_fp64, bool atomic_flush, hipStream_t s)
 {
-    if (rays.n <= 0) return hipSuccess;
+    if (n <= 0) return hipSuccess;
     const SortGeom g = geometry(t, m);
     if (g.n_keys == 0) return hipErrorInvalidValue;
     switch (t.prec) {
     case VRC_P64:
-        return rays_fp64 ? run_sorted<double, double, double>(ctx, t, m, rays, g, atomic_flush, s)
-                         : run_sorted<double, float, double>(ctx, t, m, rays, g, atomic_flush, s);
+        return rays_fp64 ? run_sorted<double, double, double>(ctx, t, m, src, n, g, atomic_flush, s)
+                         : run_sorted<double, float, double>(ctx, t, m, src, n, g, atomic_flush, s);
     case VRC_P32_T64:
-        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, rays, g, atomic_flush, s)
-                         : run_sorted<float, float, float>(ctx, t, m, rays, g, atomic_flush, s);
+        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, src, n, g, atomic_flush, s)
+                         : run_sorted<float, float, float>(ctx, t, m, src, n, g, atomic_flush, s);
     case VRC_P32_D64:
-        return rays_fp64 ? run_sorted<float, double, double>(ctx, t, m, rays, g, atomic_flush, s)
-                         : run_sorted<float, float, double>(ctx, t, m, rays, g, atomic_flush, s);
+        return rays_fp64 ? run_sorted<float, double, double>(ctx, t, m, src, n, g, atomic_flush, s)
+                         : run_sorted<float, float, double>(ctx, t, m, src, n, g, atomic_flush, s);
     default:
         return hipErrorInvalidValue;
     }
+}
+
+}  // namespace
+
+hipError_t launch_cast_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays, bool rays_fp64,
+                              bool atomic_flush, hipStream_t s)
+{
+    const RaySrc src{rays, nullptr, 0, 0};
+    return dispatch_sorted(ctx, t, m, src, rays.n, rays_fp64, atomic_flush, s);
+}
+
+hipError_t launch_cast_sorted_batches(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const BatchRef *d_refs,
+                                      int n_refs, int64_t n_rays, bool rays_fp64, bool atomic_flush, hipStream_t s)
+{
+    RaySrc src{};
+    src.refs = d_refs;
+    src.n_refs = n_refs;
+    src.first = 0;
+    return dispatch_sorted(ctx, t, m, src, n_rays, rays_fp64, atomic_flush, s);
 }
 
 }  // namespace vrc

@@ -139,13 +139,14 @@ vrc_status vrc_autotune_batched(vrc_ctx *ctx, int n_batches, const vrc_batch *ba
         std::lock_guard<std::mutex> lk(g_cache_mu);
         load_cache_file();
         auto it = g_cache.find(key);
-        if (it != g_cache.end() && it->second.size() == 7) {
+        if (it != g_cache.end() && it->second.size() == 8) {
             const auto &v = it->second;
             vrc_batched_launch l{static_cast<int32_t>(v[0]), static_cast<int32_t>(v[1]), static_cast<int32_t>(v[2]),
-                                 static_cast<int32_t>(v[3]), static_cast<int32_t>(v[4]), static_cast<int32_t>(v[5])};
+                                 static_cast<int32_t>(v[3]), static_cast<int32_t>(v[4]), static_cast<int32_t>(v[5]),
+                                 static_cast<int32_t>(v[6])};
             if (vrc_status st = vrc_set_batched_launch(ctx, &l)) return st;
             *best = l;
-            if (best_ms) *best_ms = v[6];
+            if (best_ms) *best_ms = v[7];
             return VRC_OK;
         }
     }
@@ -167,33 +168,32 @@ vrc_status vrc_autotune_batched(vrc_ctx *ctx, int n_batches, const vrc_batch *ba
     vrc_status result = tm.ok ? VRC_OK : set_error(VRC_ERR_DEVICE, "timer set-up");
     double best_t = 1e300;
     vrc_batched_launch best_l = saved;
-    const int blocks[] = {128, 256, 512};
-    const int bpcs[] = {4, 8};
-    const int chunk_mul[] = {1, 4, 16};
-    for (int block : blocks) {
-        for (int bpc : bpcs) {
-            for (int cm : chunk_mul) {
-                for (int agg = 0; agg <= 1 && result == VRC_OK; ++agg) {
-                    vrc_batched_launch l{block, bpc, block * cm, 1, agg, 1};
-                    if ((result = vrc_set_batched_launch(ctx, &l)) != VRC_OK) break;
-                    if ((result = vrc_cast_batches(ctx, n_batches, bb.data(), tm.s)) != VRC_OK) break;  // warm-up
-                    if (hipEventRecord(tm.a, tm.s) != hipSuccess) { result = VRC_ERR_DEVICE; break; }
-                    for (int r = 0; r < repeats && result == VRC_OK; ++r)
-                        result = vrc_cast_batches(ctx, n_batches, bb.data(), tm.s);
-                    if (result != VRC_OK) break;
-                    float ms = 0.f;
-                    if (hipEventRecord(tm.b, tm.s) != hipSuccess || hipEventSynchronize(tm.b) != hipSuccess ||
-                        hipEventElapsedTime(&ms, tm.a, tm.b) != hipSuccess) {
-                        result = set_error(VRC_ERR_DEVICE, "timing a candidate");
-                        break;
-                    }
-                    const double t = ms / repeats;
-                    if (t < best_t) {
-                        best_t = t;
-                        best_l = l;
-                    }
-                }
-            }
+    // persistent-kernel shapes, then the tile-split accumulation (rays presorted by length)
+    std::vector<vrc_batched_launch> cands;
+    for (int block : {128, 256, 512})
+        for (int bpc : {4, 8})
+            for (int cm : {1, 4, 16})
+                for (int agg = 0; agg <= 1; ++agg)
+                    cands.push_back(vrc_batched_launch{block, bpc, block * cm, 1, agg, 1, 0});
+    cands.push_back(vrc_batched_launch{256, 8, 1024, 1, 0, 1, 1});
+    for (const vrc_batched_launch &l : cands) {
+        if (result != VRC_OK) break;
+        if ((result = vrc_set_batched_launch(ctx, &l)) != VRC_OK) break;
+        if ((result = vrc_cast_batches(ctx, n_batches, bb.data(), tm.s)) != VRC_OK) break;  // warm-up
+        if (hipEventRecord(tm.a, tm.s) != hipSuccess) { result = VRC_ERR_DEVICE; break; }
+        for (int r = 0; r < repeats && result == VRC_OK; ++r)
+            result = vrc_cast_batches(ctx, n_batches, bb.data(), tm.s);
+        if (result != VRC_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(tm.b, tm.s) != hipSuccess || hipEventSynchronize(tm.b) != hipSuccess ||
+            hipEventElapsedTime(&ms, tm.a, tm.b) != hipSuccess) {
+            result = set_error(VRC_ERR_DEVICE, "timing a candidate");
+            break;
+        }
+        const double t = ms / repeats;
+        if (t < best_t) {
+            best_t = t;
+            best_l = l;
         }
     }
     (void)hipStreamSynchronize(tm.s);
@@ -207,7 +207,7 @@ vrc_status vrc_autotune_batched(vrc_ctx *ctx, int n_batches, const vrc_batch *ba
     if (best_ms) *best_ms = best_t;
     std::lock_guard<std::mutex> lk(g_cache_mu);
     store(key, {double(best_l.block), double(best_l.blocks_per_cu), double(best_l.chunk), double(best_l.hash_in_lds),
-                double(best_l.aggregate), double(best_l.use_graph), best_t});
+                double(best_l.aggregate), double(best_l.use_graph), double(best_l.split), best_t});
     return VRC_OK;
 }
 

@@ -57,11 +57,14 @@ def setup_tallies(ctx, wl, prec):
     return meshes, tallies
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("prec", ["p64", "p32_t64", "p32_kahan", "p32_d64"])
-def test_batched_equals_plain_casts(ctx, prec):
+def test_batched_equals_plain_casts(ctx, prec, split):
+    """split = 1: the tile-split accumulation per tally (p32_kahan tallies fall back to the persistent kernel)."""
     wl = small_batched_workload()
-    say(f"case: batched vs plain, {prec}, {len(wl.extra['batches'])} batches on 4 meshes")
+    say(f"case: batched vs plain, {prec}, split {split}, {len(wl.extra['batches'])} batches on 4 meshes")
     meshes, t_b = setup_tallies(ctx, wl, prec)
+    ctx.set_batched_launch(split=split)
     t_p = [ctx.create_tally(i, prec) for i in range(len(meshes))]
     dt = "f64" if prec == "p64" else "f32"
     arrays = [dev_arrays(b, dt) for b in wl.extra["batches"]]
@@ -76,10 +79,12 @@ def test_batched_equals_plain_casts(ctx, prec):
         assert a.sum() > 0
 
 
-def test_batched_matches_oracle(ctx):
+@pytest.mark.parametrize("split", [0, 1])
+def test_batched_matches_oracle(ctx, split):
     wl = small_batched_workload(n_batches=80, median=400.0)
-    say("case: batched p64 vs oracle")
+    say(f"case: batched p64 vs oracle, split {split}")
     meshes, t_b = setup_tallies(ctx, wl, "p64")
+    ctx.set_batched_launch(split=split)
     mesh_of = wl.extra["mesh_of"]
     items = [(t_b[mesh_of[i]], dev_arrays(b, "f64")) for i, b in enumerate(wl.extra["batches"])]
     ctx.cast_batches(items)
@@ -94,14 +99,15 @@ def test_batched_matches_oracle(ctx):
         assert g <= 1e-12
 
 
-@pytest.mark.parametrize("use_graph", [1, 0])
-def test_graph_replays_with_eager_work_between(ctx, use_graph):
-    """Several replays of the captured graph, eager casts and reads in between; every replay checked."""
+@pytest.mark.parametrize("use_graph,split", [(1, 0), (0, 0), (1, 1)])
+def test_graph_replays_with_eager_work_between(ctx, use_graph, split):
+    """Several replays of the captured graph (or tile-split calls reusing their batch table), eager casts and
+    reads in between; every call checked."""
     wl = small_batched_workload(n_batches=60)
-    say(f"case: graph replays use_graph={use_graph}")
+    say(f"case: repeated batched calls use_graph={use_graph} split={split}")
     meshes, t_b = setup_tallies(ctx, wl, "p64")
     t_ref = [ctx.create_tally(i, "p64") for i in range(len(meshes))]
-    ctx.set_batched_launch(use_graph=use_graph)
+    ctx.set_batched_launch(use_graph=use_graph, split=split)
     mesh_of = wl.extra["mesh_of"]
     arrays = [dev_arrays(b, "f64") for b in wl.extra["batches"]]
     items = [(t_b[mesh_of[i]], a) for i, a in enumerate(arrays)]
