@@ -101,8 +101,9 @@ typedef struct {
  * 3 = as 2 with a plain read-add-write of each voxel instead of the atomic,
  * which requires that no other work writing the same tally (a cast on
  * another stream, a batched or serving launch, load/reset) overlaps the
- * cast: order such work with streams or events.  The tile-split modes apply
- * to the FP64-tally forms when the tally has at most 4096 (tile, energy bin)
+ * cast: order such work with streams or events (for a compensated FP32
+ * tally, 3 flushes like 2, with a compensated atomic update).  The
+ * tile-split modes apply when the tally has at most 4096 (tile, energy bin)
  * pairs and the cross-section columns fit in LDS; otherwise the atomic path
  * runs.  They use scratch device memory grown on demand (about n_rays *
  * (tiles along x + y + z) * 48..96 bytes, at most about 4 GB per sub-launch),
@@ -210,8 +211,8 @@ typedef struct {
  * split: 0 = the persistent kernel (one atomic per segment); 1 = the
  * tile-split accumulation of vrc_launch (rays ordered by length, split at
  * tile entries, scored per tile in LDS), run once per tally over all of that
- * tally's batches, when every tally of the call allows it (FP64-tally forms,
- * at most 4096 (tile, bin) pairs), else the persistent kernel.  With split,
+ * tally's batches, when every tally of the call allows it (at most 4096
+ * (tile, bin) pairs), else the persistent kernel.  With split,
  * a call waits on the host for the previous tile-split work of the context
  * before it rewrites its batch table.                                      */
 typedef struct {

@@ -12,19 +12,19 @@
 //      sort), as one record per ray.
 //   1. entries: every block takes a run of the ordered rays and every lane
 //      walks its ray accumulating only the optical depth (no exponentials,
-//      no tally); at each tile entry it
-//      appends a record {ray, entry voxel, entry parameter, optical depth so
-//      far} to its block's region (wavefront-compacted, coalesced stores),
-//      counting records per key in LDS.  A ray crosses at most
-//      n_tx + n_ty + n_tz - 2 tiles, which sizes the regions exactly.
+//      no tally); at each tile entry it appends a record {ray, entry voxel,
+//      entry parameter, optical depth so far} to its block's region
+//      (wavefront-compacted, coalesced stores), counting records per key in
+//      LDS.  A ray crosses at most n_tx + n_ty + n_tz - 2 tiles, which sizes
+//      the regions exactly.
 //   2. scan_rows / scan_keys: exclusive scans give every (block, key) pair
 //      its place in key-major order.
 //   3. partition: every block scatters its records to their key's run.
 //   4. tiles: one block per key orders the key's records by estimated
 //      length, resumes each ray at its tile entry, scores the pieces inside
-//      the tile into an FP64 tile in LDS, and
-//      adds the tile to the tally (one atomic per non-zero voxel, or a plain
-//      read-add-write: no two blocks share a tally element).
+//      the tile into an FP64 tile in LDS, and adds the tile to the tally:
+//      one atomic per non-zero voxel, a plain read-add-write (no two blocks
+//      share a tally element), or a compensated update of an FP32 pair.
 //
 // The score re-anchors its entering weight at every tile entry (vrc_device.h),
 // so resuming from (optical depth, entry voxel, entry parameter) reproduces
@@ -46,6 +46,13 @@ constexpr int kTileVoxels = kTileEdge * kTileEdge * kTileEdge;  // 4096
 constexpr int kLocalBits = 3 * kTileBits;                        // 12
 constexpr int kMaxKeys = 4096;
 constexpr uint32_t kFirst = 1u << 31;  // the record is the ray's first tile
+
+// How a finished tile goes into the tally.
+enum Flush {
+    kFlushAtomic = 0,  // FP64 atomic add per non-zero voxel
+    kFlushPlain = 1,   // FP64 read-add-write (no other writer of the tally may overlap the cast)
+    kFlushKahan = 2,   // compensated FP32 pair {sum, compensation}
+};
 
 // One tile entry of one ray.  code: kFirst | key << 12 | voxel within tile.
 template <typename R, typename S>
@@ -563,7 +570,7 @@ struct TileArgs {
     const void *sorted;
     const uint32_t *key_base;
     int64_t nvox;
-    double *tally;
+    void *tally;  // FP64, or FP32 {sum, compensation} pairs (kFlushKahan)
 };
 
 struct PutLds {
@@ -578,7 +585,7 @@ struct PutLds {
 // One block per key: the key's rays resumed at their tile entries and
 // scored into the tile in LDS, then the tile into the tally.
 // (FP32 scores: register budget for eight wavefronts per SIMD, two blocks of 1024)
-template <typename R, typename S, bool ATOMIC>
+template <typename R, typename S, int FLUSH>
 __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(TileArgs<R> A)
 {
     __shared__ double acc[kTileVoxels];
@@ -649,7 +656,6 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
         }
         __syncthreads();  // s_perm is rewritten by the next chunk
     }
-    double *out = A.tally + static_cast<int64_t>(bin) * A.nvox;
     for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) {
         const double v = acc[i];
         if (v == 0.0) continue;
@@ -657,11 +663,25 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
         const int y = ty * kTileEdge + ((i >> kTileBits) & (kTileEdge - 1));
         const int z = tz * kTileEdge + (i >> (2 * kTileBits));
         if (x >= nx || y >= ny || z >= nz) continue;
-        double *p = out + x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z);
-        if constexpr (ATOMIC)
-            unsafeAtomicAdd(p, v);
-        else
-            *p += v;
+        const int64_t idx = static_cast<int64_t>(bin) * A.nvox + x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z);
+        if constexpr (FLUSH == kFlushKahan) {
+            // v = hi + lo exactly to FP32 x FP32; hi goes into the sum with an atomic
+            // that returns the old sum, so the rounding error of the add made in
+            // memory is recovered (TwoSum) and joins lo in the compensation
+            float *p = static_cast<float *>(A.tally) + 2 * idx;
+            const float hi = static_cast<float>(v);
+            const float lo = static_cast<float>(v - static_cast<double>(hi));
+            const float old = unsafeAtomicAdd(p, hi);
+            const float sum = old + hi;
+            const float bv = sum - old;
+            const float av = sum - bv;
+            const float err = ((old - av) + (hi - bv)) + lo;
+            if (err != 0.f) unsafeAtomicAdd(p + 1, err);
+        } else if constexpr (FLUSH == kFlushAtomic) {
+            unsafeAtomicAdd(static_cast<double *>(A.tally) + idx, v);
+        } else {
+            static_cast<double *>(A.tally)[idx] += v;
+        }
     }
 }
 
@@ -733,7 +753,7 @@ int tile_block(const vrc_ctx &ctx, size_t s_bytes)
 
 template <typename R, typename RT, typename S>
 hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
-                      const SortGeom &g, bool atomic_flush, hipStream_t s)
+                      const SortGeom &g, int flush, hipStream_t s)
 {
     SortScratch &sc = ctx.sort_scratch;
     const int G = ctx.n_cu * 8;
@@ -831,11 +851,18 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         T.sorted = sc.sorted;
         T.key_base = static_cast<const uint32_t *>(sc.key_base);
         T.nvox = t.nvox;
-        T.tally = static_cast<double *>(t.d_data);
-        if (atomic_flush)
-            hipLaunchKernelGGL((tile_kernel<R, S, true>), dim3(g.n_keys), dim3(tb), lds2, s, T);
+        T.tally = t.d_data;
+        if constexpr (sizeof(S) == 4) {
+            if (flush == kFlushKahan) {
+                hipLaunchKernelGGL((tile_kernel<R, S, kFlushKahan>), dim3(g.n_keys), dim3(tb), lds2, s, T);
+                goto launched;
+            }
+        }
+        if (flush == kFlushAtomic)
+            hipLaunchKernelGGL((tile_kernel<R, S, kFlushAtomic>), dim3(g.n_keys), dim3(tb), lds2, s, T);
         else
-            hipLaunchKernelGGL((tile_kernel<R, S, false>), dim3(g.n_keys), dim3(tb), lds2, s, T);
+            hipLaunchKernelGGL((tile_kernel<R, S, kFlushPlain>), dim3(g.n_keys), dim3(tb), lds2, s, T);
+    launched:
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -850,10 +877,10 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
 
 bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m)
 {
-    if (t.prec == VRC_P32_KAHAN || ctx.sort_scratch.done == nullptr) return false;
+    if (ctx.sort_scratch.done == nullptr) return false;
     const SortGeom g = geometry(t, m);
     if (g.n_keys == 0) return false;
-    const size_t sb = t.prec == VRC_P32_T64 ? sizeof(float) : sizeof(double);
+    const size_t sb = (t.prec == VRC_P32_T64 || t.prec == VRC_P32_KAHAN) ? sizeof(float) : sizeof(double);
     return kEntriesStatic + sigma_lds(ctx, sb, kBlock) <= kLdsMax && tile_block(ctx, sb) > 0;
 }
 
@@ -865,16 +892,20 @@ hipError_t dispatch_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     if (n <= 0) return hipSuccess;
     const SortGeom g = geometry(t, m);
     if (g.n_keys == 0) return hipErrorInvalidValue;
+    const int flush = atomic_flush ? kFlushAtomic : kFlushPlain;
     switch (t.prec) {
     case VRC_P64:
-        return rays_fp64 ? run_sorted<double, double, double>(ctx, t, m, src, n, g, atomic_flush, s)
-                         : run_sorted<double, float, double>(ctx, t, m, src, n, g, atomic_flush, s);
+        return rays_fp64 ? run_sorted<double, double, double>(ctx, t, m, src, n, g, flush, s)
+                         : run_sorted<double, float, double>(ctx, t, m, src, n, g, flush, s);
     case VRC_P32_T64:
-        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, src, n, g, atomic_flush, s)
-                         : run_sorted<float, float, float>(ctx, t, m, src, n, g, atomic_flush, s);
+        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, src, n, g, flush, s)
+                         : run_sorted<float, float, float>(ctx, t, m, src, n, g, flush, s);
+    case VRC_P32_KAHAN:
+        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, src, n, g, kFlushKahan, s)
+                         : run_sorted<float, float, float>(ctx, t, m, src, n, g, kFlushKahan, s);
     case VRC_P32_D64:
-        return rays_fp64 ? run_sorted<float, double, double>(ctx, t, m, src, n, g, atomic_flush, s)
-                         : run_sorted<float, float, double>(ctx, t, m, src, n, g, atomic_flush, s);
+        return rays_fp64 ? run_sorted<float, double, double>(ctx, t, m, src, n, g, flush, s)
+                         : run_sorted<float, float, double>(ctx, t, m, src, n, g, flush, s);
     default:
         return hipErrorInvalidValue;
     }

@@ -60,7 +60,7 @@ def setup_tallies(ctx, wl, prec):
 @pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("prec", ["p64", "p32_t64", "p32_kahan", "p32_d64"])
 def test_batched_equals_plain_casts(ctx, prec, split):
-    """split = 1: the tile-split accumulation per tally (p32_kahan tallies fall back to the persistent kernel)."""
+    """split = 1: the tile-split accumulation per tally (p32_kahan: with the compensated flush)."""
     wl = small_batched_workload()
     say(f"case: batched vs plain, {prec}, split {split}, {len(wl.extra['batches'])} batches on 4 meshes")
     meshes, t_b = setup_tallies(ctx, wl, prec)

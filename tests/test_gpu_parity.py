@@ -208,8 +208,8 @@ def eps_phi_max(got, res, se_max=0.3):
     return float(eps[i])
 
 
-@pytest.mark.parametrize("prec,accumulate", [("p32_t64", 0), ("p32_t64", 1), ("p32_kahan", 0), ("p32_d64", 0),
-                                              ("p32_d64", 1)])
+@pytest.mark.parametrize("prec,accumulate", [("p32_t64", 0), ("p32_t64", 1), ("p32_kahan", 0), ("p32_kahan", 1),
+                                              ("p32_d64", 0), ("p32_d64", 1)])
 def test_tally_multimaterial_fp32_well_sampled(ctx, prec, accumulate):
     """FP32 forms on a well-sampled mesh (16^3 of the multimat tables, 1.6e6 rays).
 

@@ -93,7 +93,7 @@ def test_sorted_fp64_multibin_ragged_mesh(ctx, accumulate):
     assert o <= TOL_ORDER
 
 
-@pytest.mark.parametrize("prec", ["p32_t64", "p32_d64"])
+@pytest.mark.parametrize("prec", ["p32_t64", "p32_d64", "p32_kahan"])
 def test_sorted_fp32_forms(ctx, prec):
     mesh = W.slab_mesh(202, 16, 0.5, slab=4)
     wl = W.config2_multimaterial(n_rays=0)
@@ -109,7 +109,8 @@ def test_sorted_fp32_forms(ctx, prec):
     say(f"  sorted vs oracle gated max rel {g:.3e} over {n} ({a:.3e} all); sorted vs atomic {o:.3e}")
     assert n > 0.5 * mesh.n_voxels
     assert g <= TOL_P32
-    assert o <= TOL_ORDER
+    # a compensated FP32 pair holds the sum to about 2^-46; the order of the additions shows there
+    assert o <= (TOL_ORDER if prec != "p32_kahan" else 1e-9)
 
 
 def diagonal_rays(seed, mesh, n):
