@@ -259,6 +259,7 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         free_dev(sc.d_refs);
         if (sc.h_refs) (void)hipHostFree(sc.h_refs);
         free_dev(sc.bucket);
+        free_dev(sc.partial);
         if (sc.done) (void)hipEventDestroy(sc.done);
     }
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);

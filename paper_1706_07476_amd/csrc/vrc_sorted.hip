@@ -308,11 +308,10 @@ struct EntryArgs {
     TallyP tally;
     int hash_in_lds;
     SortGeom g;
-    void *records;     // G regions of cap records
+    void *records;     // one region of cap records per block
     int64_t cap;       // records per block region
-    uint32_t *counts;  // G
-    uint32_t *hist;    // G * n_keys
-    int64_t rays_per_block;
+    uint32_t *counts;  // per block
+    uint32_t *hist;    // blocks * n_keys
     const void *ordered;  // RayRec<R>: the rays by estimated length, longest first
 };
 
@@ -415,14 +414,23 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     S(*mysig)[2] = sig + threadIdx.x;
     Entry<R, S> *region = static_cast<Entry<R, S> *>(A.records) + static_cast<int64_t>(blockIdx.x) * A.cap;
     const int64_t n = A.rays.n;
-    const int64_t first = static_cast<int64_t>(blockIdx.x) * A.rays_per_block;
-    const int64_t last = first + A.rays_per_block < n ? first + A.rays_per_block : n;
+    // The length-ordered rays are dealt out in slices of 64 (one per
+    // wavefront, so the lanes of a wavefront walk rays of about the same
+    // length), in rounds of one slice per wavefront of the grid.  A round's
+    // slices go to wavefront 0 of every block, then wavefront 1, ..., so each
+    // block gets slices from all of the round's lengths, and every other round
+    // is dealt in reverse: the blocks get about the same amount of walking.
+    const int64_t per_round = static_cast<int64_t>(gridDim.x) * (bd >> 6);
+    const int64_t pos = static_cast<int64_t>(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
+    const int64_t slices = (n + 63) >> 6;
     EmitEntries<R, S> em{mysig, bd, S(0), S(0), 0u, false, R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0),
                          0, A.g, region, A.cap, &s_cursor, s_hist};
     Walker<R> wk;
     const MeshMaterials mats{A.mesh.mat};
     const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
-    for (int64_t j = first + threadIdx.x; j < last; j += bd) {
+    for (int64_t round = 0; round * per_round < slices; ++round) {
+        const int64_t j = ((round * per_round + ((round & 1) ? per_round - 1 - pos : pos)) << 6) + (threadIdx.x & 63);
+        if (j >= n) continue;
         const RayRec<R> rr = ordered[j];
         const R ox = rr.ox, oy = rr.oy, oz = rr.oz, ux = rr.ux, uy = rr.uy, uz = rr.uz, E = rr.e, wt = rr.w;
         const int bin = energy_bin(A.tally, static_cast<double>(E));
@@ -570,7 +578,9 @@ struct TileArgs {
     const void *sorted;
     const uint32_t *key_base;
     int64_t nvox;
-    void *tally;  // FP64, or FP32 {sum, compensation} pairs (kFlushKahan)
+    void *tally;      // FP64, or FP32 {sum, compensation} pairs (kFlushKahan)
+    double *partial;  // 2 tiles per block: keys the block shares with others
+    int n_blocks;     // blocks the records are dealt out to (the grid)
 };
 
 struct PutLds {
@@ -582,8 +592,71 @@ struct PutLds {
     }
 };
 
-// One block per key: the key's rays resumed at their tile entries and
-// scored into the tile in LDS, then the tile into the tally.
+// The key-major records are dealt out to the blocks of the tiles pass in
+// equal contiguous ranges (a key's records may span several blocks, a block's
+// range several keys), so every block has the same number of tile entries to
+// walk however the records fall on the keys.
+struct TileDeal {
+    uint32_t total;  // records
+    uint32_t per;    // records per block
+    __device__ __forceinline__ TileDeal(const uint32_t *key_base, int n_keys, int n_blocks)
+    {
+        total = key_base[n_keys];
+        const uint32_t nb = total < static_cast<uint32_t>(n_blocks) ? total : static_cast<uint32_t>(n_blocks);
+        per = nb == 0u ? 0u : (total + nb - 1u) / nb;
+    }
+    // A key's records [kb, ke) (non-empty) lie in blocks kb / per .. (ke - 1) / per.
+    __device__ __forceinline__ uint32_t first_block(uint32_t kb) const { return kb / per; }
+    __device__ __forceinline__ uint32_t last_block(uint32_t ke) const { return (ke - 1u) / per; }
+    // Partial-tile slot of a key shared by block b: 2b if the key began before
+    // the block's range (at most one such key per block), 2b + 1 if it begins
+    // inside it and runs past its end (at most one too).
+    __device__ __forceinline__ uint32_t slot(uint32_t b, uint32_t kb) const
+    {
+        return 2u * b + (kb > b * per ? 1u : 0u);
+    }
+};
+
+// One tile sum v into the tally element idx.
+template <int FLUSH>
+__device__ __forceinline__ void flush_voxel(void *tally, int64_t idx, double v)
+{
+    if constexpr (FLUSH == kFlushKahan) {
+        // v = hi + lo exactly to FP32 x FP32; hi goes into the sum with an atomic
+        // that returns the old sum, so the rounding error of the add made in
+        // memory is recovered (TwoSum) and joins lo in the compensation
+        float *p = static_cast<float *>(tally) + 2 * idx;
+        const float hi = static_cast<float>(v);
+        const float lo = static_cast<float>(v - static_cast<double>(hi));
+        const float old = unsafeAtomicAdd(p, hi);
+        const float sum = old + hi;
+        const float bv = sum - old;
+        const float av = sum - bv;
+        const float err = ((old - av) + (hi - bv)) + lo;
+        if (err != 0.f) unsafeAtomicAdd(p + 1, err);
+    } else if constexpr (FLUSH == kFlushAtomic) {
+        unsafeAtomicAdd(static_cast<double *>(tally) + idx, v);
+    } else {
+        static_cast<double *>(tally)[idx] += v;
+    }
+}
+
+// Tally element of voxel i of the key's tile; -1 beyond the mesh.
+__device__ __forceinline__ int64_t tile_element(int i, int bin, int tx, int ty, int tz, int nx, int ny, int nz,
+                                                int64_t nvox)
+{
+    const int x = tx * kTileEdge + (i & (kTileEdge - 1));
+    const int y = ty * kTileEdge + ((i >> kTileBits) & (kTileEdge - 1));
+    const int z = tz * kTileEdge + (i >> (2 * kTileBits));
+    if (x >= nx || y >= ny || z >= nz) return -1;
+    return static_cast<int64_t>(bin) * nvox + x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z);
+}
+
+// Each block walks its range of the key-major records, key by key: the key's
+// tile and materials in LDS, its records resumed at their tile entries and
+// scored into the tile, then the tile into the tally if the block holds all
+// of the key's records, else into the block's partial-tile slot for
+// tile_reduce_kernel.
 // (FP32 scores: register budget for eight wavefronts per SIMD, two blocks of 1024)
 template <typename R, typename S, int FLUSH>
 __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(TileArgs<R> A)
@@ -592,96 +665,130 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
     __shared__ uint8_t s_mat[kTileVoxels];
     __shared__ uint32_t s_cnt[kBucketsT];
     __shared__ uint16_t s_perm[kMaxBlock];
-    const int key = blockIdx.x;
-    const uint32_t lo = A.key_base[key], hi = A.key_base[key + 1];
-    if (lo == hi) return;
-    const int bin = key / A.g.n_tiles;
-    const int tile = key - bin * A.g.n_tiles;
-    const int tx = tile % A.g.ntx;
-    const int ty = (tile / A.g.ntx) % A.g.nty;
-    const int tz = tile / (A.g.ntx * A.g.nty);
-    const int nx = A.mesh.n[0], ny = A.mesh.n[1], nz = A.mesh.n[2];
-    // the tile's materials (voxels beyond the mesh are never read)
-    for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) {
-        acc[i] = 0.0;
-        const int x = tx * kTileEdge + (i & (kTileEdge - 1));
-        const int y = ty * kTileEdge + ((i >> kTileBits) & (kTileEdge - 1));
-        const int z = tz * kTileEdge + (i >> (2 * kTileBits));
-        s_mat[i] = (x < nx && y < ny && z < nz)
-                       ? A.mesh.mat[x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z)]
-                       : static_cast<uint8_t>(0);
+    const int n_keys = A.g.n_keys;
+    const TileDeal deal(A.key_base, n_keys, A.n_blocks);
+    const uint32_t b = blockIdx.x;
+    if (deal.per == 0u) return;
+    const uint32_t r0 = b * deal.per;
+    if (r0 >= deal.total) return;
+    const uint32_t r1 = deal.total - r0 < deal.per ? deal.total : r0 + deal.per;
+    // the key holding record r0: key_base[key] <= r0 < key_base[key + 1]
+    int key;
+    {
+        int lo = 0, hi = n_keys;  // key_base[lo] <= r0 < key_base[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (A.key_base[mid] <= r0) lo = mid; else hi = mid;
+        }
+        key = lo;
     }
+    const int nx = A.mesh.n[0], ny = A.mesh.n[1], nz = A.mesh.n[2];
     const int32_t *hash;
     S(*sig)[2];
     stage_lds(A.xs, A.hash_in_lds, hash, sig);
-    __syncthreads();
     const int bd = blockDim.x;
     S(*mysig)[2] = sig + threadIdx.x;
-    const TileMaterials mats{s_mat, tx * kTileEdge, ty * kTileEdge, tz * kTileEdge};
     const Entry<R, S> *rec = static_cast<const Entry<R, S> *>(A.sorted);
     PutLds put{acc};
     Scorer<S, PutLds> sc(mysig, bd, S(0), put);
     Walker<R> wk;
-    const uint32_t tg = tile_tag(tx, ty, tz);
     constexpr int PER = 1;  // the records of one block-sized chunk are ordered together
-    for (uint32_t c0 = lo; c0 < hi; c0 += bd) {
-        const int m = static_cast<int>(hi - c0 < static_cast<uint32_t>(bd) ? hi - c0 : static_cast<uint32_t>(bd));
-        int bucket[PER];
+    for (; key < n_keys; ++key) {
+        const uint32_t kb = A.key_base[key], ke = A.key_base[key + 1];
+        if (kb >= r1) break;
+        const uint32_t lo = kb > r0 ? kb : r0;
+        const uint32_t hi = ke < r1 ? ke : r1;
+        if (lo >= hi) continue;
+        const int bin = key / A.g.n_tiles;
+        const int tile = key - bin * A.g.n_tiles;
+        const int tx = tile % A.g.ntx;
+        const int ty = (tile / A.g.ntx) % A.g.nty;
+        const int tz = tile / (A.g.ntx * A.g.nty);
+        __syncthreads();  // the previous key's tile has been flushed
+        // the tile's materials (voxels beyond the mesh are never read)
+        for (int i = threadIdx.x; i < kTileVoxels; i += bd) {
+            acc[i] = 0.0;
+            const int x = tx * kTileEdge + (i & (kTileEdge - 1));
+            const int y = ty * kTileEdge + ((i >> kTileBits) & (kTileEdge - 1));
+            const int z = tz * kTileEdge + (i >> (2 * kTileBits));
+            s_mat[i] = (x < nx && y < ny && z < nz)
+                           ? A.mesh.mat[x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z)]
+                           : static_cast<uint8_t>(0);
+        }
+        __syncthreads();
+        const TileMaterials mats{s_mat, tx * kTileEdge, ty * kTileEdge, tz * kTileEdge};
+        const uint32_t tg = tile_tag(tx, ty, tz);
+        for (uint32_t c0 = lo; c0 < hi; c0 += bd) {
+            const int m = static_cast<int>(hi - c0 < static_cast<uint32_t>(bd) ? hi - c0 : static_cast<uint32_t>(bd));
+            int bucket[PER];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            bucket[j] = 0;
-            const int idx = j * bd + static_cast<int>(threadIdx.x);
-            if (idx < m) {
-                const Entry<R, S> &r = rec[c0 + idx];
+            for (int j = 0; j < PER; ++j) {
+                bucket[j] = 0;
+                const int idx = j * bd + static_cast<int>(threadIdx.x);
+                if (idx < m) {
+                    const Entry<R, S> &r = rec[c0 + idx];
+                    const uint32_t loc = r.code & static_cast<uint32_t>(kTileVoxels - 1);
+                    const int est = tile_pieces_estimate(
+                        A.mesh, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz,
+                        tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1)),
+                        ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1)),
+                        tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits)));
+                    bucket[j] = est < kBucketsT ? est : kBucketsT - 1;
+                }
+            }
+            sort_desc(bucket, m, kBucketsT, s_cnt, s_perm);
+            for (int j = threadIdx.x; j < m; j += bd) {
+                const Entry<R, S> r = rec[c0 + s_perm[j]];
+                xs_lookup(A.xs, hash, r.e, mysig, bd);
                 const uint32_t loc = r.code & static_cast<uint32_t>(kTileVoxels - 1);
-                const int est = tile_pieces_estimate(A.mesh, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz,
-                                                     tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1)),
-                                                     ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1)),
-                                                     tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits)));
-                bucket[j] = est < kBucketsT ? est : kBucketsT - 1;
+                const int ci = tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1));
+                const int cj = ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1));
+                const int ck = tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits));
+                sc.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, tg, (r.code & kFirst) != 0u);
+                wk.resume_tile(A.mesh, mats, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz, ci, cj, ck, r.t0);
+                while (wk.step(A.mesh, sc, mats)) {
+                }
             }
+            __syncthreads();  // s_perm is rewritten by the next chunk; acc is complete after the last
         }
-        sort_desc(bucket, m, kBucketsT, s_cnt, s_perm);
-        for (int j = threadIdx.x; j < m; j += bd) {
-            const Entry<R, S> r = rec[c0 + s_perm[j]];
-            xs_lookup(A.xs, hash, r.e, mysig, bd);
-            const uint32_t loc = r.code & static_cast<uint32_t>(kTileVoxels - 1);
-            const int ci = tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1));
-            const int cj = ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1));
-            const int ck = tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits));
-            sc.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, tg, (r.code & kFirst) != 0u);
-            wk.resume_tile(A.mesh, mats, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz, ci, cj, ck, r.t0);
-            while (wk.step(A.mesh, sc, mats)) {
+        if (deal.first_block(kb) == deal.last_block(ke)) {
+            for (int i = threadIdx.x; i < kTileVoxels; i += bd) {
+                const double v = acc[i];
+                if (v == 0.0) continue;
+                const int64_t idx = tile_element(i, bin, tx, ty, tz, nx, ny, nz, A.nvox);
+                if (idx >= 0) flush_voxel<FLUSH>(A.tally, idx, v);
             }
-        }
-        __syncthreads();  // s_perm is rewritten by the next chunk
-    }
-    for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) {
-        const double v = acc[i];
-        if (v == 0.0) continue;
-        const int x = tx * kTileEdge + (i & (kTileEdge - 1));
-        const int y = ty * kTileEdge + ((i >> kTileBits) & (kTileEdge - 1));
-        const int z = tz * kTileEdge + (i >> (2 * kTileBits));
-        if (x >= nx || y >= ny || z >= nz) continue;
-        const int64_t idx = static_cast<int64_t>(bin) * A.nvox + x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z);
-        if constexpr (FLUSH == kFlushKahan) {
-            // v = hi + lo exactly to FP32 x FP32; hi goes into the sum with an atomic
-            // that returns the old sum, so the rounding error of the add made in
-            // memory is recovered (TwoSum) and joins lo in the compensation
-            float *p = static_cast<float *>(A.tally) + 2 * idx;
-            const float hi = static_cast<float>(v);
-            const float lo = static_cast<float>(v - static_cast<double>(hi));
-            const float old = unsafeAtomicAdd(p, hi);
-            const float sum = old + hi;
-            const float bv = sum - old;
-            const float av = sum - bv;
-            const float err = ((old - av) + (hi - bv)) + lo;
-            if (err != 0.f) unsafeAtomicAdd(p + 1, err);
-        } else if constexpr (FLUSH == kFlushAtomic) {
-            unsafeAtomicAdd(static_cast<double *>(A.tally) + idx, v);
         } else {
-            static_cast<double *>(A.tally)[idx] += v;
+            double *part = A.partial + static_cast<int64_t>(deal.slot(b, kb)) * kTileVoxels;
+            for (int i = threadIdx.x; i < kTileVoxels; i += bd) part[i] = acc[i];
         }
+    }
+}
+
+// Keys whose records span two or more blocks: the blocks' partial tiles are
+// summed in block order and the sum goes into the tally.  One block per key.
+template <int FLUSH>
+__global__ void __launch_bounds__(256) tile_reduce_kernel(const uint32_t *key_base, SortGeom g, int n_blocks,
+                                                          const double *partial, int nx, int ny, int nz,
+                                                          int64_t nvox, void *tally)
+{
+    const int key = blockIdx.x;
+    const uint32_t kb = key_base[key], ke = key_base[key + 1];
+    if (kb == ke) return;
+    const TileDeal deal(key_base, g.n_keys, n_blocks);
+    const uint32_t b0 = deal.first_block(kb), b1 = deal.last_block(ke);
+    if (b0 == b1) return;
+    const int bin = key / g.n_tiles;
+    const int tile = key - bin * g.n_tiles;
+    const int tx = tile % g.ntx;
+    const int ty = (tile / g.ntx) % g.nty;
+    const int tz = tile / (g.ntx * g.nty);
+    for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) {
+        double v = 0.0;
+        for (uint32_t bb = b0; bb <= b1; ++bb) v += partial[static_cast<int64_t>(deal.slot(bb, kb)) * kTileVoxels + i];
+        if (v == 0.0) continue;
+        const int64_t idx = tile_element(i, bin, tx, ty, tz, nx, ny, nz, nvox);
+        if (idx >= 0) flush_voxel<FLUSH>(tally, idx, v);
     }
 }
 
@@ -751,6 +858,41 @@ int tile_block(const vrc_ctx &ctx, size_t s_bytes)
     return 0;
 }
 
+// Blocks of a kernel that fit on one CU at once (cached per kernel and LDS size).
+hipError_t resident_per_cu(SortScratch &sc, const void *fn, int block, size_t lds, int &per_cu)
+{
+    auto it = sc.occupancy.find({fn, lds});
+    if (it == sc.occupancy.end()) {
+        int b = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, block, lds);
+        if (e != hipSuccess) return e;
+        it = sc.occupancy.emplace(std::make_pair(fn, lds), b < 1 ? 1 : b).first;
+    }
+    per_cu = it->second;
+    return hipSuccess;
+}
+
+// The tiles pass over every resident block (so the records are dealt out to
+// all of the GPU at once), then the reduction of keys that span blocks.
+template <typename R, typename S, int FLUSH>
+hipError_t launch_tiles(vrc_ctx &ctx, TileArgs<R> T, int tb, size_t lds, hipStream_t s)
+{
+    SortScratch &sc = ctx.sort_scratch;
+    int per_cu = 0;
+    hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&tile_kernel<R, S, FLUSH>), tb, lds, per_cu);
+    if (e != hipSuccess) return e;
+    const int n_blocks = ctx.n_cu * per_cu;
+    e = grow(sc.partial, sc.partial_cap, sizeof(double) * 2 * static_cast<size_t>(n_blocks) * kTileVoxels);
+    if (e != hipSuccess) return e;
+    T.partial = static_cast<double *>(sc.partial);
+    T.n_blocks = n_blocks;
+    hipLaunchKernelGGL((tile_kernel<R, S, FLUSH>), dim3(n_blocks), dim3(tb), lds, s, T);
+    hipLaunchKernelGGL((tile_reduce_kernel<FLUSH>), dim3(T.g.n_keys), dim3(256), 0, s, T.key_base, T.g, n_blocks,
+                       static_cast<const double *>(T.partial), T.mesh.n[0], T.mesh.n[1], T.mesh.n[2], T.nvox,
+                       T.tally);
+    return hipGetLastError();
+}
+
 template <typename R, typename RT, typename S>
 hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
                       const SortGeom &g, int flush, hipStream_t s)
@@ -760,8 +902,6 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
     const int ntz = g.n_tiles / (g.ntx * g.nty);
     const int64_t per_ray = static_cast<int64_t>(g.ntx) + g.nty + ntz;  // > tiles a ray can cross
     const size_t rec = sizeof(Entry<R, S>);
-    const int64_t max_rays_block = static_cast<int64_t>(kScratchBudget / (rec * per_ray * G));
-    const int64_t group_rays = (max_rays_block < 1 ? 1 : max_rays_block) * G;
     int shift = 0;
     while (((static_cast<int64_t>(m.n[0]) + m.n[1] + m.n[2]) >> shift) >= kBucketsE) ++shift;
     const int hist_keys = g.n_keys > kBucketsE ? g.n_keys : kBucketsE;  // hist rows serve both sorts
@@ -770,20 +910,44 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
     const size_t lds1 = sigma_lds(ctx, sizeof(S), kBlock);
     const int tb = tile_block(ctx, sizeof(S));
     const size_t lds2 = sigma_lds(ctx, sizeof(S), tb);
+    // The entries pass runs one block per resident slot (its ray deal keeps
+    // them equally busy); a sub-launch takes as many rounds of 256 rays per
+    // block as the record budget allows, and at the least one round on as
+    // many blocks as fit in it.
+    int per_cu = 0;
+    {
+        hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&entries_kernel<R, RT, S>), kBlock, lds1,
+                                       per_cu);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t round_bytes = static_cast<int64_t>(rec) * kBlock * per_ray;  // one block, one round
+    int64_t G_lim = static_cast<int64_t>(ctx.n_cu) * per_cu;
+    int64_t rounds_max = static_cast<int64_t>(kScratchBudget) / (round_bytes * G_lim);
+    if (rounds_max < 1) {
+        rounds_max = 1;
+        G_lim = static_cast<int64_t>(kScratchBudget) / round_bytes;
+        if (G_lim < 1) G_lim = 1;
+    }
+    const int64_t group_rays = rounds_max * kBlock * G_lim;
     if (sc.busy && sc.stream != s) {
         hipError_t e = hipStreamWaitEvent(s, sc.done, 0);
         if (e != hipSuccess) return e;
     }
     for (int64_t r0 = 0; r0 < n_rays; r0 += group_rays) {
         const int64_t nr = n_rays - r0 < group_rays ? n_rays - r0 : group_rays;
-        const int64_t rays_block = (nr + G - 1) / G;
-        const int64_t cap = rays_block * per_ray;
-        const size_t rec_bytes = rec * static_cast<size_t>(cap) * G;
+        const int64_t rays_block = (nr + G - 1) / G;  // ordering kernels
+        // entries pass: every block a region for rounds x 256 rays
+        const int64_t slices = (nr + 63) / 64;
+        const int Ge = static_cast<int>(G_lim < (slices + 3) / 4 ? G_lim : (slices + 3) / 4);
+        const int64_t rounds = (slices + 4 * static_cast<int64_t>(Ge) - 1) / (4 * static_cast<int64_t>(Ge));
+        const int64_t cap = rounds * kBlock * per_ray;
+        const size_t rec_bytes = rec * static_cast<size_t>(cap) * Ge;
+        const size_t rows = static_cast<size_t>(G > Ge ? G : Ge);
         hipError_t e = grow(sc.records, sc.records_cap, rec_bytes);
         if (e == hipSuccess) e = grow(sc.sorted, sc.sorted_cap, rec_bytes);
-        if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * static_cast<size_t>(G) * hist_keys);
-        if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * static_cast<size_t>(G) * hist_keys);
-        if (e == hipSuccess) e = grow(sc.counts, sc.counts_cap, sizeof(uint32_t) * G);
+        if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * rows * hist_keys);
+        if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * rows * hist_keys);
+        if (e == hipSuccess) e = grow(sc.counts, sc.counts_cap, sizeof(uint32_t) * Ge);
         if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (hist_keys + 1));
         if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (hist_keys + 1));
         if (e == hipSuccess) e = grow(sc.ordered, sc.ordered_cap, sizeof(RayRec<R>) * static_cast<size_t>(nr));
@@ -819,7 +983,6 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         A.cap = cap;
         A.counts = static_cast<uint32_t *>(sc.counts);
         A.hist = static_cast<uint32_t *>(sc.hist);
-        A.rays_per_block = rays_block;
         A.ordered = sc.ordered;
         uint32_t *hist = static_cast<uint32_t *>(sc.hist);
         uint32_t *row_off = static_cast<uint32_t *>(sc.row_off);
@@ -833,13 +996,13 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, sub, nr,
                            static_cast<const uint8_t *>(sc.bucket), rays_block, row_off, key_base,
                            static_cast<RayRec<R> *>(sc.ordered));
-        hipLaunchKernelGGL((entries_kernel<R, RT, S>), dim3(G), dim3(kBlock), lds1, s, A);
+        hipLaunchKernelGGL((entries_kernel<R, RT, S>), dim3(Ge), dim3(kBlock), lds1, s, A);
         hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
-                           static_cast<const uint32_t *>(sc.hist), G, g.n_keys, static_cast<uint32_t *>(sc.row_off),
+                           static_cast<const uint32_t *>(sc.hist), Ge, g.n_keys, static_cast<uint32_t *>(sc.row_off),
                            static_cast<uint32_t *>(sc.key_tot));
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(sc.key_tot),
                            g.n_keys, static_cast<uint32_t *>(sc.key_base));
-        hipLaunchKernelGGL((partition_kernel<Entry<R, S>>), dim3(G), dim3(256), 0, s,
+        hipLaunchKernelGGL((partition_kernel<Entry<R, S>>), dim3(Ge), dim3(256), 0, s,
                            static_cast<const Entry<R, S> *>(sc.records), cap, static_cast<const uint32_t *>(sc.counts),
                            static_cast<const uint32_t *>(sc.row_off), static_cast<const uint32_t *>(sc.key_base),
                            g.n_keys, static_cast<Entry<R, S> *>(sc.sorted));
@@ -854,16 +1017,14 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         T.tally = t.d_data;
         if constexpr (sizeof(S) == 4) {
             if (flush == kFlushKahan) {
-                hipLaunchKernelGGL((tile_kernel<R, S, kFlushKahan>), dim3(g.n_keys), dim3(tb), lds2, s, T);
+                e = launch_tiles<R, S, kFlushKahan>(ctx, T, tb, lds2, s);
                 goto launched;
             }
         }
-        if (flush == kFlushAtomic)
-            hipLaunchKernelGGL((tile_kernel<R, S, kFlushAtomic>), dim3(g.n_keys), dim3(tb), lds2, s, T);
-        else
-            hipLaunchKernelGGL((tile_kernel<R, S, kFlushPlain>), dim3(g.n_keys), dim3(tb), lds2, s, T);
+        e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic>(ctx, T, tb, lds2, s)
+                                  : launch_tiles<R, S, kFlushPlain>(ctx, T, tb, lds2, s);
     launched:
-        e = hipGetLastError();
+        if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipError_t e = hipEventRecord(sc.done, s);
