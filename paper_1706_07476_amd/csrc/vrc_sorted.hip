@@ -592,6 +592,42 @@ struct PutLds {
     }
 };
 
+// The score of a ray piece inside one tile.  The walk of the tiles pass
+// never leaves the tile, so the optical depth is not carried: the entering
+// weight is set at the tile entry as the uninterrupted walk re-anchors it
+// there, w e^{-tau_hi} (1 - tau_lo), and then multiplied by each piece's
+// e^{-x}, giving the same scores bit for bit.
+template <typename R, class Put>
+struct TileScorer {
+    const R (*sig)[2];
+    int stride;
+    R w_in;
+    Put &put;
+    __device__ __forceinline__ void resume(R w, R th, R tl, bool first)
+    {
+        if (first) {
+            w_in = w;
+        } else {
+            R G, unused;
+            attenuation(th, G, unused);
+            w_in = (w * G) * (R(1) - tl);
+        }
+    }
+    template <typename L>
+    __device__ __forceinline__ void operator()(int32_t vox, int m, L len, int ci, int cj, int ck, L)
+    {
+        const R l = static_cast<R>(len);
+        const R s = sig[m * stride][0];
+        const R is = sig[m * stride][1];
+        const R x = s * l;
+        R g, em;
+        attenuation(x, g, em);
+        const R f = s > R(0) ? (w_in * em) * is : w_in * l;
+        put(vox, l, f, ci, cj, ck);
+        w_in = w_in * g;
+    }
+};
+
 // The key-major records are dealt out to the blocks of the tiles pass in
 // equal contiguous ranges (a key's records may span several blocks, a block's
 // range several keys), so every block has the same number of tile entries to
@@ -690,7 +726,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
     S(*mysig)[2] = sig + threadIdx.x;
     const Entry<R, S> *rec = static_cast<const Entry<R, S> *>(A.sorted);
     PutLds put{acc};
-    Scorer<S, PutLds> sc(mysig, bd, S(0), put);
+    TileScorer<S, PutLds> sc{mysig, bd, S(0), put};
     Walker<R> wk;
     constexpr int PER = 1;  // the records of one block-sized chunk are ordered together
     for (; key < n_keys; ++key) {
@@ -717,7 +753,6 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
         }
         __syncthreads();
         const TileMaterials mats{s_mat, tx * kTileEdge, ty * kTileEdge, tz * kTileEdge};
-        const uint32_t tg = tile_tag(tx, ty, tz);
         for (uint32_t c0 = lo; c0 < hi; c0 += bd) {
             const int m = static_cast<int>(hi - c0 < static_cast<uint32_t>(bd) ? hi - c0 : static_cast<uint32_t>(bd));
             int bucket[PER];
@@ -744,7 +779,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
                 const int ci = tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1));
                 const int cj = ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1));
                 const int ck = tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits));
-                sc.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, tg, (r.code & kFirst) != 0u);
+                sc.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, (r.code & kFirst) != 0u);
                 wk.resume_tile(A.mesh, mats, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz, ci, cj, ck, r.t0);
                 while (wk.step(A.mesh, sc, mats)) {
                 }
@@ -766,7 +801,9 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
 }
 
 // Keys whose records span two or more blocks: the blocks' partial tiles are
-// summed in block order and the sum goes into the tally.  One block per key.
+// summed in block order and the sum goes into the tally.  Blocks of 256
+// threads, kReduceSplit per key (a slice of the tile each).
+constexpr int kReduceSplit = 4;
 template <int FLUSH>
 __global__ void __launch_bounds__(256) tile_reduce_kernel(const uint32_t *key_base, SortGeom g, int n_blocks,
                                                           const double *partial, int nx, int ny, int nz,
@@ -783,7 +820,9 @@ __global__ void __launch_bounds__(256) tile_reduce_kernel(const uint32_t *key_ba
     const int tx = tile % g.ntx;
     const int ty = (tile / g.ntx) % g.nty;
     const int tz = tile / (g.ntx * g.nty);
-    for (int i = threadIdx.x; i < kTileVoxels; i += blockDim.x) {
+    constexpr int kSlice = kTileVoxels / kReduceSplit;
+    const int i0 = static_cast<int>(blockIdx.y) * kSlice;
+    for (int i = i0 + threadIdx.x; i < i0 + kSlice; i += blockDim.x) {
         double v = 0.0;
         for (uint32_t bb = b0; bb <= b1; ++bb) v += partial[static_cast<int64_t>(deal.slot(bb, kb)) * kTileVoxels + i];
         if (v == 0.0) continue;
@@ -887,7 +926,7 @@ hipError_t launch_tiles(vrc_ctx &ctx, TileArgs<R> T, int tb, size_t lds, hipStre
     T.partial = static_cast<double *>(sc.partial);
     T.n_blocks = n_blocks;
     hipLaunchKernelGGL((tile_kernel<R, S, FLUSH>), dim3(n_blocks), dim3(tb), lds, s, T);
-    hipLaunchKernelGGL((tile_reduce_kernel<FLUSH>), dim3(T.g.n_keys), dim3(256), 0, s, T.key_base, T.g, n_blocks,
+    hipLaunchKernelGGL((tile_reduce_kernel<FLUSH>), dim3(T.g.n_keys, kReduceSplit), dim3(256), 0, s, T.key_base, T.g, n_blocks,
                        static_cast<const double *>(T.partial), T.mesh.n[0], T.mesh.n[1], T.mesh.n[2], T.nvox,
                        T.tally);
     return hipGetLastError();
