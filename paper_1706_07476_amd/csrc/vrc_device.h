@@ -138,18 +138,14 @@ __device__ __forceinline__ uint32_t tile_tag(int ti, int tj, int tk)
 
 // Where a walk reads voxel materials: the mesh array in global memory, or a
 // copy of one tile's materials in LDS (indexed by the voxel's position in
-// its tile).
+// its tile, which is what a walk resumed in a tile counts as its voxel index).
 struct MeshMaterials {
     const uint8_t *mat;
     __device__ __forceinline__ int operator()(int32_t vox, int, int, int) const { return mat[vox]; }
 };
 struct TileMaterials {
     const uint8_t *mat;  // LDS, kTileEdge^3, x fastest
-    int lo_x, lo_y, lo_z;
-    __device__ __forceinline__ int operator()(int32_t, int i, int j, int k) const
-    {
-        return mat[(i - lo_x) + kTileEdge * ((j - lo_y) + kTileEdge * (k - lo_z))];
-    }
+    __device__ __forceinline__ int operator()(int32_t local, int, int, int) const { return mat[local]; }
 };
 
 // The walk of one ray as explicit state, one piece per step(), so that a
@@ -213,7 +209,9 @@ struct Walker {
     // Resume at voxel (kx, ky, kz), entered at ray parameter cur, limited to
     // that voxel's tile.  The per-axis crossings are recomputed from the plane
     // indices exactly as step() computes them, so the pieces are
-    // bit-identical to those of the uninterrupted walk.
+    // bit-identical to those of the uninterrupted walk.  The voxel index the
+    // walk carries (and hands to its sink) is the voxel's position in the
+    // tile, x fastest: (i mod 16) + 16 (j mod 16) + 256 (k mod 16).
     template <class Mat>
     __device__ __forceinline__ void resume_tile(const MeshP<R> &M, const Mat &mats, R ox_, R oy_, R oz_, R ux, R uy,
                                                 R uz, int kx_, int ky_, int kz_, R cur_)
@@ -249,9 +247,9 @@ struct Walker {
         stop_y = sy > 0 ? (ay0 + kTileEdge < ny ? ay0 + kTileEdge : ny) : ay0 - 1;
         stop_z = sz > 0 ? (az0 + kTileEdge < nz ? az0 + kTileEdge : nz) : az0 - 1;
         dvx = sx;
-        dvy = sy * nx;
-        dvz = sz * nx * ny;
-        vox = kx + nx * (ky + ny * kz);
+        dvy = sy * kTileEdge;
+        dvz = sz * kTileEdge * kTileEdge;
+        vox = (kx - ax0) + kTileEdge * ((ky - ay0) + kTileEdge * (kz - az0));
         m = mats(vox, kx, ky, kz);
     }
 

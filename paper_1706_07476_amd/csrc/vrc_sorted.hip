@@ -583,12 +583,13 @@ struct TileArgs {
     int n_blocks;     // blocks the records are dealt out to (the grid)
 };
 
+// Tile sums in LDS, indexed by the voxel's position in the tile.
 struct PutLds {
     double *acc;
     template <typename S>
-    __device__ __forceinline__ void operator()(int32_t, S, S f, int ci, int cj, int ck)
+    __device__ __forceinline__ void operator()(int32_t local, S, S f, int, int, int)
     {
-        if (f != S(0)) atomicAdd(acc + local_index(ci, cj, ck), static_cast<double>(f));
+        if (f != S(0)) atomicAdd(acc + local, static_cast<double>(f));
     }
 };
 
@@ -752,7 +753,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
                            : static_cast<uint8_t>(0);
         }
         __syncthreads();
-        const TileMaterials mats{s_mat, tx * kTileEdge, ty * kTileEdge, tz * kTileEdge};
+        const TileMaterials mats{s_mat};
         for (uint32_t c0 = lo; c0 < hi; c0 += bd) {
             const int m = static_cast<int>(hi - c0 < static_cast<uint32_t>(bd) ? hi - c0 : static_cast<uint32_t>(bd));
             int bucket[PER];
