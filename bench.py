@@ -106,8 +106,8 @@ def _counter_rows(csv_path: str, kernel: str, counter: str) -> list:
 # the kernels of one cast of the bench workload; the first one runs exactly once per cast
 PIPELINE = {0: ["cast_f64_kernel<float, float, false"],
             1: ["entries_kernel<float, float, float>", "order_hist_kernel<float, float>",
-                "order_scatter_kernel<float, float>", "scan_rows_kernel", "scan_keys_kernel",
-                "partition_kernel<vrc::(anonymous namespace)::Entry<float, float> >", "tile_kernel<float, float, 0>"]}
+                "order_scatter_kernel<float, float>", "count_entries_kernel<float>", "scan_rows_kernel",
+                "scan_keys_kernel", "tile_kernel<float, float, 0>", "tile_reduce_kernel<0>"]}
 
 
 def write_traffic(paths, precision="p32_t64", copy_mib=1024) -> None:

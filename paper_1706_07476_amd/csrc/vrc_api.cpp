@@ -248,11 +248,9 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
     free_dev(ctx->d_mesh64);
     {
         SortScratch &sc = ctx->sort_scratch;
-        free_dev(sc.records);
         free_dev(sc.sorted);
         free_dev(sc.hist);
         free_dev(sc.row_off);
-        free_dev(sc.counts);
         free_dev(sc.key_tot);
         free_dev(sc.key_base);
         free_dev(sc.ordered);

@@ -87,11 +87,11 @@ constexpr int64_t kSplitMinRays = int64_t(1) << 17;
 
 // Scratch of the tile-sorted accumulation (vrc_sorted.hip), grown on demand.
 struct SortScratch {
-    void *records = nullptr, *sorted = nullptr, *hist = nullptr, *row_off = nullptr;
-    void *counts = nullptr, *key_tot = nullptr, *key_base = nullptr, *ordered = nullptr, *bucket = nullptr;
+    void *sorted = nullptr, *hist = nullptr, *row_off = nullptr;
+    void *key_tot = nullptr, *key_base = nullptr, *ordered = nullptr, *bucket = nullptr;
     void *partial = nullptr;  // tiles of keys shared by two or more blocks of the tiles pass
-    size_t records_cap = 0, sorted_cap = 0, hist_cap = 0, row_off_cap = 0;
-    size_t counts_cap = 0, key_tot_cap = 0, key_base_cap = 0, ordered_cap = 0, bucket_cap = 0, partial_cap = 0;
+    size_t sorted_cap = 0, hist_cap = 0, row_off_cap = 0;
+    size_t key_tot_cap = 0, key_base_cap = 0, ordered_cap = 0, bucket_cap = 0, partial_cap = 0;
     std::map<std::pair<const void *, size_t>, int> occupancy;  // (kernel, LDS bytes) -> resident blocks per CU
     hipEvent_t done = nullptr;   // after the last kernel that used the scratch
     hipStream_t stream = nullptr;

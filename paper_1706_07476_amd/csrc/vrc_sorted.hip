@@ -10,21 +10,22 @@
 //
 //   0. order: the rays are copied in order of estimated length (counting
 //      sort), as one record per ray.
-//   1. entries: every block takes a run of the ordered rays and every lane
-//      walks its ray accumulating only the optical depth (no exponentials,
-//      no tally); at each tile entry it appends a record {ray, entry voxel,
-//      entry parameter, optical depth so far} to its block's region
-//      (wavefront-compacted, coalesced stores), counting records per key in
-//      LDS.  A ray crosses at most n_tx + n_ty + n_tz - 2 tiles, which sizes
-//      the regions exactly.
+//   1. count: every block takes its deal of the ordered rays and walks each
+//      ray over the tile planes only (no voxels), counting per key the tiles
+//      the ray has pieces of positive length in.
 //   2. scan_rows / scan_keys: exclusive scans give every (block, key) pair
-//      its place in key-major order.
-//   3. partition: every block scatters its records to their key's run.
-//   4. tiles: one block per key orders the key's records by estimated
-//      length, resumes each ray at its tile entry, scores the pieces inside
-//      the tile into an FP64 tile in LDS, and adds the tile to the tally:
-//      one atomic per non-zero voxel, a plain read-add-write (no two blocks
-//      share a tally element), or a compensated update of an FP32 pair.
+//      its run in key-major order.
+//   3. entries: every block walks the same rays voxel by voxel accumulating
+//      only the optical depth (no exponentials, no tally); at each tile entry
+//      a lane writes a record {ray, entry voxel, entry parameter, optical
+//      depth so far} to the next place of its block's run for the key.
+//   4. tiles: the key-major records are dealt out to the blocks in equal
+//      ranges; a block orders a chunk of records by estimated length,
+//      resumes each ray at its tile entry, scores the pieces inside the tile
+//      into an FP64 tile in LDS, and adds the tile to the tally: one atomic
+//      per non-zero voxel, a plain read-add-write, or a compensated update of
+//      an FP32 pair (a key shared by several blocks goes through their
+//      partial tiles and a reduction).
 //
 // The score re-anchors its entering weight at every tile entry (vrc_device.h),
 // so resuming from (optical depth, entry voxel, entry parameter) reproduces
@@ -308,15 +309,112 @@ struct EntryArgs {
     TallyP tally;
     int hash_in_lds;
     SortGeom g;
-    void *records;     // one region of cap records per block
-    int64_t cap;       // records per block region
-    uint32_t *counts;  // per block
-    uint32_t *hist;    // blocks * n_keys
-    const void *ordered;  // RayRec<R>: the rays by estimated length, longest first
+    const void *ordered;      // RayRec<R>: the rays by estimated length, longest first
+    uint32_t *hist;           // blocks * n_keys: records per (block, key) (counting pass)
+    const uint32_t *row_off;  // blocks * n_keys: records of earlier blocks per key (entries pass)
+    const uint32_t *key_base; // n_keys + 1: first record of each key
+    void *sorted;             // the records in key-major order (entries pass)
+    int64_t cap;              // records sorted has room for
 };
 
+// The length-ordered rays are dealt out in slices of 64 (one per wavefront,
+// so the lanes of a wavefront walk rays of about the same length), in rounds
+// of one slice per wavefront of the grid.  A round's slices go to wavefront
+// 0 of every block, then wavefront 1, ..., so each block gets slices from
+// all of the round's lengths, and every other round is dealt in reverse: the
+// blocks get about the same amount of walking.  The counting and the entries
+// pass deal the same rays to the same blocks.
+struct RayDeal {
+    int64_t per_round, pos, slices;
+    __device__ __forceinline__ RayDeal(int64_t n)
+    {
+        per_round = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
+        pos = static_cast<int64_t>(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
+        slices = (n + 63) >> 6;
+    }
+    __device__ __forceinline__ bool more(int64_t round) const { return round * per_round < slices; }
+    __device__ __forceinline__ int64_t ray(int64_t round) const
+    {
+        return ((round * per_round + ((round & 1) ? per_round - 1 - pos : pos)) << 6) + (threadIdx.x & 63);
+    }
+};
+
+// Tiles in which a whole-mesh walk has a piece of positive length, in walk
+// order, without walking the voxels: the walk of the tile planes (every 16th
+// plane of each axis) with the voxel walk's clip, start voxel and crossing
+// arithmetic.  The voxel walk's crossing parameters are non-decreasing and
+// include these, so its pieces in a tile are of positive length exactly when
+// the tile's interval here is (ties between axes only make zero-length
+// intervals, which neither walk counts).  on_tile(ti, tj, tk) per tile.
+template <typename R, class F>
+__device__ __forceinline__ void walk_tiles(const MeshP<R> &M, R ox, R oy, R oz, R ux, R uy, R uz, F &&on_tile)
+{
+    Walker<R> w;
+    if (!w.start(M, ox, oy, oz, ux, uy, uz)) return;
+    const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
+    const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
+    int ti = w.kx >> kTileBits, tj = w.ky >> kTileBits, tk = w.kz >> kTileBits;
+    // parameter of the next tile plane on each axis (the far side of the tile in the direction of travel)
+    auto cross = [](R lo, R h, R o, R inv, int s, int t) -> R {
+        return s == 0 ? Num<R>::inf() : (plane(lo, h, (t + (s > 0 ? 1 : 0)) << kTileBits) - o) * inv;
+    };
+    R cx = cross(lox, hx, ox, w.ix, w.sx, ti);
+    R cy = cross(loy, hy, oy, w.iy, w.sy, tj);
+    R cz = cross(loz, hz, oz, w.iz, w.sz, tk);
+    R cur = w.cur;
+    const R t_exit = w.t_exit;
+    for (int guard = (M.n[0] + M.n[1] + M.n[2]) / kTileEdge + 6; guard > 0; --guard) {
+        const bool ax = (cx <= cy) && (cx <= cz);
+        const bool ay = !ax && (cy <= cz);
+        const R ta = ax ? cx : (ay ? cy : cz);
+        const bool last = !(ta < t_exit);
+        if ((last ? t_exit : ta) - cur > R(0)) on_tile(ti, tj, tk);
+        if (last) return;
+        cur = ta;
+        if (ax) {
+            ti += w.sx;
+            cx = cross(lox, hx, ox, w.ix, w.sx, ti);
+        } else if (ay) {
+            tj += w.sy;
+            cy = cross(loy, hy, oy, w.iy, w.sy, tj);
+        } else {
+            tk += w.sz;
+            cz = cross(loz, hz, oz, w.iz, w.sz, tk);
+        }
+    }
+}
+
+// Counting pass: records per (block, key) of the entries pass, from the
+// tile walk of each ray the block will walk.
+template <typename R>
+__global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
+{
+    __shared__ uint32_t s_hist[kMaxKeys];
+    for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_hist[k] = 0u;
+    __syncthreads();
+    const int64_t n = A.rays.n;
+    const RayDeal deal(n);
+    const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
+    for (int64_t round = 0; deal.more(round); ++round) {
+        const int64_t j = deal.ray(round);
+        if (j >= n) continue;
+        const RayRec<R> rr = ordered[j];
+        const int bin = energy_bin(A.tally, static_cast<double>(rr.e));
+        if (bin < 0) continue;
+        const int key0 = bin * A.g.n_tiles;
+        walk_tiles(A.mesh, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz, [&](int ti, int tj, int tk) {
+            atomicAdd(&s_hist[key0 + ti + A.g.ntx * (tj + A.g.nty * tk)], 1u);
+        });
+    }
+    __syncthreads();
+    uint32_t *row = A.hist + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
+    for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) row[k] = s_hist[k];
+}
+
 // Walk sink of the entries pass: the optical depth as the score sums it
-// (same products, same TwoSum), and a record at every tile entry.
+// (same products, same TwoSum), and a record at every tile entry, written
+// straight to its place in key-major order (the block's next place for the
+// key, from the counting pass).
 template <typename R, typename S>
 struct EmitEntries {
     const S (*sig)[2];
@@ -327,24 +425,15 @@ struct EmitEntries {
     R ox, oy, oz, ux, uy, uz, e, w;
     int key0;  // bin * n_tiles
     SortGeom g;
-    Entry<R, S> *region;
-    int64_t cap;
-    uint32_t *cursor;  // LDS
-    uint32_t *hist;    // LDS
+    Entry<R, S> *sorted;
+    uint32_t cap;
+    uint32_t *next;  // LDS, per key
     __device__ __forceinline__ void emit(bool first, int ci, int cj, int ck, R t0)
     {
-        const uint64_t mask = __ballot(1);
-        const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-        const uint32_t cnt = static_cast<uint32_t>(__popcll(mask));
-        const uint32_t prefix = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
-        uint32_t start = 0;
-        if (static_cast<int>(__lane_id()) == leader) start = atomicAdd(cursor, cnt);
-        start = __builtin_amdgcn_readfirstlane(start);  // the leader is the first active lane
-        const int64_t pos = static_cast<int64_t>(start) + prefix;
         const int tl = (ci >> kTileBits) + g.ntx * ((cj >> kTileBits) + g.nty * (ck >> kTileBits));
         const uint32_t key = static_cast<uint32_t>(key0 + tl);
-        // regions are sized for the most tiles a ray can cross; the guard only keeps stores in bounds
+        const uint32_t pos = atomicAdd(next + key, 1u);
+        // the counting pass sized every key's run; the guard only keeps stores in bounds
         if (pos < cap) {
             Entry<R, S> r;
             r.ox = ox;
@@ -359,8 +448,7 @@ struct EmitEntries {
             r.tau_hi = tau_hi;
             r.tau_lo = tau_lo;
             r.code = (first ? kFirst : 0u) | (key << kLocalBits) | local_index(ci, cj, ck);
-            region[pos] = r;
-            atomicAdd(hist + key, 1u);
+            sorted[pos] = r;
         }
     }
     __device__ __forceinline__ void reset(R ox_, R oy_, R oz_, R ux_, R uy_, R uz_, R e_, R w_, int key0_)
@@ -402,34 +490,24 @@ template <typename R, typename RT, typename S>
 __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     entries_kernel(EntryArgs<R> A)
 {
-    __shared__ uint32_t s_hist[kMaxKeys];
-    __shared__ uint32_t s_cursor;
-    for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_hist[k] = 0u;
-    if (threadIdx.x == 0) s_cursor = 0u;
+    __shared__ uint32_t s_next[kMaxKeys];
+    const uint32_t *row = A.row_off + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
+    for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_next[k] = A.key_base[k] + row[k];
     __syncthreads();
     const int32_t *hash;
     S(*sig)[2];
     stage_lds(A.xs, A.hash_in_lds, hash, sig);
     const int bd = blockDim.x;
     S(*mysig)[2] = sig + threadIdx.x;
-    Entry<R, S> *region = static_cast<Entry<R, S> *>(A.records) + static_cast<int64_t>(blockIdx.x) * A.cap;
     const int64_t n = A.rays.n;
-    // The length-ordered rays are dealt out in slices of 64 (one per
-    // wavefront, so the lanes of a wavefront walk rays of about the same
-    // length), in rounds of one slice per wavefront of the grid.  A round's
-    // slices go to wavefront 0 of every block, then wavefront 1, ..., so each
-    // block gets slices from all of the round's lengths, and every other round
-    // is dealt in reverse: the blocks get about the same amount of walking.
-    const int64_t per_round = static_cast<int64_t>(gridDim.x) * (bd >> 6);
-    const int64_t pos = static_cast<int64_t>(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
-    const int64_t slices = (n + 63) >> 6;
+    const RayDeal deal(n);
     EmitEntries<R, S> em{mysig, bd, S(0), S(0), 0u, false, R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0),
-                         0, A.g, region, A.cap, &s_cursor, s_hist};
+                         0, A.g, static_cast<Entry<R, S> *>(A.sorted), static_cast<uint32_t>(A.cap), s_next};
     Walker<R> wk;
     const MeshMaterials mats{A.mesh.mat};
     const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
-    for (int64_t round = 0; round * per_round < slices; ++round) {
-        const int64_t j = ((round * per_round + ((round & 1) ? per_round - 1 - pos : pos)) << 6) + (threadIdx.x & 63);
+    for (int64_t round = 0; deal.more(round); ++round) {
+        const int64_t j = deal.ray(round);
         if (j >= n) continue;
         const RayRec<R> rr = ordered[j];
         const R ox = rr.ox, oy = rr.oy, oz = rr.oz, ux = rr.ux, uy = rr.uy, uz = rr.uz, E = rr.e, wt = rr.w;
@@ -441,11 +519,6 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
         while (wk.step(A.mesh, em, mats)) {
         }
     }
-    __syncthreads();
-    const uint32_t used = s_cursor < A.cap ? s_cursor : static_cast<uint32_t>(A.cap);
-    if (threadIdx.x == 0) A.counts[blockIdx.x] = used;
-    uint32_t *row = A.hist + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
-    for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) row[k] = s_hist[k];
 }
 
 // Block of 1024 threads, 64 keys: lane = key, each of the 16 wavefronts a
@@ -523,50 +596,6 @@ __global__ void __launch_bounds__(256) scan_keys_kernel(const uint32_t *key_tot,
         }
     }
     if (threadIdx.x == 0) key_base[n_keys] = total;
-}
-
-// Every block scatters its region's records to their places in key-major
-// order (the order within one key's run is immaterial).  Each record goes
-// to a place of its own, so a record per lane written with 16-byte stores
-// would leave the memory system many partial-sector writes; instead the
-// block stages 256 records in LDS and writes them back word by word, so
-// consecutive lanes write consecutive words of one record.
-template <typename E>
-__global__ void __launch_bounds__(256) partition_kernel(const E *records, int64_t cap, const uint32_t *counts,
-                                                        const uint32_t *row_off, const uint32_t *key_base,
-                                                        int n_keys, E *sorted)
-{
-    constexpr int W = static_cast<int>(sizeof(E) / 4);  // words per record
-    __shared__ uint32_t s_base[kMaxKeys];
-    __shared__ uint32_t s_cnt[kMaxKeys];
-    __shared__ uint32_t s_stage[256 * W];
-    __shared__ uint32_t s_dst[256];
-    const int b = blockIdx.x;
-    const int t = threadIdx.x;
-    const uint32_t *row = row_off + static_cast<int64_t>(b) * n_keys;
-    for (int k = t; k < n_keys; k += blockDim.x) {
-        s_base[k] = key_base[k] + row[k];
-        s_cnt[k] = 0u;
-    }
-    __syncthreads();
-    const E *region = records + static_cast<int64_t>(b) * cap;
-    uint32_t *out = reinterpret_cast<uint32_t *>(sorted);
-    const uint32_t n = counts[b];
-    for (uint32_t c0 = 0; c0 < n; c0 += 256) {
-        const int m = n - c0 < 256u ? static_cast<int>(n - c0) : 256;
-        if (t < m) {
-            const E r = region[c0 + t];
-            const uint32_t key = (r.code >> kLocalBits) & static_cast<uint32_t>(kMaxKeys - 1);
-            s_dst[t] = s_base[key] + atomicAdd(&s_cnt[key], 1u);
-            *reinterpret_cast<E *>(s_stage + t * W) = r;
-        }
-        __syncthreads();
-        for (int w = t; w < m * W; w += 256) {
-            const int q = w / W;
-            out[static_cast<int64_t>(s_dst[q]) * W + (w - q * W)] = s_stage[w];
-        }
-        __syncthreads();
-    }
 }
 
 template <typename R>
@@ -864,9 +893,9 @@ hipError_t grow(void *&p, size_t &cap, size_t need)
     return hipSuccess;
 }
 
-constexpr int kBlock = 256;  // entries and partition
+constexpr int kBlock = 256;  // ordering, counting and entries passes
 constexpr size_t kLdsMax = 65536;
-constexpr size_t kEntriesStatic = 4 * (kMaxKeys + 16);                                      // hist, cursor
+constexpr size_t kEntriesStatic = 4 * kMaxKeys;                                             // next place per key
 constexpr size_t kTileStatic = (sizeof(double) + 1) * kTileVoxels + 4 * kBucketsT + 2 * kMaxBlock;  // acc, mat, sort
 constexpr size_t kScratchBudget = size_t(2) << 30;            // record bytes per sub-launch
 
@@ -950,25 +979,19 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
     const size_t lds1 = sigma_lds(ctx, sizeof(S), kBlock);
     const int tb = tile_block(ctx, sizeof(S));
     const size_t lds2 = sigma_lds(ctx, sizeof(S), tb);
-    // The entries pass runs one block per resident slot (its ray deal keeps
-    // them equally busy); a sub-launch takes as many rounds of 256 rays per
-    // block as the record budget allows, and at the least one round on as
-    // many blocks as fit in it.
+    // The counting and entries passes run one block per resident slot of the
+    // entries pass (the ray deal keeps them equally busy); a sub-launch takes
+    // as many rays as the record space allows for the most tiles a ray can
+    // cross.
     int per_cu = 0;
     {
         hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&entries_kernel<R, RT, S>), kBlock, lds1,
                                        per_cu);
         if (e != hipSuccess) return e;
     }
-    const int64_t round_bytes = static_cast<int64_t>(rec) * kBlock * per_ray;  // one block, one round
-    int64_t G_lim = static_cast<int64_t>(ctx.n_cu) * per_cu;
-    int64_t rounds_max = static_cast<int64_t>(kScratchBudget) / (round_bytes * G_lim);
-    if (rounds_max < 1) {
-        rounds_max = 1;
-        G_lim = static_cast<int64_t>(kScratchBudget) / round_bytes;
-        if (G_lim < 1) G_lim = 1;
-    }
-    const int64_t group_rays = rounds_max * kBlock * G_lim;
+    const int64_t G_res = static_cast<int64_t>(ctx.n_cu) * per_cu;
+    int64_t group_rays = static_cast<int64_t>(kScratchBudget / (rec * static_cast<size_t>(per_ray)));
+    if (group_rays < 1) group_rays = 1;
     if (sc.busy && sc.stream != s) {
         hipError_t e = hipStreamWaitEvent(s, sc.done, 0);
         if (e != hipSuccess) return e;
@@ -976,18 +999,13 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
     for (int64_t r0 = 0; r0 < n_rays; r0 += group_rays) {
         const int64_t nr = n_rays - r0 < group_rays ? n_rays - r0 : group_rays;
         const int64_t rays_block = (nr + G - 1) / G;  // ordering kernels
-        // entries pass: every block a region for rounds x 256 rays
         const int64_t slices = (nr + 63) / 64;
-        const int Ge = static_cast<int>(G_lim < (slices + 3) / 4 ? G_lim : (slices + 3) / 4);
-        const int64_t rounds = (slices + 4 * static_cast<int64_t>(Ge) - 1) / (4 * static_cast<int64_t>(Ge));
-        const int64_t cap = rounds * kBlock * per_ray;
-        const size_t rec_bytes = rec * static_cast<size_t>(cap) * Ge;
+        const int Ge = static_cast<int>(G_res < (slices + 3) / 4 ? G_res : (slices + 3) / 4);
+        const int64_t cap = nr * per_ray;  // records
         const size_t rows = static_cast<size_t>(G > Ge ? G : Ge);
-        hipError_t e = grow(sc.records, sc.records_cap, rec_bytes);
-        if (e == hipSuccess) e = grow(sc.sorted, sc.sorted_cap, rec_bytes);
+        hipError_t e = grow(sc.sorted, sc.sorted_cap, rec * static_cast<size_t>(cap));
         if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * rows * hist_keys);
         if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * rows * hist_keys);
-        if (e == hipSuccess) e = grow(sc.counts, sc.counts_cap, sizeof(uint32_t) * Ge);
         if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (hist_keys + 1));
         if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (hist_keys + 1));
         if (e == hipSuccess) e = grow(sc.ordered, sc.ordered_cap, sizeof(RayRec<R>) * static_cast<size_t>(nr));
@@ -1019,11 +1037,12 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         A.tally = TallyP{t.d_data, t.d_edges, t.nvox, t.n_bins};
         A.hash_in_lds = 0;
         A.g = g;
-        A.records = sc.records;
-        A.cap = cap;
-        A.counts = static_cast<uint32_t *>(sc.counts);
-        A.hist = static_cast<uint32_t *>(sc.hist);
         A.ordered = sc.ordered;
+        A.hist = static_cast<uint32_t *>(sc.hist);
+        A.row_off = static_cast<const uint32_t *>(sc.row_off);
+        A.key_base = static_cast<const uint32_t *>(sc.key_base);
+        A.sorted = sc.sorted;
+        A.cap = cap;
         uint32_t *hist = static_cast<uint32_t *>(sc.hist);
         uint32_t *row_off = static_cast<uint32_t *>(sc.row_off);
         uint32_t *key_tot = static_cast<uint32_t *>(sc.key_tot);
@@ -1036,16 +1055,13 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, sub, nr,
                            static_cast<const uint8_t *>(sc.bucket), rays_block, row_off, key_base,
                            static_cast<RayRec<R> *>(sc.ordered));
-        hipLaunchKernelGGL((entries_kernel<R, RT, S>), dim3(Ge), dim3(kBlock), lds1, s, A);
+        hipLaunchKernelGGL((count_entries_kernel<R>), dim3(Ge), dim3(kBlock), 0, s, A);
         hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
                            static_cast<const uint32_t *>(sc.hist), Ge, g.n_keys, static_cast<uint32_t *>(sc.row_off),
                            static_cast<uint32_t *>(sc.key_tot));
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(sc.key_tot),
                            g.n_keys, static_cast<uint32_t *>(sc.key_base));
-        hipLaunchKernelGGL((partition_kernel<Entry<R, S>>), dim3(Ge), dim3(256), 0, s,
-                           static_cast<const Entry<R, S> *>(sc.records), cap, static_cast<const uint32_t *>(sc.counts),
-                           static_cast<const uint32_t *>(sc.row_off), static_cast<const uint32_t *>(sc.key_base),
-                           g.n_keys, static_cast<Entry<R, S> *>(sc.sorted));
+        hipLaunchKernelGGL((entries_kernel<R, RT, S>), dim3(Ge), dim3(kBlock), lds1, s, A);
         TileArgs<R> T;
         T.mesh = mesh;
         T.xs = A.xs;
