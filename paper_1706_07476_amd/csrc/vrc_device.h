@@ -283,29 +283,27 @@ struct Walker {
         const int32_t vcur = vox;
         const int mcur = m;
         const int cx = kx, cy = ky, cz = kz;
-        bool inside = true;
-        if (!last) {
-            // advance along the chosen axis and fetch the next voxel's material early
-            const int s = ax ? sx : (ay ? sy : sz);
-            const int ni = (ax ? kx : (ay ? ky : kz)) + s;
-            inside = ni != (ax ? stop_x : (ay ? stop_y : stop_z));
-            if (inside) {
-                vox = vcur + (ax ? dvx : (ay ? dvy : dvz));
-                m = mats(vox, ax ? ni : kx, ay ? ni : ky, az ? ni : kz);
-                const R plo = ax ? lox : (ay ? loy : loz);
-                const R h = ax ? hx : (ay ? hy : hz);
-                const R oa = ax ? ox : (ay ? oy : oz);
-                const R inv = ax ? ix : (ay ? iy : iz);
-                const R tnew = (plane(plo, h, ni + (s > 0 ? 1 : 0)) - oa) * inv;
-                kx = ax ? ni : kx;
-                ky = ay ? ni : ky;
-                kz = az ? ni : kz;
-                tx = ax ? tnew : tx;
-                ty = ay ? tnew : ty;
-                tz = az ? tnew : tz;
-            }
-            cur = ta;
-        }
+        // the step along the chosen axis, computed whether or not it is taken
+        // (no branches: the lanes of a wavefront take different axes and end
+        // at different steps)
+        const int s = ax ? sx : (ay ? sy : sz);
+        const int ni = (ax ? kx : (ay ? ky : kz)) + s;
+        const bool inside = ni != (ax ? stop_x : (ay ? stop_y : stop_z));
+        const bool adv = !last && inside;
+        vox = adv ? vcur + (ax ? dvx : (ay ? dvy : dvz)) : vcur;
+        m = mats(vox, adv && ax ? ni : kx, adv && ay ? ni : ky, adv && az ? ni : kz);  // early: overlaps the score
+        const R plo = ax ? lox : (ay ? loy : loz);
+        const R h = ax ? hx : (ay ? hy : hz);
+        const R oa = ax ? ox : (ay ? oy : oz);
+        const R inv = ax ? ix : (ay ? iy : iz);
+        const R tnew = (plane(plo, h, ni + (s > 0 ? 1 : 0)) - oa) * inv;
+        kx = adv && ax ? ni : kx;
+        ky = adv && ay ? ni : ky;
+        kz = adv && az ? ni : kz;
+        tx = adv && ax ? tnew : tx;
+        ty = adv && ay ? tnew : ty;
+        tz = adv && az ? tnew : tz;
+        cur = last ? cur : ta;
         this->kx = kx;
         this->ky = ky;
         this->kz = kz;
@@ -316,7 +314,7 @@ struct Walker {
         this->vox = vox;
         this->m = m;
         if (l > R(0)) seg(vcur, mcur, l, cx, cy, cz, t0);
-        return !(last || !inside || --budget <= 0);
+        return adv && --budget > 0;
     }
 };
 

@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
 template <typename R, typename S>
 struct EmitEntries {
     const S (*sig)[2];
-    int stride;
+    int shift;  // log2 of the LDS column stride (the block size)
     S tau_hi, tau_lo;
     uint32_t tile;  // tile_tag of the current tile
     bool started;   // a piece has been seen
@@ -476,7 +476,7 @@ struct EmitEntries {
             emit(first, ci, cj, ck, t0);
         }
         const S l = static_cast<S>(len);
-        const S x = sig[m * stride][0] * l;
+        const S x = sig[m << shift][0] * l;
         const S t = tau_hi + x;
         const S bv = t - tau_hi;
         const S err = (tau_hi - (t - bv)) + (x - bv);
@@ -501,7 +501,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     S(*mysig)[2] = sig + threadIdx.x;
     const int64_t n = A.rays.n;
     const RayDeal deal(n);
-    EmitEntries<R, S> em{mysig, bd, S(0), S(0), 0u, false, R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0),
+    EmitEntries<R, S> em{mysig, __ffs(bd) - 1, S(0), S(0), 0u, false, R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0),
                          0, A.g, static_cast<Entry<R, S> *>(A.sorted), static_cast<uint32_t>(A.cap), s_next};
     Walker<R> wk;
     const MeshMaterials mats{A.mesh.mat};
@@ -630,7 +630,7 @@ struct PutLds {
 template <typename R, class Put>
 struct TileScorer {
     const R (*sig)[2];
-    int stride;
+    int shift;  // log2 of the LDS column stride (the block size)
     R w_in;
     Put &put;
     __device__ __forceinline__ void resume(R w, R th, R tl, bool first)
@@ -647,8 +647,8 @@ struct TileScorer {
     __device__ __forceinline__ void operator()(int32_t vox, int m, L len, int ci, int cj, int ck, L)
     {
         const R l = static_cast<R>(len);
-        const R s = sig[m * stride][0];
-        const R is = sig[m * stride][1];
+        const R s = sig[m << shift][0];
+        const R is = sig[m << shift][1];
         const R x = s * l;
         R g, em;
         attenuation(x, g, em);
@@ -756,7 +756,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
     S(*mysig)[2] = sig + threadIdx.x;
     const Entry<R, S> *rec = static_cast<const Entry<R, S> *>(A.sorted);
     PutLds put{acc};
-    TileScorer<S, PutLds> sc{mysig, bd, S(0), put};
+    TileScorer<S, PutLds> sc{mysig, __ffs(bd) - 1, S(0), put};
     Walker<R> wk;
     constexpr int PER = 1;  // the records of one block-sized chunk are ordered together
     for (; key < n_keys; ++key) {
