@@ -83,6 +83,10 @@ def parse():
     ap.add_argument("--serving", type=int, default=1,
                     help="also run the serving form fed by 8 walker threads (p50/p99 latency per offered load)")
     ap.add_argument("--serving-seconds", type=float, default=2.0)
+    ap.add_argument("--fom", type=int, default=1,
+                    help="also measure eta, the VRC estimator's figure of merit over the track-length estimator's")
+    ap.add_argument("--fom-batches", type=int, default=20)
+    ap.add_argument("--fom-histories", type=int, default=100000)
     ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
     ap.add_argument("--precision-report", action="store_true",
@@ -332,6 +336,48 @@ def bench_serving(seconds: float) -> dict:
             "precision": "p32_t64", "loads": loads, "saturation": sat}
 
 
+def bench_fom(batches: int, histories: int) -> dict:
+    """Efficiency of the VRC estimator against the track-length estimator (Eqs. 5-6).
+
+    The serving problem scaled to a 64^3 mesh of 1 cm (sphere r = 16 cm,
+    Sigma = 1.0 in 0.1, one group, p_abs 0.3, point source at the centre),
+    a one-bin p32_t64 tally.  For 1 and 8 walker threads: the track-length
+    estimator on the walkers, then the VRC estimator with 1, 4 and 8 rays per
+    collision cast on the GPU (one vrc_cast_rays per full 16384-ray buffer);
+    `batches` batches of `histories` histories each; eta per voxel over the
+    voxels where both relative errors of the mean are below 10 %.
+    """
+    import paper_1706_07476_amd as vrc
+    from paper_1706_07476_amd import fom
+    import workloads as W
+
+    wl = W.config5_serving_geometry(n=64, radius=16.0)
+    mesh = wl.mesh
+    ctx = vrc.Context(0)
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    tally = ctx.create_tally(0, "p32_t64")
+    centre = mesh.lo + 0.5 * mesh.n * mesh.h + 0.01
+    sigma = list(wl.extra["sigma"])
+    inner = np.asarray(mesh.mat).reshape(-1) == 1
+    rows = []
+    for n_threads in (1, 8):
+        tl = fom.track_length(ctx, tally, mesh.n_voxels, sigma, centre, batches=batches, histories=histories,
+                              n_threads=n_threads, seed=11)
+        for n_per in (1, 4, 8):
+            res = fom.efficiency(ctx, tally, mesh.n_voxels, sigma, centre, batches=batches, histories=histories,
+                                 n_threads=n_threads, rays_per_collision=n_per, seed=11, region=inner, tl=tl)
+            sm = res["summary"]
+            rows.append(sm)
+            log(f"bench: eta (VRC / track length), {n_threads} walker threads, {n_per} rays per collision: median "
+                f"{sm['all'].get('eta_median', float('nan')):.3g} over {sm['all']['voxels']} voxels "
+                f"(T_tl {sm['T_tl_s']:.3f} s, T_vrc {sm['T_vrc_s']:.3f} s)")
+    ctx.close()
+    return {"workload": "64^3 mesh of 1 cm, sphere r=16 cm Sigma=1.0 in Sigma=0.1, one group, analog walk (p_abs 0.3) "
+                        "from a point source at the centre; one-bin p32_t64 tally",
+            "batches": batches, "histories_per_batch": histories, "runs": rows}
+
+
 def precision_report() -> None:
     """Per workload and form: relative error per voxel against the FP64 oracle (Eqs. 7-8).
 
@@ -498,6 +544,13 @@ def main():
     serving = None
     if args.serving:
         serving = bench_serving(args.serving_seconds)
+    fom_form = None
+    if args.fom:
+        try:
+            fom_form = bench_fom(args.fom_batches, args.fom_histories)
+        except Exception as exc:  # the headline line must still be printed
+            log(f"bench: eta measurement failed: {exc!r}")
+            fom_form = {"error": repr(exc)}
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
@@ -542,6 +595,7 @@ def main():
         "other_forms": others,
         "batched_form": batched,
         "serving_form": serving,
+        "fom_form": fom_form,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)

@@ -337,8 +337,17 @@ vrc_status vrc_serve_stop(vrc_ctx *ctx);
  * have passed (or to vrc_cast_rays if direct = 1; the serving loop need not
  * run then).  Each of n_threads walkers emits at rate_rays_per_s /
  * n_threads on average with exponential gaps (a Poisson process), sleeping
- * when ahead of it.  The run ends after duration_s or after max_rays rays
- * (if > 0); then vrc_walkers_run drains the loop.                          */
+ * when ahead of it.  The run ends after duration_s (if > 0), after max_rays
+ * rays (if > 0) or once the walkers have started max_histories histories
+ * (if > 0), whichever comes first; then vrc_walkers_run drains the loop.
+ *
+ * Track-length estimator (the estimator the VRC estimator is measured
+ * against, Sec. 1 and Eq. 6): if tl_tally is not NULL (a host array of
+ * n0*n1*n2 doubles of the tally's mesh, x fastest, owned by the caller),
+ * every flight adds its weight (1, analog) times its length in each voxel it
+ * crosses to it, up to the collision or the mesh boundary; each walker keeps
+ * a private copy and the copies are added to tl_tally when the run ends.
+ * tl_only = 1 emits no rays (a track-length run: no serving loop needed). */
 typedef struct {
     int32_t tally_id;
     int32_t n_threads;
@@ -359,7 +368,9 @@ typedef struct {
     int32_t direct;            /* 1: skip the serving loop: each buffer is one vrc_cast_rays
                                   call (one launch per buffer, as the paper ships each full
                                   buffer); for comparisons */
-    int32_t reserved;
+    int32_t tl_only;           /* 1: emit no rays (track-length scoring only) */
+    int64_t max_histories;     /* > 0: start no more histories than this (all walkers) */
+    double *tl_tally;          /* NULL, or the track-length tally (see above), added to */
 } vrc_walker_config;
 
 typedef struct {

@@ -85,6 +85,9 @@ class vrc_serve_stats(ctypes.Structure):
                 ("mean_requests_per_launch", ctypes.c_double), ("busy_s", ctypes.c_double)]
 
 
+_PD_T = ctypes.POINTER(ctypes.c_double)
+
+
 class vrc_walker_config(ctypes.Structure):
     _fields_ = [("tally_id", ctypes.c_int32), ("n_threads", ctypes.c_int32), ("rate_rays_per_s", ctypes.c_double),
                 ("duration_s", ctypes.c_double), ("max_rays", ctypes.c_int64), ("rays_per_collision", ctypes.c_int32),
@@ -92,7 +95,7 @@ class vrc_walker_config(ctypes.Structure):
                 ("sigma", ctypes.c_double * 64), ("p_abs", ctypes.c_double), ("source", ctypes.c_double * 3),
                 ("e_min", ctypes.c_double), ("e_max", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("fp64_rays", ctypes.c_int32), ("record", ctypes.c_int32), ("direct", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("tl_only", ctypes.c_int32), ("max_histories", ctypes.c_int64), ("tl_tally", _PD_T)]
 
 
 class vrc_walker_report(ctypes.Structure):
@@ -452,7 +455,10 @@ def vrc_serve_stop(ctx: int) -> None:
 
 def vrc_walkers_run(ctx: int, tally_id: int, sigma, source, n_threads=8, rate_rays_per_s=0.0, duration_s=1.0,
                     max_rays=0, rays_per_collision=1, flush_rays=16384, flush_us=1000, p_abs=0.3,
-                    e_min=1e-11, e_max=20.0, seed=1, fp64_rays=0, record=0, direct=0) -> dict:
+                    e_min=1e-11, e_max=20.0, seed=1, fp64_rays=0, record=0, direct=0, tl_only=0,
+                    max_histories=0, tl=None) -> dict:
+    """tl: None, or a C-contiguous float64 array of the mesh's voxels that the
+    track-length scores are added to."""
     c = vrc_walker_config()
     c.tally_id = tally_id
     c.n_threads = n_threads
@@ -473,6 +479,12 @@ def vrc_walkers_run(ctx: int, tally_id: int, sigma, source, n_threads=8, rate_ra
     c.fp64_rays = fp64_rays
     c.record = record
     c.direct = direct
+    c.tl_only = tl_only
+    c.max_histories = max_histories
+    if tl is not None:
+        if not (isinstance(tl, np.ndarray) and tl.dtype == np.float64 and tl.flags.c_contiguous):
+            raise TypeError("tl must be a C-contiguous float64 numpy array")
+        c.tl_tally = tl.ctypes.data_as(_PD_T)
     r = vrc_walker_report()
     _check(load_library().vrc_walkers_run(ctx, ctypes.byref(c), ctypes.byref(r)))
     return _struct_dict(r)

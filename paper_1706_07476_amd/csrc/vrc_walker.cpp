@@ -5,7 +5,9 @@
 //
 // This is a workload driver for the library, not part of the estimator: it
 // needs collision points, not scores, so its geometry is a plain double
-// precision voxel walk of its own.
+// precision voxel walk of its own.  The same walk can score the
+// track-length estimator the VRC estimator is compared with (Sec. 1): a
+// flight adds its length in every voxel it crosses.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -71,7 +73,9 @@ struct Geometry {
 
 // Fly from p along u for the optical distance tau_star; returns the distance
 // to the collision, or a negative value if the particle leaves the mesh first.
-double fly(const Geometry &G, const double p[3], const double u[3], double tau_star)
+// With tl, the flight's length in each voxel is added to tl[voxel] (the
+// track-length estimator, weight 1).
+double fly(const Geometry &G, const double p[3], const double u[3], double tau_star, double *tl)
 {
     int idx[3], step[3];
     double tn[3], dt[3];
@@ -99,8 +103,13 @@ double fly(const Geometry &G, const double p[3], const double u[3], double tau_s
     for (int it = 0; it < budget; ++it) {
         const int a = (tn[0] <= tn[1] && tn[0] <= tn[2]) ? 0 : (tn[1] <= tn[2] ? 1 : 2);
         const double seg = tn[a] - t;
-        const double sg = G.sigma[G.mat[idx[0] + G.n[0] * (idx[1] + G.n[1] * idx[2])]];
-        if (sg > 0 && sg * seg >= left) return t + left / sg;
+        const int64_t v = idx[0] + static_cast<int64_t>(G.n[0]) * (idx[1] + static_cast<int64_t>(G.n[1]) * idx[2]);
+        const double sg = G.sigma[G.mat[v]];
+        if (sg > 0 && sg * seg >= left) {
+            if (tl) tl[v] += left / sg;
+            return t + left / sg;
+        }
+        if (tl && seg > 0) tl[v] += seg;
         left -= sg * seg;
         t = tn[a];
         idx[a] += step[a];
@@ -114,11 +123,13 @@ struct WalkerOut {
     int64_t histories = 0, collisions = 0, emitted = 0, submitted = 0, submits = 0, busy = 0;
     vrc_status status = VRC_OK;
     std::vector<double> rec[8];
+    std::vector<double> tl;  // the walker's track-length tally (if asked for)
 };
 
 void walker_main(vrc_ctx *ctx, const vrc_walker_config *cfg, const Geometry G, int id, Clock::time_point start,
-                 std::atomic<int64_t> *total, WalkerOut *out)
+                 std::atomic<int64_t> *total, std::atomic<int64_t> *started, WalkerOut *out)
 {
+    double *tl = out->tl.empty() ? nullptr : out->tl.data();
     Rng rng(cfg->seed * 0x100000001B3ull + static_cast<uint64_t>(id) * 7919 + 1);
     const int N = cfg->rays_per_collision;
     const double wN = 1.0 / N;
@@ -186,22 +197,24 @@ void walker_main(vrc_ctx *ctx, const vrc_walker_config *cfg, const Geometry G, i
             (rate <= 0 && static_cast<int64_t>(buf[0].size()) >= cfg->flush_rays)) {
             if (!flush()) stop = true;
         }
-        if (elapsed() >= cfg->duration_s) stop = true;
+        if (cfg->duration_s > 0 && elapsed() >= cfg->duration_s) stop = true;
     };
     while (!stop) {
+        if (cfg->max_histories > 0 && started->fetch_add(1) >= cfg->max_histories) break;
+        if (cfg->duration_s > 0 && elapsed() >= cfg->duration_s) break;
         out->histories++;
         double p[3] = {cfg->source[0], cfg->source[1], cfg->source[2]};
         double u[3];
         rng.iso(u[0], u[1], u[2]);
-        emit(p);
+        if (!cfg->tl_only) emit(p);
         while (!stop) {
-            const double d = fly(G, p, u, -std::log(1.0 - rng.uniform()));
+            const double d = fly(G, p, u, -std::log(1.0 - rng.uniform()), tl);
             if (d < 0) break;  // leaked
             for (int a = 0; a < 3; ++a) p[a] += d * u[a];
             out->collisions++;
             if (rng.uniform() < cfg->p_abs) break;  // absorbed
             rng.iso(u[0], u[1], u[2]);
-            emit(p);
+            if (!cfg->tl_only) emit(p);
         }
     }
     if (out->status == VRC_OK) flush();
@@ -214,11 +227,14 @@ extern "C" {
 vrc_status vrc_walkers_run(vrc_ctx *ctx, const vrc_walker_config *cfg, vrc_walker_report *report)
 {
     if (!ctx || !cfg) return set_error(VRC_ERR_INVALID, "null argument");
-    if (!ctx->serve && !cfg->direct) return set_error(VRC_ERR_STATE, "start the serving loop first");
+    if (!ctx->serve && !cfg->direct && !cfg->tl_only) return set_error(VRC_ERR_STATE, "start the serving loop first");
     if (cfg->n_threads < 1 || cfg->n_threads > 256) return set_error(VRC_ERR_INVALID, "n_threads in 1..256");
     if (cfg->rays_per_collision < 1 || cfg->flush_rays < 1 || cfg->flush_us < 0)
         return set_error(VRC_ERR_INVALID, "rays_per_collision, flush_rays >= 1, flush_us >= 0");
-    if (!(cfg->duration_s > 0) && cfg->max_rays <= 0) return set_error(VRC_ERR_INVALID, "set duration_s or max_rays");
+    if (!(cfg->duration_s > 0) && cfg->max_rays <= 0 && cfg->max_histories <= 0)
+        return set_error(VRC_ERR_INVALID, "set duration_s, max_rays or max_histories");
+    if (cfg->tl_only && cfg->max_histories <= 0 && !(cfg->duration_s > 0))
+        return set_error(VRC_ERR_INVALID, "a track-length-only run needs duration_s or max_histories");
     if (!(cfg->p_abs >= 0 && cfg->p_abs <= 1)) return set_error(VRC_ERR_INVALID, "p_abs in [0, 1]");
     if (!(cfg->e_min > 0 && cfg->e_max > cfg->e_min)) return set_error(VRC_ERR_INVALID, "0 < e_min < e_max");
     Geometry G;
@@ -245,13 +261,22 @@ vrc_status vrc_walkers_run(vrc_ctx *ctx, const vrc_walker_config *cfg, vrc_walke
         for (auto &v : ctx->walk_rec) v.clear();
     }
     std::vector<WalkerOut> outs(static_cast<size_t>(cfg->n_threads));
-    std::atomic<int64_t> total{0};
+    const int64_t nvox = static_cast<int64_t>(G.n[0]) * G.n[1] * G.n[2];
+    if (cfg->tl_tally)
+        for (auto &o : outs) o.tl.assign(static_cast<size_t>(nvox), 0.0);
+    std::atomic<int64_t> total{0}, started{0};
     const auto start = Clock::now();
     std::vector<std::thread> th;
-    for (int i = 0; i < cfg->n_threads; ++i) th.emplace_back(walker_main, ctx, cfg, G, i, start, &total, &outs[i]);
+    for (int i = 0; i < cfg->n_threads; ++i)
+        th.emplace_back(walker_main, ctx, cfg, G, i, start, &total, &started, &outs[i]);
     for (auto &t : th) t.join();
+    if (cfg->tl_tally)
+        for (auto &o : outs)
+            for (int64_t v = 0; v < nvox; ++v) cfg->tl_tally[v] += o.tl[static_cast<size_t>(v)];
     vrc_status st = VRC_OK;
-    if (cfg->direct) {
+    if (cfg->tl_only) {
+        // no rays were sent
+    } else if (cfg->direct) {
         (void)hipSetDevice(ctx->device);
         if (hipDeviceSynchronize() != hipSuccess) st = device_error(ctx, hipErrorUnknown, "walker casts");
     } else {

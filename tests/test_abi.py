@@ -82,3 +82,34 @@ def test_create_without_device_is_an_error_not_a_crash(lib):
         pytest.skip("a GPU is present")
     with pytest.raises(vrc.VrcError):
         vrc.vrc_create(0)
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets of the C struct (compiled with gcc)."""
+    import shutil
+    import subprocess
+    import paper_1706_07476_amd as vrc
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [getattr(vrc, n) for n in dir(vrc) if n.startswith("vrc_") and isinstance(getattr(vrc, n), type)
+               and issubclass(getattr(vrc, n), ctypes.Structure)]
+    assert len(structs) >= 8
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st in structs:
+        name = st.__name__
+        assert got[(name, "size")] == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert got[(name, f)] == getattr(st, f).offset, (name, f)

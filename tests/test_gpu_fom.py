@@ -1,0 +1,141 @@
+"""The track-length estimator on the walkers and the efficiency harness (Eqs. 5-6).
+
+* The walkers' track-length tally in a pure absorber (no scattering) has,
+  per history, the mean int_{V_i} exp(-Sigma r) / (4 pi r^2) dV of an
+  isotropic point source (checked by Gauss-Legendre cubature, within four
+  standard errors, on voxels not next to the source).
+* In a scattering problem, the track-length tally of one walk and the GPU's
+  VRC tally of an independent walk agree in the mean (both estimate the
+  expected path length per voxel, Secs. 1-2): |z| < 4 on 99 % of the
+  well-sampled voxels and a mean z^2 below 1.35 (the walkers are
+  multi-threaded, so runs are not bit-reproducible; the bounds allow for it).
+* The history budget is exact, and the harness returns positive, finite
+  eta for a small run.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vrc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1706_07476_amd as vrc_mod
+    vrc_mod.load_library()
+    return vrc_mod
+
+
+@pytest.fixture()
+def ctx(vrc):
+    c = vrc.Context(0)
+    yield c
+    c.close()
+
+
+def gauss_box(f, a, b, n=10):
+    x, wq = np.polynomial.legendre.leggauss(n)
+    pts = [0.5 * (b[i] - a[i]) * x + 0.5 * (b[i] + a[i]) for i in range(3)]
+    ww = [0.5 * (b[i] - a[i]) * wq for i in range(3)]
+    X, Y, Z = np.meshgrid(*pts, indexing="ij")
+    Wt = ww[0][:, None, None] * ww[1][None, :, None] * ww[2][None, None, :]
+    return float(np.sum(Wt * f(X, Y, Z)))
+
+
+def test_track_length_pure_absorber_matches_point_source_integral(ctx):
+    n, h, sig = 9, 1.0, 0.35
+    mesh = W.Mesh(np.zeros(3), np.full(3, h), np.full(3, n, np.int32), np.zeros(n ** 3, np.uint8))
+    src = np.array([4.37, 4.61, 4.52])
+    say("case: track-length, pure absorber 9^3, Sigma 0.35, 40 batches x 20000 histories")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(W.gen.make_xs([W.constant_sigma_table(sig)]))
+    tid = ctx.create_tally(0, "p64")
+    B, H = 40, 20000
+    per = []
+    for b in range(B):
+        tl = np.zeros(mesh.n_voxels)
+        r = ctx.walkers_run(tid, [sig], src, n_threads=4, tl_only=1, max_histories=H, duration_s=0.0, p_abs=1.0,
+                            seed=500 + b, tl=tl)
+        assert r["histories"] == H and r["rays_emitted"] == 0
+        per.append(tl / H)
+    per = np.array(per)
+    mean = per.mean(axis=0)
+    se = per.std(axis=0, ddof=1) / math.sqrt(B)
+    zs = []
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                if max(abs(i - 4), abs(j - 4), abs(k - 4)) < 2:
+                    continue
+                v = i + n * (j + n * k)
+
+                def f(X, Y, Z):
+                    r2 = (X - src[0]) ** 2 + (Y - src[1]) ** 2 + (Z - src[2]) ** 2
+                    return np.exp(-sig * np.sqrt(r2)) / (4 * math.pi * r2)
+
+                exact = gauss_box(f, (i, j, k), (i + 1, j + 1, k + 1), n=12)
+                zs.append((mean[v] - exact) / se[v])
+    zs = np.abs(np.array(zs))
+    say(f"  {zs.size} voxels: max |z| {zs.max():.2f}, frac |z|<4 {np.mean(zs < 4):.4f}")
+    assert np.mean(zs < 4) > 0.99
+    assert zs.max() < 6
+
+
+def test_track_length_and_vrc_agree_in_the_mean(vrc, ctx):
+    from paper_1706_07476_amd import fom
+    mesh = W.sphere_mesh(24, 1.0, 6.0)
+    xs = W.gen.make_xs([W.constant_sigma_table(0.1), W.constant_sigma_table(1.0)])
+    say("case: track-length vs VRC, sphere 24^3, 60 batches x 20000 histories, 4 rays per collision")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    tid = ctx.create_tally(0, "p64")
+    centre = mesh.lo + 0.5 * mesh.n * mesh.h + 0.01
+    res = fom.efficiency(ctx, tid, mesh.n_voxels, [0.1, 1.0], centre, batches=60, histories=20000, n_threads=8,
+                         rays_per_collision=4, seed=77, region=np.asarray(mesh.mat) == 1)
+    sm = res["summary"]
+    ok = res["ok"]
+    z = np.abs(res["z"][ok])
+    say(f"  {ok.sum()} voxels: frac |z|<4 {np.mean(z < 4):.4f}, chi2/voxel {np.mean(z * z):.3f}; "
+        f"eta median {sm['all']['eta_median']:.3g} (sphere {sm['region'].get('eta_median', float('nan')):.3g})")
+    assert ok.sum() >= 500  # voxels where both relative errors of the mean are below 10 %
+    assert np.mean(z < 4) >= 0.99
+    # z is t-like (two means, 59 degrees of freedom each, skewed batch totals): E[z^2] a little above 1
+    # without bias; a bias of a fraction of the standard error in many voxels would exceed the bound
+    assert float(np.mean(z * z)) < 1.35
+    assert sm["histories_tl"] == sm["histories_vrc"] == 60 * 20000
+    e = res["eta"][ok]
+    assert np.all(np.isfinite(e)) and np.all(e > 0)
+
+
+def test_walker_budget_and_validation(vrc, ctx):
+    mesh = W.sphere_mesh(16, 1.0, 4.0)
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(W.gen.make_xs([W.constant_sigma_table(0.1), W.constant_sigma_table(1.0)]))
+    tid = ctx.create_tally(0, "p64")
+    centre = mesh.lo + 0.5 * mesh.n * mesh.h + 0.01
+    say("case: walker history budget, direct casts")
+    r = ctx.walkers_run(tid, [0.1, 1.0], centre, n_threads=8, direct=1, max_histories=12345, duration_s=0.0,
+                        rays_per_collision=3, seed=5)
+    assert r["histories"] == 12345
+    # 3 rays at every source event and at every scatter (a collision that is not an absorption)
+    assert r["rays_emitted"] % 3 == 0
+    assert 3 * r["histories"] <= r["rays_emitted"] <= 3 * (r["histories"] + r["collisions"])
+    assert r["rays_submitted"] == r["rays_emitted"]
+    assert ctx.read(tid).sum() > 0
+    # a track-length run needs a history budget or a duration
+    with pytest.raises(vrc.VrcError):
+        ctx.walkers_run(tid, [0.1, 1.0], centre, tl_only=1, duration_s=0.0)
+    with pytest.raises(TypeError):
+        ctx.walkers_run(tid, [0.1, 1.0], centre, tl_only=1, max_histories=10, tl=np.zeros(mesh.n_voxels, np.float32))
