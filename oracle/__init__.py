@@ -5,7 +5,9 @@ CPU-baseline leg may use this package; the GPU library never does.  The
 oracle computes, in double precision and in the order the method states it:
 Sigma_t(E) per material by table lookup and linear interpolation (Sec. 3),
 the voxels a ray crosses with their lengths (Sec. 3), and the VRC score
-W e^{-tau_in} (1 - e^{-Sigma l}) / Sigma of every crossed voxel (Eqs. 1-4).
+W e^{-tau_in} (1 - e^{-Sigma l}) / Sigma of every crossed voxel (Eqs. 1-4);
+and the next-event (point-detector) score w e^{-tau} / (4 pi r^2) of an
+event seen from a detector point (Sec. 6.3).
 """
 from __future__ import annotations
 
@@ -243,3 +245,45 @@ def cast(mesh, xs, rays, edges=None, n_threads: int = 1, with_stats: bool = True
     if rc != 0:
         raise RuntimeError(f"oracle cast failed ({rc})")
     return CastResult(tally, sq, cnt, stats, secs.value, arrs[0].size)
+
+
+# --------------------------------------------------------------------------
+# next-event (point-detector) estimator (Sec. 6.3)
+# --------------------------------------------------------------------------
+
+def next_event(mesh, xs, px, py, pz, E, w, det, precision: str = "f64") -> np.ndarray:
+    """Next-event scores of events (points p, energies E, weights w) at the detector point det.
+
+    Sec. 6.3: a ray is cast from each source or collision event to the
+    estimator's location.  For an isotropic event the score is the density of
+    reaching det without a collision, w e^{-tau} / (4 pi r^2), with
+    r = |det - p| and tau the optical depth of the segment from p to det: the
+    sum over the voxels the ray crosses of Sigma_m(E) times the length of the
+    piece that lies between p and det (vacuum outside the mesh).  r = 0 scores
+    0.  The direction is (det - p) / r in the traversal precision; the pieces
+    come from this oracle's own traversal; tau and the score are summed in FP64.
+    """
+    dt = np.float64 if precision == "f64" else np.float32
+    px, py, pz = (np.asarray(a, dt) for a in (px, py, pz))
+    D = np.asarray(det, dt)
+    sig = sigma_all(xs, np.asarray(E, np.float64))
+    mat = np.asarray(mesh.mat)
+    out = np.zeros(px.size)
+    for i in range(px.size):
+        d = np.array([D[0] - px[i], D[1] - py[i], D[2] - pz[i]], dt)
+        r = dt(np.sqrt(dt(dt(d[0] * d[0] + d[1] * d[1]) + d[2] * d[2])))
+        if not r > 0:
+            continue
+        u = np.array([d[0] / r, d[1] / r, d[2] / r], dt)
+        vox, ln, (t0, _) = trace(mesh, np.array([px[i], py[i], pz[i]], dt), u, precision)
+        tau = 0.0
+        a = float(t0)
+        for v, l in zip(vox, ln):
+            if a >= float(r):
+                break
+            b = a + float(l)
+            tau += sig[i, mat[v]] * (min(b, float(r)) - a)
+            a = b
+        rr = [float(D[k]) - float(p) for k, p in enumerate((px[i], py[i], pz[i]))]
+        out[i] = float(w[i]) * np.exp(-tau) / (4.0 * np.pi * (rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2]))
+    return out
