@@ -392,6 +392,28 @@ vrc_status vrc_walkers_run(vrc_ctx *ctx, const vrc_walker_config *config, vrc_wa
 vrc_status vrc_walkers_take(vrc_ctx *ctx, double *ox, double *oy, double *oz, double *ux, double *uy, double *uz,
                             double *e, double *w, int64_t cap, int64_t *n);
 
+/* ---- next-event (point-detector) estimator ---------------------------- */
+
+/* Sec. 6.3: the next-event estimator casts a ray from each source or
+ * collision event to the estimator's location.  For n events (points
+ * px, py, pz in cm, energies e in MeV, weights w; device arrays of double if
+ * fp64 = 1, else float, owned by the caller and read until the work on the
+ * stream completes) and the detector point `detector` (cm, host), writes
+ * scores[i] = w_i e^{-tau_i} / (4 pi r_i^2) to the caller's device array of
+ * n doubles: r_i = |detector - p_i|, tau_i the optical depth of the segment
+ * from p_i to the detector through mesh `mesh_id` with the context's cross
+ * sections Sigma_m(e_i) (vacuum outside the mesh); the score of an isotropic
+ * event for the density of reaching the detector without a collision.  An
+ * event at the detector (r_i = 0) scores 0.  The walk runs in FP64 for
+ * VRC_P64, else in FP32; tau and the score are summed in FP64.  Runs on
+ * hip_stream (NULL: the default stream) and returns without waiting.
+ * Errors: VRC_ERR_INVALID (no such mesh, unknown precision, null arrays,
+ * non-finite detector, n out of range), VRC_ERR_STATE (no cross sections,
+ * material ids beyond the tables), VRC_ERR_DEVICE.                          */
+vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision, int64_t n, int32_t fp64,
+                          const void *px, const void *py, const void *pz, const void *e, const void *w,
+                          const double detector[3], double *scores, void *hip_stream);
+
 /* ---- inspection hooks (not on the timed path) ------------------------- */
 
 /* Number of positive-length voxel segments of every ray of a batch on mesh

@@ -144,6 +144,7 @@ _SIGNATURES = {
     "vrc_serve_stop": [_P],
     "vrc_walkers_run": [_P, ctypes.POINTER(vrc_walker_config), ctypes.POINTER(vrc_walker_report)],
     "vrc_walkers_take": [_P] + [_PD] * 8 + [_I64, _PI64],
+    "vrc_next_event": [_P, ctypes.c_int32, _I, _I64, ctypes.c_int32, _P, _P, _P, _P, _P, _PD, _P, _P],
 }
 _STRING_FUNCS = {"vrc_last_error": [], "vrc_version": []}
 
@@ -369,6 +370,30 @@ def vrc_trace_rays(ctx: int, tally_id: int, batch: vrc_ray_batch, cap: Optional[
     return offs, vox[:k], ln[:k], sc[:k]
 
 
+def vrc_next_event(ctx: int, mesh_id: int, precision, points, e, w, detector, scores, stream=None) -> None:
+    """Next-event scores of events at `points` (3 device arrays px, py, pz), energies `e`, weights `w`
+    (all float32 or all float64 device tensors, contiguous, equal length) into `scores` (float64
+    device tensor of the same length) for the detector point `detector` (3 floats)."""
+    import torch
+    arrs = list(points) + [e, w]
+    if len(arrs) != 5:
+        raise ValueError("points is (px, py, pz)")
+    dt = arrs[0].dtype
+    n = arrs[0].numel()
+    for a in arrs:
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.is_contiguous() and a.dtype == dt and a.numel() == n):
+            raise TypeError("events are contiguous device tensors of one dtype and length")
+    if dt not in (torch.float32, torch.float64):
+        raise TypeError("events are float32 or float64")
+    if not (isinstance(scores, torch.Tensor) and scores.is_cuda and scores.dtype == torch.float64
+            and scores.is_contiguous() and scores.numel() == n):
+        raise TypeError("scores is a contiguous float64 device tensor of the events' length")
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    det = (ctypes.c_double * 3)(*[float(v) for v in detector])
+    _check(load_library().vrc_next_event(ctx, mesh_id, prec, n, 1 if dt == torch.float64 else 0,
+                                         *[_ptr(a) for a in arrs], det, _ptr(scores), _stream(stream)))
+
+
 def make_batches(items):
     """ctypes array of vrc_batch from (tally_id, [8 device arrays]) pairs."""
     arr = (vrc_batch * max(1, len(items)))()
@@ -547,6 +572,9 @@ class Context:
 
     def read(self, tally_id: int) -> np.ndarray:
         return vrc_read_tally(self.handle, tally_id)
+
+    def next_event(self, mesh_id: int, precision, points, e, w, detector, scores, stream=None) -> None:
+        vrc_next_event(self.handle, mesh_id, precision, points, e, w, detector, scores, stream)
 
     def load(self, tally_id: int, values) -> None:
         vrc_load_tally(self.handle, tally_id, values)

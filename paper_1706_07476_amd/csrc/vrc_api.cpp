@@ -465,6 +465,35 @@ vrc_status vrc_cast_rays(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch,
     return mark_stage_used(ctx, slot, s);
 }
 
+vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision, int64_t n, int32_t fp64,
+                          const void *px, const void *py, const void *pz, const void *e, const void *w,
+                          const double detector[3], double *scores, void *hip_stream)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    if (n < 0 || n > (int64_t(1) << 40)) return set_error(VRC_ERR_INVALID, "event count out of range");
+    if (fp64 != 0 && fp64 != 1) return set_error(VRC_ERR_INVALID, "fp64 must be 0 or 1");
+    if (precision != VRC_P64 && precision != VRC_P32_T64 && precision != VRC_P32_KAHAN && precision != VRC_P32_D64)
+        return set_error(VRC_ERR_INVALID, "unknown precision");
+    if (!detector) return set_error(VRC_ERR_INVALID, "null detector point");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(detector[a])) return set_error(VRC_ERR_INVALID, "detector point must be finite");
+    if (n == 0) return VRC_OK;
+    if (!px || !py || !pz || !e || !w || !scores) return set_error(VRC_ERR_INVALID, "null event or score array");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
+        return set_error(VRC_ERR_INVALID, "no such mesh");
+    const MeshHost &mesh = ctx->meshes[mesh_id];
+    if (!ctx->xs.set) return set_error(VRC_ERR_STATE, "no cross-section tables set");
+    if (mesh.max_mat >= ctx->xs.n_mat) return set_error(VRC_ERR_STATE, "mesh has a material id >= n_mat");
+    if (precision != VRC_P64 && !ctx->xs.f32_ok)
+        return set_error(VRC_ERR_INVALID, "energy grid is not strictly increasing once rounded to FP32");
+    (void)hipSetDevice(ctx->device);
+    hipError_t err = launch_next_event(*ctx, mesh, precision, n, fp64 != 0, px, py, pz, e, w, detector, scores,
+                                       static_cast<hipStream_t>(hip_stream));
+    if (err != hipSuccess) return device_error(ctx, err, "next-event kernel launch");
+    return VRC_OK;
+}
+
 vrc_status vrc_read_tally(vrc_ctx *ctx, int tally_id, double *out)
 {
     if (vrc_status s = check_ctx(ctx)) return s;

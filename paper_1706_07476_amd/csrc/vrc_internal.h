@@ -290,6 +290,9 @@ hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precisi
 hipError_t launch_batched(const vrc_ctx &ctx, const BatchedShape &shape, vrc_precision prec, bool rays_fp64,
                           const unsigned char *d_buf, hipStream_t s);
 hipError_t launch_tally_to_f64(const TallyHost &t, double *out, hipStream_t s);
+hipError_t launch_next_event(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, int64_t n, bool fp64,
+                             const void *px, const void *py, const void *pz, const void *e, const void *w,
+                             const double det[3], double *scores, hipStream_t s);
 hipError_t launch_tally_from_f64(const TallyHost &t, const double *in, hipStream_t s);
 
 }  // namespace vrc

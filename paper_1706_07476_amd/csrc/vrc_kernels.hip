@@ -120,6 +120,67 @@ __global__ void __launch_bounds__(256) count_total_kernel(MeshP<R> M, RaysP rays
     if (threadIdx.x == 0 && part[0] != 0) atomicAdd(total, part[0]);
 }
 
+// Next-event (point-detector) estimator, Sec. 6.3: a ray from every event
+// to the detector point.  The walk is the cast's, with its exit moved to the
+// detector; instead of scoring voxels it sums the optical depth (in FP64) of
+// the pieces between the event and the detector.
+template <typename R>
+struct TauSink {
+    const R (*sig)[2];
+    int stride;
+    double tau;
+    __device__ __forceinline__ void operator()(int32_t, int m, R len, int, int, int, R)
+    {
+        tau += static_cast<double>(sig[m * stride][0] * len);
+    }
+};
+
+struct EventsP {
+    const void *px, *py, *pz, *e, *w;
+    int64_t n;
+};
+
+// scores[i] = w e^{-tau} / (4 pi r^2); the walk in R, tau and the score in FP64
+// (r^2 from the event and detector coordinates in FP64); r = 0 scores 0.
+template <typename R, typename RT>
+__global__ void __launch_bounds__(256) next_event_kernel(MeshP<R> M, XsP<R> X, int hash_in_lds, EventsP ev,
+                                                         double dx, double dy, double dz, double *scores)
+{
+    const int32_t *hash;
+    R(*sig)[2];
+    stage_lds(X, hash_in_lds, hash, sig);
+    const int bd = blockDim.x;
+    R(*mysig)[2] = sig + threadIdx.x;
+    const R Dx = static_cast<R>(dx), Dy = static_cast<R>(dy), Dz = static_cast<R>(dz);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * bd;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * bd + threadIdx.x; i < ev.n; i += stride) {
+        const RT qx = static_cast<const RT *>(ev.px)[i], qy = static_cast<const RT *>(ev.py)[i],
+                 qz = static_cast<const RT *>(ev.pz)[i];
+        const R ox = static_cast<R>(qx), oy = static_cast<R>(qy), oz = static_cast<R>(qz);
+        const R ax = Dx - ox, ay = Dy - oy, az = Dz - oz;
+        const R d = sqrt((ax * ax + ay * ay) + az * az);
+        double score = 0.0;
+        if (d > R(0)) {
+            const R E = static_cast<R>(static_cast<const RT *>(ev.e)[i]);
+            xs_lookup(X, hash, E, mysig, bd);
+            TauSink<R> ts{mysig, bd, 0.0};
+            Walker<R> wk;
+            if (wk.start(M, ox, oy, oz, ax / d, ay / d, az / d)) {
+                if (d < wk.t_exit) wk.t_exit = d;
+                const MeshMaterials mats{M.mat};
+                while (wk.step(M, ts, mats)) {
+                }
+            }
+            const double rx = dx - static_cast<double>(qx), ry = dy - static_cast<double>(qy),
+                         rz = dz - static_cast<double>(qz);
+            const double r2 = (rx * rx + ry * ry) + rz * rz;
+            const double w = static_cast<double>(static_cast<const RT *>(ev.w)[i]);
+            score = w * exp(-ts.tau) / (4.0 * 3.14159265358979323846 * r2);
+        }
+        scores[i] = score;
+    }
+}
+
 __global__ void fill_zero_kernel(uint32_t *p, size_t n_words)
 {
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
@@ -382,6 +443,43 @@ hipError_t launch_tally_from_f64(const TallyHost &t, const double *in, hipStream
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(kahan_from_f64_kernel, dim3(static_cast<unsigned>(grid)), dim3(block), 0, s,
                        static_cast<float *>(t.d_data), in, n);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_next_event(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, int64_t n, bool fp64,
+                             const void *px, const void *py, const void *pz, const void *e, const void *w,
+                             const double det[3], double *scores, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const EventsP ev{px, py, pz, e, w, n};
+    int block;
+    bool hash;
+    size_t lds;
+    const bool r64 = prec == VRC_P64;
+    const bool ok = r64 ? pick_shape<double>(ctx.xs, 256, true, block, hash, lds)
+                        : pick_shape<float>(ctx.xs, 256, true, block, hash, lds);
+    if (!ok) return hipErrorInvalidConfiguration;
+    const int grid = grid_for(ctx, n, block);
+    if (r64) {
+        const MeshP<double> M = mesh_args<double>(m);
+        const XsP<double> X = xs_args<double>(ctx.xs);
+        if (fp64)
+            hipLaunchKernelGGL((next_event_kernel<double, double>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
+                               ev, det[0], det[1], det[2], scores);
+        else
+            hipLaunchKernelGGL((next_event_kernel<double, float>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
+                               ev, det[0], det[1], det[2], scores);
+    } else {
+        const MeshP<float> M = mesh_args<float>(m);
+        const XsP<float> X = xs_args<float>(ctx.xs);
+        if (fp64)
+            hipLaunchKernelGGL((next_event_kernel<float, double>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
+                               ev, det[0], det[1], det[2], scores);
+        else
+            hipLaunchKernelGGL((next_event_kernel<float, float>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
+                               ev, det[0], det[1], det[2], scores);
+    }
     return hipGetLastError();
 }
 
