@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--fom", type=int, default=1,
                     help="also measure eta, the VRC estimator's figure of merit over the track-length estimator's")
     ap.add_argument("--fom-batches", type=int, default=20)
+    ap.add_argument("--next-event", type=int, default=1,
+                    help="also time the next-event (point-detector) estimator on the multimat mesh")
     ap.add_argument("--fom-histories", type=int, default=100000)
     ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
@@ -176,6 +178,49 @@ def time_casts(vrc, ctx, tid, arrays, steps, warmup, stream, torch):
     per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])  # ms, per launch
     total_ms = ev[0].elapsed_time(ev[steps])
     return per, total_ms, wall
+
+
+def bench_next_event(vrc, ctx, wl, torch, stream, steps: int = 20) -> dict:
+    """Next-event estimator (Sec. 6.3) on the multimat mesh: the workload's 1e6 ray origins as events
+    (their energies and weights), the detector at the mesh centre, FP32 walk (p32_t64), float events.
+
+    Reported: events per second (HIP events around `steps` launches) and the
+    pieces walked per event, counted with the oracle's traversal on a sample
+    of 2000 events, giving an estimate of the segments per second.
+    """
+    import oracle
+
+    m = wl.mesh
+    det = tuple(float(v) for v in (m.lo + 0.5 * m.n * m.h + np.array([0.013, -0.021, 0.017])))
+    r = wl.rays
+    dev = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0") for a in (r.ox, r.oy, r.oz, r.e, r.w)]
+    out = torch.empty(r.n, dtype=torch.float64, device="cuda:0")
+    for _ in range(3):
+        ctx.next_event(0, "p32_t64", dev[:3], dev[3], dev[4], det, out, stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        ctx.next_event(0, "p32_t64", dev[:3], dev[3], dev[4], det, out, stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    # pieces per event on a sample (FP32 traversal of the oracle, truncated at the detector)
+    pieces = []
+    D = np.array(det, np.float32)
+    for i in range(2000):
+        p = np.array([r.ox[i], r.oy[i], r.oz[i]], np.float32)
+        d = D - p
+        dist = np.float32(np.sqrt(np.float32(np.float32(d[0] * d[0] + d[1] * d[1]) + d[2] * d[2])))
+        vox, ln, (t0, _) = oracle.trace(m, p, d / dist, "f32")
+        starts = float(t0) + np.concatenate([[0.0], np.cumsum(ln.astype(np.float64))[:-1]])
+        pieces.append(int(np.sum(starts < float(dist))))
+    per_event = float(np.mean(pieces))
+    eps = r.n / (ms / 1e3)
+    return {"workload": "multimat 100^3 mesh and tables; the 1e6 ray origins, energies and weights as events; "
+                        "detector at the mesh centre; FP32 walk, float events", "events": r.n,
+            "ms_per_launch": ms, "events_per_s": eps, "pieces_per_event_sampled": per_event,
+            "segments_per_s_estimate": eps * per_event}
 
 
 def cpu_baseline(wl, target_s):
@@ -544,6 +589,15 @@ def main():
     serving = None
     if args.serving:
         serving = bench_serving(args.serving_seconds)
+    next_event = None
+    if args.next_event:
+        try:
+            next_event = bench_next_event(vrc, ctx, wl, torch, stream)
+            log(f"bench: next-event {next_event['events_per_s']:.3e} events/s "
+                f"({next_event['pieces_per_event_sampled']:.1f} pieces per event)")
+        except Exception as exc:  # the headline line must still be printed
+            log(f"bench: next-event measurement failed: {exc!r}")
+            next_event = {"error": repr(exc)}
     fom_form = None
     if args.fom:
         try:
@@ -596,6 +650,7 @@ def main():
         "batched_form": batched,
         "serving_form": serving,
         "fom_form": fom_form,
+        "next_event_form": next_event,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)
