@@ -251,9 +251,11 @@ __device__ __forceinline__ void load_ray(const RaySrc &S, int64_t r, R &ox, R &o
 // Ordering of the rays by estimated length, longest first (a counting sort
 // over the whole batch, through the same block-row scans as the records):
 // order_hist counts each block's rays per length bucket, order_scatter
-// writes each ray, as one record, to its place.
+// writes each ray, as one record, to its place.  Few large blocks: the
+// block-row scans that follow are shorter, and each thread has few rays.
+constexpr int kOrderBlock = 1024;
 template <typename R, typename RT>
-__global__ void __launch_bounds__(256) order_hist_kernel(MeshP<R> M, RaySrc src, int64_t n, int64_t rays_per_block,
+__global__ void __launch_bounds__(kOrderBlock) order_hist_kernel(MeshP<R> M, RaySrc src, int64_t n, int64_t rays_per_block,
                                                          int shift, uint8_t *bucket, uint32_t *hist)
 {
     __shared__ uint32_t s_hist[kBucketsE];
@@ -284,7 +286,7 @@ struct __align__(16) RayRec {
 };
 
 template <typename R, typename RT>
-__global__ void __launch_bounds__(256) order_scatter_kernel(RaySrc src, int64_t n, const uint8_t *bucket,
+__global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(RaySrc src, int64_t n, const uint8_t *bucket,
                                                             int64_t rays_per_block, const uint32_t *row_off,
                                                             const uint32_t *key_base, RayRec<R> *ordered)
 {
@@ -967,7 +969,7 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
                       const SortGeom &g, int flush, hipStream_t s)
 {
     SortScratch &sc = ctx.sort_scratch;
-    const int G = ctx.n_cu * 8;
+    const int G = ctx.n_cu * 2;  // blocks of the ordering pass (a run of rays each)
     const int ntz = g.n_tiles / (g.ntx * g.nty);
     const int64_t per_ray = static_cast<int64_t>(g.ntx) + g.nty + ntz;  // > tiles a ray can cross
     const size_t rec = sizeof(Entry<R, S>);
@@ -1047,12 +1049,12 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         uint32_t *row_off = static_cast<uint32_t *>(sc.row_off);
         uint32_t *key_tot = static_cast<uint32_t *>(sc.key_tot);
         uint32_t *key_base = static_cast<uint32_t *>(sc.key_base);
-        hipLaunchKernelGGL((order_hist_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, mesh, sub, nr, rays_block, shift,
+        hipLaunchKernelGGL((order_hist_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, mesh, sub, nr, rays_block, shift,
                            static_cast<uint8_t *>(sc.bucket), hist);
         hipLaunchKernelGGL(scan_rows_kernel, dim3(kBucketsE / 64), dim3(64 * kScanWaves), 0, s, hist, G, kBucketsE,
                            row_off, key_tot);
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, key_tot, kBucketsE, key_base);
-        hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kBlock), 0, s, sub, nr,
+        hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, sub, nr,
                            static_cast<const uint8_t *>(sc.bucket), rays_block, row_off, key_base,
                            static_cast<RayRec<R> *>(sc.ordered));
         hipLaunchKernelGGL((count_entries_kernel<R>), dim3(Ge), dim3(kBlock), 0, s, A);
