@@ -405,11 +405,17 @@ vrc_status vrc_walkers_take(vrc_ctx *ctx, double *ox, double *oy, double *oz, do
  * sections Sigma_m(e_i) (vacuum outside the mesh); the score of an isotropic
  * event for the density of reaching the detector without a collision.  An
  * event at the detector (r_i = 0) scores 0.  The walk runs in FP64 for
- * VRC_P64, else in FP32; tau and the score are summed in FP64.  Runs on
- * hip_stream (NULL: the default stream) and returns without waiting.
+ * VRC_P64, else in FP32; tau and the score are summed in FP64.  From 65536
+ * events on, the events are first ordered by estimated path length (so the
+ * lanes of a wavefront walk about equally far; the scores are the same bit
+ * for bit), in scratch device memory shared with the tile-split
+ * accumulation: grown on demand (the first call of a larger n allocates and
+ * is not capturable in a graph), and such calls of one context are
+ * serialised with the tile-split casts.  Runs on hip_stream (NULL: the
+ * default stream) and returns without waiting.
  * Errors: VRC_ERR_INVALID (no such mesh, unknown precision, null arrays,
  * non-finite detector, n out of range), VRC_ERR_STATE (no cross sections,
- * material ids beyond the tables), VRC_ERR_DEVICE.                          */
+ * material ids beyond the tables), VRC_ERR_NOMEM (scratch), VRC_ERR_DEVICE. */
 vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision, int64_t n, int32_t fp64,
                           const void *px, const void *py, const void *pz, const void *e, const void *w,
                           const double detector[3], double *scores, void *hip_stream);

@@ -488,8 +488,13 @@ vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision
     if (precision != VRC_P64 && !ctx->xs.f32_ok)
         return set_error(VRC_ERR_INVALID, "energy grid is not strictly increasing once rounded to FP32");
     (void)hipSetDevice(ctx->device);
-    hipError_t err = launch_next_event(*ctx, mesh, precision, n, fp64 != 0, px, py, pz, e, w, detector, scores,
-                                       static_cast<hipStream_t>(hip_stream));
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const bool ordered = n >= kNextEventOrderMin && next_event_ordered_eligible(*ctx, precision);
+    hipError_t err = ordered ? launch_next_event_ordered(*ctx, mesh, precision, n, fp64 != 0, px, py, pz, e, w,
+                                                         detector, scores, s)
+                             : launch_next_event(*ctx, mesh, precision, n, fp64 != 0, px, py, pz, e, w, detector,
+                                                 scores, s);
+    if (err == hipErrorOutOfMemory) return set_error(VRC_ERR_NOMEM, "scratch of the ordered next-event path");
     if (err != hipSuccess) return device_error(ctx, err, "next-event kernel launch");
     return VRC_OK;
 }

@@ -584,6 +584,47 @@ __device__ __forceinline__ void cast_one(const MeshP<R> &M, const XsP<R> &X, con
     walk(M, ox, oy, oz, ux, uy, uz, sc);
 }
 
+// Next-event (point-detector) estimator, Sec. 6.3: a ray from an event to
+// the detector point.  The walk is the cast's, with its exit moved to the
+// detector; instead of scoring voxels it sums the optical depth (in FP64) of
+// the pieces between the event and the detector.
+template <typename R>
+struct TauSink {
+    const R (*sig)[2];
+    int stride;
+    double tau;
+    __device__ __forceinline__ void operator()(int32_t, int m, R len, int, int, int, R)
+    {
+        tau += static_cast<double>(sig[m * stride][0] * len);
+    }
+};
+
+// w e^{-tau} / (4 pi r^2) of one event at q (input precision RT) seen from
+// the detector D: the walk in R, tau and the score in FP64 (r^2 from the
+// event's and the detector's coordinates in FP64); r = 0 scores 0.
+template <typename R, typename RT>
+__device__ __forceinline__ double next_event_score(const MeshP<R> &M, const XsP<R> &X, const int32_t *hash,
+                                                   R (*mysig)[2], int bd, RT qx, RT qy, RT qz, RT qe, RT qw, R Dx,
+                                                   R Dy, R Dz, double dx, double dy, double dz)
+{
+    const R ox = static_cast<R>(qx), oy = static_cast<R>(qy), oz = static_cast<R>(qz);
+    const R ax = Dx - ox, ay = Dy - oy, az = Dz - oz;
+    const R d = sqrt((ax * ax + ay * ay) + az * az);
+    if (!(d > R(0))) return 0.0;
+    xs_lookup(X, hash, static_cast<R>(qe), mysig, bd);
+    TauSink<R> ts{mysig, bd, 0.0};
+    Walker<R> wk;
+    if (wk.start(M, ox, oy, oz, ax / d, ay / d, az / d)) {
+        if (d < wk.t_exit) wk.t_exit = d;
+        const MeshMaterials mats{M.mat};
+        while (wk.step(M, ts, mats)) {
+        }
+    }
+    const double rx = dx - static_cast<double>(qx), ry = dy - static_cast<double>(qy), rz = dz - static_cast<double>(qz);
+    const double r2 = (rx * rx + ry * ry) + rz * rz;
+    return static_cast<double>(qw) * exp(-ts.tau) / (4.0 * 3.14159265358979323846 * r2);
+}
+
 template <typename P>
 struct Active {
     P inner;

@@ -290,6 +290,11 @@ hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precisi
 hipError_t launch_batched(const vrc_ctx &ctx, const BatchedShape &shape, vrc_precision prec, bool rays_fp64,
                           const unsigned char *d_buf, hipStream_t s);
 hipError_t launch_tally_to_f64(const TallyHost &t, double *out, hipStream_t s);
+bool next_event_ordered_eligible(const vrc_ctx &ctx, vrc_precision prec);
+hipError_t launch_next_event_ordered(vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, int64_t n, bool fp64,
+                                     const void *px, const void *py, const void *pz, const void *e, const void *w,
+                                     const double det[3], double *scores, hipStream_t s);
+constexpr int64_t kNextEventOrderMin = 1 << 16;  // events from which the ordered path pays for its sort
 hipError_t launch_next_event(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, int64_t n, bool fp64,
                              const void *px, const void *py, const void *pz, const void *e, const void *w,
                              const double det[3], double *scores, hipStream_t s);

@@ -120,28 +120,13 @@ __global__ void __launch_bounds__(256) count_total_kernel(MeshP<R> M, RaysP rays
     if (threadIdx.x == 0 && part[0] != 0) atomicAdd(total, part[0]);
 }
 
-// Next-event (point-detector) estimator, Sec. 6.3: a ray from every event
-// to the detector point.  The walk is the cast's, with its exit moved to the
-// detector; instead of scoring voxels it sums the optical depth (in FP64) of
-// the pieces between the event and the detector.
-template <typename R>
-struct TauSink {
-    const R (*sig)[2];
-    int stride;
-    double tau;
-    __device__ __forceinline__ void operator()(int32_t, int m, R len, int, int, int, R)
-    {
-        tau += static_cast<double>(sig[m * stride][0] * len);
-    }
-};
-
 struct EventsP {
     const void *px, *py, *pz, *e, *w;
     int64_t n;
 };
 
-// scores[i] = w e^{-tau} / (4 pi r^2); the walk in R, tau and the score in FP64
-// (r^2 from the event and detector coordinates in FP64); r = 0 scores 0.
+// Next-event (point-detector) estimator, Sec. 6.3, events in input order:
+// scores[i] = w e^{-tau} / (4 pi r^2) (next_event_score).
 template <typename R, typename RT>
 __global__ void __launch_bounds__(256) next_event_kernel(MeshP<R> M, XsP<R> X, int hash_in_lds, EventsP ev,
                                                          double dx, double dy, double dz, double *scores)
@@ -156,28 +141,8 @@ __global__ void __launch_bounds__(256) next_event_kernel(MeshP<R> M, XsP<R> X, i
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * bd + threadIdx.x; i < ev.n; i += stride) {
         const RT qx = static_cast<const RT *>(ev.px)[i], qy = static_cast<const RT *>(ev.py)[i],
                  qz = static_cast<const RT *>(ev.pz)[i];
-        const R ox = static_cast<R>(qx), oy = static_cast<R>(qy), oz = static_cast<R>(qz);
-        const R ax = Dx - ox, ay = Dy - oy, az = Dz - oz;
-        const R d = sqrt((ax * ax + ay * ay) + az * az);
-        double score = 0.0;
-        if (d > R(0)) {
-            const R E = static_cast<R>(static_cast<const RT *>(ev.e)[i]);
-            xs_lookup(X, hash, E, mysig, bd);
-            TauSink<R> ts{mysig, bd, 0.0};
-            Walker<R> wk;
-            if (wk.start(M, ox, oy, oz, ax / d, ay / d, az / d)) {
-                if (d < wk.t_exit) wk.t_exit = d;
-                const MeshMaterials mats{M.mat};
-                while (wk.step(M, ts, mats)) {
-                }
-            }
-            const double rx = dx - static_cast<double>(qx), ry = dy - static_cast<double>(qy),
-                         rz = dz - static_cast<double>(qz);
-            const double r2 = (rx * rx + ry * ry) + rz * rz;
-            const double w = static_cast<double>(static_cast<const RT *>(ev.w)[i]);
-            score = w * exp(-ts.tau) / (4.0 * 3.14159265358979323846 * r2);
-        }
-        scores[i] = score;
+        scores[i] = next_event_score<R, RT>(M, X, hash, mysig, bd, qx, qy, qz, static_cast<const RT *>(ev.e)[i],
+                                            static_cast<const RT *>(ev.w)[i], Dx, Dy, Dz, dx, dy, dz);
     }
 }
 

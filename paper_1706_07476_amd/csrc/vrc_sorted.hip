@@ -303,6 +303,97 @@ __global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(RaySrc src, 
     }
 }
 
+// Next-event events (Sec. 6.3) in the same counting sort: by the voxel
+// distance between the event and the detector (each clamped into the mesh),
+// longest first, as records in the input precision with their index, so
+// that the lanes of a wavefront walk about equally far and every score goes
+// back to its event's place.
+template <typename T>
+struct __align__(16) EventRec {
+    T px, py, pz, e, w;
+    int64_t idx;
+};
+
+struct EventArrays {
+    const void *px, *py, *pz, *e, *w;
+};
+
+template <typename R>
+__device__ __forceinline__ int event_pieces_estimate(const MeshP<R> &M, R px, R py, R pz, R dx, R dy, R dz)
+{
+    const R gx = R(1) / M.h[0], gy = R(1) / M.h[1], gz = R(1) / M.h[2];
+    return iabs(axis_index(px, M.lo[0], gx, M.n[0]) - axis_index(dx, M.lo[0], gx, M.n[0])) +
+           iabs(axis_index(py, M.lo[1], gy, M.n[1]) - axis_index(dy, M.lo[1], gy, M.n[1])) +
+           iabs(axis_index(pz, M.lo[2], gz, M.n[2]) - axis_index(dz, M.lo[2], gz, M.n[2])) + 1;
+}
+
+template <typename R, typename RT>
+__global__ void __launch_bounds__(kOrderBlock) order_hist_events_kernel(MeshP<R> M, EventArrays ev, int64_t n,
+                                                                        int64_t per_block, int shift, R dx, R dy,
+                                                                        R dz, uint8_t *bucket, uint32_t *hist)
+{
+    __shared__ uint32_t s_hist[kBucketsE];
+    for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) s_hist[k] = 0u;
+    __syncthreads();
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * per_block;
+    const int64_t last = first + per_block < n ? first + per_block : n;
+    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
+        const R px = ld<R, RT>(ev.px, i), py = ld<R, RT>(ev.py, i), pz = ld<R, RT>(ev.pz, i);
+        const int bk = event_pieces_estimate(M, px, py, pz, dx, dy, dz) >> shift;
+        const int slot = kBucketsE - 1 - (bk < kBucketsE ? bk : kBucketsE - 1);  // longest first
+        bucket[i] = static_cast<uint8_t>(slot);
+        atomicAdd(&s_hist[slot], 1u);
+    }
+    __syncthreads();
+    uint32_t *row = hist + static_cast<int64_t>(blockIdx.x) * kBucketsE;
+    for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) row[k] = s_hist[k];
+}
+
+template <typename RT>
+__global__ void __launch_bounds__(kOrderBlock) order_scatter_events_kernel(EventArrays ev, int64_t n,
+                                                                           const uint8_t *bucket, int64_t per_block,
+                                                                           const uint32_t *row_off,
+                                                                           const uint32_t *key_base,
+                                                                           EventRec<RT> *ordered)
+{
+    __shared__ uint32_t s_base[kBucketsE];
+    const uint32_t *row = row_off + static_cast<int64_t>(blockIdx.x) * kBucketsE;
+    for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) s_base[k] = key_base[k] + row[k];
+    __syncthreads();
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * per_block;
+    const int64_t last = first + per_block < n ? first + per_block : n;
+    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
+        EventRec<RT> r;
+        r.px = static_cast<const RT *>(ev.px)[i];
+        r.py = static_cast<const RT *>(ev.py)[i];
+        r.pz = static_cast<const RT *>(ev.pz)[i];
+        r.e = static_cast<const RT *>(ev.e)[i];
+        r.w = static_cast<const RT *>(ev.w)[i];
+        r.idx = i;
+        ordered[atomicAdd(&s_base[bucket[i]], 1u)] = r;
+    }
+}
+
+// The ordered events, consecutive ones to the lanes of a wavefront.
+template <typename R, typename RT>
+__global__ void __launch_bounds__(256) next_event_ordered_kernel(MeshP<R> M, XsP<R> X, const EventRec<RT> *ev,
+                                                                 int64_t n, double dx, double dy, double dz,
+                                                                 double *scores)
+{
+    const int32_t *hash;
+    R(*sig)[2];
+    stage_lds(X, 0, hash, sig);
+    const int bd = blockDim.x;
+    R(*mysig)[2] = sig + threadIdx.x;
+    const R Dx = static_cast<R>(dx), Dy = static_cast<R>(dy), Dz = static_cast<R>(dz);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * bd;
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * bd + threadIdx.x; j < n; j += stride) {
+        const EventRec<RT> r = ev[j];
+        scores[r.idx] = next_event_score<R, RT>(M, X, hash, mysig, bd, r.px, r.py, r.pz, r.e, r.w, Dx, Dy, Dz, dx,
+                                                dy, dz);
+    }
+}
+
 template <typename R>
 struct EntryArgs {
     MeshP<R> mesh;
@@ -1131,6 +1222,85 @@ hipError_t dispatch_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
 }
 
 }  // namespace
+
+namespace {
+
+template <typename R, typename RT>
+hipError_t run_next_event_ordered(vrc_ctx &ctx, const MeshHost &m, int64_t n, const EventArrays &ev,
+                                  const double det[3], double *scores, hipStream_t s)
+{
+    SortScratch &sc = ctx.sort_scratch;
+    const int G = ctx.n_cu * 2;
+    const int64_t per_block = (n + G - 1) / G;
+    int shift = 0;
+    while (((static_cast<int64_t>(m.n[0]) + m.n[1] + m.n[2]) >> shift) >= kBucketsE) ++shift;
+    if (sc.busy && sc.stream != s) {
+        hipError_t e = hipStreamWaitEvent(s, sc.done, 0);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = grow(sc.bucket, sc.bucket_cap, static_cast<size_t>(n));
+    if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * static_cast<size_t>(G) * kBucketsE);
+    if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * static_cast<size_t>(G) * kBucketsE);
+    if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (kBucketsE + 1));
+    if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (kBucketsE + 1));
+    if (e == hipSuccess) e = grow(sc.ordered, sc.ordered_cap, sizeof(EventRec<RT>) * static_cast<size_t>(n));
+    if (e != hipSuccess) return e;
+    MeshP<R> M;
+    for (int a = 0; a < 3; ++a) {
+        M.lo[a] = static_cast<R>(m.lo[a]);
+        M.h[a] = static_cast<R>(m.h[a]);
+        M.n[a] = m.n[a];
+    }
+    M.mat = m.d_mat;
+    uint32_t *hist = static_cast<uint32_t *>(sc.hist);
+    uint32_t *row_off = static_cast<uint32_t *>(sc.row_off);
+    uint32_t *key_tot = static_cast<uint32_t *>(sc.key_tot);
+    uint32_t *key_base = static_cast<uint32_t *>(sc.key_base);
+    hipLaunchKernelGGL((order_hist_events_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, M, ev, n, per_block, shift,
+                       static_cast<R>(det[0]), static_cast<R>(det[1]), static_cast<R>(det[2]),
+                       static_cast<uint8_t *>(sc.bucket), hist);
+    hipLaunchKernelGGL(scan_rows_kernel, dim3(kBucketsE / 64), dim3(64 * kScanWaves), 0, s, hist, G, kBucketsE,
+                       row_off, key_tot);
+    hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, key_tot, kBucketsE, key_base);
+    hipLaunchKernelGGL((order_scatter_events_kernel<RT>), dim3(G), dim3(kOrderBlock), 0, s, ev, n,
+                       static_cast<const uint8_t *>(sc.bucket), per_block, row_off, key_base,
+                       static_cast<EventRec<RT> *>(sc.ordered));
+    const size_t lds = sigma_lds(ctx, sizeof(R), 256);
+    int64_t grid = (n + 255) / 256;
+    const int64_t cap = static_cast<int64_t>(ctx.n_cu) * 8;
+    if (grid > cap) grid = cap;
+    hipLaunchKernelGGL((next_event_ordered_kernel<R, RT>), dim3(static_cast<unsigned>(grid)), dim3(256), lds, s, M,
+                       xs_of<R>(ctx.xs), static_cast<const EventRec<RT> *>(sc.ordered), n, det[0], det[1], det[2],
+                       scores);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(sc.done, s);
+    if (e != hipSuccess) return e;
+    sc.busy = true;
+    sc.stream = s;
+    return hipSuccess;
+}
+
+}  // namespace
+
+bool next_event_ordered_eligible(const vrc_ctx &ctx, vrc_precision prec)
+{
+    const size_t sb = prec == VRC_P64 ? sizeof(double) : sizeof(float);
+    return ctx.sort_scratch.done != nullptr && sigma_lds(ctx, sb, 256) <= kLdsMax;
+}
+
+hipError_t launch_next_event_ordered(vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, int64_t n, bool fp64,
+                                     const void *px, const void *py, const void *pz, const void *e, const void *w,
+                                     const double det[3], double *scores, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const EventArrays ev{px, py, pz, e, w};
+    if (prec == VRC_P64)
+        return fp64 ? run_next_event_ordered<double, double>(ctx, m, n, ev, det, scores, s)
+                    : run_next_event_ordered<double, float>(ctx, m, n, ev, det, scores, s);
+    return fp64 ? run_next_event_ordered<float, double>(ctx, m, n, ev, det, scores, s)
+                : run_next_event_ordered<float, float>(ctx, m, n, ev, det, scores, s);
+}
 
 hipError_t launch_cast_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays, bool rays_fp64,
                               bool atomic_flush, hipStream_t s)

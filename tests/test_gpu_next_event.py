@@ -143,3 +143,38 @@ def test_edge_cases(vrc, ctx):
     with pytest.raises(vrc.VrcError):
         one = torch.zeros(1, dtype=torch.float64, device="cuda:0")
         ctx.next_event(0, "p64", [one] * 3, one, one, (float("nan"), 0.0, 0.0), one)
+
+
+@pytest.mark.parametrize("dtype,prec", [("f64", "p64"), ("f32", "p32_t64")])
+def test_ordered_path_equals_input_order_path(ctx, dtype, prec):
+    """From 65536 events the events are first ordered by estimated path length; every score is the
+    same bit for bit as from the events in input order (two calls below the threshold), and a
+    sample matches the oracle."""
+    import torch
+    mesh = W.slab_mesh(816, 48, 0.5, slab=6)
+    xs = W.gen.three_material_xs(817, 2000)
+    n = 70_001
+    p, e, w = events(818, mesh, n, margin=2.0)
+    det = (11.3, 12.1, 9.6)
+    say(f"case: next-event ordered path {prec}, {n} events, slab 48^3")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    dev = [torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda:0") for a in (p[:, 0], p[:, 1], p[:, 2], e, w)]
+    ordered = torch.full((n,), -1.0, dtype=torch.float64, device="cuda:0")
+    ctx.next_event(0, prec, dev[:3], dev[3], dev[4], det, ordered)
+    plain = torch.full((n,), -1.0, dtype=torch.float64, device="cuda:0")
+    h = n // 2
+    ctx.next_event(0, prec, [a[:h] for a in dev[:3]], dev[3][:h], dev[4][:h], det, plain[:h])
+    ctx.next_event(0, prec, [a[h:] for a in dev[:3]], dev[3][h:], dev[4][h:], det, plain[h:])
+    torch.cuda.synchronize()
+    a, b = ordered.cpu().numpy(), plain.cpu().numpy()
+    assert np.all(a >= 0.0)
+    assert np.array_equal(a, b)
+    if dtype == "f64":
+        idx = np.arange(0, n, 35)
+        ref = oracle.next_event(mesh, xs, p[idx, 0], p[idx, 1], p[idx, 2], e[idx], w[idx], det)
+        pos = ref > 1e-300
+        rel = np.abs(a[idx][pos] - ref[pos]) / ref[pos]
+        say(f"  sample of {idx.size}: max rel vs oracle {rel.max():.3e}")
+        assert rel.max() <= 1e-12
