@@ -106,7 +106,7 @@ typedef struct {
  * tile-split modes apply when the tally has at most 4096 (tile, energy bin)
  * pairs and the cross-section columns fit in LDS; otherwise the atomic path
  * runs.  They use scratch device memory grown on demand (about n_rays *
- * (tiles along x + y + z) * 48..96 bytes, at most about 4 GB per sub-launch),
+ * (tiles along x + y + z) * 48..96 bytes, at most about 2 GB per sub-launch),
  * so the first cast of a larger batch allocates and is not capturable in a
  * graph; tile-split casts of one context are serialised with each other.
  * block and blocks_per_cu apply to the atomic path.  The scores are
