@@ -71,6 +71,18 @@ def _p(a: Optional[np.ndarray], ct):
     return a.ctypes.data_as(ct)
 
 
+def _geom(mesh, dtype):
+    """(lo, h) as the C oracle takes them: a uniform mesh's origin and spacing, or, for a
+    rectilinear mesh, its x, y and z plane tables one after the other and h = None."""
+    if hasattr(mesh, "planes"):
+        return _c(np.concatenate([np.asarray(p, np.float64) for p in mesh.planes]), dtype), None
+    return _c(mesh.lo, dtype), _c(mesh.h, dtype)
+
+
+def _addr(a) -> int:
+    return 0 if a is None else a.ctypes.data
+
+
 def _c(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
 
@@ -117,14 +129,14 @@ def trace(mesh, o, u, precision: str = "f64"):
     n = _c(mesh.n, np.int32)
     vox = np.empty(cap, np.int64)
     if precision == "f64":
-        lo, h = _c(mesh.lo, np.float64), _c(mesh.h, np.float64)
+        lo, h = _geom(mesh, np.float64)
         oo, uu = _c(o, np.float64), _c(u, np.float64)
         ln = np.empty(cap, np.float64)
         span = np.empty(2, np.float64)
         k = lib().oracle_trace_f64(_p(lo, _d), _p(h, _d), _p(n, _i32), _p(oo, _d), _p(uu, _d), cap,
                                    _p(vox, _i64), _p(ln, _d), _p(span, _d))
     elif precision == "f32":
-        lo, h = _c(mesh.lo, np.float32), _c(mesh.h, np.float32)
+        lo, h = _geom(mesh, np.float32)
         oo, uu = _c(o, np.float32), _c(u, np.float32)
         ln = np.empty(cap, np.float32)
         span = np.empty(2, np.float32)
@@ -141,7 +153,7 @@ def trace_many(mesh, rays, precision: str = "f64"):
     """CSR traces of a ray batch: (offs[n+1], vox, len) in the given traversal precision."""
     dt, ct = (np.float64, _d) if precision == "f64" else (np.float32, _f)
     fn = lib().oracle_trace_many_f64 if precision == "f64" else lib().oracle_trace_many_f32
-    lo, h = _c(mesh.lo, dt), _c(mesh.h, dt)
+    lo, h = _geom(mesh, dt)
     n = _c(mesh.n, np.int32)
     arrs = [_c(getattr(rays, f), dt) for f in ("ox", "oy", "oz", "ux", "uy", "uz")]
     nr = arrs[0].size
@@ -163,11 +175,11 @@ def trace_many(mesh, rays, precision: str = "f64"):
 def count_segments(mesh, rays, precision: str = "f64", n_threads: int = 1) -> np.ndarray:
     """Number of positive-length segments of every ray, in FP64 or FP32 traversal."""
     dt = np.float64 if precision == "f64" else np.float32
-    lo, h = _c(mesh.lo, dt), _c(mesh.h, dt)
+    lo, h = _geom(mesh, dt)
     n = _c(mesh.n, np.int32)
     arrs = [_c(getattr(rays, f), dt) for f in ("ox", "oy", "oz", "ux", "uy", "uz")]
     counts = np.empty(arrs[0].size, np.int64)
-    tot = lib().oracle_count_many(1 if precision == "f64" else 0, lo.ctypes.data, h.ctypes.data, _p(n, _i32),
+    tot = lib().oracle_count_many(1 if precision == "f64" else 0, _addr(lo), _addr(h), _p(n, _i32),
                                   arrs[0].size, *[a.ctypes.data for a in arrs], int(n_threads), _p(counts, _i64))
     if tot < 0:
         raise RuntimeError("oracle count failed")
@@ -181,7 +193,7 @@ def count_segments(mesh, rays, precision: str = "f64", n_threads: int = 1) -> np
 def ray_scores(mesh, xs, o, u, E, w, edges=None):
     """(vox, len, score, bin) of one ray, all in FP64."""
     cap = _cap(mesh)
-    lo, h = _c(mesh.lo, np.float64), _c(mesh.h, np.float64)
+    lo, h = _geom(mesh, np.float64)
     n = _c(mesh.n, np.int32)
     mat = _c(mesh.mat, np.uint8)
     offs, en, sg = _c(xs.offs, np.int64), _c(xs.energy, np.float64), _c(xs.sigma, np.float64)
@@ -225,7 +237,7 @@ class CastResult:
 
 def cast(mesh, xs, rays, edges=None, n_threads: int = 1, with_stats: bool = True) -> CastResult:
     """Tally of a whole ray batch, FP64; shape (n_bins, n_voxels)."""
-    lo, h = _c(mesh.lo, np.float64), _c(mesh.h, np.float64)
+    lo, h = _geom(mesh, np.float64)
     n = _c(mesh.n, np.int32)
     mat = _c(mesh.mat, np.uint8)
     offs, en, sg = _c(xs.offs, np.int64), _c(xs.energy, np.float64), _c(xs.sigma, np.float64)

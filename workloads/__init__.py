@@ -8,6 +8,8 @@ inputs from here without sharing any of the method's code.
 
 from .gen import (  # noqa: F401
     Mesh,
+    RectMesh,
+    rect_mesh,
     XSTables,
     Rays,
     Workload,

@@ -56,6 +56,47 @@ class Mesh:
 
 
 @dataclasses.dataclass
+class RectMesh:
+    """Rectilinear mesh: per axis a table of n_a + 1 increasing planes (cm)."""
+    planes: list  # 3 arrays of float64
+    mat: np.ndarray  # (nx*ny*nz,) uint8, x fastest
+
+    @property
+    def n(self) -> np.ndarray:
+        return np.array([p.size - 1 for p in self.planes], np.int32)
+
+    @property
+    def lo(self) -> np.ndarray:
+        return np.array([p[0] for p in self.planes], np.float64)
+
+    @property
+    def hi(self) -> np.ndarray:
+        return np.array([p[-1] for p in self.planes], np.float64)
+
+    @property
+    def n_voxels(self) -> int:
+        return int(np.prod(self.n.astype(np.int64)))
+
+    def check(self) -> None:
+        assert len(self.planes) == 3
+        for p in self.planes:
+            assert p.ndim == 1 and p.size >= 2 and np.all(np.diff(p) > 0)
+        assert self.mat.dtype == np.uint8 and self.mat.size == self.n_voxels
+
+
+def rect_mesh(seed: int, n, lo=(0.0, 0.0, 0.0), h_min: float = 0.2, h_max: float = 1.5, n_mat: int = 3,
+              slab: int = 4) -> RectMesh:
+    """Rectilinear mesh with spacings drawn uniformly in [h_min, h_max] per plane, materials per z slab."""
+    rng = _rng(seed)
+    planes = [lo[a] + np.concatenate([[0.0], np.cumsum(rng.uniform(h_min, h_max, int(n[a])))]) for a in range(3)]
+    nz_slabs = (int(n[2]) + slab - 1) // slab
+    slab_mat = rng.integers(0, n_mat, nz_slabs).astype(np.uint8)
+    mat = np.repeat(slab_mat, slab)[: int(n[2])]
+    vol = np.broadcast_to(mat[:, None, None], (int(n[2]), int(n[1]), int(n[0]))).reshape(-1).copy()
+    return RectMesh(planes, vol)
+
+
+@dataclasses.dataclass
 class XSTables:
     offs: np.ndarray  # (n_mat+1,) int64
     energy: np.ndarray  # float64 MeV, concatenated per material
@@ -288,7 +329,7 @@ def _finish_rays(rng, ox, oy, oz, weights: str, w_value: float = 1.0) -> Rays:
 
 def rays_in_box(seed: int, mesh: Mesh, n: int, weights: str = "lognormal", w_value: float = 1.0) -> Rays:
     rng = _rng(seed)
-    hi = mesh.lo + mesh.n * mesh.h
+    hi = mesh.hi if isinstance(mesh, RectMesh) else mesh.lo + mesh.n * mesh.h
     o = [rng.uniform(mesh.lo[a], hi[a], n) for a in range(3)]
     return _finish_rays(rng, *o, weights=weights, w_value=w_value)
 
