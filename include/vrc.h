@@ -143,6 +143,23 @@ const char *vrc_version(void);
 vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const double h[3],
                         const int32_t n[3], const uint8_t *mat);
 
+/* Define (or replace) mesh `mesh_id` as a rectilinear mesh: the Cartesian
+ * mesh of Sec. 3 with unequal spacing, voxel (i,j,k) spanning
+ * [x_planes[i], x_planes[i+1]) x [y_planes[j], ...) x [z_planes[k], ...).
+ * n > 0 (at most 2^20 per axis, fewer than 2^31 voxels); each plane table
+ * has n[a]+1 finite, strictly increasing host values in cm, copied (FP64,
+ * and an FP32 copy for the FP32 traversal forms).  mat as in vrc_set_mesh.
+ * The traversal is the same 3D DDA with the next plane read from the table
+ * instead of lo + k h.  Rectilinear meshes are cast by vrc_cast_rays (plain
+ * accumulation only: accumulate 1..3 fall back to it), vrc_trace_rays and
+ * vrc_count_segments; the batched, serving, walker and next-event calls
+ * return VRC_ERR_INVALID on them.  Tallies in an FP32 form are refused
+ * (VRC_ERR_INVALID at cast time) when two planes of an axis round to the
+ * same float.  Errors: VRC_ERR_INVALID (bad n or planes), VRC_ERR_STATE (a
+ * tally uses the mesh), VRC_ERR_NOMEM.                                     */
+vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], const double *x_planes,
+                             const double *y_planes, const double *z_planes, const uint8_t *mat);
+
 /* Total macroscopic cross sections Sigma_t(E) of n_mat materials (1..64).
  * Material m's table is energy_MeV[offs[m] .. offs[m+1]) (strictly
  * increasing, > 0) with values sigma_per_cm[...] (>= 0, finite); offs has

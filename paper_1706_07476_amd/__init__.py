@@ -119,6 +119,7 @@ _SIGNATURES = {
     "vrc_create": [_I, ctypes.POINTER(_P)],
     "vrc_destroy": [_P],
     "vrc_set_mesh": [_P, _I, _PD, _PD, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8)],
+    "vrc_set_mesh_rect": [_P, _I, ctypes.POINTER(ctypes.c_int32), _PD, _PD, _PD, ctypes.POINTER(ctypes.c_uint8)],
     "vrc_set_xs_tables": [_P, _I, _PI64, _PD, _PD],
     "vrc_create_tally": [_P, _I, _I, _PD, _I, ctypes.POINTER(_I)],
     "vrc_destroy_tally": [_P, _I],
@@ -274,6 +275,23 @@ def vrc_set_mesh(ctx: int, mesh_id: int, lo, h, n, mat) -> None:
     _check(load_library().vrc_set_mesh(ctx, mesh_id, lo.ctypes.data_as(_PD), h.ctypes.data_as(_PD),
                                        n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        mat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+
+
+def vrc_set_mesh_rect(ctx: int, mesh_id: int, planes, mat) -> None:
+    """Rectilinear mesh: planes = three increasing plane tables (x, y, z) of n[a] + 1 values."""
+    if len(planes) != 3:
+        raise ValueError("three plane tables are needed")
+    pl = [np.ascontiguousarray(p, np.float64) for p in planes]
+    if any(p.ndim != 1 or p.size < 2 for p in pl):
+        raise ValueError("each plane table needs at least two planes")
+    n = np.array([p.size - 1 for p in pl], np.int32)
+    mat = np.ascontiguousarray(mat, np.uint8)
+    if mat.size != int(np.prod(n.astype(np.int64))):
+        raise ValueError("mesh arrays have the wrong size")
+    _check(load_library().vrc_set_mesh_rect(ctx, mesh_id, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            pl[0].ctypes.data_as(_PD), pl[1].ctypes.data_as(_PD),
+                                            pl[2].ctypes.data_as(_PD),
+                                            mat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
 
 
 def vrc_set_xs_tables(ctx: int, offs, energy, sigma) -> None:
@@ -555,7 +573,11 @@ class Context:
             pass
 
     def set_mesh(self, mesh_id: int, mesh) -> None:
-        vrc_set_mesh(self.handle, mesh_id, mesh.lo, mesh.h, mesh.n, mesh.mat)
+        """A uniform mesh (lo, h, n, mat) or a rectilinear one (planes, mat)."""
+        if hasattr(mesh, "planes"):
+            vrc_set_mesh_rect(self.handle, mesh_id, mesh.planes, mesh.mat)
+        else:
+            vrc_set_mesh(self.handle, mesh_id, mesh.lo, mesh.h, mesh.n, mesh.mat)
 
     def set_xs(self, xs) -> None:
         vrc_set_xs_tables(self.handle, xs.offs, xs.energy, xs.sigma)

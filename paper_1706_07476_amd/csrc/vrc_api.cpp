@@ -154,6 +154,87 @@ vrc_status mark_stage_used(vrc_ctx *ctx, int slot, hipStream_t s)
     return VRC_OK;
 }
 
+// Store mesh `mesh_id` (arguments already checked except n and the voxel
+// count).  planes == nullptr: uniform mesh lo + k h; otherwise the three
+// plane tables of a rectilinear mesh (lo and h then only describe it).
+vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const double h[3], const int32_t n[3],
+                      const uint8_t *mat, const double *const *planes)
+{
+    int64_t nvox = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] <= 0 || n[a] > (1 << 20)) return set_error(VRC_ERR_INVALID, "n must be in 1..2^20 per axis");
+        nvox *= n[a];
+    }
+    if (nvox >= (int64_t(1) << 31)) return set_error(VRC_ERR_INVALID, "mesh too large (at most 2^31-1 voxels)");
+    MeshHost &m = ctx->meshes[mesh_id];
+    if (m.users > 0) return set_error(VRC_ERR_STATE, "mesh is used by a tally");
+    (void)hipSetDevice(ctx->device);
+    int max_mat = 0;
+    for (int64_t i = 0; i < nvox; ++i) max_mat = std::max(max_mat, static_cast<int>(mat[i]));
+    free_dev(m.d_mat);
+    free_dev(m.d_pl64);
+    free_dev(m.d_pl32);
+    m.set = false;
+    m.rect = false;
+    m.rect_f32_ok = false;
+    m.h_planes.clear();
+    void *d = nullptr;
+    if (vrc_status s = upload(ctx, &d, mat, static_cast<size_t>(nvox))) return s;
+    m.d_mat = static_cast<uint8_t *>(d);
+    if (planes) {
+        std::vector<float> p32;
+        bool f32_ok = true;
+        for (int a = 0; a < 3; ++a) {
+            for (int k = 0; k <= n[a]; ++k) {
+                m.h_planes.push_back(planes[a][k]);
+                const float f = static_cast<float>(planes[a][k]);
+                if (k > 0 && !(f > p32.back())) f32_ok = false;
+                p32.push_back(f);
+            }
+        }
+        if (vrc_status s = upload(ctx, &d, m.h_planes.data(), sizeof(double) * m.h_planes.size())) {
+            free_dev(m.d_mat);
+            return s;
+        }
+        m.d_pl64 = static_cast<double *>(d);
+        if (vrc_status s = upload(ctx, &d, p32.data(), sizeof(float) * p32.size())) {
+            free_dev(m.d_mat);
+            free_dev(m.d_pl64);
+            return s;
+        }
+        m.d_pl32 = static_cast<float *>(d);
+        m.rect = true;
+        m.rect_f32_ok = f32_ok;
+    }
+    for (int a = 0; a < 3; ++a) {
+        m.lo[a] = lo[a];
+        m.h[a] = h[a];
+        m.n[a] = n[a];
+    }
+    m.nvox = nvox;
+    m.max_mat = max_mat;
+    m.h_mat.assign(mat, mat + nvox);
+    m.set = true;
+    // Device descriptors read by the batched kernels.  A rectilinear mesh is
+    // not cast there (refused before launch); its descriptor has n = 0, which
+    // any traversal treats as an empty mesh.
+    MeshP<float> m32;
+    MeshP<double> m64;
+    for (int a = 0; a < 3; ++a) {
+        m32.lo[a] = static_cast<float>(lo[a]);
+        m32.h[a] = static_cast<float>(h[a]);
+        m32.n[a] = m.rect ? 0 : n[a];
+        m64.lo[a] = lo[a];
+        m64.h[a] = h[a];
+        m64.n[a] = m.rect ? 0 : n[a];
+    }
+    m32.mat = m.d_mat;
+    m64.mat = m.d_mat;
+    VRC_HIP(ctx, hipMemcpy(ctx->d_mesh32 + mesh_id, &m32, sizeof(m32), hipMemcpyHostToDevice));
+    VRC_HIP(ctx, hipMemcpy(ctx->d_mesh64 + mesh_id, &m64, sizeof(m64), hipMemcpyHostToDevice));
+    return VRC_OK;
+}
+
 }  // namespace
 
 vrc_status vrc::check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
@@ -164,6 +245,16 @@ vrc_status vrc::check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
     if (m.max_mat >= ctx->xs.n_mat) return set_error(VRC_ERR_STATE, "mesh has a material id >= n_mat");
     if (t->prec != VRC_P64 && !ctx->xs.f32_ok)
         return set_error(VRC_ERR_INVALID, "energy grid is not strictly increasing once rounded to FP32");
+    if (m.rect && t->prec != VRC_P64 && !m.rect_f32_ok)
+        return set_error(VRC_ERR_INVALID, "mesh planes are not strictly increasing once rounded to FP32");
+    return VRC_OK;
+}
+
+vrc_status vrc::check_uniform_mesh(vrc_ctx *ctx, const TallyHost *t, const char *what)
+{
+    if (ctx->meshes[t->mesh_id].rect)
+        return set_error(VRC_ERR_INVALID, std::string(what) + " takes uniform meshes only; cast rays on a "
+                                                               "rectilinear mesh with vrc_cast_rays");
     return VRC_OK;
 }
 
@@ -230,7 +321,11 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
             free_dev(t->d_edges);
         }
     }
-    for (auto &m : ctx->meshes) free_dev(m.d_mat);
+    for (auto &m : ctx->meshes) {
+        free_dev(m.d_mat);
+        free_dev(m.d_pl64);
+        free_dev(m.d_pl32);
+    }
     free_xs(ctx->xs);
     for (auto &st : ctx->stage) {
         if (st.h_buf) (void)hipHostFree(st.h_buf);
@@ -272,48 +367,32 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (mesh_id < 0 || mesh_id >= kMaxMeshes) return set_error(VRC_ERR_INVALID, "mesh_id must be in 0..7");
     if (!lo || !h || !n || !mat) return set_error(VRC_ERR_INVALID, "null mesh argument");
-    int64_t nvox = 1;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 3; ++a)
         if (!(std::isfinite(lo[a]) && std::isfinite(h[a]) && h[a] > 0))
             return set_error(VRC_ERR_INVALID, "lo must be finite and h finite and > 0");
+    return store_mesh(ctx, mesh_id, lo, h, n, mat, nullptr);
+}
+
+vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], const double *x_planes,
+                             const double *y_planes, const double *z_planes, const uint8_t *mat)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (mesh_id < 0 || mesh_id >= kMaxMeshes) return set_error(VRC_ERR_INVALID, "mesh_id must be in 0..7");
+    if (!n || !x_planes || !y_planes || !z_planes || !mat) return set_error(VRC_ERR_INVALID, "null mesh argument");
+    const double *src[3] = {x_planes, y_planes, z_planes};
+    double lo[3], h[3];
+    for (int a = 0; a < 3; ++a) {
         if (n[a] <= 0 || n[a] > (1 << 20)) return set_error(VRC_ERR_INVALID, "n must be in 1..2^20 per axis");
-        nvox *= n[a];
+        for (int k = 0; k <= n[a]; ++k) {
+            if (!std::isfinite(src[a][k])) return set_error(VRC_ERR_INVALID, "planes must be finite");
+            if (k > 0 && !(src[a][k] > src[a][k - 1]))
+                return set_error(VRC_ERR_INVALID, "planes must be strictly increasing");
+        }
+        lo[a] = src[a][0];
+        h[a] = (src[a][n[a]] - src[a][0]) / n[a];  // mean width, informative only
     }
-    if (nvox >= (int64_t(1) << 31)) return set_error(VRC_ERR_INVALID, "mesh too large (at most 2^31-1 voxels)");
-    MeshHost &m = ctx->meshes[mesh_id];
-    if (m.users > 0) return set_error(VRC_ERR_STATE, "mesh is used by a tally");
-    (void)hipSetDevice(ctx->device);
-    int max_mat = 0;
-    for (int64_t i = 0; i < nvox; ++i) max_mat = std::max(max_mat, static_cast<int>(mat[i]));
-    free_dev(m.d_mat);
-    m.set = false;
-    void *d = nullptr;
-    if (vrc_status s = upload(ctx, &d, mat, static_cast<size_t>(nvox))) return s;
-    m.d_mat = static_cast<uint8_t *>(d);
-    for (int a = 0; a < 3; ++a) {
-        m.lo[a] = lo[a];
-        m.h[a] = h[a];
-        m.n[a] = n[a];
-    }
-    m.nvox = nvox;
-    m.max_mat = max_mat;
-    m.h_mat.assign(mat, mat + nvox);
-    m.set = true;
-    MeshP<float> m32;
-    MeshP<double> m64;
-    for (int a = 0; a < 3; ++a) {
-        m32.lo[a] = static_cast<float>(lo[a]);
-        m32.h[a] = static_cast<float>(h[a]);
-        m32.n[a] = n[a];
-        m64.lo[a] = lo[a];
-        m64.h[a] = h[a];
-        m64.n[a] = n[a];
-    }
-    m32.mat = m.d_mat;
-    m64.mat = m.d_mat;
-    VRC_HIP(ctx, hipMemcpy(ctx->d_mesh32 + mesh_id, &m32, sizeof(m32), hipMemcpyHostToDevice));
-    VRC_HIP(ctx, hipMemcpy(ctx->d_mesh64 + mesh_id, &m64, sizeof(m64), hipMemcpyHostToDevice));
-    return VRC_OK;
+    return store_mesh(ctx, mesh_id, lo, h, n, mat, src);
 }
 
 vrc_status vrc_set_xs_tables(vrc_ctx *ctx, int n_mat, const int64_t *offs, const double *energy_MeV,
@@ -483,6 +562,7 @@ vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision
     if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
         return set_error(VRC_ERR_INVALID, "no such mesh");
     const MeshHost &mesh = ctx->meshes[mesh_id];
+    if (mesh.rect) return set_error(VRC_ERR_INVALID, "the next-event estimator takes uniform meshes only");
     if (!ctx->xs.set) return set_error(VRC_ERR_STATE, "no cross-section tables set");
     if (mesh.max_mat >= ctx->xs.n_mat) return set_error(VRC_ERR_STATE, "mesh has a material id >= n_mat");
     if (precision != VRC_P64 && !ctx->xs.f32_ok)
@@ -598,6 +678,10 @@ vrc_status vrc_count_segments(vrc_ctx *ctx, int mesh_id, vrc_precision precision
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
         return set_error(VRC_ERR_INVALID, "mesh_id does not name a set mesh");
+    if (precision != VRC_P64 && precision != VRC_P32_T64 && precision != VRC_P32_KAHAN && precision != VRC_P32_D64)
+        return set_error(VRC_ERR_INVALID, "unknown precision");
+    if (ctx->meshes[mesh_id].rect && precision != VRC_P64 && !ctx->meshes[mesh_id].rect_f32_ok)
+        return set_error(VRC_ERR_INVALID, "mesh planes are not strictly increasing once rounded to FP32");
     (void)hipSetDevice(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     RaysP rays;
@@ -891,6 +975,7 @@ vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batche
         if (prec != static_cast<int>(t->prec)) return set_error(VRC_ERR_INVALID, "tallies of one call must share a precision form");
         if (fp64 != b.fp64) return set_error(VRC_ERR_INVALID, "batches of one call must share the ray type");
         if (vrc_status st = check_cast_ready(ctx, t)) return st;
+        if (vrc_status st = check_uniform_mesh(ctx, t, "the batched cast")) return st;
         if (b.n == 0) continue;
         if (!b.ox || !b.oy || !b.oz || !b.ux || !b.uy || !b.uz || !b.e || !b.w)
             return set_error(VRC_ERR_INVALID, "null ray array in a batch");

@@ -73,45 +73,74 @@ __device__ __forceinline__ int guess_index(R p, R lo, R h, int n)
     return k > n - 1 ? n - 1 : k;
 }
 
-// Start voxel on one axis (the rule in the file header) and its first
-// crossing time.  The guess from the entry point is corrected by a search
-// that only ever moves a step or two.
+// Rectilinear axis: the voxel whose planes bracket p (planes pl[0..n]),
+// clamped into [0, n-1] (NaN -> 0).
 template <typename R>
-__device__ __forceinline__ void start_axis(R lo, R h, int n, R o, R u, R inv, bool par, R t_enter,
-                                           int &idx, R &tn, int &step)
+__device__ __forceinline__ int guess_index_table(R p, const R *pl, int n)
+{
+    if (!(p >= pl[0])) return 0;
+    int lo = 0, hi = n;  // pl[lo] <= p, the answer is below hi
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pl[mid] <= p) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Start voxel on one axis (the rule in the file header) and its first
+// crossing time, planes X(k) from `X`.  The guess from the entry point is
+// corrected by a search that only ever moves a step or two.
+template <typename R, class Planes>
+__device__ __forceinline__ void start_axis_planes(const Planes &X, int n, int guess_o, int guess_p, R o, R u, R inv,
+                                                  bool par, R t_enter, int &idx, R &tn, int &step)
 {
     int k;
     if (par) {
-        k = guess_index(o, lo, h, n);
-        while (k > 0 && plane(lo, h, k) > o) --k;
-        while (k < n - 1 && plane(lo, h, k + 1) <= o) ++k;
+        k = guess_o;
+        while (k > 0 && X(k) > o) --k;
+        while (k < n - 1 && X(k + 1) <= o) ++k;
         tn = Num<R>::inf();
         step = 0;
     } else {
-        const R p = o + t_enter * u;
-        k = guess_index(p, lo, h, n);
+        k = guess_p;
         if (u > R(0)) {
-            while (k > 0 && (plane(lo, h, k) - o) * inv > t_enter) --k;
-            while (k < n - 1 && (plane(lo, h, k + 1) - o) * inv <= t_enter) ++k;
-            tn = (plane(lo, h, k + 1) - o) * inv;
+            while (k > 0 && (X(k) - o) * inv > t_enter) --k;
+            while (k < n - 1 && (X(k + 1) - o) * inv <= t_enter) ++k;
+            tn = (X(k + 1) - o) * inv;
             step = 1;
         } else {
-            while (k > 0 && (plane(lo, h, k) - o) * inv <= t_enter) --k;
-            while (k < n - 1 && (plane(lo, h, k + 1) - o) * inv > t_enter) ++k;
-            tn = (plane(lo, h, k) - o) * inv;
+            while (k > 0 && (X(k) - o) * inv <= t_enter) --k;
+            while (k < n - 1 && (X(k + 1) - o) * inv > t_enter) ++k;
+            tn = (X(k) - o) * inv;
             step = -1;
         }
     }
     idx = k;
 }
 
-// Slab clip on one axis: narrows [t_enter, t_exit]; false if the ray runs
-// parallel to the axis outside the mesh.
 template <typename R>
-__device__ __forceinline__ bool clip_axis(R lo, R h, int n, R o, R inv, bool par, R &t_enter, R &t_exit)
+__device__ __forceinline__ void start_axis(R lo, R h, int n, R o, R u, R inv, bool par, R t_enter,
+                                           int &idx, R &tn, int &step)
 {
-    const R x0 = plane(lo, h, 0);
-    const R x1 = plane(lo, h, n);
+    const auto X = [&](int k) { return plane(lo, h, k); };
+    start_axis_planes(X, n, par ? guess_index(o, lo, h, n) : 0, par ? 0 : guess_index(o + t_enter * u, lo, h, n), o,
+                      u, inv, par, t_enter, idx, tn, step);
+}
+
+template <typename R>
+__device__ __forceinline__ void start_axis_table(const R *pl, int n, R o, R u, R inv, bool par, R t_enter,
+                                                 int &idx, R &tn, int &step)
+{
+    const auto X = [&](int k) { return pl[k]; };
+    start_axis_planes(X, n, par ? guess_index_table(o, pl, n) : 0,
+                      par ? 0 : guess_index_table(o + t_enter * u, pl, n), o, u, inv, par, t_enter, idx, tn, step);
+}
+
+// Slab clip on one axis between its first and last planes x0, x1: narrows
+// [t_enter, t_exit]; false if the ray runs parallel to the axis outside.
+template <typename R>
+__device__ __forceinline__ bool clip_planes(R x0, R x1, R o, R inv, bool par, R &t_enter, R &t_exit)
+{
     if (par) return x0 <= o && o < x1;
     const R ta = (x0 - o) * inv;
     const R tb = (x1 - o) * inv;
@@ -120,6 +149,12 @@ __device__ __forceinline__ bool clip_axis(R lo, R h, int n, R o, R inv, bool par
     if (tmin > t_enter) t_enter = tmin;
     if (tmax < t_exit) t_exit = tmax;
     return true;
+}
+
+template <typename R>
+__device__ __forceinline__ bool clip_axis(R lo, R h, int n, R o, R inv, bool par, R &t_enter, R &t_exit)
+{
+    return clip_planes(plane(lo, h, 0), plane(lo, h, n), o, inv, par, t_enter, t_exit);
 }
 
 // Tiles of 16^3 voxels: the score re-anchors the entering weight at every
@@ -156,7 +191,7 @@ struct TileMaterials {
 // range (the whole mesh, or one tile); it ends when the index it steps to on
 // an axis equals that axis' stop index (one past the range in the direction
 // of travel).
-template <typename R>
+template <typename R, bool RECT = false>  // RECT: the mesh's planes come from its tables
 struct Walker {
     R ox, oy, oz, ix, iy, iz;
     int sx, sy, sz;        // step per axis: +1, -1, 0 (parallel)
@@ -185,14 +220,26 @@ struct Walker {
         const bool px = __builtin_isinf(ix), py = __builtin_isinf(iy), pz = __builtin_isinf(iz);
         R t_enter = R(0);
         t_exit = Num<R>::inf();
-        if (!clip_axis(lox, hx, nx, ox, ix, px, t_enter, t_exit)) return false;
-        if (!clip_axis(loy, hy, ny, oy, iy, py, t_enter, t_exit)) return false;
-        if (!clip_axis(loz, hz, nz, oz, iz, pz, t_enter, t_exit)) return false;
+        if constexpr (RECT) {
+            if (!clip_planes(M.pl[0][0], M.pl[0][nx], ox, ix, px, t_enter, t_exit)) return false;
+            if (!clip_planes(M.pl[1][0], M.pl[1][ny], oy, iy, py, t_enter, t_exit)) return false;
+            if (!clip_planes(M.pl[2][0], M.pl[2][nz], oz, iz, pz, t_enter, t_exit)) return false;
+        } else {
+            if (!clip_axis(lox, hx, nx, ox, ix, px, t_enter, t_exit)) return false;
+            if (!clip_axis(loy, hy, ny, oy, iy, py, t_enter, t_exit)) return false;
+            if (!clip_axis(loz, hz, nz, oz, iz, pz, t_enter, t_exit)) return false;
+        }
         if (!(t_enter < t_exit)) return false;
         if (!(t_exit < Num<R>::inf())) return false;  // zero direction: not a ray
-        start_axis(lox, hx, nx, ox, ux, ix, px, t_enter, kx, tx, sx);
-        start_axis(loy, hy, ny, oy, uy, iy, py, t_enter, ky, ty, sy);
-        start_axis(loz, hz, nz, oz, uz, iz, pz, t_enter, kz, tz, sz);
+        if constexpr (RECT) {
+            start_axis_table(M.pl[0], nx, ox, ux, ix, px, t_enter, kx, tx, sx);
+            start_axis_table(M.pl[1], ny, oy, uy, iy, py, t_enter, ky, ty, sy);
+            start_axis_table(M.pl[2], nz, oz, uz, iz, pz, t_enter, kz, tz, sz);
+        } else {
+            start_axis(lox, hx, nx, ox, ux, ix, px, t_enter, kx, tx, sx);
+            start_axis(loy, hy, ny, oy, uy, iy, py, t_enter, ky, ty, sy);
+            start_axis(loz, hz, nz, oz, uz, iz, pz, t_enter, kz, tz, sz);
+        }
         cur = t_enter;
         budget = nx + ny + nz + 3;
         stop_x = sx > 0 ? nx : -1;
@@ -292,11 +339,18 @@ struct Walker {
         const bool adv = !last && inside;
         vox = adv ? vcur + (ax ? dvx : (ay ? dvy : dvz)) : vcur;
         m = mats(vox, adv && ax ? ni : kx, adv && ay ? ni : ky, adv && az ? ni : kz);  // early: overlaps the score
-        const R plo = ax ? lox : (ay ? loy : loz);
-        const R h = ax ? hx : (ay ? hy : hz);
         const R oa = ax ? ox : (ay ? oy : oz);
         const R inv = ax ? ix : (ay ? iy : iz);
-        const R tnew = (plane(plo, h, ni + (s > 0 ? 1 : 0)) - oa) * inv;
+        R tnew;
+        if constexpr (RECT) {
+            // the next plane's table entry (a plane inside the table when the walk goes on)
+            const R *pa = ax ? M.pl[0] : (ay ? M.pl[1] : M.pl[2]);
+            tnew = (pa[adv ? ni + (s > 0 ? 1 : 0) : 0] - oa) * inv;
+        } else {
+            const R plo = ax ? lox : (ay ? loy : loz);
+            const R h = ax ? hx : (ay ? hy : hz);
+            tnew = (plane(plo, h, ni + (s > 0 ? 1 : 0)) - oa) * inv;
+        }
         kx = adv && ax ? ni : kx;
         ky = adv && ay ? ni : ky;
         kz = adv && az ? ni : kz;
@@ -319,10 +373,10 @@ struct Walker {
 };
 
 // Cast one ray through the whole mesh; false if it misses.
-template <typename R, class Seg>
+template <typename R, class Seg, bool RECT = false>
 __device__ __forceinline__ bool walk(const MeshP<R> &M, R ox, R oy, R oz, R ux, R uy, R uz, Seg &seg)
 {
-    Walker<R> w;
+    Walker<R, RECT> w;
     if (!w.start(M, ox, oy, oz, ux, uy, uz)) return false;
     const MeshMaterials mats{M.mat};
     while (w.step(M, seg, mats)) {
@@ -575,13 +629,13 @@ __device__ __forceinline__ void stage_lds(const XsP<R> &X, int hash_in_lds, cons
 
 // Cross sections of the ray's energy, then the walk (in R) with the running
 // score (in S: R itself, or double over an FP32 walk).
-template <typename R, typename S, class Put>
+template <typename R, typename S, class Put, bool RECT = false>
 __device__ __forceinline__ void cast_one(const MeshP<R> &M, const XsP<R> &X, const int32_t *hash, S (*mysig)[2],
                                          int bd, R ox, R oy, R oz, R ux, R uy, R uz, R E, R w, Put &put)
 {
     xs_lookup(X, hash, E, mysig, bd);
     Scorer<S, Put> sc(mysig, bd, static_cast<S>(w), put);
-    walk(M, ox, oy, oz, ux, uy, uz, sc);
+    walk<R, Scorer<S, Put>, RECT>(M, ox, oy, oz, ux, uy, uz, sc);
 }
 
 // Next-event (point-detector) estimator, Sec. 6.3: a ray from an event to

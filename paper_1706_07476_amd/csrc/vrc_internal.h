@@ -31,6 +31,9 @@ struct MeshP {
     R h[3];
     int32_t n[3];
     const uint8_t *mat;  // n0*n1*n2 material ids, x fastest
+    // rectilinear mesh: per axis a device table of n_a + 1 increasing planes
+    // (walks instantiated for rectilinear meshes read these instead of lo + k h)
+    const R *pl[3] = {nullptr, nullptr, nullptr};
 };
 
 // Cross sections on the union energy grid.  E[K] strictly increasing;
@@ -145,6 +148,13 @@ struct MeshHost {
     std::vector<uint8_t> h_mat;  // host copy (used by the CPU walkers)
     double lo[3] = {0, 0, 0};
     double h[3] = {1, 1, 1};
+    // rectilinear meshes: the x, y and z plane tables one after the other
+    // (host FP64, device FP64 and FP32 copies); lo holds the first planes
+    bool rect = false;
+    bool rect_f32_ok = false;  // the planes stay strictly increasing in FP32
+    std::vector<double> h_planes;
+    double *d_pl64 = nullptr;
+    float *d_pl32 = nullptr;
     int32_t n[3] = {0, 0, 0};
     int64_t nvox = 0;
     int max_mat = 0;
@@ -248,6 +258,8 @@ vrc_status set_error(vrc_status st, const std::string &msg);
 vrc_status device_error(vrc_ctx *ctx, hipError_t e, const char *what);
 // Tables, mesh and material ids ready for casting into tally t.
 vrc_status check_cast_ready(vrc_ctx *ctx, const TallyHost *t);
+// VRC_ERR_INVALID when the tally's mesh is rectilinear (`what` names the caller).
+vrc_status check_uniform_mesh(vrc_ctx *ctx, const TallyHost *t, const char *what);
 // Upload a descriptor table through slot bs and run the persistent kernel.
 vrc_status run_batched(vrc_ctx *ctx, BatchedSlot &bs, const BatchedShape &shape, vrc_precision prec, bool fp64,
                        const std::vector<BatchDescDev> &desc, int64_t items, hipStream_t s);

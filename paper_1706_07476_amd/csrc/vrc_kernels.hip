@@ -4,6 +4,8 @@
 // vrc_device.h.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cmath>
 #include <cstdint>
 
@@ -29,7 +31,8 @@ struct CastArgs {
     int hash_in_lds;
 };
 
-template <typename R, typename RT, typename S, class PutMaker>
+// RECT: the mesh is rectilinear (plane tables); otherwise uniform.
+template <typename R, typename RT, typename S, bool RECT, class PutMaker>
 __device__ __forceinline__ void cast_block(const CastArgs<R> &A, PutMaker make_put)
 {
     const int32_t *hash;
@@ -47,41 +50,42 @@ __device__ __forceinline__ void cast_block(const CastArgs<R> &A, PutMaker make_p
         const int bin = energy_bin(A.tally, static_cast<double>(E));
         auto put = make_put(r, bin);
         if (!put.active()) continue;
-        cast_one(A.mesh, A.xs, hash, mysig, bd, ox, oy, oz, ux, uy, uz, E, wt, put.inner);
+        cast_one<R, S, typename std::decay<decltype(put.inner)>::type, RECT>(A.mesh, A.xs, hash, mysig, bd, ox, oy, oz,
+                                                                             ux, uy, uz, E, wt, put.inner);
     }
 }
 
 // S: scoring precision (R, or double over an FP32 walk: the paper's scheme).
-template <typename R, typename RT, bool AGG, typename S>
+template <typename R, typename RT, bool AGG, typename S, bool RECT>
 __global__ void __launch_bounds__(1024) cast_f64_kernel(CastArgs<R> A)
 {
     __shared__ double agg_lds[AGG ? 1024 : 1];
     double *wave_lds = agg_lds + (AGG ? (threadIdx.x & ~63u) : 0);
-    cast_block<R, RT, S>(A, [&](int64_t, int bin) {
+    cast_block<R, RT, S, RECT>(A, [&](int64_t, int bin) {
         return Active<PutF64<AGG>>{PutF64<AGG>{static_cast<double *>(A.tally.data), bin * A.tally.nvox, wave_lds},
                                    bin >= 0};
     });
 }
 
-template <typename RT>
+template <typename RT, bool RECT>
 __global__ void __launch_bounds__(1024) cast_kahan_kernel(CastArgs<float> A)
 {
-    cast_block<float, RT, float>(A, [&](int64_t, int bin) {
+    cast_block<float, RT, float, RECT>(A, [&](int64_t, int bin) {
         return Active<PutKahan>{PutKahan{static_cast<float *>(A.tally.data), bin * A.tally.nvox}, bin >= 0};
     });
 }
 
 // Inspection: the same walk and score, written out as CSR.
-template <typename R, typename RT, typename S>
+template <typename R, typename RT, typename S, bool RECT>
 __global__ void __launch_bounds__(256) trace_kernel(CastArgs<R> A)
 {
-    cast_block<R, RT, S>(A, [&](int64_t r, int bin) {
+    cast_block<R, RT, S, RECT>(A, [&](int64_t r, int bin) {
         return Active<PutTrace>{PutTrace{A.trace.offs[r], A.trace.voxel, A.trace.len, A.trace.score, bin >= 0},
                                 true};
     });
 }
 
-template <typename R, typename RT>
+template <typename R, typename RT, bool RECT>
 __global__ void __launch_bounds__(256) count_kernel(MeshP<R> M, RaysP rays, int64_t *counts)
 {
     const int64_t n = rays.n;
@@ -90,14 +94,14 @@ __global__ void __launch_bounds__(256) count_kernel(MeshP<R> M, RaysP rays, int6
         const R ox = ld<R, RT>(rays.ox, r), oy = ld<R, RT>(rays.oy, r), oz = ld<R, RT>(rays.oz, r);
         const R ux = ld<R, RT>(rays.ux, r), uy = ld<R, RT>(rays.uy, r), uz = ld<R, RT>(rays.uz, r);
         CountSeg c;
-        walk(M, ox, oy, oz, ux, uy, uz, c);
+        walk<R, CountSeg, RECT>(M, ox, oy, oz, ux, uy, uz, c);
         counts[r] = c.n;
     }
 }
 
 // Total segments of a batch: per-lane counts, summed over the block in LDS,
 // one 64-bit atomic per block.
-template <typename R, typename RT>
+template <typename R, typename RT, bool RECT>
 __global__ void __launch_bounds__(256) count_total_kernel(MeshP<R> M, RaysP rays, unsigned long long *total)
 {
     __shared__ unsigned long long part[256];
@@ -108,7 +112,7 @@ __global__ void __launch_bounds__(256) count_total_kernel(MeshP<R> M, RaysP rays
         const R ox = ld<R, RT>(rays.ox, r), oy = ld<R, RT>(rays.oy, r), oz = ld<R, RT>(rays.oz, r);
         const R ux = ld<R, RT>(rays.ux, r), uy = ld<R, RT>(rays.uy, r), uz = ld<R, RT>(rays.uz, r);
         CountSeg c;
-        walk(M, ox, oy, oz, ux, uy, uz, c);
+        walk<R, CountSeg, RECT>(M, ox, oy, oz, ux, uy, uz, c);
         mine += static_cast<unsigned long long>(c.n);
     }
     part[threadIdx.x] = mine;
@@ -175,6 +179,13 @@ __global__ void kahan_from_f64_kernel(float *pairs, const double *in, int64_t n)
 // ---------------------------------------------------------------------------
 
 template <typename R>
+const R *mesh_planes(const MeshHost &m);
+template <>
+const float *mesh_planes<float>(const MeshHost &m) { return m.d_pl32; }
+template <>
+const double *mesh_planes<double>(const MeshHost &m) { return m.d_pl64; }
+
+template <typename R>
 MeshP<R> mesh_args(const MeshHost &m)
 {
     MeshP<R> p;
@@ -184,6 +195,12 @@ MeshP<R> mesh_args(const MeshHost &m)
         p.n[a] = m.n[a];
     }
     p.mat = m.d_mat;
+    if (m.rect) {
+        const R *base = mesh_planes<R>(m);
+        p.pl[0] = base;
+        p.pl[1] = base + m.n[0] + 1;
+        p.pl[2] = base + m.n[0] + 1 + m.n[1] + 1;
+    }
     return p;
 }
 
@@ -235,7 +252,7 @@ bool pick_shape(const XsHost &x, int want_block, bool want_hash, int &block, boo
     return lds <= kLdsLimit;
 }
 
-template <typename R, typename RT, typename S = R>
+template <typename R, typename RT, typename S, bool RECT>
 hipError_t cast_f64_launch(const vrc_ctx &ctx, CastArgs<R> A, hipStream_t s)
 {
     int block;
@@ -246,9 +263,9 @@ hipError_t cast_f64_launch(const vrc_ctx &ctx, CastArgs<R> A, hipStream_t s)
     A.hash_in_lds = hash ? 1 : 0;
     const int grid = grid_for(ctx, A.rays.n, block);
     if (ctx.launch.aggregate)
-        hipLaunchKernelGGL((cast_f64_kernel<R, RT, true, S>), dim3(grid), dim3(block), lds, s, A);
+        hipLaunchKernelGGL((cast_f64_kernel<R, RT, true, S, RECT>), dim3(grid), dim3(block), lds, s, A);
     else
-        hipLaunchKernelGGL((cast_f64_kernel<R, RT, false, S>), dim3(grid), dim3(block), lds, s, A);
+        hipLaunchKernelGGL((cast_f64_kernel<R, RT, false, S, RECT>), dim3(grid), dim3(block), lds, s, A);
     return hipGetLastError();
 }
 
@@ -267,23 +284,24 @@ CastArgs<R> make_args(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m,
 
 }  // namespace
 
-hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
+template <bool RECT>
+hipError_t launch_cast_impl(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
                        bool rays_fp64, hipStream_t s)
 {
     if (rays.n <= 0) return hipSuccess;
     switch (t.prec) {
     case VRC_P64: {
         CastArgs<double> A = make_args<double>(ctx, t, m, rays);
-        return rays_fp64 ? cast_f64_launch<double, double>(ctx, A, s) : cast_f64_launch<double, float>(ctx, A, s);
+        return rays_fp64 ? cast_f64_launch<double, double, double, RECT>(ctx, A, s) : cast_f64_launch<double, float, double, RECT>(ctx, A, s);
     }
     case VRC_P32_T64: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
-        return rays_fp64 ? cast_f64_launch<float, double>(ctx, A, s) : cast_f64_launch<float, float>(ctx, A, s);
+        return rays_fp64 ? cast_f64_launch<float, double, float, RECT>(ctx, A, s) : cast_f64_launch<float, float, float, RECT>(ctx, A, s);
     }
     case VRC_P32_D64: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
-        return rays_fp64 ? cast_f64_launch<float, double, double>(ctx, A, s)
-                         : cast_f64_launch<float, float, double>(ctx, A, s);
+        return rays_fp64 ? cast_f64_launch<float, double, double, RECT>(ctx, A, s)
+                         : cast_f64_launch<float, float, double, RECT>(ctx, A, s);
     }
     case VRC_P32_KAHAN: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
@@ -295,16 +313,17 @@ hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = grid_for(ctx, rays.n, block);
         if (rays_fp64)
-            hipLaunchKernelGGL((cast_kahan_kernel<double>), dim3(grid), dim3(block), lds, s, A);
+            hipLaunchKernelGGL((cast_kahan_kernel<double, RECT>), dim3(grid), dim3(block), lds, s, A);
         else
-            hipLaunchKernelGGL((cast_kahan_kernel<float>), dim3(grid), dim3(block), lds, s, A);
+            hipLaunchKernelGGL((cast_kahan_kernel<float, RECT>), dim3(grid), dim3(block), lds, s, A);
         return hipGetLastError();
     }
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
+template <bool RECT>
+hipError_t launch_trace_impl(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
                         bool rays_fp64, const TraceP &tr, hipStream_t s)
 {
     if (rays.n <= 0) return hipSuccess;
@@ -317,29 +336,30 @@ hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &
         if (!pick_shape<double>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = static_cast<int>((rays.n + block - 1) / block);
-        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<double, double, double>), dim3(grid), dim3(block), lds, s, A);
-        else hipLaunchKernelGGL((trace_kernel<double, float, double>), dim3(grid), dim3(block), lds, s, A);
+        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<double, double, double, RECT>), dim3(grid), dim3(block), lds, s, A);
+        else hipLaunchKernelGGL((trace_kernel<double, float, double, RECT>), dim3(grid), dim3(block), lds, s, A);
     } else if (t.prec == VRC_P32_D64) {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
         A.trace = tr;
         if (!pick_shape<double>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = static_cast<int>((rays.n + block - 1) / block);
-        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, double>), dim3(grid), dim3(block), lds, s, A);
-        else hipLaunchKernelGGL((trace_kernel<float, float, double>), dim3(grid), dim3(block), lds, s, A);
+        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, double, RECT>), dim3(grid), dim3(block), lds, s, A);
+        else hipLaunchKernelGGL((trace_kernel<float, float, double, RECT>), dim3(grid), dim3(block), lds, s, A);
     } else {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
         A.trace = tr;
         if (!pick_shape<float>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = static_cast<int>((rays.n + block - 1) / block);
-        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, float>), dim3(grid), dim3(block), lds, s, A);
-        else hipLaunchKernelGGL((trace_kernel<float, float, float>), dim3(grid), dim3(block), lds, s, A);
+        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, float, RECT>), dim3(grid), dim3(block), lds, s, A);
+        else hipLaunchKernelGGL((trace_kernel<float, float, float, RECT>), dim3(grid), dim3(block), lds, s, A);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
+template <bool RECT>
+hipError_t launch_count_impl(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
                         bool rays_fp64, int64_t *counts, hipStream_t s)
 {
     if (rays.n <= 0) return hipSuccess;
@@ -347,17 +367,18 @@ hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision pre
     const int grid = grid_for(ctx, rays.n, block);
     if (prec == VRC_P64) {
         MeshP<double> M = mesh_args<double>(m);
-        if (rays_fp64) hipLaunchKernelGGL((count_kernel<double, double>), dim3(grid), dim3(block), 0, s, M, rays, counts);
-        else hipLaunchKernelGGL((count_kernel<double, float>), dim3(grid), dim3(block), 0, s, M, rays, counts);
+        if (rays_fp64) hipLaunchKernelGGL((count_kernel<double, double, RECT>), dim3(grid), dim3(block), 0, s, M, rays, counts);
+        else hipLaunchKernelGGL((count_kernel<double, float, RECT>), dim3(grid), dim3(block), 0, s, M, rays, counts);
     } else {
         MeshP<float> M = mesh_args<float>(m);
-        if (rays_fp64) hipLaunchKernelGGL((count_kernel<float, double>), dim3(grid), dim3(block), 0, s, M, rays, counts);
-        else hipLaunchKernelGGL((count_kernel<float, float>), dim3(grid), dim3(block), 0, s, M, rays, counts);
+        if (rays_fp64) hipLaunchKernelGGL((count_kernel<float, double, RECT>), dim3(grid), dim3(block), 0, s, M, rays, counts);
+        else hipLaunchKernelGGL((count_kernel<float, float, RECT>), dim3(grid), dim3(block), 0, s, M, rays, counts);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
+template <bool RECT>
+hipError_t launch_count_total_impl(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
                               bool rays_fp64, unsigned long long *total, hipStream_t s)
 {
     if (rays.n <= 0) return hipSuccess;
@@ -365,14 +386,42 @@ hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precisi
     const int grid = grid_for(ctx, rays.n, block);
     if (prec == VRC_P64) {
         MeshP<double> M = mesh_args<double>(m);
-        if (rays_fp64) hipLaunchKernelGGL((count_total_kernel<double, double>), dim3(grid), dim3(block), 0, s, M, rays, total);
-        else hipLaunchKernelGGL((count_total_kernel<double, float>), dim3(grid), dim3(block), 0, s, M, rays, total);
+        if (rays_fp64) hipLaunchKernelGGL((count_total_kernel<double, double, RECT>), dim3(grid), dim3(block), 0, s, M, rays, total);
+        else hipLaunchKernelGGL((count_total_kernel<double, float, RECT>), dim3(grid), dim3(block), 0, s, M, rays, total);
     } else {
         MeshP<float> M = mesh_args<float>(m);
-        if (rays_fp64) hipLaunchKernelGGL((count_total_kernel<float, double>), dim3(grid), dim3(block), 0, s, M, rays, total);
-        else hipLaunchKernelGGL((count_total_kernel<float, float>), dim3(grid), dim3(block), 0, s, M, rays, total);
+        if (rays_fp64) hipLaunchKernelGGL((count_total_kernel<float, double, RECT>), dim3(grid), dim3(block), 0, s, M, rays, total);
+        else hipLaunchKernelGGL((count_total_kernel<float, float, RECT>), dim3(grid), dim3(block), 0, s, M, rays, total);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
+                       bool rays_fp64, hipStream_t s)
+{
+    return m.rect ? launch_cast_impl<true>(ctx, t, m, rays, rays_fp64, s)
+                  : launch_cast_impl<false>(ctx, t, m, rays, rays_fp64, s);
+}
+
+hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
+                        bool rays_fp64, const TraceP &tr, hipStream_t s)
+{
+    return m.rect ? launch_trace_impl<true>(ctx, t, m, rays, rays_fp64, tr, s)
+                  : launch_trace_impl<false>(ctx, t, m, rays, rays_fp64, tr, s);
+}
+
+hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
+                        bool rays_fp64, int64_t *counts, hipStream_t s)
+{
+    return m.rect ? launch_count_impl<true>(ctx, m, prec, rays, rays_fp64, counts, s)
+                  : launch_count_impl<false>(ctx, m, prec, rays, rays_fp64, counts, s);
+}
+
+hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
+                              bool rays_fp64, unsigned long long *total, hipStream_t s)
+{
+    return m.rect ? launch_count_total_impl<true>(ctx, m, prec, rays, rays_fp64, total, s)
+                  : launch_count_total_impl<false>(ctx, m, prec, rays, rays_fp64, total, s);
 }
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)

@@ -441,6 +441,7 @@ vrc_status vrc_serve_submit(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *bat
         if (tally_id < 0 || tally_id >= static_cast<int>(ctx->tallies.size()) || !ctx->tallies[tally_id])
             return set_error(VRC_ERR_INVALID, "no such tally");
         if (vrc_status st = check_cast_ready(ctx, ctx->tallies[tally_id].get())) return st;
+        if (vrc_status st = check_uniform_mesh(ctx, ctx->tallies[tally_id].get(), "the serving form")) return st;
     }
     const size_t el = batch->fp64 ? 8 : 4;
     const size_t arr = el * static_cast<size_t>(batch->n);

@@ -243,6 +243,7 @@ vrc_status vrc_walkers_run(vrc_ctx *ctx, const vrc_walker_config *cfg, vrc_walke
         const int id = cfg->tally_id;
         if (id < 0 || id >= static_cast<int>(ctx->tallies.size()) || !ctx->tallies[id])
             return set_error(VRC_ERR_INVALID, "no such tally");
+        if (vrc_status st = check_uniform_mesh(ctx, ctx->tallies[id].get(), "the walkers")) return st;
         const MeshHost &m = ctx->meshes[ctx->tallies[id]->mesh_id];
         if (cfg->n_sigma < m.max_mat + 1 || cfg->n_sigma > 64)
             return set_error(VRC_ERR_INVALID, "sigma must cover every material of the mesh");
