@@ -5,7 +5,9 @@ CPU-baseline leg may use this package; the GPU library never does.  The
 oracle computes, in double precision and in the order the method states it:
 Sigma_t(E) per material by table lookup and linear interpolation (Sec. 3),
 the voxels a ray crosses with their lengths (Sec. 3), and the VRC score
-W e^{-tau_in} (1 - e^{-Sigma l}) / Sigma of every crossed voxel (Eqs. 1-4);
+W e^{-tau_in} (1 - e^{-Sigma l}) / Sigma of every crossed voxel (Eqs. 1-4),
+a voxel's Sigma optionally scaled by its density factor and a material
+optionally a mixture of tabulated components;
 and the next-event (point-detector) score w e^{-tau} / (4 pi r^2) of an
 event seen from a detector point (Sec. 6.3).
 """
@@ -52,14 +54,14 @@ def lib():
         L.oracle_trace_many_f64.restype = _ll
         L.oracle_trace_many_f64.argtypes = [_d, _d, _i32, _ll] + [_d] * 6 + [_ll, _i64, _i64, _d]
         L.oracle_ray_scores.restype = _ll
-        L.oracle_ray_scores.argtypes = [_d, _d, _i32, _u8, _int, _i64, _d, _d, _int, _d,
+        L.oracle_ray_scores.argtypes = [_d, _d, _i32, _u8, _int, _i64, _d, _d, _int, _d, _d, _int, _i64, _i32, _d,
                                         _d, _d, ctypes.c_double, ctypes.c_double,
                                         _ll, _i64, _d, _d, ctypes.POINTER(ctypes.c_int)]
         L.oracle_count_many.restype = _ll
         L.oracle_count_many.argtypes = [_int, ctypes.c_void_p, ctypes.c_void_p, _i32, _ll] + [ctypes.c_void_p] * 6 + [
             _int, _i64]
         L.oracle_cast.restype = _int
-        L.oracle_cast.argtypes = ([_d, _d, _i32, _u8, _int, _i64, _d, _d, _int, _d, _ll]
+        L.oracle_cast.argtypes = ([_d, _d, _i32, _u8, _int, _i64, _d, _d, _int, _d, _d, _int, _i64, _i32, _d, _ll]
                                   + [_d] * 8 + [_int, _d, _d, _i64, _i64, _d])
         _lib = L
     return _lib
@@ -190,8 +192,30 @@ def count_segments(mesh, rays, precision: str = "f64", n_threads: int = 1) -> np
 # steps 3-4: scores and tallies
 # --------------------------------------------------------------------------
 
-def ray_scores(mesh, xs, o, u, E, w, edges=None):
-    """(vox, len, score, bin) of one ray, all in FP64."""
+def _density(mesh):
+    """The mesh's per-voxel density factors (FP64), or None."""
+    rho = getattr(mesh, "density", None)
+    if rho is None:
+        return None
+    rho = _c(rho, np.float64)
+    if rho.size != int(np.prod(np.asarray(mesh.n, np.int64))):
+        raise ValueError("one density factor per voxel is needed")
+    return rho
+
+
+def _mixtures(mix):
+    """(n_mix, offs, comp, frac) of a mixture list (offs, comp, frac), or zeros when mix is None."""
+    if mix is None:
+        return 0, None, None, None
+    offs, comp, frac = _c(mix.offs, np.int64), _c(mix.comp, np.int32), _c(mix.frac, np.float64)
+    return offs.size - 1, offs, comp, frac
+
+
+def ray_scores(mesh, xs, o, u, E, w, edges=None, mix=None):
+    """(vox, len, score, bin) of one ray, all in FP64.
+
+    The voxel's Sigma is its material's (a table of xs, or with mix a mixture
+    of them) times the mesh's density factor when it has one."""
     cap = _cap(mesh)
     lo, h = _geom(mesh, np.float64)
     n = _c(mesh.n, np.int32)
@@ -204,8 +228,11 @@ def ray_scores(mesh, xs, o, u, E, w, edges=None):
     ln = np.empty(cap, np.float64)
     sc = np.empty(cap, np.float64)
     b = ctypes.c_int(0)
+    rho = _density(mesh)
+    nm, mo, mc, mf = _mixtures(mix)
     k = lib().oracle_ray_scores(_p(lo, _d), _p(h, _d), _p(n, _i32), _p(mat, _u8), xs.n_mat, _p(offs, _i64),
-                                _p(en, _d), _p(sg, _d), nb, _p(ed, _d), _p(oo, _d), _p(uu, _d),
+                                _p(en, _d), _p(sg, _d), nb, _p(ed, _d), _p(rho, _d), nm, _p(mo, _i64), _p(mc, _i32),
+                                _p(mf, _d), _p(oo, _d), _p(uu, _d),
                                 float(E), float(w), cap, _p(vox, _i64), _p(ln, _d), _p(sc, _d), ctypes.byref(b))
     if k < 0:
         raise RuntimeError("oracle ray_scores failed")
@@ -235,8 +262,10 @@ class CastResult:
         return rel
 
 
-def cast(mesh, xs, rays, edges=None, n_threads: int = 1, with_stats: bool = True) -> CastResult:
-    """Tally of a whole ray batch, FP64; shape (n_bins, n_voxels)."""
+def cast(mesh, xs, rays, edges=None, n_threads: int = 1, with_stats: bool = True, mix=None) -> CastResult:
+    """Tally of a whole ray batch, FP64; shape (n_bins, n_voxels).
+
+    Voxel Sigma as in ray_scores (density factors of the mesh, mixtures mix)."""
     lo, h = _geom(mesh, np.float64)
     n = _c(mesh.n, np.int32)
     mat = _c(mesh.mat, np.uint8)
@@ -250,8 +279,11 @@ def cast(mesh, xs, rays, edges=None, n_threads: int = 1, with_stats: bool = True
     cnt = np.empty((nb, nvox), np.int64) if with_stats else None
     stats = np.zeros(5, np.int64)
     secs = ctypes.c_double(0.0)
+    rho = _density(mesh)
+    nm, mo, mc, mf = _mixtures(mix)
     rc = lib().oracle_cast(_p(lo, _d), _p(h, _d), _p(n, _i32), _p(mat, _u8), xs.n_mat, _p(offs, _i64),
-                           _p(en, _d), _p(sg, _d), nb, _p(ed, _d), arrs[0].size, *[_p(a, _d) for a in arrs],
+                           _p(en, _d), _p(sg, _d), nb, _p(ed, _d), _p(rho, _d), nm, _p(mo, _i64), _p(mc, _i32),
+                           _p(mf, _d), arrs[0].size, *[_p(a, _d) for a in arrs],
                            int(n_threads), _p(tally, _d), _p(sq, _d), _p(cnt, _i64), _p(stats, _i64),
                            ctypes.byref(secs))
     if rc != 0:

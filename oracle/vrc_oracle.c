@@ -12,7 +12,11 @@
  *     cross sections of all materials are found first, by table lookup and
  *     linear interpolation between table points).  Here: binary search for
  *     the bracketing interval, lin-lin interpolation, end values held
- *     outside the table.
+ *     outside the table.  Optionally a material is a mixture of tabulated
+ *     components, Sigma_m(E) = sum_j f_j Sigma_j(E), each component looked
+ *     up on its own table and the terms added in component order; and
+ *     optionally every voxel carries a density factor, the cell's
+ *     Sigma_t,i(E) of Eqs. 1-4 then being rho_i * Sigma_m(E).
  *  2. Trace the ray through the mesh (Sec. 3; trav.inc): the voxels crossed,
  *     in order, with the length in each.
  *  3. Score every crossed voxel i by the VRC estimator (Eq. 4, i.e. the
@@ -36,7 +40,12 @@
  * form, an axis-aligned closed form and fine-step path integration; the
  * tally against exactly rounded sums; the estimator's mean against cubature
  * of a point source and against the track-length estimator of an analog
- * walk.  No function here is left unpinned.
+ * walk.  Density factors and mixtures (tests/test_oracle_density.py): unit
+ * factors and one-component mixtures against the plain tallies, density
+ * levels against scaled tables, closed forms on homogeneous and two-region
+ * meshes, zero density against a void material, mixtures against summed
+ * tables and against numpy's interpolation.  No function here is left
+ * unpinned.
  */
 #include <math.h>
 #include <pthread.h>
@@ -269,7 +278,49 @@ typedef struct {
     const double *energy, *sigma;
     int n_bins;
     const double *edges;
+    const double *rho;       /* per-voxel density factor, or NULL (1 everywhere) */
+    int n_mix;               /* > 0: the mesh's ids name mixtures of the n_mat tables */
+    const int64_t *mix_offs; /* mixture k: components mix_comp[mix_offs[k] .. mix_offs[k+1]) */
+    const int32_t *mix_comp;
+    const double *mix_frac;
 } problem;
+
+/* Sigma of every material id at energy E into sig (n_mat tables, or n_mix
+ * mixtures of them); the number of table lookups outside a table is added to
+ * *clamped when clamped is not NULL.  Returns the number of ids, -1 on a bad
+ * argument. */
+static int material_sigmas(const problem *p, double E, double *sig, int64_t *clamped)
+{
+    double tab[256];
+    if (p->n_mat > 256 || p->n_mix > 256) return -1;
+    for (int m = 0; m < p->n_mat; ++m) {
+        const double *ee = p->energy + p->offs[m];
+        int64_t K = p->offs[m + 1] - p->offs[m];
+        tab[m] = oracle_sigma(ee, p->sigma + p->offs[m], K, E);
+        if (clamped && outside_table(ee, K, E)) ++*clamped;
+    }
+    if (p->n_mix <= 0) {
+        memcpy(sig, tab, sizeof(double) * (size_t)p->n_mat);
+        return p->n_mat;
+    }
+    for (int k = 0; k < p->n_mix; ++k) {
+        double v = 0.0;
+        for (int64_t j = p->mix_offs[k]; j < p->mix_offs[k + 1]; ++j) {
+            int c = p->mix_comp[j];
+            if (c < 0 || c >= p->n_mat) return -1;
+            v += p->mix_frac[j] * tab[c];
+        }
+        sig[k] = v;
+    }
+    return p->n_mix;
+}
+
+/* Sigma of voxel v: its material's Sigma times its density factor */
+static double voxel_sigma(const problem *p, const double *sig, int64_t v)
+{
+    double s = sig[p->mat[v]];
+    return p->rho ? p->rho[v] * s : s;
+}
 
 /* optical depth tau = tau_hi + tau_lo, accumulated with Neumaier's compensated sum */
 typedef struct {
@@ -302,21 +353,21 @@ static double vrc_score(double w, depth tau_in, double sig, double l)
  */
 int64_t oracle_ray_scores(const double *lo, const double *h, const int32_t *n, const uint8_t *mat,
                           int n_mat, const int64_t *offs, const double *energy, const double *sigma,
-                          int n_bins, const double *edges,
+                          int n_bins, const double *edges, const double *rho,
+                          int n_mix, const int64_t *mix_offs, const int32_t *mix_comp, const double *mix_frac,
                           const double *o, const double *u, double E, double w,
                           int64_t cap, int64_t *vox, double *len, double *score, int *bin_out)
 {
+    problem p = {lo, h, n, mat, n_mat, offs, energy, sigma, n_bins, edges, rho, n_mix, mix_offs, mix_comp, mix_frac};
     double sig[256];
-    if (n_mat > 256) return -1;
-    for (int m = 0; m < n_mat; ++m)
-        sig[m] = oracle_sigma(energy + offs[m], sigma + offs[m], offs[m + 1] - offs[m], E);
+    if (material_sigmas(&p, E, sig, NULL) < 0) return -1;
     *bin_out = oracle_ebin(n_bins, edges, E);
     int64_t k = oracle_trace_f64(lo, h, n, o, u, cap, vox, len, NULL);
     if (k < 0) return k;
     int64_t m_seg = k < cap ? k : cap;
     depth tau = {0.0, 0.0};
     for (int64_t s = 0; s < m_seg; ++s) {
-        double sg = sig[mat[vox[s]]];
+        double sg = voxel_sigma(&p, sig, vox[s]);
         score[s] = (*bin_out >= 0) ? vrc_score(w, tau, sg, len[s]) : 0.0;
         depth_add(&tau, sg * len[s]);
     }
@@ -350,7 +401,7 @@ static void *run_job(void *arg)
     double *len = (double *)malloc(sizeof(double) * (size_t)cap);
     event_f64 *ws = (event_f64 *)malloc(sizeof(event_f64) * (size_t)cap);
     double sig[256];
-    if (!vox || !len || !ws || p->n_mat > 256) { j->n_err = 1; free(vox); free(len); free(ws); return NULL; }
+    if (!vox || !len || !ws) { j->n_err = 1; free(vox); free(len); free(ws); return NULL; }
     for (int64_t r = j->r0; r < j->r1; ++r) {
         double E = j->e[r];
         int b = oracle_ebin(p->n_bins, p->edges, E);
@@ -361,15 +412,10 @@ static void *run_job(void *arg)
         j->n_seg += k;
         if (b < 0) { j->n_out_of_range++; continue; }
         j->n_scored++;
-        for (int m = 0; m < p->n_mat; ++m) {
-            const double *ee = p->energy + p->offs[m];
-            int64_t K = p->offs[m + 1] - p->offs[m];
-            sig[m] = oracle_sigma(ee, p->sigma + p->offs[m], K, E);
-            if (outside_table(ee, K, E)) { j->n_clamped++; }
-        }
+        if (material_sigmas(p, E, sig, &j->n_clamped) < 0) { j->n_err++; continue; }
         depth tau = {0.0, 0.0};
         for (int64_t s = 0; s < k; ++s) {
-            double sg = sig[p->mat[vox[s]]];
+            double sg = voxel_sigma(p, sig, vox[s]);
             double f = vrc_score(j->w[r], tau, sg, len[s]);
             depth_add(&tau, sg * len[s]);
             int64_t t = (int64_t)b * nvox + vox[s];
@@ -401,14 +447,16 @@ static double now_s(void)
  */
 int oracle_cast(const double *lo, const double *h, const int32_t *n, const uint8_t *mat,
                 int n_mat, const int64_t *offs, const double *energy, const double *sigma,
-                int n_bins, const double *edges, int64_t n_rays,
+                int n_bins, const double *edges, const double *rho,
+                int n_mix, const int64_t *mix_offs, const int32_t *mix_comp, const double *mix_frac,
+                int64_t n_rays,
                 const double *ox, const double *oy, const double *oz,
                 const double *ux, const double *uy, const double *uz,
                 const double *e, const double *w, int n_threads,
                 double *tally, double *tally_sq, int64_t *tally_cnt,
                 int64_t *stats, double *seconds)
 {
-    problem p = {lo, h, n, mat, n_mat, offs, energy, sigma, n_bins, edges};
+    problem p = {lo, h, n, mat, n_mat, offs, energy, sigma, n_bins, edges, rho, n_mix, mix_offs, mix_comp, mix_frac};
     const int64_t nvox = (int64_t)n[0] * n[1] * n[2];
     const int64_t nt = (int64_t)n_bins * nvox;
     if (n_threads < 1) n_threads = 1;

@@ -11,6 +11,9 @@ from .gen import (  # noqa: F401
     RectMesh,
     rect_mesh,
     XSTables,
+    Mixtures,
+    random_mixtures,
+    density_field,
     Rays,
     Workload,
     E_MIN_MEV,

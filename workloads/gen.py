@@ -44,6 +44,7 @@ class Mesh:
     h: np.ndarray  # (3,) float64, cm
     n: np.ndarray  # (3,) int32
     mat: np.ndarray  # (nx*ny*nz,) uint8, x fastest
+    density: Optional[np.ndarray] = None  # (nx*ny*nz,) float64 factors on the material's Sigma, or None
 
     @property
     def n_voxels(self) -> int:
@@ -60,6 +61,7 @@ class RectMesh:
     """Rectilinear mesh: per axis a table of n_a + 1 increasing planes (cm)."""
     planes: list  # 3 arrays of float64
     mat: np.ndarray  # (nx*ny*nz,) uint8, x fastest
+    density: Optional[np.ndarray] = None  # per-voxel factors, as for Mesh
 
     @property
     def n(self) -> np.ndarray:
@@ -224,6 +226,41 @@ def make_xs(tables) -> XSTables:
 
 _MAT_A = (0.3, 0.1, 0.15)
 _MAT_B = (0.1, 0.3, 0.05)
+
+
+@dataclasses.dataclass
+class Mixtures:
+    """Materials made of tabulated components: material k takes components
+    comp[offs[k]:offs[k+1]] with factors frac[offs[k]:offs[k+1]] (>= 0)."""
+    offs: np.ndarray  # (n_mix+1,) int64
+    comp: np.ndarray  # int32 component (table) ids
+    frac: np.ndarray  # float64 factors
+
+    @property
+    def n_mix(self) -> int:
+        return int(self.offs.size - 1)
+
+
+def random_mixtures(seed: int, n_comp: int, n_mix: int, max_comp: int = 3) -> Mixtures:
+    """n_mix mixtures of 1..max_comp distinct components with factors in [0.05, 1.5]."""
+    rng = _rng(seed)
+    offs, comp, frac = [0], [], []
+    for _ in range(n_mix):
+        k = int(rng.integers(1, min(max_comp, n_comp) + 1))
+        c = rng.choice(n_comp, size=k, replace=False)
+        comp.extend(int(x) for x in c)
+        frac.extend(float(x) for x in rng.uniform(0.05, 1.5, k))
+        offs.append(len(comp))
+    return Mixtures(np.array(offs, np.int64), np.array(comp, np.int32), np.array(frac, np.float64))
+
+
+def density_field(seed: int, n_voxels: int, low: float = 0.5, high: float = 2.0, frac_zero: float = 0.0) -> np.ndarray:
+    """Per-voxel density factors uniform in [low, high], a fraction frac_zero of them 0 (voids)."""
+    rng = _rng(seed)
+    rho = rng.uniform(low, high, n_voxels)
+    if frac_zero > 0:
+        rho[rng.uniform(size=n_voxels) < frac_zero] = 0.0
+    return rho
 
 
 def three_material_xs(seed: int, K: int, clip_lo=0.05, clip_hi=50.0) -> XSTables:
