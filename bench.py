@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--next-event", type=int, default=1,
                     help="also time the next-event (point-detector) estimator on the multimat mesh")
     ap.add_argument("--fom-histories", type=int, default=100000)
+    ap.add_argument("--rect", type=int, default=1,
+                    help="also time the cast on a rectilinear mesh of the multimat box (plain path)")
     ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
     ap.add_argument("--precision-report", action="store_true",
@@ -221,6 +223,46 @@ def bench_next_event(vrc, ctx, wl, torch, stream, steps: int = 20) -> dict:
                         "detector at the mesh centre; FP32 walk, float events", "events": r.n,
             "ms_per_launch": ms, "events_per_s": eps, "pieces_per_event_sampled": per_event,
             "segments_per_s_estimate": eps * per_event}
+
+
+def bench_rect(vrc, ctx, wl, arrays, counts, torch, stream, steps: int = 10) -> dict:
+    """Rectilinear mesh: the multimat workload on a 100^3 mesh of the same 50 cm box with unequal
+    spacings (drawn in [0.25, 0.75] cm and scaled to the box), the same materials, tables and rays.
+
+    A rectilinear mesh is cast by the plain kernel (one atomic per segment); the
+    uniform mesh on the same path is timed beside it for the cost of the table
+    reads.
+    """
+    import workloads as W
+
+    m = wl.mesh
+    rng = np.random.default_rng(2024)
+    planes = []
+    for a in range(3):
+        h = rng.uniform(0.25, 0.75, int(m.n[a]))
+        span = float(m.n[a] * m.h[a])
+        planes.append(m.lo[a] + np.concatenate([[0.0], np.cumsum(h) * (span / h.sum())]))
+    rect = W.RectMesh(planes, m.mat)
+    ctx.set_mesh(1, rect)
+    prec = "p32_t64"
+    S = ctx.count_segments(1, prec, arrays, counts, stream)
+    launch = ctx.get_launch()
+    ctx.set_launch(accumulate=0)
+    try:
+        t_r = ctx.create_tally(1, prec)
+        per_r, tot_r, _ = time_casts(vrc, ctx, t_r, arrays, steps, 2, stream, torch)
+        S_u = ctx.count_segments(0, prec, arrays, counts, stream)
+        t_u = ctx.create_tally(0, prec)
+        per_u, tot_u, _ = time_casts(vrc, ctx, t_u, arrays, steps, 2, stream, torch)
+    finally:
+        ctx.set_launch(**launch)
+    ms_r, ms_u = tot_r / steps, tot_u / steps
+    alg = RAY_BYTES["f32"] * wl.rays.n + SEG_BYTES * S
+    return {"workload": "multimat materials, tables and 1e6 rays on a 100^3 rectilinear mesh of the same box "
+                        "(spacings 0.25-0.75 cm before scaling)", "precision": prec, "path": "plain (accumulate 0)",
+            "segments_per_step": S, "ms_per_step": ms_r, "segments_per_s": S / (ms_r / 1e3),
+            "hbm_frac": alg / (ms_r / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "uniform_same_path": {"segments_per_step": S_u, "ms_per_step": ms_u, "segments_per_s": S_u / (ms_u / 1e3)}}
 
 
 def cpu_baseline(wl, target_s):
@@ -509,8 +551,8 @@ def precision_report() -> None:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the path shards by replicating the tally per GPU, see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(across GPUs the path would shard the rays and replicate the tally per GPU)", file=sys.stderr)
         sys.exit(2)
     if args.write_traffic:
         write_traffic(args.write_traffic)
@@ -598,6 +640,15 @@ def main():
         except Exception as exc:  # the headline line must still be printed
             log(f"bench: next-event measurement failed: {exc!r}")
             next_event = {"error": repr(exc)}
+    rect_form = None
+    if args.rect:
+        try:
+            rect_form = bench_rect(vrc, ctx, wl, arrays, counts, torch, stream)
+            log(f"bench: rectilinear mesh {rect_form['segments_per_s']:.3e} segments/s (uniform on the same path "
+                f"{rect_form['uniform_same_path']['segments_per_s']:.3e})")
+        except Exception as exc:  # the headline line must still be printed
+            log(f"bench: rectilinear measurement failed: {exc!r}")
+            rect_form = {"error": repr(exc)}
     fom_form = None
     if args.fom:
         try:
@@ -651,6 +702,7 @@ def main():
         "serving_form": serving,
         "fom_form": fom_form,
         "next_event_form": next_event,
+        "rect_form": rect_form,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)

@@ -160,6 +160,19 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
 vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], const double *x_planes,
                              const double *y_planes, const double *z_planes, const uint8_t *mat);
 
+/* Give mesh `mesh_id` (uniform or rectilinear, already set) per-voxel
+ * density factors: the Sigma_t,i of voxel i in Eqs. 1-4 becomes
+ * rho[i] * Sigma_m(E) of its material m.  rho: host array of n0*n1*n2
+ * finite values >= 0 (x fastest; 0 makes a voxel void), copied as the pairs
+ * (rho, 1/rho) in FP64 and FP32; the score divides by the voxel's Sigma as
+ * (1/Sigma_m) * (1/rho).  rho == NULL removes the factors.  Setting or
+ * replacing the mesh removes them too.  Such a mesh is cast by vrc_cast_rays
+ * (plain accumulation; accumulate 1..3 fall back to it), vrc_trace_rays and
+ * vrc_count_segments; the batched, serving, walker and next-event calls
+ * return VRC_ERR_INVALID on it.  Errors: VRC_ERR_INVALID (no such mesh, a
+ * bad factor), VRC_ERR_STATE (a tally uses the mesh), VRC_ERR_NOMEM.        */
+vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho);
+
 /* Total macroscopic cross sections Sigma_t(E) of n_mat materials (1..64).
  * Material m's table is energy_MeV[offs[m] .. offs[m+1]) (strictly
  * increasing, > 0) with values sigma_per_cm[...] (>= 0, finite); offs has
@@ -170,6 +183,20 @@ vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], cons
  * with a hashed log-energy index.                                          */
 vrc_status vrc_set_xs_tables(vrc_ctx *ctx, int n_mat, const int64_t *offs,
                              const double *energy_MeV, const double *sigma_per_cm);
+
+/* Materials that are mixtures of tabulated components.  The n_comp
+ * component tables are given as in vrc_set_xs_tables (comp_offs with
+ * n_comp+1 entries, at most 65536 components); material k (0..n_mat-1,
+ * n_mat in 1..64) is the mixture sum_j mix_frac[j] * Sigma_{mix_comp[j]}(E)
+ * over j in [mix_offs[k], mix_offs[k+1]) (at least one component, at most
+ * 4096; factors finite and >= 0, e.g. atom-density fractions).  The sum of
+ * piecewise-linear tables is piecewise linear on the union of the
+ * components' grids, so each mixture is tabulated there (its values summed
+ * in component order) and the result set as by vrc_set_xs_tables, with the
+ * same errors.  Host arrays, copied.                                        */
+vrc_status vrc_set_xs_mixtures(vrc_ctx *ctx, int n_comp, const int64_t *comp_offs, const double *energy_MeV,
+                               const double *sigma_per_cm, int n_mat, const int64_t *mix_offs,
+                               const int32_t *mix_comp, const double *mix_frac);
 
 /* ---- tallies (Sec. 3: the tally stays on the GPU until the end) ------- */
 

@@ -121,6 +121,8 @@ _SIGNATURES = {
     "vrc_set_mesh": [_P, _I, _PD, _PD, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8)],
     "vrc_set_mesh_rect": [_P, _I, ctypes.POINTER(ctypes.c_int32), _PD, _PD, _PD, ctypes.POINTER(ctypes.c_uint8)],
     "vrc_set_xs_tables": [_P, _I, _PI64, _PD, _PD],
+    "vrc_set_xs_mixtures": [_P, _I, _PI64, _PD, _PD, _I, _PI64, ctypes.POINTER(ctypes.c_int32), _PD],
+    "vrc_set_mesh_density": [_P, _I, _PD],
     "vrc_create_tally": [_P, _I, _I, _PD, _I, ctypes.POINTER(_I)],
     "vrc_destroy_tally": [_P, _I],
     "vrc_tally_size": [_P, _I, _PI64],
@@ -302,6 +304,34 @@ def vrc_set_xs_tables(ctx: int, offs, energy, sigma) -> None:
         raise ValueError("table arrays disagree")
     _check(load_library().vrc_set_xs_tables(ctx, offs.size - 1, offs.ctypes.data_as(_PI64),
                                             energy.ctypes.data_as(_PD), sigma.ctypes.data_as(_PD)))
+
+
+def vrc_set_xs_mixtures(ctx: int, offs, energy, sigma, mix_offs, mix_comp, mix_frac) -> None:
+    """Materials as mixtures of the component tables (offs, energy, sigma)."""
+    offs = np.ascontiguousarray(offs, np.int64)
+    energy = np.ascontiguousarray(energy, np.float64)
+    sigma = np.ascontiguousarray(sigma, np.float64)
+    mo = np.ascontiguousarray(mix_offs, np.int64)
+    mc = np.ascontiguousarray(mix_comp, np.int32)
+    mf = np.ascontiguousarray(mix_frac, np.float64)
+    if energy.size != sigma.size or offs.size < 2 or offs[-1] != energy.size:
+        raise ValueError("table arrays disagree")
+    if mo.size < 2 or mc.size != mf.size or mo[-1] != mc.size:
+        raise ValueError("mixture arrays disagree")
+    _check(load_library().vrc_set_xs_mixtures(ctx, offs.size - 1, offs.ctypes.data_as(_PI64),
+                                              energy.ctypes.data_as(_PD), sigma.ctypes.data_as(_PD), mo.size - 1,
+                                              mo.ctypes.data_as(_PI64),
+                                              mc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                              mf.ctypes.data_as(_PD)))
+
+
+def vrc_set_mesh_density(ctx: int, mesh_id: int, rho) -> None:
+    """Per-voxel density factors of a set mesh (None removes them)."""
+    if rho is None:
+        _check(load_library().vrc_set_mesh_density(ctx, mesh_id, ctypes.cast(None, _PD)))
+        return
+    rho = np.ascontiguousarray(rho, np.float64)
+    _check(load_library().vrc_set_mesh_density(ctx, mesh_id, rho.ctypes.data_as(_PD)))
 
 
 def vrc_create_tally(ctx: int, mesh_id: int, precision="p64", edges=None) -> int:
@@ -573,11 +603,20 @@ class Context:
             pass
 
     def set_mesh(self, mesh_id: int, mesh) -> None:
-        """A uniform mesh (lo, h, n, mat) or a rectilinear one (planes, mat)."""
+        """A uniform mesh (lo, h, n, mat) or a rectilinear one (planes, mat), with its density factors if any."""
         if hasattr(mesh, "planes"):
             vrc_set_mesh_rect(self.handle, mesh_id, mesh.planes, mesh.mat)
         else:
             vrc_set_mesh(self.handle, mesh_id, mesh.lo, mesh.h, mesh.n, mesh.mat)
+        rho = getattr(mesh, "density", None)
+        if rho is not None:
+            if np.asarray(rho).size != int(np.prod(np.asarray(mesh.n, np.int64))):
+                raise ValueError("one density factor per voxel is needed")
+            vrc_set_mesh_density(self.handle, mesh_id, rho)
+
+    def set_xs_mixtures(self, xs, mix) -> None:
+        """Materials as the mixtures mix (offs, comp, frac) of the tables of xs."""
+        vrc_set_xs_mixtures(self.handle, xs.offs, xs.energy, xs.sigma, mix.offs, mix.comp, mix.frac)
 
     def set_xs(self, xs) -> None:
         vrc_set_xs_tables(self.handle, xs.offs, xs.energy, xs.sigma)

@@ -174,6 +174,10 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
     free_dev(m.d_mat);
     free_dev(m.d_pl64);
     free_dev(m.d_pl32);
+    free_dev(m.d_rho64);
+    free_dev(m.d_rho32);
+    m.dens = false;
+    m.h_rho.clear();
     m.set = false;
     m.rect = false;
     m.rect_f32_ok = false;
@@ -252,9 +256,10 @@ vrc_status vrc::check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
 
 vrc_status vrc::check_uniform_mesh(vrc_ctx *ctx, const TallyHost *t, const char *what)
 {
-    if (ctx->meshes[t->mesh_id].rect)
-        return set_error(VRC_ERR_INVALID, std::string(what) + " takes uniform meshes only; cast rays on a "
-                                                               "rectilinear mesh with vrc_cast_rays");
+    const MeshHost &m = ctx->meshes[t->mesh_id];
+    if (m.rect || m.dens)
+        return set_error(VRC_ERR_INVALID, std::string(what) + " takes uniform meshes without density factors only; "
+                                                               "cast rays on such a mesh with vrc_cast_rays");
     return VRC_OK;
 }
 
@@ -325,6 +330,8 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         free_dev(m.d_mat);
         free_dev(m.d_pl64);
         free_dev(m.d_pl32);
+        free_dev(m.d_rho64);
+        free_dev(m.d_rho32);
     }
     free_xs(ctx->xs);
     for (auto &st : ctx->stage) {
@@ -395,6 +402,48 @@ vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], cons
     return store_mesh(ctx, mesh_id, lo, h, n, mat, src);
 }
 
+vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
+        return set_error(VRC_ERR_INVALID, "mesh_id does not name a set mesh");
+    MeshHost &m = ctx->meshes[mesh_id];
+    if (m.users > 0) return set_error(VRC_ERR_STATE, "mesh is used by a tally");
+    const size_t nv = static_cast<size_t>(m.nvox);
+    if (rho) {
+        for (size_t v = 0; v < nv; ++v)
+            if (!(std::isfinite(rho[v]) && rho[v] >= 0))
+                return set_error(VRC_ERR_INVALID, "density factors must be finite and >= 0");
+    }
+    (void)hipSetDevice(ctx->device);
+    free_dev(m.d_rho64);
+    free_dev(m.d_rho32);
+    m.dens = false;
+    m.h_rho.clear();
+    if (!rho) return VRC_OK;
+    // (rho, 1/rho) per voxel; 1/rho is rounded from FP64 in both copies (inf
+    // for rho = 0, never used: such a voxel's Sigma is 0)
+    std::vector<DensPair<double>> p64(nv);
+    std::vector<DensPair<float>> p32(nv);
+    for (size_t v = 0; v < nv; ++v) {
+        const double inv = 1.0 / rho[v];
+        p64[v] = DensPair<double>{rho[v], inv};
+        p32[v] = DensPair<float>{static_cast<float>(rho[v]), static_cast<float>(inv)};
+    }
+    void *d = nullptr;
+    if (vrc_status s = upload(ctx, &d, p64.data(), sizeof(DensPair<double>) * nv)) return s;
+    m.d_rho64 = static_cast<DensPair<double> *>(d);
+    if (vrc_status s = upload(ctx, &d, p32.data(), sizeof(DensPair<float>) * nv)) {
+        free_dev(m.d_rho64);
+        return s;
+    }
+    m.d_rho32 = static_cast<DensPair<float> *>(d);
+    m.h_rho.assign(rho, rho + nv);
+    m.dens = true;
+    return VRC_OK;
+}
+
 vrc_status vrc_set_xs_tables(vrc_ctx *ctx, int n_mat, const int64_t *offs, const double *energy_MeV,
                              const double *sigma_per_cm)
 {
@@ -433,6 +482,19 @@ vrc_status vrc_set_xs_tables(vrc_ctx *ctx, int n_mat, const int64_t *offs, const
     x.d_hash64 = static_cast<int32_t *>(p);
     ctx->xs = std::move(x);
     return VRC_OK;
+}
+
+vrc_status vrc_set_xs_mixtures(vrc_ctx *ctx, int n_comp, const int64_t *comp_offs, const double *energy_MeV,
+                               const double *sigma_per_cm, int n_mat, const int64_t *mix_offs,
+                               const int32_t *mix_comp, const double *mix_frac)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    std::vector<int64_t> offs;
+    std::vector<double> e, sg;
+    if (vrc_status s = mix_tables(n_comp, comp_offs, energy_MeV, sigma_per_cm, n_mat, mix_offs, mix_comp, mix_frac,
+                                  offs, e, sg))
+        return s;
+    return vrc_set_xs_tables(ctx, n_mat, offs.data(), e.data(), sg.data());
 }
 
 vrc_status vrc_create_tally(vrc_ctx *ctx, int mesh_id, int n_ebins, const double *edges, vrc_precision precision,
@@ -562,7 +624,8 @@ vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision
     if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
         return set_error(VRC_ERR_INVALID, "no such mesh");
     const MeshHost &mesh = ctx->meshes[mesh_id];
-    if (mesh.rect) return set_error(VRC_ERR_INVALID, "the next-event estimator takes uniform meshes only");
+    if (mesh.rect || mesh.dens)
+        return set_error(VRC_ERR_INVALID, "the next-event estimator takes uniform meshes without density factors only");
     if (!ctx->xs.set) return set_error(VRC_ERR_STATE, "no cross-section tables set");
     if (mesh.max_mat >= ctx->xs.n_mat) return set_error(VRC_ERR_STATE, "mesh has a material id >= n_mat");
     if (precision != VRC_P64 && !ctx->xs.f32_ok)

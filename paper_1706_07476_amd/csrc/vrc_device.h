@@ -36,6 +36,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "vrc_internal.h"
 #include "vrc_math.h"
@@ -466,9 +467,10 @@ __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, 
 // state at a tile entry is just (tau_hi, tau_lo), a cast split at tile
 // entries (the tile-split accumulation) scores bit-identically to an
 // uninterrupted one.
-template <typename R, class Put>
+template <typename R, class Put, bool DENS = false>
 struct Scorer {
     const R (*sig)[2];
+    const DensPair<R> *dens = nullptr;  // DENS: per-voxel (rho, 1/rho) on the voxel's Sigma
     int stride;
     R w0;
     R w_in;
@@ -507,8 +509,13 @@ struct Scorer {
             tile = tg;
         }
         const R l = static_cast<R>(len);
-        const R s = sig[m * stride][0];
-        const R is = sig[m * stride][1];
+        R s = sig[m * stride][0];
+        R is = sig[m * stride][1];
+        if constexpr (DENS) {
+            const DensPair<R> d = dens[vox];
+            s = s * d.rho;  // the voxel's Sigma; 1/Sigma from the two reciprocals
+            is = is * d.inv;
+        }
         const R x = s * l;
         R g, em;
         attenuation(x, g, em);
@@ -629,13 +636,17 @@ __device__ __forceinline__ void stage_lds(const XsP<R> &X, int hash_in_lds, cons
 
 // Cross sections of the ray's energy, then the walk (in R) with the running
 // score (in S: R itself, or double over an FP32 walk).
-template <typename R, typename S, class Put, bool RECT = false>
+template <typename R, typename S, class Put, bool RECT = false, bool DENS = false>
 __device__ __forceinline__ void cast_one(const MeshP<R> &M, const XsP<R> &X, const int32_t *hash, S (*mysig)[2],
                                          int bd, R ox, R oy, R oz, R ux, R uy, R uz, R E, R w, Put &put)
 {
     xs_lookup(X, hash, E, mysig, bd);
-    Scorer<S, Put> sc(mysig, bd, static_cast<S>(w), put);
-    walk<R, Scorer<S, Put>, RECT>(M, ox, oy, oz, ux, uy, uz, sc);
+    Scorer<S, Put, DENS> sc(mysig, bd, static_cast<S>(w), put);
+    if constexpr (DENS) {
+        if constexpr (std::is_same<S, double>::value) sc.dens = M.rho64;
+        else sc.dens = M.rho32;
+    }
+    walk<R, Scorer<S, Put, DENS>, RECT>(M, ox, oy, oz, ux, uy, uz, sc);
 }
 
 // Next-event (point-detector) estimator, Sec. 6.3: a ray from an event to

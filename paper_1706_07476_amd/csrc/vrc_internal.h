@@ -24,6 +24,13 @@ constexpr int kMaxEbins = 64;
 // Parameters handed to the kernels by value.
 // ---------------------------------------------------------------------------
 
+// Density factor of a voxel with its reciprocal (both rounded from FP64).
+template <typename R>
+struct DensPair {
+    R rho;
+    R inv;
+};
+
 // Uniform Cartesian mesh in the traversal precision R.
 template <typename R>
 struct MeshP {
@@ -34,6 +41,10 @@ struct MeshP {
     // rectilinear mesh: per axis a device table of n_a + 1 increasing planes
     // (walks instantiated for rectilinear meshes read these instead of lo + k h)
     const R *pl[3] = {nullptr, nullptr, nullptr};
+    // per-voxel density factors in both scoring precisions (walks instantiated
+    // for density read the one of their score type), or null
+    const DensPair<float> *rho32 = nullptr;
+    const DensPair<double> *rho64 = nullptr;
 };
 
 // Cross sections on the union energy grid.  E[K] strictly increasing;
@@ -155,6 +166,11 @@ struct MeshHost {
     std::vector<double> h_planes;
     double *d_pl64 = nullptr;
     float *d_pl32 = nullptr;
+    // per-voxel density factors (Sigma of a voxel = rho * Sigma of its material)
+    bool dens = false;
+    std::vector<double> h_rho;
+    DensPair<double> *d_rho64 = nullptr;
+    DensPair<float> *d_rho32 = nullptr;
     int32_t n[3] = {0, 0, 0};
     int64_t nvox = 0;
     int max_mat = 0;
@@ -270,6 +286,11 @@ vrc_status run_split_batches(vrc_ctx *ctx, const std::vector<int> &ids, const st
 // Builds the union grid, per-material values on it and the log2-energy hash.
 vrc_status build_xs(int n_mat, const int64_t *offs, const double *energy, const double *sigma,
                     XsHost &out);
+// Mixture tables (Sigma = sum_j f_j Sigma_j) as ordinary material tables on
+// the union of each mixture's component grids.
+vrc_status mix_tables(int n_comp, const int64_t *comp_offs, const double *energy, const double *sigma, int n_mix,
+                      const int64_t *mix_offs, const int32_t *mix_comp, const double *mix_frac,
+                      std::vector<int64_t> &offs, std::vector<double> &e_out, std::vector<double> &s_out);
 
 // Kernel launchers (vrc_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m,

@@ -31,8 +31,9 @@ struct CastArgs {
     int hash_in_lds;
 };
 
-// RECT: the mesh is rectilinear (plane tables); otherwise uniform.
-template <typename R, typename RT, typename S, bool RECT, class PutMaker>
+// RECT: the mesh is rectilinear (plane tables); otherwise uniform.  DENS: the
+// mesh carries per-voxel density factors (each voxel's Sigma scaled by its own).
+template <typename R, typename RT, typename S, bool RECT, bool DENS, class PutMaker>
 __device__ __forceinline__ void cast_block(const CastArgs<R> &A, PutMaker make_put)
 {
     const int32_t *hash;
@@ -50,36 +51,36 @@ __device__ __forceinline__ void cast_block(const CastArgs<R> &A, PutMaker make_p
         const int bin = energy_bin(A.tally, static_cast<double>(E));
         auto put = make_put(r, bin);
         if (!put.active()) continue;
-        cast_one<R, S, typename std::decay<decltype(put.inner)>::type, RECT>(A.mesh, A.xs, hash, mysig, bd, ox, oy, oz,
+        cast_one<R, S, typename std::decay<decltype(put.inner)>::type, RECT, DENS>(A.mesh, A.xs, hash, mysig, bd, ox, oy, oz,
                                                                              ux, uy, uz, E, wt, put.inner);
     }
 }
 
 // S: scoring precision (R, or double over an FP32 walk: the paper's scheme).
-template <typename R, typename RT, bool AGG, typename S, bool RECT>
+template <typename R, typename RT, bool AGG, typename S, bool RECT, bool DENS>
 __global__ void __launch_bounds__(1024) cast_f64_kernel(CastArgs<R> A)
 {
     __shared__ double agg_lds[AGG ? 1024 : 1];
     double *wave_lds = agg_lds + (AGG ? (threadIdx.x & ~63u) : 0);
-    cast_block<R, RT, S, RECT>(A, [&](int64_t, int bin) {
+    cast_block<R, RT, S, RECT, DENS>(A, [&](int64_t, int bin) {
         return Active<PutF64<AGG>>{PutF64<AGG>{static_cast<double *>(A.tally.data), bin * A.tally.nvox, wave_lds},
                                    bin >= 0};
     });
 }
 
-template <typename RT, bool RECT>
+template <typename RT, bool RECT, bool DENS>
 __global__ void __launch_bounds__(1024) cast_kahan_kernel(CastArgs<float> A)
 {
-    cast_block<float, RT, float, RECT>(A, [&](int64_t, int bin) {
+    cast_block<float, RT, float, RECT, DENS>(A, [&](int64_t, int bin) {
         return Active<PutKahan>{PutKahan{static_cast<float *>(A.tally.data), bin * A.tally.nvox}, bin >= 0};
     });
 }
 
 // Inspection: the same walk and score, written out as CSR.
-template <typename R, typename RT, typename S, bool RECT>
+template <typename R, typename RT, typename S, bool RECT, bool DENS>
 __global__ void __launch_bounds__(256) trace_kernel(CastArgs<R> A)
 {
-    cast_block<R, RT, S, RECT>(A, [&](int64_t r, int bin) {
+    cast_block<R, RT, S, RECT, DENS>(A, [&](int64_t r, int bin) {
         return Active<PutTrace>{PutTrace{A.trace.offs[r], A.trace.voxel, A.trace.len, A.trace.score, bin >= 0},
                                 true};
     });
@@ -195,6 +196,8 @@ MeshP<R> mesh_args(const MeshHost &m)
         p.n[a] = m.n[a];
     }
     p.mat = m.d_mat;
+    p.rho32 = m.d_rho32;
+    p.rho64 = m.d_rho64;
     if (m.rect) {
         const R *base = mesh_planes<R>(m);
         p.pl[0] = base;
@@ -252,7 +255,7 @@ bool pick_shape(const XsHost &x, int want_block, bool want_hash, int &block, boo
     return lds <= kLdsLimit;
 }
 
-template <typename R, typename RT, typename S, bool RECT>
+template <typename R, typename RT, typename S, bool RECT, bool DENS>
 hipError_t cast_f64_launch(const vrc_ctx &ctx, CastArgs<R> A, hipStream_t s)
 {
     int block;
@@ -263,9 +266,9 @@ hipError_t cast_f64_launch(const vrc_ctx &ctx, CastArgs<R> A, hipStream_t s)
     A.hash_in_lds = hash ? 1 : 0;
     const int grid = grid_for(ctx, A.rays.n, block);
     if (ctx.launch.aggregate)
-        hipLaunchKernelGGL((cast_f64_kernel<R, RT, true, S, RECT>), dim3(grid), dim3(block), lds, s, A);
+        hipLaunchKernelGGL((cast_f64_kernel<R, RT, true, S, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
     else
-        hipLaunchKernelGGL((cast_f64_kernel<R, RT, false, S, RECT>), dim3(grid), dim3(block), lds, s, A);
+        hipLaunchKernelGGL((cast_f64_kernel<R, RT, false, S, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
     return hipGetLastError();
 }
 
@@ -284,7 +287,7 @@ CastArgs<R> make_args(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m,
 
 }  // namespace
 
-template <bool RECT>
+template <bool RECT, bool DENS>
 hipError_t launch_cast_impl(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
                        bool rays_fp64, hipStream_t s)
 {
@@ -292,16 +295,16 @@ hipError_t launch_cast_impl(const vrc_ctx &ctx, const TallyHost &t, const MeshHo
     switch (t.prec) {
     case VRC_P64: {
         CastArgs<double> A = make_args<double>(ctx, t, m, rays);
-        return rays_fp64 ? cast_f64_launch<double, double, double, RECT>(ctx, A, s) : cast_f64_launch<double, float, double, RECT>(ctx, A, s);
+        return rays_fp64 ? cast_f64_launch<double, double, double, RECT, DENS>(ctx, A, s) : cast_f64_launch<double, float, double, RECT, DENS>(ctx, A, s);
     }
     case VRC_P32_T64: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
-        return rays_fp64 ? cast_f64_launch<float, double, float, RECT>(ctx, A, s) : cast_f64_launch<float, float, float, RECT>(ctx, A, s);
+        return rays_fp64 ? cast_f64_launch<float, double, float, RECT, DENS>(ctx, A, s) : cast_f64_launch<float, float, float, RECT, DENS>(ctx, A, s);
     }
     case VRC_P32_D64: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
-        return rays_fp64 ? cast_f64_launch<float, double, double, RECT>(ctx, A, s)
-                         : cast_f64_launch<float, float, double, RECT>(ctx, A, s);
+        return rays_fp64 ? cast_f64_launch<float, double, double, RECT, DENS>(ctx, A, s)
+                         : cast_f64_launch<float, float, double, RECT, DENS>(ctx, A, s);
     }
     case VRC_P32_KAHAN: {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
@@ -313,16 +316,16 @@ hipError_t launch_cast_impl(const vrc_ctx &ctx, const TallyHost &t, const MeshHo
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = grid_for(ctx, rays.n, block);
         if (rays_fp64)
-            hipLaunchKernelGGL((cast_kahan_kernel<double, RECT>), dim3(grid), dim3(block), lds, s, A);
+            hipLaunchKernelGGL((cast_kahan_kernel<double, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
         else
-            hipLaunchKernelGGL((cast_kahan_kernel<float, RECT>), dim3(grid), dim3(block), lds, s, A);
+            hipLaunchKernelGGL((cast_kahan_kernel<float, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
         return hipGetLastError();
     }
     }
     return hipErrorInvalidValue;
 }
 
-template <bool RECT>
+template <bool RECT, bool DENS>
 hipError_t launch_trace_impl(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
                         bool rays_fp64, const TraceP &tr, hipStream_t s)
 {
@@ -336,24 +339,24 @@ hipError_t launch_trace_impl(const vrc_ctx &ctx, const TallyHost &t, const MeshH
         if (!pick_shape<double>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = static_cast<int>((rays.n + block - 1) / block);
-        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<double, double, double, RECT>), dim3(grid), dim3(block), lds, s, A);
-        else hipLaunchKernelGGL((trace_kernel<double, float, double, RECT>), dim3(grid), dim3(block), lds, s, A);
+        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<double, double, double, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
+        else hipLaunchKernelGGL((trace_kernel<double, float, double, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
     } else if (t.prec == VRC_P32_D64) {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
         A.trace = tr;
         if (!pick_shape<double>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = static_cast<int>((rays.n + block - 1) / block);
-        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, double, RECT>), dim3(grid), dim3(block), lds, s, A);
-        else hipLaunchKernelGGL((trace_kernel<float, float, double, RECT>), dim3(grid), dim3(block), lds, s, A);
+        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, double, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
+        else hipLaunchKernelGGL((trace_kernel<float, float, double, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
     } else {
         CastArgs<float> A = make_args<float>(ctx, t, m, rays);
         A.trace = tr;
         if (!pick_shape<float>(ctx.xs, 256, true, block, hash, lds)) return hipErrorInvalidConfiguration;
         A.hash_in_lds = hash ? 1 : 0;
         const int grid = static_cast<int>((rays.n + block - 1) / block);
-        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, float, RECT>), dim3(grid), dim3(block), lds, s, A);
-        else hipLaunchKernelGGL((trace_kernel<float, float, float, RECT>), dim3(grid), dim3(block), lds, s, A);
+        if (rays_fp64) hipLaunchKernelGGL((trace_kernel<float, double, float, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
+        else hipLaunchKernelGGL((trace_kernel<float, float, float, RECT, DENS>), dim3(grid), dim3(block), lds, s, A);
     }
     return hipGetLastError();
 }
@@ -399,15 +402,21 @@ hipError_t launch_count_total_impl(const vrc_ctx &ctx, const MeshHost &m, vrc_pr
 hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
                        bool rays_fp64, hipStream_t s)
 {
-    return m.rect ? launch_cast_impl<true>(ctx, t, m, rays, rays_fp64, s)
-                  : launch_cast_impl<false>(ctx, t, m, rays, rays_fp64, s);
+    if (m.dens)
+        return m.rect ? launch_cast_impl<true, true>(ctx, t, m, rays, rays_fp64, s)
+                      : launch_cast_impl<false, true>(ctx, t, m, rays, rays_fp64, s);
+    return m.rect ? launch_cast_impl<true, false>(ctx, t, m, rays, rays_fp64, s)
+                  : launch_cast_impl<false, false>(ctx, t, m, rays, rays_fp64, s);
 }
 
 hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
                         bool rays_fp64, const TraceP &tr, hipStream_t s)
 {
-    return m.rect ? launch_trace_impl<true>(ctx, t, m, rays, rays_fp64, tr, s)
-                  : launch_trace_impl<false>(ctx, t, m, rays, rays_fp64, tr, s);
+    if (m.dens)
+        return m.rect ? launch_trace_impl<true, true>(ctx, t, m, rays, rays_fp64, tr, s)
+                      : launch_trace_impl<false, true>(ctx, t, m, rays, rays_fp64, tr, s);
+    return m.rect ? launch_trace_impl<true, false>(ctx, t, m, rays, rays_fp64, tr, s)
+                  : launch_trace_impl<false, false>(ctx, t, m, rays, rays_fp64, tr, s);
 }
 
 hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,

@@ -1187,7 +1187,7 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
 
 bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m)
 {
-    if (ctx.sort_scratch.done == nullptr || m.rect) return false;
+    if (ctx.sort_scratch.done == nullptr || m.rect || m.dens) return false;
     const SortGeom g = geometry(t, m);
     if (g.n_keys == 0) return false;
     const size_t sb = (t.prec == VRC_P32_T64 || t.prec == VRC_P32_KAHAN) ? sizeof(float) : sizeof(double);

@@ -66,7 +66,7 @@ std::string mesh_key(const vrc_ctx *ctx, const std::set<int> &meshes)
     std::ostringstream os;
     for (int m : meshes) {
         const MeshHost &mh = ctx->meshes[m];
-        os << mh.n[0] << 'x' << mh.n[1] << 'x' << mh.n[2] << (mh.rect ? "r," : ",");
+        os << mh.n[0] << 'x' << mh.n[1] << 'x' << mh.n[2] << (mh.rect ? "r" : "") << (mh.dens ? "d," : ",");
     }
     return os.str();
 }

@@ -122,4 +122,70 @@ vrc_status build_xs(int n_mat, const int64_t *offs, const double *energy, const 
     return VRC_OK;
 }
 
+// Tables of mixtures of tabulated components: mixture k's Sigma is
+// sum_j f_j Sigma_j(E) over its components.  Each component is piecewise
+// linear with its end values held, so the sum is piecewise linear between
+// consecutive points of the union of the components' grids: its values at
+// those points (terms added in component order) describe it exactly up to
+// rounding, and the mixture becomes an ordinary material table.
+vrc_status mix_tables(int n_comp, const int64_t *comp_offs, const double *energy, const double *sigma, int n_mix,
+                      const int64_t *mix_offs, const int32_t *mix_comp, const double *mix_frac,
+                      std::vector<int64_t> &offs, std::vector<double> &e_out, std::vector<double> &s_out)
+{
+    if (n_comp < 1 || n_comp > (1 << 16)) return set_error(VRC_ERR_INVALID, "n_comp must be in 1..65536");
+    if (n_mix < 1 || n_mix > kMaxMaterials) return set_error(VRC_ERR_INVALID, "n_mat must be in 1..64");
+    if (!comp_offs || !energy || !sigma || !mix_offs || !mix_comp || !mix_frac)
+        return set_error(VRC_ERR_INVALID, "null table or mixture pointer");
+    if (comp_offs[0] != 0 || mix_offs[0] != 0) return set_error(VRC_ERR_INVALID, "offsets must start at 0");
+    for (int c = 0; c < n_comp; ++c) {
+        const int64_t a = comp_offs[c], b = comp_offs[c + 1];
+        if (b <= a) return set_error(VRC_ERR_INVALID, "every component needs at least one table point");
+        if (b - a > (int64_t(1) << 30)) return set_error(VRC_ERR_INVALID, "table too large");
+        for (int64_t i = a; i < b; ++i) {
+            if (!(std::isfinite(energy[i]) && energy[i] > 0))
+                return set_error(VRC_ERR_INVALID, "energies must be finite and positive");
+            if (i > a && !(energy[i] > energy[i - 1]))
+                return set_error(VRC_ERR_INVALID, "energies must be strictly increasing per component");
+            if (!(std::isfinite(sigma[i]) && sigma[i] >= 0))
+                return set_error(VRC_ERR_INVALID, "cross sections must be finite and >= 0");
+        }
+    }
+    offs.assign(1, 0);
+    e_out.clear();
+    s_out.clear();
+    for (int k = 0; k < n_mix; ++k) {
+        const int64_t a = mix_offs[k], b = mix_offs[k + 1];
+        if (b <= a) return set_error(VRC_ERR_INVALID, "every mixture needs at least one component");
+        if (b - a > 4096) return set_error(VRC_ERR_INVALID, "at most 4096 components per mixture");
+        std::vector<double> grid;
+        for (int64_t j = a; j < b; ++j) {
+            const int c = mix_comp[j];
+            if (c < 0 || c >= n_comp) return set_error(VRC_ERR_INVALID, "mixture names no such component");
+            if (!(std::isfinite(mix_frac[j]) && mix_frac[j] >= 0))
+                return set_error(VRC_ERR_INVALID, "mixture factors must be finite and >= 0");
+            grid.insert(grid.end(), energy + comp_offs[c], energy + comp_offs[c + 1]);
+        }
+        std::sort(grid.begin(), grid.end());
+        grid.erase(std::unique(grid.begin(), grid.end()), grid.end());
+        if (e_out.size() + grid.size() > (static_cast<size_t>(1) << 30))
+            return set_error(VRC_ERR_INVALID, "mixture tables too large");
+        for (double x : grid) {
+            double v = 0.0;
+            for (int64_t j = a; j < b; ++j) {
+                const int c = mix_comp[j];
+                const double *e = energy + comp_offs[c];
+                const double *sg = sigma + comp_offs[c];
+                const int64_t K = comp_offs[c + 1] - comp_offs[c];
+                const double *p = std::lower_bound(e, e + K, x);
+                const double t = (p != e + K && *p == x) ? sg[p - e] : interp_own(e, sg, K, x);
+                v += mix_frac[j] * t;
+            }
+            e_out.push_back(x);
+            s_out.push_back(v);
+        }
+        offs.push_back(static_cast<int64_t>(e_out.size()));
+    }
+    return VRC_OK;
+}
+
 }  // namespace vrc

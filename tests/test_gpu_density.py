@@ -1,0 +1,246 @@
+"""Per-voxel density factors and material mixtures on the GPU against the oracle.
+
+A voxel's Sigma is rho_i Sigma_m(E) (the kernel scales the material's Sigma
+and its reciprocal by the stored pair (rho, 1/rho)); a mixture's Sigma is
+sum_j f_j Sigma_j(E) (tabulated by the library on the union of its
+components' grids, evaluated by the oracle component by component).
+Tallies: 1e-12 (FP64), 1e-5 on well-sampled voxels (FP32 forms, against the
+oracle on the same FP32-rounded inputs); per-segment scores 1e-13.
+Unit factors give the plain scores bit for bit.  Paths that take plain
+meshes only refuse a mesh with factors.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from vrc_testutil import dev_arrays, host_arrays, oracle_threads, rel_report, unscored_ok
+
+pytestmark = pytest.mark.gpu
+
+TOL_P64 = 1e-12
+TOL_P32 = 1e-5
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vrc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1706_07476_amd as vrc_mod
+    vrc_mod.load_library()
+    return vrc_mod
+
+
+@pytest.fixture()
+def ctx(vrc):
+    c = vrc.Context(0)
+    yield c
+    c.close()
+
+
+def with_density(mesh, rho):
+    if hasattr(mesh, "planes"):
+        return W.RectMesh(mesh.planes, mesh.mat, rho)
+    return W.Mesh(mesh.lo, mesh.h, mesh.n, mesh.mat, rho)
+
+
+def f32_inputs(mesh, xs, rays, round_density):
+    """The FP32 forms' inputs promoted back to FP64 (density rounded when the form scores in FP32)."""
+    rho = mesh.density.astype(np.float32).astype(np.float64) if round_density else mesh.density
+    m = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
+               mesh.n, mesh.mat, rho)
+    x = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
+                   xs.sigma.astype(np.float32).astype(np.float64))
+    return m, x, W.rays_to_f32(rays).as_f64()
+
+
+@pytest.mark.parametrize("accumulate", [0, 1])
+def test_density_tally_fp64(ctx, accumulate):
+    """accumulate 1 with 140000 rays: the tile-split accumulation does not take density factors,
+    the plain accumulation runs."""
+    base = W.slab_mesh(951, 40, 0.5, slab=5)
+    mesh = with_density(base, W.density_field(952, base.n_voxels, 0.3, 2.5, frac_zero=0.05))
+    xs = W.gen.three_material_xs(953, 2000)
+    rays = W.rays_in_box(954, mesh, 140_000)
+    say(f"case: density tally p64, slab 40^3 (5 % void voxels), {rays.n} rays, accumulate {accumulate}")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    ctx.set_launch(accumulate=accumulate)
+    tid = ctx.create_tally(0, "p64")
+    ctx.cast(tid, dev_arrays(rays, "f64"))
+    res = oracle.cast(mesh, xs, rays, n_threads=oracle_threads())
+    g, _, n = rel_report(ctx.read(tid), res, gate="all")
+    say(f"  max rel over {n} voxels {g:.3e}")
+    assert n > 0.9 * mesh.n_voxels
+    assert g <= TOL_P64
+
+
+def test_density_on_a_rectilinear_mesh_fp64(ctx):
+    base = W.rect_mesh(955, (33, 29, 31), h_min=0.2, h_max=1.1)
+    mesh = with_density(base, W.density_field(956, base.n_voxels, 0.5, 2.0, frac_zero=0.02))
+    xs = W.gen.three_material_xs(957, 1000)
+    rays = W.rays_in_box(958, mesh, 60_000)
+    say(f"case: density on a rect mesh, p64, 33x29x31, {rays.n} rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    tid = ctx.create_tally(0, "p64")
+    ctx.cast(tid, dev_arrays(rays, "f64"))
+    res = oracle.cast(mesh, xs, rays, n_threads=oracle_threads())
+    g, _, n = rel_report(ctx.read(tid), res, gate="all")
+    say(f"  max rel over {n} voxels {g:.3e}")
+    assert g <= TOL_P64
+
+
+@pytest.mark.parametrize("prec", ["p32_t64", "p32_kahan", "p32_d64"])
+def test_density_fp32_forms_well_sampled(ctx, prec):
+    base = W.slab_mesh(959, 16, 0.5, slab=4)
+    mesh = with_density(base, W.density_field(960, base.n_voxels, 0.4, 2.2))
+    xs = W.gen.three_material_xs(961, 2000)
+    rays = W.rays_in_box(962, mesh, 1_600_000)
+    say(f"case: density tally {prec}, slab 16^3, {rays.n} rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    tid = ctx.create_tally(0, prec)
+    ctx.cast(tid, dev_arrays(rays, "f32"))
+    m, x, r = f32_inputs(mesh, xs, rays, round_density=prec != "p32_d64")
+    res = oracle.cast(m, x, r, n_threads=oracle_threads())
+    got = ctx.read(tid)
+    g, a, n = rel_report(got, res, gate="stderr")
+    say(f"  max rel over {n} gated voxels {g:.3e}; all voxels {a:.3e}")
+    assert n > 0.5 * mesh.n_voxels
+    assert g <= TOL_P32
+    assert unscored_ok(got, res)
+
+
+def test_density_scores_and_unit_factors(ctx):
+    base = W.slab_mesh(963, 24, 0.5, slab=3)
+    rho = W.density_field(964, base.n_voxels, 0.2, 3.0, frac_zero=0.1)
+    mesh = with_density(base, rho)
+    xs = W.gen.three_material_xs(965, 1000)
+    rays = W.rays_in_box(966, mesh, 3000)
+    say(f"case: density trace scores p64 and unit factors, slab 24^3, {rays.n} rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    tid = ctx.create_tally(0, "p64")
+    offs, vox, ln, sc = ctx.trace(tid, dev_arrays(rays, "f64"))
+    o_offs, o_vox, o_len = oracle.trace_many(base, rays, precision="f64")
+    np.testing.assert_array_equal(offs, o_offs)
+    np.testing.assert_array_equal(vox, o_vox)
+    for r in range(0, rays.n, 29):
+        o = [rays.ox[r], rays.oy[r], rays.oz[r]]
+        u = [rays.ux[r], rays.uy[r], rays.uz[r]]
+        _, _, s_ref, _ = oracle.ray_scores(mesh, xs, o, u, rays.e[r], rays.w[r])
+        np.testing.assert_allclose(sc[offs[r]:offs[r + 1]], s_ref, rtol=1e-13, atol=1e-300)
+    # unit factors: the plain scores bit for bit (rho * Sigma and (1/Sigma) * 1 are exact)
+    ctx.set_mesh(1, with_density(base, np.ones(base.n_voxels)))
+    ctx.set_mesh(2, base)
+    for prec, dt in (("p64", "f64"), ("p32_t64", "f32"), ("p32_d64", "f32")):
+        a = ctx.trace(ctx.create_tally(1, prec), dev_arrays(rays, dt))
+        b = ctx.trace(ctx.create_tally(2, prec), dev_arrays(rays, dt))
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", ["p64", "p32_t64"])
+def test_mixtures_match_the_oracle(ctx, prec):
+    """Five components on different energy grids, six mixtures of one to three of them."""
+    rng = np.random.default_rng(967)
+    tabs = []
+    for j in range(5):
+        k = int(rng.integers(40, 400))
+        lo_e, hi_e = np.exp(rng.uniform(np.log(1e-9), np.log(1e-4))), np.exp(rng.uniform(np.log(2.0), np.log(20.0)))
+        e = np.unique(np.exp(rng.uniform(np.log(lo_e), np.log(hi_e), k)))
+        tabs.append((e, rng.uniform(0.02, 0.6, e.size)))
+    comps = W.gen.make_xs(tabs)
+    mix = W.random_mixtures(968, 5, 6)
+    # FP64: every voxel; FP32: a well-sampled mesh (the 5 % standard-error gate)
+    n, n_rays = (32, 100_000) if prec == "p64" else (16, 1_600_000)
+    mesh = W.slab_mesh(969, n, 0.5, slab=2, n_mat=6)
+    rays = W.rays_in_box(970, mesh, n_rays)
+    say(f"case: mixtures {prec}, 6 mixtures of 5 components, slab {n}^3, {rays.n} rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs_mixtures(comps, mix)
+    tid = ctx.create_tally(0, prec)
+    if prec == "p64":
+        ctx.cast(tid, dev_arrays(rays, "f64"))
+        res = oracle.cast(mesh, comps, rays, n_threads=oracle_threads(), mix=mix)
+        g, _, n = rel_report(ctx.read(tid), res, gate="all")
+        say(f"  max rel over {n} voxels {g:.3e}")
+        assert g <= TOL_P64
+    else:
+        # the FP32 form rounds the mixed tables to FP32: compare on well-sampled voxels
+        ctx.cast(tid, dev_arrays(rays, "f32"))
+        res = oracle.cast(mesh, comps, W.rays_to_f32(rays).as_f64(), n_threads=oracle_threads(), mix=mix)
+        got = ctx.read(tid)
+        g, a, n = rel_report(got, res, gate="stderr", se_max=0.05)
+        say(f"  max rel over {n} gated voxels {g:.3e}; all voxels {a:.3e}")
+        assert n > 0.5 * mesh.n_voxels
+        # Beyond the FP32 arithmetic the other FP32 tests bound, the mixed tables are rounded to
+        # FP32 here and the oracle keeps FP64 components: |d Sigma| <= 2^-24 Sigma per lookup, so
+        # |d tau| <= 2^-24 tau, about 1e-6 at the optical depths of this mesh (tau < 20).
+        assert g <= TOL_P32
+
+
+def test_density_and_mixture_errors(vrc, ctx):
+    import torch
+    say("case: density and mixture errors and refusals")
+    base = W.slab_mesh(971, 8, 1.0, slab=2)
+    xs = W.gen.three_material_xs(972, 200)
+    ctx.set_xs(xs)
+    ctx.set_mesh(0, base)
+    for bad in (np.full(base.n_voxels, -1.0), np.full(base.n_voxels, np.nan)):
+        with pytest.raises(vrc.VrcError) as e:
+            vrc.vrc_set_mesh_density(ctx.handle, 0, bad)
+        assert e.value.status == vrc.VRC_ERR_INVALID
+    with pytest.raises(vrc.VrcError) as e:
+        vrc.vrc_set_mesh_density(ctx.handle, 5, np.ones(base.n_voxels))
+    assert e.value.status == vrc.VRC_ERR_INVALID
+    vrc.vrc_set_mesh_density(ctx.handle, 0, W.density_field(973, base.n_voxels))
+    tid = ctx.create_tally(0, "p32_t64")
+    rays = W.rays_in_box(974, base, 300)
+    arrays = dev_arrays(rays, "f32")
+    with pytest.raises(vrc.VrcError) as e:
+        ctx.cast_batches([(tid, arrays)])
+    assert e.value.status == vrc.VRC_ERR_INVALID
+    ctx.serve_start()
+    try:
+        with pytest.raises(vrc.VrcError) as e:
+            ctx.serve_submit(tid, host_arrays(rays, "f32"))
+        assert e.value.status == vrc.VRC_ERR_INVALID
+    finally:
+        ctx.serve_stop()
+    t64 = ctx.create_tally(0, "p64")
+    with pytest.raises(vrc.VrcError) as e:
+        ctx.walkers_run(t64, [0.1, 0.5, 1.0], base.lo + 4.0, direct=1, max_histories=10, duration_s=0.0)
+    assert e.value.status == vrc.VRC_ERR_INVALID
+    one = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(vrc.VrcError) as e:
+        ctx.next_event(0, "p64", [one] * 3, one, one, (0.0, 0.0, 0.0), one)
+    assert e.value.status == vrc.VRC_ERR_INVALID
+    with pytest.raises(vrc.VrcError) as e:
+        vrc.vrc_set_mesh_density(ctx.handle, 0, None)  # in use
+    assert e.value.status == vrc.VRC_ERR_STATE
+    ctx.cast(tid, arrays)
+    assert ctx.read(tid).sum() > 0
+    # removing the factors makes the mesh plain again
+    ctx.destroy_tally(tid)
+    ctx.destroy_tally(t64)
+    vrc.vrc_set_mesh_density(ctx.handle, 0, None)
+    tid = ctx.create_tally(0, "p32_t64")
+    ctx.cast_batches([(tid, arrays)])
+    assert ctx.read(tid).sum() > 0
+    # mixtures: bad component id, negative factor, empty mixture
+    comps = W.gen.make_xs([W.constant_sigma_table(0.5), W.constant_sigma_table(1.0)])
+    for offs, comp, frac in (([0, 1], [2], [1.0]), ([0, 1], [0], [-0.5]), ([0, 0, 1], [0], [1.0])):
+        with pytest.raises(vrc.VrcError) as e:
+            ctx.set_xs_mixtures(comps, W.Mixtures(np.array(offs, np.int64), np.array(comp, np.int32),
+                                                  np.array(frac)))
+        assert e.value.status == vrc.VRC_ERR_INVALID
