@@ -90,7 +90,7 @@ def parse():
                     help="also time the next-event (point-detector) estimator on the multimat mesh")
     ap.add_argument("--fom-histories", type=int, default=100000)
     ap.add_argument("--rect", type=int, default=1,
-                    help="also time the cast on a rectilinear mesh of the multimat box (plain path)")
+                    help="also time the cast on a rectilinear mesh of the multimat box (tile-split and atomic paths)")
     ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
     ap.add_argument("--precision-report", action="store_true",
@@ -113,9 +113,9 @@ def _counter_rows(csv_path: str, kernel: str, counter: str) -> list:
 
 # the kernels of one cast of the bench workload; the first one runs exactly once per cast
 PIPELINE = {0: ["cast_f64_kernel<float, float, false"],
-            1: ["entries_kernel<float, float, float>", "order_hist_kernel<float, float>",
-                "order_scatter_kernel<float, float>", "count_entries_kernel<float>", "scan_rows_kernel",
-                "scan_keys_kernel", "tile_kernel<float, float, 0>", "tile_reduce_kernel<0>"]}
+            1: ["entries_kernel<float, float, float, false>", "order_hist_kernel<float, float>",
+                "order_scatter_kernel<float, float>", "count_entries_kernel<float, false>", "scan_rows_kernel",
+                "scan_keys_kernel", "tile_kernel<float, float, 0, false>", "tile_reduce_kernel<0>"]}
 
 
 def write_traffic(paths, precision="p32_t64", copy_mib=1024) -> None:
@@ -229,9 +229,8 @@ def bench_rect(vrc, ctx, wl, arrays, counts, torch, stream, steps: int = 10) -> 
     """Rectilinear mesh: the multimat workload on a 100^3 mesh of the same 50 cm box with unequal
     spacings (drawn in [0.25, 0.75] cm and scaled to the box), the same materials, tables and rays.
 
-    A rectilinear mesh is cast by the plain kernel (one atomic per segment); the
-    uniform mesh on the same path is timed beside it for the cost of the table
-    reads.
+    Timed with the default tile-split accumulation and with one atomic per
+    segment (accumulate 0), each beside the uniform mesh on the same path.
     """
     import workloads as W
 
@@ -246,23 +245,27 @@ def bench_rect(vrc, ctx, wl, arrays, counts, torch, stream, steps: int = 10) -> 
     ctx.set_mesh(1, rect)
     prec = "p32_t64"
     S = ctx.count_segments(1, prec, arrays, counts, stream)
+    S_u = ctx.count_segments(0, prec, arrays, counts, stream)
     launch = ctx.get_launch()
-    ctx.set_launch(accumulate=0)
+    out = {"workload": "multimat materials, tables and 1e6 rays on a 100^3 rectilinear mesh of the same box "
+                       "(spacings 0.25-0.75 cm before scaling)", "precision": prec, "segments_per_step": S}
     try:
-        t_r = ctx.create_tally(1, prec)
-        per_r, tot_r, _ = time_casts(vrc, ctx, t_r, arrays, steps, 2, stream, torch)
-        S_u = ctx.count_segments(0, prec, arrays, counts, stream)
-        t_u = ctx.create_tally(0, prec)
-        per_u, tot_u, _ = time_casts(vrc, ctx, t_u, arrays, steps, 2, stream, torch)
+        for name, acc in (("tile_split", launch["accumulate"]), ("atomic", 0)):
+            ctx.set_launch(accumulate=acc)
+            t_r = ctx.create_tally(1, prec)
+            _, tot_r, _ = time_casts(vrc, ctx, t_r, arrays, steps, 2, stream, torch)
+            t_u = ctx.create_tally(0, prec)
+            _, tot_u, _ = time_casts(vrc, ctx, t_u, arrays, steps, 2, stream, torch)
+            ctx.destroy_tally(t_r)
+            ctx.destroy_tally(t_u)
+            ms_r, ms_u = tot_r / steps, tot_u / steps
+            alg = RAY_BYTES["f32"] * wl.rays.n + SEG_BYTES * S
+            out[name] = {"accumulate": acc, "ms_per_step": ms_r, "segments_per_s": S / (ms_r / 1e3),
+                         "hbm_frac": alg / (ms_r / 1e3) / 1e9 / HBM_PEAK_GBS,
+                         "uniform_ms_per_step": ms_u, "uniform_segments_per_s": S_u / (ms_u / 1e3)}
     finally:
         ctx.set_launch(**launch)
-    ms_r, ms_u = tot_r / steps, tot_u / steps
-    alg = RAY_BYTES["f32"] * wl.rays.n + SEG_BYTES * S
-    return {"workload": "multimat materials, tables and 1e6 rays on a 100^3 rectilinear mesh of the same box "
-                        "(spacings 0.25-0.75 cm before scaling)", "precision": prec, "path": "plain (accumulate 0)",
-            "segments_per_step": S, "ms_per_step": ms_r, "segments_per_s": S / (ms_r / 1e3),
-            "hbm_frac": alg / (ms_r / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "uniform_same_path": {"segments_per_step": S_u, "ms_per_step": ms_u, "segments_per_s": S_u / (ms_u / 1e3)}}
+    return out
 
 
 def cpu_baseline(wl, target_s):
@@ -644,8 +647,10 @@ def main():
     if args.rect:
         try:
             rect_form = bench_rect(vrc, ctx, wl, arrays, counts, torch, stream)
-            log(f"bench: rectilinear mesh {rect_form['segments_per_s']:.3e} segments/s (uniform on the same path "
-                f"{rect_form['uniform_same_path']['segments_per_s']:.3e})")
+            log(f"bench: rectilinear mesh {rect_form['tile_split']['segments_per_s']:.3e} segments/s tile-split, "
+                f"{rect_form['atomic']['segments_per_s']:.3e} atomic (uniform: "
+                f"{rect_form['tile_split']['uniform_segments_per_s']:.3e}, "
+                f"{rect_form['atomic']['uniform_segments_per_s']:.3e})")
         except Exception as exc:  # the headline line must still be printed
             log(f"bench: rectilinear measurement failed: {exc!r}")
             rect_form = {"error": repr(exc)}

@@ -23,7 +23,9 @@
  *     same context returns VRC_ERR_DEVICE.
  *   - Meshes are uniform per axis: lo[3] (cm), h[3] (cm), n[3] voxels; voxel
  *     (i,j,k) covers [lo+i h, lo+(i+1) h) on each axis (half-open), and has
- *     linear index i + n0 (j + n1 k) ("x fastest").  Outside the mesh is
+ *     linear index i + n0 (j + n1 k) ("x fastest").  A rectilinear mesh
+ *     (vrc_set_mesh_rect) takes the planes from a table per axis instead, and
+ *     density factors (vrc_set_mesh_density) scale each voxel's Sigma.  Outside the mesh is
  *     vacuum: rays start scoring where they enter and stop where they leave
  *     (Sec. 5.1: no reflecting boundary).
  *   - Tallies are raw sums in weight * cm, laid out [bin][k][j][i]; divide by
@@ -150,10 +152,10 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
  * has n[a]+1 finite, strictly increasing host values in cm, copied (FP64,
  * and an FP32 copy for the FP32 traversal forms).  mat as in vrc_set_mesh.
  * The traversal is the same 3D DDA with the next plane read from the table
- * instead of lo + k h.  Rectilinear meshes are cast by vrc_cast_rays (plain
- * accumulation only: accumulate 1..3 fall back to it), vrc_trace_rays and
- * vrc_count_segments; the batched, serving, walker and next-event calls
- * return VRC_ERR_INVALID on them.  Tallies in an FP32 form are refused
+ * instead of lo + k h.  Rectilinear meshes are cast by vrc_cast_rays (every
+ * accumulate setting, the tile-split accumulation included: its tile walks
+ * read the tables too), vrc_trace_rays and vrc_count_segments; the batched,
+ * serving, walker and next-event calls return VRC_ERR_INVALID on them.  Tallies in an FP32 form are refused
  * (VRC_ERR_INVALID at cast time) when two planes of an axis round to the
  * same float.  Errors: VRC_ERR_INVALID (bad n or planes), VRC_ERR_STATE (a
  * tally uses the mesh), VRC_ERR_NOMEM.                                     */

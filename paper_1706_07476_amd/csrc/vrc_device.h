@@ -276,18 +276,30 @@ struct Walker {
         const bool px = __builtin_isinf(ix), py = __builtin_isinf(iy), pz = __builtin_isinf(iz);
         R t_enter = R(0);
         t_exit = Num<R>::inf();
-        clip_axis(lox, hx, nx, ox, ix, px, t_enter, t_exit);
-        clip_axis(loy, hy, ny, oy, iy, py, t_enter, t_exit);
-        clip_axis(loz, hz, nz, oz, iz, pz, t_enter, t_exit);
+        if constexpr (RECT) {
+            clip_planes(M.pl[0][0], M.pl[0][nx], ox, ix, px, t_enter, t_exit);
+            clip_planes(M.pl[1][0], M.pl[1][ny], oy, iy, py, t_enter, t_exit);
+            clip_planes(M.pl[2][0], M.pl[2][nz], oz, iz, pz, t_enter, t_exit);
+        } else {
+            clip_axis(lox, hx, nx, ox, ix, px, t_enter, t_exit);
+            clip_axis(loy, hy, ny, oy, iy, py, t_enter, t_exit);
+            clip_axis(loz, hz, nz, oz, iz, pz, t_enter, t_exit);
+        }
         sx = px ? 0 : (ux > R(0) ? 1 : -1);
         sy = py ? 0 : (uy > R(0) ? 1 : -1);
         sz = pz ? 0 : (uz > R(0) ? 1 : -1);
         kx = kx_;
         ky = ky_;
         kz = kz_;
-        tx = px ? Num<R>::inf() : (plane(lox, hx, kx + (sx > 0 ? 1 : 0)) - ox) * ix;
-        ty = py ? Num<R>::inf() : (plane(loy, hy, ky + (sy > 0 ? 1 : 0)) - oy) * iy;
-        tz = pz ? Num<R>::inf() : (plane(loz, hz, kz + (sz > 0 ? 1 : 0)) - oz) * iz;
+        if constexpr (RECT) {
+            tx = px ? Num<R>::inf() : (M.pl[0][kx + (sx > 0 ? 1 : 0)] - ox) * ix;
+            ty = py ? Num<R>::inf() : (M.pl[1][ky + (sy > 0 ? 1 : 0)] - oy) * iy;
+            tz = pz ? Num<R>::inf() : (M.pl[2][kz + (sz > 0 ? 1 : 0)] - oz) * iz;
+        } else {
+            tx = px ? Num<R>::inf() : (plane(lox, hx, kx + (sx > 0 ? 1 : 0)) - ox) * ix;
+            ty = py ? Num<R>::inf() : (plane(loy, hy, ky + (sy > 0 ? 1 : 0)) - oy) * iy;
+            tz = pz ? Num<R>::inf() : (plane(loz, hz, kz + (sz > 0 ? 1 : 0)) - oz) * iz;
+        }
         cur = cur_;
         budget = 3 * kTileEdge + 3;
         const int ax0 = kx & ~(kTileEdge - 1), ay0 = ky & ~(kTileEdge - 1), az0 = kz & ~(kTileEdge - 1);

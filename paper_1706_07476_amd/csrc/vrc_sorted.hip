@@ -439,21 +439,26 @@ struct RayDeal {
 // include these, so its pieces in a tile are of positive length exactly when
 // the tile's interval here is (ties between axes only make zero-length
 // intervals, which neither walk counts).  on_tile(ti, tj, tk) per tile.
-template <typename R, class F>
+template <typename R, bool RECT, class F>
 __device__ __forceinline__ void walk_tiles(const MeshP<R> &M, R ox, R oy, R oz, R ux, R uy, R uz, F &&on_tile)
 {
-    Walker<R> w;
+    Walker<R, RECT> w;
     if (!w.start(M, ox, oy, oz, ux, uy, uz)) return;
     const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
     const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
     int ti = w.kx >> kTileBits, tj = w.ky >> kTileBits, tk = w.kz >> kTileBits;
-    // parameter of the next tile plane on each axis (the far side of the tile in the direction of travel)
-    auto cross = [](R lo, R h, R o, R inv, int s, int t) -> R {
-        return s == 0 ? Num<R>::inf() : (plane(lo, h, (t + (s > 0 ? 1 : 0)) << kTileBits) - o) * inv;
+    // parameter of the next tile plane on each axis (the far side of the tile in the direction of travel);
+    // a rectilinear mesh reads the plane from its table, the far side of a last, partial tile being the
+    // mesh's last plane (a uniform mesh's formula may run past it: that crossing lies beyond the exit too)
+    auto cross = [&](int a, R lo, R h, R o, R inv, int s, int t) -> R {
+        if (s == 0) return Num<R>::inf();
+        const int k = (t + (s > 0 ? 1 : 0)) << kTileBits;
+        if constexpr (RECT) return (M.pl[a][k < M.n[a] ? k : M.n[a]] - o) * inv;
+        else return (plane(lo, h, k) - o) * inv;
     };
-    R cx = cross(lox, hx, ox, w.ix, w.sx, ti);
-    R cy = cross(loy, hy, oy, w.iy, w.sy, tj);
-    R cz = cross(loz, hz, oz, w.iz, w.sz, tk);
+    R cx = cross(0, lox, hx, ox, w.ix, w.sx, ti);
+    R cy = cross(1, loy, hy, oy, w.iy, w.sy, tj);
+    R cz = cross(2, loz, hz, oz, w.iz, w.sz, tk);
     R cur = w.cur;
     const R t_exit = w.t_exit;
     for (int guard = (M.n[0] + M.n[1] + M.n[2]) / kTileEdge + 6; guard > 0; --guard) {
@@ -466,20 +471,20 @@ __device__ __forceinline__ void walk_tiles(const MeshP<R> &M, R ox, R oy, R oz, 
         cur = ta;
         if (ax) {
             ti += w.sx;
-            cx = cross(lox, hx, ox, w.ix, w.sx, ti);
+            cx = cross(0, lox, hx, ox, w.ix, w.sx, ti);
         } else if (ay) {
             tj += w.sy;
-            cy = cross(loy, hy, oy, w.iy, w.sy, tj);
+            cy = cross(1, loy, hy, oy, w.iy, w.sy, tj);
         } else {
             tk += w.sz;
-            cz = cross(loz, hz, oz, w.iz, w.sz, tk);
+            cz = cross(2, loz, hz, oz, w.iz, w.sz, tk);
         }
     }
 }
 
 // Counting pass: records per (block, key) of the entries pass, from the
 // tile walk of each ray the block will walk.
-template <typename R>
+template <typename R, bool RECT>
 __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
 {
     __shared__ uint32_t s_hist[kMaxKeys];
@@ -495,7 +500,7 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
         const int bin = energy_bin(A.tally, static_cast<double>(rr.e));
         if (bin < 0) continue;
         const int key0 = bin * A.g.n_tiles;
-        walk_tiles(A.mesh, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz, [&](int ti, int tj, int tk) {
+        walk_tiles<R, RECT>(A.mesh, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz, [&](int ti, int tj, int tk) {
             atomicAdd(&s_hist[key0 + ti + A.g.ntx * (tj + A.g.nty * tk)], 1u);
         });
     }
@@ -579,7 +584,7 @@ struct EmitEntries {
 };
 
 // (FP32 walks: register budget for six wavefronts per SIMD, all that LDS allows)
-template <typename R, typename RT, typename S>
+template <typename R, typename RT, typename S, bool RECT>
 __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     entries_kernel(EntryArgs<R> A)
 {
@@ -596,7 +601,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     const RayDeal deal(n);
     EmitEntries<R, S> em{mysig, __ffs(bd) - 1, S(0), S(0), 0u, false, R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0),
                          0, A.g, static_cast<Entry<R, S> *>(A.sorted), static_cast<uint32_t>(A.cap), s_next};
-    Walker<R> wk;
+    Walker<R, RECT> wk;
     const MeshMaterials mats{A.mesh.mat};
     const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
     for (int64_t round = 0; deal.more(round); ++round) {
@@ -817,7 +822,7 @@ __device__ __forceinline__ int64_t tile_element(int i, int bin, int tx, int ty, 
 // of the key's records, else into the block's partial-tile slot for
 // tile_reduce_kernel.
 // (FP32 scores: register budget for eight wavefronts per SIMD, two blocks of 1024)
-template <typename R, typename S, int FLUSH>
+template <typename R, typename S, int FLUSH, bool RECT>
 __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(TileArgs<R> A)
 {
     __shared__ double acc[kTileVoxels];
@@ -850,7 +855,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
     const Entry<R, S> *rec = static_cast<const Entry<R, S> *>(A.sorted);
     PutLds put{acc};
     TileScorer<S, PutLds> sc{mysig, __ffs(bd) - 1, S(0), put};
-    Walker<R> wk;
+    Walker<R, RECT> wk;
     constexpr int PER = 1;  // the records of one block-sized chunk are ordered together
     for (; key < n_keys; ++key) {
         const uint32_t kb = A.key_base[key], ke = A.key_base[key + 1];
@@ -1036,28 +1041,36 @@ hipError_t resident_per_cu(SortScratch &sc, const void *fn, int block, size_t ld
 
 // The tiles pass over every resident block (so the records are dealt out to
 // all of the GPU at once), then the reduction of keys that span blocks.
-template <typename R, typename S, int FLUSH>
+template <typename R, typename S, int FLUSH, bool RECT>
 hipError_t launch_tiles(vrc_ctx &ctx, TileArgs<R> T, int tb, size_t lds, hipStream_t s)
 {
     SortScratch &sc = ctx.sort_scratch;
     int per_cu = 0;
-    hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&tile_kernel<R, S, FLUSH>), tb, lds, per_cu);
+    hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&tile_kernel<R, S, FLUSH, RECT>), tb, lds, per_cu);
     if (e != hipSuccess) return e;
     const int n_blocks = ctx.n_cu * per_cu;
     e = grow(sc.partial, sc.partial_cap, sizeof(double) * 2 * static_cast<size_t>(n_blocks) * kTileVoxels);
     if (e != hipSuccess) return e;
     T.partial = static_cast<double *>(sc.partial);
     T.n_blocks = n_blocks;
-    hipLaunchKernelGGL((tile_kernel<R, S, FLUSH>), dim3(n_blocks), dim3(tb), lds, s, T);
+    hipLaunchKernelGGL((tile_kernel<R, S, FLUSH, RECT>), dim3(n_blocks), dim3(tb), lds, s, T);
     hipLaunchKernelGGL((tile_reduce_kernel<FLUSH>), dim3(T.g.n_keys, kReduceSplit), dim3(256), 0, s, T.key_base, T.g, n_blocks,
                        static_cast<const double *>(T.partial), T.mesh.n[0], T.mesh.n[1], T.mesh.n[2], T.nvox,
                        T.tally);
     return hipGetLastError();
 }
 
-template <typename R, typename RT, typename S>
-hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
-                      const SortGeom &g, int flush, hipStream_t s)
+template <typename R>
+const R *plane_tables(const MeshHost &m);
+template <>
+const float *plane_tables<float>(const MeshHost &m) { return m.d_pl32; }
+template <>
+const double *plane_tables<double>(const MeshHost &m) { return m.d_pl64; }
+
+// RECT: the mesh is rectilinear (its walks read the plane tables).
+template <typename R, typename RT, typename S, bool RECT>
+hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
+                           const SortGeom &g, int flush, hipStream_t s)
 {
     SortScratch &sc = ctx.sort_scratch;
     const int G = ctx.n_cu * 2;  // blocks of the ordering pass (a run of rays each)
@@ -1078,8 +1091,8 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
     // cross.
     int per_cu = 0;
     {
-        hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&entries_kernel<R, RT, S>), kBlock, lds1,
-                                       per_cu);
+        hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&entries_kernel<R, RT, S, RECT>), kBlock,
+                                       lds1, per_cu);
         if (e != hipSuccess) return e;
     }
     const int64_t G_res = static_cast<int64_t>(ctx.n_cu) * per_cu;
@@ -1111,6 +1124,12 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
             mesh.n[a] = m.n[a];
         }
         mesh.mat = m.d_mat;
+        if constexpr (RECT) {
+            const R *base = plane_tables<R>(m);  // x, y and z tables back to back
+            mesh.pl[0] = base;
+            mesh.pl[1] = base + m.n[0] + 1;
+            mesh.pl[2] = base + m.n[0] + 1 + m.n[1] + 1;
+        }
         EntryArgs<R> A;
         A.mesh = mesh;
         A.xs = xs_of<R>(ctx.xs);
@@ -1148,13 +1167,13 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, sub, nr,
                            static_cast<const uint8_t *>(sc.bucket), rays_block, row_off, key_base,
                            static_cast<RayRec<R> *>(sc.ordered));
-        hipLaunchKernelGGL((count_entries_kernel<R>), dim3(Ge), dim3(kBlock), 0, s, A);
+        hipLaunchKernelGGL((count_entries_kernel<R, RECT>), dim3(Ge), dim3(kBlock), 0, s, A);
         hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
                            static_cast<const uint32_t *>(sc.hist), Ge, g.n_keys, static_cast<uint32_t *>(sc.row_off),
                            static_cast<uint32_t *>(sc.key_tot));
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(sc.key_tot),
                            g.n_keys, static_cast<uint32_t *>(sc.key_base));
-        hipLaunchKernelGGL((entries_kernel<R, RT, S>), dim3(Ge), dim3(kBlock), lds1, s, A);
+        hipLaunchKernelGGL((entries_kernel<R, RT, S, RECT>), dim3(Ge), dim3(kBlock), lds1, s, A);
         TileArgs<R> T;
         T.mesh = mesh;
         T.xs = A.xs;
@@ -1166,12 +1185,12 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
         T.tally = t.d_data;
         if constexpr (sizeof(S) == 4) {
             if (flush == kFlushKahan) {
-                e = launch_tiles<R, S, kFlushKahan>(ctx, T, tb, lds2, s);
+                e = launch_tiles<R, S, kFlushKahan, RECT>(ctx, T, tb, lds2, s);
                 goto launched;
             }
         }
-        e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic>(ctx, T, tb, lds2, s)
-                                  : launch_tiles<R, S, kFlushPlain>(ctx, T, tb, lds2, s);
+        e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic, RECT>(ctx, T, tb, lds2, s)
+                                  : launch_tiles<R, S, kFlushPlain, RECT>(ctx, T, tb, lds2, s);
     launched:
         if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1183,11 +1202,19 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
     return hipSuccess;
 }
 
+template <typename R, typename RT, typename S>
+hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
+                      const SortGeom &g, int flush, hipStream_t s)
+{
+    return m.rect ? run_sorted_kind<R, RT, S, true>(ctx, t, m, src, n_rays, g, flush, s)
+                  : run_sorted_kind<R, RT, S, false>(ctx, t, m, src, n_rays, g, flush, s);
+}
+
 }  // namespace
 
 bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m)
 {
-    if (ctx.sort_scratch.done == nullptr || m.rect || m.dens) return false;
+    if (ctx.sort_scratch.done == nullptr || m.dens) return false;
     const SortGeom g = geometry(t, m);
     if (g.n_keys == 0) return false;
     const size_t sb = (t.prec == VRC_P32_T64 || t.prec == VRC_P32_KAHAN) ? sizeof(float) : sizeof(double);

@@ -5,7 +5,8 @@ axis's table.  Both sides compute every crossing time as (X_a(k) - o_a) inv_a
 from the same table values, so voxel sequences, segment counts and lengths
 are compared bit for bit (FP64, and FP32 on the FP32-rounded planes and
 rays); tallies within 1e-12 (FP64) and 1e-5 on well-sampled voxels (FP32
-forms), as for uniform meshes.  Plane tables equal to a uniform mesh's
+forms), as for uniform meshes, on the per-segment atomic path and on the
+tile-split accumulation.  Plane tables equal to a uniform mesh's
 planes give the uniform mesh's traces bit for bit.  Rays start inside,
 outside, on planes and along planes.  Paths that take uniform meshes only
 refuse a rectilinear one.
@@ -146,10 +147,11 @@ def test_segment_counts_bit_exact(ctx):
         assert total == int(ref.sum())
 
 
-@pytest.mark.parametrize("accumulate", [0, 1])
+@pytest.mark.parametrize("accumulate", [0, 1, 3])
 def test_tally_fp64_matches_oracle(ctx, accumulate):
-    """accumulate 1 with more than 131072 rays: the tile-split accumulation does not take
-    rectilinear meshes, so the plain accumulation runs; the tally is the same."""
+    """accumulate 0: one atomic per segment; 1 (more than 131072 rays) and 3: the tile-split
+    accumulation (atomic and plain flush), its tile walks reading the plane tables; the mesh's
+    extents are not multiples of the 16-voxel tile."""
     mesh = W.rect_mesh(906, (52, 47, 49), lo=(1.0, -3.0, 0.5), h_min=0.15, h_max=1.4)
     xs = W.gen.three_material_xs(907, 2000)
     rays = mixed_rays(908, mesh, 140_000)
@@ -166,14 +168,16 @@ def test_tally_fp64_matches_oracle(ctx, accumulate):
     assert g <= TOL_P64
 
 
+@pytest.mark.parametrize("accumulate", [0, 1])
 @pytest.mark.parametrize("prec", ["p32_t64", "p32_kahan", "p32_d64"])
-def test_tally_fp32_forms_well_sampled(ctx, prec):
+def test_tally_fp32_forms_well_sampled(ctx, prec, accumulate):
     mesh = W.rect_mesh(909, (17, 15, 16), h_min=0.3, h_max=0.9)
     xs = W.gen.three_material_xs(910, 2000)
     rays = W.rays_in_box(911, mesh, 1_600_000)
-    say(f"case: rect tally {prec}, 17x15x16, {rays.n} rays")
+    say(f"case: rect tally {prec}, 17x15x16, {rays.n} rays, accumulate {accumulate}")
     ctx.set_mesh(0, mesh)
     ctx.set_xs(xs)
+    ctx.set_launch(accumulate=accumulate)
     tid = ctx.create_tally(0, prec)
     ctx.cast(tid, dev_arrays(rays, "f32"))
     res = oracle.cast(rect32(mesh), xs32(xs), W.rays_to_f32(rays).as_f64(), n_threads=oracle_threads())
