@@ -90,7 +90,8 @@ def parse():
                     help="also time the next-event (point-detector) estimator on the multimat mesh")
     ap.add_argument("--fom-histories", type=int, default=100000)
     ap.add_argument("--rect", type=int, default=1,
-                    help="also time the cast on a rectilinear mesh of the multimat box (tile-split and atomic paths)")
+                    help="also time the cast on a rectilinear mesh of the multimat box and on the multimat mesh with "
+                         "per-voxel density factors (tile-split and atomic paths)")
     ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
     ap.add_argument("--precision-report", action="store_true",
@@ -113,9 +114,9 @@ def _counter_rows(csv_path: str, kernel: str, counter: str) -> list:
 
 # the kernels of one cast of the bench workload; the first one runs exactly once per cast
 PIPELINE = {0: ["cast_f64_kernel<float, float, false"],
-            1: ["entries_kernel<float, float, float, false>", "order_hist_kernel<float, float>",
+            1: ["entries_kernel<float, float, float, false, false>", "order_hist_kernel<float, float>",
                 "order_scatter_kernel<float, float>", "count_entries_kernel<float, false>", "scan_rows_kernel",
-                "scan_keys_kernel", "tile_kernel<float, float, 0, false>", "tile_reduce_kernel<0>"]}
+                "scan_keys_kernel", "tile_kernel<float, float, 0, false, false>", "tile_reduce_kernel<0>"]}
 
 
 def write_traffic(paths, precision="p32_t64", copy_mib=1024) -> None:
@@ -263,6 +264,33 @@ def bench_rect(vrc, ctx, wl, arrays, counts, torch, stream, steps: int = 10) -> 
             out[name] = {"accumulate": acc, "ms_per_step": ms_r, "segments_per_s": S / (ms_r / 1e3),
                          "hbm_frac": alg / (ms_r / 1e3) / 1e9 / HBM_PEAK_GBS,
                          "uniform_ms_per_step": ms_u, "uniform_segments_per_s": S_u / (ms_u / 1e3)}
+    finally:
+        ctx.set_launch(**launch)
+    return out
+
+
+def bench_density(vrc, ctx, wl, arrays, torch, stream, steps: int = 10) -> dict:
+    """Per-voxel density factors: the multimat workload with a factor uniform in [0.5, 2] per voxel,
+    timed with the default tile-split accumulation and with one atomic per segment, each beside the
+    mesh without factors on the same path."""
+    import workloads as W
+
+    m = wl.mesh
+    ctx.set_mesh(2, W.Mesh(m.lo, m.h, m.n, m.mat, W.density_field(2025, m.n_voxels, 0.5, 2.0)))
+    prec = "p32_t64"
+    launch = ctx.get_launch()
+    out = {"workload": "multimat mesh, tables and 1e6 rays; density factors uniform in [0.5, 2] per voxel",
+           "precision": prec}
+    try:
+        for name, acc in (("tile_split", launch["accumulate"]), ("atomic", 0)):
+            ctx.set_launch(accumulate=acc)
+            t_d = ctx.create_tally(2, prec)
+            _, tot_d, _ = time_casts(vrc, ctx, t_d, arrays, steps, 2, stream, torch)
+            t_u = ctx.create_tally(0, prec)
+            _, tot_u, _ = time_casts(vrc, ctx, t_u, arrays, steps, 2, stream, torch)
+            ctx.destroy_tally(t_d)
+            ctx.destroy_tally(t_u)
+            out[name] = {"accumulate": acc, "ms_per_step": tot_d / steps, "plain_mesh_ms_per_step": tot_u / steps}
     finally:
         ctx.set_launch(**launch)
     return out
@@ -654,6 +682,17 @@ def main():
         except Exception as exc:  # the headline line must still be printed
             log(f"bench: rectilinear measurement failed: {exc!r}")
             rect_form = {"error": repr(exc)}
+    density_form = None
+    if args.rect:
+        try:
+            density_form = bench_density(vrc, ctx, wl, arrays, torch, stream)
+            for k in ("tile_split", "atomic"):
+                density_form[k]["segments_per_s"] = S / (density_form[k]["ms_per_step"] / 1e3)
+            log(f"bench: density factors {density_form['tile_split']['segments_per_s']:.3e} segments/s tile-split, "
+                f"{density_form['atomic']['segments_per_s']:.3e} atomic")
+        except Exception as exc:  # the headline line must still be printed
+            log(f"bench: density measurement failed: {exc!r}")
+            density_form = {"error": repr(exc)}
     fom_form = None
     if args.fom:
         try:
@@ -708,6 +747,7 @@ def main():
         "fom_form": fom_form,
         "next_event_form": next_event,
         "rect_form": rect_form,
+        "density_form": density_form,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)

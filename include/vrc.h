@@ -169,9 +169,9 @@ vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], cons
  * (rho, 1/rho) in FP64 and FP32; the score divides by the voxel's Sigma as
  * (1/Sigma_m) * (1/rho).  rho == NULL removes the factors.  Setting or
  * replacing the mesh removes them too.  Such a mesh is cast by vrc_cast_rays
- * (plain accumulation; accumulate 1..3 fall back to it), vrc_trace_rays and
- * vrc_count_segments; the batched, serving, walker and next-event calls
- * return VRC_ERR_INVALID on it.  Errors: VRC_ERR_INVALID (no such mesh, a
+ * (every accumulate setting), vrc_trace_rays and vrc_count_segments; the
+ * batched, serving, walker and next-event calls return VRC_ERR_INVALID on
+ * it.  Errors: VRC_ERR_INVALID (no such mesh, a
  * bad factor), VRC_ERR_STATE (a tally uses the mesh), VRC_ERR_NOMEM.        */
 vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho);
 

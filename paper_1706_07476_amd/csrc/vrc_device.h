@@ -648,16 +648,21 @@ __device__ __forceinline__ void stage_lds(const XsP<R> &X, int hash_in_lds, cons
 
 // Cross sections of the ray's energy, then the walk (in R) with the running
 // score (in S: R itself, or double over an FP32 walk).
+// The density-factor pairs of a mesh in the scoring precision S.
+template <typename S, typename R>
+__device__ __forceinline__ const DensPair<S> *density_of(const MeshP<R> &M)
+{
+    if constexpr (std::is_same<S, double>::value) return M.rho64;
+    else return M.rho32;
+}
+
 template <typename R, typename S, class Put, bool RECT = false, bool DENS = false>
 __device__ __forceinline__ void cast_one(const MeshP<R> &M, const XsP<R> &X, const int32_t *hash, S (*mysig)[2],
                                          int bd, R ox, R oy, R oz, R ux, R uy, R uz, R E, R w, Put &put)
 {
     xs_lookup(X, hash, E, mysig, bd);
     Scorer<S, Put, DENS> sc(mysig, bd, static_cast<S>(w), put);
-    if constexpr (DENS) {
-        if constexpr (std::is_same<S, double>::value) sc.dens = M.rho64;
-        else sc.dens = M.rho32;
-    }
+    if constexpr (DENS) sc.dens = density_of<S>(M);
     walk<R, Scorer<S, Put, DENS>, RECT>(M, ox, oy, oz, ux, uy, uz, sc);
 }
 

@@ -513,9 +513,10 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
 // (same products, same TwoSum), and a record at every tile entry, written
 // straight to its place in key-major order (the block's next place for the
 // key, from the counting pass).
-template <typename R, typename S>
+template <typename R, typename S, bool DENS>
 struct EmitEntries {
     const S (*sig)[2];
+    const DensPair<S> *dens;  // DENS: per-voxel factors on Sigma (the score's product, so tau matches)
     int shift;  // log2 of the LDS column stride (the block size)
     S tau_hi, tau_lo;
     uint32_t tile;  // tile_tag of the current tile
@@ -564,7 +565,7 @@ struct EmitEntries {
         w = w_;
         key0 = key0_;
     }
-    __device__ __forceinline__ void operator()(int32_t, int m, R len, int ci, int cj, int ck, R t0)
+    __device__ __forceinline__ void operator()(int32_t vox, int m, R len, int ci, int cj, int ck, R t0)
     {
         const uint32_t tg = tile_tag(ci >> kTileBits, cj >> kTileBits, ck >> kTileBits);
         if (tg != tile || !started) {
@@ -574,7 +575,9 @@ struct EmitEntries {
             emit(first, ci, cj, ck, t0);
         }
         const S l = static_cast<S>(len);
-        const S x = sig[m << shift][0] * l;
+        S sg = sig[m << shift][0];
+        if constexpr (DENS) sg = sg * dens[vox].rho;
+        const S x = sg * l;
         const S t = tau_hi + x;
         const S bv = t - tau_hi;
         const S err = (tau_hi - (t - bv)) + (x - bv);
@@ -584,7 +587,7 @@ struct EmitEntries {
 };
 
 // (FP32 walks: register budget for six wavefronts per SIMD, all that LDS allows)
-template <typename R, typename RT, typename S, bool RECT>
+template <typename R, typename RT, typename S, bool RECT, bool DENS>
 __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     entries_kernel(EntryArgs<R> A)
 {
@@ -599,8 +602,9 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     S(*mysig)[2] = sig + threadIdx.x;
     const int64_t n = A.rays.n;
     const RayDeal deal(n);
-    EmitEntries<R, S> em{mysig, __ffs(bd) - 1, S(0), S(0), 0u, false, R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0),
-                         0, A.g, static_cast<Entry<R, S> *>(A.sorted), static_cast<uint32_t>(A.cap), s_next};
+    EmitEntries<R, S, DENS> em{mysig, density_of<S>(A.mesh), __ffs(bd) - 1, S(0), S(0), 0u, false, R(0), R(0), R(0),
+                               R(0), R(0), R(0), R(0), R(0), 0, A.g, static_cast<Entry<R, S> *>(A.sorted),
+                               static_cast<uint32_t>(A.cap), s_next};
     Walker<R, RECT> wk;
     const MeshMaterials mats{A.mesh.mat};
     const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
@@ -725,12 +729,14 @@ struct PutLds {
 // weight is set at the tile entry as the uninterrupted walk re-anchors it
 // there, w e^{-tau_hi} (1 - tau_lo), and then multiplied by each piece's
 // e^{-x}, giving the same scores bit for bit.
-template <typename R, class Put>
+template <typename R, class Put, bool DENS>
 struct TileScorer {
     const R (*sig)[2];
     int shift;  // log2 of the LDS column stride (the block size)
     R w_in;
     Put &put;
+    const DensPair<R> *dens;  // DENS: per-voxel factors, by global voxel index
+    int nx, ny;
     __device__ __forceinline__ void resume(R w, R th, R tl, bool first)
     {
         if (first) {
@@ -745,8 +751,13 @@ struct TileScorer {
     __device__ __forceinline__ void operator()(int32_t vox, int m, L len, int ci, int cj, int ck, L)
     {
         const R l = static_cast<R>(len);
-        const R s = sig[m << shift][0];
-        const R is = sig[m << shift][1];
+        R s = sig[m << shift][0];
+        R is = sig[m << shift][1];
+        if constexpr (DENS) {
+            const DensPair<R> d = dens[ci + nx * (cj + ny * ck)];
+            s = s * d.rho;  // as the whole-ray score scales them
+            is = is * d.inv;
+        }
         const R x = s * l;
         R g, em;
         attenuation(x, g, em);
@@ -822,7 +833,7 @@ __device__ __forceinline__ int64_t tile_element(int i, int bin, int tx, int ty, 
 // of the key's records, else into the block's partial-tile slot for
 // tile_reduce_kernel.
 // (FP32 scores: register budget for eight wavefronts per SIMD, two blocks of 1024)
-template <typename R, typename S, int FLUSH, bool RECT>
+template <typename R, typename S, int FLUSH, bool RECT, bool DENS>
 __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(TileArgs<R> A)
 {
     __shared__ double acc[kTileVoxels];
@@ -854,7 +865,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
     S(*mysig)[2] = sig + threadIdx.x;
     const Entry<R, S> *rec = static_cast<const Entry<R, S> *>(A.sorted);
     PutLds put{acc};
-    TileScorer<S, PutLds> sc{mysig, __ffs(bd) - 1, S(0), put};
+    TileScorer<S, PutLds, DENS> sc{mysig, __ffs(bd) - 1, S(0), put, density_of<S>(A.mesh), nx, ny};
     Walker<R, RECT> wk;
     constexpr int PER = 1;  // the records of one block-sized chunk are ordered together
     for (; key < n_keys; ++key) {
@@ -1041,19 +1052,20 @@ hipError_t resident_per_cu(SortScratch &sc, const void *fn, int block, size_t ld
 
 // The tiles pass over every resident block (so the records are dealt out to
 // all of the GPU at once), then the reduction of keys that span blocks.
-template <typename R, typename S, int FLUSH, bool RECT>
+template <typename R, typename S, int FLUSH, bool RECT, bool DENS>
 hipError_t launch_tiles(vrc_ctx &ctx, TileArgs<R> T, int tb, size_t lds, hipStream_t s)
 {
     SortScratch &sc = ctx.sort_scratch;
     int per_cu = 0;
-    hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&tile_kernel<R, S, FLUSH, RECT>), tb, lds, per_cu);
+    hipError_t e =
+        resident_per_cu(sc, reinterpret_cast<const void *>(&tile_kernel<R, S, FLUSH, RECT, DENS>), tb, lds, per_cu);
     if (e != hipSuccess) return e;
     const int n_blocks = ctx.n_cu * per_cu;
     e = grow(sc.partial, sc.partial_cap, sizeof(double) * 2 * static_cast<size_t>(n_blocks) * kTileVoxels);
     if (e != hipSuccess) return e;
     T.partial = static_cast<double *>(sc.partial);
     T.n_blocks = n_blocks;
-    hipLaunchKernelGGL((tile_kernel<R, S, FLUSH, RECT>), dim3(n_blocks), dim3(tb), lds, s, T);
+    hipLaunchKernelGGL((tile_kernel<R, S, FLUSH, RECT, DENS>), dim3(n_blocks), dim3(tb), lds, s, T);
     hipLaunchKernelGGL((tile_reduce_kernel<FLUSH>), dim3(T.g.n_keys, kReduceSplit), dim3(256), 0, s, T.key_base, T.g, n_blocks,
                        static_cast<const double *>(T.partial), T.mesh.n[0], T.mesh.n[1], T.mesh.n[2], T.nvox,
                        T.tally);
@@ -1067,8 +1079,9 @@ const float *plane_tables<float>(const MeshHost &m) { return m.d_pl32; }
 template <>
 const double *plane_tables<double>(const MeshHost &m) { return m.d_pl64; }
 
-// RECT: the mesh is rectilinear (its walks read the plane tables).
-template <typename R, typename RT, typename S, bool RECT>
+// RECT: the mesh is rectilinear (its walks read the plane tables); DENS: it
+// carries per-voxel density factors.
+template <typename R, typename RT, typename S, bool RECT, bool DENS>
 hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
                            const SortGeom &g, int flush, hipStream_t s)
 {
@@ -1091,8 +1104,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     // cross.
     int per_cu = 0;
     {
-        hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&entries_kernel<R, RT, S, RECT>), kBlock,
-                                       lds1, per_cu);
+        hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&entries_kernel<R, RT, S, RECT, DENS>),
+                                       kBlock, lds1, per_cu);
         if (e != hipSuccess) return e;
     }
     const int64_t G_res = static_cast<int64_t>(ctx.n_cu) * per_cu;
@@ -1129,6 +1142,10 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             mesh.pl[0] = base;
             mesh.pl[1] = base + m.n[0] + 1;
             mesh.pl[2] = base + m.n[0] + 1 + m.n[1] + 1;
+        }
+        if constexpr (DENS) {
+            mesh.rho32 = m.d_rho32;
+            mesh.rho64 = m.d_rho64;
         }
         EntryArgs<R> A;
         A.mesh = mesh;
@@ -1173,7 +1190,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
                            static_cast<uint32_t *>(sc.key_tot));
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(sc.key_tot),
                            g.n_keys, static_cast<uint32_t *>(sc.key_base));
-        hipLaunchKernelGGL((entries_kernel<R, RT, S, RECT>), dim3(Ge), dim3(kBlock), lds1, s, A);
+        hipLaunchKernelGGL((entries_kernel<R, RT, S, RECT, DENS>), dim3(Ge), dim3(kBlock), lds1, s, A);
         TileArgs<R> T;
         T.mesh = mesh;
         T.xs = A.xs;
@@ -1185,12 +1202,12 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         T.tally = t.d_data;
         if constexpr (sizeof(S) == 4) {
             if (flush == kFlushKahan) {
-                e = launch_tiles<R, S, kFlushKahan, RECT>(ctx, T, tb, lds2, s);
+                e = launch_tiles<R, S, kFlushKahan, RECT, DENS>(ctx, T, tb, lds2, s);
                 goto launched;
             }
         }
-        e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic, RECT>(ctx, T, tb, lds2, s)
-                                  : launch_tiles<R, S, kFlushPlain, RECT>(ctx, T, tb, lds2, s);
+        e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic, RECT, DENS>(ctx, T, tb, lds2, s)
+                                  : launch_tiles<R, S, kFlushPlain, RECT, DENS>(ctx, T, tb, lds2, s);
     launched:
         if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1206,15 +1223,18 @@ template <typename R, typename RT, typename S>
 hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
                       const SortGeom &g, int flush, hipStream_t s)
 {
-    return m.rect ? run_sorted_kind<R, RT, S, true>(ctx, t, m, src, n_rays, g, flush, s)
-                  : run_sorted_kind<R, RT, S, false>(ctx, t, m, src, n_rays, g, flush, s);
+    if (m.dens)
+        return m.rect ? run_sorted_kind<R, RT, S, true, true>(ctx, t, m, src, n_rays, g, flush, s)
+                      : run_sorted_kind<R, RT, S, false, true>(ctx, t, m, src, n_rays, g, flush, s);
+    return m.rect ? run_sorted_kind<R, RT, S, true, false>(ctx, t, m, src, n_rays, g, flush, s)
+                  : run_sorted_kind<R, RT, S, false, false>(ctx, t, m, src, n_rays, g, flush, s);
 }
 
 }  // namespace
 
 bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m)
 {
-    if (ctx.sort_scratch.done == nullptr || m.dens) return false;
+    if (ctx.sort_scratch.done == nullptr) return false;
     const SortGeom g = geometry(t, m);
     if (g.n_keys == 0) return false;
     const size_t sb = (t.prec == VRC_P32_T64 || t.prec == VRC_P32_KAHAN) ? sizeof(float) : sizeof(double);

@@ -5,7 +5,8 @@ and its reciprocal by the stored pair (rho, 1/rho)); a mixture's Sigma is
 sum_j f_j Sigma_j(E) (tabulated by the library on the union of its
 components' grids, evaluated by the oracle component by component).
 Tallies: 1e-12 (FP64), 1e-5 on well-sampled voxels (FP32 forms, against the
-oracle on the same FP32-rounded inputs); per-segment scores 1e-13.
+oracle on the same FP32-rounded inputs), on the per-segment atomic path and
+the tile-split accumulation; per-segment scores 1e-13.
 Unit factors give the plain scores bit for bit.  Paths that take plain
 meshes only refuse a mesh with factors.
 """
@@ -62,10 +63,10 @@ def f32_inputs(mesh, xs, rays, round_density):
     return m, x, W.rays_to_f32(rays).as_f64()
 
 
-@pytest.mark.parametrize("accumulate", [0, 1])
+@pytest.mark.parametrize("accumulate", [0, 1, 3])
 def test_density_tally_fp64(ctx, accumulate):
-    """accumulate 1 with 140000 rays: the tile-split accumulation does not take density factors,
-    the plain accumulation runs."""
+    """accumulate 0: one atomic per segment; 1 (140000 rays) and 3: the tile-split accumulation,
+    its entries pass scaling the optical depth and its tiles pass the scores by the factors."""
     base = W.slab_mesh(951, 40, 0.5, slab=5)
     mesh = with_density(base, W.density_field(952, base.n_voxels, 0.3, 2.5, frac_zero=0.05))
     xs = W.gen.three_material_xs(953, 2000)
@@ -83,14 +84,16 @@ def test_density_tally_fp64(ctx, accumulate):
     assert g <= TOL_P64
 
 
-def test_density_on_a_rectilinear_mesh_fp64(ctx):
+@pytest.mark.parametrize("accumulate", [0, 2])
+def test_density_on_a_rectilinear_mesh_fp64(ctx, accumulate):
     base = W.rect_mesh(955, (33, 29, 31), h_min=0.2, h_max=1.1)
     mesh = with_density(base, W.density_field(956, base.n_voxels, 0.5, 2.0, frac_zero=0.02))
     xs = W.gen.three_material_xs(957, 1000)
     rays = W.rays_in_box(958, mesh, 60_000)
-    say(f"case: density on a rect mesh, p64, 33x29x31, {rays.n} rays")
+    say(f"case: density on a rect mesh, p64, 33x29x31, {rays.n} rays, accumulate {accumulate}")
     ctx.set_mesh(0, mesh)
     ctx.set_xs(xs)
+    ctx.set_launch(accumulate=accumulate)
     tid = ctx.create_tally(0, "p64")
     ctx.cast(tid, dev_arrays(rays, "f64"))
     res = oracle.cast(mesh, xs, rays, n_threads=oracle_threads())
@@ -99,15 +102,17 @@ def test_density_on_a_rectilinear_mesh_fp64(ctx):
     assert g <= TOL_P64
 
 
+@pytest.mark.parametrize("accumulate", [0, 1])
 @pytest.mark.parametrize("prec", ["p32_t64", "p32_kahan", "p32_d64"])
-def test_density_fp32_forms_well_sampled(ctx, prec):
+def test_density_fp32_forms_well_sampled(ctx, prec, accumulate):
     base = W.slab_mesh(959, 16, 0.5, slab=4)
     mesh = with_density(base, W.density_field(960, base.n_voxels, 0.4, 2.2))
     xs = W.gen.three_material_xs(961, 2000)
     rays = W.rays_in_box(962, mesh, 1_600_000)
-    say(f"case: density tally {prec}, slab 16^3, {rays.n} rays")
+    say(f"case: density tally {prec}, slab 16^3, {rays.n} rays, accumulate {accumulate}")
     ctx.set_mesh(0, mesh)
     ctx.set_xs(xs)
+    ctx.set_launch(accumulate=accumulate)
     tid = ctx.create_tally(0, prec)
     ctx.cast(tid, dev_arrays(rays, "f32"))
     m, x, r = f32_inputs(mesh, xs, rays, round_density=prec != "p32_d64")
