@@ -184,6 +184,39 @@ struct TileMaterials {
     __device__ __forceinline__ int operator()(int32_t local, int, int, int) const { return mat[local]; }
 };
 
+// The same, with the voxel's density-factor pair loaded beside its material:
+// a walk asks for the next voxel's material one step before it scores that
+// voxel, so every call moves the pair of the previous call to *cur (the
+// voxel about to be scored) and loads the new voxel's into *next.  The
+// gather's latency then overlaps a whole step.  (A walk started with start()
+// reads its first material directly: its caller loads the first pair into
+// *next.)
+template <typename S>
+struct MeshMaterialsDens {
+    const uint8_t *mat;
+    const DensPair<S> *dens;
+    DensPair<S> *cur, *next;
+    __device__ __forceinline__ int operator()(int32_t vox, int, int, int) const
+    {
+        *cur = *next;
+        *next = dens[vox];
+        return mat[vox];
+    }
+};
+template <typename S>
+struct TileMaterialsDens {
+    const uint8_t *mat;  // LDS, kTileEdge^3, x fastest
+    const DensPair<S> *dens;
+    int nx, ny;  // the mesh, for the voxel's global index
+    DensPair<S> *cur, *next;
+    __device__ __forceinline__ int operator()(int32_t local, int i, int j, int k) const
+    {
+        *cur = *next;
+        *next = dens[i + nx * (j + ny * k)];
+        return mat[local];
+    }
+};
+
 // The walk of one ray as explicit state, one piece per step(), so that a
 // lane can switch to its next ray (or ray piece) the moment the current one
 // ends instead of waiting for the longest ray of its wavefront.  All state is

@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
 template <typename R, typename S, bool DENS>
 struct EmitEntries {
     const S (*sig)[2];
-    const DensPair<S> *dens;  // DENS: per-voxel factors on Sigma (the score's product, so tau matches)
+    const DensPair<S> *cur;  // DENS: the factors of the voxel being walked (loaded with its material)
     int shift;  // log2 of the LDS column stride (the block size)
     S tau_hi, tau_lo;
     uint32_t tile;  // tile_tag of the current tile
@@ -576,7 +576,7 @@ struct EmitEntries {
         }
         const S l = static_cast<S>(len);
         S sg = sig[m << shift][0];
-        if constexpr (DENS) sg = sg * dens[vox].rho;
+        if constexpr (DENS) sg = sg * cur->rho;  // the score's own product, so tau matches
         const S x = sg * l;
         const S t = tau_hi + x;
         const S bv = t - tau_hi;
@@ -602,11 +602,16 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     S(*mysig)[2] = sig + threadIdx.x;
     const int64_t n = A.rays.n;
     const RayDeal deal(n);
-    EmitEntries<R, S, DENS> em{mysig, density_of<S>(A.mesh), __ffs(bd) - 1, S(0), S(0), 0u, false, R(0), R(0), R(0),
+    DensPair<S> dcur{S(0), S(0)}, dnext{S(0), S(0)};
+    EmitEntries<R, S, DENS> em{mysig, &dcur, __ffs(bd) - 1, S(0), S(0), 0u, false, R(0), R(0), R(0),
                                R(0), R(0), R(0), R(0), R(0), 0, A.g, static_cast<Entry<R, S> *>(A.sorted),
                                static_cast<uint32_t>(A.cap), s_next};
     Walker<R, RECT> wk;
-    const MeshMaterials mats{A.mesh.mat};
+    const DensPair<S> *dens = density_of<S>(A.mesh);
+    const auto mats = [&] {
+        if constexpr (DENS) return MeshMaterialsDens<S>{A.mesh.mat, dens, &dcur, &dnext};
+        else return MeshMaterials{A.mesh.mat};
+    }();
     const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
     for (int64_t round = 0; deal.more(round); ++round) {
         const int64_t j = deal.ray(round);
@@ -618,6 +623,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
         xs_lookup(A.xs, hash, E, mysig, bd);
         em.reset(ox, oy, oz, ux, uy, uz, E, wt, bin * A.g.n_tiles);
         if (!wk.start(A.mesh, ox, oy, oz, ux, uy, uz)) continue;
+        if constexpr (DENS) dnext = dens[wk.vox];  // the first voxel's pair (start() reads its material itself)
         while (wk.step(A.mesh, em, mats)) {
         }
     }
@@ -735,8 +741,7 @@ struct TileScorer {
     int shift;  // log2 of the LDS column stride (the block size)
     R w_in;
     Put &put;
-    const DensPair<R> *dens;  // DENS: per-voxel factors, by global voxel index
-    int nx, ny;
+    const DensPair<R> *cur;  // DENS: the factors of the voxel being walked (loaded with its material)
     __device__ __forceinline__ void resume(R w, R th, R tl, bool first)
     {
         if (first) {
@@ -754,7 +759,7 @@ struct TileScorer {
         R s = sig[m << shift][0];
         R is = sig[m << shift][1];
         if constexpr (DENS) {
-            const DensPair<R> d = dens[ci + nx * (cj + ny * ck)];
+            const DensPair<R> d = *cur;
             s = s * d.rho;  // as the whole-ray score scales them
             is = is * d.inv;
         }
@@ -865,7 +870,9 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
     S(*mysig)[2] = sig + threadIdx.x;
     const Entry<R, S> *rec = static_cast<const Entry<R, S> *>(A.sorted);
     PutLds put{acc};
-    TileScorer<S, PutLds, DENS> sc{mysig, __ffs(bd) - 1, S(0), put, density_of<S>(A.mesh), nx, ny};
+    DensPair<S> dcur{S(0), S(0)}, dnext{S(0), S(0)};
+    TileScorer<S, PutLds, DENS> sc{mysig, __ffs(bd) - 1, S(0), put, &dcur};
+    const DensPair<S> *dens = density_of<S>(A.mesh);
     Walker<R, RECT> wk;
     constexpr int PER = 1;  // the records of one block-sized chunk are ordered together
     for (; key < n_keys; ++key) {
@@ -891,7 +898,10 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
                            : static_cast<uint8_t>(0);
         }
         __syncthreads();
-        const TileMaterials mats{s_mat};
+        const auto mats = [&] {
+            if constexpr (DENS) return TileMaterialsDens<S>{s_mat, dens, nx, ny, &dcur, &dnext};
+            else return TileMaterials{s_mat};
+        }();
         for (uint32_t c0 = lo; c0 < hi; c0 += bd) {
             const int m = static_cast<int>(hi - c0 < static_cast<uint32_t>(bd) ? hi - c0 : static_cast<uint32_t>(bd));
             int bucket[PER];
