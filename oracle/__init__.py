@@ -303,7 +303,8 @@ def next_event(mesh, xs, px, py, pz, E, w, det, precision: str = "f64") -> np.nd
     reaching det without a collision, w e^{-tau} / (4 pi r^2), with
     r = |det - p| and tau the optical depth of the segment from p to det: the
     sum over the voxels the ray crosses of Sigma_m(E) times the length of the
-    piece that lies between p and det (vacuum outside the mesh).  r = 0 scores
+    piece that lies between p and det (vacuum outside the mesh), a voxel's
+    Sigma scaled by its density factor when the mesh has them.  r = 0 scores
     0.  The direction is (det - p) / r in the traversal precision; the pieces
     come from this oracle's own traversal; tau and the score are summed in FP64.
     """
@@ -312,6 +313,7 @@ def next_event(mesh, xs, px, py, pz, E, w, det, precision: str = "f64") -> np.nd
     D = np.asarray(det, dt)
     sig = sigma_all(xs, np.asarray(E, np.float64))
     mat = np.asarray(mesh.mat)
+    rho = _density(mesh)
     out = np.zeros(px.size)
     for i in range(px.size):
         d = np.array([D[0] - px[i], D[1] - py[i], D[2] - pz[i]], dt)
@@ -326,7 +328,8 @@ def next_event(mesh, xs, px, py, pz, E, w, det, precision: str = "f64") -> np.nd
             if a >= float(r):
                 break
             b = a + float(l)
-            tau += sig[i, mat[v]] * (min(b, float(r)) - a)
+            sv = sig[i, mat[v]] if rho is None else rho[v] * sig[i, mat[v]]
+            tau += sv * (min(b, float(r)) - a)
             a = b
         rr = [float(D[k]) - float(p) for k, p in enumerate((px[i], py[i], pz[i]))]
         out[i] = float(w[i]) * np.exp(-tau) / (4.0 * np.pi * (rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2]))

@@ -112,3 +112,33 @@ def test_event_at_the_detector_scores_zero(oracle_lib):
     xs = xs_const(0.5)
     p = np.array([1.5, 1.5, 1.5])
     assert score(oracle_lib, mesh, xs, p, p) == 0.0
+
+
+def test_constant_density_closed_form(oracle_lib):
+    """A density factor c everywhere: e^{-c Sigma r} / (4 pi r^2), on a uniform and a rectilinear mesh."""
+    sig, c = 0.45, 1.8
+    n = (7, 6, 5)
+    nv = 7 * 6 * 5
+    uni = box(n, h=1.2)
+    uni = W.Mesh(uni.lo, uni.h, uni.n, uni.mat, np.full(nv, c))
+    rect = W.rect_mesh(12, n, h_min=0.6, h_max=1.9)
+    rect = W.RectMesh(rect.planes, np.zeros(nv, np.uint8), np.full(nv, c))
+    xs = xs_const(sig)
+    rng = np.random.default_rng(13)
+    for mesh, hi in ((uni, uni.lo + uni.n * uni.h), (rect, rect.hi)):
+        for _ in range(30):
+            p = rng.uniform(mesh.lo, hi)
+            d = rng.uniform(mesh.lo, hi)
+            r = float(np.linalg.norm(d - p))
+            exact = math.exp(-c * sig * r) / (4 * math.pi * r * r)
+            assert abs(score(oracle_lib, mesh, xs, p, d) - exact) <= 1e-13 * exact
+
+
+def test_density_regions_by_hand(oracle_lib):
+    rho = np.array([0.0] * 3 + [0.5] * 3 + [2.0] * 4)  # a void, then two densities along x
+    mesh = W.Mesh(np.zeros(3), np.ones(3), np.array([10, 1, 1], np.int32), np.zeros(10, np.uint8), rho)
+    xs = xs_const(0.8)
+    p, d = np.array([1.5, 0.5, 0.5]), np.array([8.25, 0.5, 0.5])
+    tau = 0.5 * 0.8 * 3.0 + 2.0 * 0.8 * 2.25
+    exact = math.exp(-tau) / (4 * math.pi * (8.25 - 1.5) ** 2)
+    assert abs(score(oracle_lib, mesh, xs, p, d) - exact) <= 1e-13 * exact
