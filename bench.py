@@ -90,8 +90,8 @@ def parse():
                     help="also time the next-event (point-detector) estimator on the multimat mesh")
     ap.add_argument("--fom-histories", type=int, default=100000)
     ap.add_argument("--rect", type=int, default=1,
-                    help="also time the cast on a rectilinear mesh of the multimat box and on the multimat mesh with "
-                         "per-voxel density factors (tile-split and atomic paths)")
+                    help="also time the cast on a rectilinear mesh of the multimat box, on the multimat mesh with "
+                         "per-voxel density factors (tile-split and atomic paths) and with mixture materials")
     ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
     ap.add_argument("--precision-report", action="store_true",
@@ -294,6 +294,37 @@ def bench_density(vrc, ctx, wl, arrays, torch, stream, steps: int = 10) -> dict:
     finally:
         ctx.set_launch(**launch)
     return out
+
+
+def bench_mixtures(vrc, ctx, wl, arrays, torch, stream, steps: int = 10) -> dict:
+    """Materials as mixtures: the multimat mesh and rays with its three materials made mixtures of
+    five components (the three multimat tables and two tables on a 15000-point grid of their own:
+    the union energy grid grows to about 35000 points), timed with the default accumulation
+    beside the plain tables."""
+    import workloads as W
+
+    xs = wl.xs
+    K2 = 15000
+    E2 = W.gen.log_energy_grid(K2)
+    tabs = [xs.table(m) for m in range(3)]
+    tabs += [(E2, W.synthetic_sigma_table(7001, K2, 0.2, 0.2, 0.05, 50.0)),
+             (E2, W.synthetic_sigma_table(7002, K2, 0.05, 0.4, 0.05, 50.0))]
+    comps = W.gen.make_xs(tabs)
+    mix = W.Mixtures(np.array([0, 2, 4, 7], np.int64), np.array([0, 3, 1, 4, 2, 3, 4], np.int32),
+                     np.array([0.7, 0.3, 1.0, 0.2, 0.5, 0.5, 0.1]))
+    prec = "p32_t64"
+    t_p = ctx.create_tally(0, prec)
+    _, tot_p, _ = time_casts(vrc, ctx, t_p, arrays, steps, 2, stream, torch)
+    ctx.destroy_tally(t_p)
+    try:
+        ctx.set_xs_mixtures(comps, mix)
+        t_m = ctx.create_tally(0, prec)
+        _, tot_m, _ = time_casts(vrc, ctx, t_m, arrays, steps, 2, stream, torch)
+        ctx.destroy_tally(t_m)
+    finally:
+        ctx.set_xs(xs)
+    return {"workload": "multimat mesh and 1e6 rays; 3 materials as mixtures of 5 components on two energy grids",
+            "precision": prec, "ms_per_step": tot_m / steps, "plain_tables_ms_per_step": tot_p / steps}
 
 
 def cpu_baseline(wl, target_s):
@@ -693,6 +724,16 @@ def main():
         except Exception as exc:  # the headline line must still be printed
             log(f"bench: density measurement failed: {exc!r}")
             density_form = {"error": repr(exc)}
+    mixture_form = None
+    if args.rect:
+        try:
+            mixture_form = bench_mixtures(vrc, ctx, wl, arrays, torch, stream)
+            mixture_form["segments_per_s"] = S / (mixture_form["ms_per_step"] / 1e3)
+            log(f"bench: mixtures {mixture_form['segments_per_s']:.3e} segments/s "
+                f"({mixture_form['ms_per_step']:.3f} ms; plain tables {mixture_form['plain_tables_ms_per_step']:.3f} ms)")
+        except Exception as exc:  # the headline line must still be printed
+            log(f"bench: mixture measurement failed: {exc!r}")
+            mixture_form = {"error": repr(exc)}
     fom_form = None
     if args.fom:
         try:
@@ -748,6 +789,7 @@ def main():
         "next_event_form": next_event,
         "rect_form": rect_form,
         "density_form": density_form,
+        "mixture_form": mixture_form,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)

@@ -154,10 +154,10 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
  * The traversal is the same 3D DDA with the next plane read from the table
  * instead of lo + k h.  Rectilinear meshes are cast by vrc_cast_rays (every
  * accumulate setting, the tile-split accumulation included: its tile walks
- * read the tables too), vrc_trace_rays and vrc_count_segments; the batched,
- * serving, walker and next-event calls return VRC_ERR_INVALID on them.  Tallies in an FP32 form are refused
- * (VRC_ERR_INVALID at cast time) when two planes of an axis round to the
- * same float.  Errors: VRC_ERR_INVALID (bad n or planes), VRC_ERR_STATE (a
+ * read the tables too), vrc_trace_rays, vrc_count_segments and
+ * vrc_next_event; the batched, serving and walker calls return
+ * VRC_ERR_INVALID on them.  FP32 forms are refused (VRC_ERR_INVALID at cast
+ * time) when two planes of an axis round to the same float.  Errors: VRC_ERR_INVALID (bad n or planes), VRC_ERR_STATE (a
  * tally uses the mesh), VRC_ERR_NOMEM.                                     */
 vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], const double *x_planes,
                              const double *y_planes, const double *z_planes, const uint8_t *mat);
@@ -169,10 +169,10 @@ vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], cons
  * (rho, 1/rho) in FP64 and FP32; the score divides by the voxel's Sigma as
  * (1/Sigma_m) * (1/rho).  rho == NULL removes the factors.  Setting or
  * replacing the mesh removes them too.  Such a mesh is cast by vrc_cast_rays
- * (every accumulate setting), vrc_trace_rays and vrc_count_segments; the
- * batched, serving, walker and next-event calls return VRC_ERR_INVALID on
- * it.  Errors: VRC_ERR_INVALID (no such mesh, a
- * bad factor), VRC_ERR_STATE (a tally uses the mesh), VRC_ERR_NOMEM.        */
+ * (every accumulate setting), vrc_trace_rays, vrc_count_segments and
+ * vrc_next_event; the batched, serving and walker calls return
+ * VRC_ERR_INVALID on it.  Errors: VRC_ERR_INVALID (no such mesh, a bad
+ * factor), VRC_ERR_STATE (a tally uses the mesh), VRC_ERR_NOMEM.           */
 vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho);
 
 /* Total macroscopic cross sections Sigma_t(E) of n_mat materials (1..64).
@@ -448,11 +448,12 @@ vrc_status vrc_walkers_take(vrc_ctx *ctx, double *ox, double *oy, double *oz, do
  * scores[i] = w_i e^{-tau_i} / (4 pi r_i^2) to the caller's device array of
  * n doubles: r_i = |detector - p_i|, tau_i the optical depth of the segment
  * from p_i to the detector through mesh `mesh_id` with the context's cross
- * sections Sigma_m(e_i) (vacuum outside the mesh); the score of an isotropic
+ * sections Sigma_m(e_i) (times the voxel's density factor if the mesh has
+ * them; the mesh may be rectilinear; vacuum outside the mesh); the score of an isotropic
  * event for the density of reaching the detector without a collision.  An
  * event at the detector (r_i = 0) scores 0.  The walk runs in FP64 for
  * VRC_P64, else in FP32; tau and the score are summed in FP64.  From 65536
- * events on, the events are first ordered by estimated path length (so the
+ * events on a uniform mesh without factors, the events are first ordered by estimated path length (so the
  * lanes of a wavefront walk about equally far; the scores are the same bit
  * for bit), in scratch device memory shared with the tile-split
  * accumulation: grown on demand (the first call of a larger n allocates and

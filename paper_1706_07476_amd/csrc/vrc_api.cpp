@@ -624,15 +624,17 @@ vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision
     if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
         return set_error(VRC_ERR_INVALID, "no such mesh");
     const MeshHost &mesh = ctx->meshes[mesh_id];
-    if (mesh.rect || mesh.dens)
-        return set_error(VRC_ERR_INVALID, "the next-event estimator takes uniform meshes without density factors only");
     if (!ctx->xs.set) return set_error(VRC_ERR_STATE, "no cross-section tables set");
     if (mesh.max_mat >= ctx->xs.n_mat) return set_error(VRC_ERR_STATE, "mesh has a material id >= n_mat");
     if (precision != VRC_P64 && !ctx->xs.f32_ok)
         return set_error(VRC_ERR_INVALID, "energy grid is not strictly increasing once rounded to FP32");
+    if (mesh.rect && precision != VRC_P64 && !mesh.rect_f32_ok)
+        return set_error(VRC_ERR_INVALID, "mesh planes are not strictly increasing once rounded to FP32");
     (void)hipSetDevice(ctx->device);
     const hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const bool ordered = n >= kNextEventOrderMin && next_event_ordered_eligible(*ctx, precision);
+    // the ordered path (events sorted by distance first) is for plain uniform meshes
+    const bool ordered = n >= kNextEventOrderMin && !mesh.rect && !mesh.dens &&
+                         next_event_ordered_eligible(*ctx, precision);
     hipError_t err = ordered ? launch_next_event_ordered(*ctx, mesh, precision, n, fp64 != 0, px, py, pz, e, w,
                                                          detector, scores, s)
                              : launch_next_event(*ctx, mesh, precision, n, fp64 != 0, px, py, pz, e, w, detector,

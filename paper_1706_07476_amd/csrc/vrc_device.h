@@ -703,21 +703,24 @@ __device__ __forceinline__ void cast_one(const MeshP<R> &M, const XsP<R> &X, con
 // the detector point.  The walk is the cast's, with its exit moved to the
 // detector; instead of scoring voxels it sums the optical depth (in FP64) of
 // the pieces between the event and the detector.
-template <typename R>
+template <typename R, bool DENS = false>
 struct TauSink {
     const R (*sig)[2];
     int stride;
     double tau;
-    __device__ __forceinline__ void operator()(int32_t, int m, R len, int, int, int, R)
+    const DensPair<R> *dens;  // DENS: per-voxel factors on Sigma
+    __device__ __forceinline__ void operator()(int32_t vox, int m, R len, int, int, int, R)
     {
-        tau += static_cast<double>(sig[m * stride][0] * len);
+        R s = sig[m * stride][0];
+        if constexpr (DENS) s = s * dens[vox].rho;
+        tau += static_cast<double>(s * len);
     }
 };
 
 // w e^{-tau} / (4 pi r^2) of one event at q (input precision RT) seen from
 // the detector D: the walk in R, tau and the score in FP64 (r^2 from the
 // event's and the detector's coordinates in FP64); r = 0 scores 0.
-template <typename R, typename RT>
+template <typename R, typename RT, bool RECT = false, bool DENS = false>
 __device__ __forceinline__ double next_event_score(const MeshP<R> &M, const XsP<R> &X, const int32_t *hash,
                                                    R (*mysig)[2], int bd, RT qx, RT qy, RT qz, RT qe, RT qw, R Dx,
                                                    R Dy, R Dz, double dx, double dy, double dz)
@@ -727,8 +730,8 @@ __device__ __forceinline__ double next_event_score(const MeshP<R> &M, const XsP<
     const R d = sqrt((ax * ax + ay * ay) + az * az);
     if (!(d > R(0))) return 0.0;
     xs_lookup(X, hash, static_cast<R>(qe), mysig, bd);
-    TauSink<R> ts{mysig, bd, 0.0};
-    Walker<R> wk;
+    TauSink<R, DENS> ts{mysig, bd, 0.0, density_of<R>(M)};
+    Walker<R, RECT> wk;
     if (wk.start(M, ox, oy, oz, ax / d, ay / d, az / d)) {
         if (d < wk.t_exit) wk.t_exit = d;
         const MeshMaterials mats{M.mat};

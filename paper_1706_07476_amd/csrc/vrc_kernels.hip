@@ -132,7 +132,7 @@ struct EventsP {
 
 // Next-event (point-detector) estimator, Sec. 6.3, events in input order:
 // scores[i] = w e^{-tau} / (4 pi r^2) (next_event_score).
-template <typename R, typename RT>
+template <typename R, typename RT, bool RECT, bool DENS>
 __global__ void __launch_bounds__(256) next_event_kernel(MeshP<R> M, XsP<R> X, int hash_in_lds, EventsP ev,
                                                          double dx, double dy, double dz, double *scores)
 {
@@ -146,8 +146,9 @@ __global__ void __launch_bounds__(256) next_event_kernel(MeshP<R> M, XsP<R> X, i
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * bd + threadIdx.x; i < ev.n; i += stride) {
         const RT qx = static_cast<const RT *>(ev.px)[i], qy = static_cast<const RT *>(ev.py)[i],
                  qz = static_cast<const RT *>(ev.pz)[i];
-        scores[i] = next_event_score<R, RT>(M, X, hash, mysig, bd, qx, qy, qz, static_cast<const RT *>(ev.e)[i],
-                                            static_cast<const RT *>(ev.w)[i], Dx, Dy, Dz, dx, dy, dz);
+        scores[i] = next_event_score<R, RT, RECT, DENS>(M, X, hash, mysig, bd, qx, qy, qz,
+                                                        static_cast<const RT *>(ev.e)[i],
+                                                        static_cast<const RT *>(ev.w)[i], Dx, Dy, Dz, dx, dy, dz);
     }
 }
 
@@ -470,7 +471,8 @@ hipError_t launch_tally_from_f64(const TallyHost &t, const double *in, hipStream
 }
 
 
-hipError_t launch_next_event(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, int64_t n, bool fp64,
+template <bool RECT, bool DENS>
+hipError_t launch_next_event_kind(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, int64_t n, bool fp64,
                              const void *px, const void *py, const void *pz, const void *e, const void *w,
                              const double det[3], double *scores, hipStream_t s)
 {
@@ -488,22 +490,33 @@ hipError_t launch_next_event(const vrc_ctx &ctx, const MeshHost &m, vrc_precisio
         const MeshP<double> M = mesh_args<double>(m);
         const XsP<double> X = xs_args<double>(ctx.xs);
         if (fp64)
-            hipLaunchKernelGGL((next_event_kernel<double, double>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
+            hipLaunchKernelGGL((next_event_kernel<double, double, RECT, DENS>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
                                ev, det[0], det[1], det[2], scores);
         else
-            hipLaunchKernelGGL((next_event_kernel<double, float>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
+            hipLaunchKernelGGL((next_event_kernel<double, float, RECT, DENS>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
                                ev, det[0], det[1], det[2], scores);
     } else {
         const MeshP<float> M = mesh_args<float>(m);
         const XsP<float> X = xs_args<float>(ctx.xs);
         if (fp64)
-            hipLaunchKernelGGL((next_event_kernel<float, double>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
+            hipLaunchKernelGGL((next_event_kernel<float, double, RECT, DENS>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
                                ev, det[0], det[1], det[2], scores);
         else
-            hipLaunchKernelGGL((next_event_kernel<float, float>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
+            hipLaunchKernelGGL((next_event_kernel<float, float, RECT, DENS>), dim3(grid), dim3(block), lds, s, M, X, hash ? 1 : 0,
                                ev, det[0], det[1], det[2], scores);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_next_event(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, int64_t n, bool fp64,
+                             const void *px, const void *py, const void *pz, const void *e, const void *w,
+                             const double det[3], double *scores, hipStream_t s)
+{
+    if (m.dens)
+        return m.rect ? launch_next_event_kind<true, true>(ctx, m, prec, n, fp64, px, py, pz, e, w, det, scores, s)
+                      : launch_next_event_kind<false, true>(ctx, m, prec, n, fp64, px, py, pz, e, w, det, scores, s);
+    return m.rect ? launch_next_event_kind<true, false>(ctx, m, prec, n, fp64, px, py, pz, e, w, det, scores, s)
+                  : launch_next_event_kind<false, false>(ctx, m, prec, n, fp64, px, py, pz, e, w, det, scores, s);
 }
 
 }  // namespace vrc

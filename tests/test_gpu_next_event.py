@@ -178,3 +178,54 @@ def test_ordered_path_equals_input_order_path(ctx, dtype, prec):
         rel = np.abs(a[idx][pos] - ref[pos]) / ref[pos]
         say(f"  sample of {idx.size}: max rel vs oracle {rel.max():.3e}")
         assert rel.max() <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["rect", "density", "rect+density"])
+def test_rectilinear_and_density_meshes(ctx, kind):
+    """The walk reads the plane tables on a rectilinear mesh and scales Sigma by the voxel's factor:
+    FP64 within 1e-12 per event; the FP32 walk against the oracle's FP32 traversal of the same
+    rounded inputs within the bound of the FP32 test above."""
+    base = W.rect_mesh(820, (28, 25, 30), lo=(-3.0, 1.0, 0.5), h_min=0.2, h_max=1.1) if "rect" in kind \
+        else W.slab_mesh(820, 28, 0.5, slab=4)
+    rho = W.density_field(821, base.n_voxels, 0.3, 2.5, frac_zero=0.05) if "density" in kind else None
+    mesh = W.RectMesh(base.planes, base.mat, rho) if "rect" in kind else W.Mesh(base.lo, base.h, base.n, base.mat, rho)
+    xs = W.gen.three_material_xs(822, 2000)
+    hi = mesh.hi if "rect" in kind else mesh.lo + mesh.n * mesh.h
+    rng = np.random.default_rng(823)
+    n = 3000
+    p = rng.uniform(mesh.lo - 2.0, hi + 2.0, (n, 3))
+    e = W.log_uniform_energies(rng, n)
+    w = rng.lognormal(0.0, 0.5, n)
+    det = tuple(float(v) for v in (0.5 * (mesh.lo + hi) + np.array([0.137, -0.211, 0.173])))
+    say(f"case: next-event on a {kind} mesh, {n} events")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    got = gpu_scores(ctx, "p64", p, e, w, det, "f64")
+    ref = oracle.next_event(mesh, xs, p[:, 0], p[:, 1], p[:, 2], e, w, det)
+    pos = ref > 1e-300
+    rel = np.abs(got[pos] - ref[pos]) / ref[pos]
+    say(f"  FP64: {pos.sum()} positive scores, max rel {rel.max():.3e}")
+    assert np.all(got[~pos] <= 1e-300)
+    assert rel.max() <= 1e-12
+    # FP32 walk (p32_t64) on the FP32-rounded inputs
+    det32 = tuple(float(np.float32(v)) for v in det)
+    got32 = gpu_scores(ctx, "p32_t64", p, e, w, det32, "f32")
+    f = lambda a: a.astype(np.float32)
+    if "rect" in kind:
+        m32 = W.RectMesh([np.asarray(q, np.float32).astype(np.float64) for q in mesh.planes], mesh.mat,
+                         None if rho is None else rho.astype(np.float32).astype(np.float64))
+    else:
+        m32 = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
+                     mesh.n, mesh.mat, None if rho is None else rho.astype(np.float32).astype(np.float64))
+    x32 = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
+                     xs.sigma.astype(np.float32).astype(np.float64))
+    ref32 = oracle.next_event(m32, x32, f(p[:, 0]), f(p[:, 1]), f(p[:, 2]), f(e).astype(np.float64),
+                              f(w).astype(np.float64), det32, precision="f32")
+    pos = ref32 > 1e-300
+    q = np.stack([f(p[:, k]).astype(np.float64) for k in range(3)], axis=1)
+    r2 = np.sum((np.asarray(det32)[None, :] - q) ** 2, axis=1)
+    tau = -np.log(ref32[pos] * 4 * math.pi * r2[pos] / f(w).astype(np.float64)[pos])
+    dtau = np.abs(np.log(got32[pos] / ref32[pos]))
+    say(f"  FP32: max |dtau|/(1+tau) {np.max(dtau / (1 + tau)):.3e}")
+    # each term (rho Sigma) l is rounded twice in FP32 here (the factor's product, then the length's)
+    assert np.all(dtau <= 2e-6 * (1.0 + tau))

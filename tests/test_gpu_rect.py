@@ -253,10 +253,6 @@ def test_rect_errors_and_refusals(vrc, ctx):
         ctx.walkers_run(t64, [0.1, 0.5, 1.0], mesh.lo + 0.5 * (mesh.hi - mesh.lo), direct=1, max_histories=10,
                         duration_s=0.0)
     assert e.value.status == vrc.VRC_ERR_INVALID
-    one = torch.zeros(1, dtype=torch.float64, device="cuda:0")
-    with pytest.raises(vrc.VrcError) as e:
-        ctx.next_event(0, "p64", [one] * 3, one, one, (0.0, 0.0, 0.0), one)
-    assert e.value.status == vrc.VRC_ERR_INVALID
     # a mesh in use cannot be replaced
     with pytest.raises(vrc.VrcError) as e:
         ctx.set_mesh(0, mesh)
