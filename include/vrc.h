@@ -154,9 +154,9 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
  * The traversal is the same 3D DDA with the next plane read from the table
  * instead of lo + k h.  Rectilinear meshes are cast by vrc_cast_rays (every
  * accumulate setting, the tile-split accumulation included: its tile walks
- * read the tables too), vrc_trace_rays, vrc_count_segments and
- * vrc_next_event; the batched, serving and walker calls return
- * VRC_ERR_INVALID on them.  FP32 forms are refused (VRC_ERR_INVALID at cast
+ * read the tables too), vrc_trace_rays, vrc_count_segments,
+ * vrc_next_event and vrc_cast_batches with split = 1; the serving and
+ * walker calls return VRC_ERR_INVALID on them.  FP32 forms are refused (VRC_ERR_INVALID at cast
  * time) when two planes of an axis round to the same float.  Errors: VRC_ERR_INVALID (bad n or planes), VRC_ERR_STATE (a
  * tally uses the mesh), VRC_ERR_NOMEM.                                     */
 vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], const double *x_planes,
@@ -169,9 +169,9 @@ vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], cons
  * (rho, 1/rho) in FP64 and FP32; the score divides by the voxel's Sigma as
  * (1/Sigma_m) * (1/rho).  rho == NULL removes the factors.  Setting or
  * replacing the mesh removes them too.  Such a mesh is cast by vrc_cast_rays
- * (every accumulate setting), vrc_trace_rays, vrc_count_segments and
- * vrc_next_event; the batched, serving and walker calls return
- * VRC_ERR_INVALID on it.  Errors: VRC_ERR_INVALID (no such mesh, a bad
+ * (every accumulate setting), vrc_trace_rays, vrc_count_segments,
+ * vrc_next_event and vrc_cast_batches with split = 1; the serving and
+ * walker calls return VRC_ERR_INVALID on it.  Errors: VRC_ERR_INVALID (no such mesh, a bad
  * factor), VRC_ERR_STATE (a tally uses the mesh), VRC_ERR_NOMEM.           */
 vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho);
 
@@ -258,7 +258,10 @@ typedef struct {
  * tile-split accumulation of vrc_launch (rays ordered by length, split at
  * tile entries, scored per tile in LDS), run once per tally over all of that
  * tally's batches, when every tally of the call allows it (at most 4096
- * (tile, bin) pairs), else the persistent kernel.  With split,
+ * (tile, bin) pairs), else the persistent kernel.  Tallies on rectilinear
+ * meshes or meshes with density factors are cast with split = 1 only (the
+ * persistent kernel walks plain uniform meshes): otherwise VRC_ERR_INVALID,
+ * and the autotuner tries only the split setting for them.  With split,
  * a call waits on the host for the previous tile-split work of the context
  * before it rewrites its batch table.                                      */
 typedef struct {

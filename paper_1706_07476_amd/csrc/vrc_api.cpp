@@ -1026,6 +1026,7 @@ vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batche
     std::lock_guard<std::mutex> lk(ctx->mu);
     const BatchedShape shape = ctx->batched;
     int prec = -1, fp64 = -1;
+    bool kinds = false;  // a tally on a rectilinear mesh or with density factors: tile-split only
     std::vector<BatchDescDev> desc;
     desc.reserve(static_cast<size_t>(n_batches));
     int64_t items = 0;
@@ -1040,7 +1041,7 @@ vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batche
         if (prec != static_cast<int>(t->prec)) return set_error(VRC_ERR_INVALID, "tallies of one call must share a precision form");
         if (fp64 != b.fp64) return set_error(VRC_ERR_INVALID, "batches of one call must share the ray type");
         if (vrc_status st = check_cast_ready(ctx, t)) return st;
-        if (vrc_status st = check_uniform_mesh(ctx, t, "the batched cast")) return st;
+        kinds = kinds || ctx->meshes[t->mesh_id].rect || ctx->meshes[t->mesh_id].dens;
         if (b.n == 0) continue;
         if (!b.ox || !b.oy || !b.oz || !b.ux || !b.uy || !b.uz || !b.e || !b.w)
             return set_error(VRC_ERR_INVALID, "null ray array in a batch");
@@ -1080,6 +1081,10 @@ vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batche
         if (ok)
             return run_split_batches(ctx, ids, groups, batches, fp64 != 0, static_cast<hipStream_t>(hip_stream));
     }
+    // the persistent kernel walks uniform meshes without density factors only
+    if (kinds)
+        return set_error(VRC_ERR_INVALID, "a tally on a rectilinear mesh or with density factors needs the "
+                                          "tile-split batched cast (split = 1, at most 4096 (tile, bin) pairs)");
     BatchedSlot &bs = ctx->bslot[ctx->bslot_next];
     ctx->bslot_next ^= 1;
     return run_batched(ctx, bs, shape, static_cast<vrc_precision>(prec), fp64 != 0, desc, items,

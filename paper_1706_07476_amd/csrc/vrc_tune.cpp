@@ -122,6 +122,7 @@ vrc_status vrc_autotune_batched(vrc_ctx *ctx, int n_batches, const vrc_batch *ba
     if (repeats < 1) return set_error(VRC_ERR_INVALID, "repeats must be >= 1");
     std::set<int> tally_ids, meshes;
     int prec = -1, fp64 = -1;
+    bool kinds = false;  // rectilinear meshes or density factors: only the tile-split setting runs them
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         for (int i = 0; i < n_batches; ++i) {
@@ -130,6 +131,8 @@ vrc_status vrc_autotune_batched(vrc_ctx *ctx, int n_batches, const vrc_batch *ba
                 return set_error(VRC_ERR_INVALID, "batch names no tally");
             tally_ids.insert(id);
             meshes.insert(ctx->tallies[id]->mesh_id);
+            const MeshHost &mh = ctx->meshes[ctx->tallies[id]->mesh_id];
+            kinds = kinds || mh.rect || mh.dens;
             prec = static_cast<int>(ctx->tallies[id]->prec);
             fp64 = batches[i].fp64;
         }
@@ -170,11 +173,12 @@ vrc_status vrc_autotune_batched(vrc_ctx *ctx, int n_batches, const vrc_batch *ba
     vrc_batched_launch best_l = saved;
     // persistent-kernel shapes, then the tile-split accumulation (rays presorted by length)
     std::vector<vrc_batched_launch> cands;
-    for (int block : {128, 256, 512})
-        for (int bpc : {4, 8})
-            for (int cm : {1, 4, 16})
-                for (int agg = 0; agg <= 1; ++agg)
-                    cands.push_back(vrc_batched_launch{block, bpc, block * cm, 1, agg, 1, 0});
+    if (!kinds)
+        for (int block : {128, 256, 512})
+            for (int bpc : {4, 8})
+                for (int cm : {1, 4, 16})
+                    for (int agg = 0; agg <= 1; ++agg)
+                        cands.push_back(vrc_batched_launch{block, bpc, block * cm, 1, agg, 1, 0});
     cands.push_back(vrc_batched_launch{256, 8, 1024, 1, 0, 1, 1});
     for (const vrc_batched_launch &l : cands) {
         if (result != VRC_OK) break;

@@ -244,3 +244,36 @@ def test_density_and_mixture_errors(vrc, ctx):
             ctx.set_xs_mixtures(comps, W.Mixtures(np.array(offs, np.int64), np.array(comp, np.int32),
                                                   np.array(frac)))
         assert e.value.status == vrc.VRC_ERR_INVALID
+
+
+def test_batched_tile_split_on_rectilinear_and_density_meshes(vrc, ctx):
+    """The batched cast with split = 1 runs one tile-split pipeline per tally, which walks every mesh
+    kind: batches on a uniform, a rectilinear and a rectilinear mesh with factors, against the oracle
+    (FP64, 1e-12); with split = 0 the call is refused, and the autotuner tries only split = 1."""
+    uni = W.slab_mesh(975, 20, 0.5, slab=4)
+    rect = W.rect_mesh(976, (21, 18, 19), h_min=0.3, h_max=0.8)
+    rect_d = W.RectMesh(rect.planes, rect.mat, W.density_field(977, rect.n_voxels, 0.5, 2.0, frac_zero=0.05))
+    xs = W.gen.three_material_xs(978, 1000)
+    meshes = [uni, rect, rect_d]
+    say("case: batched tile-split on uniform, rect and rect+density meshes, 9 batches")
+    ctx.set_xs(xs)
+    for i, m in enumerate(meshes):
+        ctx.set_mesh(i, m)
+    tids = [ctx.create_tally(i, "p64") for i in range(3)]
+    rays = [[W.rays_in_box(980 + 3 * i + j, meshes[i], 5000 + 1700 * j) for j in range(3)] for i in range(3)]
+    items = [(tids[i], dev_arrays(r, "f64")) for i in range(3) for r in rays[i]]
+    ctx.set_batched_launch(split=0)
+    with pytest.raises(vrc.VrcError) as e:
+        ctx.cast_batches(items)
+    assert e.value.status == vrc.VRC_ERR_INVALID
+    ctx.set_batched_launch(split=1)
+    ctx.cast_batches(items)
+    for i in range(3):
+        allr = W.Rays(*[np.concatenate([getattr(r, f) for r in rays[i]])
+                        for f in ("ox", "oy", "oz", "ux", "uy", "uz", "e", "w")])
+        res = oracle.cast(meshes[i], xs, allr, n_threads=oracle_threads())
+        g, _, n = rel_report(ctx.read(tids[i]), res, gate="all")
+        say(f"  mesh {i}: max rel over {n} voxels {g:.3e}")
+        assert g <= TOL_P64
+    best, _ = ctx.autotune_batched(items, repeats=1)
+    assert best["split"] == 1

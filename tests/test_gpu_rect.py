@@ -237,7 +237,8 @@ def test_rect_errors_and_refusals(vrc, ctx):
     tid = ctx.create_tally(0, "p32_t64")
     rays = W.rays_in_box(917, mesh, 300)
     arrays = dev_arrays(rays, "f32")
-    # the batched cast, the serving form and the walkers take uniform meshes only
+    # the persistent batched kernel (split = 0, the default), the serving form and the walkers take
+    # uniform meshes only
     with pytest.raises(vrc.VrcError) as e:
         ctx.cast_batches([(tid, arrays)])
     assert e.value.status == vrc.VRC_ERR_INVALID
