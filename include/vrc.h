@@ -154,11 +154,12 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
  * The traversal is the same 3D DDA with the next plane read from the table
  * instead of lo + k h.  Rectilinear meshes are cast by vrc_cast_rays (every
  * accumulate setting, the tile-split accumulation included: its tile walks
- * read the tables too), vrc_trace_rays, vrc_count_segments,
- * vrc_next_event and vrc_cast_batches with split = 1; the serving and
- * walker calls return VRC_ERR_INVALID on them.  FP32 forms are refused (VRC_ERR_INVALID at cast
- * time) when two planes of an axis round to the same float.  Errors: VRC_ERR_INVALID (bad n or planes), VRC_ERR_STATE (a
- * tally uses the mesh), VRC_ERR_NOMEM.                                     */
+ * read the tables too), vrc_trace_rays, vrc_count_segments, vrc_next_event
+ * and vrc_cast_batches with split = 1; the serving and walker calls return
+ * VRC_ERR_INVALID on them.  FP32 forms are refused (VRC_ERR_INVALID at cast
+ * time) when two planes of an axis round to the same float.
+ * Errors: VRC_ERR_INVALID (bad n or planes), VRC_ERR_STATE (a tally uses
+ * the mesh), VRC_ERR_NOMEM.                                                */
 vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], const double *x_planes,
                              const double *y_planes, const double *z_planes, const uint8_t *mat);
 

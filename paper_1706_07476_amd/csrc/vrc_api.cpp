@@ -219,9 +219,9 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
     m.max_mat = max_mat;
     m.h_mat.assign(mat, mat + nvox);
     m.set = true;
-    // Device descriptors read by the batched kernels.  A rectilinear mesh is
-    // not cast there (refused before launch); its descriptor has n = 0, which
-    // any traversal treats as an empty mesh.
+    // Device descriptors read by the persistent batched kernel.  A
+    // rectilinear mesh is not cast there (refused before launch); its
+    // descriptor has n = 0, which any traversal treats as an empty mesh.
     MeshP<float> m32;
     MeshP<double> m64;
     for (int a = 0; a < 3; ++a) {

@@ -31,7 +31,8 @@ struct DensPair {
     R inv;
 };
 
-// Uniform Cartesian mesh in the traversal precision R.
+// Cartesian mesh in the traversal precision R: uniform (lo + k h per axis) or
+// rectilinear (plane tables), optionally with per-voxel density factors.
 template <typename R>
 struct MeshP {
     R lo[3];
