@@ -69,6 +69,10 @@ struct Geometry {
     int n[3];
     const uint8_t *mat;
     const double *sigma;
+    const double *planes[3] = {nullptr, nullptr, nullptr};  // rectilinear mesh: each axis' n + 1 planes
+    const double *rho = nullptr;                             // per-voxel density factors, or none
+    double plane(int a, int k) const { return planes[a] ? planes[a][k] : lo[a] + k * h[a]; }
+    double hi(int a) const { return plane(a, n[a]); }
 };
 
 // Fly from p along u for the optical distance tau_star; returns the distance
@@ -80,16 +84,22 @@ double fly(const Geometry &G, const double p[3], const double u[3], double tau_s
     int idx[3], step[3];
     double tn[3], dt[3];
     for (int a = 0; a < 3; ++a) {
-        int k = static_cast<int>(std::floor((p[a] - G.lo[a]) / G.h[a]));
+        int k;
+        if (G.planes[a]) {
+            const double *pl = G.planes[a];
+            k = static_cast<int>(std::upper_bound(pl, pl + G.n[a] + 1, p[a]) - pl) - 1;
+        } else {
+            k = static_cast<int>(std::floor((p[a] - G.lo[a]) / G.h[a]));
+        }
         k = std::min(std::max(k, 0), G.n[a] - 1);
         idx[a] = k;
         if (u[a] > 0) {
             step[a] = 1;
-            tn[a] = (G.lo[a] + (k + 1) * G.h[a] - p[a]) / u[a];
+            tn[a] = (G.plane(a, k + 1) - p[a]) / u[a];
             dt[a] = G.h[a] / u[a];
         } else if (u[a] < 0) {
             step[a] = -1;
-            tn[a] = (G.lo[a] + k * G.h[a] - p[a]) / u[a];
+            tn[a] = (G.plane(a, k) - p[a]) / u[a];
             dt[a] = -G.h[a] / u[a];
         } else {
             step[a] = 0;
@@ -104,7 +114,7 @@ double fly(const Geometry &G, const double p[3], const double u[3], double tau_s
         const int a = (tn[0] <= tn[1] && tn[0] <= tn[2]) ? 0 : (tn[1] <= tn[2] ? 1 : 2);
         const double seg = tn[a] - t;
         const int64_t v = idx[0] + static_cast<int64_t>(G.n[0]) * (idx[1] + static_cast<int64_t>(G.n[1]) * idx[2]);
-        const double sg = G.sigma[G.mat[v]];
+        const double sg = G.rho ? G.rho[v] * G.sigma[G.mat[v]] : G.sigma[G.mat[v]];
         if (sg > 0 && sg * seg >= left) {
             if (tl) tl[v] += left / sg;
             return t + left / sg;
@@ -114,7 +124,8 @@ double fly(const Geometry &G, const double p[3], const double u[3], double tau_s
         t = tn[a];
         idx[a] += step[a];
         if (idx[a] < 0 || idx[a] >= G.n[a]) return -1.0;
-        tn[a] += dt[a];
+        // uniform spacing: the next plane is dt further; a plane table gives it directly
+        tn[a] = G.planes[a] ? (G.planes[a][idx[a] + (step[a] > 0 ? 1 : 0)] - p[a]) / u[a] : tn[a] + dt[a];
     }
     return -1.0;
 }
@@ -243,17 +254,26 @@ vrc_status vrc_walkers_run(vrc_ctx *ctx, const vrc_walker_config *cfg, vrc_walke
         const int id = cfg->tally_id;
         if (id < 0 || id >= static_cast<int>(ctx->tallies.size()) || !ctx->tallies[id])
             return set_error(VRC_ERR_INVALID, "no such tally");
-        if (vrc_status st = check_uniform_mesh(ctx, ctx->tallies[id].get(), "the walkers")) return st;
         const MeshHost &m = ctx->meshes[ctx->tallies[id]->mesh_id];
+        // the serving loop takes plain uniform meshes only; direct casts and track-length runs take any
+        if (!cfg->direct && !cfg->tl_only)
+            if (vrc_status st = check_uniform_mesh(ctx, ctx->tallies[id].get(), "the serving form")) return st;
         if (cfg->n_sigma < m.max_mat + 1 || cfg->n_sigma > 64)
             return set_error(VRC_ERR_INVALID, "sigma must cover every material of the mesh");
+        // the tables and factors are host copies that stay put while a tally uses the mesh
+        size_t off = 0;
         for (int a = 0; a < 3; ++a) {
             G.lo[a] = m.lo[a];
             G.h[a] = m.h[a];
             G.n[a] = m.n[a];
-            if (!(cfg->source[a] >= m.lo[a] && cfg->source[a] < m.lo[a] + m.n[a] * m.h[a]))
+            if (m.rect) {
+                G.planes[a] = m.h_planes.data() + off;
+                off += static_cast<size_t>(m.n[a]) + 1;
+            }
+            if (!(cfg->source[a] >= G.plane(a, 0) && cfg->source[a] < G.hi(a)))
                 return set_error(VRC_ERR_INVALID, "the source must lie inside the mesh");
         }
+        if (m.dens) G.rho = m.h_rho.data();
         G.mat = m.h_mat.data();
         for (int k = 0; k < cfg->n_sigma; ++k)
             if (!(cfg->sigma[k] >= 0 && std::isfinite(cfg->sigma[k])))

@@ -214,17 +214,19 @@ def test_density_and_mixture_errors(vrc, ctx):
     with pytest.raises(vrc.VrcError) as e:
         ctx.cast_batches([(tid, arrays)])
     assert e.value.status == vrc.VRC_ERR_INVALID
+    t64 = ctx.create_tally(0, "p64")
     ctx.serve_start()
     try:
         with pytest.raises(vrc.VrcError) as e:
             ctx.serve_submit(tid, host_arrays(rays, "f32"))
         assert e.value.status == vrc.VRC_ERR_INVALID
+        with pytest.raises(vrc.VrcError) as e:  # walkers feeding the serving loop
+            ctx.walkers_run(t64, [0.1, 0.5, 1.0], base.lo + 4.0, max_histories=10, duration_s=0.0)
+        assert e.value.status == vrc.VRC_ERR_INVALID
     finally:
         ctx.serve_stop()
-    t64 = ctx.create_tally(0, "p64")
-    with pytest.raises(vrc.VrcError) as e:
-        ctx.walkers_run(t64, [0.1, 0.5, 1.0], base.lo + 4.0, direct=1, max_histories=10, duration_s=0.0)
-    assert e.value.status == vrc.VRC_ERR_INVALID
+    r = ctx.walkers_run(t64, [0.1, 0.5, 1.0], base.lo + 4.0, direct=1, max_histories=10, duration_s=0.0)
+    assert r["histories"] == 10
     with pytest.raises(vrc.VrcError) as e:
         vrc.vrc_set_mesh_density(ctx.handle, 0, None)  # in use
     assert e.value.status == vrc.VRC_ERR_STATE

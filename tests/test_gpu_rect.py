@@ -237,23 +237,26 @@ def test_rect_errors_and_refusals(vrc, ctx):
     tid = ctx.create_tally(0, "p32_t64")
     rays = W.rays_in_box(917, mesh, 300)
     arrays = dev_arrays(rays, "f32")
-    # the persistent batched kernel (split = 0, the default), the serving form and the walkers take
-    # uniform meshes only
+    # the persistent batched kernel (split = 0, the default) and the serving form take uniform meshes
+    # only
     with pytest.raises(vrc.VrcError) as e:
         ctx.cast_batches([(tid, arrays)])
     assert e.value.status == vrc.VRC_ERR_INVALID
+    t64 = ctx.create_tally(0, "p64")
+    src = mesh.lo + 0.5 * (mesh.hi - mesh.lo)
     ctx.serve_start()
     try:
         with pytest.raises(vrc.VrcError) as e:
             ctx.serve_submit(tid, host_arrays(rays, "f32"))
         assert e.value.status == vrc.VRC_ERR_INVALID
+        with pytest.raises(vrc.VrcError) as e:  # walkers feeding the serving loop
+            ctx.walkers_run(t64, [0.1, 0.5, 1.0], src, max_histories=10, duration_s=0.0)
+        assert e.value.status == vrc.VRC_ERR_INVALID
     finally:
         ctx.serve_stop()
-    t64 = ctx.create_tally(0, "p64")
-    with pytest.raises(vrc.VrcError) as e:
-        ctx.walkers_run(t64, [0.1, 0.5, 1.0], mesh.lo + 0.5 * (mesh.hi - mesh.lo), direct=1, max_histories=10,
-                        duration_s=0.0)
-    assert e.value.status == vrc.VRC_ERR_INVALID
+    # walkers with direct casts walk the plane tables
+    r = ctx.walkers_run(t64, [0.1, 0.5, 1.0], src, direct=1, max_histories=10, duration_s=0.0)
+    assert r["histories"] == 10
     # a mesh in use cannot be replaced
     with pytest.raises(vrc.VrcError) as e:
         ctx.set_mesh(0, mesh)
