@@ -289,3 +289,29 @@ def test_rect_errors_and_refusals(vrc, ctx):
     ru = W.rays_in_box(918, uni, 200)
     ctx.cast_batches([(tu, dev_arrays(ru, "f32"))])
     assert ctx.read(tu).sum() > 0
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (700, 1, 2), (1, 3, 450)])
+def test_degenerate_and_thin_rect_meshes(ctx, shape):
+    """One voxel, and long thin meshes (many tiles along one axis, one voxel across): traces bit-exact,
+    tallies on the atomic and the tile-split paths within 1e-12 of the oracle."""
+    mesh = W.rect_mesh(930 + sum(shape), shape, lo=(-1.0, 0.25, 2.0), h_min=0.05, h_max=0.4)
+    xs = W.gen.three_material_xs(931, 500)
+    rays = mixed_rays(932, mesh, 4000, frac_out=0.3)
+    say(f"case: rect mesh {shape}, {rays.n} rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    t = ctx.create_tally(0, "p64")
+    offs, vox, ln, _ = ctx.trace(t, dev_arrays(rays, "f64"))
+    o_offs, o_vox, o_len = oracle.trace_many(mesh, rays, precision="f64")
+    np.testing.assert_array_equal(offs, o_offs)
+    np.testing.assert_array_equal(vox, o_vox)
+    np.testing.assert_array_equal(ln, o_len)
+    res = oracle.cast(mesh, xs, rays, n_threads=oracle_threads())
+    for acc in (0, 2):
+        ctx.set_launch(accumulate=acc)
+        tid = ctx.create_tally(0, "p64")
+        ctx.cast(tid, dev_arrays(rays, "f64"))
+        g, _, n = rel_report(ctx.read(tid), res, gate="all")
+        say(f"  accumulate {acc}: max rel over {n} voxels {g:.3e}")
+        assert g <= TOL_P64
