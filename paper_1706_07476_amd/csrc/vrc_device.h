@@ -389,9 +389,12 @@ struct Walker {
         const R inv = ax ? ix : (ay ? iy : iz);
         R tnew;
         if constexpr (RECT) {
-            // the next plane's table entry (a plane inside the table when the walk goes on)
+            // the next plane's table entry (a plane inside the table when the walk goes on); the
+            // piece is scored while the load is in flight, then the state moves on
             const R *pa = ax ? M.pl[0] : (ay ? M.pl[1] : M.pl[2]);
-            tnew = (pa[adv ? ni + (s > 0 ? 1 : 0) : 0] - oa) * inv;
+            const R xp = pa[adv ? ni + (s > 0 ? 1 : 0) : 0];
+            if (l > R(0)) seg(vcur, mcur, l, cx, cy, cz, t0);
+            tnew = (xp - oa) * inv;
         } else {
             const R plo = ax ? lox : (ay ? loy : loz);
             const R h = ax ? hx : (ay ? hy : hz);
@@ -413,7 +416,9 @@ struct Walker {
         this->cur = cur;
         this->vox = vox;
         this->m = m;
-        if (l > R(0)) seg(vcur, mcur, l, cx, cy, cz, t0);
+        if constexpr (!RECT) {
+            if (l > R(0)) seg(vcur, mcur, l, cx, cy, cz, t0);
+        }
         return adv && --budget > 0;
     }
 };
