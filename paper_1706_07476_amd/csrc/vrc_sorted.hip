@@ -527,13 +527,17 @@ struct EmitEntries {
     Entry<R, S> *sorted;
     uint32_t cap;
     uint32_t *next;  // LDS, per key
-    __device__ __forceinline__ void emit(bool first, int ci, int cj, int ck, R t0)
+    // A record whose place is taken but whose stores wait for the next tile
+    // entry (or the end of the ray's walk), so that the walk never waits for
+    // the atomic's return.
+    bool pend;
+    uint32_t pend_pos, pend_code;
+    R pend_t0;
+    S pend_th, pend_tl;
+    __device__ __forceinline__ void store_pending()
     {
-        const int tl = (ci >> kTileBits) + g.ntx * ((cj >> kTileBits) + g.nty * (ck >> kTileBits));
-        const uint32_t key = static_cast<uint32_t>(key0 + tl);
-        const uint32_t pos = atomicAdd(next + key, 1u);
         // the counting pass sized every key's run; the guard only keeps stores in bounds
-        if (pos < cap) {
+        if (pend && pend_pos < cap) {
             Entry<R, S> r;
             r.ox = ox;
             r.oy = oy;
@@ -543,12 +547,25 @@ struct EmitEntries {
             r.uz = uz;
             r.e = e;
             r.w = w;
-            r.t0 = t0;
-            r.tau_hi = tau_hi;
-            r.tau_lo = tau_lo;
-            r.code = (first ? kFirst : 0u) | (key << kLocalBits) | local_index(ci, cj, ck);
-            sorted[pos] = r;
+            r.t0 = pend_t0;
+            r.tau_hi = pend_th;
+            r.tau_lo = pend_tl;
+            r.code = pend_code;
+            sorted[pend_pos] = r;
         }
+        pend = false;
+    }
+    __device__ __forceinline__ void emit(bool first, int ci, int cj, int ck, R t0)
+    {
+        store_pending();
+        const int tl = (ci >> kTileBits) + g.ntx * ((cj >> kTileBits) + g.nty * (ck >> kTileBits));
+        const uint32_t key = static_cast<uint32_t>(key0 + tl);
+        pend_pos = atomicAdd(next + key, 1u);
+        pend_code = (first ? kFirst : 0u) | (key << kLocalBits) | local_index(ci, cj, ck);
+        pend_t0 = t0;
+        pend_th = tau_hi;
+        pend_tl = tau_lo;
+        pend = true;
     }
     __device__ __forceinline__ void reset(R ox_, R oy_, R oz_, R ux_, R uy_, R uz_, R e_, R w_, int key0_)
     {
@@ -567,17 +584,18 @@ struct EmitEntries {
     }
     __device__ __forceinline__ void operator()(int32_t vox, int m, R len, int ci, int cj, int ck, R t0)
     {
+        // Sigma first: its LDS read is then not queued behind the atomic of a tile entry
+        const S l = static_cast<S>(len);
+        S sg = sig[m << shift][0];
+        if constexpr (DENS) sg = sg * cur->rho;  // the score's own product, so tau matches
+        const S x = sg * l;
         const uint32_t tg = tile_tag(ci >> kTileBits, cj >> kTileBits, ck >> kTileBits);
         if (tg != tile || !started) {
             const bool first = !started;
             started = true;
             tile = tg;
-            emit(first, ci, cj, ck, t0);
+            emit(first, ci, cj, ck, t0);  // the optical depth up to the entry, before this piece
         }
-        const S l = static_cast<S>(len);
-        S sg = sig[m << shift][0];
-        if constexpr (DENS) sg = sg * cur->rho;  // the score's own product, so tau matches
-        const S x = sg * l;
         const S t = tau_hi + x;
         const S bv = t - tau_hi;
         const S err = (tau_hi - (t - bv)) + (x - bv);
@@ -605,7 +623,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     DensPair<S> dcur{S(0), S(0)}, dnext{S(0), S(0)};
     EmitEntries<R, S, DENS> em{mysig, &dcur, __ffs(bd) - 1, S(0), S(0), 0u, false, R(0), R(0), R(0),
                                R(0), R(0), R(0), R(0), R(0), 0, A.g, static_cast<Entry<R, S> *>(A.sorted),
-                               static_cast<uint32_t>(A.cap), s_next};
+                               static_cast<uint32_t>(A.cap), s_next, false, 0u, 0u, R(0), S(0), S(0)};
     Walker<R, RECT> wk;
     const DensPair<S> *dens = density_of<S>(A.mesh);
     const auto mats = [&] {
@@ -626,6 +644,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
         if constexpr (DENS) dnext = dens[wk.vox];  // the first voxel's pair (start() reads its material itself)
         while (wk.step(A.mesh, em, mats)) {
         }
+        em.store_pending();  // the ray's last record
     }
 }
 
