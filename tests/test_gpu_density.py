@@ -279,3 +279,50 @@ def test_batched_tile_split_on_rectilinear_and_density_meshes(vrc, ctx):
         assert g <= TOL_P64
     best, _ = ctx.autotune_batched(items, repeats=1)
     assert best["split"] == 1
+
+
+@pytest.mark.parametrize("accumulate", [0, 2])
+def test_energy_bins_on_a_rectilinear_mesh_with_factors(ctx, accumulate):
+    """Energy bins (tile-split keys = bins x tiles) on rectilinear meshes with density factors, rays
+    below, on the edges of and above the bins: 8 bins in FP64 on a 37x33x35 mesh (every pair within
+    1e-12 of the oracle); 3 bins in the p32_t64 form on a well-sampled 18x17x17 mesh, cast from FP64
+    rays (rounded on load), against the oracle on the FP32-rounded inputs (1e-5 on gated pairs)."""
+    xs = W.gen.three_material_xs(992, 1000)
+    ctx.set_xs(xs)
+    ctx.set_launch(accumulate=accumulate)
+    base = W.rect_mesh(990, (37, 33, 35), h_min=0.2, h_max=0.7)
+    rho = W.density_field(991, base.n_voxels, 0.4, 2.0, frac_zero=0.03)
+    mesh = W.RectMesh(base.planes, base.mat, rho)
+    edges = W.log_bin_edges(8, 1e-9, 1.0)
+    rays = W.rays_in_box(993, mesh, 150_000)
+    rays.e[:7] = edges[-1]
+    rays.e[7:14] = edges[0]
+    rays.e[14:20] = 5.0  # above the top edge: not scored
+    say(f"case: 8-bin p64 tally on a rect mesh with factors, {rays.n} rays, accumulate {accumulate}")
+    ctx.set_mesh(0, mesh)
+    t64 = ctx.create_tally(0, "p64", edges)
+    ctx.cast(t64, dev_arrays(rays, "f64"))
+    res = oracle.cast(mesh, xs, rays, edges=edges, n_threads=oracle_threads())
+    assert res.rays_out_of_range > 1000
+    g, _, n = rel_report(ctx.read(t64).reshape(8, -1), res, gate="all")
+    say(f"  FP64: max rel over {n} (bin, voxel) pairs {g:.3e}")
+    assert g <= TOL_P64
+    small = W.rect_mesh(994, (18, 17, 17), h_min=0.3, h_max=0.8)
+    rho2 = W.density_field(995, small.n_voxels, 0.4, 2.0)
+    mesh2 = W.RectMesh(small.planes, small.mat, rho2)
+    edges3 = W.log_bin_edges(3, 1e-9, 1.0)
+    rays2 = W.rays_in_box(997, mesh2, 2_000_000)
+    say(f"case: 3-bin p32_t64 tally from FP64 rays, 18x17x17, {rays2.n} rays, accumulate {accumulate}")
+    ctx.set_mesh(1, mesh2)
+    t32 = ctx.create_tally(1, "p32_t64", edges3)
+    ctx.cast(t32, dev_arrays(rays2, "f64"))  # FP64 rays into the FP32 form: rounded on load
+    m32 = W.RectMesh([np.asarray(p, np.float32).astype(np.float64) for p in mesh2.planes], mesh2.mat,
+                     rho2.astype(np.float32).astype(np.float64))
+    x32 = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
+                     xs.sigma.astype(np.float32).astype(np.float64))
+    res32 = oracle.cast(m32, x32, W.rays_to_f32(rays2).as_f64(), edges=edges3, n_threads=oracle_threads())
+    got32 = ctx.read(t32).reshape(3, -1)
+    g32, a32, n32 = rel_report(got32, res32, gate="stderr")
+    say(f"  FP32: max rel over {n32} gated pairs {g32:.3e}; all {a32:.3e}")
+    assert n32 > 1000
+    assert g32 <= TOL_P32
