@@ -155,10 +155,10 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
  * instead of lo + k h.  Rectilinear meshes are cast by vrc_cast_rays (every
  * accumulate setting, the tile-split accumulation included: its tile walks
  * read the tables too), vrc_trace_rays, vrc_count_segments, vrc_next_event,
- * vrc_cast_batches with split = 1 and the walkers with direct casts or track
- * length only; the serving calls return VRC_ERR_INVALID on them.  FP32
- * forms are refused (VRC_ERR_INVALID at cast
- * time) when two planes of an axis round to the same float.
+ * vrc_cast_batches with split = 1, the serving loop (which casts such
+ * requests with the plain kernel) and the walkers.  FP32 forms are refused
+ * (VRC_ERR_INVALID at cast time) when two planes of an axis round to the
+ * same float.
  * Errors: VRC_ERR_INVALID (bad n or planes), VRC_ERR_STATE (a tally uses
  * the mesh), VRC_ERR_NOMEM.                                                */
 vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], const double *x_planes,
@@ -172,9 +172,8 @@ vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], cons
  * (1/Sigma_m) * (1/rho).  rho == NULL removes the factors.  Setting or
  * replacing the mesh removes them too.  Such a mesh is cast by vrc_cast_rays
  * (every accumulate setting), vrc_trace_rays, vrc_count_segments,
- * vrc_next_event, vrc_cast_batches with split = 1 and the walkers with
- * direct casts or track length only; the serving calls return
- * VRC_ERR_INVALID on it.  Errors: VRC_ERR_INVALID (no such mesh, a bad
+ * vrc_next_event, vrc_cast_batches with split = 1, the serving loop (which
+ * casts such requests with the plain kernel) and the walkers.  Errors: VRC_ERR_INVALID (no such mesh, a bad
  * factor), VRC_ERR_STATE (a tally uses the mesh), VRC_ERR_NOMEM.           */
 vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho);
 
@@ -401,9 +400,7 @@ vrc_status vrc_serve_stop(vrc_ctx *ctx);
  * a private copy and the copies are added to tl_tally when the run ends.
  * tl_only = 1 emits no rays (a track-length run: no serving loop needed).
  * On a rectilinear mesh the walk reads the planes from the mesh's tables,
- * and density factors scale sigma[m] per voxel; such meshes are walked with
- * direct = 1 or tl_only = 1 only (the serving loop takes plain uniform
- * meshes: VRC_ERR_INVALID otherwise). */
+ * and density factors scale sigma[m] per voxel. */
 typedef struct {
     int32_t tally_id;
     int32_t n_threads;

@@ -254,14 +254,6 @@ vrc_status vrc::check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
     return VRC_OK;
 }
 
-vrc_status vrc::check_uniform_mesh(vrc_ctx *ctx, const TallyHost *t, const char *what)
-{
-    const MeshHost &m = ctx->meshes[t->mesh_id];
-    if (m.rect || m.dens)
-        return set_error(VRC_ERR_INVALID, std::string(what) + " takes uniform meshes without density factors only; "
-                                                               "cast rays on such a mesh with vrc_cast_rays");
-    return VRC_OK;
-}
 
 extern "C" {
 

@@ -275,8 +275,6 @@ vrc_status set_error(vrc_status st, const std::string &msg);
 vrc_status device_error(vrc_ctx *ctx, hipError_t e, const char *what);
 // Tables, mesh and material ids ready for casting into tally t.
 vrc_status check_cast_ready(vrc_ctx *ctx, const TallyHost *t);
-// VRC_ERR_INVALID when the tally's mesh is rectilinear (`what` names the caller).
-vrc_status check_uniform_mesh(vrc_ctx *ctx, const TallyHost *t, const char *what);
 // Upload a descriptor table through slot bs and run the persistent kernel.
 vrc_status run_batched(vrc_ctx *ctx, BatchedSlot &bs, const BatchedShape &shape, vrc_precision prec, bool fp64,
                        const std::vector<BatchDescDev> &desc, int64_t items, hipStream_t s);

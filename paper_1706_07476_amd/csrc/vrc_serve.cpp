@@ -176,7 +176,11 @@ double percentile(std::vector<double> v, double q)
     return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
 }
 
-// Launch one group of requests (same tally form and ray type) on stream s.
+// Launch one group of requests (same tally form and ray type) on stream s:
+// the persistent kernel for requests on plain uniform meshes, and before it
+// one plain cast per request on a rectilinear mesh or a mesh with density
+// factors (the persistent kernel walks plain uniform meshes only).  The
+// slot's event, recorded after the last launch, marks the group done.
 vrc_status launch_group(vrc_ctx *ctx, ServeState &S, std::vector<ServeRequest> &reqs, int slot, hipStream_t s)
 {
     std::vector<BatchDescDev> desc;
@@ -189,8 +193,18 @@ vrc_status launch_group(vrc_ctx *ctx, ServeState &S, std::vector<ServeRequest> &
         for (const auto &r : reqs) {
             const TallyHost *t = ctx->tallies[r.tally_id].get();
             prec = t->prec;
-            BatchDescDev d;
             const size_t el = r.fp64 ? 8 : 4;
+            const MeshHost &m = ctx->meshes[t->mesh_id];
+            if (m.rect || m.dens) {
+                RaysP rays;
+                const void **p[8] = {&rays.ox, &rays.oy, &rays.oz, &rays.ux, &rays.uy, &rays.uz, &rays.e, &rays.w};
+                for (int k = 0; k < 8; ++k) *p[k] = S.d_ring + r.ring_off + k * el * static_cast<size_t>(r.n);
+                rays.n = r.n;
+                hipError_t e = launch_cast(*ctx, *t, m, rays, r.fp64 != 0, s);
+                if (e != hipSuccess) return device_error(ctx, e, "serving cast on a rectilinear or density mesh");
+                continue;
+            }
+            BatchDescDev d;
             for (int k = 0; k < 8; ++k) d.ray[k] = S.d_ring + r.ring_off + k * el * static_cast<size_t>(r.n);
             d.n = r.n;
             d.item_begin = items;
@@ -203,7 +217,12 @@ vrc_status launch_group(vrc_ctx *ctx, ServeState &S, std::vector<ServeRequest> &
             desc.push_back(d);
         }
     }
-    return run_batched(ctx, S.slots[slot], shape, prec, reqs.front().fp64 != 0, desc, items, s);
+    if (!desc.empty()) return run_batched(ctx, S.slots[slot], shape, prec, reqs.front().fp64 != 0, desc, items, s);
+    BatchedSlot &bs = S.slots[slot];
+    const hipError_t e = hipEventRecord(bs.done, s);
+    if (e != hipSuccess) return device_error(ctx, e, "recording a serving launch");
+    bs.used = true;
+    return VRC_OK;
 }
 
 void count_group(vrc_ctx *ctx, ServeState &S, const std::vector<ServeRequest> &reqs, hipStream_t s)
@@ -441,7 +460,6 @@ vrc_status vrc_serve_submit(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *bat
         if (tally_id < 0 || tally_id >= static_cast<int>(ctx->tallies.size()) || !ctx->tallies[tally_id])
             return set_error(VRC_ERR_INVALID, "no such tally");
         if (vrc_status st = check_cast_ready(ctx, ctx->tallies[tally_id].get())) return st;
-        if (vrc_status st = check_uniform_mesh(ctx, ctx->tallies[tally_id].get(), "the serving form")) return st;
     }
     const size_t el = batch->fp64 ? 8 : 4;
     const size_t arr = el * static_cast<size_t>(batch->n);

@@ -255,9 +255,6 @@ vrc_status vrc_walkers_run(vrc_ctx *ctx, const vrc_walker_config *cfg, vrc_walke
         if (id < 0 || id >= static_cast<int>(ctx->tallies.size()) || !ctx->tallies[id])
             return set_error(VRC_ERR_INVALID, "no such tally");
         const MeshHost &m = ctx->meshes[ctx->tallies[id]->mesh_id];
-        // the serving loop takes plain uniform meshes only; direct casts and track-length runs take any
-        if (!cfg->direct && !cfg->tl_only)
-            if (vrc_status st = check_uniform_mesh(ctx, ctx->tallies[id].get(), "the serving form")) return st;
         if (cfg->n_sigma < m.max_mat + 1 || cfg->n_sigma > 64)
             return set_error(VRC_ERR_INVALID, "sigma must cover every material of the mesh");
         // the tables and factors are host copies that stay put while a tally uses the mesh

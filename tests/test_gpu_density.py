@@ -7,8 +7,9 @@ components' grids, evaluated by the oracle component by component).
 Tallies: 1e-12 (FP64), 1e-5 on well-sampled voxels (FP32 forms, against the
 oracle on the same FP32-rounded inputs), on the per-segment atomic path and
 the tile-split accumulation; per-segment scores 1e-13.
-Unit factors give the plain scores bit for bit.  Paths that take plain
-meshes only refuse a mesh with factors.
+Unit factors give the plain scores bit for bit.  The persistent batched
+kernel refuses a mesh with factors; the serving loop casts such requests
+with the plain kernel.
 """
 import sys
 
@@ -215,16 +216,18 @@ def test_density_and_mixture_errors(vrc, ctx):
         ctx.cast_batches([(tid, arrays)])
     assert e.value.status == vrc.VRC_ERR_INVALID
     t64 = ctx.create_tally(0, "p64")
+    # the serving loop casts requests on a mesh with factors with the plain kernel; walkers may feed it
     ctx.serve_start()
     try:
-        with pytest.raises(vrc.VrcError) as e:
-            ctx.serve_submit(tid, host_arrays(rays, "f32"))
-        assert e.value.status == vrc.VRC_ERR_INVALID
-        with pytest.raises(vrc.VrcError) as e:  # walkers feeding the serving loop
-            ctx.walkers_run(t64, [0.1, 0.5, 1.0], base.lo + 4.0, max_histories=10, duration_s=0.0)
-        assert e.value.status == vrc.VRC_ERR_INVALID
+        t_s = ctx.create_tally(0, "p32_t64")
+        ctx.serve_wait(ctx.serve_submit(t_s, host_arrays(rays, "f32")))
+        r = ctx.walkers_run(t64, [0.1, 0.5, 1.0], base.lo + 4.0, max_histories=10, duration_s=0.0)
+        assert r["histories"] == 10 and r["rays_submitted"] == r["rays_emitted"]
     finally:
         ctx.serve_stop()
+    t_d = ctx.create_tally(0, "p32_t64")
+    ctx.cast(t_d, arrays)
+    np.testing.assert_allclose(ctx.read(t_s), ctx.read(t_d), rtol=1e-12, atol=0)
     r = ctx.walkers_run(t64, [0.1, 0.5, 1.0], base.lo + 4.0, direct=1, max_histories=10, duration_s=0.0)
     assert r["histories"] == 10
     with pytest.raises(vrc.VrcError) as e:
@@ -233,8 +236,8 @@ def test_density_and_mixture_errors(vrc, ctx):
     ctx.cast(tid, arrays)
     assert ctx.read(tid).sum() > 0
     # removing the factors makes the mesh plain again
-    ctx.destroy_tally(tid)
-    ctx.destroy_tally(t64)
+    for t in (tid, t64, t_s, t_d):
+        ctx.destroy_tally(t)
     vrc.vrc_set_mesh_density(ctx.handle, 0, None)
     tid = ctx.create_tally(0, "p32_t64")
     ctx.cast_batches([(tid, arrays)])
@@ -326,3 +329,36 @@ def test_energy_bins_on_a_rectilinear_mesh_with_factors(ctx, accumulate):
     say(f"  FP32: max rel over {n32} gated pairs {g32:.3e}; all {a32:.3e}")
     assert n32 > 1000
     assert g32 <= TOL_P32
+
+
+def test_serving_mixes_plain_rectilinear_and_density_meshes(ctx):
+    """One serving session with requests on a uniform mesh (persistent kernel), a rectilinear mesh and
+    a mesh with factors (plain casts in the same launch group): every request's tally equals a direct
+    cast of the same rays up to the order of the additions."""
+    xs = W.gen.three_material_xs(1000, 1000)
+    ctx.set_xs(xs)
+    uni = W.slab_mesh(1001, 24, 0.5, slab=4)
+    rect = W.rect_mesh(1002, (22, 25, 21), h_min=0.3, h_max=0.7)
+    dens = W.Mesh(uni.lo, uni.h, uni.n, uni.mat, W.density_field(1003, uni.n_voxels, 0.5, 2.0))
+    meshes = [uni, rect, dens]
+    for i, m in enumerate(meshes):
+        ctx.set_mesh(i, m)
+    say("case: serving with uniform, rect and density meshes, 3 x 6 requests")
+    served = [ctx.create_tally(i, "p32_t64") for i in range(3)]
+    direct = [ctx.create_tally(i, "p32_t64") for i in range(3)]
+    reqs = [(i, W.rays_in_box(1010 + 6 * i + k, meshes[i], 3000 + 500 * k)) for k in range(6) for i in range(3)]
+    ctx.serve_start(linger_us=2000)
+    try:
+        tickets = [ctx.serve_submit(served[i], host_arrays(r, "f32")) for i, r in reqs]
+        for t in tickets:
+            ctx.serve_wait(t)
+    finally:
+        ctx.serve_stop()
+    for i, r in reqs:
+        ctx.cast(direct[i], dev_arrays(r, "f32"))
+    for i in range(3):
+        a, b = ctx.read(served[i]), ctx.read(direct[i])
+        assert b.sum() > 0
+        rel = np.max(np.abs(a - b) / np.where(b > 0, b, 1.0))
+        say(f"  mesh {i}: max rel served vs direct {rel:.3e}")
+        assert rel <= 1e-12

@@ -8,8 +8,9 @@ rays); tallies within 1e-12 (FP64) and 1e-5 on well-sampled voxels (FP32
 forms), as for uniform meshes, on the per-segment atomic path and on the
 tile-split accumulation.  Plane tables equal to a uniform mesh's
 planes give the uniform mesh's traces bit for bit.  Rays start inside,
-outside, on planes and along planes.  Paths that take uniform meshes only
-refuse a rectilinear one.
+outside, on planes and along planes.  The persistent batched kernel, which
+takes uniform meshes only, refuses a rectilinear one; the serving loop casts
+such requests with the plain kernel.
 """
 import math
 import sys
@@ -237,23 +238,26 @@ def test_rect_errors_and_refusals(vrc, ctx):
     tid = ctx.create_tally(0, "p32_t64")
     rays = W.rays_in_box(917, mesh, 300)
     arrays = dev_arrays(rays, "f32")
-    # the persistent batched kernel (split = 0, the default) and the serving form take uniform meshes
-    # only
+    # the persistent batched kernel (split = 0, the default) takes uniform meshes only
     with pytest.raises(vrc.VrcError) as e:
         ctx.cast_batches([(tid, arrays)])
     assert e.value.status == vrc.VRC_ERR_INVALID
     t64 = ctx.create_tally(0, "p64")
     src = mesh.lo + 0.5 * (mesh.hi - mesh.lo)
+    # the serving loop casts requests on a rectilinear mesh with the plain kernel; walkers may feed it
     ctx.serve_start()
     try:
-        with pytest.raises(vrc.VrcError) as e:
-            ctx.serve_submit(tid, host_arrays(rays, "f32"))
-        assert e.value.status == vrc.VRC_ERR_INVALID
-        with pytest.raises(vrc.VrcError) as e:  # walkers feeding the serving loop
-            ctx.walkers_run(t64, [0.1, 0.5, 1.0], src, max_histories=10, duration_s=0.0)
-        assert e.value.status == vrc.VRC_ERR_INVALID
+        t_s = ctx.create_tally(0, "p32_t64")
+        ctx.serve_wait(ctx.serve_submit(t_s, host_arrays(rays, "f32")))
+        r = ctx.walkers_run(t64, [0.1, 0.5, 1.0], src, max_histories=10, duration_s=0.0)
+        assert r["histories"] == 10 and r["rays_submitted"] == r["rays_emitted"]
     finally:
         ctx.serve_stop()
+    t_d = ctx.create_tally(0, "p32_t64")
+    ctx.cast(t_d, arrays)
+    a_s, a_d = ctx.read(t_s), ctx.read(t_d)
+    assert a_d.sum() > 0
+    np.testing.assert_allclose(a_s, a_d, rtol=1e-12, atol=0)
     # walkers with direct casts walk the plane tables
     r = ctx.walkers_run(t64, [0.1, 0.5, 1.0], src, direct=1, max_histories=10, duration_s=0.0)
     assert r["histories"] == 10
