@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--next-event", type=int, default=1,
                     help="also time the next-event (point-detector) estimator on the multimat mesh")
     ap.add_argument("--fom-histories", type=int, default=100000)
+    ap.add_argument("--host-input", type=int, default=1,
+                    help="also time the cast from host arrays (the PCIe-inclusive rate; never the headline value)")
     ap.add_argument("--rect", type=int, default=1,
                     help="also time the cast on a rectilinear mesh of the multimat box, on the multimat mesh with "
                          "per-voxel density factors (tile-split and atomic paths) and with mixture materials")
@@ -325,6 +327,26 @@ def bench_mixtures(vrc, ctx, wl, arrays, torch, stream, steps: int = 10) -> dict
         ctx.set_xs(xs)
     return {"workload": "multimat mesh and 1e6 rays; 3 materials as mixtures of 5 components on two energy grids",
             "precision": prec, "ms_per_step": tot_m / steps, "plain_tables_ms_per_step": tot_p / steps}
+
+
+def bench_host_input(vrc, ctx, wl, torch, S, steps: int = 10) -> dict:
+    """The bench cast from host arrays (the PCIe-inclusive rate): FP32 rays in pageable numpy arrays,
+    copied by the library into its pinned staging buffer and then to the device, cast with the
+    default accumulation; wall-clock over `steps` calls, synchronised at both ends."""
+    host = [np.ascontiguousarray(a, dtype=np.float32) for a in wl.rays.arrays()]
+    tid = ctx.create_tally(0, "p32_t64")
+    for _ in range(2):
+        ctx.cast(tid, host)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.cast(tid, host)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    ctx.destroy_tally(tid)
+    return {"workload": "the bench workload's 1e6 FP32 rays in host memory (32 MB per cast)",
+            "ms_per_step": ms, "segments_per_s": S / (ms / 1e3),
+            "host_bytes_per_s": 32.0 * wl.rays.n / (ms / 1e3)}
 
 
 def cpu_baseline(wl, target_s):
@@ -713,6 +735,15 @@ def main():
         except Exception as exc:  # the headline line must still be printed
             log(f"bench: rectilinear measurement failed: {exc!r}")
             rect_form = {"error": repr(exc)}
+    host_input = None
+    if args.host_input:
+        try:
+            host_input = bench_host_input(vrc, ctx, wl, torch, S)
+            log(f"bench: from host arrays {host_input['segments_per_s']:.3e} segments/s "
+                f"({host_input['ms_per_step']:.3f} ms per cast)")
+        except Exception as exc:  # the headline line must still be printed
+            log(f"bench: host-input measurement failed: {exc!r}")
+            host_input = {"error": repr(exc)}
     density_form = None
     if args.rect:
         try:
@@ -789,6 +820,7 @@ def main():
         "next_event_form": next_event,
         "rect_form": rect_form,
         "density_form": density_form,
+        "host_input_form": host_input,
         "mixture_form": mixture_form,
         "wall_s_timed": wall,
     }
