@@ -362,3 +362,67 @@ def test_serving_mixes_plain_rectilinear_and_density_meshes(ctx):
         rel = np.max(np.abs(a - b) / np.where(b > 0, b, 1.0))
         say(f"  mesh {i}: max rel served vs direct {rel:.3e}")
         assert rel <= 1e-12
+
+
+def _bench_rect_mesh(wl):
+    """The bench's rectilinear form: 100 spacings per axis in [0.25, 0.75] cm scaled to the 50 cm box."""
+    m = wl.mesh
+    rng = np.random.default_rng(2024)
+    planes = []
+    for a in range(3):
+        h = rng.uniform(0.25, 0.75, int(m.n[a]))
+        span = float(m.n[a] * m.h[a])
+        planes.append(m.lo[a] + np.concatenate([[0.0], np.cumsum(h) * (span / h.sum())]))
+    return W.RectMesh(planes, m.mat)
+
+
+@pytest.mark.parametrize("kind,prec", [("rect", "p64"), ("rect", "p32_t64"), ("density", "p64"),
+                                       ("density", "p32_t64")])
+def test_full_size_extension_forms(ctx, kind, prec):
+    """The bench's rectilinear and density forms at full size (100^3, 1e6 rays, default launch: the
+    tile-split accumulation) against the oracle: FP64 on every voxel (1e-12), FP32 on the gated voxels
+    (1e-5) and eps_phi (Eq. 8) at most 1e-2, and the exact segment counts."""
+    import torch
+    from test_gpu_parity import eps_phi_max
+    wl = W.config2_multimaterial()
+    if kind == "rect":
+        mesh = _bench_rect_mesh(wl)
+    else:
+        m = wl.mesh
+        mesh = W.Mesh(m.lo, m.h, m.n, m.mat, W.density_field(2025, m.n_voxels, 0.5, 2.0))
+    say(f"case: full-size {kind} form, 100^3, 1e6 rays, {prec}, launch {ctx.get_launch()}")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    dt = "f64" if prec == "p64" else "f32"
+    arrays = dev_arrays(wl.rays, dt)
+    tid = ctx.create_tally(0, prec)
+    ctx.cast(tid, arrays)
+    got = ctx.read(tid)
+    counts = torch.empty(wl.rays.n, dtype=torch.int64, device="cuda:0")
+    total = ctx.count_segments(0, prec, arrays, counts)
+    if prec == "p64":
+        res = oracle.cast(mesh, wl.xs, wl.rays, n_threads=oracle_threads())
+        g, _, n = rel_report(got, res, gate="all")
+        say(f"  FP64 max rel over {n} voxels {g:.3e}")
+        assert g <= TOL_P64
+        o_counts = oracle.count_segments(mesh, wl.rays, "f64", oracle_threads())
+    else:
+        r32 = W.rays_to_f32(wl.rays)
+        if kind == "rect":
+            m32 = W.RectMesh([np.asarray(p, np.float32).astype(np.float64) for p in mesh.planes], mesh.mat)
+        else:
+            m32 = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
+                         mesh.n, mesh.mat, mesh.density.astype(np.float32).astype(np.float64))
+        x32 = W.XSTables(wl.xs.offs, wl.xs.energy.astype(np.float32).astype(np.float64),
+                         wl.xs.sigma.astype(np.float32).astype(np.float64))
+        res = oracle.cast(m32, x32, r32.as_f64(), n_threads=oracle_threads())
+        g, a, n = rel_report(got, res, gate="stderr")
+        eps = eps_phi_max(got, res)
+        say(f"  FP32: gated {n} voxels max rel {g:.3e}; all voxels {a:.3e}; max eps_phi {eps:.3e}")
+        assert g <= TOL_P32
+        assert eps <= 1e-2
+        o_counts = oracle.count_segments(m32 if kind == "rect" else
+                                         W.Mesh(mesh.lo.astype(np.float32), mesh.h.astype(np.float32), mesh.n,
+                                                mesh.mat), r32, "f32", oracle_threads())
+    np.testing.assert_array_equal(counts.cpu().numpy(), o_counts)
+    assert total == int(o_counts.sum())
