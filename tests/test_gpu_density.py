@@ -18,7 +18,7 @@ import pytest
 
 import oracle
 import workloads as W
-from vrc_testutil import dev_arrays, host_arrays, oracle_threads, rel_report, unscored_ok
+from vrc_testutil import dev_arrays, f32_view, host_arrays, oracle_threads, rel_report, unscored_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -52,16 +52,6 @@ def with_density(mesh, rho):
     if hasattr(mesh, "planes"):
         return W.RectMesh(mesh.planes, mesh.mat, rho)
     return W.Mesh(mesh.lo, mesh.h, mesh.n, mesh.mat, rho)
-
-
-def f32_inputs(mesh, xs, rays, round_density):
-    """The FP32 forms' inputs promoted back to FP64 (density rounded when the form scores in FP32)."""
-    rho = mesh.density.astype(np.float32).astype(np.float64) if round_density else mesh.density
-    m = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
-               mesh.n, mesh.mat, rho)
-    x = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
-                   xs.sigma.astype(np.float32).astype(np.float64))
-    return m, x, W.rays_to_f32(rays).as_f64()
 
 
 @pytest.mark.parametrize("accumulate", [0, 1, 3])
@@ -116,7 +106,7 @@ def test_density_fp32_forms_well_sampled(ctx, prec, accumulate):
     ctx.set_launch(accumulate=accumulate)
     tid = ctx.create_tally(0, prec)
     ctx.cast(tid, dev_arrays(rays, "f32"))
-    m, x, r = f32_inputs(mesh, xs, rays, round_density=prec != "p32_d64")
+    m, x, r = f32_view(mesh, xs, rays, round_density=prec != "p32_d64")
     res = oracle.cast(m, x, r, n_threads=oracle_threads())
     got = ctx.read(tid)
     g, a, n = rel_report(got, res, gate="stderr")
@@ -319,11 +309,8 @@ def test_energy_bins_on_a_rectilinear_mesh_with_factors(ctx, accumulate):
     ctx.set_mesh(1, mesh2)
     t32 = ctx.create_tally(1, "p32_t64", edges3)
     ctx.cast(t32, dev_arrays(rays2, "f64"))  # FP64 rays into the FP32 form: rounded on load
-    m32 = W.RectMesh([np.asarray(p, np.float32).astype(np.float64) for p in mesh2.planes], mesh2.mat,
-                     rho2.astype(np.float32).astype(np.float64))
-    x32 = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
-                     xs.sigma.astype(np.float32).astype(np.float64))
-    res32 = oracle.cast(m32, x32, W.rays_to_f32(rays2).as_f64(), edges=edges3, n_threads=oracle_threads())
+    m32, x32, r32 = f32_view(mesh2, xs, rays2)
+    res32 = oracle.cast(m32, x32, r32, edges=edges3, n_threads=oracle_threads())
     got32 = ctx.read(t32).reshape(3, -1)
     g32, a32, n32 = rel_report(got32, res32, gate="stderr")
     say(f"  FP32: max rel over {n32} gated pairs {g32:.3e}; all {a32:.3e}")
@@ -407,22 +394,13 @@ def test_full_size_extension_forms(ctx, kind, prec):
         assert g <= TOL_P64
         o_counts = oracle.count_segments(mesh, wl.rays, "f64", oracle_threads())
     else:
-        r32 = W.rays_to_f32(wl.rays)
-        if kind == "rect":
-            m32 = W.RectMesh([np.asarray(p, np.float32).astype(np.float64) for p in mesh.planes], mesh.mat)
-        else:
-            m32 = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
-                         mesh.n, mesh.mat, mesh.density.astype(np.float32).astype(np.float64))
-        x32 = W.XSTables(wl.xs.offs, wl.xs.energy.astype(np.float32).astype(np.float64),
-                         wl.xs.sigma.astype(np.float32).astype(np.float64))
-        res = oracle.cast(m32, x32, r32.as_f64(), n_threads=oracle_threads())
+        m32, x32, r64 = f32_view(mesh, wl.xs, wl.rays)
+        res = oracle.cast(m32, x32, r64, n_threads=oracle_threads())
         g, a, n = rel_report(got, res, gate="stderr")
         eps = eps_phi_max(got, res)
         say(f"  FP32: gated {n} voxels max rel {g:.3e}; all voxels {a:.3e}; max eps_phi {eps:.3e}")
         assert g <= TOL_P32
         assert eps <= 1e-2
-        o_counts = oracle.count_segments(m32 if kind == "rect" else
-                                         W.Mesh(mesh.lo.astype(np.float32), mesh.h.astype(np.float32), mesh.n,
-                                                mesh.mat), r32, "f32", oracle_threads())
+        o_counts = oracle.count_segments(m32, W.rays_to_f32(wl.rays), "f32", oracle_threads())
     np.testing.assert_array_equal(counts.cpu().numpy(), o_counts)
     assert total == int(o_counts.sum())

@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 import workloads as W
+from vrc_testutil import mesh32, xs32
 
 pytestmark = pytest.mark.gpu
 
@@ -94,10 +95,7 @@ def test_fp32_walk_matches_oracle_on_fp32_inputs(ctx, prec):
     ctx.set_mesh(0, mesh)
     ctx.set_xs(xs)
     got = gpu_scores(ctx, prec, p, e, w, det, "f32")
-    m32 = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
-                 mesh.n, mesh.mat)
-    x32 = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
-                     xs.sigma.astype(np.float32).astype(np.float64))
+    m32, x32 = mesh32(mesh), xs32(xs)
     f = lambda a: a.astype(np.float32)
     ref = oracle.next_event(m32, x32, f(p[:, 0]), f(p[:, 1]), f(p[:, 2]), f(e).astype(np.float64),
                             f(w).astype(np.float64), det, precision="f32")
@@ -211,14 +209,7 @@ def test_rectilinear_and_density_meshes(ctx, kind):
     det32 = tuple(float(np.float32(v)) for v in det)
     got32 = gpu_scores(ctx, "p32_t64", p, e, w, det32, "f32")
     f = lambda a: a.astype(np.float32)
-    if "rect" in kind:
-        m32 = W.RectMesh([np.asarray(q, np.float32).astype(np.float64) for q in mesh.planes], mesh.mat,
-                         None if rho is None else rho.astype(np.float32).astype(np.float64))
-    else:
-        m32 = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
-                     mesh.n, mesh.mat, None if rho is None else rho.astype(np.float32).astype(np.float64))
-    x32 = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
-                     xs.sigma.astype(np.float32).astype(np.float64))
+    m32, x32 = mesh32(mesh), xs32(xs)
     ref32 = oracle.next_event(m32, x32, f(p[:, 0]), f(p[:, 1]), f(p[:, 2]), f(e).astype(np.float64),
                               f(w).astype(np.float64), det32, precision="f32")
     pos = ref32 > 1e-300

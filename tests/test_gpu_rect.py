@@ -20,7 +20,7 @@ import pytest
 
 import oracle
 import workloads as W
-from vrc_testutil import dev_arrays, host_arrays, oracle_threads, rel_report, unscored_ok
+from vrc_testutil import dev_arrays, host_arrays, mesh32, oracle_threads, rel_report, unscored_ok, xs32
 
 pytestmark = pytest.mark.gpu
 
@@ -48,16 +48,6 @@ def ctx(vrc):
     c = vrc.Context(0)
     yield c
     c.close()
-
-
-def rect32(mesh):
-    """The mesh as the FP32 forms see it: every plane rounded to FP32."""
-    return W.RectMesh([np.asarray(p, np.float32).astype(np.float64) for p in mesh.planes], mesh.mat)
-
-
-def xs32(xs):
-    return W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
-                      xs.sigma.astype(np.float32).astype(np.float64))
 
 
 def mixed_rays(seed, mesh, n, frac_out=0.2):
@@ -128,7 +118,7 @@ def test_trace_bit_exact_fp64_and_fp32(ctx):
         np.testing.assert_allclose(sc[offs[r]:offs[r + 1]], s_ref, rtol=1e-13, atol=1e-300)
     t32 = ctx.create_tally(0, "p32_t64")
     offs, vox, ln, _ = ctx.trace(t32, dev_arrays(rays, "f32"))
-    o_offs, o_vox, o_len = oracle.trace_many(rect32(mesh), W.rays_to_f32(rays), precision="f32")
+    o_offs, o_vox, o_len = oracle.trace_many(mesh32(mesh), W.rays_to_f32(rays), precision="f32")
     np.testing.assert_array_equal(offs, o_offs)
     np.testing.assert_array_equal(vox, o_vox)
     np.testing.assert_array_equal(ln, np.asarray(o_len, dtype=np.float64))
@@ -140,7 +130,7 @@ def test_segment_counts_bit_exact(ctx):
     rays = mixed_rays(905, mesh, 20_003)
     say(f"case: rect segment counts p64 and p32_t64, 30x33x29, {rays.n} rays")
     ctx.set_mesh(0, mesh)
-    for prec, dt, m, r in (("p64", "f64", mesh, rays), ("p32_t64", "f32", rect32(mesh), W.rays_to_f32(rays))):
+    for prec, dt, m, r in (("p64", "f64", mesh, rays), ("p32_t64", "f32", mesh32(mesh), W.rays_to_f32(rays))):
         counts = torch.zeros(rays.n, dtype=torch.int64, device="cuda:0")
         total = ctx.count_segments(0, prec, dev_arrays(rays, dt), counts)
         ref = oracle.count_segments(m, r, precision=dt, n_threads=oracle_threads())
@@ -181,7 +171,7 @@ def test_tally_fp32_forms_well_sampled(ctx, prec, accumulate):
     ctx.set_launch(accumulate=accumulate)
     tid = ctx.create_tally(0, prec)
     ctx.cast(tid, dev_arrays(rays, "f32"))
-    res = oracle.cast(rect32(mesh), xs32(xs), W.rays_to_f32(rays).as_f64(), n_threads=oracle_threads())
+    res = oracle.cast(mesh32(mesh), xs32(xs), W.rays_to_f32(rays).as_f64(), n_threads=oracle_threads())
     got = ctx.read(tid)
     g, a, n = rel_report(got, res, gate="stderr")
     say(f"  max rel over {n} gated voxels {g:.3e}; all voxels {a:.3e}")

@@ -12,19 +12,37 @@ def oracle_threads() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def f32_view(mesh: W.Mesh, xs: W.XSTables, rays: W.Rays):
+def _f32(a) -> np.ndarray:
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def mesh32(mesh, round_density: bool = True):
+    """The mesh as the FP32 forms see it, promoted back to FP64: the spacing (or
+    the plane tables) rounded to FP32, and the density factors too when the
+    form scores in FP32 (round_density False for p32_d64, which scores with
+    the FP64 factors)."""
+    rho = getattr(mesh, "density", None)
+    if rho is not None and round_density:
+        rho = _f32(rho)
+    if hasattr(mesh, "planes"):
+        return W.RectMesh([_f32(p) for p in mesh.planes], mesh.mat, rho)
+    return W.Mesh(_f32(mesh.lo), _f32(mesh.h), mesh.n, mesh.mat, rho)
+
+
+def xs32(xs: W.XSTables) -> W.XSTables:
+    """The cross-section tables rounded to FP32, promoted back to FP64."""
+    return W.XSTables(xs.offs, _f32(xs.energy), _f32(xs.sigma))
+
+
+def f32_view(mesh, xs: W.XSTables, rays: W.Rays, round_density: bool = True):
     """Inputs as the FP32 forms see them (every value rounded to FP32), promoted back to FP64.
 
-    The FP32 forms compute on FP32 copies of the mesh spacing, the tables and
-    the rays; the oracle is run on exactly those values so that a comparison
-    measures the FP32 arithmetic, not the rounding of the inputs.
+    The FP32 forms compute on FP32 copies of the mesh spacing or planes, the
+    density factors, the tables and the rays; the oracle is run on exactly
+    those values so that a comparison measures the FP32 arithmetic, not the
+    rounding of the inputs.
     """
-    m = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
-               mesh.n, mesh.mat)
-    x = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
-                   xs.sigma.astype(np.float32).astype(np.float64))
-    r = W.rays_to_f32(rays).as_f64()
-    return m, x, r
+    return mesh32(mesh, round_density), xs32(xs), W.rays_to_f32(rays).as_f64()
 
 
 def dev_arrays(rays: W.Rays, dtype: str = "f64"):
