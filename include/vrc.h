@@ -145,8 +145,9 @@ const char *vrc_version(void);
 vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const double h[3],
                         const int32_t n[3], const uint8_t *mat);
 
-/* Define (or replace) mesh `mesh_id` as a rectilinear mesh: the Cartesian
- * mesh of Sec. 3 with unequal spacing, voxel (i,j,k) spanning
+/* Define (or replace) mesh `mesh_id` as a rectilinear mesh (a structured
+ * mesh, among the geometry extensions of Sec. 6.3): the Cartesian mesh of
+ * Sec. 3 with unequal spacing, voxel (i,j,k) spanning
  * [x_planes[i], x_planes[i+1]) x [y_planes[j], ...) x [z_planes[k], ...).
  * n > 0 (at most 2^20 per axis, fewer than 2^31 voxels); each plane table
  * has n[a]+1 finite, strictly increasing host values in cm, copied (FP64,
@@ -173,8 +174,9 @@ vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], cons
  * replacing the mesh removes them too.  Such a mesh is cast by vrc_cast_rays
  * (every accumulate setting), vrc_trace_rays, vrc_count_segments,
  * vrc_next_event, vrc_cast_batches with split = 1, the serving loop (which
- * casts such requests with the plain kernel) and the walkers.  Errors: VRC_ERR_INVALID (no such mesh, a bad
- * factor), VRC_ERR_STATE (a tally uses the mesh), VRC_ERR_NOMEM.           */
+ * casts such requests with the plain kernel) and the walkers.
+ * Errors: VRC_ERR_INVALID (no such mesh, a bad factor), VRC_ERR_STATE (a
+ * tally uses the mesh), VRC_ERR_NOMEM.                                     */
 vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho);
 
 /* Total macroscopic cross sections Sigma_t(E) of n_mat materials (1..64).
