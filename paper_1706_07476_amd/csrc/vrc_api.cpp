@@ -176,6 +176,8 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
     free_dev(m.d_pl32);
     free_dev(m.d_rho64);
     free_dev(m.d_rho32);
+    free_dev(m.d_rhos64);
+    free_dev(m.d_rhos32);
     m.dens = false;
     m.h_rho.clear();
     m.set = false;
@@ -324,6 +326,8 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         free_dev(m.d_pl32);
         free_dev(m.d_rho64);
         free_dev(m.d_rho32);
+        free_dev(m.d_rhos64);
+        free_dev(m.d_rhos32);
     }
     free_xs(ctx->xs);
     for (auto &st : ctx->stage) {
@@ -411,6 +415,8 @@ vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho)
     (void)hipSetDevice(ctx->device);
     free_dev(m.d_rho64);
     free_dev(m.d_rho32);
+    free_dev(m.d_rhos64);
+    free_dev(m.d_rhos32);
     m.dens = false;
     m.h_rho.clear();
     if (!rho) return VRC_OK;
@@ -431,6 +437,21 @@ vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho)
         return s;
     }
     m.d_rho32 = static_cast<DensPair<float> *>(d);
+    // the factors alone as well, in both precisions (the same values as the pairs' first members)
+    std::vector<float> f32(nv);
+    for (size_t v = 0; v < nv; ++v) f32[v] = p32[v].rho;
+    vrc_status st = upload(ctx, &d, rho, sizeof(double) * nv);
+    if (st == VRC_OK) {
+        m.d_rhos64 = static_cast<double *>(d);
+        st = upload(ctx, &d, f32.data(), sizeof(float) * nv);
+        if (st == VRC_OK) m.d_rhos32 = static_cast<float *>(d);
+    }
+    if (st != VRC_OK) {
+        free_dev(m.d_rho64);
+        free_dev(m.d_rho32);
+        free_dev(m.d_rhos64);
+        return st;
+    }
     m.h_rho.assign(rho, rho + nv);
     m.dens = true;
     return VRC_OK;

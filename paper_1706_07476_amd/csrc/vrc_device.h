@@ -194,12 +194,12 @@ struct TileMaterials {
 template <typename S>
 struct MeshMaterialsDens {
     const uint8_t *mat;
-    const DensPair<S> *dens;
-    DensPair<S> *cur, *next;
+    const S *rho;  // the factors alone: the whole-mesh walk needs rho, not 1/rho
+    S *cur, *next;
     __device__ __forceinline__ int operator()(int32_t vox, int, int, int) const
     {
         *cur = *next;
-        *next = dens[vox];
+        *next = rho[vox];
         return mat[vox];
     }
 };
@@ -686,12 +686,19 @@ __device__ __forceinline__ void stage_lds(const XsP<R> &X, int hash_in_lds, cons
 
 // Cross sections of the ray's energy, then the walk (in R) with the running
 // score (in S: R itself, or double over an FP32 walk).
-// The density-factor pairs of a mesh in the scoring precision S.
+// The density-factor pairs of a mesh in the scoring precision S, and the
+// factors alone.
 template <typename S, typename R>
 __device__ __forceinline__ const DensPair<S> *density_of(const MeshP<R> &M)
 {
     if constexpr (std::is_same<S, double>::value) return M.rho64;
     else return M.rho32;
+}
+template <typename S, typename R>
+__device__ __forceinline__ const S *factors_of(const MeshP<R> &M)
+{
+    if constexpr (std::is_same<S, double>::value) return M.rhos64;
+    else return M.rhos32;
 }
 
 template <typename R, typename S, class Put, bool RECT = false, bool DENS = false>

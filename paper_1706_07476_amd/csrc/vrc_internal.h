@@ -46,6 +46,9 @@ struct MeshP {
     // for density read the one of their score type), or null
     const DensPair<float> *rho32 = nullptr;
     const DensPair<double> *rho64 = nullptr;
+    // the factors alone (half the bytes: walks that need only rho gather these)
+    const float *rhos32 = nullptr;
+    const double *rhos64 = nullptr;
 };
 
 // Cross sections on the union energy grid.  E[K] strictly increasing;
@@ -172,6 +175,8 @@ struct MeshHost {
     std::vector<double> h_rho;
     DensPair<double> *d_rho64 = nullptr;
     DensPair<float> *d_rho32 = nullptr;
+    double *d_rhos64 = nullptr;  // the factors alone, FP64 and FP32
+    float *d_rhos32 = nullptr;
     int32_t n[3] = {0, 0, 0};
     int64_t nvox = 0;
     int max_mat = 0;

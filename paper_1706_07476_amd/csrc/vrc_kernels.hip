@@ -199,6 +199,8 @@ MeshP<R> mesh_args(const MeshHost &m)
     p.mat = m.d_mat;
     p.rho32 = m.d_rho32;
     p.rho64 = m.d_rho64;
+    p.rhos32 = m.d_rhos32;
+    p.rhos64 = m.d_rhos64;
     if (m.rect) {
         const R *base = mesh_planes<R>(m);
         p.pl[0] = base;

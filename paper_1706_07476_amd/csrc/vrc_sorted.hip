@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
 template <typename R, typename S, bool DENS>
 struct EmitEntries {
     const S (*sig)[2];
-    const DensPair<S> *cur;  // DENS: the factors of the voxel being walked (loaded with its material)
+    const S *cur;  // DENS: the factor of the voxel being walked (loaded with its material)
     int shift;  // log2 of the LDS column stride (the block size)
     S tau_hi, tau_lo;
     uint32_t tile;  // tile_tag of the current tile
@@ -587,7 +587,7 @@ struct EmitEntries {
         // Sigma first: its LDS read is then not queued behind the atomic of a tile entry
         const S l = static_cast<S>(len);
         S sg = sig[m << shift][0];
-        if constexpr (DENS) sg = sg * cur->rho;  // the score's own product, so tau matches
+        if constexpr (DENS) sg = sg * *cur;  // the score's own product, so tau matches
         const S x = sg * l;
         const uint32_t tg = tile_tag(ci >> kTileBits, cj >> kTileBits, ck >> kTileBits);
         if (tg != tile || !started) {
@@ -620,12 +620,12 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     S(*mysig)[2] = sig + threadIdx.x;
     const int64_t n = A.rays.n;
     const RayDeal deal(n);
-    DensPair<S> dcur{S(0), S(0)}, dnext{S(0), S(0)};
+    S dcur = S(0), dnext = S(0);
     EmitEntries<R, S, DENS> em{mysig, &dcur, __ffs(bd) - 1, S(0), S(0), 0u, false, R(0), R(0), R(0),
                                R(0), R(0), R(0), R(0), R(0), 0, A.g, static_cast<Entry<R, S> *>(A.sorted),
                                static_cast<uint32_t>(A.cap), s_next, false, 0u, 0u, R(0), S(0), S(0)};
     Walker<R, RECT> wk;
-    const DensPair<S> *dens = density_of<S>(A.mesh);
+    const S *dens = factors_of<S>(A.mesh);
     const auto mats = [&] {
         if constexpr (DENS) return MeshMaterialsDens<S>{A.mesh.mat, dens, &dcur, &dnext};
         else return MeshMaterials{A.mesh.mat};
@@ -1175,6 +1175,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         if constexpr (DENS) {
             mesh.rho32 = m.d_rho32;
             mesh.rho64 = m.d_rho64;
+            mesh.rhos32 = m.d_rhos32;
+            mesh.rhos64 = m.d_rhos64;
         }
         EntryArgs<R> A;
         A.mesh = mesh;
