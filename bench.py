@@ -1,18 +1,22 @@
 """Throughput benchmark of the VRC hot path on one MI355X.
 
 One step = one call of vrc_cast_rays over the whole ray batch of the
-multi-material workload (100^3 mesh of 0.5 cm voxels, 3 materials in
-10-voxel z slabs, 20k-point Sigma_t(E) tables, 1e6 rays with uniform
-origins, isotropic directions, log-uniform energies, lognormal weights),
-i.e. every step of the path: ray load, cross-section lookup, clip, voxel
-walk, attenuation, score and tally accumulation (the library's default
-tile-split accumulation: entries, scans, partition and tiles kernels; or
-one atomic per segment with --accumulate 0).  Inputs are resident in HBM
-before the timed region.
+cylinder workload (256^3 mesh of 0.2 cm voxels: a water-like cylinder with
+8 spherical inserts of two other materials, void outside; 50k-point
+Sigma_t(E) tables; 1e7 rays with origins uniform in the cylinder,
+isotropic directions, log-uniform energies, lognormal weights), in the
+paper's precision scheme (p32_d64: FP32 cross sections and distances, FP64
+optical depth, exponentials, Eq. 4 and tally), i.e. every step of the path:
+ray load, cross-section lookup, clip, voxel walk, attenuation, score and
+tally accumulation (the library's default tile-split accumulation: ordering,
+counting, scans, entries and tiles kernels; or one atomic per segment with
+--accumulate 0).  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: segments/s (the metric), the roofline of the cast
 (all of its kernels, per step) against HBM bandwidth, p50/p99 per-batch
-latency, and the CPU oracle timed on a bounded sample of the same workload.
+latency, the CPU oracle timed on a bounded sample of the same workload, and
+the other forms (the multimat workload, other precisions, batched, serving,
+next-event, mesh extensions) as extra keys.
 """
 from __future__ import annotations
 
@@ -36,7 +40,14 @@ SEG_BYTES = 1 + 2 * 8
 KERNEL_SOURCES = ["paper_1706_07476_amd/csrc/vrc_kernels.hip", "paper_1706_07476_amd/csrc/vrc_sorted.hip",
                   "paper_1706_07476_amd/csrc/vrc_internal.h", "paper_1706_07476_amd/csrc/vrc_math.h",
                   "paper_1706_07476_amd/csrc/vrc_device.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cast_multimat_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cast_cylinder_traffic.json")
+WORKLOADS = {
+    "cylinder": "cylinder: 256^3 mesh of 0.2 cm voxels, water-like cylinder r=20 cm (50k-point Sigma_t table, "
+                "0.1-5/cm) with 8 spherical inserts of 2 other materials, void outside; 1e7 rays (origins uniform "
+                "in the cylinder, isotropic, log-uniform E, lognormal w)",
+    "multimat": "multimat: 100^3 mesh of 0.5 cm voxels, 3 materials in 10-voxel z slabs, 20k-point log-energy "
+                "Sigma_t tables, 1e6 rays (uniform origins, isotropic, log-uniform E, lognormal w)",
+}
 
 
 def kernel_hash() -> str:
@@ -47,14 +58,15 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision: str, launch: dict):
+def measured_traffic(precision: str, launch: dict, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it is for this kernel."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash() or t.get("precision") != precision or t.get("launch") != launch:
+    if (t.get("kernel_hash") != kernel_hash() or t.get("precision") != precision or t.get("launch") != launch
+            or t.get("workload") != workload):
         return None
     return t.get("bytes_per_launch")
 
@@ -64,8 +76,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--rays", type=int, default=1_000_000)
-    ap.add_argument("--precision", default="p32_t64", choices=["p64", "p32_t64", "p32_kahan", "p32_d64"])
+    ap.add_argument("--workload", default="cylinder", choices=sorted(WORKLOADS),
+                    help="the headline workload (the other one is timed as an extra key unless --multimat 0)")
+    ap.add_argument("--rays", type=int, default=None, help="rays per step (default: the workload's)")
+    ap.add_argument("--precision", default="p32_d64", choices=["p64", "p32_t64", "p32_kahan", "p32_d64"])
+    ap.add_argument("--extras", type=int, default=1,
+                    help="0: the headline cast only (profiling runs); 1: every other form too")
+    ap.add_argument("--multimat", type=int, default=1, help="also time the multimat workload's forms")
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--hash-in-lds", type=int, default=None)
@@ -114,14 +131,22 @@ def _counter_rows(csv_path: str, kernel: str, counter: str) -> list:
     return vals
 
 
-# the kernels of one cast of the bench workload; the first one runs exactly once per cast
-PIPELINE = {0: ["cast_f64_kernel<float, float, false"],
-            1: ["entries_kernel<float, float, float, false, false>", "order_hist_kernel<float, float>",
-                "order_scatter_kernel<float, float>", "count_entries_kernel<float, false>", "scan_rows_kernel",
-                "scan_keys_kernel", "tile_kernel<float, float, 0, false, false>", "tile_reduce_kernel<0>"]}
+def pipeline(precision: str, accumulate: int) -> list:
+    """Names (as rocprofv3 prints them, up to the argument list) of the kernels of one cast of
+    FP32 rays (FP64 rays for p64) on a uniform mesh; the first one runs exactly once per cast."""
+    R = "double" if precision == "p64" else "float"
+    S = "float" if precision in ("p32_t64", "p32_kahan") else "double"
+    if accumulate == 0:
+        if precision == "p32_kahan":
+            return [f"cast_kahan_kernel<{R}, false, false>"]
+        return [f"cast_f64_kernel<{R}, {R}, false, {S}, false, false>"]
+    flush = 2 if precision == "p32_kahan" else (1 if accumulate == 3 else 0)
+    return [f"entries_kernel<{R}, {R}, {S}, false, false>", f"order_hist_kernel<{R}, {R}>",
+            f"order_scatter_kernel<{R}, {R}>", f"count_entries_kernel<{R}, false>", "scan_rows_kernel",
+            "scan_keys_kernel", f"tile_kernel<{R}, {S}, {flush}, false, false>", f"tile_reduce_kernel<{flush}>"]
 
 
-def write_traffic(paths, precision="p32_t64", copy_mib=1024) -> None:
+def write_traffic(paths, workload="cylinder", precision="p32_d64", copy_mib=1024) -> None:
     """Scale FETCH_SIZE/WRITE_SIZE (KiB per dispatch) of the cast's kernels by a plain copy of known size.
 
     Per cast: the sum over every dispatch of the cast's kernels divided by the
@@ -130,16 +155,17 @@ def write_traffic(paths, precision="p32_t64", copy_mib=1024) -> None:
     cf, cw, pf, pw = paths
     acc = 1
     launch = {"block": 256, "blocks_per_cu": 8, "hash_in_lds": 1, "aggregate": 0, "accumulate": acc}
-    casts = len(_counter_rows(cf, PIPELINE[acc][0], "FETCH_SIZE"))
-    fetch = sum(sum(_counter_rows(cf, k, "FETCH_SIZE")) for k in PIPELINE[acc]) / casts
-    write = sum(sum(_counter_rows(cw, k, "WRITE_SIZE")) for k in PIPELINE[acc]) / casts
+    kernels = pipeline(precision, acc)
+    casts = len(_counter_rows(cf, kernels[0], "FETCH_SIZE"))
+    fetch = sum(sum(_counter_rows(cf, k, "FETCH_SIZE")) for k in kernels) / casts
+    write = sum(sum(_counter_rows(cw, k, "WRITE_SIZE")) for k in kernels) / casts
     copy_f = sum(_counter_rows(pf, "__amd_rocclr_copyBuffer", "FETCH_SIZE"))
     copy_f /= len(_counter_rows(pf, "__amd_rocclr_copyBuffer", "FETCH_SIZE"))
     copy_w = sum(_counter_rows(pw, "__amd_rocclr_copyBuffer", "WRITE_SIZE"))
     copy_w /= len(_counter_rows(pw, "__amd_rocclr_copyBuffer", "WRITE_SIZE"))
     nbytes = copy_mib * (1 << 20)
     ff, fw = nbytes / (copy_f * 1024), nbytes / (copy_w * 1024)
-    t = {"kernels": PIPELINE[acc], "workload": "multimat 100^3, 1e6 rays (bench.py default)", "precision": precision,
+    t = {"kernels": kernels, "workload": workload, "precision": precision,
          "launch": launch, "kernel_hash": kernel_hash(), "casts_profiled": casts,
          "fetch_size_kib_per_launch": fetch, "write_size_kib_per_launch": write,
          "copy_calibration": {"bytes_read_and_written": nbytes, "fetch_size_kib": copy_f, "write_size_kib": copy_w,
@@ -349,20 +375,56 @@ def bench_host_input(vrc, ctx, wl, torch, S, steps: int = 10) -> dict:
             "host_bytes_per_s": 32.0 * wl.rays.n / (ms / 1e3)}
 
 
+def host_cpu():
+    """(threads the oracle runs on, what was counted): the host's CPUs available to this process,
+    capped by OMP_NUM_THREADS (the share of a shared GPU machine's cores given to one GPU's jobs)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    share = os.environ.get("OMP_NUM_THREADS")
+    threads = min(avail, int(share)) if share and share.isdigit() and int(share) > 0 else avail
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(1, threads), {"nproc": os.cpu_count(), "affinity": avail, "omp_num_threads": share, "model": model}
+
+
 def cpu_baseline(wl, target_s):
-    """The FP64 oracle on the same workload: whole passes on all host threads for about target_s seconds."""
+    """The FP64 oracle (built -O3 -march=native for this host) on a bounded sample of the same workload:
+    passes over a slice of its rays on all the host threads this process may use, for about target_s
+    seconds of tracing and scoring."""
+    import tempfile
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    from oracle import build as oracle_build
+    native = oracle_build.build_native(tempfile.mkdtemp(prefix="vrc_oracle_"))
+    oracle.use_library(native)
+    threads, host = host_cpu()
+    # a slice that takes a few seconds per pass on this host's threads
+    probe = wl.rays.take(slice(0, min(wl.rays.n, 100_000)))
+    r0 = oracle.cast(wl.mesh, wl.xs, probe, n_threads=threads, with_stats=False)
+    per_ray_s = max(r0.seconds, 1e-6) / probe.n
+    n_slice = int(min(wl.rays.n, max(probe.n, (target_s / 3.0) / per_ray_s)))
+    sample = wl.rays.take(slice(0, n_slice))
     segs, secs, passes = 0, 0.0, 0
     while secs < target_s and passes < 64:
-        res = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=threads, with_stats=False)
+        res = oracle.cast(wl.mesh, wl.xs, sample, n_threads=threads, with_stats=False)
         segs += res.segments
         secs += res.seconds
         passes += 1
     one = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, 20_000)), n_threads=1, with_stats=False)
+    oracle.use_library(oracle_build.LIB)
     return {"value": segs / secs, "unit": "segments/s", "cores": threads, "kind": "oracle",
-            "sample": f"{passes} full passes over the {wl.rays.n} rays of the same workload on {threads} threads "
-                      f"(FP64 oracle, {segs} segments in {secs:.2f} s of tracing and scoring)",
+            "sample": f"{passes} passes over the first {n_slice} of the {wl.rays.n} rays of the same workload on "
+                      f"{threads} threads (FP64 oracle, gcc -O3 -march=native; {segs} segments in {secs:.2f} s of "
+                      f"tracing and scoring, setup excluded)",
+            "host": host,
             "single_thread_segments_per_s": one.segments / one.seconds}
 
 
@@ -553,8 +615,10 @@ def precision_report() -> None:
     """Per workload and form: relative error per voxel against the FP64 oracle (Eqs. 7-8).
 
     FP32 forms are compared with the oracle run on the same FP32-rounded
-    inputs (their arithmetic error) and, separately, with the oracle on the
-    FP64 inputs (what a user of FP32 inputs sees).  Gate: voxels whose oracle
+    inputs and on the planes the FP32 walk places (lo + k h in FP32: their
+    arithmetic error), with the oracle on the FP64 planes (FP32-rounded rays
+    and tables: adds the shift of the planes), and with the oracle on the FP64
+    inputs (what a user of FP32 inputs sees).  Gate: voxels whose oracle
     relative standard error is < 5% (the paper's gate); also the maximum over
     every voxel with phi > 1e-30 max(phi), and Eq. 8's max |dphi|/sigma.
     """
@@ -563,11 +627,18 @@ def precision_report() -> None:
     import paper_1706_07476_amd as vrc
     import workloads as W
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads, _ = host_cpu()
+
+    def f32_planes(mesh):
+        out = []
+        for a in range(3):
+            k = np.arange(int(mesh.n[a]) + 1, dtype=np.float32)
+            lo, h = np.float32(mesh.lo[a]), np.float32(mesh.h[a])
+            out.append((lo + (k * h).astype(np.float32)).astype(np.float32).astype(np.float64))
+        return out
 
     def f32_view(mesh, xs, rays):
-        m = W.Mesh(mesh.lo.astype(np.float32).astype(np.float64), mesh.h.astype(np.float32).astype(np.float64),
-                   mesh.n, mesh.mat)
+        m = W.RectMesh(f32_planes(mesh), mesh.mat)
         x = W.XSTables(xs.offs, xs.energy.astype(np.float32).astype(np.float64),
                        xs.sigma.astype(np.float32).astype(np.float64))
         return m, x, W.rays_to_f32(rays).as_f64()
@@ -594,14 +665,28 @@ def precision_report() -> None:
     dev = torch.device("cuda:0")
     well = W.config2_multimaterial(n_rays=1_600_000, n=16, h=0.5)
     well.mesh = W.slab_mesh(202, 16, 0.5, slab=4)  # every voxel well sampled: the 5% gate is populated
+    # the cylinder mesh with rays from a 3 cm ball around one insert: the 5% gate is populated
+    ball = W.config3_precision(n_rays=0)
+    centre, _ = ball.mesh.extra_spheres[0]
+    rng = np.random.default_rng(31)
+    n_b = 2_000_000
+    d = rng.normal(size=(n_b, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    o = centre[None, :] + d * (3.0 * rng.uniform(size=n_b) ** (1.0 / 3.0))[:, None]
+    ux, uy, uz = W.isotropic_directions(rng, n_b)
+    ball.rays = W.Rays(o[:, 0].copy(), o[:, 1].copy(), o[:, 2].copy(), ux, uy, uz,
+                       W.log_uniform_energies(rng, n_b), rng.lognormal(0.0, 0.5, n_b))
     cases = [("tiny", W.config1_tiny()), ("multimat", W.config2_multimaterial()),
-             ("multimat-16^3-well-sampled", well), ("cylinder", W.config3_precision())]
+             ("multimat-16^3-well-sampled", well), ("cylinder", W.config3_precision()),
+             ("cylinder-ball-source-2e6", ball)]
     for name, wl in cases:
         log(f"precision: {name}: oracle on FP64 inputs")
         ref64 = oracle.cast(wl.mesh, wl.xs, wl.rays, n_threads=threads)
-        log(f"precision: {name}: oracle on FP32-rounded inputs")
+        log(f"precision: {name}: oracle on FP32-rounded inputs and the FP32 planes")
         m32, x32, r32 = f32_view(wl.mesh, wl.xs, wl.rays)
         ref32 = oracle.cast(m32, x32, r32, n_threads=threads)
+        log(f"precision: {name}: oracle on FP32-rounded rays and tables, FP64 planes")
+        ref64p = oracle.cast(wl.mesh, x32, r32, n_threads=threads)
         ctx = vrc.Context(0)
         ctx.set_mesh(0, wl.mesh)
         ctx.set_xs(wl.xs)
@@ -618,6 +703,7 @@ def precision_report() -> None:
                 line["vs_oracle"] = stats(got, ref64)
             else:
                 line["vs_oracle_same_fp32_inputs"] = stats(got, ref32)
+                line["vs_oracle_fp64_planes"] = stats(got, ref64p)
                 line["vs_oracle_fp64_inputs"] = stats(got, ref64)
             print(json.dumps(line), flush=True)
         # FP32 vs FP64 voxel sequences of the same (FP32) rays, on a sample
@@ -625,11 +711,117 @@ def precision_report() -> None:
         sample = W.rays_to_f32(wl.rays.take(slice(0, k)))
         m32f = W.Mesh(wl.mesh.lo.astype(np.float32), wl.mesh.h.astype(np.float32), wl.mesh.n, wl.mesh.mat)
         o32, v32, _ = oracle.trace_many(m32f, sample, "f32")
-        o64, v64, _ = oracle.trace_many(m32, sample.as_f64(), "f64")
+        o64, v64, _ = oracle.trace_many(m32f, sample.as_f64(), "f64")
         differ = sum(1 for r in range(k) if not np.array_equal(v32[o32[r]:o32[r + 1]], v64[o64[r]:o64[r + 1]]))
         print(json.dumps({"workload": name, "sequence_check_rays": k, "rays_whose_fp32_walk_differs_from_fp64": differ}),
               flush=True)
         ctx.close()
+
+
+def load_workload(name: str, n_rays):
+    import workloads as W
+    if name == "cylinder":
+        return W.config3_precision(n_rays=n_rays or 10_000_000)
+    return W.config2_multimaterial(n_rays=n_rays or 1_000_000)
+
+
+def device_rays(wl, dt, torch):
+    npdt = np.float64 if dt == "f64" else np.float32
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=npdt)).to("cuda:0") for a in wl.rays.arrays()]
+
+
+def time_form(vrc, ctx, wl, prec, arrays, counts, stream, torch, steps) -> dict:
+    """segments/s, ms per step and the fraction of the HBM roofline of one precision form."""
+    d2 = "f64" if prec == "p64" else "f32"
+    S2 = ctx.count_segments(0, prec, arrays, counts, stream)
+    t2 = ctx.create_tally(0, prec)
+    per2, tot2, _ = time_casts(vrc, ctx, t2, arrays, steps, 2, stream, torch)
+    ctx.destroy_tally(t2)
+    return {"segments_per_s": S2 * len(per2) / (tot2 / 1e3), "ms_per_step": tot2 / len(per2),
+            "hbm_frac": (RAY_BYTES[d2] * wl.rays.n + SEG_BYTES * S2) / (float(np.mean(per2)) / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
+def other_forms(vrc, ctx, wl, skip, arrays_by_dt, counts, stream, torch, steps) -> dict:
+    out = {}
+    for p in ("p64", "p32_t64", "p32_kahan", "p32_d64"):
+        if p == skip:
+            continue
+        d2 = "f64" if p == "p64" else "f32"
+        if d2 not in arrays_by_dt:
+            arrays_by_dt[d2] = device_rays(wl, d2, torch)
+        out[p] = time_form(vrc, ctx, wl, p, arrays_by_dt[d2], counts, stream, torch, steps)
+        log(f"bench: form {p}: {out[p]['segments_per_s']:.3e} segments/s ({out[p]['ms_per_step']:.3f} ms)")
+    return out
+
+
+def accumulation_modes(vrc, ctx, prec, arrays, S, launch, stream, torch, steps) -> dict:
+    modes = {}
+    for acc in (0, 1, 3):
+        if acc == launch["accumulate"]:
+            continue
+        ctx.set_launch(accumulate=acc)
+        t3 = ctx.create_tally(0, prec)
+        per3, tot3, _ = time_casts(vrc, ctx, t3, arrays, steps, 2, stream, torch)
+        ctx.destroy_tally(t3)
+        modes[acc] = {"segments_per_s": S * len(per3) / (tot3 / 1e3), "ms_per_step": tot3 / len(per3)}
+        log(f"bench: accumulate={acc}: {modes[acc]['segments_per_s']:.3e} segments/s")
+    ctx.set_launch(**launch)
+    return modes
+
+
+def guarded(name, fn):
+    """Run an extra measurement; its failure is reported in its key, never stops the headline line."""
+    try:
+        return fn()
+    except Exception as exc:
+        log(f"bench: {name} measurement failed: {exc!r}")
+        return {"error": repr(exc)}
+
+
+def multimat_forms(vrc, torch, args) -> dict:
+    """The multimat workload (100^3, 1e6 rays): the p32_t64 form with every accumulation setting and
+    the other precision forms, then the next-event estimator, the mesh extensions and the cast from
+    host arrays on it."""
+    import workloads as W
+    log("bench: generating the multimat workload")
+    wl = W.config2_multimaterial()
+    ctx = vrc.Context(0)
+    ctx.set_mesh(0, wl.mesh)
+    ctx.set_xs(wl.xs)
+    stream = torch.cuda.current_stream()
+    arrays = device_rays(wl, "f32", torch)
+    counts = torch.empty(wl.rays.n, dtype=torch.int64, device="cuda:0")
+    launch = ctx.get_launch()
+    S = ctx.count_segments(0, "p32_t64", arrays, counts, stream)
+    tid = ctx.create_tally(0, "p32_t64")
+    per, total_ms, _ = time_casts(vrc, ctx, tid, arrays, 20, 3, stream, torch)
+    ctx.destroy_tally(tid)
+    ms = total_ms / 20
+    out = {"workload": WORKLOADS["multimat"], "rays_per_step": wl.rays.n, "segments_per_step": S,
+           "precision": "p32_t64", "ms_per_step": ms, "segments_per_s": S / (ms / 1e3),
+           "hbm_frac": (RAY_BYTES["f32"] * wl.rays.n + SEG_BYTES * S) / (float(np.mean(per)) / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))}}
+    log(f"bench: multimat p32_t64 {out['segments_per_s']:.3e} segments/s ({ms:.3f} ms)")
+    out["accumulation_modes"] = accumulation_modes(vrc, ctx, "p32_t64", arrays, S, launch, stream, torch, 5)
+    out["other_forms"] = other_forms(vrc, ctx, wl, "p32_t64", {"f32": arrays}, counts, stream, torch, 5)
+    out["next_event_form"] = guarded("next-event", lambda: bench_next_event(vrc, ctx, wl, torch, stream))
+    out["rect_form"] = guarded("rectilinear", lambda: bench_rect(vrc, ctx, wl, arrays, counts, torch, stream))
+    out["host_input_form"] = guarded("host-input", lambda: bench_host_input(vrc, ctx, wl, torch, S))
+
+    def density():
+        d = bench_density(vrc, ctx, wl, arrays, torch, stream)
+        for k in ("tile_split", "atomic"):
+            d[k]["segments_per_s"] = S / (d[k]["ms_per_step"] / 1e3)
+        return d
+    out["density_form"] = guarded("density", density)
+
+    def mixtures():
+        d = bench_mixtures(vrc, ctx, wl, arrays, torch, stream)
+        d["segments_per_s"] = S / (d["ms_per_step"] / 1e3)
+        return d
+    out["mixture_form"] = guarded("mixtures", mixtures)
+    ctx.close()
+    return out
 
 
 def main():
@@ -639,7 +831,7 @@ def main():
               "(across GPUs the path would shard the rays and replicate the tally per GPU)", file=sys.stderr)
         sys.exit(2)
     if args.write_traffic:
-        write_traffic(args.write_traffic)
+        write_traffic(args.write_traffic, args.workload, args.precision)
         return
     if args.precision_report:
         precision_report()
@@ -649,17 +841,14 @@ def main():
         return
     import torch
     import paper_1706_07476_amd as vrc
-    import workloads as W
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    log("bench: generating the multimat workload")
-    wl = W.config2_multimaterial(n_rays=args.rays)
+    log(f"bench: generating the {args.workload} workload")
+    wl = load_workload(args.workload, args.rays)
     dt = "f64" if args.precision == "p64" else "f32"
-    npdt = np.float64 if dt == "f64" else np.float32
-    dev = torch.device("cuda:0")
-    arrays = [torch.from_numpy(np.ascontiguousarray(a, dtype=npdt)).to(dev) for a in wl.rays.arrays()]
+    arrays = device_rays(wl, dt, torch)
     ctx = vrc.Context(0)
     ctx.set_mesh(0, wl.mesh)
     ctx.set_xs(wl.xs)
@@ -670,108 +859,38 @@ def main():
         ctx.set_launch(**shape)
     launch = ctx.get_launch()
     stream = torch.cuda.current_stream()
-    counts = torch.empty(wl.rays.n, dtype=torch.int64, device=dev)
+    counts = torch.empty(wl.rays.n, dtype=torch.int64, device="cuda:0")
     S = ctx.count_segments(0, args.precision, arrays, counts, stream)
     R = wl.rays.n
     tid = ctx.create_tally(0, args.precision)
     log(f"bench: {R} rays, {S} segments per step; timing {args.steps} steps after {args.warmup} warm-up")
     per, total_ms, wall = time_casts(vrc, ctx, tid, arrays, args.steps, args.warmup, stream, torch)
+    ctx.destroy_tally(tid)
     ms_step = total_ms / args.steps
     value = S * args.steps / (total_ms / 1e3)
     alg_bytes = RAY_BYTES[dt] * R + SEG_BYTES * S
     kern_s = float(np.mean(per)) / 1e3
     achieved = alg_bytes / kern_s / 1e9
-    traffic = measured_traffic(args.precision, launch)
-    modes = {}
-    if args.accumulate_modes:
-        for acc in (0, 1, 3):
-            if acc == launch["accumulate"]:
-                continue
-            ctx.set_launch(accumulate=acc)
-            t3 = ctx.create_tally(0, args.precision)
-            per3, tot3, _ = time_casts(vrc, ctx, t3, arrays, max(5, args.steps // 5), 2, stream, torch)
-            modes[acc] = {"segments_per_s": S * len(per3) / (tot3 / 1e3), "ms_per_step": tot3 / len(per3)}
-            log(f"bench: accumulate={acc}: {modes[acc]['segments_per_s']:.3e} segments/s")
-        ctx.set_launch(**launch)
-    others = {}
-    if args.other_forms:
-        for p in ("p64", "p32_t64", "p32_kahan", "p32_d64"):
-            if p == args.precision:
-                continue
-            d2 = "f64" if p == "p64" else "f32"
-            arr2 = arrays if d2 == dt else [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64 if d2 == "f64" else np.float32)).to(dev)
-                                            for a in wl.rays.arrays()]
-            S2 = ctx.count_segments(0, p, arr2, counts, stream)
-            t2 = ctx.create_tally(0, p)
-            per2, tot2, _ = time_casts(vrc, ctx, t2, arr2, max(5, args.steps // 5), 2, stream, torch)
-            others[p] = {"segments_per_s": S2 * len(per2) / (tot2 / 1e3), "ms_per_step": tot2 / len(per2),
-                         "hbm_frac": (RAY_BYTES[d2] * R + SEG_BYTES * S2) / (float(np.mean(per2)) / 1e3) / 1e9 / HBM_PEAK_GBS}
-            log(f"bench: form {p}: {others[p]['segments_per_s']:.3e} segments/s")
-    batched = None
-    if args.batched:
-        batched = bench_batched(args.batched_steps)
-        log(f"bench: batched {batched['batched_segments_per_s']:.3e} vs plain {batched['plain_segments_per_s']:.3e} "
-            "segments/s")
-    serving = None
-    if args.serving:
-        serving = bench_serving(args.serving_seconds)
-    next_event = None
-    if args.next_event:
-        try:
-            next_event = bench_next_event(vrc, ctx, wl, torch, stream)
-            log(f"bench: next-event {next_event['events_per_s']:.3e} events/s "
-                f"({next_event['pieces_per_event_sampled']:.1f} pieces per event)")
-        except Exception as exc:  # the headline line must still be printed
-            log(f"bench: next-event measurement failed: {exc!r}")
-            next_event = {"error": repr(exc)}
-    rect_form = None
-    if args.rect:
-        try:
-            rect_form = bench_rect(vrc, ctx, wl, arrays, counts, torch, stream)
-            log(f"bench: rectilinear mesh {rect_form['tile_split']['segments_per_s']:.3e} segments/s tile-split, "
-                f"{rect_form['atomic']['segments_per_s']:.3e} atomic (uniform: "
-                f"{rect_form['tile_split']['uniform_segments_per_s']:.3e}, "
-                f"{rect_form['atomic']['uniform_segments_per_s']:.3e})")
-        except Exception as exc:  # the headline line must still be printed
-            log(f"bench: rectilinear measurement failed: {exc!r}")
-            rect_form = {"error": repr(exc)}
-    host_input = None
-    if args.host_input:
-        try:
-            host_input = bench_host_input(vrc, ctx, wl, torch, S)
-            log(f"bench: from host arrays {host_input['segments_per_s']:.3e} segments/s "
-                f"({host_input['ms_per_step']:.3f} ms per cast)")
-        except Exception as exc:  # the headline line must still be printed
-            log(f"bench: host-input measurement failed: {exc!r}")
-            host_input = {"error": repr(exc)}
-    density_form = None
-    if args.rect:
-        try:
-            density_form = bench_density(vrc, ctx, wl, arrays, torch, stream)
-            for k in ("tile_split", "atomic"):
-                density_form[k]["segments_per_s"] = S / (density_form[k]["ms_per_step"] / 1e3)
-            log(f"bench: density factors {density_form['tile_split']['segments_per_s']:.3e} segments/s tile-split, "
-                f"{density_form['atomic']['segments_per_s']:.3e} atomic")
-        except Exception as exc:  # the headline line must still be printed
-            log(f"bench: density measurement failed: {exc!r}")
-            density_form = {"error": repr(exc)}
-    mixture_form = None
-    if args.rect:
-        try:
-            mixture_form = bench_mixtures(vrc, ctx, wl, arrays, torch, stream)
-            mixture_form["segments_per_s"] = S / (mixture_form["ms_per_step"] / 1e3)
-            log(f"bench: mixtures {mixture_form['segments_per_s']:.3e} segments/s "
-                f"({mixture_form['ms_per_step']:.3f} ms; plain tables {mixture_form['plain_tables_ms_per_step']:.3f} ms)")
-        except Exception as exc:  # the headline line must still be printed
-            log(f"bench: mixture measurement failed: {exc!r}")
-            mixture_form = {"error": repr(exc)}
-    fom_form = None
-    if args.fom:
-        try:
-            fom_form = bench_fom(args.fom_batches, args.fom_histories)
-        except Exception as exc:  # the headline line must still be printed
-            log(f"bench: eta measurement failed: {exc!r}")
-            fom_form = {"error": repr(exc)}
+    traffic = measured_traffic(args.precision, launch, args.workload)
+    log(f"bench: headline {value:.3e} segments/s ({ms_step:.3f} ms per step, {achieved / HBM_PEAK_GBS:.3f} of HBM peak)")
+    extra = {}
+    if args.extras:
+        steps = max(3, args.steps // 4)
+        extra["other_accumulation_modes"] = accumulation_modes(vrc, ctx, args.precision, arrays, S, launch, stream,
+                                                               torch, steps)
+        extra["other_forms"] = other_forms(vrc, ctx, wl, args.precision, {dt: arrays}, counts, stream, torch, steps)
+    ctx.close()
+    del arrays, counts
+    torch.cuda.empty_cache()
+    if args.extras:
+        if args.multimat and args.workload != "multimat":
+            extra["multimat_form"] = guarded("multimat", lambda: multimat_forms(vrc, torch, args))
+        if args.batched:
+            extra["batched_form"] = guarded("batched", lambda: bench_batched(args.batched_steps))
+        if args.serving:
+            extra["serving_form"] = guarded("serving", lambda: bench_serving(args.serving_seconds))
+        if args.fom:
+            extra["fom_form"] = guarded("eta", lambda: bench_fom(args.fom_batches, args.fom_histories))
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
@@ -790,9 +909,7 @@ def main():
         "dtype": "f32" if dt == "f32" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "multimat: 100^3 mesh of 0.5 cm voxels, 3 materials in 10-voxel z slabs, "
-                        "20k-point log-energy Sigma_t tables, 1e6 rays (uniform origins, isotropic, "
-                        "log-uniform E, lognormal w)",
+            "workload": WORKLOADS[args.workload],
             "rays_per_step": R,
             "segments_per_step": S,
             "precision": args.precision,
@@ -800,32 +917,23 @@ def main():
             "forms": {"p64": "FP64 walk, optical depth, exponentials, tally",
                       "p32_t64": "FP32 walk, optical depth, exponentials; FP64 tally",
                       "p32_kahan": "FP32 throughout; compensated FP32 tally",
-                      "p32_d64": "FP32 cross sections and walk; FP64 optical depth, exponentials, tally"},
+                      "p32_d64": "FP32 cross sections and walk; FP64 optical depth, exponentials, tally "
+                                 "(the paper's scheme, Sec. 3)"},
             "launch": launch,
         },
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
-                       "what": "per-batch kernel time of 1e6-ray batches (HIP events on the launch stream)"},
+                       "what": f"per-batch kernel time of {R}-ray batches (HIP events on the launch stream)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_ms": kern_s * 1e3,
-                     "kernels": PIPELINE[1 if launch["accumulate"] else 0]},
+                     "kernels": pipeline(args.precision, launch["accumulate"])},
         "cpu_baseline": cpu,
-        "other_accumulation_modes": modes,
-        "other_forms": others,
-        "batched_form": batched,
-        "serving_form": serving,
-        "fom_form": fom_form,
-        "next_event_form": next_event,
-        "rect_form": rect_form,
-        "density_form": density_form,
-        "host_input_form": host_input,
-        "mixture_form": mixture_form,
         "wall_s_timed": wall,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -32,12 +32,20 @@ _int = ctypes.c_int
 _ll = ctypes.c_int64
 
 
-def lib():
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (e.g. build.build_native's)."""
+    global _lib
+    _lib = None
+    lib(path)
+
+
+def lib(path: Optional[str] = None):
     global _lib
     if _lib is None:
-        path = _build.LIB
-        if not os.path.exists(path):
-            _build.build(force=True)
+        if path is None:
+            path = _build.LIB
+            if not os.path.exists(path):
+                _build.build(force=True)
         L = ctypes.CDLL(path)
         L.oracle_sigma.restype = ctypes.c_double
         L.oracle_sigma.argtypes = [_d, _d, _ll, ctypes.c_double]

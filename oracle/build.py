@@ -14,8 +14,9 @@ DEPS = SRC + [os.path.join(HERE, "trav.inc")]
 
 # -ffp-contract=off: no fused multiply-add, so the FP32/FP64 traversal is the
 # exact IEEE sequence of operations the traversal reading prescribes.
-# No -march=native: the library built here also runs on other hosts.
-CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+# No -march=native here: the library built here also runs on other hosts
+# (build_native() makes a copy for the host it runs on, for timing).
+CFLAGS = ["-std=c11", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-pthread", "-D_POSIX_C_SOURCE=200809L", "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 
@@ -31,6 +32,17 @@ def build(force: bool = True, verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_native(out_dir: str, verbose: bool = False) -> str:
+    """The same library built for the host that runs this (-march=native), into out_dir."""
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, "_vrc_oracle_native.so")
+    cmd = ["gcc", *CFLAGS, "-march=native", "-o", path, *SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return path
 
 
 if __name__ == "__main__":

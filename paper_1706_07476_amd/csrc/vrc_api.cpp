@@ -468,6 +468,7 @@ vrc_status vrc_set_xs_tables(vrc_ctx *ctx, int n_mat, const int64_t *offs, const
     VRC_HIP(ctx, hipDeviceSynchronize());
     free_xs(ctx->xs);
     ctx->xs = XsHost();
+    ++ctx->xs_gen;
     // FP64 copies
     std::vector<double> S64(static_cast<size_t>(x.K + 1) * x.s_stride64, 0.0);
     std::vector<float> S32(static_cast<size_t>(x.K + 1) * x.s_stride32, 0.f);
@@ -993,7 +994,7 @@ vrc_status vrc::run_batched(vrc_ctx *ctx, BatchedSlot &bs, const BatchedShape &s
     const int f64 = fp64 ? 1 : 0;
     if (shape.use_graph) {
         const bool stale = !bs.exec || !(bs.graph_shape == shape) || bs.graph_prec != prec || bs.graph_fp64 != f64 ||
-                           bs.graph_bytes != bs.cap;
+                           bs.graph_bytes != bs.cap || bs.graph_xs_gen != ctx->xs_gen;
         if (stale) {
             if (bs.exec) (void)hipGraphExecDestroy(bs.exec);
             if (bs.graph) (void)hipGraphDestroy(bs.graph);
@@ -1017,6 +1018,7 @@ vrc_status vrc::run_batched(vrc_ctx *ctx, BatchedSlot &bs, const BatchedShape &s
             bs.graph_prec = prec;
             bs.graph_fp64 = f64;
             bs.graph_bytes = bs.cap;
+            bs.graph_xs_gen = ctx->xs_gen;
         }
         VRC_HIP(ctx, hipGraphLaunch(bs.exec, s));
     } else {

@@ -233,6 +233,7 @@ struct BatchedSlot {
     int graph_prec = -1;
     int graph_fp64 = -1;
     size_t graph_bytes = 0;
+    uint64_t graph_xs_gen = 0;       // cross-section tables the graph's kernel arguments point at
 };
 
 struct ServeState;
@@ -254,6 +255,9 @@ struct vrc_ctx {
     std::mutex mu;
     vrc::MeshHost meshes[vrc::kMaxMeshes];
     vrc::XsHost xs;
+    // bumped by every vrc_set_xs_tables: a captured graph holds the tables' device pointers and
+    // sizes as kernel arguments, so a graph captured under another generation is stale
+    uint64_t xs_gen = 0;
     std::vector<std::unique_ptr<vrc::TallyHost>> tallies;
     vrc::LaunchShape launch;
     vrc::SortScratch sort_scratch;

@@ -187,3 +187,33 @@ def test_batched_errors(ctx, vrc):
     with pytest.raises(vrc.VrcError):
         ctx.set_batched_launch(chunk=3)
     ctx.cast_batches([])  # nothing to do
+
+
+def test_graph_recaptured_after_new_tables(ctx):
+    """The captured graph holds the cross-section tables' device pointers and sizes: after new tables
+    (another material count and grid) the next batched call must use them, not replay the old graph."""
+    wl = small_batched_workload(n_batches=30, median=400.0)
+    say("case: batched graph, tables replaced between calls")
+    meshes, _ = setup_tallies(ctx, wl, "p64")
+    ctx.set_batched_launch(use_graph=1, split=0)
+    mesh_of = wl.extra["mesh_of"]
+    arrays = [dev_arrays(b, "f64") for b in wl.extra["batches"]]
+    t_first = [ctx.create_tally(i, "p64") for i in range(len(meshes))]
+    ctx.cast_batches([(t_first[mesh_of[i]], a) for i, a in enumerate(arrays)])
+    # four materials on their own 700-point grids (the meshes use ids 0..2)
+    tabs = [(W.gen.log_energy_grid(700, 1e-11 * (1 + m), 20.0),
+             W.synthetic_sigma_table(4100 + m, 700, 0.2 + 0.1 * m, 0.1, 0.05, 50.0)) for m in range(4)]
+    xs2 = W.gen.make_xs(tabs)
+    ctx.set_xs(xs2)
+    t_second = [ctx.create_tally(i, "p64") for i in range(len(meshes))]
+    ctx.cast_batches([(t_second[mesh_of[i]], a) for i, a in enumerate(arrays)])
+    for k, m in enumerate(meshes):
+        sel = [b for i, b in enumerate(wl.extra["batches"]) if mesh_of[i] == k and b.n > 0]
+        if not sel:
+            continue
+        rays = W.Rays.concat(sel)
+        for xs, t in ((wl.xs, t_first[k]), (xs2, t_second[k])):
+            res = oracle.cast(m, xs, rays, n_threads=oracle_threads())
+            g, _, n = rel_report(ctx.read(t), res, gate="all")
+            say(f"  mesh {k}: max rel {g:.3e} over {n} voxels")
+            assert g <= 1e-12

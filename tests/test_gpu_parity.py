@@ -237,7 +237,12 @@ def test_tally_multimaterial_fp32_well_sampled(ctx, prec, accumulate):
 
 
 def test_tally_cylinder_with_void(ctx):
-    """256^3 mesh with a void outside the cylinder (Sigma = 0 limit): FP64 on 3e4 rays, FP32 on 1e6 rays."""
+    """256^3 mesh with a void outside the cylinder (Sigma = 0 limit): FP64 on 3e4 rays, FP32 on 1e6 rays.
+
+    At 1e6 rays no voxel of this mesh reaches the 5 % standard-error gate, so
+    the FP32 tally is checked by Eq. 8 (|dphi| / sigma) on voxels with some
+    statistics; the gated 1e-5 check on this geometry is in test_gpu_precision.
+    """
     wl = W.config3_precision(n_rays=30_000)
     say("case: tally p64, cylinder 256^3 with void, 3e4 rays")
     setup(ctx, wl)
@@ -254,10 +259,9 @@ def test_tally_cylinder_with_void(ctx):
     m, x, r = f32_view(wl.mesh, wl.xs, wl.rays)
     res32 = oracle.cast(m, x, r, n_threads=min(8, oracle_threads()))
     got32 = ctx.read(t32)
-    g32, a32, n32 = rel_report(got32, res32, gate="stderr")
+    _, a32, n32 = rel_report(got32, res32, gate="all")
     eps = eps_phi_max(got32, res32)
-    say(f"  FP32 max rel {g32:.3e} over {n32} gated ({a32:.3e} all); max eps_phi {eps:.3e}")
-    assert g32 <= TOL_P32
+    say(f"  FP32 max rel over all {n32} voxels {a32:.3e}; max eps_phi {eps:.3e}")
     assert eps <= 1e-2
 
 
@@ -268,21 +272,28 @@ def test_energy_bins_and_out_of_range(ctx):
     rays = wl.rays
     rays.e[:5] = edges[-1]
     rays.e[5:10] = edges[0]
-    say("case: 10-bin tally p64 + p32_t64, 40^3, 2e4 rays")
+    say("case: 10-bin tally p64, 40^3, 2e4 rays; p32_kahan, 8^3, 1.6e6 rays")
     setup(ctx, wl)
     t64 = ctx.create_tally(0, "p64", edges)
-    t32 = ctx.create_tally(0, "p32_kahan", edges)
     ctx.cast(t64, dev_arrays(rays, "f64"))
-    ctx.cast(t32, dev_arrays(rays, "f32"))
     res = oracle.cast(wl.mesh, wl.xs, rays, edges=edges, n_threads=oracle_threads())
     assert res.rays_out_of_range > 1000
     got = ctx.read(t64).reshape(10, -1)
     g, _, _ = rel_report(got, res, gate="all")
     assert g <= TOL_P64
-    m, x, r = f32_view(wl.mesh, wl.xs, rays)
+    # the compensated FP32 form on a mesh small enough for the 5 % gate to fill (1.3e5 rays per bin)
+    small = W.slab_mesh(203, 8, 0.5, slab=2)
+    rays2 = W.rays_in_box(204, small, 1_600_000)
+    rays2.e[:] = W.log_uniform_energies(np.random.default_rng(205), rays2.n, 1e-10, 10.0)
+    ctx.set_mesh(1, small)
+    t32 = ctx.create_tally(1, "p32_kahan", edges)
+    ctx.cast(t32, dev_arrays(rays2, "f32"))
+    m, x, r = f32_view(small, wl.xs, rays2)
     res32 = oracle.cast(m, x, r, edges=edges, n_threads=oracle_threads())
-    g32, _, n32 = rel_report(ctx.read(t32), res32, gate="stderr")
-    say(f"  FP32 kahan gated {g32:.3e} over {n32}")
+    assert res32.rays_out_of_range > 1000
+    g32, _, n32 = rel_report(ctx.read(t32).reshape(10, -1), res32, gate="stderr")
+    say(f"  FP32 kahan, 8^3, 1.6e6 rays: max rel {g32:.3e} over {n32} gated (bin, voxel) pairs")
+    assert n32 > 1000
     assert g32 <= TOL_P32
 
 
@@ -363,12 +374,15 @@ def test_aggregation_with_coherent_rays(ctx):
         if prec == "p64":
             g, _, _ = rel_report(got, res, gate="all")
             assert g <= TOL_P64, (agg, g)
+    # FP32: 200 points of 64 rays leave the 5 % gate empty; the two settings agree with each other to
+    # the order of the additions, and with the oracle by Eq. 8
     m, x, r = f32_view(mesh, xs, rays)
     res32 = oracle.cast(m, x, r, n_threads=oracle_threads())
-    for agg, prec, got in out:
-        if prec == "p32_kahan":
-            g, _, n32 = rel_report(got, res32, gate="stderr")
-            assert g <= TOL_P32, (agg, g)
+    k32 = [got for _, prec, got in out if prec == "p32_kahan"]
+    pos = res32.tally.reshape(-1) > 1e-30 * res32.tally.max()
+    assert np.max(np.abs(k32[0][pos] - k32[1][pos]) / res32.tally.reshape(-1)[pos]) <= 1e-6
+    for got in k32:
+        assert eps_phi_max(got, res32) <= 1e-2
 
 
 def test_single_voxel_and_long_thin_meshes(ctx):
@@ -473,10 +487,10 @@ def test_full_size_bench_workload(ctx, prec, accumulate):
     else:
         m, x, r = f32_view(wl.mesh, wl.xs, wl.rays)
         res = oracle.cast(m, x, r, n_threads=oracle_threads())
-        g, a, n = rel_report(got, res, gate="stderr")
+        # 1e6 rays on 1e6 voxels leave the 5 % gate empty: Eq. 8 on voxels with some statistics
+        _, a, n = rel_report(got, res, gate="all")
         eps = eps_phi_max(got, res)
-        say(f"  FP32: gated {n} voxels max rel {g:.3e}; all voxels {a:.3e}; max eps_phi {eps:.3e}")
-        assert g <= TOL_P32
+        say(f"  FP32: all {n} voxels max rel {a:.3e}; max eps_phi {eps:.3e}")
         assert eps <= 1e-2
     if prec == "p64":
         o_counts = oracle.count_segments(wl.mesh, wl.rays, "f64", oracle_threads())
