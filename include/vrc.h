@@ -227,6 +227,23 @@ vrc_status vrc_tally_size(vrc_ctx *ctx, int tally_id, int64_t *n_values);
  * >= n_mat in the mesh), VRC_ERR_DEVICE.                                   */
 vrc_status vrc_cast_rays(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the cast
+ * of vrc_cast_rays, with the same arguments, results and launch settings,
+ * that allocates nothing.  The scratch of the tile-split accumulation
+ * (ordered rays, per-(block, key) counts and scans, tile-entry records,
+ * partial tiles) comes from one fixed device array of VRC_NOALLOC_SCRATCH_MIB
+ * MiB that every GPU the library runs on holds until the process ends;
+ * batches whose records exceed it are cast in several sub-launches.  Device
+ * ray arrays only (on_device = 1; host arrays give VRC_ERR_INVALID, they
+ * would need pinned staging).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (several streams, threads or
+ * contexts) race and give wrong tallies, so serialise them, e.g. on one
+ * stream.  Errors as vrc_cast_rays, and VRC_ERR_INVALID when the records of
+ * a single ray on this mesh would not fit the array.                       */
+#define VRC_NOALLOC_SCRATCH_MIB 256
+vrc_status vrc_cast_rays_noalloc(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch, void *hip_stream);
+
 /* Copy the tally to host memory `out` (vrc_tally_size doubles).  Waits for
  * all casting queued on the context's streams.                              */
 vrc_status vrc_read_tally(vrc_ctx *ctx, int tally_id, double *out);

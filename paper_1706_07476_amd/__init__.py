@@ -127,6 +127,7 @@ _SIGNATURES = {
     "vrc_destroy_tally": [_P, _I],
     "vrc_tally_size": [_P, _I, _PI64],
     "vrc_cast_rays": [_P, _I, ctypes.POINTER(vrc_ray_batch), _P],
+    "vrc_cast_rays_noalloc": [_P, _I, ctypes.POINTER(vrc_ray_batch), _P],
     "vrc_read_tally": [_P, _I, _PD],
     "vrc_load_tally": [_P, _I, _PD],
     "vrc_reset_tally": [_P, _I],
@@ -358,6 +359,10 @@ def vrc_tally_size(ctx: int, tally_id: int) -> int:
 
 def vrc_cast_rays(ctx: int, tally_id: int, batch: vrc_ray_batch, stream=None) -> None:
     _check(load_library().vrc_cast_rays(ctx, tally_id, ctypes.byref(batch), _stream(stream)))
+
+
+def vrc_cast_rays_noalloc(ctx: int, tally_id: int, batch: vrc_ray_batch, stream=None) -> None:
+    _check(load_library().vrc_cast_rays_noalloc(ctx, tally_id, ctypes.byref(batch), _stream(stream)))
 
 
 def vrc_read_tally(ctx: int, tally_id: int) -> np.ndarray:
@@ -630,6 +635,10 @@ class Context:
     def cast(self, tally_id: int, arrays, stream=None) -> None:
         b = make_batch(arrays)
         vrc_cast_rays(self.handle, tally_id, b, stream)
+
+    def cast_noalloc(self, tally_id: int, arrays, stream=None) -> None:
+        """vrc_cast_rays_noalloc: the same cast with no device allocation (device arrays only)."""
+        vrc_cast_rays_noalloc(self.handle, tally_id, make_batch(arrays), stream)
 
     def read(self, tally_id: int) -> np.ndarray:
         return vrc_read_tally(self.handle, tally_id)

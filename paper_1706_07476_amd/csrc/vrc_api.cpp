@@ -294,6 +294,9 @@ vrc_status vrc_create(int device, vrc_ctx **out)
             return set_error(VRC_ERR_DEVICE, "hipEventCreate failed");
         }
     }
+    // the allocation-free cast's scratch array on this device (looked up once per device; a failure
+    // leaves only that entry point unusable, and it reports the error)
+    ctx->noalloc_init = noalloc_scratch_init(device);
     e = hipEventCreateWithFlags(&ctx->sort_scratch.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&ctx->d_mesh32, sizeof(MeshP<float>) * kMaxMeshes);
@@ -618,6 +621,36 @@ vrc_status vrc_cast_rays(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch,
     if (e == hipErrorOutOfMemory) return set_error(VRC_ERR_NOMEM, "scratch of the sorted accumulation");
     if (e != hipSuccess) return device_error(ctx, e, "cast kernel launch");
     return mark_stage_used(ctx, slot, s);
+}
+
+vrc_status vrc_cast_rays_noalloc(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *batch, void *hip_stream)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    if (vrc_status s = validate_batch(batch)) return s;
+    if (batch->n > 0 && !batch->on_device)
+        return set_error(VRC_ERR_INVALID, "vrc_cast_rays_noalloc takes device ray arrays only (on_device = 1)");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    TallyHost *t = get_tally(ctx, tally_id);
+    if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
+    if (vrc_status s = check_cast_ready(ctx, t)) return s;
+    if (batch->n == 0) return VRC_OK;
+    if (ctx->noalloc_init != hipSuccess)
+        return device_error(ctx, ctx->noalloc_init, "looking up the allocation-free cast's scratch array");
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    RaysP rays;
+    int slot = -1;
+    if (vrc_status st = stage_rays(ctx, batch, s, rays, slot)) return st;  // device arrays: pointers only
+    const MeshHost &mesh = ctx->meshes[t->mesh_id];
+    const int acc = ctx->launch.accumulate;
+    const bool split = acc != 0 && (acc != 1 || batch->n >= kSplitMinRays) && sorted_eligible(*ctx, *t, mesh);
+    hipError_t e = split ? launch_cast_sorted_noalloc(*ctx, *t, mesh, rays, batch->fp64 != 0, acc != 3, s)
+                       : launch_cast(*ctx, *t, mesh, rays, batch->fp64 != 0, s);
+    if (e == hipErrorOutOfMemory)
+        return set_error(VRC_ERR_INVALID, "the records of one ray on this mesh do not fit the allocation-free "
+                                          "cast's scratch of " + std::to_string(kNoAllocScratchBytes >> 20) + " MiB");
+    if (e != hipSuccess) return device_error(ctx, e, "allocation-free cast launch");
+    return VRC_OK;
 }
 
 vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision, int64_t n, int32_t fp64,

@@ -275,6 +275,7 @@ struct vrc_ctx {
     vrc::ServeState *serve = nullptr;  // serving loop (vrc_serve.cpp), null when stopped
     std::vector<double> walk_rec[8];  // rays recorded by the last walker run
     std::atomic<int> sticky{0};
+    hipError_t noalloc_init = hipErrorNotInitialized;  // the allocation-free cast's scratch lookup
 };
 
 namespace vrc {
@@ -323,6 +324,15 @@ hipError_t launch_cast_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &
 // batches holding n_rays rays in all), all cast into tally t.
 hipError_t launch_cast_sorted_batches(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const BatchRef *d_refs,
                                       int n_refs, int64_t n_rays, bool rays_fp64, bool atomic_flush, hipStream_t s);
+// The allocation-free cast (vrc_cast_rays_noalloc): the tile-split scratch
+// comes from one fixed device array of kNoAllocScratchBytes per GPU.
+// noalloc_scratch_init looks up that GPU's address of the array, once per
+// device, with `device` current; the launcher returns hipErrorNotInitialized
+// before that, and hipErrorOutOfMemory when not even one ray's records fit.
+constexpr size_t kNoAllocScratchBytes = size_t(VRC_NOALLOC_SCRATCH_MIB) << 20;
+hipError_t noalloc_scratch_init(int device);
+hipError_t launch_cast_sorted_noalloc(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
+                                      bool rays_fp64, bool atomic_flush, hipStream_t s);
 // Adds the batch's total segment count to *total (device).
 hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
                               bool rays_fp64, unsigned long long *total, hipStream_t s);

@@ -33,7 +33,9 @@
 // additions differs from the atomic kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "vrc_device.h"
 
@@ -1079,26 +1081,51 @@ hipError_t resident_per_cu(SortScratch &sc, const void *fn, int block, size_t ld
     return hipSuccess;
 }
 
-// The tiles pass over every resident block (so the records are dealt out to
-// all of the GPU at once), then the reduction of keys that span blocks.
+// Blocks of the tiles pass: every resident block (so the records are dealt
+// out to all of the GPU at once).
 template <typename R, typename S, int FLUSH, bool RECT, bool DENS>
-hipError_t launch_tiles(vrc_ctx &ctx, TileArgs<R> T, int tb, size_t lds, hipStream_t s)
+hipError_t tile_blocks(vrc_ctx &ctx, int tb, size_t lds, int &n_blocks)
 {
-    SortScratch &sc = ctx.sort_scratch;
     int per_cu = 0;
-    hipError_t e =
-        resident_per_cu(sc, reinterpret_cast<const void *>(&tile_kernel<R, S, FLUSH, RECT, DENS>), tb, lds, per_cu);
-    if (e != hipSuccess) return e;
-    const int n_blocks = ctx.n_cu * per_cu;
-    e = grow(sc.partial, sc.partial_cap, sizeof(double) * 2 * static_cast<size_t>(n_blocks) * kTileVoxels);
-    if (e != hipSuccess) return e;
-    T.partial = static_cast<double *>(sc.partial);
-    T.n_blocks = n_blocks;
-    hipLaunchKernelGGL((tile_kernel<R, S, FLUSH, RECT, DENS>), dim3(n_blocks), dim3(tb), lds, s, T);
-    hipLaunchKernelGGL((tile_reduce_kernel<FLUSH>), dim3(T.g.n_keys, kReduceSplit), dim3(256), 0, s, T.key_base, T.g, n_blocks,
-                       static_cast<const double *>(T.partial), T.mesh.n[0], T.mesh.n[1], T.mesh.n[2], T.nvox,
-                       T.tally);
+    hipError_t e = resident_per_cu(ctx.sort_scratch,
+                                   reinterpret_cast<const void *>(&tile_kernel<R, S, FLUSH, RECT, DENS>), tb, lds,
+                                   per_cu);
+    n_blocks = ctx.n_cu * per_cu;
+    return e;
+}
+
+// The tiles pass over T.n_blocks blocks, then the reduction of keys that span blocks.
+template <typename R, typename S, int FLUSH, bool RECT, bool DENS>
+hipError_t launch_tiles(TileArgs<R> T, int tb, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((tile_kernel<R, S, FLUSH, RECT, DENS>), dim3(T.n_blocks), dim3(tb), lds, s, T);
+    hipLaunchKernelGGL((tile_reduce_kernel<FLUSH>), dim3(T.g.n_keys, kReduceSplit), dim3(256), 0, s, T.key_base, T.g,
+                       T.n_blocks, static_cast<const double *>(T.partial), T.mesh.n[0], T.mesh.n[1], T.mesh.n[2],
+                       T.nvox, T.tally);
     return hipGetLastError();
+}
+
+// Where the tile-split accumulation takes its scratch: the context's device
+// buffers, grown on demand (base == nullptr), or consecutive slices of one
+// fixed device region of `size` bytes (the allocation-free cast).
+struct Arena {
+    unsigned char *base = nullptr;
+    size_t size = 0;
+};
+
+constexpr size_t kArenaAlign = 256;
+constexpr int64_t kArenaRows = 512;  // blocks of the counting and entries passes on an arena
+
+size_t arena_round(size_t v) { return (v + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+
+// The next `need` bytes of the arena at offset off.
+hipError_t carve(const Arena &ar, size_t &off, void *&p, size_t need)
+{
+    off = arena_round(off);
+    if (need > ar.size || off > ar.size - need) return hipErrorOutOfMemory;
+    p = ar.base + off;
+    off += need;
+    return hipSuccess;
 }
 
 template <typename R>
@@ -1112,7 +1139,7 @@ const double *plane_tables<double>(const MeshHost &m) { return m.d_pl64; }
 // carries per-voxel density factors.
 template <typename R, typename RT, typename S, bool RECT, bool DENS>
 hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
-                           const SortGeom &g, int flush, hipStream_t s)
+                           const SortGeom &g, int flush, const Arena &arena, hipStream_t s)
 {
     SortScratch &sc = ctx.sort_scratch;
     const int G = ctx.n_cu * 2;  // blocks of the ordering pass (a run of rays each)
@@ -1137,12 +1164,45 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
                                        kBlock, lds1, per_cu);
         if (e != hipSuccess) return e;
     }
-    const int64_t G_res = static_cast<int64_t>(ctx.n_cu) * per_cu;
-    int64_t group_rays = static_cast<int64_t>(kScratchBudget / (rec * static_cast<size_t>(per_ray)));
-    if (group_rays < 1) group_rays = 1;
-    if (sc.busy && sc.stream != s) {
-        hipError_t e = hipStreamWaitEvent(s, sc.done, 0);
+    // an arena holds the per-(block, key) rows of at most kArenaRows blocks (the deal works for any grid)
+    const int64_t G_res = arena.base ? std::min<int64_t>(static_cast<int64_t>(ctx.n_cu) * per_cu, kArenaRows)
+                                     : static_cast<int64_t>(ctx.n_cu) * per_cu;
+    int n_tb = 0;  // blocks of the tiles pass
+    {
+        hipError_t e;
+        if constexpr (sizeof(S) == 4) {
+            if (flush == kFlushKahan) e = tile_blocks<R, S, kFlushKahan, RECT, DENS>(ctx, tb, lds2, n_tb);
+            else e = flush == kFlushAtomic ? tile_blocks<R, S, kFlushAtomic, RECT, DENS>(ctx, tb, lds2, n_tb)
+                                           : tile_blocks<R, S, kFlushPlain, RECT, DENS>(ctx, tb, lds2, n_tb);
+        } else {
+            e = flush == kFlushAtomic ? tile_blocks<R, S, kFlushAtomic, RECT, DENS>(ctx, tb, lds2, n_tb)
+                                      : tile_blocks<R, S, kFlushPlain, RECT, DENS>(ctx, tb, lds2, n_tb);
+        }
         if (e != hipSuccess) return e;
+    }
+    const size_t rows_max = static_cast<size_t>(G > G_res ? G : G_res);
+    const size_t partial_bytes = sizeof(double) * 2 * static_cast<size_t>(n_tb) * kTileVoxels;
+    int64_t group_rays;
+    if (arena.base == nullptr) {
+        group_rays = static_cast<int64_t>(kScratchBudget / (rec * static_cast<size_t>(per_ray)));
+        hipError_t e = grow(sc.partial, sc.partial_cap, partial_bytes);
+        if (e != hipSuccess) return e;
+        if (sc.busy && sc.stream != s) {
+            e = hipStreamWaitEvent(s, sc.done, 0);
+            if (e != hipSuccess) return e;
+        }
+    } else {
+        // what every sub-launch takes whatever its ray count, then the bytes per ray
+        const size_t fixed = 2 * arena_round(sizeof(uint32_t) * rows_max * hist_keys) +
+                             2 * arena_round(sizeof(uint32_t) * (hist_keys + 1)) + arena_round(partial_bytes) +
+                             3 * kArenaAlign;
+        const size_t per_ray_bytes = rec * static_cast<size_t>(per_ray) + sizeof(RayRec<R>) + 1;
+        if (arena.size <= fixed) return hipErrorOutOfMemory;
+        group_rays = static_cast<int64_t>((arena.size - fixed) / per_ray_bytes);
+    }
+    if (group_rays < 1) {
+        if (arena.base != nullptr) return hipErrorOutOfMemory;
+        group_rays = 1;
     }
     for (int64_t r0 = 0; r0 < n_rays; r0 += group_rays) {
         const int64_t nr = n_rays - r0 < group_rays ? n_rays - r0 : group_rays;
@@ -1151,14 +1211,37 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         const int Ge = static_cast<int>(G_res < (slices + 3) / 4 ? G_res : (slices + 3) / 4);
         const int64_t cap = nr * per_ray;  // records
         const size_t rows = static_cast<size_t>(G > Ge ? G : Ge);
-        hipError_t e = grow(sc.sorted, sc.sorted_cap, rec * static_cast<size_t>(cap));
-        if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * rows * hist_keys);
-        if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * rows * hist_keys);
-        if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (hist_keys + 1));
-        if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (hist_keys + 1));
-        if (e == hipSuccess) e = grow(sc.ordered, sc.ordered_cap, sizeof(RayRec<R>) * static_cast<size_t>(nr));
-        if (e == hipSuccess) e = grow(sc.bucket, sc.bucket_cap, static_cast<size_t>(nr));
-        if (e != hipSuccess) return e;
+        void *b_sorted, *b_hist, *b_row_off, *b_key_tot, *b_key_base, *b_ordered, *b_bucket, *b_partial;
+        hipError_t e = hipSuccess;
+        if (arena.base == nullptr) {
+            e = grow(sc.sorted, sc.sorted_cap, rec * static_cast<size_t>(cap));
+            if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * rows * hist_keys);
+            if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * rows * hist_keys);
+            if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (hist_keys + 1));
+            if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (hist_keys + 1));
+            if (e == hipSuccess) e = grow(sc.ordered, sc.ordered_cap, sizeof(RayRec<R>) * static_cast<size_t>(nr));
+            if (e == hipSuccess) e = grow(sc.bucket, sc.bucket_cap, static_cast<size_t>(nr));
+            if (e != hipSuccess) return e;
+            b_sorted = sc.sorted;
+            b_hist = sc.hist;
+            b_row_off = sc.row_off;
+            b_key_tot = sc.key_tot;
+            b_key_base = sc.key_base;
+            b_ordered = sc.ordered;
+            b_bucket = sc.bucket;
+            b_partial = sc.partial;
+        } else {
+            size_t off = 0;
+            e = carve(arena, off, b_hist, sizeof(uint32_t) * rows * hist_keys);
+            if (e == hipSuccess) e = carve(arena, off, b_row_off, sizeof(uint32_t) * rows * hist_keys);
+            if (e == hipSuccess) e = carve(arena, off, b_key_tot, sizeof(uint32_t) * (hist_keys + 1));
+            if (e == hipSuccess) e = carve(arena, off, b_key_base, sizeof(uint32_t) * (hist_keys + 1));
+            if (e == hipSuccess) e = carve(arena, off, b_partial, partial_bytes);
+            if (e == hipSuccess) e = carve(arena, off, b_ordered, sizeof(RayRec<R>) * static_cast<size_t>(nr));
+            if (e == hipSuccess) e = carve(arena, off, b_bucket, static_cast<size_t>(nr));
+            if (e == hipSuccess) e = carve(arena, off, b_sorted, rec * static_cast<size_t>(cap));
+            if (e != hipSuccess) return e;
+        }
         MeshP<R> mesh;
         for (int a = 0; a < 3; ++a) {
             mesh.lo[a] = static_cast<R>(m.lo[a]);
@@ -1197,52 +1280,54 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         A.tally = TallyP{t.d_data, t.d_edges, t.nvox, t.n_bins};
         A.hash_in_lds = 0;
         A.g = g;
-        A.ordered = sc.ordered;
-        A.hist = static_cast<uint32_t *>(sc.hist);
-        A.row_off = static_cast<const uint32_t *>(sc.row_off);
-        A.key_base = static_cast<const uint32_t *>(sc.key_base);
-        A.sorted = sc.sorted;
+        A.ordered = b_ordered;
+        A.hist = static_cast<uint32_t *>(b_hist);
+        A.row_off = static_cast<const uint32_t *>(b_row_off);
+        A.key_base = static_cast<const uint32_t *>(b_key_base);
+        A.sorted = b_sorted;
         A.cap = cap;
-        uint32_t *hist = static_cast<uint32_t *>(sc.hist);
-        uint32_t *row_off = static_cast<uint32_t *>(sc.row_off);
-        uint32_t *key_tot = static_cast<uint32_t *>(sc.key_tot);
-        uint32_t *key_base = static_cast<uint32_t *>(sc.key_base);
+        uint32_t *hist = static_cast<uint32_t *>(b_hist);
+        uint32_t *row_off = static_cast<uint32_t *>(b_row_off);
+        uint32_t *key_tot = static_cast<uint32_t *>(b_key_tot);
+        uint32_t *key_base = static_cast<uint32_t *>(b_key_base);
         hipLaunchKernelGGL((order_hist_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, mesh, sub, nr, rays_block, shift,
-                           static_cast<uint8_t *>(sc.bucket), hist);
+                           static_cast<uint8_t *>(b_bucket), hist);
         hipLaunchKernelGGL(scan_rows_kernel, dim3(kBucketsE / 64), dim3(64 * kScanWaves), 0, s, hist, G, kBucketsE,
                            row_off, key_tot);
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, key_tot, kBucketsE, key_base);
         hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, sub, nr,
-                           static_cast<const uint8_t *>(sc.bucket), rays_block, row_off, key_base,
-                           static_cast<RayRec<R> *>(sc.ordered));
+                           static_cast<const uint8_t *>(b_bucket), rays_block, row_off, key_base,
+                           static_cast<RayRec<R> *>(b_ordered));
         hipLaunchKernelGGL((count_entries_kernel<R, RECT>), dim3(Ge), dim3(kBlock), 0, s, A);
         hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
-                           static_cast<const uint32_t *>(sc.hist), Ge, g.n_keys, static_cast<uint32_t *>(sc.row_off),
-                           static_cast<uint32_t *>(sc.key_tot));
-        hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(sc.key_tot),
-                           g.n_keys, static_cast<uint32_t *>(sc.key_base));
+                           static_cast<const uint32_t *>(hist), Ge, g.n_keys, row_off, key_tot);
+        hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
+                           g.n_keys, key_base);
         hipLaunchKernelGGL((entries_kernel<R, RT, S, RECT, DENS>), dim3(Ge), dim3(kBlock), lds1, s, A);
         TileArgs<R> T;
         T.mesh = mesh;
         T.xs = A.xs;
         T.hash_in_lds = 0;
         T.g = g;
-        T.sorted = sc.sorted;
-        T.key_base = static_cast<const uint32_t *>(sc.key_base);
+        T.sorted = b_sorted;
+        T.key_base = static_cast<const uint32_t *>(b_key_base);
         T.nvox = t.nvox;
         T.tally = t.d_data;
+        T.partial = static_cast<double *>(b_partial);
+        T.n_blocks = n_tb;
         if constexpr (sizeof(S) == 4) {
             if (flush == kFlushKahan) {
-                e = launch_tiles<R, S, kFlushKahan, RECT, DENS>(ctx, T, tb, lds2, s);
+                e = launch_tiles<R, S, kFlushKahan, RECT, DENS>(T, tb, lds2, s);
                 goto launched;
             }
         }
-        e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic, RECT, DENS>(ctx, T, tb, lds2, s)
-                                  : launch_tiles<R, S, kFlushPlain, RECT, DENS>(ctx, T, tb, lds2, s);
+        e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic, RECT, DENS>(T, tb, lds2, s)
+                                  : launch_tiles<R, S, kFlushPlain, RECT, DENS>(T, tb, lds2, s);
     launched:
         if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (arena.base != nullptr) return hipSuccess;  // the context's buffers were not used
     hipError_t e = hipEventRecord(sc.done, s);
     if (e != hipSuccess) return e;
     sc.busy = true;
@@ -1252,13 +1337,13 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
 
 template <typename R, typename RT, typename S>
 hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n_rays,
-                      const SortGeom &g, int flush, hipStream_t s)
+                      const SortGeom &g, int flush, const Arena &ar, hipStream_t s)
 {
     if (m.dens)
-        return m.rect ? run_sorted_kind<R, RT, S, true, true>(ctx, t, m, src, n_rays, g, flush, s)
-                      : run_sorted_kind<R, RT, S, false, true>(ctx, t, m, src, n_rays, g, flush, s);
-    return m.rect ? run_sorted_kind<R, RT, S, true, false>(ctx, t, m, src, n_rays, g, flush, s)
-                  : run_sorted_kind<R, RT, S, false, false>(ctx, t, m, src, n_rays, g, flush, s);
+        return m.rect ? run_sorted_kind<R, RT, S, true, true>(ctx, t, m, src, n_rays, g, flush, ar, s)
+                      : run_sorted_kind<R, RT, S, false, true>(ctx, t, m, src, n_rays, g, flush, ar, s);
+    return m.rect ? run_sorted_kind<R, RT, S, true, false>(ctx, t, m, src, n_rays, g, flush, ar, s)
+                  : run_sorted_kind<R, RT, S, false, false>(ctx, t, m, src, n_rays, g, flush, ar, s);
 }
 
 }  // namespace
@@ -1275,7 +1360,7 @@ bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m)
 namespace {
 
 hipError_t dispatch_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaySrc &src, int64_t n,
-                           bool rays_fp64, bool atomic_flush, hipStream_t s)
+                           bool rays_fp64, bool atomic_flush, const Arena &ar, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const SortGeom g = geometry(t, m);
@@ -1283,17 +1368,17 @@ hipError_t dispatch_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     const int flush = atomic_flush ? kFlushAtomic : kFlushPlain;
     switch (t.prec) {
     case VRC_P64:
-        return rays_fp64 ? run_sorted<double, double, double>(ctx, t, m, src, n, g, flush, s)
-                         : run_sorted<double, float, double>(ctx, t, m, src, n, g, flush, s);
+        return rays_fp64 ? run_sorted<double, double, double>(ctx, t, m, src, n, g, flush, ar, s)
+                         : run_sorted<double, float, double>(ctx, t, m, src, n, g, flush, ar, s);
     case VRC_P32_T64:
-        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, src, n, g, flush, s)
-                         : run_sorted<float, float, float>(ctx, t, m, src, n, g, flush, s);
+        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, src, n, g, flush, ar, s)
+                         : run_sorted<float, float, float>(ctx, t, m, src, n, g, flush, ar, s);
     case VRC_P32_KAHAN:
-        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, src, n, g, kFlushKahan, s)
-                         : run_sorted<float, float, float>(ctx, t, m, src, n, g, kFlushKahan, s);
+        return rays_fp64 ? run_sorted<float, double, float>(ctx, t, m, src, n, g, kFlushKahan, ar, s)
+                         : run_sorted<float, float, float>(ctx, t, m, src, n, g, kFlushKahan, ar, s);
     case VRC_P32_D64:
-        return rays_fp64 ? run_sorted<float, double, double>(ctx, t, m, src, n, g, flush, s)
-                         : run_sorted<float, float, double>(ctx, t, m, src, n, g, flush, s);
+        return rays_fp64 ? run_sorted<float, double, double>(ctx, t, m, src, n, g, flush, ar, s)
+                         : run_sorted<float, float, double>(ctx, t, m, src, n, g, flush, ar, s);
     default:
         return hipErrorInvalidValue;
     }
@@ -1384,7 +1469,59 @@ hipError_t launch_cast_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &
                               bool atomic_flush, hipStream_t s)
 {
     const RaySrc src{rays, nullptr, 0, 0};
-    return dispatch_sorted(ctx, t, m, src, rays.n, rays_fp64, atomic_flush, s);
+    return dispatch_sorted(ctx, t, m, src, rays.n, rays_fp64, atomic_flush, Arena{}, s);
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free cast: the tile-split scratch in one fixed device array.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Each GPU the library runs on holds its own copy of this array until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: host code uses the address hipGetSymbolAddress returns for
+// the current device (noalloc_scratch_init), and kernels take that address as
+// an argument.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device] != nullptr) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (ptr == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+hipError_t launch_cast_sorted_noalloc(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
+                                      bool rays_fp64, bool atomic_flush, hipStream_t s)
+{
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (ctx.device >= 0 && ctx.device < kMaxDevices) ptr = g_scratch_ptr[ctx.device];
+    }
+    if (ptr == nullptr) return hipErrorNotInitialized;
+    Arena ar;
+    ar.base = static_cast<unsigned char *>(ptr);
+    ar.size = kNoAllocScratchBytes;
+    const RaySrc src{rays, nullptr, 0, 0};
+    return dispatch_sorted(ctx, t, m, src, rays.n, rays_fp64, atomic_flush, ar, s);
 }
 
 hipError_t launch_cast_sorted_batches(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const BatchRef *d_refs,
@@ -1394,7 +1531,7 @@ hipError_t launch_cast_sorted_batches(vrc_ctx &ctx, const TallyHost &t, const Me
     src.refs = d_refs;
     src.n_refs = n_refs;
     src.first = 0;
-    return dispatch_sorted(ctx, t, m, src, n_rays, rays_fp64, atomic_flush, s);
+    return dispatch_sorted(ctx, t, m, src, n_rays, rays_fp64, atomic_flush, Arena{}, s);
 }
 
 }  // namespace vrc
