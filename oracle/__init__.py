@@ -68,6 +68,26 @@ def lib(path: Optional[str] = None):
         L.oracle_count_many.restype = _ll
         L.oracle_count_many.argtypes = [_int, ctypes.c_void_p, ctypes.c_void_p, _i32, _ll] + [ctypes.c_void_p] * 6 + [
             _int, _i64]
+        L.oracle_trace_rz_f64.restype = _ll
+        L.oracle_trace_rz_f64.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, _d, ctypes.c_int32, _d,
+                                          _d, _d, _ll, _i64, _d, _d]
+        L.oracle_trace_rz_f32.restype = _ll
+        L.oracle_trace_rz_f32.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_int32, _f, ctypes.c_int32, _f,
+                                          _f, _f, _ll, _i64, _f, _f]
+        L.oracle_trace_rz_many_f64.restype = _ll
+        L.oracle_trace_rz_many_f64.argtypes = ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, _d, ctypes.c_int32,
+                                                _d, _ll] + [_d] * 6 + [_ll, _i64, _i64, _d])
+        L.oracle_trace_rz_many_f32.restype = _ll
+        L.oracle_trace_rz_many_f32.argtypes = ([ctypes.c_float, ctypes.c_float, ctypes.c_int32, _f, ctypes.c_int32,
+                                                _f, _ll] + [_f] * 6 + [_ll, _i64, _i64, _f])
+        L.oracle_cast_rz.restype = _int
+        L.oracle_cast_rz.argtypes = ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, _d, ctypes.c_int32, _d, _u8,
+                                      _int, _i64, _d, _d, _int, _d, _d, _ll] + [_d] * 8 +
+                                     [_int, _d, _d, _i64, _i64, _d])
+        L.oracle_ray_scores_rz.restype = _ll
+        L.oracle_ray_scores_rz.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, _d, ctypes.c_int32, _d,
+                                           _u8, _int, _i64, _d, _d, _int, _d, _d, _d, _d, ctypes.c_double,
+                                           ctypes.c_double, _ll, _i64, _d, _d, ctypes.POINTER(ctypes.c_int)]
         L.oracle_cast.restype = _int
         L.oracle_cast.argtypes = ([_d, _d, _i32, _u8, _int, _i64, _d, _d, _int, _d, _d, _int, _i64, _i32, _d, _ll]
                                   + [_d] * 8 + [_int, _d, _d, _i64, _i64, _d])
@@ -87,6 +107,17 @@ def _geom(mesh, dtype):
     if hasattr(mesh, "planes"):
         return _c(np.concatenate([np.asarray(p, np.float64) for p in mesh.planes]), dtype), None
     return _c(mesh.lo, dtype), _c(mesh.h, dtype)
+
+
+def _is_rz(mesh) -> bool:
+    return hasattr(mesh, "radii")
+
+
+def _rz_geom(mesh, dtype):
+    """(cx, cy, nr, radii, nz, zpl) of an R-Z mesh in the given precision."""
+    ct = float if dtype == np.float64 else (lambda v: ctypes.c_float(float(np.float32(v))))
+    return (ct(mesh.centre[0]), ct(mesh.centre[1]), int(mesh.nr), _c(mesh.radii, dtype), int(mesh.nz),
+            _c(mesh.zpl, dtype))
 
 
 def _addr(a) -> int:
@@ -133,8 +164,26 @@ def _cap(mesh) -> int:
     return int(mesh.n[0]) + int(mesh.n[1]) + int(mesh.n[2]) + 3
 
 
+def _cap_rz(mesh) -> int:
+    return 2 * int(mesh.nr) + int(mesh.nz) + 2
+
+
 def trace(mesh, o, u, precision: str = "f64"):
-    """Voxels crossed by one ray and the length in each; returns (vox, len, (t_enter, t_exit))."""
+    """Voxels (cells) crossed by one ray and the length in each; returns (vox, len, (t_enter, t_exit))."""
+    if _is_rz(mesh):
+        cap = _cap_rz(mesh)
+        vox = np.empty(cap, np.int64)
+        dt, ct = (np.float64, _d) if precision == "f64" else (np.float32, _f)
+        cx, cy, nr, radii, nz, zpl = _rz_geom(mesh, dt)
+        oo, uu = _c(o, dt), _c(u, dt)
+        ln = np.empty(cap, dt)
+        span = np.empty(2, dt)
+        fn = lib().oracle_trace_rz_f64 if precision == "f64" else lib().oracle_trace_rz_f32
+        k = fn(cx, cy, nr, _p(radii, ct), nz, _p(zpl, ct), _p(oo, ct), _p(uu, ct), cap, _p(vox, _i64),
+               _p(ln, ct), _p(span, ct))
+        if k < 0:
+            raise RuntimeError("oracle trace failed")
+        return vox[:k].copy(), ln[:k].copy(), (span[0], span[1])
     cap = _cap(mesh)
     n = _c(mesh.n, np.int32)
     vox = np.empty(cap, np.int64)
@@ -162,18 +211,23 @@ def trace(mesh, o, u, precision: str = "f64"):
 def trace_many(mesh, rays, precision: str = "f64"):
     """CSR traces of a ray batch: (offs[n+1], vox, len) in the given traversal precision."""
     dt, ct = (np.float64, _d) if precision == "f64" else (np.float32, _f)
-    fn = lib().oracle_trace_many_f64 if precision == "f64" else lib().oracle_trace_many_f32
-    lo, h = _geom(mesh, dt)
-    n = _c(mesh.n, np.int32)
     arrs = [_c(getattr(rays, f), dt) for f in ("ox", "oy", "oz", "ux", "uy", "uz")]
     nr = arrs[0].size
+    if _is_rz(mesh):
+        fn = lib().oracle_trace_rz_many_f64 if precision == "f64" else lib().oracle_trace_rz_many_f32
+        cx, cy, nrr, radii, nz, zpl = _rz_geom(mesh, dt)
+        head = (cx, cy, nrr, _p(radii, ct), nz, _p(zpl, ct))
+    else:
+        fn = lib().oracle_trace_many_f64 if precision == "f64" else lib().oracle_trace_many_f32
+        lo, h = _geom(mesh, dt)
+        n = _c(mesh.n, np.int32)
+        head = (_p(lo, ct), _p(h, ct), _p(n, _i32))
     cap = max(16, nr * 8)
     while True:
         offs = np.empty(nr + 1, np.int64)
         vox = np.empty(cap, np.int64)
         ln = np.empty(cap, dt)
-        k = fn(_p(lo, ct), _p(h, ct), _p(n, _i32), nr, *[_p(a, ct) for a in arrs], cap,
-               _p(offs, _i64), _p(vox, _i64), _p(ln, ct))
+        k = fn(*head, nr, *[_p(a, ct) for a in arrs], cap, _p(offs, _i64), _p(vox, _i64), _p(ln, ct))
         if k == -2:
             cap *= 4
             continue
@@ -184,6 +238,9 @@ def trace_many(mesh, rays, precision: str = "f64"):
 
 def count_segments(mesh, rays, precision: str = "f64", n_threads: int = 1) -> np.ndarray:
     """Number of positive-length segments of every ray, in FP64 or FP32 traversal."""
+    if _is_rz(mesh):
+        offs, _, _ = trace_many(mesh, rays, precision)
+        return np.diff(offs)
     dt = np.float64 if precision == "f64" else np.float32
     lo, h = _geom(mesh, dt)
     n = _c(mesh.n, np.int32)
@@ -206,7 +263,7 @@ def _density(mesh):
     if rho is None:
         return None
     rho = _c(rho, np.float64)
-    if rho.size != int(np.prod(np.asarray(mesh.n, np.int64))):
+    if rho.size != int(mesh.n_voxels):
         raise ValueError("one density factor per voxel is needed")
     return rho
 
@@ -224,6 +281,28 @@ def ray_scores(mesh, xs, o, u, E, w, edges=None, mix=None):
 
     The voxel's Sigma is its material's (a table of xs, or with mix a mixture
     of them) times the mesh's density factor when it has one."""
+    if _is_rz(mesh):
+        if mix is not None:
+            raise ValueError("mixtures are not taken on R-Z meshes")
+        cap = _cap_rz(mesh)
+        cx, cy, nr, radii, nz, zpl = _rz_geom(mesh, np.float64)
+        mat = _c(mesh.mat, np.uint8)
+        offs, en, sg = _c(xs.offs, np.int64), _c(xs.energy, np.float64), _c(xs.sigma, np.float64)
+        ed = None if edges is None else _c(edges, np.float64)
+        nb = 1 if edges is None else ed.size - 1
+        oo, uu = _c(o, np.float64), _c(u, np.float64)
+        vox = np.empty(cap, np.int64)
+        ln = np.empty(cap, np.float64)
+        sc = np.empty(cap, np.float64)
+        b = ctypes.c_int(0)
+        rho = _density(mesh)
+        k = lib().oracle_ray_scores_rz(cx, cy, nr, _p(radii, _d), nz, _p(zpl, _d), _p(mat, _u8), xs.n_mat,
+                                       _p(offs, _i64), _p(en, _d), _p(sg, _d), nb, _p(ed, _d), _p(rho, _d),
+                                       _p(oo, _d), _p(uu, _d), float(E), float(w), cap, _p(vox, _i64), _p(ln, _d),
+                                       _p(sc, _d), ctypes.byref(b))
+        if k < 0:
+            raise RuntimeError("oracle ray_scores failed")
+        return vox[:k].copy(), ln[:k].copy(), sc[:k].copy(), b.value
     cap = _cap(mesh)
     lo, h = _geom(mesh, np.float64)
     n = _c(mesh.n, np.int32)
@@ -274,14 +353,15 @@ def cast(mesh, xs, rays, edges=None, n_threads: int = 1, with_stats: bool = True
     """Tally of a whole ray batch, FP64; shape (n_bins, n_voxels).
 
     Voxel Sigma as in ray_scores (density factors of the mesh, mixtures mix)."""
-    lo, h = _geom(mesh, np.float64)
-    n = _c(mesh.n, np.int32)
+    rz = _is_rz(mesh)
+    if rz and mix is not None:
+        raise ValueError("mixtures are not taken on R-Z meshes")
     mat = _c(mesh.mat, np.uint8)
     offs, en, sg = _c(xs.offs, np.int64), _c(xs.energy, np.float64), _c(xs.sigma, np.float64)
     ed = None if edges is None else _c(edges, np.float64)
     nb = 1 if edges is None else ed.size - 1
     arrs = [_c(a, np.float64) for a in rays.arrays()]
-    nvox = int(np.prod(mesh.n.astype(np.int64)))
+    nvox = int(mesh.n_voxels)
     tally = np.empty((nb, nvox), np.float64)
     sq = np.empty((nb, nvox), np.float64) if with_stats else None
     cnt = np.empty((nb, nvox), np.int64) if with_stats else None
@@ -289,11 +369,20 @@ def cast(mesh, xs, rays, edges=None, n_threads: int = 1, with_stats: bool = True
     secs = ctypes.c_double(0.0)
     rho = _density(mesh)
     nm, mo, mc, mf = _mixtures(mix)
-    rc = lib().oracle_cast(_p(lo, _d), _p(h, _d), _p(n, _i32), _p(mat, _u8), xs.n_mat, _p(offs, _i64),
-                           _p(en, _d), _p(sg, _d), nb, _p(ed, _d), _p(rho, _d), nm, _p(mo, _i64), _p(mc, _i32),
-                           _p(mf, _d), arrs[0].size, *[_p(a, _d) for a in arrs],
-                           int(n_threads), _p(tally, _d), _p(sq, _d), _p(cnt, _i64), _p(stats, _i64),
-                           ctypes.byref(secs))
+    if rz:
+        cx, cy, nr, radii, nz, zpl = _rz_geom(mesh, np.float64)
+        rc = lib().oracle_cast_rz(cx, cy, nr, _p(radii, _d), nz, _p(zpl, _d), _p(mat, _u8), xs.n_mat,
+                                  _p(offs, _i64), _p(en, _d), _p(sg, _d), nb, _p(ed, _d), _p(rho, _d), arrs[0].size,
+                                  *[_p(a, _d) for a in arrs], int(n_threads), _p(tally, _d), _p(sq, _d),
+                                  _p(cnt, _i64), _p(stats, _i64), ctypes.byref(secs))
+    else:
+        lo, h = _geom(mesh, np.float64)
+        n = _c(mesh.n, np.int32)
+        rc = lib().oracle_cast(_p(lo, _d), _p(h, _d), _p(n, _i32), _p(mat, _u8), xs.n_mat, _p(offs, _i64),
+                               _p(en, _d), _p(sg, _d), nb, _p(ed, _d), _p(rho, _d), nm, _p(mo, _i64), _p(mc, _i32),
+                               _p(mf, _d), arrs[0].size, *[_p(a, _d) for a in arrs],
+                               int(n_threads), _p(tally, _d), _p(sq, _d), _p(cnt, _i64), _p(stats, _i64),
+                               ctypes.byref(secs))
     if rc != 0:
         raise RuntimeError(f"oracle cast failed ({rc})")
     return CastResult(tally, sq, cnt, stats, secs.value, arrs[0].size)

@@ -17,8 +17,9 @@
  *     up on its own table and the terms added in component order; and
  *     optionally every voxel carries a density factor, the cell's
  *     Sigma_t,i(E) of Eqs. 1-4 then being rho_i * Sigma_m(E).
- *  2. Trace the ray through the mesh (Sec. 3; trav.inc): the voxels crossed,
- *     in order, with the length in each.
+ *  2. Trace the ray through the mesh (Sec. 3; trav.inc for a Cartesian
+ *     mesh, trav_rz.inc for an R-Z one, Sec. 6.3): the cells crossed, in
+ *     order, with the length in each.
  *  3. Score every crossed voxel i by the VRC estimator (Eq. 4, i.e. the
  *     expected-value estimator of Eq. 1 with the entering weight of Eq. 2):
  *        W_i = w * exp(-tau_in)                       (Eq. 2)
@@ -65,6 +66,18 @@
 #include "trav.inc"
 #undef REAL
 #undef TRAV_NAME
+
+#define REAL double
+#define TRZ_NAME(x) x##_rz64
+#include "trav_rz.inc"
+#undef REAL
+#undef TRZ_NAME
+
+#define REAL float
+#define TRZ_NAME(x) x##_rz32
+#include "trav_rz.inc"
+#undef REAL
+#undef TRZ_NAME
 
 /* ------------------------------------------------------------------------ */
 /* step 1: Sigma_t(E) by table lookup (Sec. 3)                               */
@@ -195,6 +208,76 @@ int64_t oracle_trace_many_f64(const double *lo, const double *h, const int32_t *
     return total;
 }
 
+/* R-Z meshes (trav_rz.inc): one ray, and many rays as CSR (offs has
+ * n_rays+1 entries; returns the total, -1 inconsistency, -2 cap too small) */
+int64_t oracle_trace_rz_f64(double cx, double cy, int32_t nr, const double *radii, int32_t nz, const double *zpl,
+                            const double *o, const double *u, int64_t cap, int64_t *cell, double *len, double *span)
+{
+    rz_event_rz64 *ws = (rz_event_rz64 *)malloc(sizeof(rz_event_rz64) * (size_t)(2 * nr + nz + 2));
+    if (!ws) return -1;
+    int64_t r = trace_rz_ws_rz64(cx, cy, nr, radii, nz, zpl, o, u, cap, cell, len, span, ws);
+    free(ws);
+    return r;
+}
+
+int64_t oracle_trace_rz_f32(float cx, float cy, int32_t nr, const float *radii, int32_t nz, const float *zpl,
+                            const float *o, const float *u, int64_t cap, int64_t *cell, float *len, float *span)
+{
+    rz_event_rz32 *ws = (rz_event_rz32 *)malloc(sizeof(rz_event_rz32) * (size_t)(2 * nr + nz + 2));
+    if (!ws) return -1;
+    int64_t r = trace_rz_ws_rz32(cx, cy, nr, radii, nz, zpl, o, u, cap, cell, len, span, ws);
+    free(ws);
+    return r;
+}
+
+int64_t oracle_trace_rz_many_f64(double cx, double cy, int32_t nr, const double *radii, int32_t nz,
+                                 const double *zpl, int64_t n_rays, const double *ox, const double *oy,
+                                 const double *oz, const double *ux, const double *uy, const double *uz,
+                                 int64_t cap, int64_t *offs, int64_t *cell, double *len)
+{
+    rz_event_rz64 *ws = (rz_event_rz64 *)malloc(sizeof(rz_event_rz64) * (size_t)(2 * nr + nz + 2));
+    if (!ws) return -1;
+    int64_t total = 0;
+    offs[0] = 0;
+    for (int64_t r = 0; r < n_rays; ++r) {
+        double o[3] = {ox[r], oy[r], oz[r]};
+        double u[3] = {ux[r], uy[r], uz[r]};
+        int64_t room = cap - total;
+        if (room < 0) room = 0;
+        int64_t k = trace_rz_ws_rz64(cx, cy, nr, radii, nz, zpl, o, u, room, cell + total, len + total, NULL, ws);
+        if (k < 0) { free(ws); return -1; }
+        if (k > room) { free(ws); return -2; }
+        total += k;
+        offs[r + 1] = total;
+    }
+    free(ws);
+    return total;
+}
+
+int64_t oracle_trace_rz_many_f32(float cx, float cy, int32_t nr, const float *radii, int32_t nz,
+                                 const float *zpl, int64_t n_rays, const float *ox, const float *oy,
+                                 const float *oz, const float *ux, const float *uy, const float *uz,
+                                 int64_t cap, int64_t *offs, int64_t *cell, float *len)
+{
+    rz_event_rz32 *ws = (rz_event_rz32 *)malloc(sizeof(rz_event_rz32) * (size_t)(2 * nr + nz + 2));
+    if (!ws) return -1;
+    int64_t total = 0;
+    offs[0] = 0;
+    for (int64_t r = 0; r < n_rays; ++r) {
+        float o[3] = {ox[r], oy[r], oz[r]};
+        float u[3] = {ux[r], uy[r], uz[r]};
+        int64_t room = cap - total;
+        if (room < 0) room = 0;
+        int64_t k = trace_rz_ws_rz32(cx, cy, nr, radii, nz, zpl, o, u, room, cell + total, len + total, NULL, ws);
+        if (k < 0) { free(ws); return -1; }
+        if (k > room) { free(ws); return -2; }
+        total += k;
+        offs[r + 1] = total;
+    }
+    free(ws);
+    return total;
+}
+
 /* per-ray segment counts of a batch in FP32 (fp64 = 0; float inputs) or FP64
  * (fp64 = 1; double inputs) traversal, on n_threads threads; returns the
  * total, or -1 on an internal inconsistency */
@@ -283,7 +366,33 @@ typedef struct {
     const int64_t *mix_offs; /* mixture k: components mix_comp[mix_offs[k] .. mix_offs[k+1]) */
     const int32_t *mix_comp;
     const double *mix_frac;
+    /* R-Z mesh instead of the Cartesian one (rz = 1): axis through (cx, cy),
+     * radii[nr + 1] from 0, z planes zpl[nzz + 1]; cell i + nr k */
+    int rz;
+    double cx, cy;
+    int32_t nr, nzz;
+    const double *radii, *zpl;
 } problem;
+
+static int64_t problem_cells(const problem *p)
+{
+    return p->rz ? (int64_t)p->nr * p->nzz : (int64_t)p->n[0] * p->n[1] * p->n[2];
+}
+
+static int64_t problem_cap(const problem *p)
+{
+    return p->rz ? 2 * (int64_t)p->nr + p->nzz + 2 : (int64_t)p->n[0] + p->n[1] + p->n[2] + 3;
+}
+
+/* the ray's cells and lengths, by the problem's geometry (ws: problem_cap events of either kind) */
+static int64_t problem_trace(const problem *p, const double *o, const double *u, int64_t cap, int64_t *vox,
+                             double *len, void *ws)
+{
+    if (p->rz)
+        return trace_rz_ws_rz64(p->cx, p->cy, p->nr, p->radii, p->nzz, p->zpl, o, u, cap, vox, len, NULL,
+                                (rz_event_rz64 *)ws);
+    return trace_ws_f64(p->lo, p->h, p->n, o, u, cap, vox, len, NULL, (event_f64 *)ws);
+}
 
 /* Sigma of every material id at energy E into sig (n_mat tables, or n_mix
  * mixtures of them); the number of table lookups outside a table is added to
@@ -358,7 +467,8 @@ int64_t oracle_ray_scores(const double *lo, const double *h, const int32_t *n, c
                           const double *o, const double *u, double E, double w,
                           int64_t cap, int64_t *vox, double *len, double *score, int *bin_out)
 {
-    problem p = {lo, h, n, mat, n_mat, offs, energy, sigma, n_bins, edges, rho, n_mix, mix_offs, mix_comp, mix_frac};
+    problem p = {lo, h, n, mat, n_mat, offs, energy, sigma, n_bins, edges, rho, n_mix, mix_offs, mix_comp, mix_frac,
+                 0, 0.0, 0.0, 0, 0, NULL, NULL};
     double sig[256];
     if (material_sigmas(&p, E, sig, NULL) < 0) return -1;
     *bin_out = oracle_ebin(n_bins, edges, E);
@@ -395,11 +505,12 @@ static void *run_job(void *arg)
 {
     job *j = (job *)arg;
     const problem *p = j->p;
-    const int64_t nvox = (int64_t)p->n[0] * p->n[1] * p->n[2];
-    int64_t cap = (int64_t)p->n[0] + p->n[1] + p->n[2] + 3;
+    const int64_t nvox = problem_cells(p);
+    int64_t cap = problem_cap(p);
     int64_t *vox = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
     double *len = (double *)malloc(sizeof(double) * (size_t)cap);
-    event_f64 *ws = (event_f64 *)malloc(sizeof(event_f64) * (size_t)cap);
+    void *ws = malloc((sizeof(event_f64) > sizeof(rz_event_rz64) ? sizeof(event_f64) : sizeof(rz_event_rz64)) *
+                      (size_t)cap);
     double sig[256];
     if (!vox || !len || !ws) { j->n_err = 1; free(vox); free(len); free(ws); return NULL; }
     for (int64_t r = j->r0; r < j->r1; ++r) {
@@ -407,7 +518,7 @@ static void *run_job(void *arg)
         int b = oracle_ebin(p->n_bins, p->edges, E);
         double o[3] = {j->ox[r], j->oy[r], j->oz[r]};
         double u[3] = {j->ux[r], j->uy[r], j->uz[r]};
-        int64_t k = trace_ws_f64(p->lo, p->h, p->n, o, u, cap, vox, len, NULL, ws);
+        int64_t k = problem_trace(p, o, u, cap, vox, len, ws);
         if (k < 0 || k > cap) { j->n_err++; continue; }
         j->n_seg += k;
         if (b < 0) { j->n_out_of_range++; continue; }
@@ -445,19 +556,16 @@ static double now_s(void)
  * paper times the transport part only, Sec. 4).  Rays are split into
  * n_threads static chunks with private tallies.
  */
-int oracle_cast(const double *lo, const double *h, const int32_t *n, const uint8_t *mat,
-                int n_mat, const int64_t *offs, const double *energy, const double *sigma,
-                int n_bins, const double *edges, const double *rho,
-                int n_mix, const int64_t *mix_offs, const int32_t *mix_comp, const double *mix_frac,
-                int64_t n_rays,
-                const double *ox, const double *oy, const double *oz,
-                const double *ux, const double *uy, const double *uz,
-                const double *e, const double *w, int n_threads,
-                double *tally, double *tally_sq, int64_t *tally_cnt,
-                int64_t *stats, double *seconds)
+static int cast_problem(const problem *pp, int64_t n_rays,
+                        const double *ox, const double *oy, const double *oz,
+                        const double *ux, const double *uy, const double *uz,
+                        const double *e, const double *w, int n_threads,
+                        double *tally, double *tally_sq, int64_t *tally_cnt,
+                        int64_t *stats, double *seconds)
 {
-    problem p = {lo, h, n, mat, n_mat, offs, energy, sigma, n_bins, edges, rho, n_mix, mix_offs, mix_comp, mix_frac};
-    const int64_t nvox = (int64_t)n[0] * n[1] * n[2];
+    problem p = *pp;
+    const int n_bins = p.n_bins;
+    const int64_t nvox = problem_cells(&p);
     const int64_t nt = (int64_t)n_bins * nvox;
     if (n_threads < 1) n_threads = 1;
     job *jobs = (job *)calloc((size_t)n_threads, sizeof(job));
@@ -511,4 +619,63 @@ int oracle_cast(const double *lo, const double *h, const int32_t *n, const uint8
     }
     free(jobs); free(th);
     return rc;
+}
+
+int oracle_cast(const double *lo, const double *h, const int32_t *n, const uint8_t *mat,
+                int n_mat, const int64_t *offs, const double *energy, const double *sigma,
+                int n_bins, const double *edges, const double *rho,
+                int n_mix, const int64_t *mix_offs, const int32_t *mix_comp, const double *mix_frac,
+                int64_t n_rays,
+                const double *ox, const double *oy, const double *oz,
+                const double *ux, const double *uy, const double *uz,
+                const double *e, const double *w, int n_threads,
+                double *tally, double *tally_sq, int64_t *tally_cnt,
+                int64_t *stats, double *seconds)
+{
+    problem p = {lo, h, n, mat, n_mat, offs, energy, sigma, n_bins, edges, rho, n_mix, mix_offs, mix_comp, mix_frac,
+                 0, 0.0, 0.0, 0, 0, NULL, NULL};
+    return cast_problem(&p, n_rays, ox, oy, oz, ux, uy, uz, e, w, n_threads, tally, tally_sq, tally_cnt, stats,
+                        seconds);
+}
+
+/* The whole-tally run of oracle_cast on an R-Z mesh (cells i + nr k; the
+ * material of cell c is mat[c], its density factor rho[c] if rho is not
+ * NULL). */
+int oracle_cast_rz(double cx, double cy, int32_t nr, const double *radii, int32_t nz, const double *zpl,
+                   const uint8_t *mat, int n_mat, const int64_t *offs, const double *energy, const double *sigma,
+                   int n_bins, const double *edges, const double *rho, int64_t n_rays,
+                   const double *ox, const double *oy, const double *oz,
+                   const double *ux, const double *uy, const double *uz,
+                   const double *e, const double *w, int n_threads,
+                   double *tally, double *tally_sq, int64_t *tally_cnt,
+                   int64_t *stats, double *seconds)
+{
+    problem p = {NULL, NULL, NULL, mat, n_mat, offs, energy, sigma, n_bins, edges, rho, 0, NULL, NULL, NULL,
+                 1, cx, cy, nr, nz, radii, zpl};
+    return cast_problem(&p, n_rays, ox, oy, oz, ux, uy, uz, e, w, n_threads, tally, tally_sq, tally_cnt, stats,
+                        seconds);
+}
+
+/* Per-ray record of oracle_ray_scores on an R-Z mesh. */
+int64_t oracle_ray_scores_rz(double cx, double cy, int32_t nr, const double *radii, int32_t nz, const double *zpl,
+                             const uint8_t *mat, int n_mat, const int64_t *offs, const double *energy,
+                             const double *sigma, int n_bins, const double *edges, const double *rho,
+                             const double *o, const double *u, double E, double w,
+                             int64_t cap, int64_t *vox, double *len, double *score, int *bin_out)
+{
+    problem p = {NULL, NULL, NULL, mat, n_mat, offs, energy, sigma, n_bins, edges, rho, 0, NULL, NULL, NULL,
+                 1, cx, cy, nr, nz, radii, zpl};
+    double sig[256];
+    if (material_sigmas(&p, E, sig, NULL) < 0) return -1;
+    *bin_out = oracle_ebin(n_bins, edges, E);
+    int64_t k = oracle_trace_rz_f64(cx, cy, nr, radii, nz, zpl, o, u, cap, vox, len, NULL);
+    if (k < 0) return k;
+    int64_t m_seg = k < cap ? k : cap;
+    depth tau = {0.0, 0.0};
+    for (int64_t s = 0; s < m_seg; ++s) {
+        double sg = voxel_sigma(&p, sig, vox[s]);
+        score[s] = (*bin_out >= 0) ? vrc_score(w, tau, sg, len[s]) : 0.0;
+        depth_add(&tau, sg * len[s]);
+    }
+    return k;
 }

@@ -10,6 +10,9 @@ from .gen import (  # noqa: F401
     Mesh,
     RectMesh,
     rect_mesh,
+    RZMesh,
+    rz_mesh,
+    rays_in_rz,
     XSTables,
     Mixtures,
     random_mixtures,

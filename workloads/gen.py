@@ -86,6 +86,50 @@ class RectMesh:
         assert self.mat.dtype == np.uint8 and self.mat.size == self.n_voxels
 
 
+@dataclasses.dataclass
+class RZMesh:
+    """R-Z (cylindrical) mesh: a cylinder along z with its axis through centre = (cx, cy), cut into
+    shells by radii 0 = radii[0] < ... < radii[nr] and into slabs by planes zpl[0] < ... < zpl[nz].
+    Cell (i, k) is r_i <= rho < r_{i+1}, z_k <= z < z_{k+1}, number i + nr k; mat is r fastest."""
+    centre: np.ndarray  # (2,) float64, cm
+    radii: np.ndarray  # (nr + 1,) float64, cm, radii[0] = 0
+    zpl: np.ndarray  # (nz + 1,) float64, cm
+    mat: np.ndarray  # (nr * nz,) uint8
+    density: Optional[np.ndarray] = None  # per-cell factors on the material's Sigma, or None
+
+    @property
+    def nr(self) -> int:
+        return int(self.radii.size - 1)
+
+    @property
+    def nz(self) -> int:
+        return int(self.zpl.size - 1)
+
+    @property
+    def n_voxels(self) -> int:
+        return self.nr * self.nz
+
+    def check(self) -> None:
+        assert self.centre.shape == (2,) and self.radii[0] == 0.0
+        assert np.all(np.diff(self.radii) > 0) and np.all(np.diff(self.zpl) > 0)
+        assert self.mat.dtype == np.uint8 and self.mat.size == self.n_voxels
+
+
+def rz_mesh(seed: int, nr: int, nz: int, r_max: float, z_lo: float, z_hi: float, n_mat: int = 3,
+            centre=(0.0, 0.0), uneven: bool = True, ring: int = 5, slab: int = 10) -> RZMesh:
+    """R-Z mesh: radii uniform in r (with seeded jitter of up to a third of a spacing when uneven), z planes
+    uniform, materials drawn per block of `ring` shells x `slab` slabs."""
+    rng = _rng(seed)
+    radii = np.linspace(0.0, r_max, nr + 1)
+    if uneven and nr > 1:
+        dr = r_max / nr
+        radii[1:-1] += rng.uniform(-dr / 3, dr / 3, nr - 1)
+    zpl = np.linspace(z_lo, z_hi, nz + 1)
+    blocks = rng.integers(0, n_mat, ((nz + slab - 1) // slab, (nr + ring - 1) // ring)).astype(np.uint8)
+    mat = np.repeat(np.repeat(blocks, slab, axis=0)[:nz], ring, axis=1)[:, :nr]
+    return RZMesh(np.asarray(centre, np.float64), radii, zpl, mat.reshape(-1).copy())
+
+
 def rect_mesh(seed: int, n, lo=(0.0, 0.0, 0.0), h_min: float = 0.2, h_max: float = 1.5, n_mat: int = 3,
               slab: int = 4) -> RectMesh:
     """Rectilinear mesh with spacings drawn uniformly in [h_min, h_max] per plane, materials per z slab."""
@@ -380,6 +424,17 @@ def rays_in_cylinder(seed: int, mesh: Mesh, n: int, radius: float, weights: str 
     ox = c[0] + r * np.cos(th)
     oy = c[1] + r * np.sin(th)
     oz = rng.uniform(mesh.lo[2], mesh.lo[2] + mesh.n[2] * mesh.h[2], n)
+    return _finish_rays(rng, ox, oy, oz, weights=weights)
+
+
+def rays_in_rz(seed: int, mesh: "RZMesh", n: int, weights: str = "lognormal", r_frac: float = 1.0) -> Rays:
+    """Origins uniform in the volume of the R-Z mesh's cylinder (radius r_frac times its outer radius)."""
+    rng = _rng(seed)
+    r = r_frac * mesh.radii[-1] * np.sqrt(rng.uniform(0.0, 1.0, n))
+    th = rng.uniform(0.0, 2.0 * math.pi, n)
+    ox = mesh.centre[0] + r * np.cos(th)
+    oy = mesh.centre[1] + r * np.sin(th)
+    oz = rng.uniform(mesh.zpl[0], mesh.zpl[-1], n)
     return _finish_rays(rng, ox, oy, oz, weights=weights)
 
 
