@@ -91,7 +91,7 @@ def parse():
                     help="0: per-segment atomics; 1: tile-split from 131072 rays (default); "
                          "2, 3: tile-split always (atomic / plain flush)")
     ap.add_argument("--accumulate-modes", type=int, default=1, help="also time the other accumulation modes")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the CPU oracle leg")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target wall time of the CPU oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--other-forms", type=int, default=1, help="also time the other precision forms")
     ap.add_argument("--batched", type=int, default=1,
@@ -297,6 +297,45 @@ def bench_rect(vrc, ctx, wl, arrays, counts, torch, stream, steps: int = 10) -> 
     return out
 
 
+def bench_rz(vrc, ctx, wl, arrays, counts, torch, stream, steps: int = 10) -> dict:
+    """R-Z (cylindrical) mesh: the multimat tables and 1e6 rays on the cylinder inscribed in the multimat
+    box (axis along z through the box centre, radius half the box width), 100 shells (radii jittered by
+    up to a third of a spacing) by 100 slabs, the 3 materials in blocks of 10 shells by 10 slabs.  The
+    plain R-Z kernel (one atomic per segment) is timed beside the uniform mesh on the atomic path and on
+    the default tile-split accumulation, in the p32_t64 and p64 forms."""
+    import workloads as W
+
+    m = wl.mesh
+    hi = m.lo + m.n * m.h
+    c = 0.5 * (m.lo + hi)
+    rz = W.rz_mesh(2026, 100, 100, 0.5 * float(hi[0] - m.lo[0]), float(m.lo[2]), float(hi[2]), n_mat=3,
+                   centre=(float(c[0]), float(c[1])), uneven=True, ring=10, slab=10)
+    ctx.set_mesh(3, rz)
+    launch = ctx.get_launch()
+    out = {"workload": "multimat tables and 1e6 rays on the inscribed cylinder, R-Z mesh 100 shells x 100 slabs "
+                       "(3 materials in 10 x 10 blocks)"}
+    try:
+        for prec, dt in (("p32_t64", "f32"), ("p64", "f64")):
+            arr = arrays if dt == "f32" else device_rays(wl, "f64", torch)
+            S = ctx.count_segments(3, prec, arr, counts, stream)
+            S_u = ctx.count_segments(0, prec, arr, counts, stream)
+            t_z = ctx.create_tally(3, prec)
+            _, tot_z, _ = time_casts(vrc, ctx, t_z, arr, steps, 2, stream, torch)
+            ctx.destroy_tally(t_z)
+            row = {"segments_per_step": S, "ms_per_step": tot_z / steps, "segments_per_s": S / (tot_z / steps / 1e3)}
+            for name, acc in (("uniform_tile_split", launch["accumulate"]), ("uniform_atomic", 0)):
+                ctx.set_launch(accumulate=acc)
+                t_u = ctx.create_tally(0, prec)
+                _, tot_u, _ = time_casts(vrc, ctx, t_u, arr, steps, 2, stream, torch)
+                ctx.destroy_tally(t_u)
+                row[name + "_segments_per_s"] = S_u / (tot_u / steps / 1e3)
+            ctx.set_launch(**launch)
+            out[prec] = row
+    finally:
+        ctx.set_launch(**launch)
+    return out
+
+
 def bench_density(vrc, ctx, wl, arrays, torch, stream, steps: int = 10) -> dict:
     """Per-voxel density factors: the multimat workload with a factor uniform in [0.5, 2] per voxel,
     timed with the default tile-split accumulation and with one atomic per segment, each beside the
@@ -398,32 +437,28 @@ def host_cpu():
 
 def cpu_baseline(wl, target_s):
     """The FP64 oracle (built -O3 -march=native for this host) on a bounded sample of the same workload:
-    passes over a slice of its rays on all the host threads this process may use, for about target_s
-    seconds of tracing and scoring."""
+    one pass over the first rays of the workload, as many as take about target_s seconds of tracing
+    and scoring on all the host threads this process may use (each pass also zeroes and merges one
+    private tally per thread, a fixed cost that a larger sample amortises)."""
     import tempfile
     import oracle
     from oracle import build as oracle_build
     native = oracle_build.build_native(tempfile.mkdtemp(prefix="vrc_oracle_"))
     oracle.use_library(native)
     threads, host = host_cpu()
-    # a slice that takes a few seconds per pass on this host's threads
-    probe = wl.rays.take(slice(0, min(wl.rays.n, 100_000)))
-    r0 = oracle.cast(wl.mesh, wl.xs, probe, n_threads=threads, with_stats=False)
-    per_ray_s = max(r0.seconds, 1e-6) / probe.n
-    n_slice = int(min(wl.rays.n, max(probe.n, (target_s / 3.0) / per_ray_s)))
-    sample = wl.rays.take(slice(0, n_slice))
-    segs, secs, passes = 0, 0.0, 0
-    while secs < target_s and passes < 64:
-        res = oracle.cast(wl.mesh, wl.xs, sample, n_threads=threads, with_stats=False)
-        segs += res.segments
-        secs += res.seconds
-        passes += 1
+    # the time per ray beyond the fixed cost of a pass, from two probes
+    n1, n2 = min(wl.rays.n, 100_000), min(wl.rays.n, 400_000)
+    t1 = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, n1)), n_threads=threads, with_stats=False).seconds
+    t2 = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, n2)), n_threads=threads, with_stats=False).seconds
+    per_ray = max((t2 - t1) / max(n2 - n1, 1), t2 / max(n2, 1) * 0.1, 1e-9)
+    n_slice = int(min(wl.rays.n, max(n2, (target_s - t1) / per_ray)))
+    res = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, n_slice)), n_threads=threads, with_stats=False)
     one = oracle.cast(wl.mesh, wl.xs, wl.rays.take(slice(0, 20_000)), n_threads=1, with_stats=False)
     oracle.use_library(oracle_build.LIB)
-    return {"value": segs / secs, "unit": "segments/s", "cores": threads, "kind": "oracle",
-            "sample": f"{passes} passes over the first {n_slice} of the {wl.rays.n} rays of the same workload on "
-                      f"{threads} threads (FP64 oracle, gcc -O3 -march=native; {segs} segments in {secs:.2f} s of "
-                      f"tracing and scoring, setup excluded)",
+    return {"value": res.segments / res.seconds, "unit": "segments/s", "cores": threads, "kind": "oracle",
+            "sample": f"one pass over the first {n_slice} of the {wl.rays.n} rays of the same workload on "
+                      f"{threads} threads (FP64 oracle, gcc -O3 -march=native; {res.segments} segments in "
+                      f"{res.seconds:.2f} s of tracing, scoring and merging the per-thread tallies, setup excluded)",
             "host": host,
             "single_thread_segments_per_s": one.segments / one.seconds}
 
@@ -550,7 +585,8 @@ def bench_serving(seconds: float) -> dict:
         if mode == "serving":
             ctx.serve_start(count_segments=1)
         rep = ctx.walkers_run(tally, rate_rays_per_s=0.0, duration_s=60.0, max_rays=40_000_000, rays_per_collision=8,
-                              seed=7, direct=0 if mode == "serving" else 1, **walk)
+                              seed=7, direct=0 if mode == "serving" else 1, record=0 if mode == "serving" else 1,
+                              **walk)
         if mode == "serving":
             st = ctx.serve_stats()
             ctx.serve_stop()
@@ -563,10 +599,72 @@ def bench_serving(seconds: float) -> dict:
             sat[mode] = {"rays": rep["rays_submitted"], "wall_s": rep["wall_s"],
                          "rays_per_s": rep["rays_submitted"] / rep["wall_s"]}
         log(f"bench: saturation {mode}: {sat[mode]['rays_per_s']:.3e} rays/s")
+    cap = guarded("serving capacity", lambda: serving_capacity(vrc, ctx, wl, [float(v) for v in wl.ebin_edges]))
     ctx.close()
     return {"workload": "200^3 mesh of 1 cm, sphere r=50 cm Sigma=1.0 in Sigma=0.1, 10 log energy bins (FP64 tally, "
                         "640 MB), 8 walker threads, one-group analog walk (p_abs 0.3), flush at 16384 rays or 1 ms",
-            "precision": "p32_t64", "loads": loads, "saturation": sat}
+            "precision": "p32_t64", "loads": loads, "saturation": sat, "device_capacity": cap}
+
+
+def serving_capacity(vrc, ctx, wl, edges) -> dict:
+    """The device side of the serving form without the walkers: the rays the walkers emitted in the
+    saturation run (recorded), submitted from host memory as fast as 8 threads can in requests of 16384
+    rays, against one plain cast of all of them from device memory and one plain cast per request."""
+    import threading
+    import torch
+
+    rays = [np.ascontiguousarray(a, np.float32) for a in ctx.walkers_take()]
+    n = rays[0].size
+    chunk = 16384
+    starts = list(range(0, n, chunk))
+    stream = torch.cuda.current_stream()
+    dev = [torch.from_numpy(a).to("cuda:0") for a in rays]
+    counts = torch.empty(n, dtype=torch.int64, device="cuda:0")
+    S = ctx.count_segments(0, "p32_t64", dev, counts, stream)
+    out = {"rays": n, "segments": S, "request_rays": chunk}
+    # one plain cast of everything (device arrays; tile-split when the tally allows it)
+    t = ctx.create_tally(0, "p32_t64", edges)
+    per, tot, _ = time_casts(vrc, ctx, t, dev, 3, 1, stream, torch)
+    ctx.destroy_tally(t)
+    out["single_launch"] = {"ms": tot / 3, "segments_per_s": S / (tot / 3 / 1e3)}
+    del dev, counts
+    torch.cuda.empty_cache()
+    # one plain cast per request, from host memory
+    t = ctx.create_tally(0, "p32_t64", edges)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a in starts:
+        ctx.cast(t, [r[a:a + chunk] for r in rays])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.destroy_tally(t)
+    out["plain_per_request"] = {"wall_s": wall, "segments_per_s": S / wall}
+    # the serving loop fed by 8 submitting threads
+    t = ctx.create_tally(0, "p32_t64", edges)
+    ctx.serve_start()
+    try:
+        def feed(k):
+            for a in starts[k::8]:
+                ctx.serve_submit(t, [r[a:a + chunk] for r in rays])
+        th = [threading.Thread(target=feed, args=(k,)) for k in range(8)]
+        t0 = time.perf_counter()
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        ctx.serve_drain()
+        wall = time.perf_counter() - t0
+        st = ctx.serve_stats()
+    finally:
+        ctx.serve_stop()
+    ctx.destroy_tally(t)
+    out["serving"] = {"wall_s": wall, "segments_per_s": S / wall, "latency_p50_ms": st["latency_p50_us"] / 1e3,
+                      "latency_p99_ms": st["latency_p99_us"] / 1e3,
+                      "requests_per_launch": st["mean_requests_per_launch"]}
+    log(f"bench: serving capacity: {out['serving']['segments_per_s']:.3e} segments/s served, "
+        f"{out['single_launch']['segments_per_s']:.3e} in one launch, "
+        f"{out['plain_per_request']['segments_per_s']:.3e} with one cast per request")
+    return out
 
 
 def bench_fom(batches: int, histories: int) -> dict:
@@ -806,6 +904,7 @@ def multimat_forms(vrc, torch, args) -> dict:
     out["other_forms"] = other_forms(vrc, ctx, wl, "p32_t64", {"f32": arrays}, counts, stream, torch, 5)
     out["next_event_form"] = guarded("next-event", lambda: bench_next_event(vrc, ctx, wl, torch, stream))
     out["rect_form"] = guarded("rectilinear", lambda: bench_rect(vrc, ctx, wl, arrays, counts, torch, stream))
+    out["rz_form"] = guarded("R-Z", lambda: bench_rz(vrc, ctx, wl, arrays, counts, torch, stream))
     out["host_input_form"] = guarded("host-input", lambda: bench_host_input(vrc, ctx, wl, torch, S))
 
     def density():

@@ -24,8 +24,10 @@
  *   - Meshes are uniform per axis: lo[3] (cm), h[3] (cm), n[3] voxels; voxel
  *     (i,j,k) covers [lo+i h, lo+(i+1) h) on each axis (half-open), and has
  *     linear index i + n0 (j + n1 k) ("x fastest").  A rectilinear mesh
- *     (vrc_set_mesh_rect) takes the planes from a table per axis instead, and
- *     density factors (vrc_set_mesh_density) scale each voxel's Sigma.  Outside the mesh is
+ *     (vrc_set_mesh_rect) takes the planes from a table per axis instead,
+ *     density factors (vrc_set_mesh_density) scale each voxel's Sigma, and
+ *     an R-Z mesh (vrc_set_mesh_rz) has cylindrical shells times slabs for
+ *     cells.  Outside the mesh is
  *     vacuum: rays start scoring where they enter and stop where they leave
  *     (Sec. 5.1: no reflecting boundary).
  *   - Tallies are raw sums in weight * cm, laid out [bin][k][j][i]; divide by
@@ -165,7 +167,33 @@ vrc_status vrc_set_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const dou
 vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], const double *x_planes,
                              const double *y_planes, const double *z_planes, const uint8_t *mat);
 
-/* Give mesh `mesh_id` (uniform or rectilinear, already set) per-voxel
+/* Define (or replace) mesh `mesh_id` as an R-Z (cylindrical) mesh, one of
+ * the geometries Sec. 6.3 names for the method: a cylinder along z with its
+ * axis through (centre[0], centre[1]), cut into nr shells by radii[0..nr]
+ * (radii[0] = 0, finite, strictly increasing, cm) and into nz slabs by
+ * z_planes[0..nz] (finite, strictly increasing, cm).  Cell (i, k) holds the
+ * points at distance rho from the axis with radii[i] <= rho < radii[i+1]
+ * and z_planes[k] <= z < z_planes[k+1]; it is tally element i + nr k (the
+ * layout of an nr x 1 x nz mesh).  mat: host array of nr*nz material ids in
+ * that order, copied.  1 <= nr, nz <= 2^20, nr*nz < 2^31.
+ * The walk meets two kinds of surface: with p the origin minus the axis
+ * point and a = ux^2 + uy^2, b = px ux + py uy, c = px^2 + py^2, the ray is
+ * inside the cylinder of radius r for t- <= t < t+, t-+ = (-b -+ sqrt(D))/a,
+ * D = b^2 - a (c - r^2) (never when D <= 0; for a = 0 always when c < r^2),
+ * and crosses plane z_k at (z_k - oz) / uz.  Each piece is scored as on
+ * the Cartesian mesh (Eqs. 1-4).  Such a mesh is cast by vrc_cast_rays
+ * (always the plain kernel with FP64 or compensated FP32 atomics; the
+ * tile-split accumulation is for Cartesian meshes), vrc_trace_rays,
+ * vrc_count_segments and the serving loop, with density factors
+ * (vrc_set_mesh_density, one per cell) or without; vrc_cast_batches,
+ * vrc_next_event and the walkers refuse it (VRC_ERR_INVALID).  FP32 forms are refused at cast time when two radii or
+ * two planes round to the same float.
+ * Errors: VRC_ERR_INVALID (bad sizes, radii or planes), VRC_ERR_STATE (a
+ * tally uses the mesh), VRC_ERR_NOMEM.                                     */
+vrc_status vrc_set_mesh_rz(vrc_ctx *ctx, int mesh_id, const double centre[2], int32_t nr, const double *radii,
+                           int32_t nz, const double *z_planes, const uint8_t *mat);
+
+/* Give mesh `mesh_id` (uniform, rectilinear or R-Z, already set) per-voxel
  * density factors: the Sigma_t,i of voxel i in Eqs. 1-4 becomes
  * rho[i] * Sigma_m(E) of its material m.  rho: host array of n0*n1*n2
  * finite values >= 0 (x fastest; 0 makes a voxel void), copied as the pairs
@@ -338,8 +366,10 @@ vrc_status vrc_autotune_cast(vrc_ctx *ctx, int tally_id, const vrc_ray_batch *ba
  * rotate over, so consecutive launches overlap on the device [2];
  * max_inflight: launches in flight at once [4]; linger_us: how long the
  * dispatcher waits for more requests before sealing a launch [0];
- * count_segments: also count each launch's segments on the device, after its
- * completion event (for throughput reports; off the latency path) [0].     */
+ * count_segments: also count each launch's segments on the device (for
+ * throughput reports): a walk of every request's rays on the launch's
+ * stream before its casts, so the latencies and throughput measured with
+ * it include that walk [0].                                                */
 typedef struct {
     int64_t ring_bytes;
     int64_t staging_bytes;
@@ -504,6 +534,29 @@ vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision
 vrc_status vrc_count_segments(vrc_ctx *ctx, int mesh_id, vrc_precision precision,
                               const vrc_ray_batch *batch, int64_t *counts, int64_t *total,
                               void *hip_stream);
+
+/* Test hook, not for production use: force a failure the library must
+ * detect, from the host, with every kernel still ending normally.
+ * VRC_TEST_SHORT_COUNT with value 1 makes the counting pass of the
+ * tile-split accumulation report one tile entry fewer than it found (in its
+ * first block), so that the entries pass writes one record past a run (into
+ * the next run, inside the record buffer) and its run check sets the
+ * context's device flag; the next vrc_read_tally then returns
+ * VRC_ERR_DEVICE, and the error is sticky for the context.  Value 0 turns
+ * the hook off.  Errors: VRC_ERR_INVALID for another hook or value.        */
+#define VRC_TEST_SHORT_COUNT 1
+/* VRC_TEST_RECORD_BUDGET with value v > 0 caps the record bytes of one
+ * tile-split sub-launch at max(v, 1 MiB) (so that a test can make a batch
+ * run in several sub-launches); 0 restores the default, an eighth of the
+ * device's memory within 2..64 GiB.                                        */
+#define VRC_TEST_RECORD_BUDGET 2
+/* VRC_TEST_ENTRIES_JUMP chooses how the entries pass of the tile-split
+ * accumulation crosses tiles that hold one material: 1 jumps over them (the
+ * optical depth from the chord), 0 walks them voxel by voxel (the same
+ * optical depth), -1 restores the default (jump when at least half of the
+ * mesh's tiles hold one material).  Both give the same records.           */
+#define VRC_TEST_ENTRIES_JUMP 3
+vrc_status vrc_test_hook(vrc_ctx *ctx, int hook, int64_t value);
 
 /* Per-ray voxel sequences, lengths and scores, exactly as the casting kernel
  * of `tally_id` computes them (same traversal and arithmetic), written as

@@ -120,6 +120,7 @@ _SIGNATURES = {
     "vrc_destroy": [_P],
     "vrc_set_mesh": [_P, _I, _PD, _PD, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8)],
     "vrc_set_mesh_rect": [_P, _I, ctypes.POINTER(ctypes.c_int32), _PD, _PD, _PD, ctypes.POINTER(ctypes.c_uint8)],
+    "vrc_set_mesh_rz": [_P, _I, _PD, ctypes.c_int32, _PD, ctypes.c_int32, _PD, ctypes.POINTER(ctypes.c_uint8)],
     "vrc_set_xs_tables": [_P, _I, _PI64, _PD, _PD],
     "vrc_set_xs_mixtures": [_P, _I, _PI64, _PD, _PD, _I, _PI64, ctypes.POINTER(ctypes.c_int32), _PD],
     "vrc_set_mesh_density": [_P, _I, _PD],
@@ -128,6 +129,7 @@ _SIGNATURES = {
     "vrc_tally_size": [_P, _I, _PI64],
     "vrc_cast_rays": [_P, _I, ctypes.POINTER(vrc_ray_batch), _P],
     "vrc_cast_rays_noalloc": [_P, _I, ctypes.POINTER(vrc_ray_batch), _P],
+    "vrc_test_hook": [_P, _I, ctypes.c_int64],
     "vrc_read_tally": [_P, _I, _PD],
     "vrc_load_tally": [_P, _I, _PD],
     "vrc_reset_tally": [_P, _I],
@@ -297,6 +299,21 @@ def vrc_set_mesh_rect(ctx: int, mesh_id: int, planes, mat) -> None:
                                             mat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
 
 
+def vrc_set_mesh_rz(ctx: int, mesh_id: int, centre, radii, z_planes, mat) -> None:
+    """R-Z mesh: axis through centre (x, y), radii[0..nr] (radii[0] = 0) and z_planes[0..nz]; mat r fastest."""
+    c = np.ascontiguousarray(centre, np.float64)
+    r = np.ascontiguousarray(radii, np.float64)
+    z = np.ascontiguousarray(z_planes, np.float64)
+    mat = np.ascontiguousarray(mat, np.uint8)
+    if c.size != 2 or r.ndim != 1 or z.ndim != 1 or r.size < 2 or z.size < 2:
+        raise ValueError("centre needs two values, radii and z_planes at least two each")
+    if mat.size != (r.size - 1) * (z.size - 1):
+        raise ValueError("mesh arrays have the wrong size")
+    _check(load_library().vrc_set_mesh_rz(ctx, mesh_id, c.ctypes.data_as(_PD), r.size - 1, r.ctypes.data_as(_PD),
+                                          z.size - 1, z.ctypes.data_as(_PD),
+                                          mat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+
+
 def vrc_set_xs_tables(ctx: int, offs, energy, sigma) -> None:
     offs = np.ascontiguousarray(offs, np.int64)
     energy = np.ascontiguousarray(energy, np.float64)
@@ -363,6 +380,16 @@ def vrc_cast_rays(ctx: int, tally_id: int, batch: vrc_ray_batch, stream=None) ->
 
 def vrc_cast_rays_noalloc(ctx: int, tally_id: int, batch: vrc_ray_batch, stream=None) -> None:
     _check(load_library().vrc_cast_rays_noalloc(ctx, tally_id, ctypes.byref(batch), _stream(stream)))
+
+
+VRC_TEST_SHORT_COUNT = 1
+VRC_TEST_RECORD_BUDGET = 2
+VRC_TEST_ENTRIES_JUMP = 3
+
+
+def vrc_test_hook(ctx: int, hook: int, value: int) -> None:
+    """Test hook (see include/vrc.h): force a failure the library must detect."""
+    _check(load_library().vrc_test_hook(ctx, hook, value))
 
 
 def vrc_read_tally(ctx: int, tally_id: int) -> np.ndarray:
@@ -608,14 +635,17 @@ class Context:
             pass
 
     def set_mesh(self, mesh_id: int, mesh) -> None:
-        """A uniform mesh (lo, h, n, mat) or a rectilinear one (planes, mat), with its density factors if any."""
-        if hasattr(mesh, "planes"):
+        """A uniform mesh (lo, h, n, mat), a rectilinear one (planes, mat) or an R-Z one (centre, radii, zpl,
+        mat), with its density factors if any."""
+        if hasattr(mesh, "radii"):
+            vrc_set_mesh_rz(self.handle, mesh_id, mesh.centre, mesh.radii, mesh.zpl, mesh.mat)
+        elif hasattr(mesh, "planes"):
             vrc_set_mesh_rect(self.handle, mesh_id, mesh.planes, mesh.mat)
         else:
             vrc_set_mesh(self.handle, mesh_id, mesh.lo, mesh.h, mesh.n, mesh.mat)
         rho = getattr(mesh, "density", None)
         if rho is not None:
-            if np.asarray(rho).size != int(np.prod(np.asarray(mesh.n, np.int64))):
+            if np.asarray(rho).size != int(np.asarray(mesh.mat).size):
                 raise ValueError("one density factor per voxel is needed")
             vrc_set_mesh_density(self.handle, mesh_id, rho)
 

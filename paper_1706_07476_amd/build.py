@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvrc.so")
 SOURCES = ["vrc_api.cpp", "vrc_xs.cpp", "vrc_tune.cpp", "vrc_serve.cpp", "vrc_walker.cpp", "vrc_kernels.hip",
-           "vrc_sorted.hip", "vrc_batched.hip"]
+           "vrc_sorted.hip", "vrc_batched.hip", "vrc_rz.hip"]
 HEADERS = ["vrc_internal.h", "vrc_math.h", "vrc_device.h", os.path.join("..", "..", "include", "vrc.h")]
 ARCH = os.environ.get("VRC_OFFLOAD_ARCH", "gfx950")
 

@@ -156,9 +156,10 @@ vrc_status mark_stage_used(vrc_ctx *ctx, int slot, hipStream_t s)
 
 // Store mesh `mesh_id` (arguments already checked except n and the voxel
 // count).  planes == nullptr: uniform mesh lo + k h; otherwise the three
-// plane tables of a rectilinear mesh (lo and h then only describe it).
+// plane tables of a rectilinear mesh (lo and h then only describe it), or
+// with rz the radii, a placeholder and the z planes of an R-Z mesh.
 vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const double h[3], const int32_t n[3],
-                      const uint8_t *mat, const double *const *planes)
+                      const uint8_t *mat, const double *const *planes, bool rz = false)
 {
     int64_t nvox = 1;
     for (int a = 0; a < 3; ++a) {
@@ -172,6 +173,7 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
     int max_mat = 0;
     for (int64_t i = 0; i < nvox; ++i) max_mat = std::max(max_mat, static_cast<int>(mat[i]));
     free_dev(m.d_mat);
+    free_dev(m.d_tile_mat);
     free_dev(m.d_pl64);
     free_dev(m.d_pl32);
     free_dev(m.d_rho64);
@@ -182,11 +184,33 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
     m.h_rho.clear();
     m.set = false;
     m.rect = false;
+    m.rz = false;
     m.rect_f32_ok = false;
     m.h_planes.clear();
     void *d = nullptr;
     if (vrc_status s = upload(ctx, &d, mat, static_cast<size_t>(nvox))) return s;
     m.d_mat = static_cast<uint8_t *>(d);
+    {
+        // per tile of 16^3 voxels: its material if it holds one only, else -1 (the entries pass of the
+        // tile-split accumulation takes such a tile's optical depth from its chord)
+        const int tx = (n[0] + 15) / 16, ty = (n[1] + 15) / 16, tz = (n[2] + 15) / 16;
+        std::vector<int8_t> tm(static_cast<size_t>(tx) * ty * tz, static_cast<int8_t>(-2));  // -2: no voxel yet
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i) {
+                    int8_t &t = tm[(i >> 4) + static_cast<size_t>(tx) * ((j >> 4) + static_cast<size_t>(ty) * (k >> 4))];
+                    const int v = mat[i + static_cast<int64_t>(n[0]) * (j + static_cast<int64_t>(n[1]) * k)];
+                    if (t == -2) t = static_cast<int8_t>(v);
+                    else if (t != v) t = -1;
+                }
+        if (vrc_status s = upload(ctx, &d, tm.data(), tm.size())) {
+            free_dev(m.d_mat);
+            return s;
+        }
+        m.d_tile_mat = static_cast<int8_t *>(d);
+        m.pure_frac = static_cast<double>(std::count_if(tm.begin(), tm.end(), [](int8_t v) { return v >= 0; })) /
+                      static_cast<double>(tm.size());
+    }
     if (planes) {
         std::vector<float> p32;
         bool f32_ok = true;
@@ -200,16 +224,19 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
         }
         if (vrc_status s = upload(ctx, &d, m.h_planes.data(), sizeof(double) * m.h_planes.size())) {
             free_dev(m.d_mat);
+            free_dev(m.d_tile_mat);
             return s;
         }
         m.d_pl64 = static_cast<double *>(d);
         if (vrc_status s = upload(ctx, &d, p32.data(), sizeof(float) * p32.size())) {
             free_dev(m.d_mat);
+            free_dev(m.d_tile_mat);
             free_dev(m.d_pl64);
             return s;
         }
         m.d_pl32 = static_cast<float *>(d);
-        m.rect = true;
+        m.rect = !rz;
+        m.rz = rz;
         m.rect_f32_ok = f32_ok;
     }
     for (int a = 0; a < 3; ++a) {
@@ -222,26 +249,40 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
     m.h_mat.assign(mat, mat + nvox);
     m.set = true;
     // Device descriptors read by the persistent batched kernel.  A
-    // rectilinear mesh is not cast there (refused before launch); its
+    // rectilinear or R-Z mesh is not cast there (refused before launch); its
     // descriptor has n = 0, which any traversal treats as an empty mesh.
     MeshP<float> m32;
     MeshP<double> m64;
     for (int a = 0; a < 3; ++a) {
         m32.lo[a] = static_cast<float>(lo[a]);
         m32.h[a] = static_cast<float>(h[a]);
-        m32.n[a] = m.rect ? 0 : n[a];
+        m32.n[a] = m.rect || m.rz ? 0 : n[a];
         m64.lo[a] = lo[a];
         m64.h[a] = h[a];
-        m64.n[a] = m.rect ? 0 : n[a];
+        m64.n[a] = m.rect || m.rz ? 0 : n[a];
     }
     m32.mat = m.d_mat;
     m64.mat = m.d_mat;
+    m32.tile_mat = m.d_tile_mat;  // density factors (set later) make the persistent kernel refuse the mesh
+    m64.tile_mat = m.d_tile_mat;
     VRC_HIP(ctx, hipMemcpy(ctx->d_mesh32 + mesh_id, &m32, sizeof(m32), hipMemcpyHostToDevice));
     VRC_HIP(ctx, hipMemcpy(ctx->d_mesh64 + mesh_id, &m64, sizeof(m64), hipMemcpyHostToDevice));
     return VRC_OK;
 }
 
 }  // namespace
+
+// The kernels' consistency checks (the device is synchronised): a failed one
+// makes the context's error sticky.
+vrc_status vrc::check_device_flags(vrc_ctx *ctx)
+{
+    uint32_t flag = 0;
+    VRC_HIP(ctx, hipMemcpy(&flag, ctx->d_check, sizeof(flag), hipMemcpyDeviceToHost));
+    if (flag == 0) return VRC_OK;
+    ctx->sticky.store(1);
+    return set_error(VRC_ERR_DEVICE, "tile-split accumulation: the entries pass found another number of tile "
+                                     "entries than the counting pass (tallies of this context are not valid)");
+}
 
 vrc_status vrc::check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
 {
@@ -251,7 +292,7 @@ vrc_status vrc::check_cast_ready(vrc_ctx *ctx, const TallyHost *t)
     if (m.max_mat >= ctx->xs.n_mat) return set_error(VRC_ERR_STATE, "mesh has a material id >= n_mat");
     if (t->prec != VRC_P64 && !ctx->xs.f32_ok)
         return set_error(VRC_ERR_INVALID, "energy grid is not strictly increasing once rounded to FP32");
-    if (m.rect && t->prec != VRC_P64 && !m.rect_f32_ok)
+    if ((m.rect || m.rz) && t->prec != VRC_P64 && !m.rect_f32_ok)
         return set_error(VRC_ERR_INVALID, "mesh planes are not strictly increasing once rounded to FP32");
     return VRC_OK;
 }
@@ -279,6 +320,9 @@ vrc_status vrc_create(int device, vrc_ctx **out)
     auto *ctx = new vrc_ctx();
     ctx->device = device;
     ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    if (prop.sharedMemPerBlock > 0) ctx->lds_max = static_cast<size_t>(prop.sharedMemPerBlock);
+    ctx->sort_scratch.record_budget =
+        std::min(std::max(static_cast<size_t>(prop.totalGlobalMem) / 8, size_t(2) << 30), size_t(64) << 30);
     ctx->arch = prop.gcnArchName;
     for (auto &st : ctx->stage) {
         e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
@@ -299,6 +343,8 @@ vrc_status vrc_create(int device, vrc_ctx **out)
     ctx->noalloc_init = noalloc_scratch_init(device);
     e = hipEventCreateWithFlags(&ctx->sort_scratch.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_check, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(ctx->d_check, 0, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&ctx->d_mesh32, sizeof(MeshP<float>) * kMaxMeshes);
     if (e == hipSuccess) e = hipMalloc(&ctx->d_mesh64, sizeof(MeshP<double>) * kMaxMeshes);
     if (e == hipSuccess) e = hipMemset(ctx->d_mesh32, 0, sizeof(MeshP<float>) * kMaxMeshes);
@@ -325,6 +371,7 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
     }
     for (auto &m : ctx->meshes) {
         free_dev(m.d_mat);
+        free_dev(m.d_tile_mat);
         free_dev(m.d_pl64);
         free_dev(m.d_pl32);
         free_dev(m.d_rho64);
@@ -345,6 +392,7 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         free_dev(bs.d_buf);
         if (bs.done) (void)hipEventDestroy(bs.done);
     }
+    free_dev(ctx->d_check);
     free_dev(ctx->d_mesh32);
     free_dev(ctx->d_mesh64);
     {
@@ -399,6 +447,33 @@ vrc_status vrc_set_mesh_rect(vrc_ctx *ctx, int mesh_id, const int32_t n[3], cons
         h[a] = (src[a][n[a]] - src[a][0]) / n[a];  // mean width, informative only
     }
     return store_mesh(ctx, mesh_id, lo, h, n, mat, src);
+}
+
+vrc_status vrc_set_mesh_rz(vrc_ctx *ctx, int mesh_id, const double centre[2], int32_t nr, const double *radii,
+                           int32_t nz, const double *z_planes, const uint8_t *mat)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (mesh_id < 0 || mesh_id >= kMaxMeshes) return set_error(VRC_ERR_INVALID, "mesh_id must be in 0..7");
+    if (!centre || !radii || !z_planes || !mat) return set_error(VRC_ERR_INVALID, "null mesh argument");
+    if (!(std::isfinite(centre[0]) && std::isfinite(centre[1])))
+        return set_error(VRC_ERR_INVALID, "the axis must be finite");
+    const int32_t n[3] = {nr, 1, nz};
+    const double *src[3] = {radii, nullptr, z_planes};
+    for (int a = 0; a < 3; a += 2) {
+        if (n[a] <= 0 || n[a] > (1 << 20)) return set_error(VRC_ERR_INVALID, "nr and nz must be in 1..2^20");
+        for (int k = 0; k <= n[a]; ++k) {
+            if (!std::isfinite(src[a][k])) return set_error(VRC_ERR_INVALID, "radii and planes must be finite");
+            if (k > 0 && !(src[a][k] > src[a][k - 1]))
+                return set_error(VRC_ERR_INVALID, "radii and planes must be strictly increasing");
+        }
+    }
+    if (radii[0] != 0.0) return set_error(VRC_ERR_INVALID, "the first radius must be 0");
+    static const double placeholder[2] = {0.0, 1.0};
+    src[1] = placeholder;
+    const double lo[3] = {centre[0], centre[1], z_planes[0]};
+    const double h[3] = {radii[nr] / nr, 1.0, (z_planes[nz] - z_planes[0]) / nz};  // informative only
+    return store_mesh(ctx, mesh_id, lo, h, n, mat, src, true);
 }
 
 vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho)
@@ -653,6 +728,29 @@ vrc_status vrc_cast_rays_noalloc(vrc_ctx *ctx, int tally_id, const vrc_ray_batch
     return VRC_OK;
 }
 
+vrc_status vrc_test_hook(vrc_ctx *ctx, int hook, int64_t value)
+{
+    if (vrc_status s = check_ctx(ctx)) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hook == VRC_TEST_SHORT_COUNT && (value == 0 || value == 1)) {
+        ctx->test_short_count = static_cast<int>(value);
+        return VRC_OK;
+    }
+    if (hook == VRC_TEST_ENTRIES_JUMP && value >= -1 && value <= 1) {
+        ctx->test_entries_jump = static_cast<int>(value);
+        return VRC_OK;
+    }
+    if (hook == VRC_TEST_RECORD_BUDGET && value >= 0) {
+        hipDeviceProp_t prop;
+        VRC_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
+        const size_t dflt =
+            std::min(std::max(static_cast<size_t>(prop.totalGlobalMem) / 8, size_t(2) << 30), size_t(64) << 30);
+        ctx->sort_scratch.record_budget = value == 0 ? dflt : std::max(static_cast<size_t>(value), size_t(1) << 20);
+        return VRC_OK;
+    }
+    return set_error(VRC_ERR_INVALID, "unknown test hook or value");
+}
+
 vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision, int64_t n, int32_t fp64,
                           const void *px, const void *py, const void *pz, const void *e, const void *w,
                           const double detector[3], double *scores, void *hip_stream)
@@ -671,6 +769,7 @@ vrc_status vrc_next_event(vrc_ctx *ctx, int32_t mesh_id, vrc_precision precision
     if (mesh_id < 0 || mesh_id >= kMaxMeshes || !ctx->meshes[mesh_id].set)
         return set_error(VRC_ERR_INVALID, "no such mesh");
     const MeshHost &mesh = ctx->meshes[mesh_id];
+    if (mesh.rz) return set_error(VRC_ERR_INVALID, "the next-event estimator walks Cartesian meshes");
     if (!ctx->xs.set) return set_error(VRC_ERR_STATE, "no cross-section tables set");
     if (mesh.max_mat >= ctx->xs.n_mat) return set_error(VRC_ERR_STATE, "mesh has a material id >= n_mat");
     if (precision != VRC_P64 && !ctx->xs.f32_ok)
@@ -700,6 +799,7 @@ vrc_status vrc_read_tally(vrc_ctx *ctx, int tally_id, double *out)
     if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
     (void)hipSetDevice(ctx->device);
     VRC_HIP(ctx, hipDeviceSynchronize());
+    if (vrc_status s = check_device_flags(ctx)) return s;
     const size_t n = static_cast<size_t>(t->nvox) * t->n_bins;
     if (t->prec == VRC_P32_KAHAN) {
         double *tmp = nullptr;
@@ -723,6 +823,7 @@ vrc_status vrc_load_tally(vrc_ctx *ctx, int tally_id, const double *in)
     if (!t) return set_error(VRC_ERR_INVALID, "no such tally");
     (void)hipSetDevice(ctx->device);
     VRC_HIP(ctx, hipDeviceSynchronize());
+    if (vrc_status s = check_device_flags(ctx)) return s;
     const size_t n = static_cast<size_t>(t->nvox) * t->n_bins;
     if (t->prec == VRC_P32_KAHAN) {
         double *tmp = nullptr;
@@ -792,7 +893,8 @@ vrc_status vrc_count_segments(vrc_ctx *ctx, int mesh_id, vrc_precision precision
         return set_error(VRC_ERR_INVALID, "mesh_id does not name a set mesh");
     if (precision != VRC_P64 && precision != VRC_P32_T64 && precision != VRC_P32_KAHAN && precision != VRC_P32_D64)
         return set_error(VRC_ERR_INVALID, "unknown precision");
-    if (ctx->meshes[mesh_id].rect && precision != VRC_P64 && !ctx->meshes[mesh_id].rect_f32_ok)
+    if ((ctx->meshes[mesh_id].rect || ctx->meshes[mesh_id].rz) && precision != VRC_P64 &&
+        !ctx->meshes[mesh_id].rect_f32_ok)
         return set_error(VRC_ERR_INVALID, "mesh planes are not strictly increasing once rounded to FP32");
     (void)hipSetDevice(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -1090,6 +1192,8 @@ vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batche
         if (fp64 != b.fp64) return set_error(VRC_ERR_INVALID, "batches of one call must share the ray type");
         if (vrc_status st = check_cast_ready(ctx, t)) return st;
         kinds = kinds || ctx->meshes[t->mesh_id].rect || ctx->meshes[t->mesh_id].dens;
+        if (ctx->meshes[t->mesh_id].rz)
+            return set_error(VRC_ERR_INVALID, "a tally on an R-Z mesh is cast by vrc_cast_rays");
         if (b.n == 0) continue;
         if (!b.ox || !b.oy || !b.oz || !b.ux || !b.uy || !b.uz || !b.e || !b.w)
             return set_error(VRC_ERR_INVALID, "null ray array in a batch");

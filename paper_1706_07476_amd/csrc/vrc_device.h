@@ -288,39 +288,32 @@ struct Walker {
     }
 
     // Resume at voxel (kx, ky, kz), entered at ray parameter cur, limited to
-    // that voxel's tile.  The per-axis crossings are recomputed from the plane
-    // indices exactly as step() computes them, so the pieces are
-    // bit-identical to those of the uninterrupted walk.  The voxel index the
-    // walk carries (and hands to its sink) is the voxel's position in the
-    // tile, x fastest: (i mod 16) + 16 (j mod 16) + 256 (k mod 16).
+    // that voxel's tile, from the origin and the inverse direction the
+    // whole-mesh walk computed (ix = 1 / ux ...).  The per-axis crossings are
+    // recomputed from the plane indices exactly as step() computes them, so
+    // the pieces are bit-identical to those of the uninterrupted walk.  The
+    // mesh exit is not needed: it is a crossing of a boundary plane, which is
+    // also the far side of a tile at the mesh boundary, where the tile limit
+    // ends the walk after the same pieces (any further steps at the exit
+    // parameter have length 0 and are not scored).  The voxel index the walk
+    // carries (and hands to its sink) is the voxel's position in the tile, x
+    // fastest: (i mod 16) + 16 (j mod 16) + 256 (k mod 16).
     template <class Mat>
-    __device__ __forceinline__ void resume_tile(const MeshP<R> &M, const Mat &mats, R ox_, R oy_, R oz_, R ux, R uy,
-                                                R uz, int kx_, int ky_, int kz_, R cur_)
+    __device__ __forceinline__ void resume_tile(const MeshP<R> &M, const Mat &mats, R ox_, R oy_, R oz_, R ix_, R iy_,
+                                                R iz_, int kx_, int ky_, int kz_, R cur_)
     {
-        const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
-        const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
         const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
         ox = ox_;
         oy = oy_;
         oz = oz_;
-        ix = R(1) / ux;
-        iy = R(1) / uy;
-        iz = R(1) / uz;
+        ix = ix_;
+        iy = iy_;
+        iz = iz_;
         const bool px = __builtin_isinf(ix), py = __builtin_isinf(iy), pz = __builtin_isinf(iz);
-        R t_enter = R(0);
         t_exit = Num<R>::inf();
-        if constexpr (RECT) {
-            clip_planes(M.pl[0][0], M.pl[0][nx], ox, ix, px, t_enter, t_exit);
-            clip_planes(M.pl[1][0], M.pl[1][ny], oy, iy, py, t_enter, t_exit);
-            clip_planes(M.pl[2][0], M.pl[2][nz], oz, iz, pz, t_enter, t_exit);
-        } else {
-            clip_axis(lox, hx, nx, ox, ix, px, t_enter, t_exit);
-            clip_axis(loy, hy, ny, oy, iy, py, t_enter, t_exit);
-            clip_axis(loz, hz, nz, oz, iz, pz, t_enter, t_exit);
-        }
-        sx = px ? 0 : (ux > R(0) ? 1 : -1);
-        sy = py ? 0 : (uy > R(0) ? 1 : -1);
-        sz = pz ? 0 : (uz > R(0) ? 1 : -1);
+        sx = px ? 0 : (ix > R(0) ? 1 : -1);
+        sy = py ? 0 : (iy > R(0) ? 1 : -1);
+        sz = pz ? 0 : (iz > R(0) ? 1 : -1);
         kx = kx_;
         ky = ky_;
         kz = kz_;
@@ -329,9 +322,9 @@ struct Walker {
             ty = py ? Num<R>::inf() : (M.pl[1][ky + (sy > 0 ? 1 : 0)] - oy) * iy;
             tz = pz ? Num<R>::inf() : (M.pl[2][kz + (sz > 0 ? 1 : 0)] - oz) * iz;
         } else {
-            tx = px ? Num<R>::inf() : (plane(lox, hx, kx + (sx > 0 ? 1 : 0)) - ox) * ix;
-            ty = py ? Num<R>::inf() : (plane(loy, hy, ky + (sy > 0 ? 1 : 0)) - oy) * iy;
-            tz = pz ? Num<R>::inf() : (plane(loz, hz, kz + (sz > 0 ? 1 : 0)) - oz) * iz;
+            tx = px ? Num<R>::inf() : (plane(M.lo[0], M.h[0], kx + (sx > 0 ? 1 : 0)) - ox) * ix;
+            ty = py ? Num<R>::inf() : (plane(M.lo[1], M.h[1], ky + (sy > 0 ? 1 : 0)) - oy) * iy;
+            tz = pz ? Num<R>::inf() : (plane(M.lo[2], M.h[2], kz + (sz > 0 ? 1 : 0)) - oz) * iz;
         }
         cur = cur_;
         budget = 3 * kTileEdge + 3;
@@ -343,6 +336,37 @@ struct Walker {
         dvy = sy * kTileEdge;
         dvz = sz * kTileEdge * kTileEdge;
         vox = (kx - ax0) + kTileEdge * ((ky - ay0) + kTileEdge * (kz - az0));
+        m = mats(vox, kx, ky, kz);
+    }
+
+    // Continue a walk begun with start() at voxel (kx_, ky_, kz_), entered at
+    // ray parameter cur_, up to the exit of that voxel's tile (or of the
+    // mesh).  The crossings are recomputed from the plane indices as step()
+    // computes them, so the pieces are those of the uninterrupted walk; the
+    // voxel index stays the mesh's.
+    template <class Mat>
+    __device__ __forceinline__ void enter_tile(const MeshP<R> &M, const Mat &mats, int kx_, int ky_, int kz_, R cur_)
+    {
+        const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
+        kx = kx_;
+        ky = ky_;
+        kz = kz_;
+        if constexpr (RECT) {
+            tx = sx == 0 ? Num<R>::inf() : (M.pl[0][kx + (sx > 0 ? 1 : 0)] - ox) * ix;
+            ty = sy == 0 ? Num<R>::inf() : (M.pl[1][ky + (sy > 0 ? 1 : 0)] - oy) * iy;
+            tz = sz == 0 ? Num<R>::inf() : (M.pl[2][kz + (sz > 0 ? 1 : 0)] - oz) * iz;
+        } else {
+            tx = sx == 0 ? Num<R>::inf() : (plane(M.lo[0], M.h[0], kx + (sx > 0 ? 1 : 0)) - ox) * ix;
+            ty = sy == 0 ? Num<R>::inf() : (plane(M.lo[1], M.h[1], ky + (sy > 0 ? 1 : 0)) - oy) * iy;
+            tz = sz == 0 ? Num<R>::inf() : (plane(M.lo[2], M.h[2], kz + (sz > 0 ? 1 : 0)) - oz) * iz;
+        }
+        cur = cur_;
+        budget = 3 * kTileEdge + 3;
+        const int ax0 = kx & ~(kTileEdge - 1), ay0 = ky & ~(kTileEdge - 1), az0 = kz & ~(kTileEdge - 1);
+        stop_x = sx > 0 ? (ax0 + kTileEdge < nx ? ax0 + kTileEdge : nx) : ax0 - 1;
+        stop_y = sy > 0 ? (ay0 + kTileEdge < ny ? ay0 + kTileEdge : ny) : ay0 - 1;
+        stop_z = sz > 0 ? (az0 + kTileEdge < nz ? az0 + kTileEdge : nz) : az0 - 1;
+        vox = kx + nx * (ky + ny * kz);
         m = mats(vox, kx, ky, kz);
     }
 
@@ -457,51 +481,66 @@ __device__ __forceinline__ int energy_bin(const TallyP &T, double E)
     return lo;
 }
 
-// Sigma_m(E) of every material (Sec. 3: hashed energy lookup, linear
-// interpolation) in the table precision R, written with 1/Sigma in the
-// scoring precision S to the lane's LDS column:
-// sig[m * stride + lane] = {Sigma, 1/Sigma (0 for Sigma = 0)}.
+// Interval of the energy grid holding E (Sec. 3: hashed energy lookup): the
+// log2-energy hash bin gives a starting interval, and a search that only
+// ever moves a step or two ends on the k with E[k] <= E < E[k+1] (k = 0 and
+// no interpolation below the table, k = K - 1 and none above it).
+template <typename R>
+__device__ __forceinline__ int xs_interval(const XsP<R> &X, const int32_t *hash, R E, bool &interp)
+{
+    const int K = X.K;
+    interp = false;
+    if (K == 1 || !(E >= X.E[0])) return 0;
+    if (E >= X.E[K - 1]) return K - 1;
+    float lg = __log2f(static_cast<float>(E));
+    float fb = (lg - X.l2e0) * X.inv_dl2;
+    int b = 0;
+    if (fb >= 0.f) b = fb < static_cast<float>(X.M) ? static_cast<int>(fb) : X.M - 1;
+    int k = hash[b];
+    while (k > 0 && X.E[k] > E) --k;
+    while (k < K - 2 && X.E[k + 1] <= E) ++k;
+    interp = true;
+    return k;
+}
+
+// Sigma_m(E) of material m on interval k (linear interpolation, Sec. 3),
+// in the table precision R, rounded to S.
+template <typename R, typename S>
+__device__ __forceinline__ S xs_value(const XsP<R> &X, int k, bool interp, R E, int m)
+{
+    const R *s0 = X.S + static_cast<int64_t>(k) * X.s_stride;
+    if (!interp) return static_cast<S>(s0[m]);
+    const R e0 = X.E[k];
+    const R de = X.E[k + 1] - e0;
+    const R dx = E - e0;
+    const R slope = (s0[X.s_stride + m] - s0[m]) / de;
+    return static_cast<S>(s0[m] + slope * dx);
+}
+
+// Sigma_m(E) of every material in the table precision R, written with
+// 1/Sigma in the scoring precision S to the lane's LDS column:
+// sig[m * stride] = {Sigma, 1/Sigma (0 for Sigma = 0)}.
 template <typename R, typename S>
 __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, R E,
                                           S (*sig)[2], int stride)
 {
-    const int K = X.K;
-    int k;
-    bool interp = false;
-    if (K == 1 || !(E >= X.E[0])) {
-        k = 0;
-    } else if (E >= X.E[K - 1]) {
-        k = K - 1;
-    } else {
-        float lg = __log2f(static_cast<float>(E));
-        float fb = (lg - X.l2e0) * X.inv_dl2;
-        int b = 0;
-        if (fb >= 0.f) b = fb < static_cast<float>(X.M) ? static_cast<int>(fb) : X.M - 1;
-        k = hash[b];
-        while (k > 0 && X.E[k] > E) --k;
-        while (k < K - 2 && X.E[k + 1] <= E) ++k;
-        interp = true;
+    bool interp;
+    const int k = xs_interval(X, hash, E, interp);
+    for (int m = 0; m < X.n_mat; ++m) {
+        const S v = xs_value<R, S>(X, k, interp, E, m);
+        sig[m * stride][0] = v;
+        sig[m * stride][1] = v > S(0) ? S(1) / v : S(0);
     }
-    const R *s0 = X.S + static_cast<int64_t>(k) * X.s_stride;
-    if (interp) {
-        const R e0 = X.E[k];
-        const R e1 = X.E[k + 1];
-        const R de = e1 - e0;
-        const R dx = E - e0;
-        const R *s1 = s0 + X.s_stride;
-        for (int m = 0; m < X.n_mat; ++m) {
-            R slope = (s1[m] - s0[m]) / de;
-            const S v = static_cast<S>(s0[m] + slope * dx);
-            sig[m * stride][0] = v;
-            sig[m * stride][1] = v > S(0) ? S(1) / v : S(0);
-        }
-    } else {
-        for (int m = 0; m < X.n_mat; ++m) {
-            const S v = static_cast<S>(s0[m]);
-            sig[m * stride][0] = v;
-            sig[m * stride][1] = v > S(0) ? S(1) / v : S(0);
-        }
-    }
+}
+
+// Sigma_m(E) of every material to the lane's LDS column, sig[m * stride][0]
+// (the reciprocals are not written).
+template <typename R, typename S>
+__device__ __forceinline__ void xs_lookup_sigma(const XsP<R> &X, const int32_t *hash, R E, S (*sig)[2], int stride)
+{
+    bool interp;
+    const int k = xs_interval(X, hash, E, interp);
+    for (int m = 0; m < X.n_mat; ++m) sig[m * stride][0] = xs_value<R, S>(X, k, interp, E, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,14 +552,19 @@ __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, 
 // product of the segments' e^{-x}; the optical depth tau is summed alongside
 // with Knuth's TwoSum (compensated), and at every tile entry the weight is
 // recomputed as w e^{-tau}, so its error stays at a few ulp however long the
-// ray is (a tile holds at most 3 * 16 - 2 pieces of one ray).  Because the
-// state at a tile entry is just (tau_hi, tau_lo), a cast split at tile
-// entries (the tile-split accumulation) scores bit-identically to an
-// uninterrupted one.
+// ray is (a tile holds at most 3 * 16 - 2 pieces of one ray).  The optical
+// depth across a tile of one material is added at the tile's exit as that
+// material's Sigma times the tile's chord (from the entry of its first piece
+// to the entry of the next tile's), across any other tile piece by piece.
+// The tile-split accumulation's entries pass takes the optical depth at a
+// tile entry by the same operations, so a cast split at tile entries scores
+// bit-identically to an uninterrupted one.
 template <typename R, class Put, bool DENS = false>
 struct Scorer {
     const R (*sig)[2];
     const DensPair<R> *dens = nullptr;  // DENS: per-voxel (rho, 1/rho) on the voxel's Sigma
+    const int8_t *tile_mat = nullptr;   // !DENS: per tile its one material or -1 (nullptr: every tile by pieces)
+    int ntx = 0, nty = 0;               // tiles per row and per layer of the mesh
     int stride;
     R w0;
     R w_in;
@@ -528,35 +572,43 @@ struct Scorer {
     R tau_lo;
     bool started;   // a piece has been scored
     uint32_t tile;  // tile_tag of the current tile
+    int tile_pm;    // the current tile's one material, or -1
+    R tile_t0;      // where the current tile's first piece starts
     Put &put;
     __device__ __forceinline__ Scorer(const R (*sig_)[2], int stride_, R w, Put &put_)
-        : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), started(false), tile(0), put(put_) {}
-    // Resume at the entry of the tile tagged tg with the optical depth
-    // accumulated before it; first: the tile holds the ray's first piece.
-    __device__ __forceinline__ void resume(R w, R th, R tl, uint32_t tg, bool first)
-    {
-        w0 = w;
-        w_in = w;
-        tau_hi = th;
-        tau_lo = tl;
-        started = true;
-        tile = tg;
-        if (!first) reanchor();
-    }
+        : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), started(false), tile(0), tile_pm(-1),
+          tile_t0(0), put(put_) {}
     __device__ __forceinline__ void reanchor()
     {
         R G, unused;
         attenuation(tau_hi, G, unused);
         w_in = (w0 * G) * (R(1) - tau_lo);
     }
+    __device__ __forceinline__ void add_tau(R x)
+    {
+        const R t = tau_hi + x;
+        const R bv = t - tau_hi;
+        const R err = (tau_hi - (t - bv)) + (x - bv);
+        tau_hi = t;
+        tau_lo += err;
+    }
     template <typename L>
-    __device__ __forceinline__ void operator()(int32_t vox, int m, L len, int ci, int cj, int ck, L)
+    __device__ __forceinline__ void operator()(int32_t vox, int m, L len, int ci, int cj, int ck, L t0)
     {
         const uint32_t tg = tile_tag(ci >> kTileBits, cj >> kTileBits, ck >> kTileBits);
         if (tg != tile || !started) {
-            if (started) reanchor();
+            if (started) {
+                if (tile_pm >= 0) add_tau(sig[tile_pm * stride][0] * (static_cast<R>(t0) - tile_t0));
+                reanchor();
+            }
             started = true;
             tile = tg;
+            tile_pm = -1;
+            if constexpr (!DENS) {
+                if (tile_mat != nullptr)
+                    tile_pm = tile_mat[(ci >> kTileBits) + ntx * ((cj >> kTileBits) + nty * (ck >> kTileBits))];
+            }
+            tile_t0 = static_cast<R>(t0);
         }
         const R l = static_cast<R>(len);
         R s = sig[m * stride][0];
@@ -571,11 +623,7 @@ struct Scorer {
         attenuation(x, g, em);
         const R f = s > R(0) ? (w_in * em) * is : w_in * l;
         put(vox, l, f, ci, cj, ck);
-        const R t = tau_hi + x;
-        const R bv = t - tau_hi;
-        const R err = (tau_hi - (t - bv)) + (x - bv);
-        tau_hi = t;
-        tau_lo += err;
+        if (tile_pm < 0) add_tau(x);
         w_in = w_in * g;
     }
 };
@@ -707,7 +755,13 @@ __device__ __forceinline__ void cast_one(const MeshP<R> &M, const XsP<R> &X, con
 {
     xs_lookup(X, hash, E, mysig, bd);
     Scorer<S, Put, DENS> sc(mysig, bd, static_cast<S>(w), put);
-    if constexpr (DENS) sc.dens = density_of<S>(M);
+    if constexpr (DENS) {
+        sc.dens = density_of<S>(M);
+    } else {
+        sc.tile_mat = M.tile_mat;
+        sc.ntx = (M.n[0] + kTileEdge - 1) >> kTileBits;
+        sc.nty = (M.n[1] + kTileEdge - 1) >> kTileBits;
+    }
     walk<R, Scorer<S, Put, DENS>, RECT>(M, ox, oy, oz, ux, uy, uz, sc);
 }
 

@@ -39,6 +39,9 @@ struct MeshP {
     R h[3];
     int32_t n[3];
     const uint8_t *mat;  // n0*n1*n2 material ids, x fastest
+    // per tile of 16^3 voxels (x fastest): its material if it holds one only, else -1; nullptr for a
+    // mesh with density factors (the optical depth across such a tile is its Sigma times the chord)
+    const int8_t *tile_mat = nullptr;
     // rectilinear mesh: per axis a device table of n_a + 1 increasing planes
     // (walks instantiated for rectilinear meshes read these instead of lo + k h)
     const R *pl[3] = {nullptr, nullptr, nullptr};
@@ -111,6 +114,9 @@ struct SortScratch {
     size_t sorted_cap = 0, hist_cap = 0, row_off_cap = 0;
     size_t key_tot_cap = 0, key_base_cap = 0, ordered_cap = 0, bucket_cap = 0, partial_cap = 0;
     std::map<std::pair<const void *, size_t>, int> occupancy;  // (kernel, LDS bytes) -> resident blocks per CU
+    // record bytes of one sub-launch: room for the most tiles every ray of it could cross (an eighth of
+    // the device's memory, 2 to 64 GiB: the 256^3 mesh's 1e7 rays in one sub-launch on a 288 GB GPU)
+    size_t record_budget = size_t(2) << 30;
     hipEvent_t done = nullptr;   // after the last kernel that used the scratch
     hipStream_t stream = nullptr;
     bool busy = false;
@@ -167,6 +173,9 @@ struct MeshHost {
     // (host FP64, device FP64 and FP32 copies); lo holds the first planes
     bool rect = false;
     bool rect_f32_ok = false;  // the planes stay strictly increasing in FP32
+    // R-Z (cylindrical) mesh: n = {nr, 1, nz}, lo[0], lo[1] the axis, the plane tables radii[0..nr],
+    // a placeholder {0, 1} and z[0..nz] (rect_f32_ok covers them); cast by the kernels of vrc_rz.hip
+    bool rz = false;
     std::vector<double> h_planes;
     double *d_pl64 = nullptr;
     float *d_pl32 = nullptr;
@@ -181,6 +190,8 @@ struct MeshHost {
     int64_t nvox = 0;
     int max_mat = 0;
     uint8_t *d_mat = nullptr;
+    int8_t *d_tile_mat = nullptr;  // per 16^3 tile: its material if it holds one only, else -1
+    double pure_frac = 0.0;        // fraction of the tiles that hold one material
     int users = 0;  // tallies that refer to it
 };
 
@@ -252,6 +263,7 @@ struct StageSlot {
 struct vrc_ctx {
     int device = 0;
     int n_cu = 0;
+    size_t lds_max = 65536;  // LDS bytes one block may use on the device
     std::mutex mu;
     vrc::MeshHost meshes[vrc::kMaxMeshes];
     vrc::XsHost xs;
@@ -276,6 +288,10 @@ struct vrc_ctx {
     std::vector<double> walk_rec[8];  // rays recorded by the last walker run
     std::atomic<int> sticky{0};
     hipError_t noalloc_init = hipErrorNotInitialized;  // the allocation-free cast's scratch lookup
+    // device flag of the kernels' consistency checks (nonzero: a check failed), read by vrc_read_tally
+    uint32_t *d_check = nullptr;
+    int test_short_count = 0;    // test hooks (vrc_test_hook)
+    int test_entries_jump = -1;
 };
 
 namespace vrc {
@@ -285,6 +301,8 @@ vrc_status set_error(vrc_status st, const std::string &msg);
 vrc_status device_error(vrc_ctx *ctx, hipError_t e, const char *what);
 // Tables, mesh and material ids ready for casting into tally t.
 vrc_status check_cast_ready(vrc_ctx *ctx, const TallyHost *t);
+// After a device synchronisation: VRC_ERR_DEVICE (sticky) if a kernel's consistency check failed.
+vrc_status check_device_flags(vrc_ctx *ctx);
 // Upload a descriptor table through slot bs and run the persistent kernel.
 vrc_status run_batched(vrc_ctx *ctx, BatchedSlot &bs, const BatchedShape &shape, vrc_precision prec, bool fp64,
                        const std::vector<BatchDescDev> &desc, int64_t items, hipStream_t s);
@@ -316,6 +334,12 @@ struct BatchRef {
     int64_t begin;
 };
 
+// R-Z meshes (vrc_rz.hip): cast (tr == nullptr) or trace, and segment counts
+// per ray (counts) and/or added to *total.
+hipError_t launch_cast_rz(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
+                          bool rays_fp64, const TraceP *tr, hipStream_t s);
+hipError_t launch_count_rz(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
+                           bool rays_fp64, int64_t *counts, unsigned long long *total, hipStream_t s);
 // Tile-sorted accumulation (vrc_sorted.hip): usable for this tally and mesh?
 bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m);
 hipError_t launch_cast_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,

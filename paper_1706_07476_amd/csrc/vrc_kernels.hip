@@ -197,6 +197,7 @@ MeshP<R> mesh_args(const MeshHost &m)
         p.n[a] = m.n[a];
     }
     p.mat = m.d_mat;
+    p.tile_mat = m.dens ? nullptr : m.d_tile_mat;
     p.rho32 = m.d_rho32;
     p.rho64 = m.d_rho64;
     p.rhos32 = m.d_rhos32;
@@ -405,6 +406,7 @@ hipError_t launch_count_total_impl(const vrc_ctx &ctx, const MeshHost &m, vrc_pr
 hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
                        bool rays_fp64, hipStream_t s)
 {
+    if (m.rz) return launch_cast_rz(ctx, t, m, rays, rays_fp64, nullptr, s);
     if (m.dens)
         return m.rect ? launch_cast_impl<true, true>(ctx, t, m, rays, rays_fp64, s)
                       : launch_cast_impl<false, true>(ctx, t, m, rays, rays_fp64, s);
@@ -415,6 +417,7 @@ hipError_t launch_cast(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m
 hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const RaysP &rays,
                         bool rays_fp64, const TraceP &tr, hipStream_t s)
 {
+    if (m.rz) return launch_cast_rz(ctx, t, m, rays, rays_fp64, &tr, s);
     if (m.dens)
         return m.rect ? launch_trace_impl<true, true>(ctx, t, m, rays, rays_fp64, tr, s)
                       : launch_trace_impl<false, true>(ctx, t, m, rays, rays_fp64, tr, s);
@@ -425,6 +428,7 @@ hipError_t launch_trace(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &
 hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
                         bool rays_fp64, int64_t *counts, hipStream_t s)
 {
+    if (m.rz) return launch_count_rz(ctx, m, prec, rays, rays_fp64, counts, nullptr, s);
     return m.rect ? launch_count_impl<true>(ctx, m, prec, rays, rays_fp64, counts, s)
                   : launch_count_impl<false>(ctx, m, prec, rays, rays_fp64, counts, s);
 }
@@ -432,6 +436,7 @@ hipError_t launch_count(const vrc_ctx &ctx, const MeshHost &m, vrc_precision pre
 hipError_t launch_count_total(const vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, const RaysP &rays,
                               bool rays_fp64, unsigned long long *total, hipStream_t s)
 {
+    if (m.rz) return launch_count_rz(ctx, m, prec, rays, rays_fp64, nullptr, total, s);
     return m.rect ? launch_count_total_impl<true>(ctx, m, prec, rays, rays_fp64, total, s)
                   : launch_count_total_impl<false>(ctx, m, prec, rays, rays_fp64, total, s);
 }

@@ -178,8 +178,8 @@ double percentile(std::vector<double> v, double q)
 
 // Launch one group of requests (same tally form and ray type) on stream s:
 // the persistent kernel for requests on plain uniform meshes, and before it
-// one plain cast per request on a rectilinear mesh or a mesh with density
-// factors (the persistent kernel walks plain uniform meshes only).  The
+// one plain cast per request on a rectilinear or R-Z mesh or a mesh with
+// density factors (the persistent kernel walks plain uniform meshes only).  The
 // slot's event, recorded after the last launch, marks the group done.
 vrc_status launch_group(vrc_ctx *ctx, ServeState &S, std::vector<ServeRequest> &reqs, int slot, hipStream_t s)
 {
@@ -195,13 +195,13 @@ vrc_status launch_group(vrc_ctx *ctx, ServeState &S, std::vector<ServeRequest> &
             prec = t->prec;
             const size_t el = r.fp64 ? 8 : 4;
             const MeshHost &m = ctx->meshes[t->mesh_id];
-            if (m.rect || m.dens) {
+            if (m.rect || m.dens || m.rz) {
                 RaysP rays;
                 const void **p[8] = {&rays.ox, &rays.oy, &rays.oz, &rays.ux, &rays.uy, &rays.uz, &rays.e, &rays.w};
                 for (int k = 0; k < 8; ++k) *p[k] = S.d_ring + r.ring_off + k * el * static_cast<size_t>(r.n);
                 rays.n = r.n;
                 hipError_t e = launch_cast(*ctx, *t, m, rays, r.fp64 != 0, s);
-                if (e != hipSuccess) return device_error(ctx, e, "serving cast on a rectilinear or density mesh");
+                if (e != hipSuccess) return device_error(ctx, e, "serving cast on a rectilinear, density or R-Z mesh");
                 continue;
             }
             BatchDescDev d;
@@ -304,8 +304,10 @@ void dispatcher_main(vrc_ctx *ctx, ServeState *Sp)
                 S.next_stream = (S.next_stream + 1) % static_cast<int>(S.streams.size());
                 lk.unlock();
                 hipError_t e2 = hipStreamWaitEvent(s, S.stage_copied[b], 0);
+                // the counting walks go first: the slot's event, recorded after the casts, then also
+                // marks them done, so the requests' ring space is not freed while they still read it
+                if (e2 == hipSuccess && S.cfg.count_segments) count_group(ctx, S, part, s);
                 vrc_status st = e2 == hipSuccess ? launch_group(ctx, S, part, slot, s) : VRC_ERR_DEVICE;
-                if (st == VRC_OK && S.cfg.count_segments) count_group(ctx, S, part, s);
                 lk.lock();
                 if (st != VRC_OK) { S.thread_error = e2 != hipSuccess ? e2 : hipErrorLaunchFailure; break; }
                 ServeLaunch L;

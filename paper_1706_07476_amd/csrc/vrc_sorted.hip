@@ -49,6 +49,9 @@ constexpr int kTileVoxels = kTileEdge * kTileEdge * kTileEdge;  // 4096
 constexpr int kLocalBits = 3 * kTileBits;                        // 12
 constexpr int kMaxKeys = 4096;
 constexpr uint32_t kFirst = 1u << 31;  // the record is the ray's first tile
+// Fraction of a mesh's tiles holding one material from which the entries
+// pass jumps over such tiles instead of walking them.
+constexpr double kJumpMinPure = 0.5;
 
 // How a finished tile goes into the tally.
 enum Flush {
@@ -60,7 +63,9 @@ enum Flush {
 // One tile entry of one ray.  code: kFirst | key << 12 | voxel within tile.
 template <typename R, typename S>
 struct __align__(16) Entry {
-    R ox, oy, oz, ux, uy, uz, e, w;
+    R ox, oy, oz;
+    R ix, iy, iz;  // 1 / direction, as the walk computes it (+-inf on an axis the ray runs parallel to)
+    R e, w;
     R t0;              // ray parameter where the first piece in the tile starts
     S tau_hi, tau_lo;  // compensated optical depth before the tile
     uint32_t code;
@@ -95,6 +100,16 @@ __device__ __forceinline__ int axis_index(R p, R lo, R inv_h, int n)
 
 __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
 
+// Voxel index of coordinate p on a uniform axis (inverse spacing inv_h),
+// clamped into [k0, k1] (NaN -> k0): a starting guess only.
+template <typename R>
+__device__ __forceinline__ int guess_in(R p, R lo, R inv_h, int k0, int k1)
+{
+    const R g = (p - lo) * inv_h;
+    if (!(g >= static_cast<R>(k0))) return k0;
+    return g < static_cast<R>(k1) ? static_cast<int>(g) : k1;
+}
+
 // Pieces of a whole-mesh walk, estimated from the voxels of the clipped
 // entry and exit points (0 if the ray misses the mesh).
 template <typename R>
@@ -115,18 +130,24 @@ __device__ __forceinline__ int ray_pieces_estimate(const MeshP<R> &M, R ox, R oy
            iabs(axis_index(oz + t1 * uz, loz, gz, nz) - axis_index(oz + t0 * uz, loz, gz, nz)) + 1;
 }
 
+// a / b for estimates (the fast single-precision division; FP64 as is).
+__device__ __forceinline__ float approx_div(float a, float b) { return __fdividef(a, b); }
+__device__ __forceinline__ double approx_div(double a, double b) { return a / b; }
+
 // Exit parameter of one axis' slab [lo + a h, lo + b h) for a ray leaving
-// through the face it moves towards (infinity if it runs parallel).
+// through the face it moves towards (infinity if it runs parallel); inv is
+// 1 / direction.
 template <typename R>
-__device__ __forceinline__ R slab_exit(R lo, R h, int a, int b, R o, R u)
+__device__ __forceinline__ R slab_exit(R lo, R h, int a, int b, R o, R inv)
 {
-    if (u == R(0)) return Num<R>::inf();
-    return (plane(lo, h, u > R(0) ? b : a) - o) / u;
+    if (__builtin_isinf(inv)) return Num<R>::inf();
+    return (plane(lo, h, inv > R(0) ? b : a) - o) * inv;
 }
 
-// Pieces of a walk resumed at voxel (ci, cj, ck) up to the exit of its tile.
+// Pieces of a walk resumed at voxel (ci, cj, ck) up to the exit of its tile
+// (an estimate: it orders the work, never changes a result).
 template <typename R>
-__device__ __forceinline__ int tile_pieces_estimate(const MeshP<R> &M, R ox, R oy, R oz, R ux, R uy, R uz, int ci,
+__device__ __forceinline__ int tile_pieces_estimate(const MeshP<R> &M, R ox, R oy, R oz, R ix, R iy, R iz, int ci,
                                                     int cj, int ck)
 {
     const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
@@ -135,15 +156,15 @@ __device__ __forceinline__ int tile_pieces_estimate(const MeshP<R> &M, R ox, R o
     const int bx = ax + kTileEdge < M.n[0] ? ax + kTileEdge : M.n[0];
     const int by = ay + kTileEdge < M.n[1] ? ay + kTileEdge : M.n[1];
     const int bz = az + kTileEdge < M.n[2] ? az + kTileEdge : M.n[2];
-    R t = slab_exit(lox, hx, ax, bx, ox, ux);
-    const R ty = slab_exit(loy, hy, ay, by, oy, uy);
-    const R tz = slab_exit(loz, hz, az, bz, oz, uz);
+    R t = slab_exit(lox, hx, ax, bx, ox, ix);
+    const R ty = slab_exit(loy, hy, ay, by, oy, iy);
+    const R tz = slab_exit(loz, hz, az, bz, oz, iz);
     t = ty < t ? ty : t;
     t = tz < t ? tz : t;
     if (!(t < Num<R>::inf())) return 1;
-    const int ex = axis_index(ox + t * ux, lox, R(1) / hx, M.n[0]);
-    const int ey = axis_index(oy + t * uy, loy, R(1) / hy, M.n[1]);
-    const int ez = axis_index(oz + t * uz, loz, R(1) / hz, M.n[2]);
+    const int ex = axis_index(ox + approx_div(t, ix), lox, R(1) / hx, M.n[0]);
+    const int ey = axis_index(oy + approx_div(t, iy), loy, R(1) / hy, M.n[1]);
+    const int ez = axis_index(oz + approx_div(t, iz), loz, R(1) / hz, M.n[2]);
     const int cx = ex < ax ? ax : (ex >= bx ? bx - 1 : ex);
     const int cy = ey < ay ? ay : (ey >= by ? by - 1 : ey);
     const int cz = ez < az ? az : (ez >= bz ? bz - 1 : ez);
@@ -410,6 +431,8 @@ struct EntryArgs {
     const uint32_t *key_base; // n_keys + 1: first record of each key
     void *sorted;             // the records in key-major order (entries pass)
     int64_t cap;              // records sorted has room for
+    uint32_t *check;          // set to 1 when a block's records for a key differ from the counting pass's
+    int short_count;          // test hook: the counting pass reports one entry fewer (block 0)
 };
 
 // The length-ordered rays are dealt out in slices of 64 (one per wavefront,
@@ -507,109 +530,149 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
         });
     }
     __syncthreads();
+    if (A.short_count && blockIdx.x == 0 && threadIdx.x == 0) {
+        // test hook: report one tile entry fewer than found (the entries pass must notice)
+        for (int k = 0; k < A.g.n_keys; ++k) {
+            if (s_hist[k] > 0u) {
+                --s_hist[k];
+                break;
+            }
+        }
+    }
+    __syncthreads();
     uint32_t *row = A.hist + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
     for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) row[k] = s_hist[k];
 }
 
-// Walk sink of the entries pass: the optical depth as the score sums it
-// (same products, same TwoSum), and a record at every tile entry, written
-// straight to its place in key-major order (the block's next place for the
-// key, from the counting pass).
+// Voxel index on one axis of a walk at ray parameter t (after every crossing
+// at or before t), searched inside [k_lo, k_hi] from a guess: u > 0 the
+// largest k with T(k) <= t, u < 0 the smallest k with T(k + 1) <= t (the
+// start-voxel rule of the walk, at t instead of the mesh entry).
+template <typename R, class Planes>
+__device__ __forceinline__ int index_at(const Planes &X, int k_lo, int k_hi, int guess, R o, R inv, int s, R t)
+{
+    int k = guess < k_lo ? k_lo : (guess > k_hi ? k_hi : guess);
+    if (s > 0) {
+        while (k > k_lo && (X(k) - o) * inv > t) --k;
+        while (k < k_hi && (X(k + 1) - o) * inv <= t) ++k;
+    } else {
+        while (k < k_hi && (X(k + 1) - o) * inv > t) ++k;
+        while (k > k_lo && (X(k) - o) * inv <= t) --k;
+    }
+    return k;
+}
+
+// Optical depth of a walk in the entries pass: the sum of Sigma l over its
+// pieces as the score sums it (same products, same TwoSum).
 template <typename R, typename S, bool DENS>
-struct EmitEntries {
+struct TauSum {
     const S (*sig)[2];
-    const S *cur;  // DENS: the factor of the voxel being walked (loaded with its material)
-    int shift;  // log2 of the LDS column stride (the block size)
-    S tau_hi, tau_lo;
-    uint32_t tile;  // tile_tag of the current tile
-    bool started;   // a piece has been seen
-    R ox, oy, oz, ux, uy, uz, e, w;
-    int key0;  // bin * n_tiles
+    const S *dcur;  // DENS: the factor of the voxel being walked (loaded with its material)
+    int shift;      // log2 of the LDS column stride (the block size)
+    S hi, lo;
+    __device__ __forceinline__ void add(S x)
+    {
+        const S t = hi + x;
+        const S bv = t - hi;
+        lo += (hi - (t - bv)) + (x - bv);
+        hi = t;
+    }
+    __device__ __forceinline__ void operator()(int32_t, int m, R len, int, int, int, R)
+    {
+        S sg = sig[m << shift][0];
+        if constexpr (DENS) sg = sg * *dcur;
+        add(sg * static_cast<S>(len));
+    }
+};
+
+// Where the entries pass writes a ray's records, and the ray's fields they
+// carry.
+template <typename R, typename S>
+struct EntryOut {
+    R ox, oy, oz, ix, iy, iz, e, w;
+    uint32_t key0;
     SortGeom g;
+    uint32_t *s_next;
     Entry<R, S> *sorted;
     uint32_t cap;
-    uint32_t *next;  // LDS, per key
-    // A record whose place is taken but whose stores wait for the next tile
-    // entry (or the end of the ray's walk), so that the walk never waits for
-    // the atomic's return.
-    bool pend;
-    uint32_t pend_pos, pend_code;
-    R pend_t0;
-    S pend_th, pend_tl;
-    __device__ __forceinline__ void store_pending()
+    // The record of tile (ti, tj, tk), entered in voxel (ci, cj, ck) at t0
+    // with optical depth (hi, lo) before it.
+    __device__ __forceinline__ void write(int ti, int tj, int tk, int ci, int cj, int ck, R t0, S hi, S lo,
+                                          bool first) const
     {
+        const int tile = ti + g.ntx * (tj + g.nty * tk);
+        const uint32_t key = key0 + static_cast<uint32_t>(tile);
+        const uint32_t pos = atomicAdd(s_next + key, 1u);
         // the counting pass sized every key's run; the guard only keeps stores in bounds
-        if (pend && pend_pos < cap) {
+        if (pos < cap) {
             Entry<R, S> r;
             r.ox = ox;
             r.oy = oy;
             r.oz = oz;
-            r.ux = ux;
-            r.uy = uy;
-            r.uz = uz;
+            r.ix = ix;
+            r.iy = iy;
+            r.iz = iz;
             r.e = e;
             r.w = w;
-            r.t0 = pend_t0;
-            r.tau_hi = pend_th;
-            r.tau_lo = pend_tl;
-            r.code = pend_code;
-            sorted[pend_pos] = r;
+            r.t0 = t0;
+            r.tau_hi = hi;
+            r.tau_lo = lo;
+            r.code = (first ? kFirst : 0u) | (key << kLocalBits) | local_index(ci, cj, ck);
+            sorted[pos] = r;
         }
-        pend = false;
-    }
-    __device__ __forceinline__ void emit(bool first, int ci, int cj, int ck, R t0)
-    {
-        store_pending();
-        const int tl = (ci >> kTileBits) + g.ntx * ((cj >> kTileBits) + g.nty * (ck >> kTileBits));
-        const uint32_t key = static_cast<uint32_t>(key0 + tl);
-        pend_pos = atomicAdd(next + key, 1u);
-        pend_code = (first ? kFirst : 0u) | (key << kLocalBits) | local_index(ci, cj, ck);
-        pend_t0 = t0;
-        pend_th = tau_hi;
-        pend_tl = tau_lo;
-        pend = true;
-    }
-    __device__ __forceinline__ void reset(R ox_, R oy_, R oz_, R ux_, R uy_, R uz_, R e_, R w_, int key0_)
-    {
-        tau_hi = S(0);
-        tau_lo = S(0);
-        started = false;
-        ox = ox_;
-        oy = oy_;
-        oz = oz_;
-        ux = ux_;
-        uy = uy_;
-        uz = uz_;
-        e = e_;
-        w = w_;
-        key0 = key0_;
-    }
-    __device__ __forceinline__ void operator()(int32_t vox, int m, R len, int ci, int cj, int ck, R t0)
-    {
-        // Sigma first: its LDS read is then not queued behind the atomic of a tile entry
-        const S l = static_cast<S>(len);
-        S sg = sig[m << shift][0];
-        if constexpr (DENS) sg = sg * *cur;  // the score's own product, so tau matches
-        const S x = sg * l;
-        const uint32_t tg = tile_tag(ci >> kTileBits, cj >> kTileBits, ck >> kTileBits);
-        if (tg != tile || !started) {
-            const bool first = !started;
-            started = true;
-            tile = tg;
-            emit(first, ci, cj, ck, t0);  // the optical depth up to the entry, before this piece
-        }
-        const S t = tau_hi + x;
-        const S bv = t - tau_hi;
-        const S err = (tau_hi - (t - bv)) + (x - bv);
-        tau_hi = t;
-        tau_lo += err;
     }
 };
 
-// (FP32 walks: register budget for six wavefronts per SIMD, all that LDS allows)
-template <typename R, typename RT, typename S, bool RECT, bool DENS>
-__global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
-    entries_kernel(EntryArgs<R> A)
+// Walk sink of the entries pass when it walks every tile: at the first
+// piece of positive length in a tile it writes the tile's record (that
+// piece's voxel, where it starts, the optical depth before it).  The optical
+// depth across a tile of one material m is Sigma_m times the tile's chord,
+// from its first piece to the next tile's, added at the next tile as the
+// uninterrupted walk's Scorer adds it; across any other tile it is summed
+// piece by piece.
+template <typename R, typename S, bool DENS>
+struct EntrySink {
+    TauSum<R, S, DENS> tau;
+    EntryOut<R, S> out;
+    const int8_t *pure;  // per tile: its material if it holds one only, else -1 (nullptr: none)
+    uint32_t tag;        // tile_tag of the tile of the last piece
+    bool started;        // a record has been written for this ray
+    int pm_cur;          // the current tile's one material, or -1
+    R tile_t0;           // where the current tile's first piece starts
+    __device__ __forceinline__ void operator()(int32_t vox, int m, R len, int ci, int cj, int ck, R t0)
+    {
+        const int ti = ci >> kTileBits, tj = cj >> kTileBits, tk = ck >> kTileBits;
+        const uint32_t tg = tile_tag(ti, tj, tk);
+        if (!started || tg != tag) {
+            if (started && pm_cur >= 0)
+                tau.add(tau.sig[pm_cur << tau.shift][0] * (static_cast<S>(t0) - static_cast<S>(tile_t0)));
+            out.write(ti, tj, tk, ci, cj, ck, t0, tau.hi, tau.lo, !started);
+            started = true;
+            tag = tg;
+            pm_cur = pure != nullptr ? pure[ti + out.g.ntx * (tj + out.g.nty * tk)] : -1;
+            tile_t0 = t0;
+        }
+        if (pm_cur < 0) tau(vox, m, len, ci, cj, ck, t0);
+    }
+};
+
+// Entries pass: every block walks the rays of its deal and writes a record
+// at each tile where the walk has a piece of positive length, with the voxel
+// and parameter of that piece and the optical depth before it (the tiles of
+// the counting pass's tile walk, whose crossings are among the voxel
+// walk's).  Two ways, the same records:
+//   JUMP (most of the mesh's tiles hold one material): the walk goes tile by
+//     tile with the counting pass's tile walk; a tile of one material m is
+//     not walked (its optical depth is Sigma_m times its chord, the
+//     product the uninterrupted walk's Scorer takes), any other tile is
+//     walked voxel by voxel from the voxel the start-voxel rule gives at its
+//     entry parameter (the uninterrupted walk's voxel there);
+//   otherwise: one voxel walk through the whole mesh (EntrySink), fewer
+//     registers and no per-tile searches.
+// Each lane walks its own rays (its lane's ray of every round of the
+// block's deal); the rays of a wavefront are of about the same length.
+template <typename R, typename RT, typename S, bool RECT, bool DENS, bool JUMP>
+__global__ void __launch_bounds__(256) entries_kernel(EntryArgs<R> A)
 {
     __shared__ uint32_t s_next[kMaxKeys];
     const uint32_t *row = A.row_off + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
@@ -619,35 +682,138 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 && sizeof(S) == 4 ? 6 : 1)
     S(*sig)[2];
     stage_lds(A.xs, A.hash_in_lds, hash, sig);
     const int bd = blockDim.x;
+    const int shift = __ffs(bd) - 1;
     S(*mysig)[2] = sig + threadIdx.x;
     const int64_t n = A.rays.n;
     const RayDeal deal(n);
     S dcur = S(0), dnext = S(0);
-    EmitEntries<R, S, DENS> em{mysig, &dcur, __ffs(bd) - 1, S(0), S(0), 0u, false, R(0), R(0), R(0),
-                               R(0), R(0), R(0), R(0), R(0), 0, A.g, static_cast<Entry<R, S> *>(A.sorted),
-                               static_cast<uint32_t>(A.cap), s_next, false, 0u, 0u, R(0), S(0), S(0)};
     Walker<R, RECT> wk;
     const S *dens = factors_of<S>(A.mesh);
     const auto mats = [&] {
         if constexpr (DENS) return MeshMaterialsDens<S>{A.mesh.mat, dens, &dcur, &dnext};
         else return MeshMaterials{A.mesh.mat};
     }();
+    const MeshP<R> &M = A.mesh;
+    const int8_t *pure = DENS ? nullptr : M.tile_mat;
+    const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
+    const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
+    const R gx = R(1) / hx, gy = R(1) / hy, gz = R(1) / hz;
+    const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
     const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
+    const auto X = [&](int a) {
+        return [&M, a](int k) -> R {
+            if constexpr (RECT) return M.pl[a][k];
+            else return plane(M.lo[a], M.h[a], k);
+        };
+    };
+    // the next tile plane on each axis, as the counting pass computes it
+    const auto cross = [&](int a, R lo, R h, R o, R inv, int s, int t) -> R {
+        if (s == 0) return Num<R>::inf();
+        const int k = (t + (s > 0 ? 1 : 0)) << kTileBits;
+        if constexpr (RECT) return (M.pl[a][k < M.n[a] ? k : M.n[a]] - o) * inv;
+        else return (plane(lo, h, k) - o) * inv;
+    };
+    EntryOut<R, S> out;
+    out.g = A.g;
+    out.s_next = s_next;
+    out.sorted = static_cast<Entry<R, S> *>(A.sorted);
+    out.cap = static_cast<uint32_t>(A.cap);
     for (int64_t round = 0; deal.more(round); ++round) {
         const int64_t j = deal.ray(round);
         if (j >= n) continue;
         const RayRec<R> rr = ordered[j];
-        const R ox = rr.ox, oy = rr.oy, oz = rr.oz, ux = rr.ux, uy = rr.uy, uz = rr.uz, E = rr.e, wt = rr.w;
-        const int bin = energy_bin(A.tally, static_cast<double>(E));
+        const int bin = energy_bin(A.tally, static_cast<double>(rr.e));
         if (bin < 0) continue;
-        xs_lookup(A.xs, hash, E, mysig, bd);
-        em.reset(ox, oy, oz, ux, uy, uz, E, wt, bin * A.g.n_tiles);
-        if (!wk.start(A.mesh, ox, oy, oz, ux, uy, uz)) continue;
-        if constexpr (DENS) dnext = dens[wk.vox];  // the first voxel's pair (start() reads its material itself)
-        while (wk.step(A.mesh, em, mats)) {
+        if (!wk.start(M, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz)) continue;
+        if constexpr (DENS) dnext = dens[wk.vox];  // start() reads the first voxel's material itself
+        xs_lookup_sigma(A.xs, hash, rr.e, mysig, bd);  // the optical depth needs Sigma only
+        out.ox = rr.ox;
+        out.oy = rr.oy;
+        out.oz = rr.oz;
+        out.ix = wk.ix;
+        out.iy = wk.iy;
+        out.iz = wk.iz;
+        out.e = rr.e;
+        out.w = rr.w;
+        out.key0 = static_cast<uint32_t>(bin * A.g.n_tiles);
+        if constexpr (!JUMP) {
+            EntrySink<R, S, DENS> es{TauSum<R, S, DENS>{mysig, &dcur, shift, S(0), S(0)}, out, pure, 0u, false, -1,
+                                     R(0)};
+            while (wk.step(M, es, mats)) {
+            }
+        } else {
+            TauSum<R, S, DENS> ts{mysig, &dcur, shift, S(0), S(0)};
+            const R ox = rr.ox, oy = rr.oy, oz = rr.oz, ux = rr.ux, uy = rr.uy, uz = rr.uz;
+            int ti = wk.kx >> kTileBits, tj = wk.ky >> kTileBits, tk = wk.kz >> kTileBits;
+            const int sx = wk.sx, sy = wk.sy, sz = wk.sz;
+            const R ix = wk.ix, iy = wk.iy, iz = wk.iz;
+            R cx = cross(0, lox, hx, ox, ix, sx, ti);
+            R cy = cross(1, loy, hy, oy, iy, sy, tj);
+            R cz = cross(2, loz, hz, oz, iz, sz, tk);
+            R cur = wk.cur;
+            const R t_exit = wk.t_exit;
+            int ex = wk.kx, ey = wk.ky, ez = wk.kz;  // the walk's voxel at cur (kept on parallel axes)
+            bool first = true;
+            for (int guard = (nx + ny + nz) / kTileEdge + 6; guard > 0; --guard) {
+                const bool ax = (cx <= cy) && (cx <= cz);
+                const bool ay = !ax && (cy <= cz);
+                const R ta = ax ? cx : (ay ? cy : cz);
+                const bool last = !(ta < t_exit);
+                const R t_out = last ? t_exit : ta;
+                if (t_out - cur > R(0)) {
+                    // the voxel of the first piece in the tile
+                    const int x0 = ti << kTileBits, y0 = tj << kTileBits, z0 = tk << kTileBits;
+                    const int x1 = (x0 + kTileEdge < nx ? x0 + kTileEdge : nx) - 1;
+                    const int y1 = (y0 + kTileEdge < ny ? y0 + kTileEdge : ny) - 1;
+                    const int z1 = (z0 + kTileEdge < nz ? z0 + kTileEdge : nz) - 1;
+                    if (!first) {
+                        if constexpr (RECT) {
+                            if (sx != 0) ex = index_at(X(0), x0, x1, ex, ox, ix, sx, cur);
+                            if (sy != 0) ey = index_at(X(1), y0, y1, ey, oy, iy, sy, cur);
+                            if (sz != 0) ez = index_at(X(2), z0, z1, ez, oz, iz, sz, cur);
+                        } else {
+                            // a guess from the position (any guess is settled by the search)
+                            if (sx != 0)
+                                ex = index_at(X(0), x0, x1, guess_in(ox + cur * ux, lox, gx, x0, x1), ox, ix, sx, cur);
+                            if (sy != 0)
+                                ey = index_at(X(1), y0, y1, guess_in(oy + cur * uy, loy, gy, y0, y1), oy, iy, sy, cur);
+                            if (sz != 0)
+                                ez = index_at(X(2), z0, z1, guess_in(oz + cur * uz, loz, gz, z0, z1), oz, iz, sz, cur);
+                        }
+                    }
+                    out.write(ti, tj, tk, ex, ey, ez, cur, ts.hi, ts.lo, first);
+                    first = false;
+                    const int pm = pure != nullptr ? pure[ti + A.g.ntx * (tj + A.g.nty * tk)] : -1;
+                    if (pm >= 0) {
+                        ts.add(mysig[pm << shift][0] * (static_cast<S>(t_out) - static_cast<S>(cur)));
+                    } else {
+                        wk.enter_tile(M, mats, ex, ey, ez, cur);
+                        while (wk.step(M, ts, mats)) {
+                        }
+                    }
+                }
+                if (last) break;
+                cur = ta;
+                if (ax) {
+                    ti += sx;
+                    cx = cross(0, lox, hx, ox, ix, sx, ti);
+                } else if (ay) {
+                    tj += sy;
+                    cy = cross(1, loy, hy, oy, iy, sy, tj);
+                } else {
+                    tk += sz;
+                    cz = cross(2, loz, hz, oz, iz, sz, tk);
+                }
+            }
         }
-        em.store_pending();  // the ray's last record
     }
+    // every (block, key) run must now be full, no more, no less: the counting
+    // pass's tile walk and this one are the same, so a difference is a fault
+    // the host reports (records written past a run land in the next one)
+    __syncthreads();
+    const uint32_t *hrow = A.hist + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
+    for (int k = threadIdx.x; k < A.g.n_keys; k += bd)
+        if (s_next[k] != A.key_base[k] + row[k] + hrow[k]) *A.check = 1u;
 }
 
 // Block of 1024 threads, 64 keys: lane = key, each of the 16 wavefronts a
@@ -793,6 +959,43 @@ struct TileScorer {
     }
 };
 
+// The score of a ray piece in a tile of one material: TileScorer with the
+// material's Sigma and 1/Sigma held in registers (the same products, so the
+// same scores).
+template <typename R, class Put>
+struct OneMaterialScorer {
+    R s, is;  // Sigma and 1/Sigma (0 for Sigma = 0)
+    R w_in;
+    Put &put;
+    __device__ __forceinline__ void resume(R w, R th, R tl, bool first)
+    {
+        if (first) {
+            w_in = w;
+        } else {
+            R G, unused;
+            attenuation(th, G, unused);
+            w_in = (w * G) * (R(1) - tl);
+        }
+    }
+    template <typename L>
+    __device__ __forceinline__ void operator()(int32_t vox, int, L len, int ci, int cj, int ck, L)
+    {
+        const R l = static_cast<R>(len);
+        const R x = s * l;
+        R g, em;
+        attenuation(x, g, em);
+        const R f = s > R(0) ? (w_in * em) * is : w_in * l;
+        put(vox, l, f, ci, cj, ck);
+        w_in = w_in * g;
+    }
+};
+
+// The material of every voxel of a tile of one material.
+struct ConstMaterial {
+    int m;
+    __device__ __forceinline__ int operator()(int32_t, int, int, int) const { return m; }
+};
+
 // The key-major records are dealt out to the blocks of the tiles pass in
 // equal contiguous ranges (a key's records may span several blocks, a block's
 // range several keys), so every block has the same number of tile entries to
@@ -923,6 +1126,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
             if constexpr (DENS) return TileMaterialsDens<S>{s_mat, dens, nx, ny, &dcur, &dnext};
             else return TileMaterials{s_mat};
         }();
+        const int pm = A.mesh.tile_mat != nullptr && !DENS ? A.mesh.tile_mat[tile] : -1;  // the tile's one material
         for (uint32_t c0 = lo; c0 < hi; c0 += bd) {
             const int m = static_cast<int>(hi - c0 < static_cast<uint32_t>(bd) ? hi - c0 : static_cast<uint32_t>(bd));
             int bucket[PER];
@@ -934,7 +1138,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
                     const Entry<R, S> &r = rec[c0 + idx];
                     const uint32_t loc = r.code & static_cast<uint32_t>(kTileVoxels - 1);
                     const int est = tile_pieces_estimate(
-                        A.mesh, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz,
+                        A.mesh, r.ox, r.oy, r.oz, r.ix, r.iy, r.iz,
                         tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1)),
                         ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1)),
                         tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits)));
@@ -944,14 +1148,28 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
             sort_desc(bucket, m, kBucketsT, s_cnt, s_perm);
             for (int j = threadIdx.x; j < m; j += bd) {
                 const Entry<R, S> r = rec[c0 + s_perm[j]];
-                xs_lookup(A.xs, hash, r.e, mysig, bd);
                 const uint32_t loc = r.code & static_cast<uint32_t>(kTileVoxels - 1);
                 const int ci = tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1));
                 const int cj = ty * kTileEdge + static_cast<int>((loc >> kTileBits) & (kTileEdge - 1));
                 const int ck = tz * kTileEdge + static_cast<int>(loc >> (2 * kTileBits));
-                sc.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, (r.code & kFirst) != 0u);
-                wk.resume_tile(A.mesh, mats, r.ox, r.oy, r.oz, r.ux, r.uy, r.uz, ci, cj, ck, r.t0);
-                while (wk.step(A.mesh, sc, mats)) {
+                const bool first = (r.code & kFirst) != 0u;
+                if (pm >= 0) {
+                    // a tile of one material: its Sigma alone, no material reads
+                    bool interp;
+                    const int k = xs_interval(A.xs, hash, r.e, interp);
+                    const S sv = xs_value<R, S>(A.xs, k, interp, r.e, pm);
+                    OneMaterialScorer<S, PutLds> one{sv, sv > S(0) ? S(1) / sv : S(0), S(0), put};
+                    one.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, first);
+                    const ConstMaterial cm{pm};
+                    wk.resume_tile(A.mesh, cm, r.ox, r.oy, r.oz, r.ix, r.iy, r.iz, ci, cj, ck, r.t0);
+                    while (wk.step(A.mesh, one, cm)) {
+                    }
+                } else {
+                    xs_lookup(A.xs, hash, r.e, mysig, bd);
+                    sc.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, first);
+                    wk.resume_tile(A.mesh, mats, r.ox, r.oy, r.oz, r.ix, r.iy, r.iz, ci, cj, ck, r.t0);
+                    while (wk.step(A.mesh, sc, mats)) {
+                    }
                 }
             }
             __syncthreads();  // s_perm is rewritten by the next chunk; acc is complete after the last
@@ -1034,10 +1252,8 @@ hipError_t grow(void *&p, size_t &cap, size_t need)
 }
 
 constexpr int kBlock = 256;  // ordering, counting and entries passes
-constexpr size_t kLdsMax = 65536;
 constexpr size_t kEntriesStatic = 4 * kMaxKeys;                                             // next place per key
 constexpr size_t kTileStatic = (sizeof(double) + 1) * kTileVoxels + 4 * kBucketsT + 2 * kMaxBlock;  // acc, mat, sort
-constexpr size_t kScratchBudget = size_t(2) << 30;            // record bytes per sub-launch
 
 SortGeom geometry(const TallyHost &t, const MeshHost &m)
 {
@@ -1063,7 +1279,7 @@ size_t sigma_lds(const vrc_ctx &ctx, size_t s_bytes, int block)
 int tile_block(const vrc_ctx &ctx, size_t s_bytes)
 {
     for (int b : {1024, 512, 256})
-        if (kTileStatic + sigma_lds(ctx, s_bytes, b) <= kLdsMax) return b;
+        if (kTileStatic + sigma_lds(ctx, s_bytes, b) <= ctx.lds_max) return b;
     return 0;
 }
 
@@ -1087,9 +1303,11 @@ template <typename R, typename S, int FLUSH, bool RECT, bool DENS>
 hipError_t tile_blocks(vrc_ctx &ctx, int tb, size_t lds, int &n_blocks)
 {
     int per_cu = 0;
-    hipError_t e = resident_per_cu(ctx.sort_scratch,
-                                   reinterpret_cast<const void *>(&tile_kernel<R, S, FLUSH, RECT, DENS>), tb, lds,
-                                   per_cu);
+    const void *fn = reinterpret_cast<const void *>(&tile_kernel<R, S, FLUSH, RECT, DENS>);
+    // blocks may take more than 64 KiB of LDS on this GPU (up to its per-block limit)
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    e = resident_per_cu(ctx.sort_scratch, fn, tb, lds, per_cu);
     n_blocks = ctx.n_cu * per_cu;
     return e;
 }
@@ -1158,10 +1376,13 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     // entries pass (the ray deal keeps them equally busy); a sub-launch takes
     // as many rays as the record space allows for the most tiles a ray can
     // cross.
+    // tiles of one material jumped over in the entries pass (never with density factors)
+    const bool jump = !DENS && m.d_tile_mat != nullptr &&
+                      (ctx.test_entries_jump >= 0 ? ctx.test_entries_jump == 1 : m.pure_frac >= kJumpMinPure);
+    const auto entries = jump ? &entries_kernel<R, RT, S, RECT, DENS, true> : &entries_kernel<R, RT, S, RECT, DENS, false>;
     int per_cu = 0;
     {
-        hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(&entries_kernel<R, RT, S, RECT, DENS>),
-                                       kBlock, lds1, per_cu);
+        hipError_t e = resident_per_cu(sc, reinterpret_cast<const void *>(entries), kBlock, lds1, per_cu);
         if (e != hipSuccess) return e;
     }
     // an arena holds the per-(block, key) rows of at most kArenaRows blocks (the deal works for any grid)
@@ -1184,7 +1405,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     const size_t partial_bytes = sizeof(double) * 2 * static_cast<size_t>(n_tb) * kTileVoxels;
     int64_t group_rays;
     if (arena.base == nullptr) {
-        group_rays = static_cast<int64_t>(kScratchBudget / (rec * static_cast<size_t>(per_ray)));
+        group_rays = static_cast<int64_t>(sc.record_budget / (rec * static_cast<size_t>(per_ray)));
         hipError_t e = grow(sc.partial, sc.partial_cap, partial_bytes);
         if (e != hipSuccess) return e;
         if (sc.busy && sc.stream != s) {
@@ -1249,6 +1470,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             mesh.n[a] = m.n[a];
         }
         mesh.mat = m.d_mat;
+        mesh.tile_mat = DENS ? nullptr : m.d_tile_mat;
         if constexpr (RECT) {
             const R *base = plane_tables<R>(m);  // x, y and z tables back to back
             mesh.pl[0] = base;
@@ -1286,6 +1508,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         A.key_base = static_cast<const uint32_t *>(b_key_base);
         A.sorted = b_sorted;
         A.cap = cap;
+        A.check = ctx.d_check;
+        A.short_count = ctx.test_short_count;
         uint32_t *hist = static_cast<uint32_t *>(b_hist);
         uint32_t *row_off = static_cast<uint32_t *>(b_row_off);
         uint32_t *key_tot = static_cast<uint32_t *>(b_key_tot);
@@ -1303,7 +1527,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
                            static_cast<const uint32_t *>(hist), Ge, g.n_keys, row_off, key_tot);
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
                            g.n_keys, key_base);
-        hipLaunchKernelGGL((entries_kernel<R, RT, S, RECT, DENS>), dim3(Ge), dim3(kBlock), lds1, s, A);
+        hipLaunchKernelGGL(entries, dim3(Ge), dim3(kBlock), lds1, s, A);
         TileArgs<R> T;
         T.mesh = mesh;
         T.xs = A.xs;
@@ -1350,11 +1574,11 @@ hipError_t run_sorted(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, const
 
 bool sorted_eligible(const vrc_ctx &ctx, const TallyHost &t, const MeshHost &m)
 {
-    if (ctx.sort_scratch.done == nullptr) return false;
+    if (ctx.sort_scratch.done == nullptr || m.rz) return false;
     const SortGeom g = geometry(t, m);
     if (g.n_keys == 0) return false;
     const size_t sb = (t.prec == VRC_P32_T64 || t.prec == VRC_P32_KAHAN) ? sizeof(float) : sizeof(double);
-    return kEntriesStatic + sigma_lds(ctx, sb, kBlock) <= kLdsMax && tile_block(ctx, sb) > 0;
+    return kEntriesStatic + sigma_lds(ctx, sb, kBlock) <= ctx.lds_max && tile_block(ctx, sb) > 0;
 }
 
 namespace {
@@ -1449,7 +1673,7 @@ hipError_t run_next_event_ordered(vrc_ctx &ctx, const MeshHost &m, int64_t n, co
 bool next_event_ordered_eligible(const vrc_ctx &ctx, vrc_precision prec)
 {
     const size_t sb = prec == VRC_P64 ? sizeof(double) : sizeof(float);
-    return ctx.sort_scratch.done != nullptr && sigma_lds(ctx, sb, 256) <= kLdsMax;
+    return ctx.sort_scratch.done != nullptr && sigma_lds(ctx, sb, 256) <= ctx.lds_max;
 }
 
 hipError_t launch_next_event_ordered(vrc_ctx &ctx, const MeshHost &m, vrc_precision prec, int64_t n, bool fp64,

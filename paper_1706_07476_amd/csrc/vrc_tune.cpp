@@ -66,7 +66,7 @@ std::string mesh_key(const vrc_ctx *ctx, const std::set<int> &meshes)
     std::ostringstream os;
     for (int m : meshes) {
         const MeshHost &mh = ctx->meshes[m];
-        os << mh.n[0] << 'x' << mh.n[1] << 'x' << mh.n[2] << (mh.rect ? "r" : "") << (mh.dens ? "d," : ",");
+        os << mh.n[0] << 'x' << mh.n[1] << 'x' << mh.n[2] << (mh.rect ? "r" : "") << (mh.rz ? "z" : "") << (mh.dens ? "d," : ",");
     }
     return os.str();
 }
@@ -132,7 +132,7 @@ vrc_status vrc_autotune_batched(vrc_ctx *ctx, int n_batches, const vrc_batch *ba
             tally_ids.insert(id);
             meshes.insert(ctx->tallies[id]->mesh_id);
             const MeshHost &mh = ctx->meshes[ctx->tallies[id]->mesh_id];
-            kinds = kinds || mh.rect || mh.dens;
+            kinds = kinds || mh.rect || mh.dens || mh.rz;
             prec = static_cast<int>(ctx->tallies[id]->prec);
             fp64 = batches[i].fp64;
         }

@@ -255,6 +255,7 @@ vrc_status vrc_walkers_run(vrc_ctx *ctx, const vrc_walker_config *cfg, vrc_walke
         if (id < 0 || id >= static_cast<int>(ctx->tallies.size()) || !ctx->tallies[id])
             return set_error(VRC_ERR_INVALID, "no such tally");
         const MeshHost &m = ctx->meshes[ctx->tallies[id]->mesh_id];
+        if (m.rz) return set_error(VRC_ERR_INVALID, "the collision walkers sample Cartesian meshes");
         if (cfg->n_sigma < m.max_mat + 1 || cfg->n_sigma > 64)
             return set_error(VRC_ERR_INVALID, "sigma must cover every material of the mesh");
         // the tables and factors are host copies that stay put while a tally uses the mesh

@@ -1,11 +1,13 @@
 """The tile-split accumulation of the plain cast (launch accumulate = 2 or 3: forced).
 
 Rays are split at 16^3-tile entries and scored tile by tile in LDS; the
-scores are bit-identical to the per-segment atomic path and only the order
-of the tally additions differs, so the sorted tallies meet the same bounds
-against the oracle (FP64 1e-12 on every scored voxel; FP32 forms 1e-5 on
-voxels with oracle relative standard error below 5%) and agree with the
-atomic path to 1e-12.  Cases: several energy bins on a ragged
+scores are bit-identical to the per-segment atomic path (both take the
+optical depth at a tile entry by the same operations: across a tile of one
+material one product Sigma x chord, across other tiles one per piece) and
+only the order of the tally additions differs, so the sorted tallies meet
+the same bounds against the oracle (FP64 1e-12 on every scored voxel; FP32
+forms 1e-5 on voxels with oracle relative standard error below 5%) and agree
+with the atomic path to 1e-12.  Cases: several energy bins on a ragged
 (non-multiple-of-16) mesh, long rays crossing many tiles, the largest
 eligible key count with several sub-launches, a tally beyond the key limit
 (atomic path), ragged batch sizes, and sorted casts on two streams.
@@ -145,14 +147,16 @@ def test_sorted_long_rays_many_tiles(ctx):
 
 
 @pytest.mark.parametrize("prec", ["p64", "p32_t64"])
-def test_sorted_max_keys_several_sub_launches(ctx, prec):
-    """256^3 with one bin: exactly 4096 keys; 6e5 rays exceed one sub-launch's 2048 x 256 rays."""
+def test_sorted_max_keys_several_sub_launches(ctx, vrc, prec):
+    """256^3 with one bin: exactly 4096 keys; 6e5 rays in sub-launches of at most 256 MiB of records
+    (the test hook caps the record budget: about 1e5 rays each)."""
     wl = W.config3_precision(n_rays=0)
     mesh = wl.mesh
     rays = W.rays_in_box(510, mesh, 600_000)
-    say(f"case: sorted {prec}, cylinder 256^3 (4096 keys), 6e5 rays")
+    say(f"case: sorted {prec}, cylinder 256^3 (4096 keys), 6e5 rays, several sub-launches")
     ctx.set_mesh(0, mesh)
     ctx.set_xs(wl.xs)
+    vrc.vrc_test_hook(ctx.handle, vrc.VRC_TEST_RECORD_BUDGET, 256 << 20)
     dt = "f64" if prec == "p64" else "f32"
     got, atom = cast_both(ctx, 0, prec, dev_arrays(rays, dt))
     o = order_rel(got, atom)
@@ -163,6 +167,52 @@ def test_sorted_max_keys_several_sub_launches(ctx, prec):
         g, _, n = rel_report(got, res, gate="all")
         say(f"  sorted vs oracle {g:.3e} over {n}")
         assert g <= TOL_P64
+
+
+def one_material_tiles_mesh():
+    """32^3 of 0.5 cm, tiles of 16^3: the lower half in z all material 1 (single-material tiles), the
+    upper half void (material 3, Sigma = 0) for x < 8 cm and 2-voxel slabs of materials 0-2 beyond."""
+    n = 32
+    mat = np.empty((n, n, n), np.uint8)
+    mat[:16] = 1
+    mat[16:, :, :16] = 3
+    for k in range(16, n):
+        mat[k, :, 16:] = (k // 2) % 3
+    return W.Mesh(np.zeros(3), np.full(3, 0.5), np.full(3, n, np.int32), mat.reshape(-1).copy())
+
+
+@pytest.mark.parametrize("jump", [1, 0])
+@pytest.mark.parametrize("prec", ["p64", "p32_t64", "p32_d64"])
+def test_sorted_single_material_and_void_tiles(vrc, ctx, prec, jump):
+    """Tiles of one material (optical depth from the chord, no material reads), void tiles and tiles of
+    several materials in one mesh, against the oracle; the entries pass jumping over the tiles of one
+    material (jump 1) or walking them (jump 0), both bit-identical to the atomic path's whole-ray walk."""
+    vrc.vrc_test_hook(ctx.handle, vrc.VRC_TEST_ENTRIES_JUMP, jump)
+    mesh = one_material_tiles_mesh()
+    xs3 = W.config2_multimaterial(n_rays=0).xs
+    tabs = [xs3.table(m) for m in range(3)] + [W.constant_sigma_table(0.0)]
+    xs = W.gen.make_xs(tabs)
+    n_rays = 200_000 if prec == "p64" else 1_600_000
+    rays = W.rays_in_box(515, mesh, n_rays)
+    say(f"case: sorted {prec}, single-material and void tiles, 32^3, {n_rays} rays, jump {jump}")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    dt = "f64" if prec == "p64" else "f32"
+    got, atom = cast_both(ctx, 0, prec, dev_arrays(rays, dt))
+    o = order_rel(got, atom)
+    if prec == "p64":
+        res = oracle.cast(mesh, xs, rays, n_threads=oracle_threads())
+        g, _, n = rel_report(got, res, gate="all")
+        bound = TOL_P64
+    else:
+        m, x, r = f32_view(mesh, xs, rays)
+        res = oracle.cast(m, x, r, n_threads=oracle_threads())
+        g, _, n = rel_report(got, res, gate="stderr")
+        bound = TOL_P32
+        assert n > 3000  # the strongly absorbing half leaves its far voxels under-sampled
+    say(f"  sorted vs oracle {g:.3e} over {n} voxels; sorted vs atomic {o:.3e}")
+    assert g <= bound
+    assert o <= TOL_ORDER
 
 
 def test_beyond_key_limit_uses_atomics(ctx):
@@ -331,3 +381,40 @@ def test_fp64_rays_into_fp32_forms_and_small_batch_switch(ctx):
     ctx.set_launch(accumulate=2)
     ctx.cast(t2, dev_arrays(small, "f64"))
     assert order_rel(ctx.read(t1), ctx.read(t2)) <= TOL_ORDER
+
+
+def test_short_count_is_reported(vrc):
+    """The entries pass checks every (block, key) run against the counting pass: a count one short
+    (forced from the host through the test hook; every store stays inside the record buffer) makes the
+    next read fail with VRC_ERR_DEVICE, sticky for the context; another context is unaffected."""
+    mesh = W.slab_mesh(516, 40, 0.5)
+    wl = W.config2_multimaterial(n_rays=0)
+    rays = W.rays_in_box(517, mesh, 50_000)
+    say("case: tile-split run check, counting pass forced one entry short")
+    bad = vrc.Context(0)
+    good = vrc.Context(0)
+    try:
+        for c in (bad, good):
+            c.set_mesh(0, mesh)
+            c.set_xs(wl.xs)
+            c.set_launch(accumulate=2)
+        vrc.vrc_test_hook(bad.handle, vrc.VRC_TEST_SHORT_COUNT, 1)
+        arrays = dev_arrays(rays, "f64")
+        tb = bad.create_tally(0, "p64")
+        tg = good.create_tally(0, "p64")
+        bad.cast(tb, arrays)
+        good.cast(tg, arrays)
+        with pytest.raises(vrc.VrcError) as e:
+            bad.read(tb)
+        assert e.value.status == vrc.VRC_ERR_DEVICE
+        with pytest.raises(vrc.VrcError) as e:  # sticky
+            bad.cast(tb, arrays)
+        assert e.value.status == vrc.VRC_ERR_DEVICE
+        res = oracle.cast(mesh, wl.xs, rays, n_threads=oracle_threads())
+        g, _, _ = rel_report(good.read(tg), res, gate="all")
+        assert g <= TOL_P64
+        with pytest.raises(vrc.VrcError):
+            vrc.vrc_test_hook(good.handle, 7, 1)
+    finally:
+        bad.close()
+        good.close()
