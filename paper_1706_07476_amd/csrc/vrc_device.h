@@ -547,18 +547,43 @@ __device__ __forceinline__ void xs_lookup_sigma(const XsP<R> &X, const int32_t *
 // Segment consumers
 // ---------------------------------------------------------------------------
 
+// Compensated optical depth (hi + lo).  Within a tile the pieces' Sigma l
+// are summed from zero with Knuth's TwoSum (add); a tile's sum then joins
+// the running depth before the tile (join), its rounding error and the
+// tile's own compensation going into lo.  Every path takes the depth at a
+// tile entry by exactly these operations, so they agree bit for bit.
+template <typename R>
+struct TauPair {
+    R hi, lo;
+    __device__ __forceinline__ void add(R x)
+    {
+        const R t = hi + x;
+        const R bv = t - hi;
+        lo += (hi - (t - bv)) + (x - bv);
+        hi = t;
+    }
+    __device__ __forceinline__ void join(R a, R b)
+    {
+        const R t = hi + a;
+        const R bv = t - hi;
+        const R err = (hi - (t - bv)) + (a - bv);
+        hi = t;
+        lo = lo + (err + b);
+    }
+};
+
 // Running VRC score of one ray; calls put(voxel, length, score, i, j, k)
 // per piece.  The weight entering the next voxel is carried as a running
 // product of the segments' e^{-x}; the optical depth tau is summed alongside
-// with Knuth's TwoSum (compensated), and at every tile entry the weight is
-// recomputed as w e^{-tau}, so its error stays at a few ulp however long the
-// ray is (a tile holds at most 3 * 16 - 2 pieces of one ray).  The optical
-// depth across a tile of one material is added at the tile's exit as that
+// (TauPair: per tile, then joined at the next tile's entry), and at every
+// tile entry the weight is recomputed as w e^{-tau}, so its error stays at a
+// few ulp however long the ray is (a tile holds at most 3 * 16 - 2 pieces of
+// one ray).  The optical depth across a tile of one material is that
 // material's Sigma times the tile's chord (from the entry of its first piece
-// to the entry of the next tile's), across any other tile piece by piece.
-// The tile-split accumulation's entries pass takes the optical depth at a
-// tile entry by the same operations, so a cast split at tile entries scores
-// bit-identically to an uninterrupted one.
+// to the entry of the next tile's); across any other tile it is the sum of
+// its pieces' Sigma l.  The tile-split accumulation takes the optical depth
+// at a tile entry by the same operations, so a cast split at tile entries
+// scores bit-identically to an uninterrupted one.
 template <typename R, class Put, bool DENS = false>
 struct Scorer {
     const R (*sig)[2];
@@ -568,29 +593,21 @@ struct Scorer {
     int stride;
     R w0;
     R w_in;
-    R tau_hi;
-    R tau_lo;
+    TauPair<R> tau;   // before the current tile
+    TauPair<R> tile_tau;  // within the current tile (tiles of several materials)
     bool started;   // a piece has been scored
     uint32_t tile;  // tile_tag of the current tile
     int tile_pm;    // the current tile's one material, or -1
     R tile_t0;      // where the current tile's first piece starts
     Put &put;
     __device__ __forceinline__ Scorer(const R (*sig_)[2], int stride_, R w, Put &put_)
-        : sig(sig_), stride(stride_), w0(w), w_in(w), tau_hi(0), tau_lo(0), started(false), tile(0), tile_pm(-1),
-          tile_t0(0), put(put_) {}
+        : sig(sig_), stride(stride_), w0(w), w_in(w), tau{R(0), R(0)}, tile_tau{R(0), R(0)}, started(false), tile(0),
+          tile_pm(-1), tile_t0(0), put(put_) {}
     __device__ __forceinline__ void reanchor()
     {
         R G, unused;
-        attenuation(tau_hi, G, unused);
-        w_in = (w0 * G) * (R(1) - tau_lo);
-    }
-    __device__ __forceinline__ void add_tau(R x)
-    {
-        const R t = tau_hi + x;
-        const R bv = t - tau_hi;
-        const R err = (tau_hi - (t - bv)) + (x - bv);
-        tau_hi = t;
-        tau_lo += err;
+        attenuation(tau.hi, G, unused);
+        w_in = (w0 * G) * (R(1) - tau.lo);
     }
     template <typename L>
     __device__ __forceinline__ void operator()(int32_t vox, int m, L len, int ci, int cj, int ck, L t0)
@@ -598,7 +615,8 @@ struct Scorer {
         const uint32_t tg = tile_tag(ci >> kTileBits, cj >> kTileBits, ck >> kTileBits);
         if (tg != tile || !started) {
             if (started) {
-                if (tile_pm >= 0) add_tau(sig[tile_pm * stride][0] * (static_cast<R>(t0) - tile_t0));
+                if (tile_pm >= 0) tau.join(sig[tile_pm * stride][0] * (static_cast<R>(t0) - tile_t0), R(0));
+                else tau.join(tile_tau.hi, tile_tau.lo);
                 reanchor();
             }
             started = true;
@@ -609,6 +627,7 @@ struct Scorer {
                     tile_pm = tile_mat[(ci >> kTileBits) + ntx * ((cj >> kTileBits) + nty * (ck >> kTileBits))];
             }
             tile_t0 = static_cast<R>(t0);
+            tile_tau = TauPair<R>{R(0), R(0)};
         }
         const R l = static_cast<R>(len);
         R s = sig[m * stride][0];
@@ -623,7 +642,7 @@ struct Scorer {
         attenuation(x, g, em);
         const R f = s > R(0) ? (w_in * em) * is : w_in * l;
         put(vox, l, f, ci, cj, ck);
-        if (tile_pm < 0) add_tau(x);
+        if (tile_pm < 0) tile_tau.add(x);
         w_in = w_in * g;
     }
 };

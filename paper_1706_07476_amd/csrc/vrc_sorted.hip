@@ -562,26 +562,19 @@ __device__ __forceinline__ int index_at(const Planes &X, int k_lo, int k_hi, int
     return k;
 }
 
-// Optical depth of a walk in the entries pass: the sum of Sigma l over its
-// pieces as the score sums it (same products, same TwoSum).
+// Walk sink summing the pieces' Sigma l of one tile from zero (TauPair::add,
+// as the score sums a tile's pieces).
 template <typename R, typename S, bool DENS>
 struct TauSum {
     const S (*sig)[2];
     const S *dcur;  // DENS: the factor of the voxel being walked (loaded with its material)
     int shift;      // log2 of the LDS column stride (the block size)
-    S hi, lo;
-    __device__ __forceinline__ void add(S x)
-    {
-        const S t = hi + x;
-        const S bv = t - hi;
-        lo += (hi - (t - bv)) + (x - bv);
-        hi = t;
-    }
+    TauPair<S> tau;
     __device__ __forceinline__ void operator()(int32_t, int m, R len, int, int, int, R)
     {
         S sg = sig[m << shift][0];
         if constexpr (DENS) sg = sg * *dcur;
-        add(sg * static_cast<S>(len));
+        tau.add(sg * static_cast<S>(len));
     }
 };
 
@@ -624,15 +617,16 @@ struct EntryOut {
 };
 
 // Walk sink of the entries pass when it walks every tile: at the first
-// piece of positive length in a tile it writes the tile's record (that
-// piece's voxel, where it starts, the optical depth before it).  The optical
-// depth across a tile of one material m is Sigma_m times the tile's chord,
-// from its first piece to the next tile's, added at the next tile as the
-// uninterrupted walk's Scorer adds it; across any other tile it is summed
-// piece by piece.
+// piece of positive length in a tile it joins the previous tile's optical
+// depth to the running one and writes the tile's record (that piece's voxel,
+// where it starts, the optical depth before the tile).  A tile of one
+// material m contributes Sigma_m times its chord (from its first piece to
+// the next tile's), any other tile the sum of its pieces' Sigma l: the
+// operations of the uninterrupted walk's Scorer.
 template <typename R, typename S, bool DENS>
 struct EntrySink {
-    TauSum<R, S, DENS> tau;
+    TauSum<R, S, DENS> tile;  // within the current tile
+    TauPair<S> tau;           // before the current tile
     EntryOut<R, S> out;
     const int8_t *pure;  // per tile: its material if it holds one only, else -1 (nullptr: none)
     uint32_t tag;        // tile_tag of the tile of the last piece
@@ -644,15 +638,20 @@ struct EntrySink {
         const int ti = ci >> kTileBits, tj = cj >> kTileBits, tk = ck >> kTileBits;
         const uint32_t tg = tile_tag(ti, tj, tk);
         if (!started || tg != tag) {
-            if (started && pm_cur >= 0)
-                tau.add(tau.sig[pm_cur << tau.shift][0] * (static_cast<S>(t0) - static_cast<S>(tile_t0)));
+            if (started) {
+                if (pm_cur >= 0)
+                    tau.join(tile.sig[pm_cur << tile.shift][0] * (static_cast<S>(t0) - static_cast<S>(tile_t0)), S(0));
+                else
+                    tau.join(tile.tau.hi, tile.tau.lo);
+            }
             out.write(ti, tj, tk, ci, cj, ck, t0, tau.hi, tau.lo, !started);
             started = true;
             tag = tg;
             pm_cur = pure != nullptr ? pure[ti + out.g.ntx * (tj + out.g.nty * tk)] : -1;
             tile_t0 = t0;
+            tile.tau = TauPair<S>{S(0), S(0)};
         }
-        if (pm_cur < 0) tau(vox, m, len, ci, cj, ck, t0);
+        if (pm_cur < 0) tile(vox, m, len, ci, cj, ck, t0);
     }
 };
 
@@ -675,8 +674,11 @@ template <typename R, typename RT, typename S, bool RECT, bool DENS, bool JUMP>
 __global__ void __launch_bounds__(256) entries_kernel(EntryArgs<R> A)
 {
     __shared__ uint32_t s_next[kMaxKeys];
+    __shared__ int8_t s_pure[JUMP ? kMaxKeys : 1];  // JUMP: the tile table in LDS (read at every tile)
     const uint32_t *row = A.row_off + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
     for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_next[k] = A.key_base[k] + row[k];
+    if constexpr (JUMP)
+        for (int k = threadIdx.x; k < A.g.n_tiles; k += blockDim.x) s_pure[k] = A.mesh.tile_mat[k];
     __syncthreads();
     const int32_t *hash;
     S(*sig)[2];
@@ -694,7 +696,7 @@ __global__ void __launch_bounds__(256) entries_kernel(EntryArgs<R> A)
         else return MeshMaterials{A.mesh.mat};
     }();
     const MeshP<R> &M = A.mesh;
-    const int8_t *pure = DENS ? nullptr : M.tile_mat;
+    const int8_t *pure = DENS ? nullptr : (JUMP ? s_pure : M.tile_mat);
     const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
     const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
     const R gx = R(1) / hx, gy = R(1) / hy, gz = R(1) / hz;
@@ -737,12 +739,13 @@ __global__ void __launch_bounds__(256) entries_kernel(EntryArgs<R> A)
         out.w = rr.w;
         out.key0 = static_cast<uint32_t>(bin * A.g.n_tiles);
         if constexpr (!JUMP) {
-            EntrySink<R, S, DENS> es{TauSum<R, S, DENS>{mysig, &dcur, shift, S(0), S(0)}, out, pure, 0u, false, -1,
-                                     R(0)};
+            EntrySink<R, S, DENS> es{TauSum<R, S, DENS>{mysig, &dcur, shift, TauPair<S>{S(0), S(0)}},
+                                     TauPair<S>{S(0), S(0)}, out, pure, 0u, false, -1, R(0)};
             while (wk.step(M, es, mats)) {
             }
         } else {
-            TauSum<R, S, DENS> ts{mysig, &dcur, shift, S(0), S(0)};
+            TauPair<S> tau{S(0), S(0)};  // before the current tile
+            TauSum<R, S, DENS> ts{mysig, &dcur, shift, TauPair<S>{S(0), S(0)}};  // within a tile of several materials
             const R ox = rr.ox, oy = rr.oy, oz = rr.oz, ux = rr.ux, uy = rr.uy, uz = rr.uz;
             int ti = wk.kx >> kTileBits, tj = wk.ky >> kTileBits, tk = wk.kz >> kTileBits;
             const int sx = wk.sx, sy = wk.sy, sz = wk.sz;
@@ -781,15 +784,17 @@ __global__ void __launch_bounds__(256) entries_kernel(EntryArgs<R> A)
                                 ez = index_at(X(2), z0, z1, guess_in(oz + cur * uz, loz, gz, z0, z1), oz, iz, sz, cur);
                         }
                     }
-                    out.write(ti, tj, tk, ex, ey, ez, cur, ts.hi, ts.lo, first);
+                    out.write(ti, tj, tk, ex, ey, ez, cur, tau.hi, tau.lo, first);
                     first = false;
                     const int pm = pure != nullptr ? pure[ti + A.g.ntx * (tj + A.g.nty * tk)] : -1;
                     if (pm >= 0) {
-                        ts.add(mysig[pm << shift][0] * (static_cast<S>(t_out) - static_cast<S>(cur)));
+                        tau.join(mysig[pm << shift][0] * (static_cast<S>(t_out) - static_cast<S>(cur)), S(0));
                     } else {
+                        ts.tau = TauPair<S>{S(0), S(0)};
                         wk.enter_tile(M, mats, ex, ey, ez, cur);
                         while (wk.step(M, ts, mats)) {
                         }
+                        tau.join(ts.tau.hi, ts.tau.lo);
                     }
                 }
                 if (last) break;
@@ -1252,7 +1257,7 @@ hipError_t grow(void *&p, size_t &cap, size_t need)
 }
 
 constexpr int kBlock = 256;  // ordering, counting and entries passes
-constexpr size_t kEntriesStatic = 4 * kMaxKeys;                                             // next place per key
+constexpr size_t kEntriesStatic = 5 * kMaxKeys;  // next place per key, and the tile table of the jumping walk
 constexpr size_t kTileStatic = (sizeof(double) + 1) * kTileVoxels + 4 * kBucketsT + 2 * kMaxBlock;  // acc, mat, sort
 
 SortGeom geometry(const TallyHost &t, const MeshHost &m)
