@@ -225,6 +225,12 @@ __device__ __forceinline__ void sort_desc(const int (&bucket)[PER], int m, int n
 constexpr int kBucketsE = 256;  // entries: estimated pieces (scaled to fit)
 constexpr int kBucketsT = 64;   // tiles: pieces inside one tile, at most 3 * 16 - 2
 constexpr int kMaxBlock = 1024;
+// tiles pass: records per thread in one ordered chunk (FP64 scores: one
+// 1024-thread block per CU, registers to spare; FP32 scores: two blocks of
+// 64 VGPRs, where more records per thread spill)
+constexpr int kTilePerMax = 8;
+template <typename S>
+constexpr int tile_per() { return sizeof(S) == 8 ? 8 : 2; }
 
 // Where the ordering pass reads its rays: one batch (pointers already at the
 // sub-launch's first ray), or several batches numbered one after the other
@@ -1073,7 +1079,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
     __shared__ double acc[kTileVoxels];
     __shared__ uint8_t s_mat[kTileVoxels];
     __shared__ uint32_t s_cnt[kBucketsT];
-    __shared__ uint16_t s_perm[kMaxBlock];
+    __shared__ uint16_t s_perm[kMaxBlock * tile_per<S>()];
     const int n_keys = A.g.n_keys;
     const TileDeal deal(A.key_base, n_keys, A.n_blocks);
     const uint32_t b = blockIdx.x;
@@ -1103,7 +1109,9 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
     TileScorer<S, PutLds, DENS> sc{mysig, __ffs(bd) - 1, S(0), put, &dcur};
     const DensPair<S> *dens = density_of<S>(A.mesh);
     Walker<R, RECT> wk;
-    constexpr int PER = 1;  // the records of one block-sized chunk are ordered together
+    constexpr int PER = tile_per<S>();  // records per thread in a chunk (ordered together)
+    const int nw = bd >> 6;        // wavefronts of the block
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (; key < n_keys; ++key) {
         const uint32_t kb = A.key_base[key], ke = A.key_base[key + 1];
         if (kb >= r1) break;
@@ -1132,8 +1140,9 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
             else return TileMaterials{s_mat};
         }();
         const int pm = A.mesh.tile_mat != nullptr && !DENS ? A.mesh.tile_mat[tile] : -1;  // the tile's one material
-        for (uint32_t c0 = lo; c0 < hi; c0 += bd) {
-            const int m = static_cast<int>(hi - c0 < static_cast<uint32_t>(bd) ? hi - c0 : static_cast<uint32_t>(bd));
+        const uint32_t cb = static_cast<uint32_t>(bd * PER);  // records per chunk
+        for (uint32_t c0 = lo; c0 < hi; c0 += cb) {
+            const int m = static_cast<int>(hi - c0 < cb ? hi - c0 : cb);
             int bucket[PER];
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
@@ -1151,7 +1160,13 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
                 }
             }
             sort_desc(bucket, m, kBucketsT, s_cnt, s_perm);
-            for (int j = threadIdx.x; j < m; j += bd) {
+            // the sorted chunk in slices of 64 (one per wavefront and round), dealt to the wavefronts
+            // forwards in even rounds and backwards in odd ones, so that every wavefront gets about the
+            // same number of pieces and the block's barrier at the chunk's end finds them all near done
+#pragma unroll 1
+            for (int q = 0; q < PER; ++q) {
+                const int j = (q * nw + ((q & 1) ? nw - 1 - wave : wave)) * 64 + lane;
+                if (j >= m) continue;
                 const Entry<R, S> r = rec[c0 + s_perm[j]];
                 const uint32_t loc = r.code & static_cast<uint32_t>(kTileVoxels - 1);
                 const int ci = tx * kTileEdge + static_cast<int>(loc & (kTileEdge - 1));
@@ -1258,7 +1273,7 @@ hipError_t grow(void *&p, size_t &cap, size_t need)
 
 constexpr int kBlock = 256;  // ordering, counting and entries passes
 constexpr size_t kEntriesStatic = 5 * kMaxKeys;  // next place per key, and the tile table of the jumping walk
-constexpr size_t kTileStatic = (sizeof(double) + 1) * kTileVoxels + 4 * kBucketsT + 2 * kMaxBlock;  // acc, mat, sort
+constexpr size_t kTileStatic = (sizeof(double) + 1) * kTileVoxels + 4 * kBucketsT + 2 * kMaxBlock * kTilePerMax;  // acc, mat, sort
 
 SortGeom geometry(const TallyHost &t, const MeshHost &m)
 {
