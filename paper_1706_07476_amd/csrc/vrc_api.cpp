@@ -174,6 +174,8 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
     for (int64_t i = 0; i < nvox; ++i) max_mat = std::max(max_mat, static_cast<int>(mat[i]));
     free_dev(m.d_mat);
     free_dev(m.d_tile_mat);
+    free_dev(m.d_tile_slot);
+    free_dev(m.d_mixed);
     free_dev(m.d_pl64);
     free_dev(m.d_pl32);
     free_dev(m.d_rho64);
@@ -210,6 +212,34 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
         m.d_tile_mat = static_cast<int8_t *>(d);
         m.pure_frac = static_cast<double>(std::count_if(tm.begin(), tm.end(), [](int8_t v) { return v >= 0; })) /
                       static_cast<double>(tm.size());
+        // the tiles of several materials, tile-major (the walks of the entries pass read these)
+        std::vector<int32_t> slot(tm.size(), -1);
+        int32_t n_mixed = 0;
+        for (size_t t = 0; t < tm.size(); ++t)
+            if (tm[t] < 0) slot[t] = n_mixed++;
+        std::vector<uint8_t> mixed(static_cast<size_t>(n_mixed) * 4096, 0);
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i) {
+                    const int32_t q = slot[(i >> 4) + static_cast<size_t>(tx) * ((j >> 4) + static_cast<size_t>(ty) * (k >> 4))];
+                    if (q < 0) continue;
+                    mixed[static_cast<size_t>(q) * 4096 + (i & 15) + 16 * (j & 15) + 256 * (k & 15)] =
+                        mat[i + static_cast<int64_t>(n[0]) * (j + static_cast<int64_t>(n[1]) * k)];
+                }
+        vrc_status s = upload(ctx, &d, slot.data(), sizeof(int32_t) * slot.size());
+        if (s == VRC_OK) {
+            m.d_tile_slot = static_cast<int32_t *>(d);
+            if (n_mixed > 0) {
+                s = upload(ctx, &d, mixed.data(), mixed.size());
+                if (s == VRC_OK) m.d_mixed = static_cast<uint8_t *>(d);
+            }
+        }
+        if (s != VRC_OK) {
+            free_dev(m.d_mat);
+            free_dev(m.d_tile_mat);
+            free_dev(m.d_tile_slot);
+            return s;
+        }
     }
     if (planes) {
         std::vector<float> p32;
@@ -225,12 +255,16 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
         if (vrc_status s = upload(ctx, &d, m.h_planes.data(), sizeof(double) * m.h_planes.size())) {
             free_dev(m.d_mat);
             free_dev(m.d_tile_mat);
+            free_dev(m.d_tile_slot);
+            free_dev(m.d_mixed);
             return s;
         }
         m.d_pl64 = static_cast<double *>(d);
         if (vrc_status s = upload(ctx, &d, p32.data(), sizeof(float) * p32.size())) {
             free_dev(m.d_mat);
             free_dev(m.d_tile_mat);
+            free_dev(m.d_tile_slot);
+            free_dev(m.d_mixed);
             free_dev(m.d_pl64);
             return s;
         }
@@ -372,6 +406,8 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
     for (auto &m : ctx->meshes) {
         free_dev(m.d_mat);
         free_dev(m.d_tile_mat);
+        free_dev(m.d_tile_slot);
+        free_dev(m.d_mixed);
         free_dev(m.d_pl64);
         free_dev(m.d_pl32);
         free_dev(m.d_rho64);

@@ -42,6 +42,12 @@ struct MeshP {
     // per tile of 16^3 voxels (x fastest): its material if it holds one only, else -1; nullptr for a
     // mesh with density factors (the optical depth across such a tile is its Sigma times the chord)
     const int8_t *tile_mat = nullptr;
+    // the tiles of several materials, tile-major: per tile its place in `mixed` (-1 for a tile of one
+    // material), and there its 16^3 materials (x fastest within the tile; 0 beyond the mesh), so that a
+    // walk through such a tile reads 4 KB of adjacent bytes instead of 256 rows of 16 scattered over the
+    // mesh array
+    const int32_t *tile_slot = nullptr;
+    const uint8_t *mixed = nullptr;
     // rectilinear mesh: per axis a device table of n_a + 1 increasing planes
     // (walks instantiated for rectilinear meshes read these instead of lo + k h)
     const R *pl[3] = {nullptr, nullptr, nullptr};
@@ -191,6 +197,8 @@ struct MeshHost {
     int max_mat = 0;
     uint8_t *d_mat = nullptr;
     int8_t *d_tile_mat = nullptr;  // per 16^3 tile: its material if it holds one only, else -1
+    int32_t *d_tile_slot = nullptr;  // per tile: its place among the tiles of several materials, or -1
+    uint8_t *d_mixed = nullptr;      // those tiles' materials, 4096 per tile (tile-major)
     double pure_frac = 0.0;        // fraction of the tiles that hold one material
     int users = 0;  // tallies that refer to it
 };

@@ -68,6 +68,24 @@ VRC_HD inline float vrc_ldexp(float a, int k) { return ::ldexpf(a, k); }
 VRC_HD inline double vrc_rint(double a) { return ::rint(a); }
 VRC_HD inline float vrc_rint(float a) { return ::rintf(a); }
 
+// One Horner step p r + c with a constant coefficient c.  In FP64 device code
+// it is the three-operand FMA with c in a scalar register pair: left to
+// itself the compiler keeps the coefficients in vector registers and uses
+// the two-operand form, which overwrites its addend, so every step copies a
+// coefficient first (12 copies per evaluation and 26 registers held).  The
+// arithmetic is the same fused multiply-add.
+VRC_HD inline float horner_step(float p, float r, float c) { return vrc_fma(p, r, c); }
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ inline double horner_step(double p, double r, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(p), "v"(r), "s"(c));
+    return d;
+}
+#else
+inline double horner_step(double p, double r, double c) { return vrc_fma(p, r, c); }
+#endif
+
 // g = exp(-x), em = 1 - exp(-x) for x >= 0 (x > x_max or NaN: g = 0, em = 1).
 // Branch-free: out-of-range arguments are evaluated at 0 and their results
 // replaced, so the lanes of a wavefront never split here.
@@ -83,7 +101,7 @@ VRC_HD inline void attenuation(R x, R &g, R &em)
     // Horner: q = r (1/1! + r (1/2! + r (1/3! + ... + r / degree!)))
     R p = static_cast<R>(inv_factorial(C::degree));
 #pragma unroll
-    for (int j = C::degree - 1; j >= 1; --j) p = vrc_fma(p, r, static_cast<R>(inv_factorial(j)));
+    for (int j = C::degree - 1; j >= 1; --j) p = horner_step(p, r, static_cast<R>(inv_factorial(j)));
     const R q = p * r;
     const R s = vrc_ldexp(R(1), static_cast<int>(kf));
     const R gv = vrc_fma(s, q, s);

@@ -676,15 +676,21 @@ struct EntrySink {
 //     registers and no per-tile searches.
 // Each lane walks its own rays (its lane's ray of every round of the
 // block's deal); the rays of a wavefront are of about the same length.
+// (FP32 walks: at most 128 registers, four wavefronts per SIMD)
 template <typename R, typename RT, typename S, bool RECT, bool DENS, bool JUMP>
-__global__ void __launch_bounds__(256) entries_kernel(EntryArgs<R> A)
+__global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(EntryArgs<R> A)
 {
     __shared__ uint32_t s_next[kMaxKeys];
-    __shared__ int8_t s_pure[JUMP ? kMaxKeys : 1];  // JUMP: the tile table in LDS (read at every tile)
+    // JUMP: the tile table in LDS (read at every tile): a tile's material if it holds one only, else
+    // -1 - its place among the tiles of several materials
+    __shared__ int16_t s_code[JUMP ? kMaxKeys : 1];
     const uint32_t *row = A.row_off + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
     for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_next[k] = A.key_base[k] + row[k];
     if constexpr (JUMP)
-        for (int k = threadIdx.x; k < A.g.n_tiles; k += blockDim.x) s_pure[k] = A.mesh.tile_mat[k];
+        for (int k = threadIdx.x; k < A.g.n_tiles; k += blockDim.x) {
+            const int pm = A.mesh.tile_mat[k];
+            s_code[k] = static_cast<int16_t>(pm >= 0 ? pm : -1 - A.mesh.tile_slot[k]);
+        }
     __syncthreads();
     const int32_t *hash;
     S(*sig)[2];
@@ -702,7 +708,7 @@ __global__ void __launch_bounds__(256) entries_kernel(EntryArgs<R> A)
         else return MeshMaterials{A.mesh.mat};
     }();
     const MeshP<R> &M = A.mesh;
-    const int8_t *pure = DENS ? nullptr : (JUMP ? s_pure : M.tile_mat);
+    const int8_t *pure = DENS ? nullptr : M.tile_mat;
     const R lox = M.lo[0], loy = M.lo[1], loz = M.lo[2];
     const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
     const R gx = R(1) / hx, gy = R(1) / hy, gz = R(1) / hz;
@@ -792,13 +798,15 @@ __global__ void __launch_bounds__(256) entries_kernel(EntryArgs<R> A)
                     }
                     out.write(ti, tj, tk, ex, ey, ez, cur, tau.hi, tau.lo, first);
                     first = false;
-                    const int pm = pure != nullptr ? pure[ti + A.g.ntx * (tj + A.g.nty * tk)] : -1;
+                    const int pm = s_code[ti + A.g.ntx * (tj + A.g.nty * tk)];
                     if (pm >= 0) {
                         tau.join(mysig[pm << shift][0] * (static_cast<S>(t_out) - static_cast<S>(cur)), S(0));
                     } else {
+                        // the tile's materials from its tile-major copy
+                        const TileMaterials tm{M.mixed + static_cast<int64_t>(-1 - pm) * kTileVoxels};
                         ts.tau = TauPair<S>{S(0), S(0)};
-                        wk.enter_tile(M, mats, ex, ey, ez, cur);
-                        while (wk.step(M, ts, mats)) {
+                        wk.resume_tile(M, tm, ox, oy, oz, ix, iy, iz, ex, ey, ez, cur);
+                        while (wk.step(M, ts, tm)) {
                         }
                         tau.join(ts.tau.hi, ts.tau.lo);
                     }
@@ -1272,7 +1280,7 @@ hipError_t grow(void *&p, size_t &cap, size_t need)
 }
 
 constexpr int kBlock = 256;  // ordering, counting and entries passes
-constexpr size_t kEntriesStatic = 5 * kMaxKeys;  // next place per key, and the tile table of the jumping walk
+constexpr size_t kEntriesStatic = 6 * kMaxKeys;  // next place per key, and the tile table of the jumping walk
 constexpr size_t kTileStatic = (sizeof(double) + 1) * kTileVoxels + 4 * kBucketsT + 2 * kMaxBlock * kTilePerMax;  // acc, mat, sort
 
 SortGeom geometry(const TallyHost &t, const MeshHost &m)
@@ -1491,6 +1499,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         }
         mesh.mat = m.d_mat;
         mesh.tile_mat = DENS ? nullptr : m.d_tile_mat;
+        mesh.tile_slot = DENS ? nullptr : m.d_tile_slot;
+        mesh.mixed = DENS ? nullptr : m.d_mixed;
         if constexpr (RECT) {
             const R *base = plane_tables<R>(m);  // x, y and z tables back to back
             mesh.pl[0] = base;
