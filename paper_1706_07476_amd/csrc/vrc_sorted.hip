@@ -551,19 +551,24 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
 }
 
 // Voxel index on one axis of a walk at ray parameter t (after every crossing
-// at or before t), searched inside [k_lo, k_hi] from a guess: u > 0 the
-// largest k with T(k) <= t, u < 0 the smallest k with T(k + 1) <= t (the
-// start-voxel rule of the walk, at t instead of the mesh entry).
+// at or before t), searched inside [k_lo, k_hi] from a guess: the voxel whose
+// entry crossing is at or before t and whose exit crossing is after it (for
+// u > 0 the planes k and k + 1, for u < 0 the planes k + 1 and k: the
+// start-voxel rule of the walk, at t instead of the mesh entry).  One loop
+// serves both directions, so lanes going opposite ways do not split; the
+// crossings increase along the direction of travel, so the search moves only
+// one way.
 template <typename R, class Planes>
 __device__ __forceinline__ int index_at(const Planes &X, int k_lo, int k_hi, int guess, R o, R inv, int s, R t)
 {
     int k = guess < k_lo ? k_lo : (guess > k_hi ? k_hi : guess);
-    if (s > 0) {
-        while (k > k_lo && (X(k) - o) * inv > t) --k;
-        while (k < k_hi && (X(k + 1) - o) * inv <= t) ++k;
-    } else {
-        while (k < k_hi && (X(k + 1) - o) * inv > t) ++k;
-        while (k > k_lo && (X(k) - o) * inv <= t) --k;
+    const int de = s < 0 ? 1 : 0, dx = s > 0 ? 1 : 0;  // entry and exit plane of voxel k: k + de, k + dx
+    const int k_back = s > 0 ? k_lo : k_hi, k_fwd = s > 0 ? k_hi : k_lo;
+    for (;;) {
+        const bool back = k != k_back && (X(k + de) - o) * inv > t;
+        const bool fwd = !back && k != k_fwd && (X(k + dx) - o) * inv <= t;
+        if (!(back || fwd)) break;
+        k += back ? -s : s;
     }
     return k;
 }
@@ -768,6 +773,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
             R cur = wk.cur;
             const R t_exit = wk.t_exit;
             int ex = wk.kx, ey = wk.ky, ez = wk.kz;  // the walk's voxel at cur (kept on parallel axes)
+            int ea = -1;  // the axis of the tile plane crossed last: its voxel at cur is the new tile's first
             bool first = true;
             for (int guard = (nx + ny + nz) / kTileEdge + 6; guard > 0; --guard) {
                 const bool ax = (cx <= cy) && (cx <= cz);
@@ -777,22 +783,22 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
                 const R t_out = last ? t_exit : ta;
                 if (t_out - cur > R(0)) {
                     // the voxel of the first piece in the tile
-                    const int x0 = ti << kTileBits, y0 = tj << kTileBits, z0 = tk << kTileBits;
-                    const int x1 = (x0 + kTileEdge < nx ? x0 + kTileEdge : nx) - 1;
-                    const int y1 = (y0 + kTileEdge < ny ? y0 + kTileEdge : ny) - 1;
-                    const int z1 = (z0 + kTileEdge < nz ? z0 + kTileEdge : nz) - 1;
                     if (!first) {
+                        const int x0 = ti << kTileBits, y0 = tj << kTileBits, z0 = tk << kTileBits;
+                        const int x1 = (x0 + kTileEdge < nx ? x0 + kTileEdge : nx) - 1;
+                        const int y1 = (y0 + kTileEdge < ny ? y0 + kTileEdge : ny) - 1;
+                        const int z1 = (z0 + kTileEdge < nz ? z0 + kTileEdge : nz) - 1;
                         if constexpr (RECT) {
-                            if (sx != 0) ex = index_at(X(0), x0, x1, ex, ox, ix, sx, cur);
-                            if (sy != 0) ey = index_at(X(1), y0, y1, ey, oy, iy, sy, cur);
-                            if (sz != 0) ez = index_at(X(2), z0, z1, ez, oz, iz, sz, cur);
+                            if (sx != 0 && ea != 0) ex = index_at(X(0), x0, x1, ex, ox, ix, sx, cur);
+                            if (sy != 0 && ea != 1) ey = index_at(X(1), y0, y1, ey, oy, iy, sy, cur);
+                            if (sz != 0 && ea != 2) ez = index_at(X(2), z0, z1, ez, oz, iz, sz, cur);
                         } else {
                             // a guess from the position (any guess is settled by the search)
-                            if (sx != 0)
+                            if (sx != 0 && ea != 0)
                                 ex = index_at(X(0), x0, x1, guess_in(ox + cur * ux, lox, gx, x0, x1), ox, ix, sx, cur);
-                            if (sy != 0)
+                            if (sy != 0 && ea != 1)
                                 ey = index_at(X(1), y0, y1, guess_in(oy + cur * uy, loy, gy, y0, y1), oy, iy, sy, cur);
-                            if (sz != 0)
+                            if (sz != 0 && ea != 2)
                                 ez = index_at(X(2), z0, z1, guess_in(oz + cur * uz, loz, gz, z0, z1), oz, iz, sz, cur);
                         }
                     }
@@ -812,17 +818,35 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
                     }
                 }
                 if (last) break;
+                // into the next tile on the crossed axis (selects, no branches: the lanes cross
+                // different axes); its next tile plane as the counting pass computes it, and the
+                // walk's voxel there: the first voxel of the new tile along the direction of travel
                 cur = ta;
-                if (ax) {
-                    ti += sx;
-                    cx = cross(0, lox, hx, ox, ix, sx, ti);
-                } else if (ay) {
-                    tj += sy;
-                    cy = cross(1, loy, hy, oy, iy, sy, tj);
+                const int s = ax ? sx : (ay ? sy : sz);
+                const int tn = (ax ? ti : (ay ? tj : tk)) + s;
+                const int kp = (tn + (s > 0 ? 1 : 0)) << kTileBits;
+                const R oa = ax ? ox : (ay ? oy : oz);
+                const R inva = ax ? ix : (ay ? iy : iz);
+                R cn;
+                if constexpr (RECT) {
+                    const R *pa = ax ? M.pl[0] : (ay ? M.pl[1] : M.pl[2]);
+                    const int na = ax ? nx : (ay ? ny : nz);
+                    cn = (pa[kp < na ? kp : na] - oa) * inva;
                 } else {
-                    tk += sz;
-                    cz = cross(2, loz, hz, oz, iz, sz, tk);
+                    cn = (plane(ax ? lox : (ay ? loy : loz), ax ? hx : (ay ? hy : hz), kp) - oa) * inva;
                 }
+                const int kv = s > 0 ? tn << kTileBits : ((tn + 1) << kTileBits) - 1;
+                const bool az = !ax && !ay;
+                ti = ax ? tn : ti;
+                tj = ay ? tn : tj;
+                tk = az ? tn : tk;
+                cx = ax ? cn : cx;
+                cy = ay ? cn : cy;
+                cz = az ? cn : cz;
+                ex = ax ? kv : ex;
+                ey = ay ? kv : ey;
+                ez = az ? kv : ez;
+                ea = ax ? 0 : (ay ? 1 : 2);
             }
         }
     }
