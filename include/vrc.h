@@ -556,6 +556,14 @@ vrc_status vrc_count_segments(vrc_ctx *ctx, int mesh_id, vrc_precision precision
  * optical depth), -1 restores the default (jump when at least half of the
  * mesh's tiles hold one material).  Both give the same records.           */
 #define VRC_TEST_ENTRIES_JUMP 3
+/* VRC_TEST_PLACE_ORDER chooses the order in which the tile-split
+ * accumulation walks its rays: 1 orders them by length, then by where they
+ * start and which way they go (the tile of the origin and the direction's
+ * signs), 0 by length only, -1 restores the default (the second ordering
+ * when the entries pass jumps over tiles of one material and every one of
+ * its wavefronts takes at least 24 runs of 64 rays).  The order changes no
+ * result beyond the order of the additions.                               */
+#define VRC_TEST_PLACE_ORDER 4
 vrc_status vrc_test_hook(vrc_ctx *ctx, int hook, int64_t value);
 
 /* Per-ray voxel sequences, lengths and scores, exactly as the casting kernel

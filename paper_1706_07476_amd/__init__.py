@@ -385,6 +385,7 @@ def vrc_cast_rays_noalloc(ctx: int, tally_id: int, batch: vrc_ray_batch, stream=
 VRC_TEST_SHORT_COUNT = 1
 VRC_TEST_RECORD_BUDGET = 2
 VRC_TEST_ENTRIES_JUMP = 3
+VRC_TEST_PLACE_ORDER = 4
 
 
 def vrc_test_hook(ctx: int, hook: int, value: int) -> None:

@@ -776,6 +776,10 @@ vrc_status vrc_test_hook(vrc_ctx *ctx, int hook, int64_t value)
         ctx->test_entries_jump = static_cast<int>(value);
         return VRC_OK;
     }
+    if (hook == VRC_TEST_PLACE_ORDER && value >= -1 && value <= 1) {
+        ctx->test_place_order = static_cast<int>(value);
+        return VRC_OK;
+    }
     if (hook == VRC_TEST_RECORD_BUDGET && value >= 0) {
         hipDeviceProp_t prop;
         VRC_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));

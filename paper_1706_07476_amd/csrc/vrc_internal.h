@@ -300,6 +300,7 @@ struct vrc_ctx {
     uint32_t *d_check = nullptr;
     int test_short_count = 0;    // test hooks (vrc_test_hook)
     int test_entries_jump = -1;
+    int test_place_order = -1;   // VRC_TEST_PLACE_ORDER: -1 auto, 0 by length only, 1 also by place
 };
 
 namespace vrc {

@@ -332,6 +332,69 @@ __global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(RaySrc src, 
     }
 }
 
+// Second ordering, by where a ray starts and which way it goes: key = 8 x
+// the tile of its origin's voxel (clamped into the mesh) + the signs of its
+// direction.  Rays of one key cross about the same tiles, so the lanes of a
+// wavefront of the entries pass reach tiles of several materials together
+// instead of one at a time.  It runs after the ordering by length over the
+// length-ordered rays; each block takes a run of them, so within a key the
+// rays stay in runs of about the same length.  An order, never a result.
+template <typename R, bool RECT>
+__device__ __forceinline__ int ray_place_key(const MeshP<R> &M, const SortGeom &g, const RayRec<R> &r)
+{
+    int v[3];
+    const R o[3] = {r.ox, r.oy, r.oz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if constexpr (RECT) {
+            const R lo = M.pl[a][0], span = M.pl[a][M.n[a]] - lo;
+            v[a] = axis_index(o[a], lo, static_cast<R>(M.n[a]) / span, M.n[a]);
+        } else {
+            v[a] = axis_index(o[a], M.lo[a], R(1) / M.h[a], M.n[a]);
+        }
+    }
+    const int tile = (v[0] >> kTileBits) + g.ntx * ((v[1] >> kTileBits) + g.nty * (v[2] >> kTileBits));
+    return 8 * tile + (r.ux > R(0) ? 1 : 0) + (r.uy > R(0) ? 2 : 0) + (r.uz > R(0) ? 4 : 0);
+}
+
+// Blocks of kOrderBlock threads, dynamic LDS of 8 * n_tiles counters.
+template <typename R, bool RECT>
+__global__ void __launch_bounds__(kOrderBlock) place_hist_kernel(MeshP<R> M, SortGeom g, const RayRec<R> *in,
+                                                                 int64_t n, int64_t rays_per_block, uint32_t *hist)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint32_t *s_hist = reinterpret_cast<uint32_t *>(lds);
+    const int nk = 8 * g.n_tiles;
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) s_hist[k] = 0u;
+    __syncthreads();
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
+    const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
+    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) atomicAdd(&s_hist[ray_place_key<R, RECT>(M, g, in[r])], 1u);
+    __syncthreads();
+    uint32_t *row = hist + static_cast<int64_t>(blockIdx.x) * nk;
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) row[k] = s_hist[k];
+}
+
+template <typename R, bool RECT>
+__global__ void __launch_bounds__(kOrderBlock) place_scatter_kernel(MeshP<R> M, SortGeom g, const RayRec<R> *in,
+                                                                    int64_t n, int64_t rays_per_block,
+                                                                    const uint32_t *row_off, const uint32_t *key_base,
+                                                                    RayRec<R> *out)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint32_t *s_base = reinterpret_cast<uint32_t *>(lds);
+    const int nk = 8 * g.n_tiles;
+    const uint32_t *row = row_off + static_cast<int64_t>(blockIdx.x) * nk;
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) s_base[k] = key_base[k] + row[k];
+    __syncthreads();
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
+    const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
+    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) {
+        const RayRec<R> rr = in[r];
+        out[atomicAdd(&s_base[ray_place_key<R, RECT>(M, g, rr)], 1u)] = rr;
+    }
+}
+
 // Next-event events (Sec. 6.3) in the same counting sort: by the voxel
 // distance between the event and the detector (each clamped into the mesh),
 // longest first, as records in the input precision with their index, so
@@ -1385,6 +1448,9 @@ struct Arena {
 
 constexpr size_t kArenaAlign = 256;
 constexpr int64_t kArenaRows = 512;  // blocks of the counting and entries passes on an arena
+// Runs of 64 rays per wavefront of the entries pass from which the rays are
+// also ordered by where they start (below that, by length only).
+constexpr int64_t kPlaceMinRounds = 24;
 
 size_t arena_round(size_t v) { return (v + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
 
@@ -1418,7 +1484,22 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     const size_t rec = sizeof(Entry<R, S>);
     int shift = 0;
     while (((static_cast<int64_t>(m.n[0]) + m.n[1] + m.n[2]) >> shift) >= kBucketsE) ++shift;
-    const int hist_keys = g.n_keys > kBucketsE ? g.n_keys : kBucketsE;  // hist rows serve both sorts
+    // the second ordering (by place) when its counters fit in LDS; not on an arena, whose fixed size
+    // the place rows would mostly take (the order changes no result)
+    const int n_place = 8 * g.n_tiles;
+    const size_t lds_place = sizeof(uint32_t) * static_cast<size_t>(n_place);
+    const bool place_ok = arena.base == nullptr && lds_place <= ctx.lds_max && ctx.test_place_order != 0;
+    if (place_ok) {
+        // blocks may take more than 64 KiB of LDS on this GPU (up to its per-block limit)
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&place_hist_kernel<R, RECT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_place));
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&place_scatter_kernel<R, RECT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_place));
+        if (e != hipSuccess) return e;
+    }
+    // hist rows serve the three sorts
+    const int hist_keys = std::max(std::max(g.n_keys, kBucketsE), place_ok ? n_place : 0);
     // LDS is kept for occupancy: the energy-grid hash stays in global memory
     // (it is read once per ray or record and stays in L2).
     const size_t lds1 = sigma_lds(ctx, sizeof(S), kBlock);
@@ -1482,6 +1563,12 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         const int64_t rays_block = (nr + G - 1) / G;  // ordering kernels
         const int64_t slices = (nr + 63) / 64;
         const int Ge = static_cast<int>(G_res < (slices + 3) / 4 ? G_res : (slices + 3) / 4);
+        // the ordering by place pays for the jumping entries pass (its lanes then meet tiles of several
+        // materials together) where each wavefront takes many runs of rays (with few, the runs' unequal
+        // lengths leave some wavefronts working long after the others); the walking form walks every
+        // voxel whatever the order and loses the finer length order
+        const bool by_place =
+            place_ok && (ctx.test_place_order == 1 || (jump && slices >= kPlaceMinRounds * (kBlock / 64) * Ge));
         const int64_t cap = nr * per_ray;  // records
         const size_t rows = static_cast<size_t>(G > Ge ? G : Ge);
         void *b_sorted, *b_hist, *b_row_off, *b_key_tot, *b_key_base, *b_ordered, *b_bucket, *b_partial;
@@ -1573,9 +1660,26 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         hipLaunchKernelGGL(scan_rows_kernel, dim3(kBucketsE / 64), dim3(64 * kScanWaves), 0, s, hist, G, kBucketsE,
                            row_off, key_tot);
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, key_tot, kBucketsE, key_base);
-        hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, sub, nr,
-                           static_cast<const uint8_t *>(b_bucket), rays_block, row_off, key_base,
-                           static_cast<RayRec<R> *>(b_ordered));
+        if (by_place) {
+            // by length into the record space (free until the entries pass), then by place into b_ordered
+            RayRec<R> *by_len = static_cast<RayRec<R> *>(b_sorted);
+            hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, sub, nr,
+                               static_cast<const uint8_t *>(b_bucket), rays_block, row_off, key_base, by_len);
+            hipLaunchKernelGGL((place_hist_kernel<R, RECT>), dim3(G), dim3(kOrderBlock), lds_place, s, mesh, g,
+                               static_cast<const RayRec<R> *>(by_len), nr, rays_block, hist);
+            hipLaunchKernelGGL(scan_rows_kernel, dim3((n_place + 63) / 64), dim3(64 * kScanWaves), 0, s,
+                               static_cast<const uint32_t *>(hist), G, n_place, row_off, key_tot);
+            hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
+                               n_place, key_base);
+            hipLaunchKernelGGL((place_scatter_kernel<R, RECT>), dim3(G), dim3(kOrderBlock), lds_place, s, mesh, g,
+                               static_cast<const RayRec<R> *>(by_len), nr, rays_block,
+                               static_cast<const uint32_t *>(row_off), static_cast<const uint32_t *>(key_base),
+                               static_cast<RayRec<R> *>(b_ordered));
+        } else {
+            hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, sub, nr,
+                               static_cast<const uint8_t *>(b_bucket), rays_block, row_off, key_base,
+                               static_cast<RayRec<R> *>(b_ordered));
+        }
         hipLaunchKernelGGL((count_entries_kernel<R, RECT>), dim3(Ge), dim3(kBlock), 0, s, A);
         hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
                            static_cast<const uint32_t *>(hist), Ge, g.n_keys, row_off, key_tot);

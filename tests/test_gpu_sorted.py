@@ -215,6 +215,52 @@ def test_sorted_single_material_and_void_tiles(vrc, ctx, prec, jump):
     assert o <= TOL_ORDER
 
 
+def outside_origins(rays, mesh, frac=0.2, seed=0):
+    """A fraction of the rays moved to start up to 5 cm outside the mesh on -x, aimed back in."""
+    rng = np.random.default_rng(seed)
+    r = rays.take(slice(0, rays.n))
+    k = rng.random(r.n) < frac
+    r.ox[k] = mesh.lo[0] - 5.0 * rng.random(int(k.sum()))
+    r.ux[k] = np.abs(r.ux[k])
+    return r
+
+
+@pytest.mark.parametrize("case", ["ragged", "one-material-jump", "one-material-walk", "rect"])
+def test_sorted_place_order(vrc, ctx, case):
+    """Rays ordered by length, then by place (the tile of the origin's voxel, the origin clamped into
+    the mesh, and the direction's signs), forced on: the tally equals the atomic path's to the order
+    of the additions and the oracle's to the FP64 bound, with origins inside and outside a ragged mesh
+    (10 energy bins), on single-material tiles (jumping and walking entries passes) and on a
+    rectilinear mesh (the key from its plane tables)."""
+    vrc.vrc_test_hook(ctx.handle, vrc.VRC_TEST_PLACE_ORDER, 1)
+    edges = None
+    xs = W.config2_multimaterial(n_rays=0).xs
+    if case == "ragged":
+        mesh = ragged_mesh(seed=531)
+        rays = outside_origins(W.rays_in_box(532, mesh, 120_000), mesh, seed=533)
+        edges = W.log_bin_edges(10, 1e-9, 1.0)
+    elif case == "rect":
+        mesh = W.rect_mesh(534, (52, 47, 33), lo=(1.0, -3.0, 0.5), h_min=0.15, h_max=1.4)
+        rays = outside_origins(W.rays_in_box(535, mesh, 120_000), mesh, seed=536)
+    else:
+        vrc.vrc_test_hook(ctx.handle, vrc.VRC_TEST_ENTRIES_JUMP, 1 if case.endswith("jump") else 0)
+        mesh = one_material_tiles_mesh()
+        tabs = [xs.table(m) for m in range(3)] + [W.constant_sigma_table(0.0)]
+        xs = W.gen.make_xs(tabs)
+        rays = W.rays_in_box(537, mesh, 120_000)
+    say(f"case: sorted p64 ordered by place, {case}, {rays.n} rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(xs)
+    got, atom = cast_both(ctx, 0, "p64", dev_arrays(rays, "f64"), edges)
+    o = order_rel(got, atom)
+    res = oracle.cast(mesh, xs, rays, edges=edges, n_threads=oracle_threads())
+    g, _, n = rel_report(got.reshape(10, -1) if edges is not None else got, res, gate="all")
+    say(f"  sorted vs atomic {o:.3e}; vs oracle {g:.3e} over {n} voxels")
+    assert n > 0.5 * mesh.n_voxels
+    assert o <= TOL_ORDER
+    assert g <= TOL_P64
+
+
 def test_beyond_key_limit_uses_atomics(ctx):
     """128^3 with 9 bins = 4608 keys: the sorted setting falls back to the atomic path."""
     mesh = W.slab_mesh(511, 128, 0.5)
