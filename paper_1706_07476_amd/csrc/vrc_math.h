@@ -68,23 +68,48 @@ VRC_HD inline float vrc_ldexp(float a, int k) { return ::ldexpf(a, k); }
 VRC_HD inline double vrc_rint(double a) { return ::rint(a); }
 VRC_HD inline float vrc_rint(float a) { return ::rintf(a); }
 
-// One Horner step p r + c with a constant coefficient c.  In FP64 device code
-// it is the three-operand FMA with c in a scalar register pair: left to
-// itself the compiler keeps the coefficients in vector registers and uses
-// the two-operand form, which overwrites its addend, so every step copies a
-// coefficient first (12 copies per evaluation and 26 registers held).  The
-// arithmetic is the same fused multiply-add.
-VRC_HD inline float horner_step(float p, float r, float c) { return vrc_fma(p, r, c); }
-#if defined(__HIP_DEVICE_COMPILE__)
-__device__ inline double horner_step(double p, double r, double c)
+// The Horner sum p = 1/1! + r (1/2! + ... + r / D!) of the expm1 series.
+// In FP64 device code (D = 13) it is one block of twelve dependent
+// three-operand FMAs: left to itself the compiler keeps the coefficients in
+// vector registers and uses the two-operand FMA, which overwrites its
+// addend, so every step first copies a coefficient (twelve copies per
+// evaluation).  The arithmetic is the same sequence of fused multiply-adds.
+template <typename R>
+VRC_HD inline R horner_series(R r)
 {
-    double d;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(p), "v"(r), "s"(c));
-    return d;
+    R p = static_cast<R>(inv_factorial(AttenConst<R>::degree));
+#pragma unroll
+    for (int j = AttenConst<R>::degree - 1; j >= 1; --j) p = vrc_fma(p, r, static_cast<R>(inv_factorial(j)));
+    return p;
 }
+VRC_HD inline float horner_expm1(float r) { return horner_series(r); }
+static_assert(AttenConst<double>::degree == 13, "the FP64 Horner block below has twelve steps");
+VRC_HD inline double horner_expm1(double r)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double p;
+    asm("v_fma_f64 %0, %2, %1, %3\n\t"
+        "v_fma_f64 %0, %0, %1, %4\n\t"
+        "v_fma_f64 %0, %0, %1, %5\n\t"
+        "v_fma_f64 %0, %0, %1, %6\n\t"
+        "v_fma_f64 %0, %0, %1, %7\n\t"
+        "v_fma_f64 %0, %0, %1, %8\n\t"
+        "v_fma_f64 %0, %0, %1, %9\n\t"
+        "v_fma_f64 %0, %0, %1, %10\n\t"
+        "v_fma_f64 %0, %0, %1, %11\n\t"
+        "v_fma_f64 %0, %0, %1, %12\n\t"
+        "v_fma_f64 %0, %0, %1, %13\n\t"
+        "v_fma_f64 %0, %0, %1, %14"
+        : "=&v"(p)
+        : "v"(r), "v"(inv_factorial(13)), "v"(inv_factorial(12)), "v"(inv_factorial(11)), "v"(inv_factorial(10)),
+          "v"(inv_factorial(9)), "v"(inv_factorial(8)), "v"(inv_factorial(7)), "v"(inv_factorial(6)),
+          "v"(inv_factorial(5)), "v"(inv_factorial(4)), "v"(inv_factorial(3)), "v"(inv_factorial(2)),
+          "v"(inv_factorial(1)));
+    return p;
 #else
-inline double horner_step(double p, double r, double c) { return vrc_fma(p, r, c); }
+    return horner_series(r);
 #endif
+}
 
 // g = exp(-x), em = 1 - exp(-x) for x >= 0 (x > x_max or NaN: g = 0, em = 1).
 // Branch-free: out-of-range arguments are evaluated at 0 and their results
@@ -99,10 +124,7 @@ VRC_HD inline void attenuation(R x, R &g, R &em)
     R r = vrc_fma(-kf, C::ln2_hi, y);
     r = vrc_fma(-kf, C::ln2_lo, r);
     // Horner: q = r (1/1! + r (1/2! + r (1/3! + ... + r / degree!)))
-    R p = static_cast<R>(inv_factorial(C::degree));
-#pragma unroll
-    for (int j = C::degree - 1; j >= 1; --j) p = horner_step(p, r, static_cast<R>(inv_factorial(j)));
-    const R q = p * r;
+    const R q = horner_expm1(r) * r;
     const R s = vrc_ldexp(R(1), static_cast<int>(kf));
     const R gv = vrc_fma(s, q, s);
     const R ev = vrc_fma(-s, q, R(1) - s);
