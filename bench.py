@@ -134,7 +134,8 @@ def _counter_rows(csv_path: str, kernel: str, counter: str) -> list:
 def pipeline(precision: str, accumulate: int) -> list:
     """Names (as rocprofv3 prints them, up to the argument list; the entries kernel up to its last template
     argument, which the library picks per mesh) of the kernels of one cast of FP32 rays (FP64 rays for p64)
-    on a uniform mesh; the first one runs exactly once per cast."""
+    on a uniform mesh; the first one runs exactly once per cast (the ordering by place only on batches
+    large enough for it)."""
     R = "double" if precision == "p64" else "float"
     S = "float" if precision in ("p32_t64", "p32_kahan") else "double"
     if accumulate == 0:
@@ -143,8 +144,9 @@ def pipeline(precision: str, accumulate: int) -> list:
         return [f"cast_f64_kernel<{R}, {R}, false, {S}, false, false>"]
     flush = 2 if precision == "p32_kahan" else (1 if accumulate == 3 else 0)
     return [f"entries_kernel<{R}, {R}, {S}, false, false, ", f"order_hist_kernel<{R}, {R}>",
-            f"order_scatter_kernel<{R}, {R}>", f"count_entries_kernel<{R}, false>", "scan_rows_kernel",
-            "scan_keys_kernel", f"tile_kernel<{R}, {S}, {flush}, false, false>", f"tile_reduce_kernel<{flush}>"]
+            f"order_scatter_kernel<{R}, {R}>", f"place_hist_kernel<{R}, false>", f"place_scatter_kernel<{R}, false>",
+            f"count_entries_kernel<{R}, false>", "scan_rows_kernel", "scan_keys_kernel",
+            f"tile_kernel<{R}, {S}, {flush}, false, false>", f"tile_reduce_kernel<{flush}>"]
 
 
 def write_traffic(paths, workload="cylinder", precision="p32_d64", copy_mib=1024) -> None:

@@ -107,9 +107,11 @@ typedef struct {
  * another stream, a batched or serving launch, load/reset) overlaps the
  * cast: order such work with streams or events (for a compensated FP32
  * tally, 3 flushes like 2, with a compensated atomic update).  The
- * tile-split modes apply when the tally has at most 4096 (tile, energy bin)
- * pairs and the cross-section columns fit in LDS; otherwise the atomic path
- * runs.  They use scratch device memory grown on demand (about n_rays *
+ * tile-split modes apply when the mesh has at most 4096 tiles and the
+ * cross-section columns fit in LDS; otherwise the atomic path runs.  A tally
+ * with more than 4096 (tile, energy bin) pairs is cast in groups of bins
+ * (as many as fit 4096 pairs), one after the other over the same ordered
+ * rays.  They use scratch device memory grown on demand (about n_rays *
  * (tiles along x + y + z) * 48..96 bytes, at most about 2 GB per sub-launch),
  * so the first cast of a larger batch allocates and is not capturable in a
  * graph; tile-split casts of one context are serialised with each other.
@@ -307,8 +309,8 @@ typedef struct {
  * split: 0 = the persistent kernel (one atomic per segment); 1 = the
  * tile-split accumulation of vrc_launch (rays ordered by length, split at
  * tile entries, scored per tile in LDS), run once per tally over all of that
- * tally's batches, when every tally of the call allows it (at most 4096
- * (tile, bin) pairs), else the persistent kernel.  Tallies on rectilinear
+ * tally's batches, when every tally of the call allows it (a mesh of at
+ * most 4096 tiles), else the persistent kernel.  Tallies on rectilinear
  * meshes or meshes with density factors are cast with split = 1 only (the
  * persistent kernel walks plain uniform meshes): otherwise VRC_ERR_INVALID,
  * and the autotuner tries only the split setting for them.  With split,
@@ -400,7 +402,11 @@ typedef struct {
  * owns a device ray ring, two pinned staging buffers and its threads until
  * vrc_serve_stop.  Tallies used by requests must be FP64-tally forms
  * (VRC_P64 or VRC_P32_T64, matching the ray type: FP32 rays for VRC_P32_T64,
- * FP64 rays for VRC_P64) or the compensated form (FP32 rays).              */
+ * FP64 rays for VRC_P64) or the compensated form (FP32 rays).  A launch
+ * casts each tally's requests through the tile-split accumulation when
+ * vrc_launch's accumulate setting selects it for their total ray count and
+ * the tally allows it (see vrc_launch), else through the persistent batched
+ * kernel (one plain cast per request on rectilinear, R-Z or density meshes).*/
 vrc_status vrc_serve_start(vrc_ctx *ctx, const vrc_serve_config *config);
 
 /* Submit a host ray batch for tally_id.  Admission is by memory: the rays

@@ -1276,7 +1276,7 @@ vrc_status vrc_cast_batches(vrc_ctx *ctx, int n_batches, const vrc_batch *batche
     // the persistent kernel walks uniform meshes without density factors only
     if (kinds)
         return set_error(VRC_ERR_INVALID, "a tally on a rectilinear mesh or with density factors needs the "
-                                          "tile-split batched cast (split = 1, at most 4096 (tile, bin) pairs)");
+                                          "tile-split batched cast (split = 1, a mesh of at most 4096 tiles)");
     BatchedSlot &bs = ctx->bslot[ctx->bslot_next];
     ctx->bslot_next ^= 1;
     return run_batched(ctx, bs, shape, static_cast<vrc_precision>(prec), fp64 != 0, desc, items,

@@ -1,6 +1,7 @@
 // Serving form: a request loop that admits host ray batches by memory and
-// casts whatever has arrived, continuously, with the persistent batched
-// kernel.
+// casts whatever has arrived, continuously: each tally's share of a launch
+// through the tile-split accumulation when it is large enough, the rest
+// with the persistent batched kernel.
 //
 //   submit (any thread)  -> admission: space in the device ray ring and in
 //                           the pinned staging buffer being filled, else wait
@@ -176,11 +177,13 @@ double percentile(std::vector<double> v, double q)
     return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
 }
 
-// Launch one group of requests (same tally form and ray type) on stream s:
-// the persistent kernel for requests on plain uniform meshes, and before it
-// one plain cast per request on a rectilinear or R-Z mesh or a mesh with
-// density factors (the persistent kernel walks plain uniform meshes only).  The
-// slot's event, recorded after the last launch, marks the group done.
+// Launch one group of requests (same tally form and ray type) on stream s.
+// A tally whose requests in the group hold enough rays for the tile-split
+// accumulation (the rule of vrc_launch's accumulate setting) gets one
+// tile-split pipeline over all of them; the other requests go to the
+// persistent kernel if on plain uniform meshes, else one plain cast each (the
+// persistent kernel walks plain uniform meshes only).  The slot's event,
+// recorded after the last launch, marks the group done.
 vrc_status launch_group(vrc_ctx *ctx, ServeState &S, std::vector<ServeRequest> &reqs, int slot, hipStream_t s)
 {
     std::vector<BatchDescDev> desc;
@@ -190,11 +193,33 @@ vrc_status launch_group(vrc_ctx *ctx, ServeState &S, std::vector<ServeRequest> &
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         shape = ctx->batched;
+        std::map<int, int64_t> rays_of;  // per tally, its rays in this group
+        for (const auto &r : reqs) rays_of[r.tally_id] += r.n;
+        const int acc = ctx->launch.accumulate;
+        std::vector<vrc_batch> split_b;
+        std::vector<int> split_ids;
+        std::map<int, std::vector<int>> split_of;
         for (const auto &r : reqs) {
             const TallyHost *t = ctx->tallies[r.tally_id].get();
             prec = t->prec;
             const size_t el = r.fp64 ? 8 : 4;
             const MeshHost &m = ctx->meshes[t->mesh_id];
+            if (acc != 0 && (acc != 1 || rays_of[r.tally_id] >= kSplitMinRays) && sorted_eligible(*ctx, *t, m)) {
+                vrc_batch b{};
+                b.tally_id = r.tally_id;
+                b.fp64 = r.fp64;
+                b.n = r.n;
+                const void **p[8] = {&b.ox, &b.oy, &b.oz, &b.ux, &b.uy, &b.uz, &b.e, &b.w};
+                for (int k = 0; k < 8; ++k) *p[k] = S.d_ring + r.ring_off + k * el * static_cast<size_t>(r.n);
+                auto it = split_of.find(r.tally_id);
+                if (it == split_of.end()) {
+                    split_ids.push_back(r.tally_id);
+                    it = split_of.emplace(r.tally_id, std::vector<int>()).first;
+                }
+                it->second.push_back(static_cast<int>(split_b.size()));
+                split_b.push_back(b);
+                continue;
+            }
             if (m.rect || m.dens || m.rz) {
                 RaysP rays;
                 const void **p[8] = {&rays.ox, &rays.oy, &rays.oz, &rays.ux, &rays.uy, &rays.uz, &rays.e, &rays.w};
@@ -215,6 +240,10 @@ vrc_status launch_group(vrc_ctx *ctx, ServeState &S, std::vector<ServeRequest> &
             d.mesh = t->mesh_id;
             items += (r.n + shape.chunk - 1) / shape.chunk;
             desc.push_back(d);
+        }
+        if (!split_ids.empty()) {
+            const vrc_status st = run_split_batches(ctx, split_ids, split_of, split_b.data(), reqs.front().fp64 != 0, s);
+            if (st != VRC_OK) return st;
         }
     }
     if (!desc.empty()) return run_batched(ctx, S.slots[slot], shape, prec, reqs.front().fp64 != 0, desc, items, s);

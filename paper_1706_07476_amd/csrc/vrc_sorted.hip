@@ -71,9 +71,21 @@ struct __align__(16) Entry {
     uint32_t code;
 };
 
+// Keys of one launch: (bin - bin0) * n_tiles + tile for the n_gbins energy
+// bins from bin0 (a tally with more bins than fit kMaxKeys keys is cast in
+// groups of bins, one after the other, each over the rays of its bins).
 struct SortGeom {
     int32_t ntx, nty, n_tiles, n_keys;
+    int32_t bin0, n_gbins;
 };
+
+// The ray's energy bin within the launch's group of bins, or -1 (outside
+// the tally's bins or in another group).
+__device__ __forceinline__ int group_bin(const TallyP &T, const SortGeom &g, double E)
+{
+    const int bin = energy_bin(T, E) - g.bin0;
+    return bin >= 0 && bin < g.n_gbins ? bin : -1;
+}
 
 __device__ __forceinline__ uint32_t local_index(int ci, int cj, int ck)
 {
@@ -591,7 +603,7 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
         const int64_t j = deal.ray(round);
         if (j >= n) continue;
         const RayRec<R> rr = ordered[j];
-        const int bin = energy_bin(A.tally, static_cast<double>(rr.e));
+        const int bin = group_bin(A.tally, A.g, static_cast<double>(rr.e));
         if (bin < 0) continue;
         const int key0 = bin * A.g.n_tiles;
         walk_tiles<R, RECT>(A.mesh, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz, [&](int ti, int tj, int tk) {
@@ -804,7 +816,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
         const int64_t j = deal.ray(round);
         if (j >= n) continue;
         const RayRec<R> rr = ordered[j];
-        const int bin = energy_bin(A.tally, static_cast<double>(rr.e));
+        const int bin = group_bin(A.tally, A.g, static_cast<double>(rr.e));
         if (bin < 0) continue;
         if (!wk.start(M, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz)) continue;
         if constexpr (DENS) dnext = dens[wk.vox];  // start() reads the first voxel's material itself
@@ -1293,7 +1305,7 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
             for (int i = threadIdx.x; i < kTileVoxels; i += bd) {
                 const double v = acc[i];
                 if (v == 0.0) continue;
-                const int64_t idx = tile_element(i, bin, tx, ty, tz, nx, ny, nz, A.nvox);
+                const int64_t idx = tile_element(i, A.g.bin0 + bin, tx, ty, tz, nx, ny, nz, A.nvox);
                 if (idx >= 0) flush_voxel<FLUSH>(A.tally, idx, v);
             }
         } else {
@@ -1329,7 +1341,7 @@ __global__ void __launch_bounds__(256) tile_reduce_kernel(const uint32_t *key_ba
         double v = 0.0;
         for (uint32_t bb = b0; bb <= b1; ++bb) v += partial[static_cast<int64_t>(deal.slot(bb, kb)) * kTileVoxels + i];
         if (v == 0.0) continue;
-        const int64_t idx = tile_element(i, bin, tx, ty, tz, nx, ny, nz, nvox);
+        const int64_t idx = tile_element(i, g.bin0 + bin, tx, ty, tz, nx, ny, nz, nvox);
         if (idx >= 0) flush_voxel<FLUSH>(tally, idx, v);
     }
 }
@@ -1377,9 +1389,11 @@ SortGeom geometry(const TallyHost &t, const MeshHost &m)
     g.nty = (m.n[1] + kTileEdge - 1) / kTileEdge;
     const int ntz = (m.n[2] + kTileEdge - 1) / kTileEdge;
     const int64_t tiles = static_cast<int64_t>(g.ntx) * g.nty * ntz;
-    const int64_t keys = tiles * t.n_bins;
     g.n_tiles = tiles <= kMaxKeys ? static_cast<int32_t>(tiles) : 0;
-    g.n_keys = keys <= kMaxKeys ? static_cast<int32_t>(keys) : 0;
+    // as many bins per launch as fit kMaxKeys keys (the first group; run_sorted_kind moves bin0)
+    g.n_gbins = g.n_tiles > 0 ? std::min(t.n_bins, kMaxKeys / g.n_tiles) : 0;
+    g.n_keys = g.n_tiles * g.n_gbins;
+    g.bin0 = 0;
     return g;
 }
 
@@ -1680,34 +1694,43 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
                                static_cast<const uint8_t *>(b_bucket), rays_block, row_off, key_base,
                                static_cast<RayRec<R> *>(b_ordered));
         }
-        hipLaunchKernelGGL((count_entries_kernel<R, RECT>), dim3(Ge), dim3(kBlock), 0, s, A);
-        hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
-                           static_cast<const uint32_t *>(hist), Ge, g.n_keys, row_off, key_tot);
-        hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
-                           g.n_keys, key_base);
-        hipLaunchKernelGGL(entries, dim3(Ge), dim3(kBlock), lds1, s, A);
-        TileArgs<R> T;
-        T.mesh = mesh;
-        T.xs = A.xs;
-        T.hash_in_lds = 0;
-        T.g = g;
-        T.sorted = b_sorted;
-        T.key_base = static_cast<const uint32_t *>(b_key_base);
-        T.nvox = t.nvox;
-        T.tally = t.d_data;
-        T.partial = static_cast<double *>(b_partial);
-        T.n_blocks = n_tb;
-        if constexpr (sizeof(S) == 4) {
-            if (flush == kFlushKahan) {
-                e = launch_tiles<R, S, kFlushKahan, RECT, DENS>(T, tb, lds2, s);
-                goto launched;
+        // the tally's energy bins in groups of at most g.n_gbins (kMaxKeys keys), each group's rays
+        // counted, entered and scored in turn over the same ordered rays
+        for (int bin0 = 0; bin0 < t.n_bins; bin0 += g.n_gbins) {
+            SortGeom gg = g;
+            gg.bin0 = bin0;
+            gg.n_gbins = std::min(g.n_gbins, t.n_bins - bin0);
+            gg.n_keys = gg.n_tiles * gg.n_gbins;
+            A.g = gg;
+            hipLaunchKernelGGL((count_entries_kernel<R, RECT>), dim3(Ge), dim3(kBlock), 0, s, A);
+            hipLaunchKernelGGL(scan_rows_kernel, dim3((gg.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
+                               static_cast<const uint32_t *>(hist), Ge, gg.n_keys, row_off, key_tot);
+            hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
+                               gg.n_keys, key_base);
+            hipLaunchKernelGGL(entries, dim3(Ge), dim3(kBlock), lds1, s, A);
+            TileArgs<R> T;
+            T.mesh = mesh;
+            T.xs = A.xs;
+            T.hash_in_lds = 0;
+            T.g = gg;
+            T.sorted = b_sorted;
+            T.key_base = static_cast<const uint32_t *>(b_key_base);
+            T.nvox = t.nvox;
+            T.tally = t.d_data;
+            T.partial = static_cast<double *>(b_partial);
+            T.n_blocks = n_tb;
+            if constexpr (sizeof(S) == 4) {
+                if (flush == kFlushKahan) {
+                    e = launch_tiles<R, S, kFlushKahan, RECT, DENS>(T, tb, lds2, s);
+                    goto launched;
+                }
             }
+            e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic, RECT, DENS>(T, tb, lds2, s)
+                                      : launch_tiles<R, S, kFlushPlain, RECT, DENS>(T, tb, lds2, s);
+        launched:
+            if (e == hipSuccess) e = hipGetLastError();
+            if (e != hipSuccess) return e;
         }
-        e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic, RECT, DENS>(T, tb, lds2, s)
-                                  : launch_tiles<R, S, kFlushPlain, RECT, DENS>(T, tb, lds2, s);
-    launched:
-        if (e == hipSuccess) e = hipGetLastError();
-        if (e != hipSuccess) return e;
     }
     if (arena.base != nullptr) return hipSuccess;  // the context's buffers were not used
     hipError_t e = hipEventRecord(sc.done, s);

@@ -225,15 +225,19 @@ def serve_alone_and_mixed(ctx, mesh, prec, edges, requests, noise, n_producers=4
     return alone, mixed
 
 
-def test_served_fp64_10_bins_match_the_oracle(ctx):
-    """128^3 sphere mesh with 10 energy bins (5120 (tile, bin) pairs, beyond the tile-split key limit, as
-    the serving workload's 200^3 x 10 bins): every voxel of every bin within 1e-12 of the oracle, alone
-    and in the mix."""
+@pytest.mark.parametrize("accumulate", [0, 1, 2])
+def test_served_fp64_10_bins_match_the_oracle(ctx, accumulate):
+    """128^3 sphere mesh with 10 energy bins (5120 (tile, bin) pairs, more than one tile-split launch
+    holds, as the serving workload's 200^3 x 10 bins: groups of 8 + 2 bins): every voxel of every bin
+    within 1e-12 of the oracle, alone and in the mix; launches through the persistent kernel
+    (accumulate 0), the tile-split accumulation where a tally's share of a launch is large (1), or the
+    tile-split accumulation always (2)."""
     wl = W.config5_serving_geometry(n=128, h=1.5, radius=48.0)
     ctx.set_mesh(0, wl.mesh)
     ctx.set_xs(wl.xs)
+    ctx.set_launch(accumulate=accumulate)
     edges = wl.ebin_edges
-    say("case: served p64 10-bin tallies on 128^3 vs the oracle, alone and in the mix")
+    say(f"case: served p64 10-bin tallies on 128^3 vs the oracle, alone and in the mix, accumulate {accumulate}")
     ctx.serve_start(n_streams=2, max_inflight=4, max_requests_per_launch=16)
     reqs = [request_rays(900 + i, wl.mesh, 7000 + 1111 * i) for i in range(12)]
     noise = [request_rays(950 + i, wl.mesh, 3000 + 97 * i) for i in range(40)]
