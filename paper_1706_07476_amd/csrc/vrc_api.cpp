@@ -443,6 +443,7 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         if (sc.h_refs) (void)hipHostFree(sc.h_refs);
         free_dev(sc.bucket);
         free_dev(sc.partial);
+        free_dev(sc.bounds);
         if (sc.done) (void)hipEventDestroy(sc.done);
     }
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);

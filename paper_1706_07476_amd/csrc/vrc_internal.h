@@ -117,8 +117,9 @@ struct SortScratch {
     void *sorted = nullptr, *hist = nullptr, *row_off = nullptr;
     void *key_tot = nullptr, *key_base = nullptr, *ordered = nullptr, *bucket = nullptr;
     void *partial = nullptr;  // tiles of keys shared by two or more blocks of the tiles pass
+    void *bounds = nullptr;   // per energy-bin group its first ordered ray
     size_t sorted_cap = 0, hist_cap = 0, row_off_cap = 0;
-    size_t key_tot_cap = 0, key_base_cap = 0, ordered_cap = 0, bucket_cap = 0, partial_cap = 0;
+    size_t key_tot_cap = 0, key_base_cap = 0, ordered_cap = 0, bucket_cap = 0, partial_cap = 0, bounds_cap = 0;
     std::map<std::pair<const void *, size_t>, int> occupancy;  // (kernel, LDS bytes) -> resident blocks per CU
     // record bytes of one sub-launch: room for the most tiles every ray of it could cross (an eighth of
     // the device's memory, 2 to 64 GiB: the 256^3 mesh's 1e7 rays in one sub-launch on a 288 GB GPU)

@@ -289,18 +289,24 @@ __device__ __forceinline__ void load_ray(const RaySrc &S, int64_t r, R &ox, R &o
     w = ld<R, RT>(p7, i);
 }
 
-// Ordering of the rays by estimated length, longest first (a counting sort
-// over the whole batch, through the same block-row scans as the records):
-// order_hist counts each block's rays per length bucket, order_scatter
-// writes each ray, as one record, to its place.  Few large blocks: the
-// block-row scans that follow are shorter, and each thread has few rays.
+// Ordering of the rays by energy-bin group (a tally whose bins are cast in
+// groups gets each group's rays together), then by estimated length,
+// longest first (a counting sort over the whole batch, through the same
+// block-row scans as the records): order_hist counts each block's rays per
+// bucket, order_scatter writes each ray, as one record, to its place.
+// Bucket: group * lb + length slot; rays outside the tally's bins go to the
+// last bucket, n_buckets - 1.  Few large blocks: the block-row scans that
+// follow are shorter, and each thread has few rays.  Dynamic LDS: n_buckets
+// counters.
 constexpr int kOrderBlock = 1024;
 template <typename R, typename RT>
 __global__ void __launch_bounds__(kOrderBlock) order_hist_kernel(MeshP<R> M, RaySrc src, int64_t n, int64_t rays_per_block,
-                                                         int shift, uint8_t *bucket, uint32_t *hist)
+                                                         int shift, TallyP T, int gbins, int lb, int n_buckets,
+                                                         uint16_t *bucket, uint32_t *hist)
 {
-    __shared__ uint32_t s_hist[kBucketsE];
-    for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) s_hist[k] = 0u;
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint32_t *s_hist = reinterpret_cast<uint32_t *>(lds);
+    for (int k = threadIdx.x; k < n_buckets; k += blockDim.x) s_hist[k] = 0u;
     __syncthreads();
     const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
     const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
@@ -309,13 +315,22 @@ __global__ void __launch_bounds__(kOrderBlock) order_hist_kernel(MeshP<R> M, Ray
         load_ray<R, RT>(src, r, ox, oy, oz, ux, uy, uz, e, w);
         const int est = ray_pieces_estimate(M, ox, oy, oz, ux, uy, uz);
         const int bk = est >> shift;
-        const int slot = kBucketsE - 1 - (bk < kBucketsE ? bk : kBucketsE - 1);  // longest first
-        bucket[r] = static_cast<uint8_t>(slot);
+        const int bin = energy_bin(T, static_cast<double>(e));
+        const int slot = bin < 0 ? n_buckets - 1 : (bin / gbins) * lb + lb - 1 - (bk < lb ? bk : lb - 1);  // longest first
+        bucket[r] = static_cast<uint16_t>(slot);
         atomicAdd(&s_hist[slot], 1u);
     }
     __syncthreads();
-    uint32_t *row = hist + static_cast<int64_t>(blockIdx.x) * kBucketsE;
-    for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) row[k] = s_hist[k];
+    uint32_t *row = hist + static_cast<int64_t>(blockIdx.x) * n_buckets;
+    for (int k = threadIdx.x; k < n_buckets; k += blockDim.x) row[k] = s_hist[k];
+}
+
+// The first ordered ray of every bin group, and one past the last group's
+// rays (the start of the bucket of rays outside the bins): bounds[g] =
+// key_base[g * lb], g = 0..n_groups.
+__global__ void group_bounds_kernel(const uint32_t *key_base, int n_groups, int lb, uint32_t *bounds)
+{
+    for (int g = threadIdx.x; g <= n_groups; g += blockDim.x) bounds[g] = key_base[g * lb];
 }
 
 // One ray in the working precision, as the ordering writes it: the walk
@@ -327,13 +342,15 @@ struct __align__(16) RayRec {
 };
 
 template <typename R, typename RT>
-__global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(RaySrc src, int64_t n, const uint8_t *bucket,
-                                                            int64_t rays_per_block, const uint32_t *row_off,
-                                                            const uint32_t *key_base, RayRec<R> *ordered)
+__global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(RaySrc src, int64_t n, const uint16_t *bucket,
+                                                            int n_buckets, int64_t rays_per_block,
+                                                            const uint32_t *row_off, const uint32_t *key_base,
+                                                            RayRec<R> *ordered)
 {
-    __shared__ uint32_t s_base[kBucketsE];
-    const uint32_t *row = row_off + static_cast<int64_t>(blockIdx.x) * kBucketsE;
-    for (int k = threadIdx.x; k < kBucketsE; k += blockDim.x) s_base[k] = key_base[k] + row[k];
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint32_t *s_base = reinterpret_cast<uint32_t *>(lds);
+    const uint32_t *row = row_off + static_cast<int64_t>(blockIdx.x) * n_buckets;
+    for (int k = threadIdx.x; k < n_buckets; k += blockDim.x) s_base[k] = key_base[k] + row[k];
     __syncthreads();
     const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
     const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
@@ -369,33 +386,40 @@ __device__ __forceinline__ int ray_place_key(const MeshP<R> &M, const SortGeom &
     return 8 * tile + (r.ux > R(0) ? 1 : 0) + (r.uy > R(0) ? 2 : 0) + (r.uz > R(0) ? 4 : 0);
 }
 
-// Blocks of kOrderBlock threads, dynamic LDS of 8 * n_tiles counters.
+// Blocks of kOrderBlock threads, dynamic LDS of 8 * n_tiles + 1 counters
+// (rays outside the tally's bins stay last, under key 8 * n_tiles).
 template <typename R, bool RECT>
-__global__ void __launch_bounds__(kOrderBlock) place_hist_kernel(MeshP<R> M, SortGeom g, const RayRec<R> *in,
+__device__ __forceinline__ int place_slot(const MeshP<R> &M, const SortGeom &g, const TallyP &T, const RayRec<R> &r)
+{
+    return energy_bin(T, static_cast<double>(r.e)) < 0 ? 8 * g.n_tiles : ray_place_key<R, RECT>(M, g, r);
+}
+
+template <typename R, bool RECT>
+__global__ void __launch_bounds__(kOrderBlock) place_hist_kernel(MeshP<R> M, SortGeom g, TallyP T, const RayRec<R> *in,
                                                                  int64_t n, int64_t rays_per_block, uint32_t *hist)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     uint32_t *s_hist = reinterpret_cast<uint32_t *>(lds);
-    const int nk = 8 * g.n_tiles;
+    const int nk = 8 * g.n_tiles + 1;
     for (int k = threadIdx.x; k < nk; k += blockDim.x) s_hist[k] = 0u;
     __syncthreads();
     const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
     const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
-    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) atomicAdd(&s_hist[ray_place_key<R, RECT>(M, g, in[r])], 1u);
+    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) atomicAdd(&s_hist[place_slot<R, RECT>(M, g, T, in[r])], 1u);
     __syncthreads();
     uint32_t *row = hist + static_cast<int64_t>(blockIdx.x) * nk;
     for (int k = threadIdx.x; k < nk; k += blockDim.x) row[k] = s_hist[k];
 }
 
 template <typename R, bool RECT>
-__global__ void __launch_bounds__(kOrderBlock) place_scatter_kernel(MeshP<R> M, SortGeom g, const RayRec<R> *in,
+__global__ void __launch_bounds__(kOrderBlock) place_scatter_kernel(MeshP<R> M, SortGeom g, TallyP T, const RayRec<R> *in,
                                                                     int64_t n, int64_t rays_per_block,
                                                                     const uint32_t *row_off, const uint32_t *key_base,
                                                                     RayRec<R> *out)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     uint32_t *s_base = reinterpret_cast<uint32_t *>(lds);
-    const int nk = 8 * g.n_tiles;
+    const int nk = 8 * g.n_tiles + 1;
     const uint32_t *row = row_off + static_cast<int64_t>(blockIdx.x) * nk;
     for (int k = threadIdx.x; k < nk; k += blockDim.x) s_base[k] = key_base[k] + row[k];
     __syncthreads();
@@ -403,7 +427,7 @@ __global__ void __launch_bounds__(kOrderBlock) place_scatter_kernel(MeshP<R> M, 
     const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
     for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) {
         const RayRec<R> rr = in[r];
-        out[atomicAdd(&s_base[ray_place_key<R, RECT>(M, g, rr)], 1u)] = rr;
+        out[atomicAdd(&s_base[place_slot<R, RECT>(M, g, T, rr)], 1u)] = rr;
     }
 }
 
@@ -506,7 +530,9 @@ struct EntryArgs {
     TallyP tally;
     int hash_in_lds;
     SortGeom g;
-    const void *ordered;      // RayRec<R>: the rays by estimated length, longest first
+    const void *ordered;      // RayRec<R>: the rays by bin group, then by estimated length, longest first
+    const uint32_t *bounds;   // per bin group its first ordered ray; bounds[group + 1]: one past its last
+    int group;                // the launch's bin group
     uint32_t *hist;           // blocks * n_keys: records per (block, key) (counting pass)
     const uint32_t *row_off;  // blocks * n_keys: records of earlier blocks per key (entries pass)
     const uint32_t *key_base; // n_keys + 1: first record of each key
@@ -596,9 +622,10 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
     __shared__ uint32_t s_hist[kMaxKeys];
     for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_hist[k] = 0u;
     __syncthreads();
-    const int64_t n = A.rays.n;
+    const int64_t first = A.bounds[A.group];
+    const int64_t n = static_cast<int64_t>(A.bounds[A.group + 1]) - first;  // the group's rays
     const RayDeal deal(n);
-    const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
+    const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered) + first;
     for (int64_t round = 0; deal.more(round); ++round) {
         const int64_t j = deal.ray(round);
         if (j >= n) continue;
@@ -778,7 +805,8 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
     const int bd = blockDim.x;
     const int shift = __ffs(bd) - 1;
     S(*mysig)[2] = sig + threadIdx.x;
-    const int64_t n = A.rays.n;
+    const int64_t first = A.bounds[A.group];
+    const int64_t n = static_cast<int64_t>(A.bounds[A.group + 1]) - first;  // the group's rays
     const RayDeal deal(n);
     S dcur = S(0), dnext = S(0);
     Walker<R, RECT> wk;
@@ -793,7 +821,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
     const R hx = M.h[0], hy = M.h[1], hz = M.h[2];
     const R gx = R(1) / hx, gy = R(1) / hy, gz = R(1) / hz;
     const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
-    const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered);
+    const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered) + first;
     const auto X = [&](int a) {
         return [&M, a](int k) -> R {
             if constexpr (RECT) return M.pl[a][k];
@@ -1496,13 +1524,21 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     const int ntz = g.n_tiles / (g.ntx * g.nty);
     const int64_t per_ray = static_cast<int64_t>(g.ntx) + g.nty + ntz;  // > tiles a ray can cross
     const size_t rec = sizeof(Entry<R, S>);
+    // the ordering's buckets: per group of energy bins lb length slots, then one for the rays outside
+    // the tally's bins (at most 4097 buckets: 16 KiB of LDS)
+    const int n_groups = (t.n_bins + g.n_gbins - 1) / g.n_gbins;
+    const int lb = n_groups <= kMaxKeys / kBucketsE ? kBucketsE : kMaxKeys / n_groups;
+    const int n_buckets = n_groups * lb + 1;
+    const size_t lds_order = sizeof(uint32_t) * static_cast<size_t>(n_buckets);
     int shift = 0;
-    while (((static_cast<int64_t>(m.n[0]) + m.n[1] + m.n[2]) >> shift) >= kBucketsE) ++shift;
-    // the second ordering (by place) when its counters fit in LDS; not on an arena, whose fixed size
-    // the place rows would mostly take (the order changes no result)
-    const int n_place = 8 * g.n_tiles;
+    while (((static_cast<int64_t>(m.n[0]) + m.n[1] + m.n[2]) >> shift) >= lb) ++shift;
+    // the second ordering (by place) when the tally's bins go in one launch and its counters fit in
+    // LDS; not on an arena, whose fixed size the place rows would mostly take (the order changes no
+    // result)
+    const int n_place = 8 * g.n_tiles + 1;
     const size_t lds_place = sizeof(uint32_t) * static_cast<size_t>(n_place);
-    const bool place_ok = arena.base == nullptr && lds_place <= ctx.lds_max && ctx.test_place_order != 0;
+    const bool place_ok = arena.base == nullptr && n_groups == 1 && lds_place <= ctx.lds_max &&
+                          ctx.test_place_order != 0;
     if (place_ok) {
         // blocks may take more than 64 KiB of LDS on this GPU (up to its per-block limit)
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&place_hist_kernel<R, RECT>),
@@ -1513,7 +1549,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         if (e != hipSuccess) return e;
     }
     // hist rows serve the three sorts
-    const int hist_keys = std::max(std::max(g.n_keys, kBucketsE), place_ok ? n_place : 0);
+    const int hist_keys = std::max(std::max(g.n_keys, n_buckets), place_ok ? n_place : 0);
     // LDS is kept for occupancy: the energy-grid hash stays in global memory
     // (it is read once per ray or record and stays in L2).
     const size_t lds1 = sigma_lds(ctx, sizeof(S), kBlock);
@@ -1563,8 +1599,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         // what every sub-launch takes whatever its ray count, then the bytes per ray
         const size_t fixed = 2 * arena_round(sizeof(uint32_t) * rows_max * hist_keys) +
                              2 * arena_round(sizeof(uint32_t) * (hist_keys + 1)) + arena_round(partial_bytes) +
-                             3 * kArenaAlign;
-        const size_t per_ray_bytes = rec * static_cast<size_t>(per_ray) + sizeof(RayRec<R>) + 1;
+                             arena_round(sizeof(uint32_t) * (n_groups + 1)) + 4 * kArenaAlign;
+        const size_t per_ray_bytes = rec * static_cast<size_t>(per_ray) + sizeof(RayRec<R>) + sizeof(uint16_t);
         if (arena.size <= fixed) return hipErrorOutOfMemory;
         group_rays = static_cast<int64_t>((arena.size - fixed) / per_ray_bytes);
     }
@@ -1585,7 +1621,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             place_ok && (ctx.test_place_order == 1 || (jump && slices >= kPlaceMinRounds * (kBlock / 64) * Ge));
         const int64_t cap = nr * per_ray;  // records
         const size_t rows = static_cast<size_t>(G > Ge ? G : Ge);
-        void *b_sorted, *b_hist, *b_row_off, *b_key_tot, *b_key_base, *b_ordered, *b_bucket, *b_partial;
+        void *b_sorted, *b_hist, *b_row_off, *b_key_tot, *b_key_base, *b_ordered, *b_bucket, *b_partial, *b_bounds;
         hipError_t e = hipSuccess;
         if (arena.base == nullptr) {
             e = grow(sc.sorted, sc.sorted_cap, rec * static_cast<size_t>(cap));
@@ -1594,7 +1630,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (hist_keys + 1));
             if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (hist_keys + 1));
             if (e == hipSuccess) e = grow(sc.ordered, sc.ordered_cap, sizeof(RayRec<R>) * static_cast<size_t>(nr));
-            if (e == hipSuccess) e = grow(sc.bucket, sc.bucket_cap, static_cast<size_t>(nr));
+            if (e == hipSuccess) e = grow(sc.bucket, sc.bucket_cap, sizeof(uint16_t) * static_cast<size_t>(nr));
+            if (e == hipSuccess) e = grow(sc.bounds, sc.bounds_cap, sizeof(uint32_t) * (n_groups + 1));
             if (e != hipSuccess) return e;
             b_sorted = sc.sorted;
             b_hist = sc.hist;
@@ -1604,6 +1641,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             b_ordered = sc.ordered;
             b_bucket = sc.bucket;
             b_partial = sc.partial;
+            b_bounds = sc.bounds;
         } else {
             size_t off = 0;
             e = carve(arena, off, b_hist, sizeof(uint32_t) * rows * hist_keys);
@@ -1612,7 +1650,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             if (e == hipSuccess) e = carve(arena, off, b_key_base, sizeof(uint32_t) * (hist_keys + 1));
             if (e == hipSuccess) e = carve(arena, off, b_partial, partial_bytes);
             if (e == hipSuccess) e = carve(arena, off, b_ordered, sizeof(RayRec<R>) * static_cast<size_t>(nr));
-            if (e == hipSuccess) e = carve(arena, off, b_bucket, static_cast<size_t>(nr));
+            if (e == hipSuccess) e = carve(arena, off, b_bucket, sizeof(uint16_t) * static_cast<size_t>(nr));
+            if (e == hipSuccess) e = carve(arena, off, b_bounds, sizeof(uint32_t) * (n_groups + 1));
             if (e == hipSuccess) e = carve(arena, off, b_sorted, rec * static_cast<size_t>(cap));
             if (e != hipSuccess) return e;
         }
@@ -1669,31 +1708,38 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         uint32_t *row_off = static_cast<uint32_t *>(b_row_off);
         uint32_t *key_tot = static_cast<uint32_t *>(b_key_tot);
         uint32_t *key_base = static_cast<uint32_t *>(b_key_base);
-        hipLaunchKernelGGL((order_hist_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, mesh, sub, nr, rays_block, shift,
-                           static_cast<uint8_t *>(b_bucket), hist);
-        hipLaunchKernelGGL(scan_rows_kernel, dim3(kBucketsE / 64), dim3(64 * kScanWaves), 0, s, hist, G, kBucketsE,
-                           row_off, key_tot);
-        hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, key_tot, kBucketsE, key_base);
+        hipLaunchKernelGGL((order_hist_kernel<R, RT>), dim3(G), dim3(kOrderBlock), lds_order, s, mesh, sub, nr,
+                           rays_block, shift, A.tally, g.n_gbins, lb, n_buckets, static_cast<uint16_t *>(b_bucket),
+                           hist);
+        hipLaunchKernelGGL(scan_rows_kernel, dim3((n_buckets + 63) / 64), dim3(64 * kScanWaves), 0, s,
+                           static_cast<const uint32_t *>(hist), G, n_buckets, row_off, key_tot);
+        hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
+                           n_buckets, key_base);
+        hipLaunchKernelGGL(group_bounds_kernel, dim3(1), dim3(64), 0, s, static_cast<const uint32_t *>(key_base),
+                           n_groups, lb, static_cast<uint32_t *>(b_bounds));
         if (by_place) {
             // by length into the record space (free until the entries pass), then by place into b_ordered
             RayRec<R> *by_len = static_cast<RayRec<R> *>(b_sorted);
-            hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, sub, nr,
-                               static_cast<const uint8_t *>(b_bucket), rays_block, row_off, key_base, by_len);
+            hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), lds_order, s, sub, nr,
+                               static_cast<const uint16_t *>(b_bucket), n_buckets, rays_block,
+                               static_cast<const uint32_t *>(row_off), static_cast<const uint32_t *>(key_base), by_len);
             hipLaunchKernelGGL((place_hist_kernel<R, RECT>), dim3(G), dim3(kOrderBlock), lds_place, s, mesh, g,
-                               static_cast<const RayRec<R> *>(by_len), nr, rays_block, hist);
+                               A.tally, static_cast<const RayRec<R> *>(by_len), nr, rays_block, hist);
             hipLaunchKernelGGL(scan_rows_kernel, dim3((n_place + 63) / 64), dim3(64 * kScanWaves), 0, s,
                                static_cast<const uint32_t *>(hist), G, n_place, row_off, key_tot);
             hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
                                n_place, key_base);
             hipLaunchKernelGGL((place_scatter_kernel<R, RECT>), dim3(G), dim3(kOrderBlock), lds_place, s, mesh, g,
-                               static_cast<const RayRec<R> *>(by_len), nr, rays_block,
+                               A.tally, static_cast<const RayRec<R> *>(by_len), nr, rays_block,
                                static_cast<const uint32_t *>(row_off), static_cast<const uint32_t *>(key_base),
                                static_cast<RayRec<R> *>(b_ordered));
         } else {
-            hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), 0, s, sub, nr,
-                               static_cast<const uint8_t *>(b_bucket), rays_block, row_off, key_base,
+            hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), lds_order, s, sub, nr,
+                               static_cast<const uint16_t *>(b_bucket), n_buckets, rays_block,
+                               static_cast<const uint32_t *>(row_off), static_cast<const uint32_t *>(key_base),
                                static_cast<RayRec<R> *>(b_ordered));
         }
+        A.bounds = static_cast<const uint32_t *>(b_bounds);
         // the tally's energy bins in groups of at most g.n_gbins (kMaxKeys keys), each group's rays
         // counted, entered and scored in turn over the same ordered rays
         for (int bin0 = 0; bin0 < t.n_bins; bin0 += g.n_gbins) {
@@ -1702,6 +1748,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             gg.n_gbins = std::min(g.n_gbins, t.n_bins - bin0);
             gg.n_keys = gg.n_tiles * gg.n_gbins;
             A.g = gg;
+            A.group = bin0 / g.n_gbins;
             hipLaunchKernelGGL((count_entries_kernel<R, RECT>), dim3(Ge), dim3(kBlock), 0, s, A);
             hipLaunchKernelGGL(scan_rows_kernel, dim3((gg.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
                                static_cast<const uint32_t *>(hist), Ge, gg.n_keys, row_off, key_tot);
