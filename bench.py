@@ -145,7 +145,7 @@ def pipeline(precision: str, accumulate: int) -> list:
     flush = 2 if precision == "p32_kahan" else (1 if accumulate == 3 else 0)
     return [f"entries_kernel<{R}, {R}, {S}, false, false, ", f"order_hist_kernel<{R}, {R}>",
             f"order_scatter_kernel<{R}, {R}>", f"place_hist_kernel<{R}, false>", f"place_scatter_kernel<{R}, false>",
-            f"count_entries_kernel<{R}, false>", "scan_rows_kernel", "scan_keys_kernel",
+            f"count_entries_kernel<{R}, false>", "scan_rows_kernel", "scan_keys_kernel", "group_bounds_kernel",
             f"tile_kernel<{R}, {S}, {flush}, false, false>", f"tile_reduce_kernel<{flush}>"]
 
 
