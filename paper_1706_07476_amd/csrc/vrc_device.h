@@ -521,6 +521,15 @@ __device__ __forceinline__ S xs_value(const XsP<R> &X, int k, bool interp, R E, 
 // 1/Sigma in the scoring precision S to the lane's LDS column:
 // sig[m * stride] = {Sigma, 1/Sigma (0 for Sigma = 0)}.
 template <typename R, typename S>
+__device__ __forceinline__ void xs_lookup_at(const XsP<R> &X, int k, bool interp, R E, S (*sig)[2], int stride)
+{
+    for (int m = 0; m < X.n_mat; ++m) {
+        const S v = xs_value<R, S>(X, k, interp, E, m);
+        sig[m * stride][0] = v;
+        sig[m * stride][1] = v > S(0) ? S(1) / v : S(0);
+    }
+}
+template <typename R, typename S>
 __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, R E,
                                           S (*sig)[2], int stride)
 {
@@ -534,13 +543,16 @@ __device__ __forceinline__ void xs_lookup(const XsP<R> &X, const int32_t *hash, 
 }
 
 // Sigma_m(E) of every material to the lane's LDS column, sig[m * stride][0]
-// (the reciprocals are not written).
+// (the reciprocals are not written).  Returns the grid interval, bit 31 set
+// when E is outside the table (no interpolation), for xs_lookup_at.
 template <typename R, typename S>
-__device__ __forceinline__ void xs_lookup_sigma(const XsP<R> &X, const int32_t *hash, R E, S (*sig)[2], int stride)
+__device__ __forceinline__ uint32_t xs_lookup_sigma(const XsP<R> &X, const int32_t *hash, R E, S (*sig)[2],
+                                                    int stride)
 {
     bool interp;
     const int k = xs_interval(X, hash, E, interp);
     for (int m = 0; m < X.n_mat; ++m) sig[m * stride][0] = xs_value<R, S>(X, k, interp, E, m);
+    return static_cast<uint32_t>(k) | (interp ? 0u : 0x80000000u);
 }
 
 // ---------------------------------------------------------------------------

@@ -60,16 +60,39 @@ enum Flush {
     kFlushKahan = 2,   // compensated FP32 pair {sum, compensation}
 };
 
-// One tile entry of one ray.  code: kFirst | key << 12 | voxel within tile.
+// One tile entry of one ray.  code: kFirst | key << 12 | voxel within tile;
+// xs: the ray's interval of the energy grid (bit 31: outside the table), so
+// that the tiles pass does not search the grid again (it fills the record's
+// alignment padding; the 48-byte record of FP32 walks and scores has no
+// room for it, and its tiles pass searches).
 template <typename R, typename S>
 struct __align__(16) Entry {
     R ox, oy, oz;
     R ix, iy, iz;  // 1 / direction, as the walk computes it (+-inf on an axis the ray runs parallel to)
     R e, w;
     R t0;              // ray parameter where the first piece in the tile starts
+    uint32_t xs;
     S tau_hi, tau_lo;  // compensated optical depth before the tile
     uint32_t code;
 };
+template <>
+struct __align__(16) Entry<double, double> {
+    double ox, oy, oz, ix, iy, iz, e, w, t0;
+    double tau_hi, tau_lo;
+    uint32_t code;
+    uint32_t xs;
+};
+template <>
+struct __align__(16) Entry<float, float> {
+    float ox, oy, oz, ix, iy, iz, e, w, t0;
+    float tau_hi, tau_lo;
+    uint32_t code;
+};
+template <typename R, typename S>
+constexpr bool entry_has_xs() { return sizeof(R) == 8 || sizeof(S) == 8; }
+static_assert(sizeof(Entry<float, double>) == 64 && sizeof(Entry<float, float>) == 48 &&
+                  sizeof(Entry<double, double>) == 96,
+              "record sizes");
 
 // Keys of one launch: (bin - bin0) * n_tiles + tile for the n_gbins energy
 // bins from bin0 (a tally with more bins than fit kMaxKeys keys is cast in
@@ -697,6 +720,7 @@ template <typename R, typename S>
 struct EntryOut {
     R ox, oy, oz, ix, iy, iz, e, w;
     uint32_t key0;
+    uint32_t xs;  // the ray's energy-grid interval (xs_lookup_sigma)
     SortGeom g;
     uint32_t *s_next;
     Entry<R, S> *sorted;
@@ -724,6 +748,7 @@ struct EntryOut {
             r.tau_hi = hi;
             r.tau_lo = lo;
             r.code = (first ? kFirst : 0u) | (key << kLocalBits) | local_index(ci, cj, ck);
+            if constexpr (entry_has_xs<R, S>()) r.xs = xs;
             sorted[pos] = r;
         }
     }
@@ -848,7 +873,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
         if (bin < 0) continue;
         if (!wk.start(M, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz)) continue;
         if constexpr (DENS) dnext = dens[wk.vox];  // start() reads the first voxel's material itself
-        xs_lookup_sigma(A.xs, hash, rr.e, mysig, bd);  // the optical depth needs Sigma only
+        out.xs = xs_lookup_sigma(A.xs, hash, rr.e, mysig, bd);  // the optical depth needs Sigma only
         out.ox = rr.ox;
         out.oy = rr.oy;
         out.oz = rr.oz;
@@ -1311,7 +1336,13 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
                 if (pm >= 0) {
                     // a tile of one material: its Sigma alone, no material reads
                     bool interp;
-                    const int k = xs_interval(A.xs, hash, r.e, interp);
+                    int k;
+                    if constexpr (entry_has_xs<R, S>()) {
+                        k = static_cast<int>(r.xs & 0x7fffffffu);
+                        interp = (r.xs >> 31) == 0u;
+                    } else {
+                        k = xs_interval(A.xs, hash, r.e, interp);
+                    }
                     const S sv = xs_value<R, S>(A.xs, k, interp, r.e, pm);
                     OneMaterialScorer<S, PutLds> one{sv, sv > S(0) ? S(1) / sv : S(0), S(0), put};
                     one.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, first);
@@ -1320,7 +1351,10 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
                     while (wk.step(A.mesh, one, cm)) {
                     }
                 } else {
-                    xs_lookup(A.xs, hash, r.e, mysig, bd);
+                    if constexpr (entry_has_xs<R, S>())
+                        xs_lookup_at(A.xs, static_cast<int>(r.xs & 0x7fffffffu), (r.xs >> 31) == 0u, r.e, mysig, bd);
+                    else
+                        xs_lookup(A.xs, hash, r.e, mysig, bd);
                     sc.resume(static_cast<S>(r.w), r.tau_hi, r.tau_lo, first);
                     wk.resume_tile(A.mesh, mats, r.ox, r.oy, r.oz, r.ix, r.iy, r.iz, ci, cj, ck, r.t0);
                     while (wk.step(A.mesh, sc, mats)) {
