@@ -94,21 +94,37 @@ static_assert(sizeof(Entry<float, double>) == 64 && sizeof(Entry<float, float>) 
                   sizeof(Entry<double, double>) == 96,
               "record sizes");
 
-// Keys of one launch: (bin - bin0) * n_tiles + tile for the n_gbins energy
-// bins from bin0 (a tally with more bins than fit kMaxKeys keys is cast in
-// groups of bins, one after the other, each over the rays of its bins).
+// Keys: bin * n_tiles + tile.  A tally with more keys than the counting and
+// entries passes hold in LDS (kMaxKeys) has its energy bins in groups of
+// n_gbins: those passes give each group gblocks blocks, which count and
+// enter the group's rays under the group's keys, (bin - the group's first
+// bin) * n_tiles + tile, n_keys of them at most; the tiles pass takes every
+// key (n_keys there, bin0 = 0).
 struct SortGeom {
     int32_t ntx, nty, n_tiles, n_keys;
     int32_t bin0, n_gbins;
+    int32_t gblocks;
 };
 
-// The ray's energy bin within the launch's group of bins, or -1 (outside
-// the tally's bins or in another group).
-__device__ __forceinline__ int group_bin(const TallyP &T, const SortGeom &g, double E)
-{
-    const int bin = energy_bin(T, E) - g.bin0;
-    return bin >= 0 && bin < g.n_gbins ? bin : -1;
-}
+// The bin group a block of the counting or entries pass works for, the
+// block's place among the group's blocks, the group's first bin and its
+// number of bins.
+struct GroupBlock {
+    int group, block, bin0, bins;
+    __device__ __forceinline__ GroupBlock(const SortGeom &g, int n_bins)
+    {
+        group = static_cast<int>(blockIdx.x) / g.gblocks;
+        block = static_cast<int>(blockIdx.x) - group * g.gblocks;
+        bin0 = group * g.n_gbins;
+        bins = g.n_gbins < n_bins - bin0 ? g.n_gbins : n_bins - bin0;
+    }
+    // the ray's bin within the group, or -1 (outside the tally's bins or in another group)
+    __device__ __forceinline__ int local_bin(const TallyP &T, double E) const
+    {
+        const int bin = energy_bin(T, E) - bin0;
+        return bin >= 0 && bin < bins ? bin : -1;
+    }
+};
 
 __device__ __forceinline__ uint32_t local_index(int ci, int cj, int ck)
 {
@@ -555,7 +571,6 @@ struct EntryArgs {
     SortGeom g;
     const void *ordered;      // RayRec<R>: the rays by bin group, then by estimated length, longest first
     const uint32_t *bounds;   // per bin group its first ordered ray; bounds[group + 1]: one past its last
-    int group;                // the launch's bin group
     uint32_t *hist;           // blocks * n_keys: records per (block, key) (counting pass)
     const uint32_t *row_off;  // blocks * n_keys: records of earlier blocks per key (entries pass)
     const uint32_t *key_base; // n_keys + 1: first record of each key
@@ -574,10 +589,11 @@ struct EntryArgs {
 // pass deal the same rays to the same blocks.
 struct RayDeal {
     int64_t per_round, pos, slices;
-    __device__ __forceinline__ RayDeal(int64_t n)
+    // n rays over n_blocks blocks, this one the block-th
+    __device__ __forceinline__ RayDeal(int64_t n, int n_blocks, int block)
     {
-        per_round = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
-        pos = static_cast<int64_t>(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
+        per_round = static_cast<int64_t>(n_blocks) * (blockDim.x >> 6);
+        pos = static_cast<int64_t>(threadIdx.x >> 6) * n_blocks + block;
         slices = (n + 63) >> 6;
     }
     __device__ __forceinline__ bool more(int64_t round) const { return round * per_round < slices; }
@@ -645,15 +661,16 @@ __global__ void __launch_bounds__(256) count_entries_kernel(EntryArgs<R> A)
     __shared__ uint32_t s_hist[kMaxKeys];
     for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_hist[k] = 0u;
     __syncthreads();
-    const int64_t first = A.bounds[A.group];
-    const int64_t n = static_cast<int64_t>(A.bounds[A.group + 1]) - first;  // the group's rays
-    const RayDeal deal(n);
+    const GroupBlock gb(A.g, A.tally.n_bins);
+    const int64_t first = A.bounds[gb.group];
+    const int64_t n = static_cast<int64_t>(A.bounds[gb.group + 1]) - first;  // the group's rays
+    const RayDeal deal(n, A.g.gblocks, gb.block);
     const RayRec<R> *ordered = static_cast<const RayRec<R> *>(A.ordered) + first;
     for (int64_t round = 0; deal.more(round); ++round) {
         const int64_t j = deal.ray(round);
         if (j >= n) continue;
         const RayRec<R> rr = ordered[j];
-        const int bin = group_bin(A.tally, A.g, static_cast<double>(rr.e));
+        const int bin = gb.local_bin(A.tally, static_cast<double>(rr.e));
         if (bin < 0) continue;
         const int key0 = bin * A.g.n_tiles;
         walk_tiles<R, RECT>(A.mesh, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz, [&](int ti, int tj, int tk) {
@@ -816,8 +833,11 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
     // JUMP: the tile table in LDS (read at every tile): a tile's material if it holds one only, else
     // -1 - its place among the tiles of several materials
     __shared__ int16_t s_code[JUMP ? kMaxKeys : 1];
+    const GroupBlock gb(A.g, A.tally.n_bins);
+    const int keys = gb.bins * A.g.n_tiles;                       // the group's keys
+    const uint32_t *base = A.key_base + gb.bin0 * A.g.n_tiles;  // their first records
     const uint32_t *row = A.row_off + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
-    for (int k = threadIdx.x; k < A.g.n_keys; k += blockDim.x) s_next[k] = A.key_base[k] + row[k];
+    for (int k = threadIdx.x; k < keys; k += blockDim.x) s_next[k] = base[k] + row[k];
     if constexpr (JUMP)
         for (int k = threadIdx.x; k < A.g.n_tiles; k += blockDim.x) {
             const int pm = A.mesh.tile_mat[k];
@@ -830,9 +850,9 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
     const int bd = blockDim.x;
     const int shift = __ffs(bd) - 1;
     S(*mysig)[2] = sig + threadIdx.x;
-    const int64_t first = A.bounds[A.group];
-    const int64_t n = static_cast<int64_t>(A.bounds[A.group + 1]) - first;  // the group's rays
-    const RayDeal deal(n);
+    const int64_t first = A.bounds[gb.group];
+    const int64_t n = static_cast<int64_t>(A.bounds[gb.group + 1]) - first;  // the group's rays
+    const RayDeal deal(n, A.g.gblocks, gb.block);
     S dcur = S(0), dnext = S(0);
     Walker<R, RECT> wk;
     const S *dens = factors_of<S>(A.mesh);
@@ -869,7 +889,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
         const int64_t j = deal.ray(round);
         if (j >= n) continue;
         const RayRec<R> rr = ordered[j];
-        const int bin = group_bin(A.tally, A.g, static_cast<double>(rr.e));
+        const int bin = gb.local_bin(A.tally, static_cast<double>(rr.e));
         if (bin < 0) continue;
         if (!wk.start(M, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz)) continue;
         if constexpr (DENS) dnext = dens[wk.vox];  // start() reads the first voxel's material itself
@@ -983,47 +1003,53 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
     // the host reports (records written past a run land in the next one)
     __syncthreads();
     const uint32_t *hrow = A.hist + static_cast<int64_t>(blockIdx.x) * A.g.n_keys;
-    for (int k = threadIdx.x; k < A.g.n_keys; k += bd)
-        if (s_next[k] != A.key_base[k] + row[k] + hrow[k]) *A.check = 1u;
+    for (int k = threadIdx.x; k < keys; k += bd)
+        if (s_next[k] != base[k] + row[k] + hrow[k]) *A.check = 1u;
 }
 
 // Block of 1024 threads, 64 keys: lane = key, each of the 16 wavefronts a
-// slice of the blocks.  row_off[b * n_keys + key] = sum over b' < b of
-// hist[b' * n_keys + key]; key_tot[key] = the column sum.  Every access is a
-// coalesced row piece, with several loads in flight per lane.
+// slice of the blocks.  Rows G * y .. G * (y + 1) - 1 (blockIdx.y = y: a bin
+// group of the counting pass, 0 for the orderings) of n_keys columns:
+// row_off[b * n_keys + key] = sum over rows b' < b of the group of
+// hist[b' * n_keys + key]; key_tot[y * n_keys + key] = the column sum (the
+// keys of a group follow those of the groups before it), for y * n_keys +
+// key < total.  Every access is a coalesced row piece, with several loads in
+// flight per lane.
 constexpr int kScanWaves = 16;
 __global__ void __launch_bounds__(1024) scan_rows_kernel(const uint32_t *hist, int G, int n_keys, uint32_t *row_off,
-                                                         uint32_t *key_tot)
+                                                         uint32_t *key_tot, int total)
 {
     __shared__ uint32_t part[kScanWaves][64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int key = blockIdx.x * 64 + lane;
-    const bool on = key < n_keys;
+    const int kout = static_cast<int>(blockIdx.y) * n_keys + key;
+    const bool on = key < n_keys && kout < total;
+    const int64_t row0 = static_cast<int64_t>(blockIdx.y) * G;
     const int per = (G + kScanWaves - 1) / kScanWaves;
     const int b0 = wv * per;
     const int b1 = b0 + per < G ? b0 + per : G;
     uint32_t sum = 0;
     if (on) {
 #pragma unroll 8
-        for (int b = b0; b < b1; ++b) sum += hist[static_cast<int64_t>(b) * n_keys + key];
+        for (int b = b0; b < b1; ++b) sum += hist[(row0 + b) * n_keys + key];
     }
     part[wv][lane] = sum;
     __syncthreads();
-    uint32_t off = 0, total = 0;
+    uint32_t off = 0, tot = 0;
     for (int q = 0; q < kScanWaves; ++q) {
         if (q < wv) off += part[q][lane];
-        total += part[q][lane];
+        tot += part[q][lane];
     }
     if (!on) return;
 #pragma unroll 8
     for (int b = b0; b < b1; ++b) {
-        const int64_t i = static_cast<int64_t>(b) * n_keys + key;
+        const int64_t i = (row0 + b) * n_keys + key;
         const uint32_t h = hist[i];
         row_off[i] = off;
         off += h;
     }
-    if (wv == 0) key_tot[key] = total;
+    if (wv == 0) key_tot[kout] = tot;
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim.x <= 1024).
@@ -1452,10 +1478,11 @@ SortGeom geometry(const TallyHost &t, const MeshHost &m)
     const int ntz = (m.n[2] + kTileEdge - 1) / kTileEdge;
     const int64_t tiles = static_cast<int64_t>(g.ntx) * g.nty * ntz;
     g.n_tiles = tiles <= kMaxKeys ? static_cast<int32_t>(tiles) : 0;
-    // as many bins per launch as fit kMaxKeys keys (the first group; run_sorted_kind moves bin0)
+    // as many bins per group as fit kMaxKeys keys (run_sorted_kind sets the blocks per group)
     g.n_gbins = g.n_tiles > 0 ? std::min(t.n_bins, kMaxKeys / g.n_tiles) : 0;
     g.n_keys = g.n_tiles * g.n_gbins;
     g.bin0 = 0;
+    g.gblocks = 1;
     return g;
 }
 
@@ -1582,8 +1609,11 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_place));
         if (e != hipSuccess) return e;
     }
-    // hist rows serve the three sorts
+    // hist rows serve the three sorts (a bin group's keys per row of the counting pass); the key
+    // totals and bases take every key of the tiles pass
+    const int total_keys = g.n_tiles * t.n_bins;
     const int hist_keys = std::max(std::max(g.n_keys, n_buckets), place_ok ? n_place : 0);
+    const int base_keys = std::max(std::max(total_keys, n_buckets), place_ok ? n_place : 0);
     // LDS is kept for occupancy: the energy-grid hash stays in global memory
     // (it is read once per ray or record and stays in L2).
     const size_t lds1 = sigma_lds(ctx, sizeof(S), kBlock);
@@ -1632,7 +1662,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     } else {
         // what every sub-launch takes whatever its ray count, then the bytes per ray
         const size_t fixed = 2 * arena_round(sizeof(uint32_t) * rows_max * hist_keys) +
-                             2 * arena_round(sizeof(uint32_t) * (hist_keys + 1)) + arena_round(partial_bytes) +
+                             2 * arena_round(sizeof(uint32_t) * (base_keys + 1)) + arena_round(partial_bytes) +
                              arena_round(sizeof(uint32_t) * (n_groups + 1)) + 4 * kArenaAlign;
         const size_t per_ray_bytes = rec * static_cast<size_t>(per_ray) + sizeof(RayRec<R>) + sizeof(uint16_t);
         if (arena.size <= fixed) return hipErrorOutOfMemory;
@@ -1646,7 +1676,10 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         const int64_t nr = n_rays - r0 < group_rays ? n_rays - r0 : group_rays;
         const int64_t rays_block = (nr + G - 1) / G;  // ordering kernels
         const int64_t slices = (nr + 63) / 64;
-        const int Ge = static_cast<int>(G_res < (slices + 3) / 4 ? G_res : (slices + 3) / 4);
+        const int Ge0 = static_cast<int>(G_res < (slices + 3) / 4 ? G_res : (slices + 3) / 4);
+        // the counting and entries passes: Ge0 blocks shared out among the bin groups
+        const int gblocks = std::max(1, Ge0 / n_groups);
+        const int Ge = gblocks * n_groups;
         // the ordering by place pays for the jumping entries pass (its lanes then meet tiles of several
         // materials together) where each wavefront takes many runs of rays (with few, the runs' unequal
         // lengths leave some wavefronts working long after the others); the walking form walks every
@@ -1661,8 +1694,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             e = grow(sc.sorted, sc.sorted_cap, rec * static_cast<size_t>(cap));
             if (e == hipSuccess) e = grow(sc.hist, sc.hist_cap, sizeof(uint32_t) * rows * hist_keys);
             if (e == hipSuccess) e = grow(sc.row_off, sc.row_off_cap, sizeof(uint32_t) * rows * hist_keys);
-            if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (hist_keys + 1));
-            if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (hist_keys + 1));
+            if (e == hipSuccess) e = grow(sc.key_tot, sc.key_tot_cap, sizeof(uint32_t) * (base_keys + 1));
+            if (e == hipSuccess) e = grow(sc.key_base, sc.key_base_cap, sizeof(uint32_t) * (base_keys + 1));
             if (e == hipSuccess) e = grow(sc.ordered, sc.ordered_cap, sizeof(RayRec<R>) * static_cast<size_t>(nr));
             if (e == hipSuccess) e = grow(sc.bucket, sc.bucket_cap, sizeof(uint16_t) * static_cast<size_t>(nr));
             if (e == hipSuccess) e = grow(sc.bounds, sc.bounds_cap, sizeof(uint32_t) * (n_groups + 1));
@@ -1680,8 +1713,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             size_t off = 0;
             e = carve(arena, off, b_hist, sizeof(uint32_t) * rows * hist_keys);
             if (e == hipSuccess) e = carve(arena, off, b_row_off, sizeof(uint32_t) * rows * hist_keys);
-            if (e == hipSuccess) e = carve(arena, off, b_key_tot, sizeof(uint32_t) * (hist_keys + 1));
-            if (e == hipSuccess) e = carve(arena, off, b_key_base, sizeof(uint32_t) * (hist_keys + 1));
+            if (e == hipSuccess) e = carve(arena, off, b_key_tot, sizeof(uint32_t) * (base_keys + 1));
+            if (e == hipSuccess) e = carve(arena, off, b_key_base, sizeof(uint32_t) * (base_keys + 1));
             if (e == hipSuccess) e = carve(arena, off, b_partial, partial_bytes);
             if (e == hipSuccess) e = carve(arena, off, b_ordered, sizeof(RayRec<R>) * static_cast<size_t>(nr));
             if (e == hipSuccess) e = carve(arena, off, b_bucket, sizeof(uint16_t) * static_cast<size_t>(nr));
@@ -1746,7 +1779,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
                            rays_block, shift, A.tally, g.n_gbins, lb, n_buckets, static_cast<uint16_t *>(b_bucket),
                            hist);
         hipLaunchKernelGGL(scan_rows_kernel, dim3((n_buckets + 63) / 64), dim3(64 * kScanWaves), 0, s,
-                           static_cast<const uint32_t *>(hist), G, n_buckets, row_off, key_tot);
+                           static_cast<const uint32_t *>(hist), G, n_buckets, row_off, key_tot, n_buckets);
         hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
                            n_buckets, key_base);
         hipLaunchKernelGGL(group_bounds_kernel, dim3(1), dim3(64), 0, s, static_cast<const uint32_t *>(key_base),
@@ -1760,7 +1793,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             hipLaunchKernelGGL((place_hist_kernel<R, RECT>), dim3(G), dim3(kOrderBlock), lds_place, s, mesh, g,
                                A.tally, static_cast<const RayRec<R> *>(by_len), nr, rays_block, hist);
             hipLaunchKernelGGL(scan_rows_kernel, dim3((n_place + 63) / 64), dim3(64 * kScanWaves), 0, s,
-                               static_cast<const uint32_t *>(hist), G, n_place, row_off, key_tot);
+                               static_cast<const uint32_t *>(hist), G, n_place, row_off, key_tot, n_place);
             hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
                                n_place, key_base);
             hipLaunchKernelGGL((place_scatter_kernel<R, RECT>), dim3(G), dim3(kOrderBlock), lds_place, s, mesh, g,
@@ -1774,44 +1807,43 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
                                static_cast<RayRec<R> *>(b_ordered));
         }
         A.bounds = static_cast<const uint32_t *>(b_bounds);
-        // the tally's energy bins in groups of at most g.n_gbins (kMaxKeys keys), each group's rays
-        // counted, entered and scored in turn over the same ordered rays
-        for (int bin0 = 0; bin0 < t.n_bins; bin0 += g.n_gbins) {
-            SortGeom gg = g;
-            gg.bin0 = bin0;
-            gg.n_gbins = std::min(g.n_gbins, t.n_bins - bin0);
-            gg.n_keys = gg.n_tiles * gg.n_gbins;
-            A.g = gg;
-            A.group = bin0 / g.n_gbins;
-            hipLaunchKernelGGL((count_entries_kernel<R, RECT>), dim3(Ge), dim3(kBlock), 0, s, A);
-            hipLaunchKernelGGL(scan_rows_kernel, dim3((gg.n_keys + 63) / 64), dim3(64 * kScanWaves), 0, s,
-                               static_cast<const uint32_t *>(hist), Ge, gg.n_keys, row_off, key_tot);
-            hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
-                               gg.n_keys, key_base);
-            hipLaunchKernelGGL(entries, dim3(Ge), dim3(kBlock), lds1, s, A);
-            TileArgs<R> T;
-            T.mesh = mesh;
-            T.xs = A.xs;
-            T.hash_in_lds = 0;
-            T.g = gg;
-            T.sorted = b_sorted;
-            T.key_base = static_cast<const uint32_t *>(b_key_base);
-            T.nvox = t.nvox;
-            T.tally = t.d_data;
-            T.partial = static_cast<double *>(b_partial);
-            T.n_blocks = n_tb;
-            if constexpr (sizeof(S) == 4) {
-                if (flush == kFlushKahan) {
-                    e = launch_tiles<R, S, kFlushKahan, RECT, DENS>(T, tb, lds2, s);
-                    goto launched;
-                }
+        // every bin group at once: the counting and entries passes give each group gblocks blocks
+        // (the group's keys in their LDS tables), the tiles pass takes every key
+        SortGeom gc = g;
+        gc.gblocks = gblocks;
+        A.g = gc;
+        hipLaunchKernelGGL((count_entries_kernel<R, RECT>), dim3(Ge), dim3(kBlock), 0, s, A);
+        hipLaunchKernelGGL(scan_rows_kernel, dim3((g.n_keys + 63) / 64, n_groups), dim3(64 * kScanWaves), 0, s,
+                           static_cast<const uint32_t *>(hist), gblocks, g.n_keys, row_off, key_tot, total_keys);
+        hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
+                           total_keys, key_base);
+        hipLaunchKernelGGL(entries, dim3(Ge), dim3(kBlock), lds1, s, A);
+        SortGeom gt = g;
+        gt.n_keys = total_keys;
+        gt.bin0 = 0;
+        gt.n_gbins = t.n_bins;
+        TileArgs<R> T;
+        T.mesh = mesh;
+        T.xs = A.xs;
+        T.hash_in_lds = 0;
+        T.g = gt;
+        T.sorted = b_sorted;
+        T.key_base = static_cast<const uint32_t *>(b_key_base);
+        T.nvox = t.nvox;
+        T.tally = t.d_data;
+        T.partial = static_cast<double *>(b_partial);
+        T.n_blocks = n_tb;
+        if constexpr (sizeof(S) == 4) {
+            if (flush == kFlushKahan) {
+                e = launch_tiles<R, S, kFlushKahan, RECT, DENS>(T, tb, lds2, s);
+                goto launched;
             }
-            e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic, RECT, DENS>(T, tb, lds2, s)
-                                      : launch_tiles<R, S, kFlushPlain, RECT, DENS>(T, tb, lds2, s);
-        launched:
-            if (e == hipSuccess) e = hipGetLastError();
-            if (e != hipSuccess) return e;
         }
+        e = flush == kFlushAtomic ? launch_tiles<R, S, kFlushAtomic, RECT, DENS>(T, tb, lds2, s)
+                                  : launch_tiles<R, S, kFlushPlain, RECT, DENS>(T, tb, lds2, s);
+    launched:
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
     if (arena.base != nullptr) return hipSuccess;  // the context's buffers were not used
     hipError_t e = hipEventRecord(sc.done, s);
@@ -1909,7 +1941,7 @@ hipError_t run_next_event_ordered(vrc_ctx &ctx, const MeshHost &m, int64_t n, co
                        static_cast<R>(det[0]), static_cast<R>(det[1]), static_cast<R>(det[2]),
                        static_cast<uint8_t *>(sc.bucket), hist);
     hipLaunchKernelGGL(scan_rows_kernel, dim3(kBucketsE / 64), dim3(64 * kScanWaves), 0, s, hist, G, kBucketsE,
-                       row_off, key_tot);
+                       row_off, key_tot, kBucketsE);
     hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, key_tot, kBucketsE, key_base);
     hipLaunchKernelGGL((order_scatter_events_kernel<RT>), dim3(G), dim3(kOrderBlock), 0, s, ev, n,
                        static_cast<const uint8_t *>(sc.bucket), per_block, row_off, key_base,
