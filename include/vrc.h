@@ -109,9 +109,9 @@ typedef struct {
  * tally, 3 flushes like 2, with a compensated atomic update).  The
  * tile-split modes apply when the mesh has at most 4096 tiles and the
  * cross-section columns fit in LDS; otherwise the atomic path runs.  A tally
- * with more than 4096 (tile, energy bin) pairs is cast in groups of bins
- * (as many as fit 4096 pairs), one after the other over the same ordered
- * rays.  They use scratch device memory grown on demand (about n_rays *
+ * with more than 4096 (tile, energy bin) pairs has its bins in groups (as
+ * many as fit 4096 pairs): the passes that hold the pairs in LDS give each
+ * group its own blocks, every pass still one launch.  They use scratch device memory grown on demand (about n_rays *
  * (tiles along x + y + z) * 48..96 bytes, at most about 2 GB per sub-launch),
  * so the first cast of a larger batch allocates and is not capturable in a
  * graph; tile-split casts of one context are serialised with each other.
