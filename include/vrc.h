@@ -314,8 +314,9 @@ typedef struct {
  * meshes or meshes with density factors are cast with split = 1 only (the
  * persistent kernel walks plain uniform meshes): otherwise VRC_ERR_INVALID,
  * and the autotuner tries only the split setting for them.  With split,
- * a call waits on the host for the previous tile-split work of the context
- * before it rewrites its batch table.                                      */
+ * the batch tables go through a ring of four: a call waits on the host for
+ * the tile-split work of the call four before it (the last to use the same
+ * table) before it rewrites that table.                                    */
 typedef struct {
     int32_t block;
     int32_t blocks_per_cu;

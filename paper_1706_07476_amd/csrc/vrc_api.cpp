@@ -439,8 +439,11 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         free_dev(sc.key_tot);
         free_dev(sc.key_base);
         free_dev(sc.ordered);
-        free_dev(sc.d_refs);
-        if (sc.h_refs) (void)hipHostFree(sc.h_refs);
+        for (int q = 0; q < SortScratch::kRefSlots; ++q) {
+            free_dev(sc.d_refs[q]);
+            if (sc.h_refs[q]) (void)hipHostFree(sc.h_refs[q]);
+            if (sc.refs_done[q]) (void)hipEventDestroy(sc.refs_done[q]);
+        }
         free_dev(sc.bucket);
         free_dev(sc.partial);
         free_dev(sc.bounds);
@@ -1089,24 +1092,27 @@ vrc_status vrc::run_split_batches(vrc_ctx *ctx, const std::vector<int> &ids,
     size_t n_refs = 0;
     for (int id : ids) n_refs += groups.at(id).size();
     const size_t bytes = sizeof(BatchRef) * n_refs;
-    // the previous call's table may still be in use: wait for it before rewriting
-    if (sc.busy) VRC_HIP(ctx, hipEventSynchronize(sc.done));
-    if (sc.refs_cap < bytes) {
+    // the next table of the ring; the call that used it last may still read it: wait for that call
+    const int q = sc.refs_next;
+    sc.refs_next = (q + 1) % SortScratch::kRefSlots;
+    if (sc.refs_used[q]) VRC_HIP(ctx, hipEventSynchronize(sc.refs_done[q]));
+    if (!sc.refs_done[q]) VRC_HIP(ctx, hipEventCreateWithFlags(&sc.refs_done[q], hipEventDisableTiming));
+    if (sc.refs_cap[q] < bytes) {
         VRC_HIP(ctx, hipDeviceSynchronize());
-        if (sc.h_refs) (void)hipHostFree(sc.h_refs);
-        if (sc.d_refs) (void)hipFree(sc.d_refs);
-        sc.h_refs = sc.d_refs = nullptr;
-        sc.refs_cap = 0;
-        if (hipHostMalloc(&sc.h_refs, bytes, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc(&sc.d_refs, bytes) != hipSuccess) {
-            if (sc.h_refs) (void)hipHostFree(sc.h_refs);
-            if (sc.d_refs) (void)hipFree(sc.d_refs);
-            sc.h_refs = sc.d_refs = nullptr;
+        if (sc.h_refs[q]) (void)hipHostFree(sc.h_refs[q]);
+        if (sc.d_refs[q]) (void)hipFree(sc.d_refs[q]);
+        sc.h_refs[q] = sc.d_refs[q] = nullptr;
+        sc.refs_cap[q] = 0;
+        if (hipHostMalloc(&sc.h_refs[q], bytes, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&sc.d_refs[q], bytes) != hipSuccess) {
+            if (sc.h_refs[q]) (void)hipHostFree(sc.h_refs[q]);
+            if (sc.d_refs[q]) (void)hipFree(sc.d_refs[q]);
+            sc.h_refs[q] = sc.d_refs[q] = nullptr;
             return set_error(VRC_ERR_NOMEM, "batch table of the tile-split batched cast");
         }
-        sc.refs_cap = bytes;
+        sc.refs_cap[q] = bytes;
     }
-    BatchRef *h = static_cast<BatchRef *>(sc.h_refs);
+    BatchRef *h = static_cast<BatchRef *>(sc.h_refs[q]);
     std::vector<std::pair<size_t, int64_t>> spans;  // (first ref, rays) per tally
     size_t k = 0;
     for (int id : ids) {
@@ -1115,7 +1121,7 @@ vrc_status vrc::run_split_batches(vrc_ctx *ctx, const std::vector<int> &ids,
         for (int i : groups.at(id)) {
             const vrc_batch &b = batches[i];
             const void *src[8] = {b.ox, b.oy, b.oz, b.ux, b.uy, b.uz, b.e, b.w};
-            for (int q = 0; q < 8; ++q) h[k].ray[q] = src[q];
+            for (int r = 0; r < 8; ++r) h[k].ray[r] = src[r];
             h[k].begin = begin;
             begin += b.n;
             ++k;
@@ -1123,8 +1129,8 @@ vrc_status vrc::run_split_batches(vrc_ctx *ctx, const std::vector<int> &ids,
         spans.emplace_back(first, begin);
     }
     if (sc.busy && sc.stream != s) VRC_HIP(ctx, hipStreamWaitEvent(s, sc.done, 0));
-    VRC_HIP(ctx, hipMemcpyAsync(sc.d_refs, sc.h_refs, bytes, hipMemcpyHostToDevice, s));
-    const BatchRef *d = static_cast<const BatchRef *>(sc.d_refs);
+    VRC_HIP(ctx, hipMemcpyAsync(sc.d_refs[q], sc.h_refs[q], bytes, hipMemcpyHostToDevice, s));
+    const BatchRef *d = static_cast<const BatchRef *>(sc.d_refs[q]);
     for (size_t g = 0; g < ids.size(); ++g) {
         TallyHost *t = get_tally(ctx, ids[g]);
         const size_t nr = groups.at(ids[g]).size();
@@ -1133,6 +1139,8 @@ vrc_status vrc::run_split_batches(vrc_ctx *ctx, const std::vector<int> &ids,
         if (e == hipErrorOutOfMemory) return set_error(VRC_ERR_NOMEM, "scratch of the sorted accumulation");
         if (e != hipSuccess) return device_error(ctx, e, "tile-split batched cast");
     }
+    VRC_HIP(ctx, hipEventRecord(sc.refs_done[q], s));
+    sc.refs_used[q] = true;
     return VRC_OK;
 }
 

@@ -127,9 +127,14 @@ struct SortScratch {
     hipEvent_t done = nullptr;   // after the last kernel that used the scratch
     hipStream_t stream = nullptr;
     bool busy = false;
-    // batch tables of tile-split batched casts: pinned host copy, device copy
-    void *h_refs = nullptr, *d_refs = nullptr;
-    size_t refs_cap = 0;  // bytes of each
+    // batch tables of tile-split batched casts, a ring of kRefSlots (pinned host copy, device copy, the
+    // event after the call that used it): a call waits only for the call kRefSlots calls before it
+    static constexpr int kRefSlots = 4;
+    void *h_refs[kRefSlots] = {}, *d_refs[kRefSlots] = {};
+    size_t refs_cap[kRefSlots] = {};  // bytes of each
+    hipEvent_t refs_done[kRefSlots] = {};
+    bool refs_used[kRefSlots] = {};
+    int refs_next = 0;
 };
 
 // One ray batch of a batched call, as the persistent kernel reads it.
