@@ -287,6 +287,54 @@ def test_bins_in_groups_beyond_key_limit(ctx, shape, n_bins):
     assert o <= TOL_ORDER
 
 
+@pytest.mark.parametrize("kind", ["rect", "density", "fp32-scores"])
+def test_bins_in_groups_mesh_kinds(ctx, kind):
+    """Bins in groups (128^3-voxel meshes with 9 bins: groups of 8 + 1) on a rectilinear mesh (the
+    walks read plane tables), with density factors (the walking entries pass), and with FP32 scores
+    (records without the energy-grid interval; compensated FP32 tally): the atomic path's tally to
+    the order of the additions, and the oracle's (FP64: to the FP64 bound; FP32: on the FP32-rounded
+    inputs, the voxels its 5 % gate holds, to the FP32 bound)."""
+    rng = np.random.default_rng(521)
+    n = 128
+    mat = rng.integers(0, 3, n ** 3).astype(np.uint8)
+    if kind == "rect":
+        mesh = W.rect_mesh(522, (n, n, n), lo=(-2.0, 0.5, 1.0), h_min=0.3, h_max=0.7)
+    elif kind == "density":
+        mesh = W.Mesh(np.array([-1.0, 0.5, 2.0]), np.full(3, 0.5), np.full(3, n, np.int32), mat,
+                      W.density_field(523, n ** 3, 0.5, 2.0))
+    else:
+        mesh = W.Mesh(np.array([-1.0, 0.5, 2.0]), np.full(3, 0.5), np.full(3, n, np.int32), mat)
+    wl = W.config2_multimaterial(n_rays=0)
+    prec = "p32_kahan" if kind == "fp32-scores" else "p64"
+    n_rays = 1_600_000 if kind == "fp32-scores" else 160_000
+    rays = W.rays_in_box(524, mesh, n_rays)
+    edges = W.log_bin_edges(9, 1e-9, 1.0)
+    say(f"case: sorted {prec} with bins in groups, {kind}, 128^3 x 9 bins, {n_rays} rays")
+    ctx.set_mesh(0, mesh)
+    ctx.set_xs(wl.xs)
+    got, atom = cast_both(ctx, 0, prec, dev_arrays(rays, "f64" if prec == "p64" else "f32"), edges)
+    o = order_rel(got, atom)
+    if prec == "p64":
+        res = oracle.cast(mesh, wl.xs, rays, edges=edges, n_threads=oracle_threads())
+        g, _, nv = rel_report(got.reshape(9, -1), res, gate="all")
+        say(f"  sorted vs oracle {g:.3e} over {nv}; sorted vs atomic {o:.3e}")
+        assert nv > 0.2 * mesh.n_voxels
+        assert g <= TOL_P64
+        assert o <= TOL_ORDER
+    else:
+        # per-voxel sums are too thinly sampled here for the 5 % gate: each bin's total against the
+        # oracle's on the FP32-rounded inputs, and every voxel against the atomic path
+        m, x, r = f32_view(mesh, wl.xs, rays)
+        res = oracle.cast(m, x, r, edges=edges, n_threads=oracle_threads())
+        tot_g = got.reshape(9, -1).sum(axis=1)
+        tot_o = np.asarray(res.tally).reshape(9, -1).sum(axis=1)
+        rel = np.abs(tot_g - tot_o) / tot_o
+        say(f"  per-bin totals vs oracle max {rel.max():.3e}; sorted vs atomic {o:.3e}")
+        assert np.all(tot_o > 0)
+        assert rel.max() <= TOL_P32
+        assert o <= TOL_P32
+
+
 @pytest.mark.parametrize("n_rays", [0, 1, 65, 1023, 70_001])
 def test_sorted_ragged_batches(ctx, n_rays):
     mesh = ragged_mesh(seed=513)
