@@ -565,8 +565,8 @@ vrc_status vrc_count_segments(vrc_ctx *ctx, int mesh_id, vrc_precision precision
 #define VRC_TEST_ENTRIES_JUMP 3
 /* VRC_TEST_PLACE_ORDER chooses the order in which the tile-split
  * accumulation walks its rays: 1 orders them by length, then by where they
- * start and which way they go (the tile of the origin and the direction's
- * signs), 0 by length only, -1 restores the default (the second ordering
+ * start and which way they go (the block of tiles holding the origin and
+ * the direction's signs), 0 by length only, -1 restores the default (the second ordering
  * when the entries pass jumps over tiles of one material and every one of
  * its wavefronts takes at least 24 runs of 64 rays).  The order changes no
  * result beyond the order of the additions.                               */

@@ -401,14 +401,22 @@ __global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(RaySrc src, 
 }
 
 // Second ordering, by where a ray starts and which way it goes: key = 8 x
-// the tile of its origin's voxel (clamped into the mesh) + the signs of its
-// direction.  Rays of one key cross about the same tiles, so the lanes of a
+// the cell of its origin's voxel (clamped into the mesh) + the signs of its
+// direction, a cell being 2^shift x 2^shift x 2^shift tiles (shift chosen so
+// that a key holds a few hundred rays: a wavefront's rays then come from one
+// key).  Rays of one key cross about the same tiles, so the lanes of a
 // wavefront of the entries pass reach tiles of several materials together
 // instead of one at a time.  It runs after the ordering by length over the
 // length-ordered rays; each block takes a run of them, so within a key the
 // rays stay in runs of about the same length.  An order, never a result.
+struct PlaceGeom {
+    int shift;    // log2 of the cell edge in tiles
+    int cx, cy;   // cells per row and per layer
+    int n_keys;   // 8 per cell, and one for the rays outside the tally's bins (last)
+};
+
 template <typename R, bool RECT>
-__device__ __forceinline__ int ray_place_key(const MeshP<R> &M, const SortGeom &g, const RayRec<R> &r)
+__device__ __forceinline__ int ray_place_key(const MeshP<R> &M, const PlaceGeom &p, const RayRec<R> &r)
 {
     int v[3];
     const R o[3] = {r.ox, r.oy, r.oz};
@@ -421,52 +429,66 @@ __device__ __forceinline__ int ray_place_key(const MeshP<R> &M, const SortGeom &
             v[a] = axis_index(o[a], M.lo[a], R(1) / M.h[a], M.n[a]);
         }
     }
-    const int tile = (v[0] >> kTileBits) + g.ntx * ((v[1] >> kTileBits) + g.nty * (v[2] >> kTileBits));
-    return 8 * tile + (r.ux > R(0) ? 1 : 0) + (r.uy > R(0) ? 2 : 0) + (r.uz > R(0) ? 4 : 0);
+    const int sh = kTileBits + p.shift;
+    const int cell = (v[0] >> sh) + p.cx * ((v[1] >> sh) + p.cy * (v[2] >> sh));
+    return 8 * cell + (r.ux > R(0) ? 1 : 0) + (r.uy > R(0) ? 2 : 0) + (r.uz > R(0) ? 4 : 0);
 }
 
-// Blocks of kOrderBlock threads, dynamic LDS of 8 * n_tiles + 1 counters
-// (rays outside the tally's bins stay last, under key 8 * n_tiles).
+// Blocks of kOrderBlock threads, dynamic LDS of p.n_keys counters (rays
+// outside the tally's bins stay last, under key p.n_keys - 1).  Each
+// energy-bin group's rays (bounds) are ordered within the group: blockIdx.y
+// is the group, its gridDim.x blocks share the group's range, and the keys
+// of group y follow those of the groups before it (row y * gridDim.x + x of
+// the block counts, key y * p.n_keys + key of the key bases).
 template <typename R, bool RECT>
-__device__ __forceinline__ int place_slot(const MeshP<R> &M, const SortGeom &g, const TallyP &T, const RayRec<R> &r)
+__device__ __forceinline__ int place_slot(const MeshP<R> &M, const PlaceGeom &p, const TallyP &T, const RayRec<R> &r)
 {
-    return energy_bin(T, static_cast<double>(r.e)) < 0 ? 8 * g.n_tiles : ray_place_key<R, RECT>(M, g, r);
+    return energy_bin(T, static_cast<double>(r.e)) < 0 ? p.n_keys - 1 : ray_place_key<R, RECT>(M, p, r);
+}
+
+// The block's run of its group's rays, [first, last).
+__device__ __forceinline__ void place_run(const uint32_t *bounds, int64_t &first, int64_t &last)
+{
+    const int64_t g0 = bounds[blockIdx.y], g1 = bounds[blockIdx.y + 1];
+    const int64_t per = (g1 - g0 + gridDim.x - 1) / gridDim.x;
+    first = g0 + static_cast<int64_t>(blockIdx.x) * per;
+    last = first + per < g1 ? first + per : g1;
 }
 
 template <typename R, bool RECT>
-__global__ void __launch_bounds__(kOrderBlock) place_hist_kernel(MeshP<R> M, SortGeom g, TallyP T, const RayRec<R> *in,
-                                                                 int64_t n, int64_t rays_per_block, uint32_t *hist)
+__global__ void __launch_bounds__(kOrderBlock) place_hist_kernel(MeshP<R> M, PlaceGeom p, TallyP T, const RayRec<R> *in,
+                                                                 const uint32_t *bounds, uint32_t *hist)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     uint32_t *s_hist = reinterpret_cast<uint32_t *>(lds);
-    const int nk = 8 * g.n_tiles + 1;
+    const int nk = p.n_keys;
     for (int k = threadIdx.x; k < nk; k += blockDim.x) s_hist[k] = 0u;
     __syncthreads();
-    const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
-    const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
-    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) atomicAdd(&s_hist[place_slot<R, RECT>(M, g, T, in[r])], 1u);
+    int64_t first, last;
+    place_run(bounds, first, last);
+    for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) atomicAdd(&s_hist[place_slot<R, RECT>(M, p, T, in[r])], 1u);
     __syncthreads();
-    uint32_t *row = hist + static_cast<int64_t>(blockIdx.x) * nk;
+    uint32_t *row = hist + (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * nk;
     for (int k = threadIdx.x; k < nk; k += blockDim.x) row[k] = s_hist[k];
 }
 
 template <typename R, bool RECT>
-__global__ void __launch_bounds__(kOrderBlock) place_scatter_kernel(MeshP<R> M, SortGeom g, TallyP T, const RayRec<R> *in,
-                                                                    int64_t n, int64_t rays_per_block,
-                                                                    const uint32_t *row_off, const uint32_t *key_base,
-                                                                    RayRec<R> *out)
+__global__ void __launch_bounds__(kOrderBlock) place_scatter_kernel(MeshP<R> M, PlaceGeom p, TallyP T, const RayRec<R> *in,
+                                                                    const uint32_t *bounds, const uint32_t *row_off,
+                                                                    const uint32_t *key_base, RayRec<R> *out)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     uint32_t *s_base = reinterpret_cast<uint32_t *>(lds);
-    const int nk = 8 * g.n_tiles + 1;
-    const uint32_t *row = row_off + static_cast<int64_t>(blockIdx.x) * nk;
-    for (int k = threadIdx.x; k < nk; k += blockDim.x) s_base[k] = key_base[k] + row[k];
+    const int nk = p.n_keys;
+    const uint32_t *row = row_off + (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * nk;
+    const uint32_t *base = key_base + static_cast<int64_t>(blockIdx.y) * nk;
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) s_base[k] = base[k] + row[k];
     __syncthreads();
-    const int64_t first = static_cast<int64_t>(blockIdx.x) * rays_per_block;
-    const int64_t last = first + rays_per_block < n ? first + rays_per_block : n;
+    int64_t first, last;
+    place_run(bounds, first, last);
     for (int64_t r = first + threadIdx.x; r < last; r += blockDim.x) {
         const RayRec<R> rr = in[r];
-        out[atomicAdd(&s_base[place_slot<R, RECT>(M, g, T, rr)], 1u)] = rr;
+        out[atomicAdd(&s_base[place_slot<R, RECT>(M, p, T, rr)], 1u)] = rr;
     }
 }
 
@@ -1554,6 +1576,10 @@ constexpr int64_t kArenaRows = 512;  // blocks of the counting and entries passe
 // Runs of 64 rays per wavefront of the entries pass from which the rays are
 // also ordered by where they start (below that, by length only).
 constexpr int64_t kPlaceMinRounds = 24;
+// Rays per key of the ordering by place (on average) for which its cells are
+// a tile: with fewer, a wavefront's rays spread over several keys and the
+// lengths in it differ; the cells then grow to 2, 4, 8 tiles per edge.
+constexpr int64_t kPlaceMinRays = 200;
 
 size_t arena_round(size_t v) { return (v + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
 
@@ -1593,13 +1619,12 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     const size_t lds_order = sizeof(uint32_t) * static_cast<size_t>(n_buckets);
     int shift = 0;
     while (((static_cast<int64_t>(m.n[0]) + m.n[1] + m.n[2]) >> shift) >= lb) ++shift;
-    // the second ordering (by place) when the tally's bins go in one launch and its counters fit in
-    // LDS; not on an arena, whose fixed size the place rows would mostly take (the order changes no
-    // result)
-    const int n_place = 8 * g.n_tiles + 1;
+    // the second ordering (by place, within each bin group) when its counters fit in LDS; not on an
+    // arena, whose fixed size the place rows would mostly take (the order changes no result)
+    const int n_place = 8 * g.n_tiles + 1;  // the most keys of the ordering by place (cells of one tile)
     const size_t lds_place = sizeof(uint32_t) * static_cast<size_t>(n_place);
-    const bool place_ok = arena.base == nullptr && n_groups == 1 && lds_place <= ctx.lds_max &&
-                          ctx.test_place_order != 0;
+    const bool place_ok = arena.base == nullptr && lds_place <= ctx.lds_max && ctx.test_place_order != 0;
+    const int Gp = std::max(1, G / n_groups);  // blocks of the ordering by place per bin group
     if (place_ok) {
         // blocks may take more than 64 KiB of LDS on this GPU (up to its per-block limit)
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&place_hist_kernel<R, RECT>),
@@ -1613,7 +1638,7 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     // totals and bases take every key of the tiles pass
     const int total_keys = g.n_tiles * t.n_bins;
     const int hist_keys = std::max(std::max(g.n_keys, n_buckets), place_ok ? n_place : 0);
-    const int base_keys = std::max(std::max(total_keys, n_buckets), place_ok ? n_place : 0);
+    const int base_keys = std::max(std::max(total_keys, n_buckets), place_ok ? n_groups * n_place : 0);
     // LDS is kept for occupancy: the energy-grid hash stays in global memory
     // (it is read once per ray or record and stays in L2).
     const size_t lds1 = sigma_lds(ctx, sizeof(S), kBlock);
@@ -1685,7 +1710,17 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         // lengths leave some wavefronts working long after the others); the walking form walks every
         // voxel whatever the order and loses the finer length order
         const bool by_place =
-            place_ok && (ctx.test_place_order == 1 || (jump && slices >= kPlaceMinRounds * (kBlock / 64) * Ge));
+            place_ok && (ctx.test_place_order == 1 || (jump && slices >= kPlaceMinRounds * (kBlock / 64) * Ge0));
+        // cells of 2^shift tiles per edge, the smallest with kPlaceMinRays rays per key (on average)
+        PlaceGeom pg{};
+        for (pg.shift = 0;; ++pg.shift) {
+            const int c = (1 << pg.shift) - 1;
+            pg.cx = (g.ntx + c) >> pg.shift;
+            pg.cy = (g.nty + c) >> pg.shift;
+            const int cz = (ntz + c) >> pg.shift;
+            pg.n_keys = 8 * pg.cx * pg.cy * cz + 1;
+            if (pg.shift == 3 || nr / n_groups >= kPlaceMinRays * (pg.n_keys - 1)) break;
+        }
         const int64_t cap = nr * per_ray;  // records
         const size_t rows = static_cast<size_t>(G > Ge ? G : Ge);
         void *b_sorted, *b_hist, *b_row_off, *b_key_tot, *b_key_base, *b_ordered, *b_bucket, *b_partial, *b_bounds;
@@ -1790,16 +1825,19 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
             hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), lds_order, s, sub, nr,
                                static_cast<const uint16_t *>(b_bucket), n_buckets, rays_block,
                                static_cast<const uint32_t *>(row_off), static_cast<const uint32_t *>(key_base), by_len);
-            hipLaunchKernelGGL((place_hist_kernel<R, RECT>), dim3(G), dim3(kOrderBlock), lds_place, s, mesh, g,
-                               A.tally, static_cast<const RayRec<R> *>(by_len), nr, rays_block, hist);
-            hipLaunchKernelGGL(scan_rows_kernel, dim3((n_place + 63) / 64), dim3(64 * kScanWaves), 0, s,
-                               static_cast<const uint32_t *>(hist), G, n_place, row_off, key_tot, n_place);
+            const size_t lds_pg = sizeof(uint32_t) * static_cast<size_t>(pg.n_keys);
+            hipLaunchKernelGGL((place_hist_kernel<R, RECT>), dim3(Gp, n_groups), dim3(kOrderBlock), lds_pg, s, mesh,
+                               pg, A.tally, static_cast<const RayRec<R> *>(by_len),
+                               static_cast<const uint32_t *>(b_bounds), hist);
+            hipLaunchKernelGGL(scan_rows_kernel, dim3((pg.n_keys + 63) / 64, n_groups), dim3(64 * kScanWaves), 0, s,
+                               static_cast<const uint32_t *>(hist), Gp, pg.n_keys, row_off, key_tot,
+                               n_groups * pg.n_keys);
             hipLaunchKernelGGL(scan_keys_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint32_t *>(key_tot),
-                               n_place, key_base);
-            hipLaunchKernelGGL((place_scatter_kernel<R, RECT>), dim3(G), dim3(kOrderBlock), lds_place, s, mesh, g,
-                               A.tally, static_cast<const RayRec<R> *>(by_len), nr, rays_block,
-                               static_cast<const uint32_t *>(row_off), static_cast<const uint32_t *>(key_base),
-                               static_cast<RayRec<R> *>(b_ordered));
+                               n_groups * pg.n_keys, key_base);
+            hipLaunchKernelGGL((place_scatter_kernel<R, RECT>), dim3(Gp, n_groups), dim3(kOrderBlock), lds_pg, s,
+                               mesh, pg, A.tally, static_cast<const RayRec<R> *>(by_len),
+                               static_cast<const uint32_t *>(b_bounds), static_cast<const uint32_t *>(row_off),
+                               static_cast<const uint32_t *>(key_base), static_cast<RayRec<R> *>(b_ordered));
         } else {
             hipLaunchKernelGGL((order_scatter_kernel<R, RT>), dim3(G), dim3(kOrderBlock), lds_order, s, sub, nr,
                                static_cast<const uint16_t *>(b_bucket), n_buckets, rays_block,
