@@ -109,8 +109,9 @@ def parse():
     ap.add_argument("--host-input", type=int, default=1,
                     help="also time the cast from host arrays (the PCIe-inclusive rate; never the headline value)")
     ap.add_argument("--rect", type=int, default=1,
-                    help="also time the cast on a rectilinear mesh of the multimat box, on the multimat mesh with "
-                         "per-voxel density factors (tile-split and atomic paths) and with mixture materials")
+                    help="also time the cast on a rectilinear mesh of the multimat box and on an R-Z mesh, on the "
+                         "multimat mesh with per-voxel density factors (tile-split and atomic paths) and with "
+                         "mixture materials")
     ap.add_argument("--write-traffic", nargs=4, metavar=("CAST_FETCH", "CAST_WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary of the cast kernel from four rocprofv3 --pmc counter CSVs")
     ap.add_argument("--precision-report", action="store_true",
@@ -903,12 +904,20 @@ def multimat_forms(vrc, torch, args) -> dict:
            "hbm_frac": (RAY_BYTES["f32"] * wl.rays.n + SEG_BYTES * S) / (float(np.mean(per)) / 1e3) / 1e9 / HBM_PEAK_GBS,
            "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))}}
     log(f"bench: multimat p32_t64 {out['segments_per_s']:.3e} segments/s ({ms:.3f} ms)")
-    out["accumulation_modes"] = accumulation_modes(vrc, ctx, "p32_t64", arrays, S, launch, stream, torch, 5)
-    out["other_forms"] = other_forms(vrc, ctx, wl, "p32_t64", {"f32": arrays}, counts, stream, torch, 5)
-    out["next_event_form"] = guarded("next-event", lambda: bench_next_event(vrc, ctx, wl, torch, stream))
-    out["rect_form"] = guarded("rectilinear", lambda: bench_rect(vrc, ctx, wl, arrays, counts, torch, stream))
-    out["rz_form"] = guarded("R-Z", lambda: bench_rz(vrc, ctx, wl, arrays, counts, torch, stream))
-    out["host_input_form"] = guarded("host-input", lambda: bench_host_input(vrc, ctx, wl, torch, S))
+    if args.accumulate_modes:
+        out["accumulation_modes"] = accumulation_modes(vrc, ctx, "p32_t64", arrays, S, launch, stream, torch, 5)
+    if args.other_forms:
+        out["other_forms"] = other_forms(vrc, ctx, wl, "p32_t64", {"f32": arrays}, counts, stream, torch, 5)
+    if args.next_event:
+        out["next_event_form"] = guarded("next-event", lambda: bench_next_event(vrc, ctx, wl, torch, stream))
+    if args.rect:
+        out["rect_form"] = guarded("rectilinear", lambda: bench_rect(vrc, ctx, wl, arrays, counts, torch, stream))
+        out["rz_form"] = guarded("R-Z", lambda: bench_rz(vrc, ctx, wl, arrays, counts, torch, stream))
+    if args.host_input:
+        out["host_input_form"] = guarded("host-input", lambda: bench_host_input(vrc, ctx, wl, torch, S))
+    if not args.rect:
+        ctx.close()
+        return out
 
     def density():
         d = bench_density(vrc, ctx, wl, arrays, torch, stream)
@@ -978,9 +987,12 @@ def main():
     extra = {}
     if args.extras:
         steps = max(3, args.steps // 4)
-        extra["other_accumulation_modes"] = accumulation_modes(vrc, ctx, args.precision, arrays, S, launch, stream,
-                                                               torch, steps)
-        extra["other_forms"] = other_forms(vrc, ctx, wl, args.precision, {dt: arrays}, counts, stream, torch, steps)
+        if args.accumulate_modes:
+            extra["other_accumulation_modes"] = accumulation_modes(vrc, ctx, args.precision, arrays, S, launch,
+                                                                   stream, torch, steps)
+        if args.other_forms:
+            extra["other_forms"] = other_forms(vrc, ctx, wl, args.precision, {dt: arrays}, counts, stream, torch,
+                                               steps)
     ctx.close()
     del arrays, counts
     torch.cuda.empty_cache()

@@ -199,8 +199,8 @@ vrc_status vrc_set_mesh_rz(vrc_ctx *ctx, int mesh_id, const double centre[2], in
  * density factors: the Sigma_t,i of voxel i in Eqs. 1-4 becomes
  * rho[i] * Sigma_m(E) of its material m.  rho: host array of n0*n1*n2
  * finite values >= 0 (x fastest; 0 makes a voxel void), copied as the pairs
- * (rho, 1/rho) and as the factors alone, in FP64 and FP32 (24 B + 12 B per
- * voxel of device memory); the score divides by the voxel's Sigma as
+ * (rho, 1/rho) and as (rho, material) elements, in FP64 and FP32 (32 B +
+ * 16 B per voxel of device memory); the score divides by the voxel's Sigma as
  * (1/Sigma_m) * (1/rho).  rho == NULL removes the factors.  Setting or
  * replacing the mesh removes them too.  Such a mesh is cast by vrc_cast_rays
  * (every accumulate setting), vrc_trace_rays, vrc_count_segments,

@@ -180,8 +180,8 @@ vrc_status store_mesh(vrc_ctx *ctx, int mesh_id, const double lo[3], const doubl
     free_dev(m.d_pl32);
     free_dev(m.d_rho64);
     free_dev(m.d_rho32);
-    free_dev(m.d_rhos64);
-    free_dev(m.d_rhos32);
+    free_dev(m.d_mr64);
+    free_dev(m.d_mr32);
     m.dens = false;
     m.h_rho.clear();
     m.set = false;
@@ -412,8 +412,8 @@ vrc_status vrc_destroy(vrc_ctx *ctx)
         free_dev(m.d_pl32);
         free_dev(m.d_rho64);
         free_dev(m.d_rho32);
-        free_dev(m.d_rhos64);
-        free_dev(m.d_rhos32);
+        free_dev(m.d_mr64);
+        free_dev(m.d_mr32);
     }
     free_xs(ctx->xs);
     for (auto &st : ctx->stage) {
@@ -533,8 +533,8 @@ vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho)
     (void)hipSetDevice(ctx->device);
     free_dev(m.d_rho64);
     free_dev(m.d_rho32);
-    free_dev(m.d_rhos64);
-    free_dev(m.d_rhos32);
+    free_dev(m.d_mr64);
+    free_dev(m.d_mr32);
     m.dens = false;
     m.h_rho.clear();
     if (!rho) return VRC_OK;
@@ -555,19 +555,24 @@ vrc_status vrc_set_mesh_density(vrc_ctx *ctx, int mesh_id, const double *rho)
         return s;
     }
     m.d_rho32 = static_cast<DensPair<float> *>(d);
-    // the factors alone as well, in both precisions (the same values as the pairs' first members)
-    std::vector<float> f32(nv);
-    for (size_t v = 0; v < nv; ++v) f32[v] = p32[v].rho;
-    vrc_status st = upload(ctx, &d, rho, sizeof(double) * nv);
+    // the factors with the materials as well, in both precisions (the same values as the pairs' first
+    // members)
+    std::vector<MatRho<double>> q64(nv);
+    std::vector<MatRho<float>> q32(nv);
+    for (size_t v = 0; v < nv; ++v) {
+        q64[v] = MatRho<double>{rho[v], m.h_mat[v]};
+        q32[v] = MatRho<float>{p32[v].rho, m.h_mat[v]};
+    }
+    vrc_status st = upload(ctx, &d, q64.data(), sizeof(MatRho<double>) * nv);
     if (st == VRC_OK) {
-        m.d_rhos64 = static_cast<double *>(d);
-        st = upload(ctx, &d, f32.data(), sizeof(float) * nv);
-        if (st == VRC_OK) m.d_rhos32 = static_cast<float *>(d);
+        m.d_mr64 = static_cast<MatRho<double> *>(d);
+        st = upload(ctx, &d, q32.data(), sizeof(MatRho<float>) * nv);
+        if (st == VRC_OK) m.d_mr32 = static_cast<MatRho<float> *>(d);
     }
     if (st != VRC_OK) {
         free_dev(m.d_rho64);
         free_dev(m.d_rho32);
-        free_dev(m.d_rhos64);
+        free_dev(m.d_mr64);
         return st;
     }
     m.h_rho.assign(rho, rho + nv);

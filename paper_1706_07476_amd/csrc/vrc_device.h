@@ -193,14 +193,14 @@ struct TileMaterials {
 // *next.)
 template <typename S>
 struct MeshMaterialsDens {
-    const uint8_t *mat;
-    const S *rho;  // the factors alone: the whole-mesh walk needs rho, not 1/rho
+    const MatRho<S> *mr;  // the factors with the materials: the whole-mesh walk needs rho, not 1/rho
     S *cur, *next;
     __device__ __forceinline__ int operator()(int32_t vox, int, int, int) const
     {
+        const MatRho<S> q = mr[vox];
         *cur = *next;
-        *next = rho[vox];
-        return mat[vox];
+        *next = q.rho;
+        return static_cast<int>(q.mat);
     }
 };
 template <typename S>
@@ -774,10 +774,10 @@ __device__ __forceinline__ const DensPair<S> *density_of(const MeshP<R> &M)
     else return M.rho32;
 }
 template <typename S, typename R>
-__device__ __forceinline__ const S *factors_of(const MeshP<R> &M)
+__device__ __forceinline__ const MatRho<S> *factors_of(const MeshP<R> &M)
 {
-    if constexpr (std::is_same<S, double>::value) return M.rhos64;
-    else return M.rhos32;
+    if constexpr (std::is_same<S, double>::value) return M.mr64;
+    else return M.mr32;
 }
 
 template <typename R, typename S, class Put, bool RECT = false, bool DENS = false>

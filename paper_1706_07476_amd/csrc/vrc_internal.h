@@ -31,6 +31,14 @@ struct DensPair {
     R inv;
 };
 
+// A voxel's density factor and material in one element, for walks that need
+// rho and the material at every voxel: one gather per voxel instead of two.
+template <typename R>
+struct alignas(2 * sizeof(R)) MatRho {
+    R rho;
+    uint32_t mat;
+};
+
 // Cartesian mesh in the traversal precision R: uniform (lo + k h per axis) or
 // rectilinear (plane tables), optionally with per-voxel density factors.
 template <typename R>
@@ -55,9 +63,9 @@ struct MeshP {
     // for density read the one of their score type), or null
     const DensPair<float> *rho32 = nullptr;
     const DensPair<double> *rho64 = nullptr;
-    // the factors alone (half the bytes: walks that need only rho gather these)
-    const float *rhos32 = nullptr;
-    const double *rhos64 = nullptr;
+    // the factors with the materials (walks that need only rho and the material gather these)
+    const MatRho<float> *mr32 = nullptr;
+    const MatRho<double> *mr64 = nullptr;
 };
 
 // Cross sections on the union energy grid.  E[K] strictly increasing;
@@ -196,8 +204,8 @@ struct MeshHost {
     std::vector<double> h_rho;
     DensPair<double> *d_rho64 = nullptr;
     DensPair<float> *d_rho32 = nullptr;
-    double *d_rhos64 = nullptr;  // the factors alone, FP64 and FP32
-    float *d_rhos32 = nullptr;
+    MatRho<double> *d_mr64 = nullptr;  // the factors with the materials, FP64 and FP32
+    MatRho<float> *d_mr32 = nullptr;
     int32_t n[3] = {0, 0, 0};
     int64_t nvox = 0;
     int max_mat = 0;

@@ -200,8 +200,8 @@ MeshP<R> mesh_args(const MeshHost &m)
     p.tile_mat = m.dens ? nullptr : m.d_tile_mat;
     p.rho32 = m.d_rho32;
     p.rho64 = m.d_rho64;
-    p.rhos32 = m.d_rhos32;
-    p.rhos64 = m.d_rhos64;
+    p.mr32 = m.d_mr32;
+    p.mr64 = m.d_mr64;
     if (m.rect) {
         const R *base = mesh_planes<R>(m);
         p.pl[0] = base;

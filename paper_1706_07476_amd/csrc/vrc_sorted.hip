@@ -877,9 +877,9 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
     const RayDeal deal(n, A.g.gblocks, gb.block);
     S dcur = S(0), dnext = S(0);
     Walker<R, RECT> wk;
-    const S *dens = factors_of<S>(A.mesh);
+    const MatRho<S> *dens = factors_of<S>(A.mesh);
     const auto mats = [&] {
-        if constexpr (DENS) return MeshMaterialsDens<S>{A.mesh.mat, dens, &dcur, &dnext};
+        if constexpr (DENS) return MeshMaterialsDens<S>{dens, &dcur, &dnext};
         else return MeshMaterials{A.mesh.mat};
     }();
     const MeshP<R> &M = A.mesh;
@@ -914,7 +914,7 @@ __global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1) entries_kernel(En
         const int bin = gb.local_bin(A.tally, static_cast<double>(rr.e));
         if (bin < 0) continue;
         if (!wk.start(M, rr.ox, rr.oy, rr.oz, rr.ux, rr.uy, rr.uz)) continue;
-        if constexpr (DENS) dnext = dens[wk.vox];  // start() reads the first voxel's material itself
+        if constexpr (DENS) dnext = dens[wk.vox].rho;  // start() reads the first voxel's material itself
         out.xs = xs_lookup_sigma(A.xs, hash, rr.e, mysig, bd);  // the optical depth needs Sigma only
         out.ox = rr.ox;
         out.oy = rr.oy;
@@ -1776,8 +1776,8 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
         if constexpr (DENS) {
             mesh.rho32 = m.d_rho32;
             mesh.rho64 = m.d_rho64;
-            mesh.rhos32 = m.d_rhos32;
-            mesh.rhos64 = m.d_rhos64;
+            mesh.mr32 = m.d_mr32;
+            mesh.mr64 = m.d_mr64;
         }
         EntryArgs<R> A;
         A.mesh = mesh;
