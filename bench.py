@@ -180,6 +180,26 @@ def write_traffic(paths, workload="cylinder", precision="p32_d64", copy_mib=1024
     print(json.dumps(t))
 
 
+def measured_copy_gbs(torch, mib: int = 1024, reps: int = 10) -> float:
+    """Device-to-device copy rate (bytes read + written per second, in GB/s) of a plain mib MiB copy,
+    timed with HIP events over reps copies after one untimed copy: the bandwidth a kernel that
+    streams through HBM without re-reading can reach on this device."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    t1.synchronize()
+    gbs = 2 * n * 4 * reps / (t0.elapsed_time(t1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def copy_calibration(mib: int, steps: int) -> None:
     """A plain copy kernel of known size: reads and writes mib MiB per launch."""
     import torch
@@ -1005,6 +1025,8 @@ def main():
             extra["serving_form"] = guarded("serving", lambda: bench_serving(args.serving_seconds))
         if args.fom:
             extra["fom_form"] = guarded("eta", lambda: bench_fom(args.fom_batches, args.fom_histories))
+    copy_gbs = measured_copy_gbs(torch)
+    log(f"bench: device copy {copy_gbs:.0f} GB/s; the cast's algorithmic rate is {achieved / copy_gbs:.3f} of it")
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
@@ -1042,6 +1064,7 @@ def main():
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_ms": kern_s * 1e3,
+                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "kernels": pipeline(args.precision, launch["accumulate"])},
         "cpu_baseline": cpu,
         "wall_s_timed": wall,

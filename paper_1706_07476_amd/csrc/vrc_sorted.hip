@@ -1285,7 +1285,7 @@ template <typename R, typename S, int FLUSH, bool RECT, bool DENS>
 __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(TileArgs<R> A)
 {
     __shared__ double acc[kTileVoxels];
-    __shared__ uint8_t s_mat[kTileVoxels];
+    __shared__ __align__(16) uint8_t s_mat[kTileVoxels];
     __shared__ uint32_t s_cnt[kBucketsT];
     __shared__ uint16_t s_perm[kMaxBlock * tile_per<S>()];
     const int n_keys = A.g.n_keys;
@@ -1331,23 +1331,33 @@ __global__ void __launch_bounds__(1024, sizeof(S) == 4 ? 8 : 1) tile_kernel(Tile
         const int tx = tile % A.g.ntx;
         const int ty = (tile / A.g.ntx) % A.g.nty;
         const int tz = tile / (A.g.ntx * A.g.nty);
+        const int pm = A.mesh.tile_mat != nullptr && !DENS ? A.mesh.tile_mat[tile] : -1;  // the tile's one material
         __syncthreads();  // the previous key's tile has been flushed
-        // the tile's materials (voxels beyond the mesh are never read)
-        for (int i = threadIdx.x; i < kTileVoxels; i += bd) {
-            acc[i] = 0.0;
-            const int x = tx * kTileEdge + (i & (kTileEdge - 1));
-            const int y = ty * kTileEdge + ((i >> kTileBits) & (kTileEdge - 1));
-            const int z = tz * kTileEdge + (i >> (2 * kTileBits));
-            s_mat[i] = (x < nx && y < ny && z < nz)
-                           ? A.mesh.mat[x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z)]
-                           : static_cast<uint8_t>(0);
+        // the tile's materials (voxels beyond the mesh are never read): none for a tile of one
+        // material (its walks read no materials), a copy of its tile-major block for a tile of
+        // several, else gathered from the mesh array
+        const uint8_t *blk = !DENS && pm < 0 && A.mesh.tile_slot != nullptr
+                                 ? A.mesh.mixed + static_cast<int64_t>(A.mesh.tile_slot[tile]) * kTileVoxels
+                                 : nullptr;
+        for (int i = threadIdx.x; i < kTileVoxels; i += bd) acc[i] = 0.0;
+        if (blk != nullptr) {
+            for (int i = threadIdx.x; i < kTileVoxels / 4; i += bd)
+                reinterpret_cast<uint32_t *>(s_mat)[i] = reinterpret_cast<const uint32_t *>(blk)[i];
+        } else if (pm < 0) {
+            for (int i = threadIdx.x; i < kTileVoxels; i += bd) {
+                const int x = tx * kTileEdge + (i & (kTileEdge - 1));
+                const int y = ty * kTileEdge + ((i >> kTileBits) & (kTileEdge - 1));
+                const int z = tz * kTileEdge + (i >> (2 * kTileBits));
+                s_mat[i] = (x < nx && y < ny && z < nz)
+                               ? A.mesh.mat[x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z)]
+                               : static_cast<uint8_t>(0);
+            }
         }
         __syncthreads();
         const auto mats = [&] {
             if constexpr (DENS) return TileMaterialsDens<S>{s_mat, dens, nx, ny, &dcur, &dnext};
             else return TileMaterials{s_mat};
         }();
-        const int pm = A.mesh.tile_mat != nullptr && !DENS ? A.mesh.tile_mat[tile] : -1;  // the tile's one material
         const uint32_t cb = static_cast<uint32_t>(bd * PER);  // records per chunk
         for (uint32_t c0 = lo; c0 < hi; c0 += cb) {
             const int m = static_cast<int>(hi - c0 < cb ? hi - c0 : cb);
