@@ -225,17 +225,38 @@ def outside_origins(rays, mesh, frac=0.2, seed=0):
     return r
 
 
-@pytest.mark.parametrize("case", ["ragged", "one-material-jump", "one-material-walk", "rect"])
+def tiled_materials_mesh(n=128, seed=541):
+    """n^3 voxels of 0.5 cm, each 16^3 tile of one material except a random quarter of the tiles,
+    whose voxels take random materials (the jumping entries pass meets both kinds)."""
+    rng = np.random.default_rng(seed)
+    t = n // 16
+    tile_mat = rng.integers(0, 3, (t, t, t))
+    mat = np.repeat(np.repeat(np.repeat(tile_mat, 16, 0), 16, 1), 16, 2).astype(np.uint8)
+    mixed = rng.random((t, t, t)) < 0.25
+    for k, j, i in zip(*np.nonzero(mixed)):
+        mat[16 * k:16 * k + 16, 16 * j:16 * j + 16, 16 * i:16 * i + 16] = rng.integers(0, 3, (16, 16, 16))
+    return W.Mesh(np.array([-1.0, 0.5, 2.0]), np.full(3, 0.5), np.full(3, n, np.int32), mat.reshape(-1).copy())
+
+
+@pytest.mark.parametrize("case", ["ragged", "one-material-jump", "one-material-walk", "rect", "groups-jump",
+                                  "groups-walk"])
 def test_sorted_place_order(vrc, ctx, case):
-    """Rays ordered by length, then by place (the tile of the origin's voxel, the origin clamped into
-    the mesh, and the direction's signs), forced on: the tally equals the atomic path's to the order
-    of the additions and the oracle's to the FP64 bound, with origins inside and outside a ragged mesh
-    (10 energy bins), on single-material tiles (jumping and walking entries passes) and on a
-    rectilinear mesh (the key from its plane tables)."""
+    """Rays ordered by length, then by place (the cell of the origin's voxel, the origin clamped into
+    the mesh, and the direction's signs; cells of 1-8 tiles per edge by rays per key), forced on: the
+    tally equals the atomic path's to the order of the additions and the oracle's to the FP64 bound,
+    with origins inside and outside a ragged mesh (10 energy bins), on single-material tiles (jumping
+    and walking entries passes), on a rectilinear mesh (the key from its plane tables), and with the
+    bins in groups (128^3 voxels, 9 bins: groups of 8 + 1, each group's rays ordered by place on its
+    own; jumping and walking entries passes)."""
     vrc.vrc_test_hook(ctx.handle, vrc.VRC_TEST_PLACE_ORDER, 1)
     edges = None
     xs = W.config2_multimaterial(n_rays=0).xs
-    if case == "ragged":
+    if case.startswith("groups"):
+        vrc.vrc_test_hook(ctx.handle, vrc.VRC_TEST_ENTRIES_JUMP, 1 if case.endswith("jump") else 0)
+        mesh = tiled_materials_mesh()
+        rays = outside_origins(W.rays_in_box(542, mesh, 200_000), mesh, seed=543)
+        edges = W.log_bin_edges(9, 1e-9, 1.0)
+    elif case == "ragged":
         mesh = ragged_mesh(seed=531)
         rays = outside_origins(W.rays_in_box(532, mesh, 120_000), mesh, seed=533)
         edges = W.log_bin_edges(10, 1e-9, 1.0)
@@ -254,9 +275,9 @@ def test_sorted_place_order(vrc, ctx, case):
     got, atom = cast_both(ctx, 0, "p64", dev_arrays(rays, "f64"), edges)
     o = order_rel(got, atom)
     res = oracle.cast(mesh, xs, rays, edges=edges, n_threads=oracle_threads())
-    g, _, n = rel_report(got.reshape(10, -1) if edges is not None else got, res, gate="all")
+    g, _, n = rel_report(got.reshape(len(edges) - 1, -1) if edges is not None else got, res, gate="all")
     say(f"  sorted vs atomic {o:.3e}; vs oracle {g:.3e} over {n} voxels")
-    assert n > 0.5 * mesh.n_voxels
+    assert n > (0.2 if case.startswith("groups") else 0.5) * mesh.n_voxels
     assert o <= TOL_ORDER
     assert g <= TOL_P64
 
