@@ -440,7 +440,7 @@ def bench_host_input(vrc, ctx, wl, torch, S, steps: int = 10) -> dict:
 
 def host_cpu():
     """(threads the oracle runs on, what was counted): the host's CPUs available to this process,
-    capped by OMP_NUM_THREADS (the share of a shared GPU machine's cores given to one GPU's jobs)."""
+    capped by OMP_NUM_THREADS (the share of a shared machine's cores given to one GPU's jobs)."""
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
