@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--workload", default="cylinder", choices=sorted(WORKLOADS),
                     help="the headline workload (the other one is timed as an extra key unless --multimat 0)")
     ap.add_argument("--rays", type=int, default=None, help="rays per step (default: the workload's)")
+    ap.add_argument("--bins", type=int, default=1,
+                    help="energy bins of the headline tally, log-spaced over the rays' energies (default 1)")
     ap.add_argument("--precision", default="p32_d64", choices=["p64", "p32_t64", "p32_kahan", "p32_d64"])
     ap.add_argument("--extras", type=int, default=1,
                     help="0: the headline cast only (profiling runs); 1: every other form too")
@@ -993,8 +995,13 @@ def main():
     counts = torch.empty(wl.rays.n, dtype=torch.int64, device="cuda:0")
     S = ctx.count_segments(0, args.precision, arrays, counts, stream)
     R = wl.rays.n
-    tid = ctx.create_tally(0, args.precision)
-    log(f"bench: {R} rays, {S} segments per step; timing {args.steps} steps after {args.warmup} warm-up")
+    edges = None
+    if args.bins > 1:
+        lo, hi = float(wl.rays.e.min()), float(wl.rays.e.max())
+        edges = np.exp(np.linspace(np.log(lo * 0.999), np.log(hi * 1.001), args.bins + 1))
+    tid = ctx.create_tally(0, args.precision, edges)
+    log(f"bench: {R} rays, {S} segments per step, {args.bins} energy bins; timing {args.steps} steps after "
+        f"{args.warmup} warm-up")
     per, total_ms, wall = time_casts(vrc, ctx, tid, arrays, args.steps, args.warmup, stream, torch)
     ctx.destroy_tally(tid)
     ms_step = total_ms / args.steps
@@ -1048,6 +1055,7 @@ def main():
             "workload": WORKLOADS[args.workload],
             "rays_per_step": R,
             "segments_per_step": S,
+            "energy_bins": args.bins,
             "precision": args.precision,
             "tally_dtype": "f64" if args.precision != "p32_kahan" else "f32+f32 compensated",
             "forms": {"p64": "FP64 walk, optical depth, exponentials, tally",

@@ -1590,6 +1590,9 @@ constexpr int64_t kPlaceMinRounds = 24;
 // a tile: with fewer, a wavefront's rays spread over several keys and the
 // lengths in it differ; the cells then grow to 2, 4, 8 tiles per edge.
 constexpr int64_t kPlaceMinRays = 200;
+// Keys of the tiles pass with fewer records than this on average take blocks of kSmallKeyBlock threads.
+constexpr int64_t kSmallKeyRecords = 1024;
+constexpr int kSmallKeyBlock = 256;
 
 size_t arena_round(size_t v) { return (v + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
 
@@ -1652,7 +1655,13 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     // LDS is kept for occupancy: the energy-grid hash stays in global memory
     // (it is read once per ray or record and stays in L2).
     const size_t lds1 = sigma_lds(ctx, sizeof(S), kBlock);
-    const int tb = tile_block(ctx, sizeof(S));
+    // 256-thread blocks for the tiles pass where its keys hold few records (on average, counting a third
+    // of the most tiles a ray can cross): every key costs its block a sequence of dependent steps (the
+    // tile's setup, the chunk's order, the records' loads, the walks, the flush) that a few records
+    // leave mostly idle, and smaller blocks keep more keys in flight on each CU
+    int tb = tile_block(ctx, sizeof(S));
+    if (tb > kSmallKeyBlock && n_rays * (per_ray / 3) < kSmallKeyRecords * static_cast<int64_t>(total_keys))
+        tb = kSmallKeyBlock;
     const size_t lds2 = sigma_lds(ctx, sizeof(S), tb);
     // The counting and entries passes run one block per resident slot of the
     // entries pass (the ray deal keeps them equally busy); a sub-launch takes
