@@ -1590,7 +1590,8 @@ constexpr int64_t kPlaceMinRounds = 24;
 // a tile: with fewer, a wavefront's rays spread over several keys and the
 // lengths in it differ; the cells then grow to 2, 4, 8 tiles per edge.
 constexpr int64_t kPlaceMinRays = 200;
-// Keys of the tiles pass with fewer records than this on average take blocks of kSmallKeyBlock threads.
+// Keys of the tiles pass with fewer records than this on average take blocks of kSmallKeyBlock threads,
+// with fewer than twice as many blocks of twice as many threads.
 constexpr int64_t kSmallKeyRecords = 1024;
 constexpr int kSmallKeyBlock = 256;
 
@@ -1660,8 +1661,11 @@ hipError_t run_sorted_kind(vrc_ctx &ctx, const TallyHost &t, const MeshHost &m, 
     // tile's setup, the chunk's order, the records' loads, the walks, the flush) that a few records
     // leave mostly idle, and smaller blocks keep more keys in flight on each CU
     int tb = tile_block(ctx, sizeof(S));
-    if (tb > kSmallKeyBlock && n_rays * (per_ray / 3) < kSmallKeyRecords * static_cast<int64_t>(total_keys))
+    const int64_t est_records = n_rays * (per_ray / 3);
+    if (tb > kSmallKeyBlock && est_records < kSmallKeyRecords * static_cast<int64_t>(total_keys))
         tb = kSmallKeyBlock;
+    else if (tb > 2 * kSmallKeyBlock && est_records < 2 * kSmallKeyRecords * static_cast<int64_t>(total_keys))
+        tb = 2 * kSmallKeyBlock;
     const size_t lds2 = sigma_lds(ctx, sizeof(S), tb);
     // The counting and entries passes run one block per resident slot of the
     // entries pass (the ray deal keeps them equally busy); a sub-launch takes
